@@ -1,0 +1,194 @@
+/*
+ * dis.h -- Dense Inverse Search optical flow on AMD gfx950 (MI355X).
+ *
+ * The method is Kroeger, Timofte, Dai and Van Gool, "Fast Optical Flow using
+ * Dense Inverse Search" (ECCV 2016): a coarse-to-fine loop (Alg. 1) that on
+ * every scale s places a uniform grid of patches (Sec. 2.2 step 1),
+ * initialises each from the coarser flow (step 2), aligns it by
+ * inverse-compositional Gauss-Newton (Sec. 2.1 and Suppl. A), merges the
+ * patch displacements into a dense field by the weighted average of Eq. (3)
+ * (step 4) and refines that field variationally (Sec. 2.3); the finest
+ * computed field is upscaled bilinearly to the input size (end of Sec. 3.1).
+ *
+ * Conventions used by every entry point:
+ *   - Frames are grayscale intensities in [0, 1], row-major [h][pitch]
+ *     (pitch in elements, pitch >= w), float32, or float64 when the handle
+ *     was created with DIS_FLAG_IO_F64.
+ *   - Flow is planar and dense: [2][h][w], the u (+x, columns) plane then the
+ *     v (+y, rows) plane, same element type as the frames, such that
+ *     I1(x + U(x)) ~= I0(x) (Eq. (1)).
+ *   - Frame, flow and gradient pointers are DEVICE pointers owned by the
+ *     caller.  All scratch memory is owned by the handle and allocated once,
+ *     in dis_create.
+ *   - Calls are asynchronous on the handle's HIP stream and do not
+ *     synchronise it (except dis_debug_level, dis_autotune and dis_destroy's
+ *     documented cases); the caller synchronises before reading results.
+ *   - One host thread may use a handle at a time.
+ *   - Internally all arithmetic is float64.
+ *
+ * Error codes: every int-returning call returns DIS_OK or a negative code;
+ * dis_last_error() gives a readable message for the most recent failure.
+ */
+#ifndef DIS_H
+#define DIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DIS_OK 0
+#define DIS_EINVAL (-1)  /* bad parameter or NULL pointer */
+#define DIS_ESIZE (-2)   /* size beyond the handle's capacity, or an image too small for a patch */
+#define DIS_EHIP (-3)    /* a HIP runtime call failed; see dis_last_error */
+#define DIS_ESTATE (-4)  /* call out of order (backward without a kept forward) */
+#define DIS_ENOMEM (-5)  /* device allocation failed */
+
+/* dis_params.flags */
+#define DIS_FLAG_KEEP_FOR_BACKWARD 0x1u /* keep what dis_flow_backward needs */
+#define DIS_FLAG_NO_GRAPH 0x2u          /* launch kernels one by one instead of replaying a HIP graph */
+#define DIS_FLAG_PIXEL_CENTRE 0x4u      /* map coarse<->fine positions through pixel centres, (x+0.5)/2-0.5 */
+#define DIS_FLAG_RAW_RESIDUAL 0x8u      /* Eq. (3) residual without mean normalisation */
+#define DIS_FLAG_IO_F64 0x10u           /* frames, flow and gradients are float64 */
+
+/*
+ * Method parameters: Table 1 of the paper and the fixed values of Sec. 3.1.
+ *   patch_size      theta_ps, >= 4 and <= 16
+ *   overlap         theta_ov in [0, 1); patch stride = max(1, floor(theta_ps (1 - theta_ov)))
+ *   coarsest_scale  theta_ss; -1 picks ceil(log2(2 w / (8 theta_ps))) (Sec. 3.1);
+ *                   either way it is lowered until the level is >= theta_ps on both sides
+ *   finest_scale    theta_sf >= 0; the flow is upscaled from this level
+ *   gn_iters        theta_it >= 0, Gauss-Newton iterations per patch (fixed count)
+ *   var_outer       theta_vo, fixed-point iterations of the refinement; -1 = s + 1 on scale s
+ *   var_inner       theta_vi >= 1, red-black SOR sweeps per fixed-point iteration
+ *   w_intensity, w_gradient, w_smooth   delta, gamma, alpha of Sec. 2.3 (5, 10, 10)
+ *   sor_omega       SOR relaxation factor in (0, 2)
+ *   refine          1 = run the variational refinement (Sec. 2.3), 0 = skip it
+ *   flags           DIS_FLAG_* bits
+ */
+typedef struct dis_params {
+    int32_t patch_size;
+    double overlap;
+    int32_t coarsest_scale;
+    int32_t finest_scale;
+    int32_t gn_iters;
+    int32_t var_outer;
+    int32_t var_inner;
+    double w_intensity;
+    double w_gradient;
+    double w_smooth;
+    double sor_omega;
+    int32_t refine;
+    uint32_t flags;
+} dis_params;
+
+typedef struct dis_handle dis_handle;
+
+/*
+ * Fill *out with a preset.  Presets 1-4 are the paper's operating points
+ * (Sec. 3.3: (1) theta_sf 3, theta_it 16, theta_ps 8, theta_ov 0.3, no
+ * refinement; (2) 3/12/8/0.4 with refinement; (3) 1/16/12/0.75; (4)
+ * 0/256/12/0.75), all with theta_ss 5, delta 5, gamma 10, alpha 10,
+ * theta_vo = s+1, theta_vi 5.  Presets 101-105 are the synthetic
+ * workloads: 101 one 256x192 pair (8, 0.3, 3 levels, 8 iterations, theta_vo
+ * 1); 102/103 the 1024x436 operating points (8, 0.3, 12 it) and (8, 0.5,
+ * 16 it) over scales 5..3; 104 high quality (12, 0.75, scales 4..0, 128 it,
+ * theta_vo 5); 105 the differentiable batch (8, 0.5, scales 3..0, 16 it,
+ * theta_vo 3).  Returns DIS_EINVAL for an unknown preset or NULL out.
+ */
+int dis_default_params(int preset, dis_params* out);
+
+/*
+ * Validate *p and create a handle for frames up to max_w x max_h and batches
+ * of up to max_batch pairs, working on HIP stream `hip_stream` (a
+ * hipStream_t; NULL = the default stream) of the current device.  Allocates
+ * every device buffer the handle will use (the paper allocates all memory
+ * once, Suppl. C).  On success *out holds the handle and DIS_OK is returned;
+ * otherwise *out is NULL.  Errors: DIS_EINVAL (bad parameter, NULL p/out,
+ * max sizes < patch size, max_batch < 1), DIS_ENOMEM, DIS_EHIP.
+ */
+int dis_create(const dis_params* p, int max_w, int max_h, int max_batch,
+               void* hip_stream, dis_handle** out);
+
+/*
+ * Dense flow from I0 to I1 (Alg. 1).  I0 and I1 are w x h frames with row
+ * pitch `pitch` elements; flow receives [2][h][w].  Enqueued on the handle's
+ * stream.  Errors: DIS_EINVAL (NULL pointer, pitch < w, w or h < 1),
+ * DIS_ESIZE (w > max_w, h > max_h, or the finest scale smaller than the
+ * patch), DIS_EHIP.  With DIS_FLAG_KEEP_FOR_BACKWARD the handle keeps the
+ * frames' pointers and per-scale flows for dis_flow_backward; the frames must
+ * then stay unchanged until the backward call has run.
+ */
+int dis_compute_flow(dis_handle* h, const void* I0, const void* I1, int w, int hgt,
+                     int pitch, void* flow);
+
+/*
+ * Flow for n independent pairs of possibly different sizes, one pair per
+ * slot (n <= max_batch).  The arrays I0[], I1[], flow[] (device pointers)
+ * and w[], hgt[], pitch[] are HOST arrays of length n.  All pairs of one
+ * pyramid level are processed by a single persistent kernel launch that
+ * takes work from a queue; the whole batch is replayed as one HIP graph per
+ * batch composition.  Each pair's result is bitwise equal to
+ * dis_compute_flow on that pair.  Errors as for dis_compute_flow, plus
+ * DIS_ESIZE for n > max_batch.
+ */
+int dis_compute_flow_batched(dis_handle* h, int n, const void* const* I0,
+                             const void* const* I1, const int* w, const int* hgt,
+                             const int* pitch, void* const* flow);
+
+/*
+ * Gradient of a scalar loss with respect to both frames, given
+ * grad_flow = dL/dflow ([2][h][w], device) for the most recent
+ * dis_compute_flow on this handle (which must have run with
+ * DIS_FLAG_KEEP_FOR_BACKWARD).  Writes dL/dI0 and dL/dI1 ([h][w], dense,
+ * pitch = w) into caller buffers.  Each scale is recomputed from the kept
+ * coarser flow before its adjoint runs, so scratch stays bounded by one
+ * scale.  Errors: DIS_EINVAL (NULL pointer), DIS_ESTATE (no kept forward),
+ * DIS_EHIP.
+ */
+int dis_flow_backward(dis_handle* h, const void* grad_flow, void* grad_I0, void* grad_I1);
+
+/*
+ * Time the result-invariant launch choices (lanes per patch in the search,
+ * tile shape of the refinement) for the handle's parameters at its maximum
+ * size, keep the fastest, and append them to the JSON file `cache_path`
+ * (NULL = no file).  Synchronises the stream.  Errors: DIS_EHIP.
+ */
+int dis_autotune(dis_handle* h, const char* cache_path);
+
+/* Message for the most recent failing call on h (or on a NULL handle). */
+const char* dis_last_error(const dis_handle* h);
+
+/* Move the handle to another HIP stream.  Errors: DIS_EINVAL. */
+int dis_set_stream(dis_handle* h, void* hip_stream);
+
+/*
+ * Copy an intermediate of the most recent forward call on slot 0 at scale s
+ * into the HOST buffer dst of `bytes` bytes (float64 values).  Synchronises
+ * the stream.  `what`: DIS_DBG_J0/J1 the level images [H_s][W_s] (0..255
+ * scale), DIS_DBG_UINIT [N][2] patch initialisations, DIS_DBG_UPATCH [N][2]
+ * patch displacements after the reset test, DIS_DBG_UDENSE [2][H_s][W_s]
+ * densified flow, DIS_DBG_UREFINED [2][H_s][W_s] flow after refinement,
+ * DIS_DBG_INFO int32 {W_s, H_s, N, nx, ny, stride} (24 bytes).
+ * Errors: DIS_EINVAL (bad what/s or NULL), DIS_ESIZE (bytes too small),
+ * DIS_ESTATE (scale not computed), DIS_EHIP.
+ */
+#define DIS_DBG_J0 0
+#define DIS_DBG_J1 1
+#define DIS_DBG_UINIT 2
+#define DIS_DBG_UPATCH 3
+#define DIS_DBG_UDENSE 4
+#define DIS_DBG_UREFINED 5
+#define DIS_DBG_INFO 6
+int dis_debug_level(dis_handle* h, int s, int what, void* dst, size_t bytes);
+
+/* Release the handle and its device memory; NULL is ignored.  Synchronises
+ * the handle's stream first, so pending work finishes before memory goes. */
+void dis_destroy(dis_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIS_H */

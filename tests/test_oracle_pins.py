@@ -1,0 +1,536 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these retype the oracle's formulas: each checks a closed form, an
+invariant, a special case solved by another route, or a constant the paper
+prints (tests/golden/paper_constants.json).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+import torch
+
+from oracle import dis_oracle as O
+from oracle import search_checks as SC
+
+F64 = torch.float64
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")
+
+
+def analytic_texture(h, w, shift=(0.0, 0.0), seed=0, min_period=20.0, n=12):
+    """0.5 + sum of sinusoids, evaluated exactly at (x - tx, y - ty)."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
+    xx = xx - shift[0]
+    yy = yy - shift[1]
+    out = np.full((h, w), 0.5)
+    for _ in range(n):
+        per = rng.uniform(min_period, 3 * min_period)
+        ang = rng.uniform(0, 2 * math.pi)
+        ph = rng.uniform(0, 2 * math.pi)
+        fx, fy = math.cos(ang) / per, math.sin(ang) / per
+        out += (0.4 / n) * np.sin(2 * math.pi * (fx * xx + fy * yy) + ph)
+    return torch.from_numpy(out)
+
+
+def params(**kw):
+    base = dict(patch_size=8, overlap=0.5, coarsest_scale=3, finest_scale=0, gn_iters=16,
+                var_outer=3, var_inner=5, refine=True)
+    base.update(kw)
+    return O.OracleParams(**base)
+
+
+# ------------------------------------------------------------------ P1 -------
+@pytest.mark.parametrize("refine", [False, True])
+def test_p1_identical_frames_give_exactly_zero_flow(refine):
+    I = analytic_texture(96, 128, seed=1)
+    for sf in (0, 2):
+        U = O.dis_flow(I, I.clone(), params(refine=refine, finest_scale=sf))
+        assert torch.count_nonzero(U) == 0
+
+
+# ------------------------------------------------------------------ P2 -------
+@pytest.mark.parametrize("t", [(5.3, -3.7), (-11.6, 7.25), (0.4, 0.2)])
+@pytest.mark.parametrize("refine", [False, True])
+def test_p2_global_translation(t, refine):
+    h, w = 128, 160
+    I0 = analytic_texture(h, w, seed=2)
+    I1 = analytic_texture(h, w, shift=t, seed=2)     # I1(x + t) = I0(x)
+    U = O.dis_flow(I0, I1, params(refine=refine, coarsest_scale=3, gn_iters=16))
+    m = int(abs(t[0]) + abs(t[1])) + 10
+    err = torch.sqrt((U[0] - t[0]) ** 2 + (U[1] - t[1]) ** 2)[m:h - m, m:w - m]
+    assert err.mean() < 0.05, float(err.mean())
+
+
+# ------------------------------------------------------------------ P3 -------
+@pytest.mark.parametrize("rot_deg,scale", [(1.0, 1.0), (-1.0, 0.99), (0.0, 1.02)])
+def test_p3_small_affine_motion(rot_deg, scale):
+    """Rigid patches cannot follow a rotation exactly: the model error grows
+    with the flow gradient times the patch size (about 5% of the largest
+    displacement here), so the warps stay within 1 degree / 2 percent."""
+    h, w = 128, 160
+    c = np.array([(w - 1) / 2, (h - 1) / 2])
+    th = math.radians(rot_deg)
+    A = scale * np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    Ainv = np.linalg.inv(A)
+    rng = np.random.default_rng(3)
+    comps = [(rng.uniform(20, 60), rng.uniform(0, 2 * math.pi), rng.uniform(0, 2 * math.pi)) for _ in range(12)]
+
+    def tex(x, y):
+        out = np.full(x.shape, 0.5)
+        for per, ang, ph in comps:
+            out += (0.4 / 12) * np.sin(2 * math.pi * (math.cos(ang) * x + math.sin(ang) * y) / per + ph)
+        return out
+
+    yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
+    I0 = tex(xx, yy)
+    q = Ainv @ (np.stack([xx.ravel(), yy.ravel()]) - c[:, None]) + c[:, None]
+    I1 = tex(q[0].reshape(h, w), q[1].reshape(h, w))   # I1(A(x-c)+c) = I0(x)
+    gt = (A - np.eye(2)) @ (np.stack([xx.ravel(), yy.ravel()]) - c[:, None])
+    U = O.dis_flow(torch.from_numpy(I0), torch.from_numpy(I1), params(coarsest_scale=3))
+    err = np.sqrt((U[0].numpy().ravel() - gt[0]) ** 2 + (U[1].numpy().ravel() - gt[1]) ** 2).reshape(h, w)
+    m = 12
+    assert err[m:h - m, m:w - m].mean() < 0.1, err[m:h - m, m:w - m].mean()
+
+
+# ------------------------------------------------------------------ P4 -------
+def test_p4_bilinear_image_gn_converges_to_exact_translation():
+    """On a bilinear image Sobel/8 is the exact derivative and bilinear
+    interpolation is exact, so u = t is an exact fixed point.  With the
+    template gradient left uncentred (R9) the step's contraction factor is
+    g_mean^T (sum g g^T / n)^-1 g_mean, which vanishes when the patch is
+    centred on the saddle of J0 = c (x - xs)(y - ys): convergence is then
+    essentially exact within a few iterations."""
+    h, w = 48, 56
+    c = 0.8
+    t = (0.7, -0.4)
+    x0, y0 = 20, 18
+    xs, ys = x0 + 3.5, y0 + 3.5
+    yy, xx = torch.meshgrid(torch.arange(h, dtype=F64), torch.arange(w, dtype=F64), indexing="ij")
+    J0 = c * (xx - xs) * (yy - ys) + 100.0
+    J1 = c * (xx - t[0] - xs) * (yy - t[1] - ys) + 100.0
+    Gx, Gy = O.sobel8(J0)
+    assert torch.allclose(Gx[1:-1, 1:-1], (c * (yy - ys))[1:-1, 1:-1], atol=1e-12)
+    assert torch.allclose(Gy[1:-1, 1:-1], (c * (xx - xs))[1:-1, 1:-1], atol=1e-12)
+    tt = torch.tensor([t], dtype=F64)
+    res = O.inverse_search(J0, Gx, Gy, J1, torch.tensor([x0]), torch.tensor([y0]),
+                           torch.zeros(1, 2, dtype=F64), params(gn_iters=8, patch_size=8))
+    assert (res.u - tt).abs().max() < 1e-9
+    # off the saddle the same fixed point is reached, linearly
+    res = O.inverse_search(J0, Gx, Gy, J1, torch.tensor([x0 + 3]), torch.tensor([y0 - 2]),
+                           torch.zeros(1, 2, dtype=F64), params(gn_iters=200, patch_size=8))
+    assert (res.u - tt).abs().max() < 1e-9
+
+
+# ------------------------------------------------------------------ P5 -------
+def test_p5_hessian_symmetric_psd_and_independent():
+    rng = np.random.default_rng(5)
+    J = ndi.gaussian_filter(rng.standard_normal((40, 40)), 1.5) * 60 + 128
+    Jt = torch.from_numpy(J)
+    Gx, Gy = O.sobel8(Jt)
+    x0, y0, _, _ = O.patch_grid(40, 40, params(patch_size=8, overlap=0.5))
+    res = O.inverse_search(Jt, Gx, Gy, Jt, x0, y0, torch.zeros(len(x0), 2, dtype=F64), params(gn_iters=1))
+    H = res.hessian
+    assert torch.equal(H, H.transpose(1, 2))
+    ev = torch.linalg.eigvalsh(H)
+    assert (ev > 0).all()
+    # independent gradient: scipy's Sobel with replicated border, divided by 8
+    gx = ndi.sobel(J, axis=1, mode="nearest") / 8.0
+    gy = ndi.sobel(J, axis=0, mode="nearest") / 8.0
+    for i in range(len(x0)):
+        X, Y = int(x0[i]), int(y0[i])
+        px = gx[Y:Y + 8, X:X + 8].ravel()
+        py = gy[Y:Y + 8, X:X + 8].ravel()
+        Hi = np.array([[px @ px, px @ py], [px @ py, py @ py]])
+        assert np.allclose(H[i].numpy(), Hi, rtol=1e-12, atol=1e-9)
+
+
+def test_p5_hessian_of_a_ramp():
+    a = 2.5
+    J = torch.arange(30, dtype=F64)[None, :].repeat(30, 1) * a
+    Gx, Gy = O.sobel8(J)
+    res = O.inverse_search(J, Gx, Gy, J, torch.tensor([10]), torch.tensor([10]), torch.zeros(1, 2, dtype=F64),
+                           params(gn_iters=0))
+    assert torch.allclose(res.hessian[0], torch.tensor([[64 * a * a, 0.0], [0.0, 0.0]], dtype=F64))
+
+
+# ------------------------------------------------------------------ P6 -------
+@pytest.mark.parametrize("ps", [8, 12])
+@pytest.mark.parametrize("noise,tol", [(0.0, 1e-2), (0.5, 5e-2)])
+def test_p6_inverse_search_agrees_with_forward_additive_and_brute_force(ps, noise, tol):
+    t = (0.37, -0.62)
+    n = ps + 16
+    J0 = 255 * analytic_texture(n, n, seed=6, min_period=10.0)
+    J1 = 255 * analytic_texture(n, n, shift=t, seed=6, min_period=10.0)
+    if noise:
+        J1 = J1 + torch.from_numpy(np.random.default_rng(7).normal(0, noise, J1.shape))
+    x0 = y0 = 8
+    Gx, Gy = O.sobel8(J0)
+    ic = O.inverse_search(J0, Gx, Gy, J1, torch.tensor([x0]), torch.tensor([y0]),
+                          torch.zeros(1, 2, dtype=F64), params(gn_iters=60, patch_size=ps)).u[0]
+    fa = SC.forward_additive_lk(J0, J1, x0, y0, ps, [0.0, 0.0], iters=60)
+    bf = SC.brute_force(J0, J1, x0, y0, ps, t, radius=1.0)
+    assert (ic - bf).norm() < tol, (ic, bf)
+    assert (fa - bf).norm() < 0.01, (fa, bf)
+    assert (ic - fa).norm() < tol
+
+
+# ------------------------------------------------------------------ P7 -------
+def test_p7_constant_offset_of_second_frame_does_not_change_flow():
+    from paper_1603_03590_amd import synth
+    pr = synth.smooth_bump_pair(128, 96, 6.0, 11)
+    I0 = torch.from_numpy(pr.I0).to(F64)
+    I1 = torch.from_numpy(pr.I1).to(F64)
+    for sf in (0, 1):
+        p = params(refine=False, coarsest_scale=3, finest_scale=sf)
+        U = O.dis_flow(I0, I1, p)
+        U2 = O.dis_flow(I0, I1 + 0.137, p)
+        assert (U - U2).abs().max() < 1e-12
+
+
+# ------------------------------------------------------------------ P8 -------
+def test_p8_reset_of_a_diverging_patch():
+    rng = np.random.default_rng(8)
+    h, w = 32, 32
+    # a nearly flat template (tiny H) against a strongly textured second frame
+    J0 = torch.from_numpy(100.0 + 0.02 * rng.standard_normal((h, w)))
+    J1 = torch.from_numpy(ndi.gaussian_filter(rng.standard_normal((h, w)), 1.0) * 80 + 100)
+    Gx, Gy = O.sobel8(J0)
+    uinit = torch.tensor([[0.3, -0.2], [1.0, 2.0]], dtype=F64)
+    res = O.inverse_search(J0, Gx, Gy, J1, torch.tensor([8, 16]), torch.tensor([8, 16]), uinit, params(gn_iters=4))
+    moved = (res.u_search - uinit).norm(dim=1)
+    assert (moved > 8).all()                       # the search ran away ...
+    assert res.reset.all()
+    assert torch.equal(res.u, uinit)               # ... and was reset to its start
+
+
+def test_p8_no_reset_when_within_patch_size():
+    I0 = analytic_texture(64, 64, seed=9, min_period=8.0, n=24)
+    I1 = analytic_texture(64, 64, shift=(1.5, -0.5), seed=9, min_period=8.0, n=24)
+    J0, J1 = 255 * I0, 255 * I1
+    Gx, Gy = O.sobel8(J0)
+    x0, y0, _, _ = O.patch_grid(64, 64, params())
+    res = O.inverse_search(J0, Gx, Gy, J1, x0, y0, torch.zeros(len(x0), 2, dtype=F64), params())
+    assert not res.reset.any()
+    assert torch.equal(res.u, res.u_search)
+    # short-period texture: bilinear interpolation error keeps this at ~0.05 px
+    assert (res.u - torch.tensor([1.5, -0.5], dtype=F64)).norm(dim=1).median() < 0.1
+
+
+# ------------------------------------------------------------------ P9 -------
+def test_p9_densification_is_a_normalised_average():
+    rng = np.random.default_rng(10)
+    w, h = 37, 29
+    p = params(patch_size=8, overlap=0.5)
+    x0, y0, nx, ny = O.patch_grid(w, h, p)
+    n = len(x0)
+    d = torch.from_numpy(rng.normal(0, 5, (n, 64)))
+    c = torch.tensor([1.25, -3.5], dtype=F64)
+    U, Z = O.densify(w, h, x0, y0, c.repeat(n, 1), d, p)
+    assert (U[0] - c[0]).abs().max() < 1e-13 and (U[1] - c[1]).abs().max() < 1e-13
+    u = torch.from_numpy(rng.normal(0, 3, (n, 2)))
+    U, Z = O.densify(w, h, x0, y0, u, d, p)
+    # convex combination of the covering patches
+    lo = torch.full((2, h, w), float("inf"), dtype=F64)
+    hi = torch.full((2, h, w), -float("inf"), dtype=F64)
+    for i in range(n):
+        X, Y = int(x0[i]), int(y0[i])
+        for k in range(2):
+            lo[k, Y:Y + 8, X:X + 8] = torch.minimum(lo[k, Y:Y + 8, X:X + 8], u[i, k])
+            hi[k, Y:Y + 8, X:X + 8] = torch.maximum(hi[k, Y:Y + 8, X:X + 8], u[i, k])
+    assert (U >= lo - 1e-12).all() and (U <= hi + 1e-12).all()
+    # the top-left pixel is covered by patch 0 alone
+    assert torch.allclose(U[:, 0, 0], u[0], atol=0, rtol=1e-15)
+    # the weight of a residual below 1 is 1, of |d| > 1 is 1/|d|: check one pixel by hand
+    y, x = 5, 6
+    cov = [i for i in range(n) if x0[i] <= x < x0[i] + 8 and y0[i] <= y < y0[i] + 8]
+    wts = [1.0 / max(1.0, abs(float(d[i, (y - y0[i]) * 8 + (x - x0[i])]))) for i in cov]
+    ref = sum(wt * float(u[i, 0]) for wt, i in zip(wts, cov)) / sum(wts)
+    assert abs(float(U[0, y, x]) - ref) < 1e-12
+
+
+# ------------------------------------------------------------------ P10 ------
+@pytest.mark.parametrize("w,h,ps,ov", [(128, 54, 8, 0.4), (37, 29, 8, 0.3), (64, 48, 12, 0.75), (20, 9, 8, 0.0)])
+def test_p10_grid_covers_every_pixel(w, h, ps, ov):
+    p = params(patch_size=ps, overlap=ov)
+    st = O.grid_stride(p)
+    x0, y0, nx, ny = O.patch_grid(w, h, p)
+    assert len(x0) == (math.ceil((w - ps) / st) + 1) * (math.ceil((h - ps) / st) + 1)
+    cov = torch.zeros(h, w, dtype=torch.long)
+    for X, Y in zip(x0.tolist(), y0.tolist()):
+        assert 0 <= X <= w - ps and 0 <= Y <= h - ps
+        cov[Y:Y + ps, X:X + ps] += 1
+    assert (cov > 0).all()
+
+
+def test_p10_paper_patch_count_at_scale_3():
+    g = json.load(open(GOLDEN))["patch_count_scale3_sintel"]
+    w, h = g["level_size"]
+    p = params(patch_size=g["patch_size"], overlap=g["overlap"], grid="overhang")
+    x0, _, _, _ = O.patch_grid(w, h, p)
+    assert len(x0) == g["value"]
+    assert O.level_sizes(1024, 436, 3)[-1] == (w, h)
+
+
+# ------------------------------------------------------------------ P11 ------
+def test_p11_coarsest_scale_rule_matches_paper():
+    g = json.load(open(GOLDEN))
+    s = g["coarsest_scale_sintel"]
+    for ps in s["patch_sizes"]:
+        assert O.auto_coarsest_scale(s["width"], ps) == s["value"]
+    k = g["coarsest_scale_kitti"]
+    for w in k["widths"]:
+        assert O.auto_coarsest_scale(w, k["patch_size"]) == k["value"]
+    # the clamp keeps the coarsest level at least one patch tall
+    assert O.coarsest_scale(1242, 375, params(coarsest_scale=-1)) == 5
+    assert O.coarsest_scale(32, 32, params(coarsest_scale=3)) == 2
+
+
+# ------------------------------------------------------------------ P12 ------
+def _level_problem(seed=12, h=40, w=48):
+    from paper_1603_03590_amd import synth
+    pr = synth.smooth_bump_pair(w, h, 3.0, seed)
+    J0 = 255 * torch.from_numpy(pr.I0).to(F64)
+    J1 = 255 * torch.from_numpy(pr.I1).to(F64)
+    rng = np.random.default_rng(seed)
+    U = torch.from_numpy(pr.flow + rng.normal(0, 0.3, pr.flow.shape))
+    return J0, J1, U
+
+
+def test_p12_refinement_energies_non_increasing():
+    J0, J1, U = _level_problem()
+    p = params(var_inner=5)
+    log = []
+
+    def trace(kind, k, t, sys, du, dv):
+        log.append((kind, k, float(O.quadratic_energy(sys, U, du, dv)),
+                    float(O.linearised_energy(t, U, du, dv, p))))
+
+    O.refine(J0, J1, U, 6, p, trace)
+    starts = {}
+    prev_q = None
+    for kind, k, q, e in log:
+        if kind == "outer":
+            starts[k] = e
+            if k > 0:
+                assert e <= starts[k - 1] * (1 + 1e-13)       # across fixed-point iterations
+            prev_q = q
+        else:
+            assert q <= prev_q + 1e-9 * abs(prev_q)            # majoriser after each half sweep
+            prev_q = q
+            assert e <= starts[k] * (1 + 1e-13)                # robust energy below its start
+    assert log[-1][3] < log[0][3]
+
+
+# ------------------------------------------------------------------ P13 ------
+def test_p13_many_sor_sweeps_solve_the_frozen_system():
+    J0, J1, U = _level_problem(seed=13, h=14, w=17)
+    p = params()
+    t = O.refine_linearise(J0, J1, U)
+    zero = torch.zeros_like(U[0])
+    sys = O.sor_system(t, U, zero, zero, p)
+    du, dv = O.sor_sweeps(sys, U, zero, zero, 2000, p.sor_omega)
+    # assemble the normal equations of the quadratic independently
+    h, w = U.shape[1:]
+    n = h * w
+    idx = lambda y, x: y * w + x
+    rows, cols, vals = [], [], []
+    rhs = np.zeros(2 * n)
+    A11, A12, A22 = sys.A11.numpy(), sys.A12.numpy(), sys.A22.numpy()
+    b1, b2, ws = sys.b1.numpy(), sys.b2.numpy(), sys.ws.numpy()
+    Un, Vn = U[0].numpy(), U[1].numpy()
+    diag = np.zeros(2 * n)
+    for y in range(h):
+        for x in range(w):
+            i = idx(y, x)
+            rows += [i, n + i]
+            cols += [n + i, i]
+            vals += [A12[y, x], A12[y, x]]
+            diag[i] += A11[y, x]
+            diag[n + i] += A22[y, x]
+            rhs[i] -= b1[y, x]
+            rhs[n + i] -= b2[y, x]
+            for (yy, xx) in ((y, x + 1), (y + 1, x)):
+                if yy < h and xx < w:
+                    j = idx(yy, xx)
+                    wt = ws[y, x]
+                    for off, F in ((0, Un), (n, Vn)):
+                        diag[off + i] += wt
+                        diag[off + j] += wt
+                        rows += [off + i, off + j]
+                        cols += [off + j, off + i]
+                        vals += [-wt, -wt]
+                        rhs[off + i] += wt * (F[yy, xx] - F[y, x])
+                        rhs[off + j] += wt * (F[y, x] - F[yy, xx])
+    M = sp.csr_matrix((vals + list(diag), (rows + list(range(2 * n)), cols + list(range(2 * n)))), shape=(2 * n, 2 * n))
+    sol = spla.spsolve(M, rhs)
+    assert np.allclose(du.numpy().ravel(), sol[:n], atol=1e-8)
+    assert np.allclose(dv.numpy().ravel(), sol[n:], atol=1e-8)
+
+
+# ------------------------------------------------------------------ P14 ------
+def test_p14_without_smoothness_pixels_decouple():
+    J0, J1, U = _level_problem(seed=14, h=12, w=15)
+    p = params(alpha=0.0)
+    t = O.refine_linearise(J0, J1, U)
+    zero = torch.zeros_like(U[0])
+    sys = O.sor_system(t, U, zero, zero, p)
+    # some pixels are nearly rank one (A12^2 / (A11 A22) ~ 0.99): give them time
+    du, dv = O.sor_sweeps(sys, U, zero, zero, 2000, p.sor_omega)
+    det = sys.A11 * sys.A22 - sys.A12 ** 2
+    ref_u = (-sys.b1 * sys.A22 + sys.b2 * sys.A12) / det
+    ref_v = (-sys.b2 * sys.A11 + sys.b1 * sys.A12) / det
+    assert torch.allclose(du, ref_u, atol=1e-9, rtol=1e-7)
+    assert torch.allclose(dv, ref_v, atol=1e-9, rtol=1e-7)
+
+
+def test_p14_constant_flow_without_temporal_terms_is_a_fixed_point():
+    J0, J1, U = _level_problem(seed=15, h=12, w=15)
+    U = torch.stack([torch.full_like(U[0], 1.75), torch.full_like(U[1], -0.5)])
+    t = O.refine_linearise(J0, J1, U)
+    t.Iz = torch.zeros_like(t.Iz)
+    t.Ixz = torch.zeros_like(t.Ixz)
+    t.Iyz = torch.zeros_like(t.Iyz)
+    zero = torch.zeros_like(U[0])
+    sys = O.sor_system(t, U, zero, zero, params())
+    du, dv = O.sor_sweeps(sys, U, zero, zero, 5, 1.6)
+    assert torch.count_nonzero(du) == 0 and torch.count_nonzero(dv) == 0
+
+
+# ------------------------------------------------------------------ P15 ------
+def test_p15_pyramid_box_means_by_hand():
+    J = torch.tensor([[1., 2., 3., 4., 9.],
+                      [5., 6., 7., 8., 9.],
+                      [9., 10., 11., 12., 9.],
+                      [13., 14., 15., 16., 9.],
+                      [7., 7., 7., 7., 7.]], dtype=F64)
+    L = O.build_pyramid(J, 2)
+    assert torch.equal(L[1], torch.tensor([[3.5, 5.5], [11.5, 13.5]], dtype=F64))
+    assert torch.equal(L[2], torch.tensor([[8.5]], dtype=F64))
+    assert O.level_sizes(1024, 436, 5) == [(1024, 436), (512, 218), (256, 109), (128, 54), (64, 27), (32, 13)]
+
+
+def test_p15_upsampling_a_constant_field():
+    U = torch.stack([torch.full((6, 7), 0.75, dtype=F64), torch.full((6, 7), -2.0, dtype=F64)])
+    for s in (1, 2, 3):
+        up = O.upsample(U, 7 * 2 ** s + 1, 6 * 2 ** s + 3, s, params())
+        assert torch.equal(up[0], torch.full_like(up[0], 0.75 * 2 ** s))
+        assert torch.equal(up[1], torch.full_like(up[1], -2.0 * 2 ** s))
+
+
+# ------------------------------------------------------------------ P16 ------
+def test_p16_transposing_the_frames_transposes_the_flow():
+    from paper_1603_03590_amd import synth
+    pr = synth.smooth_bump_pair(96, 96, 5.0, 16)
+    I0 = torch.from_numpy(pr.I0).to(F64)
+    I1 = torch.from_numpy(pr.I1).to(F64)
+    p = params(refine=False, coarsest_scale=3, finest_scale=0)
+    U = O.dis_flow(I0, I1, p)
+    Ut = O.dis_flow(I0.T.contiguous(), I1.T.contiguous(), p)
+    assert (Ut[0].T - U[1]).abs().max() < 1e-9
+    assert (Ut[1].T - U[0]).abs().max() < 1e-9
+
+
+# ------------------------------------------------------------ gradient -------
+def test_oracle_autograd_matches_finite_differences():
+    """The oracle's autograd gradient (the reference for the adjoint) agrees
+    with central differences of the oracle itself."""
+    from paper_1603_03590_amd import synth
+    pr = synth.smooth_bump_pair(32, 32, 2.0, 17)
+    I0 = torch.from_numpy(pr.I0).to(F64).requires_grad_(True)
+    I1 = torch.from_numpy(pr.I1).to(F64).requires_grad_(True)
+    gt = torch.from_numpy(pr.flow)
+    p = params(coarsest_scale=2, finest_scale=0, gn_iters=6, var_outer=2)
+
+    def loss(a, b):
+        return O.endpoint_error(O.dis_flow(a, b, p), gt).mean()
+
+    L = loss(I0, I1)
+    g0, g1 = torch.autograd.grad(L, (I0, I1))
+    rng = np.random.default_rng(18)
+    hstep = 1e-6
+    for img, g in ((I0, g0), (I1, g1)):
+        for _ in range(6):
+            y, x = rng.integers(2, 30, 2)
+            e = torch.zeros_like(img)
+            e[y, x] = hstep
+            with torch.no_grad():
+                fd = (loss(I0 + (e if img is I0 else 0), I1 + (e if img is I1 else 0))
+                      - loss(I0 - (e if img is I0 else 0), I1 - (e if img is I1 else 0))) / (2 * hstep)
+            assert abs(float(fd) - float(g[y, x])) < 1e-6 + 1e-4 * abs(float(fd)), (float(fd), float(g[y, x]))
+
+
+# ------------------------------------------------------- extra pins ---------
+def test_p8_reset_threshold_is_the_patch_size():
+    """A patch that ends between theta_ps/2 and theta_ps from its start keeps
+    its result; the reset needs more than theta_ps (Sec. 2.2 step 4)."""
+    t = (6.0, 1.5)
+    J0 = 255 * analytic_texture(64, 64, seed=19, min_period=20.0, n=6)
+    J1 = 255 * analytic_texture(64, 64, shift=t, seed=19, min_period=20.0, n=6)
+    Gx, Gy = O.sobel8(J0)
+    x0, y0 = torch.tensor([28]), torch.tensor([28])
+    res = O.inverse_search(J0, Gx, Gy, J1, x0, y0, torch.zeros(1, 2, dtype=F64), params(gn_iters=100))
+    moved = float(res.u_search[0].norm())
+    assert 4.0 < moved < 8.0
+    assert not res.reset.any()
+    assert (res.u[0] - torch.tensor(t, dtype=F64)).norm() < 0.05
+
+
+def test_p15_refinement_derivatives_exact_on_quadratics():
+    """Central differences are exact for quadratics, so on I0 = q0(x, y),
+    I1 = q1(x, y) with U = 0 every linearisation term of Sec. 2.3 equals the
+    analytic derivative away from the border."""
+    h, w = 20, 24
+    yy, xx = torch.meshgrid(torch.arange(h, dtype=F64), torch.arange(w, dtype=F64), indexing="ij")
+    q0 = 0.3 * xx * xx - 0.2 * xx * yy + 0.1 * yy * yy + 2 * xx - yy + 50
+    q1 = 0.25 * xx * xx + 0.15 * xx * yy - 0.12 * yy * yy - xx + 3 * yy + 40
+    t = O.refine_linearise(q0, q1, torch.zeros(2, h, w, dtype=F64))
+    ib = lambda f: f[2:-2, 2:-2]
+    # mean image (q0+q1)/2 = 0.275 x^2 - 0.025 xy - 0.01 y^2 + 0.5 x + y + 45
+    assert torch.allclose(ib(t.Ix), ib(0.55 * xx - 0.025 * yy + 0.5), atol=1e-10)
+    assert torch.allclose(ib(t.Iy), ib(-0.025 * xx - 0.02 * yy + 1.0), atol=1e-10)
+    assert torch.allclose(ib(t.Iz), ib(q1 - q0), atol=1e-10)
+    assert torch.allclose(ib(t.Ixx), torch.full_like(ib(xx), 0.55), atol=1e-10)
+    assert torch.allclose(ib(t.Ixy), torch.full_like(ib(xx), -0.025), atol=1e-10)
+    assert torch.allclose(ib(t.Iyy), torch.full_like(ib(xx), -0.02), atol=1e-10)
+    # d/dx (q1 - q0) and d/dy (q1 - q0)
+    assert torch.allclose(ib(t.Ixz), ib(-0.1 * xx + 0.35 * yy - 3.0), atol=1e-10)
+    assert torch.allclose(ib(t.Iyz), ib(0.35 * xx - 0.44 * yy + 4.0), atol=1e-10)
+
+
+def test_p16_red_pixels_relax_first():
+    """R16: the first half sweep moves only pixels with x + y even."""
+    J0, J1, U = _level_problem(seed=20, h=9, w=11)
+    p = params()
+    t = O.refine_linearise(J0, J1, U)
+    zero = torch.zeros_like(U[0])
+    sys = O.sor_system(t, U, zero, zero, p)
+    seen = []
+    O.sor_sweeps(sys, U, zero, zero, 1, p.sor_omega, lambda a, b: seen.append((a.clone(), b.clone())))
+    yy, xx = torch.meshgrid(torch.arange(9), torch.arange(11), indexing="ij")
+    black = (xx + yy) % 2 == 1
+    du1, dv1 = seen[0]
+    assert torch.count_nonzero(du1[black]) == 0 and torch.count_nonzero(dv1[black]) == 0
+    assert torch.count_nonzero(du1[~black]) > 0
+    du2, _ = seen[1]
+    assert torch.equal(du2[~black], du1[~black])
+
+
+def test_refinement_pulls_a_perturbed_flow_towards_the_truth():
+    """On a globally translated pair, refining U = t + e reduces the error
+    (checks the sign of the temporal derivatives)."""
+    t = (2.25, -1.5)
+    J0 = 255 * analytic_texture(48, 56, seed=21, min_period=12.0, n=16)
+    J1 = 255 * analytic_texture(48, 56, shift=t, seed=21, min_period=12.0, n=16)
+    U = torch.stack([torch.full((48, 56), t[0] + 0.3, dtype=F64), torch.full((48, 56), t[1] - 0.2, dtype=F64)])
+    e0 = math.hypot(0.3, 0.2)
+    errs = []
+    for n_outer in (1, 3, 6):
+        R = O.refine(J0, J1, U, n_outer, params())
+        errs.append(float(torch.sqrt((R[0] - t[0]) ** 2 + (R[1] - t[1]) ** 2)[6:-6, 6:-6].mean()))
+    assert errs[0] < e0 and errs[1] < errs[0] and errs[2] < 0.6 * e0, errs
