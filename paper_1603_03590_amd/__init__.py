@@ -1,0 +1,135 @@
+"""Dense Inverse Search optical flow (Kroeger et al., ECCV 2016) on AMD MI355X.
+
+Every step of the method runs in the HIP kernels of ``libdis.so``; this
+module marshals torch tensors (device memory and the current HIP stream) into
+the C entry points of include/dis.h.  There is no CPU fallback: without the
+built library or a GPU these functions raise.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib
+from ._lib import (DisError, DisLibraryMissing, dis_params, DIS_FLAG_KEEP_FOR_BACKWARD, DIS_FLAG_NO_GRAPH,
+                   DIS_FLAG_PIXEL_CENTRE, DIS_FLAG_RAW_RESIDUAL, DIS_FLAG_IO_F64)
+
+__all__ = ["DIS", "params", "compute_flow", "DisError", "DisLibraryMissing", "dis_params",
+           "DIS_FLAG_KEEP_FOR_BACKWARD", "DIS_FLAG_NO_GRAPH", "DIS_FLAG_PIXEL_CENTRE",
+           "DIS_FLAG_RAW_RESIDUAL", "DIS_FLAG_IO_F64"]
+
+PRESETS = {"op1": 1, "op2": 2, "op3": 3, "op4": 4, "c1": 101, "c2a": 102, "c2b": 103, "c3": 104,
+           "c5": 105, "c4": 106}
+
+
+def params(preset=2, **overrides) -> dis_params:
+    """Parameter block from a preset (int or name in PRESETS) plus overrides."""
+    if isinstance(preset, str):
+        preset = PRESETS[preset]
+    p = _lib.dis_default_params(int(preset))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, int(v) if isinstance(v, bool) else v)
+    return p
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class DIS:
+    """A handle: all device scratch for frames up to max_w x max_h and up to
+    ``max_batch`` pairs, bound to a HIP stream (default: torch's current)."""
+
+    def __init__(self, p: dis_params, max_w: int, max_h: int, max_batch: int = 1, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("DIS needs a visible GPU")
+        self.p = p
+        self.max_w, self.max_h = max_w, max_h
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.handle = _lib.dis_create(p, max_w, max_h, max_batch, self.stream.cuda_stream)
+        self.dtype = torch.float64 if (p.flags & DIS_FLAG_IO_F64) else torch.float32
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.dis_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _frame(self, I):
+        torch = _torch()
+        if I.dtype != self.dtype or I.device.type != "cuda" or I.dim() != 2:
+            raise ValueError(f"frames must be 2-D {self.dtype} tensors on the GPU")
+        if I.stride(1) != 1:
+            raise ValueError("frames must have unit column stride")
+        return I
+
+    def flow(self, I0, I1, out=None):
+        """Dense flow [2, H, W] from I0 to I1 (device tensors, same shape)."""
+        torch = _torch()
+        I0 = self._frame(I0)
+        I1 = self._frame(I1)
+        if I0.shape != I1.shape or I0.stride() != I1.stride():
+            raise ValueError("frames must have the same shape and strides")
+        h, w = I0.shape
+        if out is None:
+            out = torch.empty((2, h, w), dtype=self.dtype, device=I0.device)
+        _lib.dis_compute_flow(self.handle, I0.data_ptr(), I1.data_ptr(), w, h, I0.stride(0), out.data_ptr())
+        return out
+
+    def flow_batched(self, I0s, I1s, outs=None):
+        """Flows of many pairs (lists of device tensors), one launch per level."""
+        torch = _torch()
+        I0s = [self._frame(a) for a in I0s]
+        I1s = [self._frame(b) for b in I1s]
+        if outs is None:
+            outs = [torch.empty((2,) + a.shape, dtype=self.dtype, device=a.device) for a in I0s]
+        _lib.dis_compute_flow_batched(self.handle, [a.data_ptr() for a in I0s], [b.data_ptr() for b in I1s],
+                                      [a.shape[1] for a in I0s], [a.shape[0] for a in I0s],
+                                      [a.stride(0) for a in I0s], [o.data_ptr() for o in outs])
+        return outs
+
+    def backward(self, grad_flow, shape):
+        """dL/dI0, dL/dI1 for the most recent forward (needs KEEP_FOR_BACKWARD)."""
+        torch = _torch()
+        g0 = torch.empty(shape, dtype=self.dtype, device=grad_flow.device)
+        g1 = torch.empty(shape, dtype=self.dtype, device=grad_flow.device)
+        _lib.dis_flow_backward(self.handle, grad_flow.contiguous().data_ptr(), g0.data_ptr(), g1.data_ptr())
+        return g0, g1
+
+    def autotune(self, cache_path=None):
+        _lib.dis_autotune(self.handle, cache_path)
+
+    def debug_level(self, s: int, what: int):
+        """Intermediate of the last forward at scale s as a float64 numpy array."""
+        info = np.zeros(6, np.int32)
+        _lib.dis_debug_level(self.handle, s, _lib.DIS_DBG_INFO, info.ctypes.data, info.nbytes)
+        W, H, N = int(info[0]), int(info[1]), int(info[2])
+        if what == _lib.DIS_DBG_INFO:
+            return info
+        shape = {_lib.DIS_DBG_J0: (H, W), _lib.DIS_DBG_J1: (H, W), _lib.DIS_DBG_UINIT: (N, 2),
+                 _lib.DIS_DBG_UPATCH: (N, 2), _lib.DIS_DBG_UDENSE: (2, H, W),
+                 _lib.DIS_DBG_UREFINED: (2, H, W)}[what]
+        out = np.zeros(shape, np.float64)
+        _lib.dis_debug_level(self.handle, s, what, out.ctypes.data, out.nbytes)
+        return out
+
+
+def compute_flow(I0, I1, p: dis_params | None = None):
+    """One-shot flow of a pair of device frames."""
+    p = p if p is not None else params(2)
+    h, w = I0.shape
+    d = DIS(p, w, h)
+    try:
+        out = d.flow(I0, I1)
+        d.stream.synchronize()
+        return out
+    finally:
+        d.close()

@@ -1,0 +1,597 @@
+// Host side of the Dense Inverse Search library: parameter validation, the
+// per-handle device arena, launch sequences per frame size, HIP graph replay.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "dis.h"
+#include "dis_internal.h"
+#include "dis_host.h"
+
+// ------------------------------------------------------------------ helpers
+
+static thread_local std::string g_null_err;
+
+static int fail(dis_handle* h, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+static int fail(dis_handle* h, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf; else g_null_err = buf;
+    return code;
+}
+
+#define HIPCHK(h, call)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((h), DIS_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));       \
+    } while (0)
+
+static bool is_supported_ps(int ps) { return ps >= 4 && ps <= 16 && ps % 2 == 0; }
+
+int dis_stride(const dis_params* p) {
+    const double s = std::floor((double)p->patch_size * (1.0 - p->overlap));
+    return s < 1.0 ? 1 : (int)s;
+}
+
+int dis_coarsest(const dis_params* p, int w, int h) {
+    int s;
+    if (p->coarsest_scale >= 0) {
+        s = p->coarsest_scale;
+    } else {
+        // smallest s with 2^s >= 2 w / (8 ps)   (Sec. 3.1 rule, f = 8)
+        s = 0;
+        while ((double)(1LL << s) * 8.0 * p->patch_size < 2.0 * w) ++s;
+    }
+    if (s > DIS_MAXL - 1) s = DIS_MAXL - 1;
+    while (s > 0 && ((w >> s) < p->patch_size || (h >> s) < p->patch_size)) --s;
+    return s;
+}
+
+void dis_grid(int n, int ps, int st, int* nr, int* ntot) {
+    *nr = (n - ps) / st + 1;
+    *ntot = *nr + (((n - ps) % st) != 0 ? 1 : 0);
+}
+
+static int validate_params(const dis_params* p) {
+    if (!p) return fail(nullptr, DIS_EINVAL, "params is NULL");
+    if (!is_supported_ps(p->patch_size))
+        return fail(nullptr, DIS_EINVAL, "patch_size %d unsupported (even, 4..16)", p->patch_size);
+    if (!(p->overlap >= 0.0 && p->overlap < 1.0))
+        return fail(nullptr, DIS_EINVAL, "overlap %g outside [0, 1)", p->overlap);
+    if (p->coarsest_scale < -1 || p->coarsest_scale >= DIS_MAXL)
+        return fail(nullptr, DIS_EINVAL, "coarsest_scale %d outside [-1, %d]", p->coarsest_scale, DIS_MAXL - 1);
+    if (p->finest_scale < 0 || p->finest_scale >= DIS_MAXL)
+        return fail(nullptr, DIS_EINVAL, "finest_scale %d outside [0, %d]", p->finest_scale, DIS_MAXL - 1);
+    if (p->coarsest_scale >= 0 && p->finest_scale > p->coarsest_scale)
+        return fail(nullptr, DIS_EINVAL, "finest_scale %d above coarsest_scale %d", p->finest_scale,
+                    p->coarsest_scale);
+    if (p->gn_iters < 0 || p->gn_iters > 100000)
+        return fail(nullptr, DIS_EINVAL, "gn_iters %d outside [0, 100000]", p->gn_iters);
+    if (p->refine) {
+        if (p->var_outer < -1 || p->var_outer > 1000)
+            return fail(nullptr, DIS_EINVAL, "var_outer %d outside [-1, 1000]", p->var_outer);
+        if (p->var_inner < 1 || p->var_inner > 100000)
+            return fail(nullptr, DIS_EINVAL, "var_inner %d outside [1, 100000]", p->var_inner);
+        if (!(p->sor_omega > 0.0 && p->sor_omega < 2.0))
+            return fail(nullptr, DIS_EINVAL, "sor_omega %g outside (0, 2)", p->sor_omega);
+        if (!(p->w_intensity >= 0.0) || !(p->w_gradient >= 0.0) || !(p->w_smooth >= 0.0))
+            return fail(nullptr, DIS_EINVAL, "refinement weights must be >= 0");
+    }
+    if (p->refine != 0 && p->refine != 1) return fail(nullptr, DIS_EINVAL, "refine must be 0 or 1");
+    const uint32_t known = DIS_FLAG_KEEP_FOR_BACKWARD | DIS_FLAG_NO_GRAPH | DIS_FLAG_PIXEL_CENTRE |
+                           DIS_FLAG_RAW_RESIDUAL | DIS_FLAG_IO_F64;
+    if (p->flags & ~known) return fail(nullptr, DIS_EINVAL, "unknown flag bits 0x%x", p->flags & ~known);
+    return DIS_OK;
+}
+
+// ------------------------------------------------------------------ presets
+
+extern "C" int dis_default_params(int preset, dis_params* out) {
+    if (!out) return fail(nullptr, DIS_EINVAL, "out is NULL");
+    dis_params p;
+    std::memset(&p, 0, sizeof p);
+    p.coarsest_scale = 5;
+    p.var_outer = -1;
+    p.var_inner = 5;
+    p.w_intensity = 5.0;
+    p.w_gradient = 10.0;
+    p.w_smooth = 10.0;
+    p.sor_omega = 1.6;
+    p.refine = 1;
+    p.flags = 0;
+    switch (preset) {
+        case 1: p.finest_scale = 3; p.gn_iters = 16; p.patch_size = 8; p.overlap = 0.3; p.refine = 0; break;
+        case 2: p.finest_scale = 3; p.gn_iters = 12; p.patch_size = 8; p.overlap = 0.4; break;
+        case 3: p.finest_scale = 1; p.gn_iters = 16; p.patch_size = 12; p.overlap = 0.75; break;
+        case 4: p.finest_scale = 0; p.gn_iters = 256; p.patch_size = 12; p.overlap = 0.75; break;
+        case 101: p.patch_size = 8; p.overlap = 0.3; p.coarsest_scale = 2; p.finest_scale = 0;
+                  p.gn_iters = 8; p.var_outer = 1; break;
+        case 102: p.patch_size = 8; p.overlap = 0.3; p.finest_scale = 3; p.gn_iters = 12; break;
+        case 103: p.patch_size = 8; p.overlap = 0.5; p.finest_scale = 3; p.gn_iters = 16; break;
+        case 104: p.patch_size = 12; p.overlap = 0.75; p.coarsest_scale = 4; p.finest_scale = 0;
+                  p.gn_iters = 128; p.var_outer = 5; break;
+        case 105: p.patch_size = 8; p.overlap = 0.5; p.coarsest_scale = 3; p.finest_scale = 0;
+                  p.gn_iters = 16; p.var_outer = 3; break;
+        case 106: p.patch_size = 8; p.overlap = 0.5; p.coarsest_scale = -1; p.finest_scale = 3;
+                  p.gn_iters = 16; break;
+        default: return fail(nullptr, DIS_EINVAL, "unknown preset %d", preset);
+    }
+    *out = p;
+    return DIS_OK;
+}
+
+// ------------------------------------------------------------------- arena
+
+static int dalloc(dis_handle* h, void** ptr, size_t bytes) {
+    *ptr = nullptr;
+    if (bytes == 0) return DIS_OK;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+            return fail(h, DIS_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        return fail(h, DIS_EHIP, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    h->allocs.push_back(*ptr);
+    return DIS_OK;
+}
+
+#define DALLOC(h, ptr, bytes)                                      \
+    do {                                                           \
+        int r_ = dalloc((h), (void**)&(ptr), (bytes));             \
+        if (r_ != DIS_OK) return r_;                               \
+    } while (0)
+
+static int alloc_slot(dis_handle* h, SlotBuf& sb) {
+    const dis_params& p = h->p;
+    const int W = h->max_w, H = h->max_h, ps = p.patch_size, st = h->st;
+    std::memset(&sb, 0, sizeof sb);
+    for (int s = 0; s <= h->top; ++s) {
+        LevelBuf& L = sb.lv[s];
+        const int ws = W >> s, hs = H >> s;
+        const size_t px = (size_t)ws * hs;
+        // level images: every level >= 1 (later pyramid passes start from a
+        // stored level); level 0 only when it is processed
+        if (s >= 1 || p.finest_scale == 0) {
+            DALLOC(h, L.J0, px * sizeof(double));
+            DALLOC(h, L.J1, px * sizeof(double));
+        }
+        if (s >= p.finest_scale && ws >= ps && hs >= ps) {
+            const int nx = (ws - ps) / st + 2, ny = (hs - ps) / st + 2;
+            L.maxN = nx * ny;
+            DALLOC(h, L.patch, (size_t)L.maxN * 4 * sizeof(double));
+            DALLOC(h, L.uinit, (size_t)L.maxN * 2 * sizeof(double));
+            DALLOC(h, L.U, 2 * px * sizeof(double));
+            if (p.refine) DALLOC(h, L.Ud, 2 * px * sizeof(double));
+            else L.Ud = L.U;
+        }
+    }
+    const int sf = p.finest_scale;
+    const size_t pf = (size_t)(W >> sf) * (H >> sf);
+    if (p.refine) {
+        DALLOC(h, sb.J1w, pf * sizeof(double));
+        DALLOC(h, sb.D, 11 * pf * sizeof(double));
+        for (int i = 0; i < 3; ++i) DALLOC(h, sb.dU[i], 2 * pf * sizeof(double));
+    }
+    return DIS_OK;
+}
+
+extern "C" int dis_create(const dis_params* p, int max_w, int max_h, int max_batch, void* stream,
+                          dis_handle** out) {
+    if (!out) return fail(nullptr, DIS_EINVAL, "out is NULL");
+    *out = nullptr;
+    int r = validate_params(p);
+    if (r != DIS_OK) return r;
+    if (max_batch < 1 || max_batch > 4096) return fail(nullptr, DIS_EINVAL, "max_batch %d outside [1, 4096]", max_batch);
+    if (max_w < 1 || max_h < 1 || max_w > 65536 || max_h > 65536)
+        return fail(nullptr, DIS_EINVAL, "max size %dx%d invalid", max_w, max_h);
+    if ((max_w >> p->finest_scale) < p->patch_size || (max_h >> p->finest_scale) < p->patch_size)
+        return fail(nullptr, DIS_ESIZE, "%dx%d at scale %d is smaller than the %d px patch", max_w, max_h,
+                    p->finest_scale, p->patch_size);
+    dis_handle* h = new dis_handle();
+    h->p = *p;
+    h->max_w = max_w;
+    h->max_h = max_h;
+    h->max_batch = max_batch;
+    h->stream = (hipStream_t)stream;
+    h->st = dis_stride(p);
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail(nullptr, DIS_EHIP, "hipGetDevice failed");
+    }
+    int top = 0;
+    while (top + 1 < DIS_MAXL && (max_w >> (top + 1)) >= p->patch_size && (max_h >> (top + 1)) >= p->patch_size) ++top;
+    h->top = top;
+    for (int s = 0; s < DIS_MAXL; ++s) h->lpp[s] = 0;
+    h->refine_tile = 0;
+    h->slots.resize(max_batch);
+    for (int i = 0; i < max_batch; ++i) {
+        r = alloc_slot(h, h->slots[i]);
+        if (r != DIS_OK) {
+            g_null_err = h->err;
+            dis_destroy(h);
+            return r;
+        }
+    }
+    *out = h;
+    return DIS_OK;
+}
+
+extern "C" void dis_destroy(dis_handle* h) {
+    if (!h) return;
+    if (h->stream || true) hipStreamSynchronize(h->stream);
+    for (auto& kv : h->plans) {
+        Plan* pl = kv.second;
+        if (pl->exec) hipGraphExecDestroy(pl->exec);
+        if (pl->graph) hipGraphDestroy(pl->graph);
+        delete pl;
+    }
+    for (auto& kv : h->bplans) {
+        BatchPlan* bp = kv.second;
+        dis_batch_plan_free(bp);
+    }
+    for (void* ptr : h->allocs) hipFree(ptr);
+    delete h;
+}
+
+extern "C" const char* dis_last_error(const dis_handle* h) {
+    return h ? h->err.c_str() : g_null_err.c_str();
+}
+
+extern "C" int dis_set_stream(dis_handle* h, void* stream) {
+    if (!h) return fail(nullptr, DIS_EINVAL, "handle is NULL");
+    h->stream = (hipStream_t)stream;
+    return DIS_OK;
+}
+
+// ------------------------------------------------------------ launch lists
+
+void Seq::add(const void* fn, dim3 grid, dim3 block, const void* arg, size_t bytes, int kind) {
+    Launch L;
+    L.fn = fn;
+    L.grid = grid;
+    L.block = block;
+    L.arg.assign((const char*)arg, (const char*)arg + bytes);
+    L.kind = kind;
+    items.push_back(std::move(L));
+}
+
+int dis_pick_lpp(const dis_handle* h, int s, int N) {
+    const int ps = h->p.patch_size;
+    if (h->lpp[s] && dis_kernel_search(ps, h->lpp[s])) return h->lpp[s];
+    // many patches: fewest lanes per patch available (less shuffle work per
+    // pixel); few patches: 16 lanes (shorter dependent chain per patch)
+    if (N >= 16384)
+        for (int l = 4; l <= 16; l *= 2)
+            if (dis_kernel_search(ps, l)) return l;
+    return 16;
+}
+
+static int grid_info(const dis_handle* h, int W, int H, LevelGrid* g) {
+    const int ps = h->p.patch_size;
+    g->W = W;
+    g->H = H;
+    g->st = h->st;
+    dis_grid(W, ps, h->st, &g->nrx, &g->nx);
+    dis_grid(H, ps, h->st, &g->nry, &g->ny);
+    return g->nx * g->ny;
+}
+
+// Launch sequence of one pair (Alg. 1) into slot `sb`.  Kind 1 launches read
+// the caller's frames, kind 2 write the caller's flow.
+int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const void* I0, const void* I1,
+                   void* flow, Seq& seq, PairInfo* info) {
+    const dis_params& p = h->p;
+    const int ps = p.patch_size;
+    const int ss = dis_coarsest(&p, w, hgt), sf = p.finest_scale;
+    if (sf > ss || (w >> sf) < ps || (hgt >> sf) < ps)
+        return fail(h, DIS_ESIZE, "%dx%d: scale %d is smaller than the %d px patch", w, hgt, sf, ps);
+    if (info) { info->ss = ss; info->sf = sf; }
+    const bool f64io = (p.flags & DIS_FLAG_IO_F64) != 0;
+    const int cmap = (p.flags & DIS_FLAG_PIXEL_CENTRE) ? 1 : 0;
+
+    // pyramid passes: levels a+1 .. a+5 from level a
+    for (int a = 0; a < ss; a += 5) {
+        PyrArgs pa;
+        std::memset(&pa, 0, sizeof pa);
+        const int w0 = w >> a, h0 = hgt >> a;
+        pa.a = a;
+        pa.nlev = std::min(5, ss - a);
+        pa.w0 = w0;
+        pa.h0 = h0;
+        if (a == 0) {
+            pa.src[0] = I0;
+            pa.src[1] = I1;
+            pa.src_kind = f64io ? 2 : 1;
+            pa.src_pitch = pitch;
+            pa.scale = 255.0;
+            if (sf == 0) { pa.lvl0[0] = sb.lv[0].J0; pa.lvl0[1] = sb.lv[0].J1; }
+        } else {
+            pa.src[0] = sb.lv[a].J0;
+            pa.src[1] = sb.lv[a].J1;
+            pa.src_kind = 0;
+            pa.src_pitch = w0;
+            pa.scale = 1.0;
+        }
+        for (int k = 1; k <= pa.nlev; ++k) {
+            const int s = a + k;
+            pa.ws[k] = w >> s;
+            pa.hs[k] = hgt >> s;
+            // keep the levels that are processed, and the start of the next pass
+            if (s >= sf || (s == a + 5 && s < ss)) { pa.dst[0][k] = sb.lv[s].J0; pa.dst[1][k] = sb.lv[s].J1; }
+        }
+        pa.tiles_x = (w0 + 31) / 32;
+        const int tiles = pa.tiles_x * ((h0 + 31) / 32);
+        seq.add(dis_kernel_pyramid(), dim3(tiles, 2), dim3(256), &pa, sizeof pa, a == 0 ? 1 : 0);
+    }
+    if (ss == 0) {
+        // no pyramid pass ran: level 0 still has to be materialised
+        PyrArgs pa;
+        std::memset(&pa, 0, sizeof pa);
+        pa.src[0] = I0; pa.src[1] = I1;
+        pa.src_kind = f64io ? 2 : 1;
+        pa.src_pitch = pitch;
+        pa.scale = 255.0;
+        pa.w0 = w; pa.h0 = hgt;
+        pa.lvl0[0] = sb.lv[0].J0; pa.lvl0[1] = sb.lv[0].J1;
+        pa.tiles_x = (w + 31) / 32;
+        seq.add(dis_kernel_pyramid(), dim3(pa.tiles_x * ((hgt + 31) / 32), 2), dim3(256), &pa, sizeof pa, 1);
+    }
+
+    for (int s = ss; s >= sf; --s) {
+        LevelBuf& L = sb.lv[s];
+        LevelGrid g;
+        const int N = grid_info(h, w >> s, hgt >> s, &g);
+        if (N > L.maxN) return fail(h, DIS_ESIZE, "internal: %d patches exceed capacity %d", N, L.maxN);
+        const int W = g.W, Hh = g.H;
+        // 1-3: grid, initialisation, inverse search
+        SearchArgs sa;
+        std::memset(&sa, 0, sizeof sa);
+        sa.J0 = L.J0; sa.J1 = L.J1; sa.W = W; sa.H = Hh;
+        if (s < ss) { sa.Un = sb.lv[s + 1].U; sa.Wn = w >> (s + 1); sa.Hn = hgt >> (s + 1); }
+        sa.st = g.st; sa.nrx = g.nrx; sa.nry = g.nry; sa.nx = g.nx; sa.ny = g.ny;
+        sa.iters = p.gn_iters;
+        sa.lam = 1e-3;
+        sa.centre_map = cmap;
+        sa.patch = L.patch;
+        sa.uinit = L.uinit;
+        const int lpp = dis_pick_lpp(h, s, N);
+        const void* fn = dis_kernel_search(ps, lpp);
+        if (!fn) return fail(h, DIS_EINVAL, "no search kernel for patch %d, %d lanes", ps, lpp);
+        const int per_block = 256 / lpp;
+        seq.add(fn, dim3((N + per_block - 1) / per_block), dim3(256), &sa, sizeof sa, 0);
+        // 4: densification
+        DensifyArgs da;
+        std::memset(&da, 0, sizeof da);
+        da.J0 = L.J0; da.J1 = L.J1; da.W = W; da.H = Hh;
+        da.patch = L.patch;
+        da.ps = ps; da.st = g.st; da.nrx = g.nrx; da.nry = g.nry; da.nx = g.nx; da.ny = g.ny;
+        da.raw_residual = (p.flags & DIS_FLAG_RAW_RESIDUAL) ? 1 : 0;
+        da.U = L.Ud;
+        da.J1w = p.refine ? sb.J1w : nullptr;
+        const dim3 pgrid((W + 63) / 64, (Hh + 3) / 4);
+        seq.add(dis_kernel_densify(), pgrid, dim3(256), &da, sizeof da, 0);
+        // 5: variational refinement
+        if (p.refine) {
+            PrepArgs pa;
+            pa.J0 = L.J0; pa.J1w = sb.J1w; pa.W = W; pa.H = Hh; pa.D = sb.D;
+            seq.add(dis_kernel_prep(), pgrid, dim3(256), &pa, sizeof pa, 0);
+            const int nouter = p.var_outer < 0 ? s + 1 : p.var_outer;
+            int tw, th;
+            dis_refine_tile(h->refine_tile, &tw, &th);
+            const int tiles_x = (W + tw - 1) / tw, tiles = tiles_x * ((Hh + th - 1) / th);
+            int cur = -1;   // buffer holding the current increment, -1 = zero
+            if (nouter == 0) {
+                // no fixed-point iteration: the refined flow is the densified one
+                RefineArgs ra;
+                std::memset(&ra, 0, sizeof ra);
+                ra.U = L.Ud; ra.dUout = sb.dU[0]; ra.Uout = L.U; ra.D = sb.D; ra.W = W; ra.H = Hh;
+                ra.nhalf = 0; ra.tiles_x = tiles_x;
+                ra.delta = p.w_intensity; ra.gamma = p.w_gradient; ra.alpha = p.w_smooth;
+                ra.omega = p.sor_omega; ra.eps = 1e-3;
+                seq.add(dis_kernel_refine(h->refine_tile), dim3(tiles), dim3(256), &ra, sizeof ra, 0);
+            }
+            for (int k = 0; k < nouter; ++k) {
+                const int frozen = cur;
+                int in = cur;
+                int left = 2 * p.var_inner;
+                while (left > 0) {
+                    const int nh = std::min(left, DIS_KMAX);
+                    left -= nh;
+                    int outb = 0;
+                    while (outb == frozen || outb == in) ++outb;
+                    RefineArgs ra;
+                    std::memset(&ra, 0, sizeof ra);
+                    ra.U = L.Ud;
+                    ra.dUf = frozen < 0 ? nullptr : sb.dU[frozen];
+                    ra.dUin = in < 0 ? nullptr : sb.dU[in];
+                    ra.dUout = sb.dU[outb];
+                    ra.Uout = (k == nouter - 1 && left == 0) ? L.U : nullptr;
+                    ra.D = sb.D;
+                    ra.W = W; ra.H = Hh;
+                    ra.nhalf = nh;
+                    ra.tiles_x = tiles_x;
+                    ra.delta = p.w_intensity; ra.gamma = p.w_gradient; ra.alpha = p.w_smooth;
+                    ra.omega = p.sor_omega; ra.eps = 1e-3;
+                    seq.add(dis_kernel_refine(h->refine_tile), dim3(tiles), dim3(256), &ra, sizeof ra, 0);
+                    in = outb;
+                }
+                cur = in;
+            }
+        }
+    }
+    // final upscaling (or copy) into the caller's flow
+    UpsArgs ua;
+    std::memset(&ua, 0, sizeof ua);
+    ua.U = sb.lv[sf].U;
+    ua.Ws = w >> sf; ua.Hs = hgt >> sf;
+    ua.W = w; ua.H = hgt;
+    ua.f = (double)(1 << sf);
+    ua.centre_map = cmap;
+    ua.out = flow;
+    ua.out_f64 = f64io ? 1 : 0;
+    seq.add(dis_kernel_upsample(), dim3((w + 63) / 64, (hgt + 3) / 4), dim3(256), &ua, sizeof ua, 2);
+    return DIS_OK;
+}
+
+// Point the caller-facing launches of a sequence at new frames / flow.
+static void rebind(Seq& seq, const void* I0, const void* I1, void* flow) {
+    for (Launch& L : seq.items) {
+        if (L.kind == 1) {
+            PyrArgs* pa = (PyrArgs*)L.arg.data();
+            pa->src[0] = I0;
+            pa->src[1] = I1;
+        } else if (L.kind == 2) {
+            ((UpsArgs*)L.arg.data())->out = flow;
+        }
+    }
+}
+
+int dis_launch_eager(dis_handle* h, Seq& seq) {
+    for (Launch& L : seq.items) {
+        void* args[1] = {L.arg.data()};
+        HIPCHK(h, hipLaunchKernel(L.fn, L.grid, L.block, args, 0, h->stream));
+    }
+    return DIS_OK;
+}
+
+static int build_graph(dis_handle* h, Plan* pl) {
+    HIPCHK(h, hipGraphCreate(&pl->graph, 0));
+    hipGraphNode_t prev = nullptr;
+    pl->nodes.resize(pl->seq.items.size());
+    for (size_t i = 0; i < pl->seq.items.size(); ++i) {
+        Launch& L = pl->seq.items[i];
+        hipKernelNodeParams kp;
+        std::memset(&kp, 0, sizeof kp);
+        void* args[1] = {L.arg.data()};
+        kp.func = (void*)L.fn;
+        kp.gridDim = L.grid;
+        kp.blockDim = L.block;
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        HIPCHK(h, hipGraphAddKernelNode(&pl->nodes[i], pl->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        prev = pl->nodes[i];
+    }
+    HIPCHK(h, hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0));
+    return DIS_OK;
+}
+
+static int update_graph_io(dis_handle* h, Plan* pl) {
+    for (size_t i = 0; i < pl->seq.items.size(); ++i) {
+        Launch& L = pl->seq.items[i];
+        if (L.kind == 0) continue;
+        hipKernelNodeParams kp;
+        std::memset(&kp, 0, sizeof kp);
+        void* args[1] = {L.arg.data()};
+        kp.func = (void*)L.fn;
+        kp.gridDim = L.grid;
+        kp.blockDim = L.block;
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        HIPCHK(h, hipGraphExecKernelNodeSetParams(pl->exec, pl->nodes[i], &kp));
+    }
+    return DIS_OK;
+}
+
+extern "C" int dis_compute_flow(dis_handle* h, const void* I0, const void* I1, int w, int hgt, int pitch,
+                                void* flow) {
+    if (!h) return fail(nullptr, DIS_EINVAL, "handle is NULL");
+    if (!I0 || !I1 || !flow) return fail(h, DIS_EINVAL, "NULL frame or flow pointer");
+    if (w < 1 || hgt < 1) return fail(h, DIS_EINVAL, "size %dx%d invalid", w, hgt);
+    if (pitch < w) return fail(h, DIS_EINVAL, "pitch %d < width %d", pitch, w);
+    if (w > h->max_w || hgt > h->max_h)
+        return fail(h, DIS_ESIZE, "%dx%d exceeds the handle's %dx%d", w, hgt, h->max_w, h->max_h);
+    const auto key = std::make_tuple(w, hgt, pitch);
+    Plan* pl;
+    auto it = h->plans.find(key);
+    if (it == h->plans.end()) {
+        pl = new Plan();
+        int r = dis_build_pair(h, h->slots[0], w, hgt, pitch, I0, I1, flow, pl->seq, &pl->info);
+        if (r != DIS_OK) {
+            delete pl;
+            return r;
+        }
+        h->plans[key] = pl;
+    } else {
+        pl = it->second;
+        rebind(pl->seq, I0, I1, flow);
+    }
+    int r;
+    if (h->p.flags & DIS_FLAG_NO_GRAPH) {
+        r = dis_launch_eager(h, pl->seq);
+    } else {
+        if (!pl->exec) {
+            r = build_graph(h, pl);
+            if (r != DIS_OK) return r;
+        } else {
+            r = update_graph_io(h, pl);
+            if (r != DIS_OK) return r;
+        }
+        HIPCHK(h, hipGraphLaunch(pl->exec, h->stream));
+        r = DIS_OK;
+    }
+    if (r == DIS_OK) {
+        h->last_w = w;
+        h->last_h = hgt;
+        h->last_ss = pl->info.ss;
+        h->last_sf = pl->info.sf;
+        h->have_last = true;
+        h->last_I0 = I0;
+        h->last_I1 = I1;
+        h->last_pitch = pitch;
+    }
+    return r;
+}
+
+// --------------------------------------------------------------- debugging
+
+extern "C" int dis_debug_level(dis_handle* h, int s, int what, void* dst, size_t bytes) {
+    if (!h) return fail(nullptr, DIS_EINVAL, "handle is NULL");
+    if (!dst) return fail(h, DIS_EINVAL, "dst is NULL");
+    if (!h->have_last) return fail(h, DIS_ESTATE, "no forward call yet");
+    if (s < h->last_sf || s > h->last_ss) return fail(h, DIS_ESTATE, "scale %d not computed (%d..%d)", s, h->last_sf, h->last_ss);
+    LevelBuf& L = h->slots[0].lv[s];
+    LevelGrid g;
+    const int N = grid_info(h, h->last_w >> s, h->last_h >> s, &g);
+    const size_t px = (size_t)g.W * g.H;
+    const void* src = nullptr;
+    size_t n = 0;
+    int32_t info[6];
+    switch (what) {
+        case DIS_DBG_J0: src = L.J0; n = px * 8; break;
+        case DIS_DBG_J1: src = L.J1; n = px * 8; break;
+        case DIS_DBG_UINIT: src = L.uinit; n = (size_t)N * 16; break;
+        case DIS_DBG_UPATCH: src = nullptr; n = (size_t)N * 16; break;
+        case DIS_DBG_UDENSE: src = L.Ud; n = 2 * px * 8; break;
+        case DIS_DBG_UREFINED: src = L.U; n = 2 * px * 8; break;
+        case DIS_DBG_INFO:
+            info[0] = g.W; info[1] = g.H; info[2] = N; info[3] = g.nx; info[4] = g.ny; info[5] = g.st;
+            if (bytes < sizeof info) return fail(h, DIS_ESIZE, "need %zu bytes", sizeof info);
+            std::memcpy(dst, info, sizeof info);
+            return DIS_OK;
+        default: return fail(h, DIS_EINVAL, "unknown debug item %d", what);
+    }
+    if (bytes < n) return fail(h, DIS_ESIZE, "need %zu bytes, have %zu", n, bytes);
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (what == DIS_DBG_UPATCH) {
+        std::vector<double> tmp((size_t)N * 4);
+        HIPCHK(h, hipMemcpy(tmp.data(), L.patch, tmp.size() * 8, hipMemcpyDeviceToHost));
+        double* o = (double*)dst;
+        for (int i = 0; i < N; ++i) { o[2 * i] = tmp[4 * i]; o[2 * i + 1] = tmp[4 * i + 1]; }
+        return DIS_OK;
+    }
+    if (!src) return fail(h, DIS_ESTATE, "item %d not kept at scale %d", what, s);
+    HIPCHK(h, hipMemcpy(dst, src, n, hipMemcpyDeviceToHost));
+    return DIS_OK;
+}

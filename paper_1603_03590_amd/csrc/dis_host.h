@@ -1,0 +1,93 @@
+// Handle layout and helpers shared by the host-side translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "dis.h"
+#include "dis_internal.h"
+
+// Device buffers of one pyramid level of one pair slot (float64, dense).
+struct LevelBuf {
+    double* J0;      // level image of frame 0 (0..255 scale)
+    double* J1;      // level image of frame 1
+    double* Ud;      // densified flow [2][H][W] (aliases U without refinement)
+    double* U;       // flow after refinement [2][H][W]
+    double* patch;   // [maxN][4]: u, v, mean residual, distance moved
+    double* uinit;   // [maxN][2]
+    int maxN;
+};
+
+// Everything one frame pair needs; a handle owns max_batch of them.
+struct SlotBuf {
+    LevelBuf lv[DIS_MAXL];
+    double* J1w;     // warped frame 1 of the level being refined
+    double* D;       // 11 linearisation planes of that level
+    double* dU[3];   // refinement increments (frozen / in / out rotation)
+};
+
+struct LevelGrid {
+    int W, H, st, nrx, nry, nx, ny;
+};
+
+// One kernel launch with its argument block (kind: 0 internal, 1 reads the
+// caller's frames, 2 writes the caller's flow).
+struct Launch {
+    const void* fn;
+    dim3 grid, block;
+    std::vector<char> arg;
+    int kind;
+};
+
+struct Seq {
+    std::vector<Launch> items;
+    void add(const void* fn, dim3 grid, dim3 block, const void* arg, size_t bytes, int kind);
+};
+
+struct PairInfo {
+    int ss, sf;
+};
+
+struct Plan {
+    Seq seq;
+    PairInfo info{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipGraphNode_t> nodes;
+};
+
+struct BatchPlan;
+void dis_batch_plan_free(BatchPlan* bp);
+
+struct dis_handle {
+    dis_params p;
+    int max_w = 0, max_h = 0, max_batch = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int st = 1;
+    int top = 0;
+    std::vector<void*> allocs;
+    std::vector<SlotBuf> slots;
+    std::string err;
+    std::map<std::tuple<int, int, int>, Plan*> plans;
+    std::map<std::vector<int>, BatchPlan*> bplans;
+    int lpp[DIS_MAXL];
+    int refine_tile = 0;
+    // most recent plain forward call (debug and backward)
+    bool have_last = false;
+    int last_w = 0, last_h = 0, last_ss = 0, last_sf = 0, last_pitch = 0;
+    const void* last_I0 = nullptr;
+    const void* last_I1 = nullptr;
+};
+
+int dis_stride(const dis_params* p);
+int dis_coarsest(const dis_params* p, int w, int h);
+void dis_grid(int n, int ps, int st, int* nr, int* ntot);
+int dis_pick_lpp(const dis_handle* h, int s, int N);
+int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const void* I0, const void* I1,
+                   void* flow, Seq& seq, PairInfo* info);
+int dis_launch_eager(dis_handle* h, Seq& seq);

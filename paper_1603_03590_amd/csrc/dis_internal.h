@@ -1,0 +1,98 @@
+// Launch-argument blocks shared by the host library and the HIP kernels.
+// Every kernel takes exactly one of these structs by value.  All planes are
+// dense row-major float64 arrays (pitch = width) owned by the handle, except
+// the caller's frames and flow.
+#pragma once
+#include <stdint.h>
+
+#define DIS_MAXL 16   // pyramid levels a handle can hold
+#define DIS_KMAX 10   // red-black half sweeps one refinement launch can fuse
+
+// Pyramid: from level `a` (the caller's frames when a == 0) compute the
+// 2x2-box levels a+1 .. a+nlev (nlev <= 5) in one pass over 32x32 tiles.
+struct PyrArgs {
+    const void* src[2];     // frame 0 / frame 1 of level a
+    int src_kind;           // 0 = float64 plane, 1 = float32 frame, 2 = float64 frame
+    int src_pitch;          // elements
+    double scale;           // 255 for frames, 1 for planes
+    int a, nlev;
+    int w0, h0;             // size of level a
+    int tiles_x;
+    double* lvl0[2];        // receives the scaled level a when non-null
+    double* dst[2][6];      // dst[f][k]: level a+k, or null when not kept
+    int ws[6], hs[6];
+};
+
+// Inverse search on one level: grid, initialisation, Gauss-Newton, reset,
+// final residual mean.
+struct SearchArgs {
+    const double* J0;
+    const double* J1;
+    int W, H;
+    const double* Un;       // coarser flow [2][Hn][Wn]; null on the coarsest level
+    int Wn, Hn;
+    int st, nrx, nry, nx, ny;   // stride; regular corners per axis; total corners per axis
+    int iters;
+    double lam;
+    int centre_map;
+    double* patch;          // [N][4]: u, v, mean residual at u, distance moved
+    double* uinit;          // [N][2]
+};
+
+// Densification (Eq. 3) and the warped second frame for the refinement.
+struct DensifyArgs {
+    const double* J0;
+    const double* J1;
+    int W, H;
+    const double* patch;
+    int ps, st, nrx, nry, nx, ny;
+    int raw_residual;
+    double* U;              // [2][H][W]
+    double* J1w;            // [H][W], or null without refinement
+};
+
+// Linearisation of the refinement energy: 11 planes
+// Ix, Iy, Iz, Ixx, Ixy, Iyy, Ixz, Iyz, beta0, betax, betay.
+struct PrepArgs {
+    const double* J0;
+    const double* J1w;
+    int W, H;
+    double* D;
+};
+
+// Part of one fixed-point iteration of the refinement: robust weights from
+// the frozen increment dUf, then nhalf red-black half sweeps starting from
+// dUin, written to dUout (and U + dU to Uout when non-null).
+struct RefineArgs {
+    const double* U;
+    const double* dUf;      // null = zero
+    const double* dUin;     // null = zero
+    double* dUout;
+    double* Uout;
+    const double* D;
+    int W, H;
+    int nhalf;
+    int tiles_x;
+    double delta, gamma, alpha, omega, eps;
+};
+
+// Bilinear upscaling of the finest computed level to the output size.
+struct UpsArgs {
+    const double* U;
+    int Ws, Hs;
+    int W, H;
+    double f;               // 2^theta_sf
+    int centre_map;
+    void* out;
+    int out_f64;
+};
+
+// Kernel entry points, looked up by the host.
+const void* dis_kernel_pyramid();
+const void* dis_kernel_search(int ps, int lpp);   // null when not compiled
+const void* dis_kernel_densify();
+const void* dis_kernel_prep();
+const void* dis_kernel_refine(int tile);          // tile id, see dis_refine_tile
+const void* dis_kernel_upsample();
+// refinement core tile (width, height) of a tile id; returns 0 for an unknown id
+int dis_refine_tile(int tile, int* tw, int* th);

@@ -1,0 +1,151 @@
+"""GPU path against the FP64 oracle, through the C ABI (ctypes binding).
+
+Every GPU test prints its case before it touches the device.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from dis_cases import PARITY_EPE_REL, PARITY_FRAC, oracle_flow, oracle_params, pair, parity
+from paper_1603_03590_amd import DIS, DisError, params, _lib
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_flow(I0, I1, p, max_wh=None, keep=False):
+    h, w = I0.shape
+    mw, mh = max_wh or (w, h)
+    d = DIS(p, mw, mh)
+    dt = d.dtype
+    t0 = torch.from_numpy(I0).to(dt).cuda()
+    t1 = torch.from_numpy(I1).to(dt).cuda()
+    out = d.flow(t0, t1)
+    torch.cuda.synchronize()
+    U = out.cpu().numpy().astype(np.float64)
+    if keep:
+        return U, d
+    d.close()
+    return U
+
+
+CASES = [
+    # name, generator (kind, w, h, max displacement, seed), preset, overrides
+    ("c1_bump_256x192", ("bump", 256, 192, 8.0, 1), 101, {}),
+    ("c2a_layered_1024x436", ("layered", 1024, 436, 100.0, 2), 102, {}),
+    ("c2b_layered_1024x436", ("layered", 1024, 436, 100.0, 2), 103, {}),
+    ("c5_bump_512x256", ("bump", 512, 256, 16.0, 2000), 105, {}),
+    ("ragged_203x149_norefine", ("layered", 203, 149, 20.0, 7), 103,
+     dict(coarsest_scale=3, finest_scale=0, refine=0)),
+    ("ragged_203x149_sf1", ("layered", 203, 149, 20.0, 8), 103, dict(coarsest_scale=3, finest_scale=1)),
+    ("c3_small_320x240", ("layered", 320, 240, 60.0, 9), 104, dict(coarsest_scale=3, gn_iters=64, var_outer=2)),
+    ("op1_norefine_640x480", ("layered", 640, 480, 40.0, 10), 1, {}),
+    ("pixel_centre_raw_300x200", ("bump", 300, 200, 10.0, 11), 105, dict(flags=0x4 | 0x8)),
+    ("io_f64_256x192", ("bump", 256, 192, 8.0, 12), 101, dict(flags=0x10)),
+    ("ps12_ov05_288x216", ("bump", 288, 216, 10.0, 13), 105, dict(patch_size=12, overlap=0.5, var_inner=7)),
+    ("ps6_ov0_auto_320x96", ("layered", 320, 96, 12.0, 14), 103,
+     dict(patch_size=6, overlap=0.0, coarsest_scale=-1, finest_scale=0)),
+    ("op3_1024x436", ("layered", 1024, 436, 100.0, 15), 3, dict(gn_iters=16)),
+]
+
+
+@pytest.mark.parametrize("name,gen,preset,over", CASES, ids=[c[0] for c in CASES])
+def test_end_to_end_parity(name, gen, preset, over):
+    say(f"[parity] case {name}")
+    pr = pair(*gen)
+    p = params(preset, **over)
+    U_ref, _ = oracle_flow(name, pr.I0, pr.I1, oracle_params(p))
+    U = gpu_flow(pr.I0, pr.I1, p)
+    frac, erel, dmax = parity(U, U_ref, pr.flow)
+    say(f"[parity] {name}: within 1e-2 px {frac:.6f}, mean EPE rel diff {erel:.2e}, max diff {dmax:.2e}")
+    assert frac >= PARITY_FRAC
+    assert erel <= PARITY_EPE_REL
+
+
+def test_level_intermediates_match_oracle():
+    """Every level's pyramid image (bitwise), patch initialisation, patch
+    displacement, densified and refined flow against the oracle's records."""
+    say("[levels] case c1_bump_256x192")
+    pr = pair("bump", 256, 192, 8.0, 1)
+    p = params(101)
+    _, recs = oracle_flow("c1_levels", pr.I0, pr.I1, oracle_params(p), records=True)
+    U, d = gpu_flow(pr.I0, pr.I1, p, keep=True)
+    try:
+        from oracle import dis_oracle as O
+        J0 = O.build_pyramid(255.0 * torch.from_numpy(pr.I0).double(), 2)
+        for r in recs:
+            s = r.s
+            g = d.debug_level(s, _lib.DIS_DBG_J0)
+            assert np.array_equal(g, J0[s].numpy()), f"level {s} image"
+            np.testing.assert_allclose(d.debug_level(s, _lib.DIS_DBG_UINIT), r.u_init.numpy(), atol=1e-9)
+            np.testing.assert_allclose(d.debug_level(s, _lib.DIS_DBG_UPATCH), r.search.u.numpy(), atol=1e-8)
+            np.testing.assert_allclose(d.debug_level(s, _lib.DIS_DBG_UDENSE), r.U_dense.numpy(), atol=1e-8)
+            np.testing.assert_allclose(d.debug_level(s, _lib.DIS_DBG_UREFINED), r.U_refined.numpy(), atol=1e-8)
+    finally:
+        d.close()
+
+
+def test_identical_frames_give_exactly_zero():
+    say("[zero] identical frames 1024x436")
+    pr = pair("layered", 1024, 436, 100.0, 2)
+    for preset in (102, 105):
+        U = gpu_flow(pr.I0, pr.I0.copy(), params(preset))
+        assert np.count_nonzero(U) == 0
+
+
+def test_deterministic_and_graph_equals_eager():
+    say("[determinism] c2b 1024x436, graph and eager")
+    pr = pair("layered", 1024, 436, 100.0, 2)
+    p = params(103)
+    a = gpu_flow(pr.I0, pr.I1, p)
+    b = gpu_flow(pr.I0, pr.I1, p)
+    c = gpu_flow(pr.I0, pr.I1, params(103, flags=_lib.DIS_FLAG_NO_GRAPH))
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, c)
+
+
+def test_pitched_frames_and_reused_handle():
+    say("[pitch] 256x192 inside 300-wide rows; handle reuse across sizes")
+    pr = pair("bump", 256, 192, 8.0, 1)
+    p = params(101)
+    ref = gpu_flow(pr.I0, pr.I1, p)
+    d = DIS(p, 320, 240)
+    try:
+        big0 = torch.zeros(192, 300, device="cuda")
+        big1 = torch.zeros(192, 300, device="cuda")
+        big0[:, :256] = torch.from_numpy(pr.I0).cuda()
+        big1[:, :256] = torch.from_numpy(pr.I1).cuda()
+        out = d.flow(big0[:, :256], big1[:, :256])
+        other = pair("bump", 300, 200, 8.0, 3)
+        d.flow(torch.from_numpy(other.I0).cuda(), torch.from_numpy(other.I1).cuda())
+        out2 = d.flow(big0[:, :256], big1[:, :256])
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
+        assert np.array_equal(out2.cpu().numpy().astype(np.float64), ref)
+    finally:
+        d.close()
+
+
+def test_size_errors():
+    say("[errors] sizes and pointers")
+    d = DIS(params(103), 256, 256)
+    try:
+        x = torch.zeros(300, 200, device="cuda")
+        with pytest.raises(DisError) as e:
+            d.flow(x, x)
+        assert e.value.code == _lib.DIS_ESIZE
+        y = torch.zeros(8, 8, device="cuda")       # coarsest level smaller than a patch at scale 3
+        with pytest.raises(DisError) as e:
+            d.flow(y, y)
+        assert e.value.code == _lib.DIS_ESIZE
+        with pytest.raises(DisError) as e:
+            _lib.dis_compute_flow(d.handle, 0, 0, 16, 16, 16, 0)
+        assert e.value.code == _lib.DIS_EINVAL
+    finally:
+        d.close()
