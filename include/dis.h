@@ -184,6 +184,29 @@ int dis_set_stream(dis_handle* h, void* hip_stream);
 #define DIS_DBG_INFO 6
 int dis_debug_level(dis_handle* h, int s, int what, void* dst, size_t bytes);
 
+/*
+ * Per-kernel timing.  dis_profile_enable(h, 1) makes the following forward
+ * calls launch their kernels one by one with a HIP event recorded on the
+ * handle's stream before and after each launch; dis_profile_enable(h, 0)
+ * returns to graph replay.  dis_profile_read synchronises the stream, folds
+ * the recorded events into per-kernel totals, writes up to `max` entries into
+ * out[] (host array), sets *n to the number of kernels seen and clears the
+ * totals.  `bytes` and `flops` are the algorithmic (compulsory) memory traffic
+ * and floating-point work of all launches of that kernel, from the sizes of
+ * the arrays each launch must read and write and the operation counts of its
+ * arithmetic (see the per-kernel models in the host source).
+ * Errors: DIS_EINVAL (NULL), DIS_EHIP.
+ */
+typedef struct dis_kernel_stat {
+    char name[32];
+    int32_t launches;
+    double total_ms;
+    double bytes;
+    double flops;
+} dis_kernel_stat;
+int dis_profile_enable(dis_handle* h, int on);
+int dis_profile_read(dis_handle* h, dis_kernel_stat* out, int max, int* n);
+
 /* Release the handle and its device memory; NULL is ignored.  Synchronises
  * the handle's stream first, so pending work finishes before memory goes. */
 void dis_destroy(dis_handle* h);

@@ -39,7 +39,7 @@ DIS_DBG_INFO = 6
 EXPORTS = (
     "dis_default_params", "dis_create", "dis_compute_flow", "dis_compute_flow_batched",
     "dis_flow_backward", "dis_autotune", "dis_last_error", "dis_set_stream",
-    "dis_debug_level", "dis_destroy",
+    "dis_debug_level", "dis_destroy", "dis_profile_enable", "dis_profile_read",
 )
 
 
@@ -74,6 +74,16 @@ class dis_params(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class dis_kernel_stat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 32),
+        ("launches", c_int32),
+        ("total_ms", c_double),
+        ("bytes", c_double),
+        ("flops", c_double),
+    ]
+
+
 _lib = None
 
 
@@ -97,6 +107,8 @@ def load(path: str = LIB_PATH):
     lib.dis_last_error.restype = c_char_p
     lib.dis_set_stream.argtypes = [H, c_void_p]
     lib.dis_debug_level.argtypes = [H, c_int, c_int, c_void_p, c_size_t]
+    lib.dis_profile_enable.argtypes = [H, c_int]
+    lib.dis_profile_read.argtypes = [H, POINTER(dis_kernel_stat), c_int, POINTER(c_int)]
     lib.dis_destroy.argtypes = [H]
     lib.dis_destroy.restype = None
     for name in EXPORTS:
@@ -161,3 +173,16 @@ def dis_debug_level(handle: int, s: int, what: int, dst: int, nbytes: int) -> No
 
 def dis_destroy(handle: int) -> None:
     load().dis_destroy(c_void_p(handle))
+
+
+def dis_profile_enable(handle: int, on: bool) -> None:
+    _check(load().dis_profile_enable(c_void_p(handle), 1 if on else 0), c_void_p(handle))
+
+
+def dis_profile_read(handle: int, max_kernels: int = 32):
+    """[{name, launches, total_ms, bytes, flops}] accumulated since the last read."""
+    arr = (dis_kernel_stat * max_kernels)()
+    n = c_int()
+    _check(load().dis_profile_read(c_void_p(handle), arr, max_kernels, ctypes.byref(n)), c_void_p(handle))
+    return [dict(name=arr[i].name.decode(), launches=arr[i].launches, total_ms=arr[i].total_ms,
+                 bytes=arr[i].bytes, flops=arr[i].flops) for i in range(min(n.value, max_kernels))]

@@ -229,7 +229,7 @@ extern "C" int dis_create(const dis_params* p, int max_w, int max_h, int max_bat
 
 extern "C" void dis_destroy(dis_handle* h) {
     if (!h) return;
-    if (h->stream || true) hipStreamSynchronize(h->stream);
+    hipStreamSynchronize(h->stream);
     for (auto& kv : h->plans) {
         Plan* pl = kv.second;
         if (pl->exec) hipGraphExecDestroy(pl->exec);
@@ -240,6 +240,8 @@ extern "C" void dis_destroy(dis_handle* h) {
         BatchPlan* bp = kv.second;
         dis_batch_plan_free(bp);
     }
+    for (ProfPending& pp : h->prof_pending) { hipEventDestroy(pp.a); hipEventDestroy(pp.b); }
+    for (hipEvent_t e : h->prof_free) hipEventDestroy(e);
     for (void* ptr : h->allocs) hipFree(ptr);
     delete h;
 }
@@ -256,13 +258,17 @@ extern "C" int dis_set_stream(dis_handle* h, void* stream) {
 
 // ------------------------------------------------------------ launch lists
 
-void Seq::add(const void* fn, dim3 grid, dim3 block, const void* arg, size_t bytes, int kind) {
+void Seq::add(const void* fn, dim3 grid, dim3 block, const void* arg, size_t bytes, int kind, const char* name,
+              double traffic, double flops) {
     Launch L;
     L.fn = fn;
     L.grid = grid;
     L.block = block;
     L.arg.assign((const char*)arg, (const char*)arg + bytes);
     L.kind = kind;
+    L.name = name;
+    L.bytes = traffic;
+    L.flops = flops;
     items.push_back(std::move(L));
 }
 
@@ -332,7 +338,15 @@ int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const 
         }
         pa.tiles_x = (w0 + 31) / 32;
         const int tiles = pa.tiles_x * ((h0 + 31) / 32);
-        seq.add(dis_kernel_pyramid(), dim3(tiles, 2), dim3(256), &pa, sizeof pa, a == 0 ? 1 : 0);
+        // traffic: both frames of level a in, every kept level out (float64)
+        double by = 2.0 * (double)w0 * h0 * (a == 0 ? (f64io ? 8 : 4) : 8), fl = a == 0 ? 2.0 * w0 * h0 : 0.0;
+        if (pa.lvl0[0]) by += 16.0 * w0 * h0;
+        for (int k = 1; k <= pa.nlev; ++k) {
+            const double px = (double)pa.ws[k] * pa.hs[k];
+            fl += 2.0 * 4.0 * px;
+            if (pa.dst[0][k]) by += 16.0 * px;
+        }
+        seq.add(dis_kernel_pyramid(), dim3(tiles, 2), dim3(256), &pa, sizeof pa, a == 0 ? 1 : 0, "pyramid", by, fl);
     }
     if (ss == 0) {
         // no pyramid pass ran: level 0 still has to be materialised
@@ -345,7 +359,9 @@ int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const 
         pa.w0 = w; pa.h0 = hgt;
         pa.lvl0[0] = sb.lv[0].J0; pa.lvl0[1] = sb.lv[0].J1;
         pa.tiles_x = (w + 31) / 32;
-        seq.add(dis_kernel_pyramid(), dim3(pa.tiles_x * ((hgt + 31) / 32), 2), dim3(256), &pa, sizeof pa, 1);
+        const double px = (double)w * hgt;
+        seq.add(dis_kernel_pyramid(), dim3(pa.tiles_x * ((hgt + 31) / 32), 2), dim3(256), &pa, sizeof pa, 1,
+                "pyramid", px * (f64io ? 16 : 8) + 16.0 * px, 2.0 * px);
     }
 
     for (int s = ss; s >= sf; --s) {
@@ -369,7 +385,15 @@ int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const 
         const void* fn = dis_kernel_search(ps, lpp);
         if (!fn) return fail(h, DIS_EINVAL, "no search kernel for patch %d, %d lanes", ps, lpp);
         const int per_block = 256 / lpp;
-        seq.add(fn, dim3((N + per_block - 1) / per_block), dim3(256), &sa, sizeof sa, 0);
+        {
+            // traffic: both level images once, the coarser flow, the patch records
+            const double px = (double)W * Hh, P = (double)ps * ps;
+            const double by = 16.0 * px + (s < ss ? 16.0 * (w >> (s + 1)) * (hgt >> (s + 1)) : 0.0) + 48.0 * N;
+            // flops per patch: Sobel + Hessian setup 24/px, 15/px and 20 per
+            // Gauss-Newton iteration, 10/px for the final residual
+            const double fl = (double)N * (24.0 * P + p.gn_iters * (15.0 * P + 20.0) + 10.0 * P);
+            seq.add(fn, dim3((N + per_block - 1) / per_block), dim3(256), &sa, sizeof sa, 0, "search", by, fl);
+        }
         // 4: densification
         DensifyArgs da;
         std::memset(&da, 0, sizeof da);
@@ -380,12 +404,18 @@ int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const 
         da.U = L.Ud;
         da.J1w = p.refine ? sb.J1w : nullptr;
         const dim3 pgrid((W + 63) / 64, (Hh + 3) / 4);
-        seq.add(dis_kernel_densify(), pgrid, dim3(256), &da, sizeof da, 0);
+        {
+            const double px = (double)W * Hh;
+            const double cover = std::pow((double)ps / g.st, 2.0);
+            const double by = 16.0 * px + 32.0 * N + 16.0 * px + (p.refine ? 8.0 * px : 0.0);
+            const double fl = px * (18.0 * cover + 2.0 + (p.refine ? 9.0 : 0.0));
+            seq.add(dis_kernel_densify(), pgrid, dim3(256), &da, sizeof da, 0, "densify", by, fl);
+        }
         // 5: variational refinement
         if (p.refine) {
             PrepArgs pa;
             pa.J0 = L.J0; pa.J1w = sb.J1w; pa.W = W; pa.H = Hh; pa.D = sb.D;
-            seq.add(dis_kernel_prep(), pgrid, dim3(256), &pa, sizeof pa, 0);
+            seq.add(dis_kernel_prep(), pgrid, dim3(256), &pa, sizeof pa, 0, "prep", 104.0 * W * Hh, 60.0 * W * Hh);
             const int nouter = p.var_outer < 0 ? s + 1 : p.var_outer;
             int tw, th;
             dis_refine_tile(h->refine_tile, &tw, &th);
@@ -399,7 +429,8 @@ int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const 
                 ra.nhalf = 0; ra.tiles_x = tiles_x;
                 ra.delta = p.w_intensity; ra.gamma = p.w_gradient; ra.alpha = p.w_smooth;
                 ra.omega = p.sor_omega; ra.eps = 1e-3;
-                seq.add(dis_kernel_refine(h->refine_tile), dim3(tiles), dim3(256), &ra, sizeof ra, 0);
+                seq.add(dis_kernel_refine(h->refine_tile), dim3(tiles), dim3(256), &ra, sizeof ra, 0, "refine",
+                        136.0 * W * Hh, 0.0);
             }
             for (int k = 0; k < nouter; ++k) {
                 const int frozen = cur;
@@ -423,7 +454,18 @@ int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const 
                     ra.tiles_x = tiles_x;
                     ra.delta = p.w_intensity; ra.gamma = p.w_gradient; ra.alpha = p.w_smooth;
                     ra.omega = p.sor_omega; ra.eps = 1e-3;
-                    seq.add(dis_kernel_refine(h->refine_tile), dim3(tiles), dim3(256), &ra, sizeof ra, 0);
+                    {
+                        // traffic: U, frozen and starting increments, 11
+                        // linearisation planes in; increment (and flow) out
+                        const double px = (double)W * Hh;
+                        const double by = px * (16.0 + (ra.dUf ? 16.0 : 0.0) + (ra.dUin ? 16.0 : 0.0) + 88.0 + 16.0 +
+                                                (ra.Uout ? 16.0 : 0.0));
+                        // 95 flops per pixel for weights and coefficients, 24
+                        // per pixel update (half the pixels each half sweep)
+                        const double fl = px * (95.0 + 12.0 * nh);
+                        seq.add(dis_kernel_refine(h->refine_tile), dim3(tiles), dim3(256), &ra, sizeof ra, 0, "refine",
+                                by, fl);
+                    }
                     in = outb;
                 }
                 cur = in;
@@ -440,7 +482,8 @@ int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const 
     ua.centre_map = cmap;
     ua.out = flow;
     ua.out_f64 = f64io ? 1 : 0;
-    seq.add(dis_kernel_upsample(), dim3((w + 63) / 64, (hgt + 3) / 4), dim3(256), &ua, sizeof ua, 2);
+    seq.add(dis_kernel_upsample(), dim3((w + 63) / 64, (hgt + 3) / 4), dim3(256), &ua, sizeof ua, 2, "upsample",
+            16.0 * ua.Ws * ua.Hs + (f64io ? 16.0 : 8.0) * w * hgt, 20.0 * w * hgt);
     return DIS_OK;
 }
 
@@ -457,11 +500,74 @@ static void rebind(Seq& seq, const void* I0, const void* I1, void* flow) {
     }
 }
 
+static int prof_event(dis_handle* h, hipEvent_t* e) {
+    if (!h->prof_free.empty()) {
+        *e = h->prof_free.back();
+        h->prof_free.pop_back();
+        return DIS_OK;
+    }
+    HIPCHK(h, hipEventCreate(e));
+    return DIS_OK;
+}
+
 int dis_launch_eager(dis_handle* h, Seq& seq) {
     for (Launch& L : seq.items) {
         void* args[1] = {L.arg.data()};
-        HIPCHK(h, hipLaunchKernel(L.fn, L.grid, L.block, args, 0, h->stream));
+        if (h->profiling) {
+            ProfPending pp;
+            int r = prof_event(h, &pp.a);
+            if (r == DIS_OK) r = prof_event(h, &pp.b);
+            if (r != DIS_OK) return r;
+            pp.name = L.name;
+            pp.bytes = L.bytes;
+            pp.flops = L.flops;
+            HIPCHK(h, hipEventRecord(pp.a, h->stream));
+            HIPCHK(h, hipLaunchKernel(L.fn, L.grid, L.block, args, 0, h->stream));
+            HIPCHK(h, hipEventRecord(pp.b, h->stream));
+            h->prof_pending.push_back(pp);
+        } else {
+            HIPCHK(h, hipLaunchKernel(L.fn, L.grid, L.block, args, 0, h->stream));
+        }
     }
+    return DIS_OK;
+}
+
+extern "C" int dis_profile_enable(dis_handle* h, int on) {
+    if (!h) return fail(nullptr, DIS_EINVAL, "handle is NULL");
+    h->profiling = on != 0;
+    return DIS_OK;
+}
+
+extern "C" int dis_profile_read(dis_handle* h, dis_kernel_stat* out, int max, int* n) {
+    if (!h) return fail(nullptr, DIS_EINVAL, "handle is NULL");
+    if (!n || (max > 0 && !out)) return fail(h, DIS_EINVAL, "NULL output");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (ProfPending& pp : h->prof_pending) {
+        float ms = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&ms, pp.a, pp.b));
+        ProfStat& st = h->prof[pp.name];
+        st.launches += 1;
+        st.ms += ms;
+        st.bytes += pp.bytes;
+        st.flops += pp.flops;
+        h->prof_free.push_back(pp.a);
+        h->prof_free.push_back(pp.b);
+    }
+    h->prof_pending.clear();
+    int i = 0;
+    for (auto& kv : h->prof) {
+        if (i < max) {
+            std::memset(&out[i], 0, sizeof out[i]);
+            std::snprintf(out[i].name, sizeof out[i].name, "%s", kv.first.c_str());
+            out[i].launches = kv.second.launches;
+            out[i].total_ms = kv.second.ms;
+            out[i].bytes = kv.second.bytes;
+            out[i].flops = kv.second.flops;
+        }
+        ++i;
+    }
+    *n = i;
+    h->prof.clear();
     return DIS_OK;
 }
 
@@ -528,16 +634,19 @@ extern "C" int dis_compute_flow(dis_handle* h, const void* I0, const void* I1, i
         rebind(pl->seq, I0, I1, flow);
     }
     int r;
-    if (h->p.flags & DIS_FLAG_NO_GRAPH) {
+    if ((h->p.flags & DIS_FLAG_NO_GRAPH) || h->profiling) {
         r = dis_launch_eager(h, pl->seq);
     } else {
         if (!pl->exec) {
             r = build_graph(h, pl);
             if (r != DIS_OK) return r;
-        } else {
+        } else if (pl->bound[0] != I0 || pl->bound[1] != I1 || pl->bound[2] != flow) {
             r = update_graph_io(h, pl);
             if (r != DIS_OK) return r;
         }
+        pl->bound[0] = I0;
+        pl->bound[1] = I1;
+        pl->bound[2] = flow;
         HIPCHK(h, hipGraphLaunch(pl->exec, h->stream));
         r = DIS_OK;
     }

@@ -41,11 +41,26 @@ struct Launch {
     dim3 grid, block;
     std::vector<char> arg;
     int kind;
+    const char* name;   // kernel family, for profiling
+    double bytes;       // algorithmic memory traffic of this launch
+    double flops;       // algorithmic floating-point work of this launch
 };
 
 struct Seq {
     std::vector<Launch> items;
-    void add(const void* fn, dim3 grid, dim3 block, const void* arg, size_t bytes, int kind);
+    void add(const void* fn, dim3 grid, dim3 block, const void* arg, size_t bytes, int kind,
+             const char* name = "", double traffic = 0.0, double flops = 0.0);
+};
+
+struct ProfStat {
+    int launches = 0;
+    double ms = 0.0, bytes = 0.0, flops = 0.0;
+};
+
+struct ProfPending {
+    hipEvent_t a, b;
+    const char* name;
+    double bytes, flops;
 };
 
 struct PairInfo {
@@ -58,6 +73,7 @@ struct Plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<hipGraphNode_t> nodes;
+    const void* bound[3] = {nullptr, nullptr, nullptr};   // frames / flow the graph points at
 };
 
 struct BatchPlan;
@@ -82,6 +98,11 @@ struct dis_handle {
     int last_w = 0, last_h = 0, last_ss = 0, last_sf = 0, last_pitch = 0;
     const void* last_I0 = nullptr;
     const void* last_I1 = nullptr;
+    // per-kernel event timing (dis_profile_enable)
+    bool profiling = false;
+    std::vector<ProfPending> prof_pending;
+    std::vector<hipEvent_t> prof_free;
+    std::map<std::string, ProfStat> prof;
 };
 
 int dis_stride(const dis_params* p);
