@@ -158,6 +158,19 @@ int dis_flow_backward(dis_handle* h, const void* grad_flow, void* grad_I0, void*
  */
 int dis_autotune(dis_handle* h, const char* cache_path);
 
+/*
+ * Set the launch choices that do not change results (for tests and the
+ * autotuner): lanes_per_patch[s] (HOST array of 16, or NULL = automatic for
+ * every scale) is the number of lanes sharing one patch in the search on
+ * scale s (0 = automatic, else 4, 8 or 16 where compiled for the patch size);
+ * refine_tile picks the refinement tile of the per-phase launches (0: 32x16,
+ * 1: 16x16, 2: 64x8); launch_mode 0 runs each scale as one persistent launch
+ * over a task queue, 1 as one launch per phase.  Every choice gives
+ * bitwise-identical flow.  Synchronises the stream and drops cached launch
+ * plans.  Errors: DIS_EINVAL.
+ */
+int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int refine_tile, int launch_mode);
+
 /* Message for the most recent failing call on h (or on a NULL handle). */
 const char* dis_last_error(const dis_handle* h);
 
@@ -171,7 +184,9 @@ int dis_set_stream(dis_handle* h, void* hip_stream);
  * scale), DIS_DBG_UINIT [N][2] patch initialisations, DIS_DBG_UPATCH [N][2]
  * patch displacements after the reset test, DIS_DBG_UDENSE [2][H_s][W_s]
  * densified flow, DIS_DBG_UREFINED [2][H_s][W_s] flow after refinement,
- * DIS_DBG_INFO int32 {W_s, H_s, N, nx, ny, stride} (24 bytes).
+ * DIS_DBG_INFO int32 {W_s, H_s, N, nx, ny, stride} (24 bytes),
+ * DIS_DBG_WAIT_ERRORS int32: how many persistent launches of that call gave
+ * up waiting on their task queue (0 unless something is broken).
  * Errors: DIS_EINVAL (bad what/s or NULL), DIS_ESIZE (bytes too small),
  * DIS_ESTATE (scale not computed), DIS_EHIP.
  */
@@ -182,6 +197,7 @@ int dis_set_stream(dis_handle* h, void* hip_stream);
 #define DIS_DBG_UDENSE 4
 #define DIS_DBG_UREFINED 5
 #define DIS_DBG_INFO 6
+#define DIS_DBG_WAIT_ERRORS 7
 int dis_debug_level(dis_handle* h, int s, int what, void* dst, size_t bytes);
 
 /*

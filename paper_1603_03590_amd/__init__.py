@@ -104,11 +104,18 @@ class DIS:
         _lib.dis_flow_backward(self.handle, grad_flow.contiguous().data_ptr(), g0.data_ptr(), g1.data_ptr())
         return g0, g1
 
+    def set_tunables(self, lanes_per_patch=None, refine_tile=0, launch_mode=0):
+        _lib.dis_set_tunables(self.handle, lanes_per_patch, refine_tile, launch_mode)
+
     def autotune(self, cache_path=None):
         _lib.dis_autotune(self.handle, cache_path)
 
     def debug_level(self, s: int, what: int):
         """Intermediate of the last forward at scale s as a float64 numpy array."""
+        if what == _lib.DIS_DBG_WAIT_ERRORS:
+            n = np.zeros(1, np.int32)
+            _lib.dis_debug_level(self.handle, s, what, n.ctypes.data, n.nbytes)
+            return int(n[0])
         info = np.zeros(6, np.int32)
         _lib.dis_debug_level(self.handle, s, _lib.DIS_DBG_INFO, info.ctypes.data, info.nbytes)
         W, H, N = int(info[0]), int(info[1]), int(info[2])

@@ -34,12 +34,13 @@ DIS_DBG_UPATCH = 3
 DIS_DBG_UDENSE = 4
 DIS_DBG_UREFINED = 5
 DIS_DBG_INFO = 6
+DIS_DBG_WAIT_ERRORS = 7
 
 # every symbol include/dis.h declares
 EXPORTS = (
     "dis_default_params", "dis_create", "dis_compute_flow", "dis_compute_flow_batched",
     "dis_flow_backward", "dis_autotune", "dis_last_error", "dis_set_stream",
-    "dis_debug_level", "dis_destroy", "dis_profile_enable", "dis_profile_read",
+    "dis_debug_level", "dis_destroy", "dis_profile_enable", "dis_profile_read", "dis_set_tunables",
 )
 
 
@@ -109,6 +110,7 @@ def load(path: str = LIB_PATH):
     lib.dis_debug_level.argtypes = [H, c_int, c_int, c_void_p, c_size_t]
     lib.dis_profile_enable.argtypes = [H, c_int]
     lib.dis_profile_read.argtypes = [H, POINTER(dis_kernel_stat), c_int, POINTER(c_int)]
+    lib.dis_set_tunables.argtypes = [H, POINTER(c_int), c_int, c_int]
     lib.dis_destroy.argtypes = [H]
     lib.dis_destroy.restype = None
     for name in EXPORTS:
@@ -186,3 +188,12 @@ def dis_profile_read(handle: int, max_kernels: int = 32):
     _check(load().dis_profile_read(c_void_p(handle), arr, max_kernels, ctypes.byref(n)), c_void_p(handle))
     return [dict(name=arr[i].name.decode(), launches=arr[i].launches, total_ms=arr[i].total_ms,
                  bytes=arr[i].bytes, flops=arr[i].flops) for i in range(min(n.value, max_kernels))]
+
+
+def dis_set_tunables(handle: int, lanes_per_patch=None, refine_tile: int = 0, launch_mode: int = 0) -> None:
+    """lanes_per_patch: None or 16 ints (per scale, 0 = automatic)."""
+    arr = None
+    if lanes_per_patch is not None:
+        vals = list(lanes_per_patch) + [0] * (16 - len(lanes_per_patch))
+        arr = (c_int * 16)(*vals[:16])
+    _check(load().dis_set_tunables(c_void_p(handle), arr, refine_tile, launch_mode), c_void_p(handle))

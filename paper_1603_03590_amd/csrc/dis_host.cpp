@@ -29,6 +29,16 @@ static int fail(dis_handle* h, int code, const char* fmt, ...) {
     return code;
 }
 
+int dis_fail(dis_handle* h, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf; else g_null_err = buf;
+    return code;
+}
+
 #define HIPCHK(h, call)                                                                      \
     do {                                                                                     \
         hipError_t e_ = (call);                                                              \
@@ -180,7 +190,6 @@ static int alloc_slot(dis_handle* h, SlotBuf& sb) {
     const size_t pf = (size_t)(W >> sf) * (H >> sf);
     if (p.refine) {
         DALLOC(h, sb.J1w, pf * sizeof(double));
-        DALLOC(h, sb.D, 11 * pf * sizeof(double));
         for (int i = 0; i < 3; ++i) DALLOC(h, sb.dU[i], 2 * pf * sizeof(double));
     }
     return DIS_OK;
@@ -209,6 +218,11 @@ extern "C" int dis_create(const dis_params* p, int max_w, int max_h, int max_bat
         delete h;
         return fail(nullptr, DIS_EHIP, "hipGetDevice failed");
     }
+    {
+        hipDeviceProp_t prop;
+        h->n_cu = hipGetDeviceProperties(&prop, h->device) == hipSuccess ? prop.multiProcessorCount : 256;
+        if (h->n_cu < 1) h->n_cu = 256;
+    }
     int top = 0;
     while (top + 1 < DIS_MAXL && (max_w >> (top + 1)) >= p->patch_size && (max_h >> (top + 1)) >= p->patch_size) ++top;
     h->top = top;
@@ -234,6 +248,7 @@ extern "C" void dis_destroy(dis_handle* h) {
         Plan* pl = kv.second;
         if (pl->exec) hipGraphExecDestroy(pl->exec);
         if (pl->graph) hipGraphDestroy(pl->graph);
+        if (pl->tabs.mem) hipFree(pl->tabs.mem);
         delete pl;
     }
     for (auto& kv : h->bplans) {
@@ -248,6 +263,38 @@ extern "C" void dis_destroy(dis_handle* h) {
 
 extern "C" const char* dis_last_error(const dis_handle* h) {
     return h ? h->err.c_str() : g_null_err.c_str();
+}
+
+static void drop_plans(dis_handle* h) {
+    hipStreamSynchronize(h->stream);
+    for (auto& kv : h->plans) {
+        Plan* pl = kv.second;
+        if (pl->exec) hipGraphExecDestroy(pl->exec);
+        if (pl->graph) hipGraphDestroy(pl->graph);
+        if (pl->tabs.mem) hipFree(pl->tabs.mem);
+        delete pl;
+    }
+    h->plans.clear();
+    for (auto& kv : h->bplans) dis_batch_plan_free(kv.second);
+    h->bplans.clear();
+}
+
+extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int refine_tile, int launch_mode) {
+    if (!h) return fail(nullptr, DIS_EINVAL, "handle is NULL");
+    int tw, th;
+    if (!dis_refine_tile(refine_tile, &tw, &th)) return fail(h, DIS_EINVAL, "unknown refinement tile %d", refine_tile);
+    if (launch_mode != 0 && launch_mode != 1) return fail(h, DIS_EINVAL, "launch mode %d not 0 or 1", launch_mode);
+    if (lanes_per_patch)
+        for (int s = 0; s < DIS_MAXL; ++s) {
+            const int l = lanes_per_patch[s];
+            if (l != 0 && !dis_kernel_search(h->p.patch_size, l))
+                return fail(h, DIS_EINVAL, "no search kernel for patch %d with %d lanes", h->p.patch_size, l);
+        }
+    drop_plans(h);
+    for (int s = 0; s < DIS_MAXL; ++s) h->lpp[s] = lanes_per_patch ? lanes_per_patch[s] : 0;
+    h->refine_tile = refine_tile;
+    h->mode_phase = launch_mode;
+    return DIS_OK;
 }
 
 extern "C" int dis_set_stream(dis_handle* h, void* stream) {
@@ -275,7 +322,7 @@ void Seq::add(const void* fn, dim3 grid, dim3 block, const void* arg, size_t byt
 int dis_pick_lpp(const dis_handle* h, int s, int N) {
     const int ps = h->p.patch_size;
     if (h->lpp[s] && dis_kernel_search(ps, h->lpp[s])) return h->lpp[s];
-    // many patches: fewest lanes per patch available (less shuffle work per
+    // many patches: fewest lanes per patch available (less cross-lane work per
     // pixel); few patches: 16 lanes (shorter dependent chain per patch)
     if (N >= 16384)
         for (int l = 4; l <= 16; l *= 2)
@@ -293,21 +340,37 @@ static int grid_info(const dis_handle* h, int W, int H, LevelGrid* g) {
     return g->nx * g->ny;
 }
 
-// Launch sequence of one pair (Alg. 1) into slot `sb`.  Kind 1 launches read
-// the caller's frames, kind 2 write the caller's flow.
-int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const void* I0, const void* I1,
-                   void* flow, Seq& seq, PairInfo* info) {
-    const dis_params& p = h->p;
-    const int ps = p.patch_size;
-    const int ss = dis_coarsest(&p, w, hgt), sf = p.finest_scale;
-    if (sf > ss || (w >> sf) < ps || (hgt >> sf) < ps)
-        return fail(h, DIS_ESIZE, "%dx%d: scale %d is smaller than the %d px patch", w, hgt, sf, ps);
-    if (info) { info->ss = ss; info->sf = sf; }
-    const bool f64io = (p.flags & DIS_FLAG_IO_F64) != 0;
-    const int cmap = (p.flags & DIS_FLAG_PIXEL_CENTRE) ? 1 : 0;
+// ------------------------------------------------------- cost models
+// Algorithmic traffic (bytes every launch must move) and floating-point work
+// per kernel family, from the sizes of the arrays each one reads and writes.
 
-    // pyramid passes: levels a+1 .. a+5 from level a
-    for (int a = 0; a < ss; a += 5) {
+static double search_bytes(double px, double pxn, double N) { return 16.0 * px + 16.0 * pxn + 48.0 * N; }
+static double search_flops(double N, double P, int iters) {
+    // Sobel + Hessian setup 24/px, 15/px and 20 per Gauss-Newton iteration,
+    // 10/px for the final residual
+    return N * (24.0 * P + iters * (15.0 * P + 20.0) + 10.0 * P);
+}
+static double densify_bytes(double px, double N, bool refine) { return 32.0 * px + 32.0 * N + (refine ? 8.0 * px : 0.0); }
+static double densify_flops(double px, double cover, bool refine) { return px * (18.0 * cover + 2.0 + (refine ? 9.0 : 0.0)); }
+static double refine_bytes(double px, bool f, bool in, bool last) {
+    // J0, J1w, U, frozen and starting increments in; increment (and flow) out
+    return px * (16.0 + 16.0 + (f ? 16.0 : 0.0) + (in ? 16.0 : 0.0) + 16.0 + (last ? 16.0 : 0.0));
+}
+static double refine_flops(double px, int nhalf) {
+    // 155 per pixel for linearisation, weights and coefficients, 24 per pixel
+    // update (half of the pixels each half sweep)
+    return px * (155.0 + 12.0 * nhalf);
+}
+
+// ------------------------------------------------------- launch sequences
+
+// Pyramid pass(es) of one pair: levels a+1 .. a+5 from level a.
+static int add_pyramid(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, int ss, const void* I0,
+                       const void* I1, Seq& seq) {
+    const dis_params& p = h->p;
+    const int sf = p.finest_scale;
+    const bool f64io = (p.flags & DIS_FLAG_IO_F64) != 0;
+    for (int a = 0; a < ss || (a == 0 && ss == 0); a += 5) {
         PyrArgs pa;
         std::memset(&pa, 0, sizeof pa);
         const int w0 = w >> a, h0 = hgt >> a;
@@ -347,143 +410,262 @@ int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const 
             if (pa.dst[0][k]) by += 16.0 * px;
         }
         seq.add(dis_kernel_pyramid(), dim3(tiles, 2), dim3(256), &pa, sizeof pa, a == 0 ? 1 : 0, "pyramid", by, fl);
+        if (ss == 0) break;
     }
-    if (ss == 0) {
-        // no pyramid pass ran: level 0 still has to be materialised
-        PyrArgs pa;
-        std::memset(&pa, 0, sizeof pa);
-        pa.src[0] = I0; pa.src[1] = I1;
-        pa.src_kind = f64io ? 2 : 1;
-        pa.src_pitch = pitch;
-        pa.scale = 255.0;
-        pa.w0 = w; pa.h0 = hgt;
-        pa.lvl0[0] = sb.lv[0].J0; pa.lvl0[1] = sb.lv[0].J1;
-        pa.tiles_x = (w + 31) / 32;
-        const double px = (double)w * hgt;
-        seq.add(dis_kernel_pyramid(), dim3(pa.tiles_x * ((hgt + 31) / 32), 2), dim3(256), &pa, sizeof pa, 1,
-                "pyramid", px * (f64io ? 16 : 8) + 16.0 * px, 2.0 * px);
-    }
+    return DIS_OK;
+}
 
-    for (int s = ss; s >= sf; --s) {
-        LevelBuf& L = sb.lv[s];
-        LevelGrid g;
-        const int N = grid_info(h, w >> s, hgt >> s, &g);
-        if (N > L.maxN) return fail(h, DIS_ESIZE, "internal: %d patches exceed capacity %d", N, L.maxN);
-        const int W = g.W, Hh = g.H;
-        // 1-3: grid, initialisation, inverse search
-        SearchArgs sa;
-        std::memset(&sa, 0, sizeof sa);
-        sa.J0 = L.J0; sa.J1 = L.J1; sa.W = W; sa.H = Hh;
-        if (s < ss) { sa.Un = sb.lv[s + 1].U; sa.Wn = w >> (s + 1); sa.Hn = hgt >> (s + 1); }
-        sa.st = g.st; sa.nrx = g.nrx; sa.nry = g.nry; sa.nx = g.nx; sa.ny = g.ny;
-        sa.iters = p.gn_iters;
-        sa.lam = 1e-3;
-        sa.centre_map = cmap;
-        sa.patch = L.patch;
-        sa.uinit = L.uinit;
-        const int lpp = dis_pick_lpp(h, s, N);
-        const void* fn = dis_kernel_search(ps, lpp);
-        if (!fn) return fail(h, DIS_EINVAL, "no search kernel for patch %d, %d lanes", ps, lpp);
-        const int per_block = 256 / lpp;
-        {
-            // traffic: both level images once, the coarser flow, the patch records
-            const double px = (double)W * Hh, P = (double)ps * ps;
-            const double by = 16.0 * px + (s < ss ? 16.0 * (w >> (s + 1)) * (hgt >> (s + 1)) : 0.0) + 48.0 * N;
-            // flops per patch: Sobel + Hessian setup 24/px, 15/px and 20 per
-            // Gauss-Newton iteration, 10/px for the final residual
-            const double fl = (double)N * (24.0 * P + p.gn_iters * (15.0 * P + 20.0) + 10.0 * P);
-            seq.add(fn, dim3((N + per_block - 1) / per_block), dim3(256), &sa, sizeof sa, 0, "search", by, fl);
-        }
-        // 4: densification
-        DensifyArgs da;
-        std::memset(&da, 0, sizeof da);
-        da.J0 = L.J0; da.J1 = L.J1; da.W = W; da.H = Hh;
-        da.patch = L.patch;
-        da.ps = ps; da.st = g.st; da.nrx = g.nrx; da.nry = g.nry; da.nx = g.nx; da.ny = g.ny;
-        da.raw_residual = (p.flags & DIS_FLAG_RAW_RESIDUAL) ? 1 : 0;
-        da.U = L.Ud;
-        da.J1w = p.refine ? sb.J1w : nullptr;
-        const dim3 pgrid((W + 63) / 64, (Hh + 3) / 4);
-        {
-            const double px = (double)W * Hh;
-            const double cover = std::pow((double)ps / g.st, 2.0);
-            const double by = 16.0 * px + 32.0 * N + 16.0 * px + (p.refine ? 8.0 * px : 0.0);
-            const double fl = px * (18.0 * cover + 2.0 + (p.refine ? 9.0 : 0.0));
-            seq.add(dis_kernel_densify(), pgrid, dim3(256), &da, sizeof da, 0, "densify", by, fl);
-        }
-        // 5: variational refinement
-        if (p.refine) {
-            PrepArgs pa;
-            pa.J0 = L.J0; pa.J1w = sb.J1w; pa.W = W; pa.H = Hh; pa.D = sb.D;
-            seq.add(dis_kernel_prep(), pgrid, dim3(256), &pa, sizeof pa, 0, "prep", 104.0 * W * Hh, 60.0 * W * Hh);
-            const int nouter = p.var_outer < 0 ? s + 1 : p.var_outer;
-            int tw, th;
-            dis_refine_tile(h->refine_tile, &tw, &th);
-            const int tiles_x = (W + tw - 1) / tw, tiles = tiles_x * ((Hh + th - 1) / th);
-            int cur = -1;   // buffer holding the current increment, -1 = zero
-            if (nouter == 0) {
-                // no fixed-point iteration: the refined flow is the densified one
-                RefineArgs ra;
-                std::memset(&ra, 0, sizeof ra);
-                ra.U = L.Ud; ra.dUout = sb.dU[0]; ra.Uout = L.U; ra.D = sb.D; ra.W = W; ra.H = Hh;
-                ra.nhalf = 0; ra.tiles_x = tiles_x;
-                ra.delta = p.w_intensity; ra.gamma = p.w_gradient; ra.alpha = p.w_smooth;
-                ra.omega = p.sor_omega; ra.eps = 1e-3;
-                seq.add(dis_kernel_refine(h->refine_tile), dim3(tiles), dim3(256), &ra, sizeof ra, 0, "refine",
-                        136.0 * W * Hh, 0.0);
-            }
-            for (int k = 0; k < nouter; ++k) {
-                const int frozen = cur;
-                int in = cur;
-                int left = 2 * p.var_inner;
-                while (left > 0) {
-                    const int nh = std::min(left, DIS_KMAX);
-                    left -= nh;
-                    int outb = 0;
-                    while (outb == frozen || outb == in) ++outb;
-                    RefineArgs ra;
-                    std::memset(&ra, 0, sizeof ra);
-                    ra.U = L.Ud;
-                    ra.dUf = frozen < 0 ? nullptr : sb.dU[frozen];
-                    ra.dUin = in < 0 ? nullptr : sb.dU[in];
-                    ra.dUout = sb.dU[outb];
-                    ra.Uout = (k == nouter - 1 && left == 0) ? L.U : nullptr;
-                    ra.D = sb.D;
-                    ra.W = W; ra.H = Hh;
-                    ra.nhalf = nh;
-                    ra.tiles_x = tiles_x;
-                    ra.delta = p.w_intensity; ra.gamma = p.w_gradient; ra.alpha = p.w_smooth;
-                    ra.omega = p.sor_omega; ra.eps = 1e-3;
-                    {
-                        // traffic: U, frozen and starting increments, 11
-                        // linearisation planes in; increment (and flow) out
-                        const double px = (double)W * Hh;
-                        const double by = px * (16.0 + (ra.dUf ? 16.0 : 0.0) + (ra.dUin ? 16.0 : 0.0) + 88.0 + 16.0 +
-                                                (ra.Uout ? 16.0 : 0.0));
-                        // 95 flops per pixel for weights and coefficients, 24
-                        // per pixel update (half the pixels each half sweep)
-                        const double fl = px * (95.0 + 12.0 * nh);
-                        seq.add(dis_kernel_refine(h->refine_tile), dim3(tiles), dim3(256), &ra, sizeof ra, 0, "refine",
-                                by, fl);
-                    }
-                    in = outb;
-                }
-                cur = in;
-            }
-        }
-    }
-    // final upscaling (or copy) into the caller's flow
+static void add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, Seq& seq) {
+    const dis_params& p = h->p;
+    const int sf = p.finest_scale;
+    const bool f64io = (p.flags & DIS_FLAG_IO_F64) != 0;
     UpsArgs ua;
     std::memset(&ua, 0, sizeof ua);
     ua.U = sb.lv[sf].U;
-    ua.Ws = w >> sf; ua.Hs = hgt >> sf;
-    ua.W = w; ua.H = hgt;
+    ua.Ws = w >> sf;
+    ua.Hs = hgt >> sf;
+    ua.W = w;
+    ua.H = hgt;
     ua.f = (double)(1 << sf);
-    ua.centre_map = cmap;
+    ua.centre_map = (p.flags & DIS_FLAG_PIXEL_CENTRE) ? 1 : 0;
     ua.out = flow;
     ua.out_f64 = f64io ? 1 : 0;
     seq.add(dis_kernel_upsample(), dim3((w + 63) / 64, (hgt + 3) / 4), dim3(256), &ua, sizeof ua, 2, "upsample",
             16.0 * ua.Ws * ua.Hs + (f64io ? 16.0 : 8.0) * w * hgt, 20.0 * w * hgt);
+}
+
+// Refinement phases of one level: theta_vo fixed-point steps, each split
+// into launches of at most DIS_KMAX half sweeps; three increment buffers
+// rotate so that a phase never writes what it reads.
+static void refine_phases(const dis_params& p, int s, std::vector<RefPhase>& out) {
+    out.clear();
+    const int nouter = p.var_outer < 0 ? s + 1 : p.var_outer;
+    if (nouter == 0) {
+        out.push_back(RefPhase{-1, -1, 0, 0, 1});
+        return;
+    }
+    int cur = -1;
+    for (int k = 0; k < nouter; ++k) {
+        const int frozen = cur;
+        int in = cur;
+        int left = 2 * p.var_inner;
+        while (left > 0) {
+            const int nh = std::min(left, DIS_KMAX);
+            left -= nh;
+            int ob = 0;
+            while (ob == frozen || ob == in) ++ob;
+            out.push_back(RefPhase{frozen, in, ob, nh, (k == nouter - 1 && left == 0) ? 1 : 0});
+            in = ob;
+        }
+        cur = in;
+    }
+}
+
+// Search, densification and refinement of every pair at every level.
+// Persistent mode: one k_level launch per level over all pairs; phase mode:
+// one launch per phase and pair.  Both give the same bits.
+int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs) {
+    const dis_params& p = h->p;
+    const int ps = p.patch_size, sf = p.finest_scale;
+    const int cmap = (p.flags & DIS_FLAG_PIXEL_CENTRE) ? 1 : 0;
+    int top = sf;
+    for (const PairRef& r : pairs) top = std::max(top, r.ss);
+    int tw = 32, th = 16;
+    const int tile_id = h->mode_phase ? h->refine_tile : DIS_LEVEL_TILE;
+    dis_refine_tile(tile_id, &tw, &th);
+
+    struct LevelHost {
+        std::vector<LevelPair> lp;
+        std::vector<RefPhase> rph;
+        std::vector<int> start;
+        int lpp;
+        int nph;
+        double by[3], fl[3];
+    };
+    std::vector<LevelHost> levels;
+    for (int s = top; s >= sf; --s) {
+        LevelHost LH;
+        refine_phases(p, s, LH.rph);
+        if (!p.refine) LH.rph.clear();
+        LH.nph = 2 + (int)LH.rph.size();
+        int maxN = 0;
+        for (const PairRef& r : pairs) {
+            if (r.ss < s) continue;
+            LevelGrid g;
+            maxN = std::max(maxN, grid_info(h, r.w >> s, r.h >> s, &g));
+        }
+        LH.lpp = dis_pick_lpp(h, s, maxN * (int)pairs.size());
+        for (int q = 0; q < 3; ++q) LH.by[q] = LH.fl[q] = 0.0;
+        for (const PairRef& r : pairs) {
+            if (r.ss < s) continue;
+            SlotBuf& sb = *r.sb;
+            LevelBuf& L = sb.lv[s];
+            LevelGrid g;
+            const int N = grid_info(h, r.w >> s, r.h >> s, &g);
+            if (N > L.maxN) return fail(h, DIS_ESIZE, "internal: %d patches exceed capacity %d", N, L.maxN);
+            const int W = g.W, Hh = g.H;
+            LevelPair P;
+            std::memset(&P, 0, sizeof P);
+            SearchArgs& sa = P.sa;
+            sa.J0 = L.J0; sa.J1 = L.J1; sa.W = W; sa.H = Hh;
+            if (s < r.ss) { sa.Un = sb.lv[s + 1].U; sa.Wn = r.w >> (s + 1); sa.Hn = r.h >> (s + 1); }
+            sa.st = g.st; sa.nrx = g.nrx; sa.nry = g.nry; sa.nx = g.nx; sa.ny = g.ny;
+            sa.iters = p.gn_iters;
+            sa.lam = 1e-3;
+            sa.centre_map = cmap;
+            sa.patch = L.patch;
+            sa.uinit = L.uinit;
+            DensifyArgs& da = P.da;
+            da.J0 = L.J0; da.J1 = L.J1; da.W = W; da.H = Hh;
+            da.patch = L.patch;
+            da.ps = ps; da.st = g.st; da.nrx = g.nrx; da.nry = g.nry; da.nx = g.nx; da.ny = g.ny;
+            da.raw_residual = (p.flags & DIS_FLAG_RAW_RESIDUAL) ? 1 : 0;
+            da.U = L.Ud;
+            da.J1w = p.refine ? sb.J1w : nullptr;
+            RefineArgs& ra = P.ra;
+            ra.U = L.Ud; ra.J0 = L.J0; ra.J1w = sb.J1w; ra.Uout = L.U;
+            ra.W = W; ra.H = Hh;
+            ra.tiles_x = (W + tw - 1) / tw;
+            ra.delta = p.w_intensity; ra.gamma = p.w_gradient; ra.alpha = p.w_smooth;
+            ra.omega = p.sor_omega; ra.eps = 1e-3;
+            for (int q = 0; q < 3; ++q) P.dU[q] = sb.dU[q];
+            P.dens_bx = (W + 63) / 64;
+            LH.lp.push_back(P);
+            const double px = (double)W * Hh;
+            const double pxn = s < r.ss ? (double)(r.w >> (s + 1)) * (r.h >> (s + 1)) : 0.0;
+            LH.by[0] += search_bytes(px, pxn, N);
+            LH.fl[0] += search_flops(N, (double)ps * ps, p.gn_iters);
+            LH.by[1] += densify_bytes(px, N, p.refine);
+            LH.fl[1] += densify_flops(px, std::pow((double)ps / g.st, 2.0), p.refine);
+        }
+        levels.push_back(std::move(LH));
+    }
+
+    if (h->mode_phase) {
+        // one launch per phase and pair
+        for (size_t li = 0; li < levels.size(); ++li) {
+            LevelHost& LH = levels[li];
+            const void* fn = dis_kernel_search(ps, LH.lpp);
+            if (!fn) return fail(h, DIS_EINVAL, "no search kernel for patch %d, %d lanes", ps, LH.lpp);
+            for (LevelPair& P : LH.lp) {
+                const int N = P.sa.nx * P.sa.ny, per = 256 / LH.lpp;
+                const double px = (double)P.sa.W * P.sa.H;
+                seq.add(fn, dim3((N + per - 1) / per), dim3(256), &P.sa, sizeof P.sa, 0, "search",
+                        search_bytes(px, P.sa.Un ? (double)P.sa.Wn * P.sa.Hn : 0.0, N),
+                        search_flops(N, (double)ps * ps, p.gn_iters));
+                seq.add(dis_kernel_densify(), dim3(P.dens_bx, (P.da.H + 3) / 4), dim3(256), &P.da, sizeof P.da, 0,
+                        "densify", densify_bytes(px, N, p.refine),
+                        densify_flops(px, std::pow((double)ps / P.da.st, 2.0), p.refine));
+                const int tiles = P.ra.tiles_x * ((P.ra.H + th - 1) / th);
+                for (const RefPhase& rp : LH.rph) {
+                    RefineArgs ra = P.ra;
+                    ra.dUf = rp.f < 0 ? nullptr : P.dU[rp.f];
+                    ra.dUin = rp.in < 0 ? nullptr : P.dU[rp.in];
+                    ra.dUout = P.dU[rp.out];
+                    ra.Uout = rp.last ? P.ra.Uout : nullptr;
+                    ra.nhalf = rp.nhalf;
+                    seq.add(dis_kernel_refine(tile_id), dim3(tiles), dim3(256), &ra, sizeof ra, 0, "refine",
+                            refine_bytes(px, rp.f >= 0, rp.in >= 0, rp.last), refine_flops(px, rp.nhalf));
+                }
+            }
+        }
+        return DIS_OK;
+    }
+
+    // persistent mode: device tables for every level, one allocation
+    size_t bytes = 0;
+    int nsync = 0;
+    std::vector<size_t> off_lp, off_rph, off_start;
+    std::vector<int> off_sync;
+    for (LevelHost& LH : levels) {
+        const int np = (int)LH.lp.size(), nseg = LH.nph * np;
+        auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+        off_lp.push_back(bytes);
+        bytes = al(bytes + sizeof(LevelPair) * np);
+        off_rph.push_back(bytes);
+        bytes = al(bytes + sizeof(RefPhase) * std::max<size_t>(1, LH.rph.size()));
+        off_start.push_back(bytes);
+        bytes = al(bytes + sizeof(int) * (nseg + 1));
+        off_sync.push_back(nsync);
+        tabs.err_index.push_back(nsync + 1);
+        nsync += 2 + nseg;
+    }
+    const size_t sync_off = bytes;
+    bytes += sizeof(int) * nsync;
+    HIPCHK(h, hipMalloc(&tabs.mem, bytes));
+    tabs.bytes = bytes;
+    tabs.sync = (int*)((char*)tabs.mem + sync_off);
+    tabs.nsync = nsync;
+    std::vector<char> host(bytes, 0);
+    for (size_t li = 0; li < levels.size(); ++li) {
+        LevelHost& LH = levels[li];
+        const int np = (int)LH.lp.size(), nseg = LH.nph * np;
+        std::memcpy(host.data() + off_lp[li], LH.lp.data(), sizeof(LevelPair) * np);
+        if (!LH.rph.empty()) std::memcpy(host.data() + off_rph[li], LH.rph.data(), sizeof(RefPhase) * LH.rph.size());
+        // queue segments, phase-major: search blocks, densification blocks,
+        // then the refinement phases, each over all pairs
+        std::vector<int> start(nseg + 1, 0);
+        int t = 0;
+        double rby = 0.0, rfl = 0.0;
+        for (int ph = 0; ph < LH.nph; ++ph) {
+            for (int j = 0; j < np; ++j) {
+                const LevelPair& P = LH.lp[j];
+                start[ph * np + j] = t;
+                int cnt;
+                if (ph == 0) cnt = (P.sa.nx * P.sa.ny * LH.lpp + 255) / 256;
+                else if (ph == 1) cnt = P.dens_bx * ((P.da.H + 3) / 4);
+                else {
+                    cnt = P.ra.tiles_x * ((P.ra.H + th - 1) / th);
+                    const RefPhase& rp = LH.rph[ph - 2];
+                    const double px = (double)P.ra.W * P.ra.H;
+                    rby += refine_bytes(px, rp.f >= 0, rp.in >= 0, rp.last);
+                    rfl += refine_flops(px, rp.nhalf);
+                }
+                t += cnt;
+            }
+        }
+        start[nseg] = t;
+        std::memcpy(host.data() + off_start[li], start.data(), sizeof(int) * (nseg + 1));
+        LevelLaunch LL;
+        std::memset(&LL, 0, sizeof LL);
+        LL.pairs = (const LevelPair*)((char*)tabs.mem + off_lp[li]);
+        LL.rph = (const RefPhase*)((char*)tabs.mem + off_rph[li]);
+        LL.start = (const int*)((char*)tabs.mem + off_start[li]);
+        LL.sync = tabs.sync + off_sync[li];
+        LL.npairs = np;
+        LL.nph = LH.nph;
+        LL.ntasks = t;
+        const void* fn = dis_kernel_level(ps, LH.lpp);
+        if (!fn) return fail(h, DIS_EINVAL, "no level kernel for patch %d, %d lanes", ps, LH.lpp);
+        const int grid = std::max(1, std::min(t, h->n_cu * 2));
+        seq.add(fn, dim3(grid), dim3(256), &LL, sizeof LL, 0, "level", LH.by[0] + LH.by[1] + rby,
+                LH.fl[0] + LH.fl[1] + rfl);
+    }
+    HIPCHK(h, hipMemcpy(tabs.mem, host.data(), bytes, hipMemcpyHostToDevice));
+    return DIS_OK;
+}
+
+// Launch sequence of one pair (Alg. 1) into slot `sb`.  Kind 1 launches read
+// the caller's frames, kind 2 write the caller's flow.
+int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const void* I0, const void* I1,
+                   void* flow, Seq& seq, PairInfo* info, PlanTables& tabs) {
+    const dis_params& p = h->p;
+    const int ps = p.patch_size;
+    const int ss = dis_coarsest(&p, w, hgt), sf = p.finest_scale;
+    if (sf > ss || (w >> sf) < ps || (hgt >> sf) < ps)
+        return fail(h, DIS_ESIZE, "%dx%d: scale %d is smaller than the %d px patch", w, hgt, sf, ps);
+    if (info) { info->ss = ss; info->sf = sf; }
+    const size_t first = seq.items.size();
+    int r = add_pyramid(h, sb, w, hgt, pitch, ss, I0, I1, seq);
+    if (r != DIS_OK) return r;
+    std::vector<PairRef> pr{PairRef{&sb, w, hgt, ss}};
+    r = dis_build_levels(h, pr, seq, tabs);
+    if (r != DIS_OK) return r;
+    add_upsample(h, sb, w, hgt, flow, seq);
+    // the first pyramid launch clears the level launches' queue state
+    PyrArgs* pa = (PyrArgs*)seq.items[first].arg.data();
+    pa->zero = tabs.sync;
+    pa->nzero = tabs.nsync;
     return DIS_OK;
 }
 
@@ -623,8 +805,9 @@ extern "C" int dis_compute_flow(dis_handle* h, const void* I0, const void* I1, i
     auto it = h->plans.find(key);
     if (it == h->plans.end()) {
         pl = new Plan();
-        int r = dis_build_pair(h, h->slots[0], w, hgt, pitch, I0, I1, flow, pl->seq, &pl->info);
+        int r = dis_build_pair(h, h->slots[0], w, hgt, pitch, I0, I1, flow, pl->seq, &pl->info, pl->tabs);
         if (r != DIS_OK) {
+            if (pl->tabs.mem) hipFree(pl->tabs.mem);
             delete pl;
             return r;
         }
@@ -659,6 +842,7 @@ extern "C" int dis_compute_flow(dis_handle* h, const void* I0, const void* I1, i
         h->last_I0 = I0;
         h->last_I1 = I1;
         h->last_pitch = pitch;
+        h->last_tabs = &pl->tabs;
     }
     return r;
 }
@@ -669,6 +853,20 @@ extern "C" int dis_debug_level(dis_handle* h, int s, int what, void* dst, size_t
     if (!h) return fail(nullptr, DIS_EINVAL, "handle is NULL");
     if (!dst) return fail(h, DIS_EINVAL, "dst is NULL");
     if (!h->have_last) return fail(h, DIS_ESTATE, "no forward call yet");
+    if (what == DIS_DBG_WAIT_ERRORS) {
+        // queue-wait timeouts of the last plan's persistent launches
+        if (bytes < sizeof(int32_t)) return fail(h, DIS_ESIZE, "need 4 bytes");
+        int32_t count = 0;
+        const PlanTables* t = h->last_tabs;
+        if (t && t->nsync > 0) {
+            std::vector<int> sync(t->nsync);
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            HIPCHK(h, hipMemcpy(sync.data(), t->sync, sizeof(int) * t->nsync, hipMemcpyDeviceToHost));
+            for (int w : t->err_index) count += sync[w] != 0;
+        }
+        std::memcpy(dst, &count, sizeof count);
+        return DIS_OK;
+    }
     if (s < h->last_sf || s > h->last_ss) return fail(h, DIS_ESTATE, "scale %d not computed (%d..%d)", s, h->last_sf, h->last_ss);
     LevelBuf& L = h->slots[0].lv[s];
     LevelGrid g;

@@ -26,7 +26,6 @@ struct LevelBuf {
 struct SlotBuf {
     LevelBuf lv[DIS_MAXL];
     double* J1w;     // warped frame 1 of the level being refined
-    double* D;       // 11 linearisation planes of that level
     double* dU[3];   // refinement increments (frozen / in / out rotation)
 };
 
@@ -67,8 +66,24 @@ struct PairInfo {
     int ss, sf;
 };
 
+// Device tables of a plan's persistent level launches (one allocation).
+struct PlanTables {
+    void* mem = nullptr;
+    size_t bytes = 0;
+    int* sync = nullptr;    // queue state of every level launch, cleared by the first pyramid launch
+    int nsync = 0;
+    std::vector<int> err_index;   // wait-timeout flag of each level launch inside sync
+};
+
+struct PairRef {
+    SlotBuf* sb;
+    int w, h;
+    int ss;
+};
+
 struct Plan {
     Seq seq;
+    PlanTables tabs;
     PairInfo info{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -93,11 +108,14 @@ struct dis_handle {
     std::map<std::vector<int>, BatchPlan*> bplans;
     int lpp[DIS_MAXL];
     int refine_tile = 0;
+    int mode_phase = 0;     // 1: one launch per phase instead of persistent level launches
+    int n_cu = 256;
     // most recent plain forward call (debug and backward)
     bool have_last = false;
     int last_w = 0, last_h = 0, last_ss = 0, last_sf = 0, last_pitch = 0;
     const void* last_I0 = nullptr;
     const void* last_I1 = nullptr;
+    const PlanTables* last_tabs = nullptr;
     // per-kernel event timing (dis_profile_enable)
     bool profiling = false;
     std::vector<ProfPending> prof_pending;
@@ -110,5 +128,7 @@ int dis_coarsest(const dis_params* p, int w, int h);
 void dis_grid(int n, int ps, int st, int* nr, int* ntot);
 int dis_pick_lpp(const dis_handle* h, int s, int N);
 int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const void* I0, const void* I1,
-                   void* flow, Seq& seq, PairInfo* info);
+                   void* flow, Seq& seq, PairInfo* info, PlanTables& tabs);
+int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs);
+int dis_fail(dis_handle* h, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 int dis_launch_eager(dis_handle* h, Seq& seq);

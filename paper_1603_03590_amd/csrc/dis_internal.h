@@ -7,6 +7,7 @@
 
 #define DIS_MAXL 16   // pyramid levels a handle can hold
 #define DIS_KMAX 10   // red-black half sweeps one refinement launch can fuse
+#define DIS_LEVEL_TILE 0   // refinement tile id used inside the persistent level kernel
 
 // Pyramid: from level `a` (the caller's frames when a == 0) compute the
 // 2x2-box levels a+1 .. a+nlev (nlev <= 5) in one pass over 32x32 tiles.
@@ -21,6 +22,8 @@ struct PyrArgs {
     double* lvl0[2];        // receives the scaled level a when non-null
     double* dst[2][6];      // dst[f][k]: level a+k, or null when not kept
     int ws[6], hs[6];
+    int* zero;              // block 0 clears these ints (queue state of the level launches)
+    int nzero;
 };
 
 // Inverse search on one level: grid, initialisation, Gauss-Newton, reset,
@@ -51,25 +54,18 @@ struct DensifyArgs {
     double* J1w;            // [H][W], or null without refinement
 };
 
-// Linearisation of the refinement energy: 11 planes
-// Ix, Iy, Iz, Ixx, Ixy, Iyy, Ixz, Iyz, beta0, betax, betay.
-struct PrepArgs {
-    const double* J0;
-    const double* J1w;
-    int W, H;
-    double* D;
-};
-
-// Part of one fixed-point iteration of the refinement: robust weights from
-// the frozen increment dUf, then nhalf red-black half sweeps starting from
-// dUin, written to dUout (and U + dU to Uout when non-null).
+// Part of one fixed-point iteration of the refinement: linearisation from
+// J0 and the warped J1w, robust weights from the frozen increment dUf, then
+// nhalf red-black half sweeps starting from dUin, written to dUout (and
+// U + dU to Uout when non-null).
 struct RefineArgs {
     const double* U;
+    const double* J0;
+    const double* J1w;
     const double* dUf;      // null = zero
     const double* dUin;     // null = zero
     double* dUout;
     double* Uout;
-    const double* D;
     int W, H;
     int nhalf;
     int tiles_x;
@@ -87,12 +83,41 @@ struct UpsArgs {
     int out_f64;
 };
 
+// One pair at one level inside a persistent level launch.  Its work is a
+// queue segment per phase: phase 0 = search blocks, phase 1 = densification
+// blocks, phases 2.. = refinement steps (one tile each).
+struct LevelPair {
+    SearchArgs sa;
+    DensifyArgs da;
+    RefineArgs ra;          // the per-phase increment buffers come from RefPhase
+    double* dU[3];
+    int dens_bx;            // densification blocks per row
+};
+
+// Buffers of one refinement phase: indices into LevelPair::dU (-1 = zero).
+struct RefPhase {
+    int f, in, out;
+    int nhalf;
+    int last;               // 1: also write U + dU
+};
+
+// A persistent launch over the queue segments of every pair at one level,
+// ordered phase-major; a task waits only for the previous phase of its own
+// pair, which sits earlier in the queue, so the queue cannot deadlock.
+struct LevelLaunch {
+    const LevelPair* pairs;
+    const RefPhase* rph;
+    const int* start;       // [nph * npairs + 1] first task of each segment
+    int* sync;              // [0] queue head, [1] wait-timeout flag, [2 + seg] finished tasks
+    int npairs, nph, ntasks;
+};
+
 // Kernel entry points, looked up by the host.
 const void* dis_kernel_pyramid();
 const void* dis_kernel_search(int ps, int lpp);   // null when not compiled
 const void* dis_kernel_densify();
-const void* dis_kernel_prep();
 const void* dis_kernel_refine(int tile);          // tile id, see dis_refine_tile
 const void* dis_kernel_upsample();
+const void* dis_kernel_level(int ps, int lpp);    // persistent level kernel, null when not compiled
 // refinement core tile (width, height) of a tile id; returns 0 for an unknown id
 int dis_refine_tile(int tile, int* tw, int* th);

@@ -7,8 +7,11 @@
 //
 // Built with -ffp-contract=off: every multiply-add the kernels fuse is an
 // explicit fma(), so results do not depend on template instance or launch
-// shape (the search's lanes-per-patch and the refinement's tile are free to
-// change without changing a bit of the output).
+// shape (the search's lanes-per-patch, the refinement's tile, the persistent
+// or per-phase launch) -- all of them give the same bits.
+//
+// Each step is a device function over one block of work; the per-phase
+// kernels and the persistent level kernel both call them.
 #include <hip/hip_runtime.h>
 #include "dis_internal.h"
 
@@ -34,12 +37,23 @@ __device__ __forceinline__ double bilin(const double* __restrict__ img, int W, i
     return (1.0 - ay) * top + ay * bot;
 }
 
+// Cross-lane move of a double with a DPP pattern (two 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int l2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+    const int h2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
+    return __hiloint2double(h2, l2);
+}
+
 // ------------------------------------------------------------------ pyramid
 
 __global__ __launch_bounds__(256) void k_pyramid(const PyrArgs a) {
     __shared__ double t0[32][33];
     __shared__ double t1[16][17];
     const int f = blockIdx.y;
+    if (blockIdx.x == 0 && f == 0)
+        for (int i = threadIdx.x; i < a.nzero; i += 256) a.zero[i] = 0;
     const int bx = blockIdx.x % a.tiles_x, by = blockIdx.x / a.tiles_x;
     const int X0 = bx * 32, Y0 = by * 32;
     for (int i = threadIdx.x; i < 1024; i += 256) {
@@ -91,8 +105,9 @@ __global__ __launch_bounds__(256) void k_pyramid(const PyrArgs a) {
 // GS = ceil(PS*PS/16) consecutive pixels; a group is summed sequentially
 // (fma for products), then the 16 group sums pairwise in a fixed binary tree.
 // A lane holds GPL = 16/LPP consecutive groups; the tree levels inside a lane
-// are done in registers, the rest by xor shuffles across the LPP lanes of
-// the patch.  The order is the same for every LPP.
+// are done in registers, the rest across the LPP lanes of the patch with DPP
+// moves that pair each block of lanes with the neighbouring block (every lane
+// of a block holds the block's sum by then, so the pairing is the tree's).
 template <int GS, int GPL, int LPP>
 __device__ __forceinline__ double tree_finish(double (&g)[GPL]) {
 #pragma unroll
@@ -100,8 +115,10 @@ __device__ __forceinline__ double tree_finish(double (&g)[GPL]) {
 #pragma unroll
         for (int j = 0; j < GPL; j += 2 * step) g[j] = g[j] + g[j + step];
     double s = g[0];
-#pragma unroll
-    for (int off = 1; off < LPP; off <<= 1) s = s + __shfl_xor(s, off, 64);
+    if (LPP >= 2) s = s + dpp_mov<0xB1>(s);    // quad_perm [1,0,3,2]
+    if (LPP >= 4) s = s + dpp_mov<0x4E>(s);    // quad_perm [2,3,0,1]
+    if (LPP >= 8) s = s + dpp_mov<0x141>(s);   // row_half_mirror
+    if (LPP >= 16) s = s + dpp_mov<0x140>(s);  // row_mirror
     return s;
 }
 
@@ -131,13 +148,13 @@ __device__ __forceinline__ double csum_prod(const double (&a)[GS * GPL], const d
     return tree_finish<GS, GPL, LPP>(g);
 }
 
-// One thread group of LPP lanes per patch, 256 threads per block.  Patch
+// One block of 256 threads = 256/LPP patches, LPP lanes per patch.  Patch
 // corners, initialisation (Sec. 2.2 steps 1-2), template and Sobel/8
 // gradients, the precomputed 2x2 Hessian, theta_it inverse-compositional
 // updates u <- u - H^-1 sum grad(T) r (Suppl. A), the reset test of step 4,
 // and the mean residual at the final u, which densification needs.
 template <int PS, int LPP>
-__global__ __launch_bounds__(256) void k_search(const SearchArgs a) {
+__device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
     constexpr int NP = PS * PS;
     constexpr int GS = (NP + 15) / 16;
     constexpr int GPL = 16 / LPP;
@@ -145,9 +162,9 @@ __global__ __launch_bounds__(256) void k_search(const SearchArgs a) {
     const int W = a.W, H = a.H;
     const int lane = threadIdx.x & (LPP - 1);
     const int N = a.nx * a.ny;
-    int pi = (int)((blockIdx.x * 256u + threadIdx.x) / LPP);
+    int pi = (int)((block * 256u + threadIdx.x) / LPP);
     const bool valid = pi < N;
-    if (!valid) pi = N - 1;    // idle groups shadow the last patch (no store): shuffles stay uniform
+    if (!valid) pi = N - 1;    // idle groups shadow the last patch (no store): DPP stays uniform
 
     const int ky = pi / a.nx, kx = pi - ky * a.nx;
     const int x0 = kx < a.nrx ? kx * a.st : W - PS;
@@ -166,7 +183,6 @@ __global__ __launch_bounds__(256) void k_search(const SearchArgs a) {
     const double* __restrict__ J0 = a.J0;
     const double* __restrict__ J1 = a.J1;
     double T[PPL], gx[PPL], gy[PPL];
-    int off[PPL];      // pixel offset py*W + px inside the frame
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int p = lane * PPL + k;
@@ -184,9 +200,8 @@ __global__ __launch_bounds__(256) void k_search(const SearchArgs a) {
             const double e0 = J0[yp * W + x] - J0[ym * W + x];
             const double ep = J0[yp * W + xp] - J0[ym * W + xp];
             gy[k] = ((em + 2.0 * e0) + ep) / 8.0;
-            off[k] = py * W + px;
         } else {
-            T[k] = 0.0; gx[k] = 0.0; gy[k] = 0.0; off[k] = -1;
+            T[k] = 0.0; gx[k] = 0.0; gy[k] = 0.0;
         }
     }
     const double h11 = csum_prod<GS, GPL, LPP>(gx, gx);
@@ -195,7 +210,9 @@ __global__ __launch_bounds__(256) void k_search(const SearchArgs a) {
     const double sgx = csum<GS, GPL, LPP>(gx);
     const double sgy = csum<GS, GPL, LPP>(gy);
     const double a11 = h11 + a.lam, a22 = h22 + a.lam, a12 = h12;
-    const double det = a11 * a22 - a12 * a12;
+    const double idet = 1.0 / (a11 * a22 - a12 * a12);
+    // H^-1 b = (m11 b1 + m12 b2, m12 b1 + m22 b2)
+    const double m11 = a22 * idet, m12 = -a12 * idet, m22 = a11 * idet;
     const double inv_n = 1.0 / (double)NP;
     const double lim = (double)(W + H + 2 * PS + 4);
 
@@ -214,8 +231,9 @@ __global__ __launch_bounds__(256) void k_search(const SearchArgs a) {
         double d[PPL];
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-            if (off[k] >= 0) {
-                const int py = (lane * PPL + k) / PS, px = (lane * PPL + k) - py * PS;
+            const int p = lane * PPL + k;
+            if (p < NP) {
+                const int py = p / PS, px = p - py * PS;
                 const int xa = x0 + px + iu, ya = y0 + py + iv;
                 const int c0 = clampi(xa, 0, W - 1), c1 = clampi(xa + 1, 0, W - 1);
                 const int r0 = clampi(ya, 0, H - 1) * W, r1 = clampi(ya + 1, 0, H - 1) * W;
@@ -232,8 +250,8 @@ __global__ __launch_bounds__(256) void k_search(const SearchArgs a) {
         // b = sum grad(T) (d - mean d): the mean-normalised residual (Sec. 2.1)
         const double b1 = csum_prod<GS, GPL, LPP>(gx, d) - md * sgx;
         const double b2 = csum_prod<GS, GPL, LPP>(gy, d) - md * sgy;
-        u = u - (a22 * b1 - a12 * b2) / det;
-        v = v - (a11 * b2 - a12 * b1) / det;
+        u = u - (m11 * b1 + m12 * b2);
+        v = v - (m12 * b1 + m22 * b2);
     }
     if (valid && lane == 0) {
         double* P = a.patch + (size_t)pi * 4;
@@ -241,6 +259,11 @@ __global__ __launch_bounds__(256) void k_search(const SearchArgs a) {
         a.uinit[(size_t)pi * 2] = ui;
         a.uinit[(size_t)pi * 2 + 1] = vi;
     }
+}
+
+template <int PS, int LPP>
+__global__ __launch_bounds__(256) void k_search(const SearchArgs a) {
+    search_block<PS, LPP>(a, blockIdx.x);
 }
 
 // ------------------------------------------------------------ densification
@@ -254,12 +277,13 @@ __device__ __forceinline__ void cover_range(int x, int n, int ps, int st, int nr
     flush = (ntot > nr) && (x >= n - ps);
 }
 
-// Eq. (3): per pixel, gather the covering patches in ascending patch index,
-// weight each displacement by 1 / max(1, |d_i(x)|) with d_i the
-// mean-normalised residual at that patch's displacement.
-__global__ __launch_bounds__(256) void k_densify(const DensifyArgs a) {
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+// Eq. (3) on a 64x4 block: per pixel, gather the covering patches in
+// ascending patch index, weight each displacement by 1 / max(1, |d_i(x)|)
+// with d_i the mean-normalised residual at that patch's displacement; then
+// the second frame warped by the dense flow, for the refinement.
+__device__ __forceinline__ void densify_block(const DensifyArgs& a, int bx, int by) {
+    const int x = bx * 64 + (threadIdx.x & 63);
+    const int y = by * 4 + (threadIdx.x >> 6);
     const int W = a.W, H = a.H;
     if (x >= W || y >= H) return;
     int kx0, kx1, ky0, ky1;
@@ -290,175 +314,216 @@ __global__ __launch_bounds__(256) void k_densify(const DensifyArgs a) {
     if (a.J1w) a.J1w[g] = bilin(a.J1, W, H, (double)x + U, (double)y + V);
 }
 
-// -------------------------------------------------------- refinement setup
-
-// Central differences [-1 0 1]/2 with replicated borders of the mean image
-// (J0 + J1w)/2, of J1w - J0, and their second differences; the three data
-// normalisations of Sec. 2.3.
-__global__ __launch_bounds__(256) void k_prep(const PrepArgs a) {
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int W = a.W, H = a.H;
-    if (x >= W || y >= H) return;
-    const double* __restrict__ A = a.J0;
-    const double* __restrict__ B = a.J1w;
-    auto cx = [&](int v) { return clampi(v, 0, W - 1); };
-    auto cy = [&](int v) { return clampi(v, 0, H - 1); };
-    auto Ib = [&](int xx, int yy) { return 0.5 * (A[yy * W + xx] + B[yy * W + xx]); };
-    auto Ixa = [&](int xx, int yy) { return (Ib(cx(xx + 1), yy) - Ib(cx(xx - 1), yy)) / 2.0; };
-    auto Iya = [&](int xx, int yy) { return (Ib(xx, cy(yy + 1)) - Ib(xx, cy(yy - 1))) / 2.0; };
-    const int xm = cx(x - 1), xp = cx(x + 1), ym = cy(y - 1), yp = cy(y + 1);
-    const double Ix = Ixa(x, y);
-    const double Iy = Iya(x, y);
-    const int g = y * W + x;
-    const double Iz = B[g] - A[g];
-    const double Ixx = (Ixa(xp, y) - Ixa(xm, y)) / 2.0;
-    const double Ixy = (Ixa(x, yp) - Ixa(x, ym)) / 2.0;
-    const double Iyy = (Iya(x, yp) - Iya(x, ym)) / 2.0;
-    const double Ixz = (B[y * W + xp] - B[y * W + xm]) / 2.0 - (A[y * W + xp] - A[y * W + xm]) / 2.0;
-    const double Iyz = (B[yp * W + x] - B[ym * W + x]) / 2.0 - (A[yp * W + x] - A[ym * W + x]) / 2.0;
-    const size_t n = (size_t)W * H;
-    double* D = a.D;
-    D[0 * n + g] = Ix;
-    D[1 * n + g] = Iy;
-    D[2 * n + g] = Iz;
-    D[3 * n + g] = Ixx;
-    D[4 * n + g] = Ixy;
-    D[5 * n + g] = Iyy;
-    D[6 * n + g] = Ixz;
-    D[7 * n + g] = Iyz;
-    D[8 * n + g] = 1.0 / ((Ix * Ix + Iy * Iy) + 0.01);
-    D[9 * n + g] = 1.0 / ((Ixx * Ixx + Ixy * Ixy) + 0.01);
-    D[10 * n + g] = 1.0 / ((Ixy * Ixy + Iyy * Iyy) + 0.01);
+__global__ __launch_bounds__(256) void k_densify(const DensifyArgs a) {
+    densify_block(a, blockIdx.x, blockIdx.y);
 }
 
 // --------------------------------------------------------------- refinement
 
-// alpha / (2 sqrt(E_S + eps^2)) at (x, y) from forward differences of U + dU
-// (zero across the last column / row).
-__device__ __forceinline__ double smooth_weight(const RefineArgs& a, int x, int y) {
-    const int W = a.W, H = a.H, g = y * W + x;
-    const size_t n = (size_t)W * H;
-    const double* U = a.U;
-    const double* F = a.dUf;
-    auto uu = [&](int i) { return F ? U[i] + F[i] : U[i]; };
-    auto vv = [&](int i) { return F ? U[n + i] + F[n + i] : U[n + i]; };
-    const double u0 = uu(g), v0 = vv(g);
-    double dxu = 0.0, dyu = 0.0, dxv = 0.0, dyv = 0.0;
-    if (x < W - 1) { dxu = uu(g + 1) - u0; dxv = vv(g + 1) - v0; }
-    if (y < H - 1) { dyu = uu(g + W) - u0; dyv = vv(g + W) - v0; }
-    const double es = ((dxu * dxu + dyu * dyu) + dxv * dxv) + dyv * dyv;
-    return a.alpha / (2.0 * sqrt(es + a.eps * a.eps));
-}
+// LDS of one refinement tile: the core (TW x TH) grows by up to K = DIS_KMAX
+// pixels per side (the region); the image tile grows by 2 more for the
+// second differences.  The increments share storage with the image tile,
+// which is dead by the time they are loaded.
+template <int TW, int TH>
+struct RefineSmem {
+    static constexpr int K = DIS_KMAX;
+    static constexpr int RWM = TW + 2 * K, RHM = TH + 2 * K;
+    static constexpr int LP = RWM + 1;               // region row pitch
+    static constexpr int IWM = RWM + 4, IHM = RHM + 4;
+    static constexpr int IP = IWM + 1;               // image-tile row pitch
+    double wr[RHM * LP];                            // weight of the edge to the right
+    double wd[RHM * LP];                            // weight of the edge below
+    union {
+        struct { double t0[IHM * IP], t1[IHM * IP]; } img;   // J0 / J1w, first U+dUf
+        struct { double du[RHM * LP], dv[RHM * LP]; } inc;
+    } u;
+};
 
-// One tile of the refinement.  The tile's core (TW x TH) is extended by
-// nhalf pixels on every side that is not the image border; the sweeps run on
-// the extended region in LDS, where an update can only be wrong at
+// One tile of one fixed-point step of the refinement (Sec. 2.3).  The core
+// is extended by nhalf pixels on every side that is not the image border;
+// the sweeps run on that region in LDS, where an update can be wrong only at
 // distance < j from a cut side after j half sweeps, so after nhalf half
 // sweeps the core equals the untiled result exactly.  Each thread owns pairs
-// of horizontally adjacent pixels (one of each colour), keeping their SOR
+// of horizontally adjacent pixels (one of each colour) and keeps their SOR
 // coefficients in registers; LDS holds the increments and the edge weights.
 template <int TW, int TH>
-__global__ __launch_bounds__(256) void k_refine(const RefineArgs a) {
-    constexpr int K = DIS_KMAX;
-    constexpr int RWM = TW + 2 * K, RHM = TH + 2 * K;
-    constexpr int LP = RWM + 1;                 // LDS row pitch
-    constexpr int PWM = (RWM + 1) / 2;
-    constexpr int PPT = (PWM * RHM + 255) / 256;
-    __shared__ double s_du[RHM * LP], s_dv[RHM * LP], s_wr[RHM * LP], s_wd[RHM * LP];
+__device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, RefineSmem<TW, TH>& sm) {
+    using S = RefineSmem<TW, TH>;
+    constexpr int LP = S::LP, IP = S::IP;
+    constexpr int PWM = (S::RWM + 1) / 2;
+    constexpr int PPT = (PWM * S::RHM + 255) / 256;
 
     const int W = a.W, H = a.H;
     const size_t n = (size_t)W * H;
-    const int kh = a.nhalf;
-    const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+    const int kh = __builtin_amdgcn_readfirstlane(a.nhalf);   // steers a loop with barriers
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int cx0 = tx * TW, cy0 = ty * TH;
     const int cx1 = min(cx0 + TW, W), cy1 = min(cy0 + TH, H);
     const int rx0 = max(cx0 - kh, 0), ry0 = max(cy0 - kh, 0);
     const int rx1 = min(cx1 + kh, W), ry1 = min(cy1 + kh, H);
     const int RW = rx1 - rx0, RH = ry1 - ry0;
+    const double* __restrict__ U = a.U;
+    const double* __restrict__ F = a.dUf;
 
-    for (int i = threadIdx.x; i < RW * RH; i += 256) {
-        const int ly = i / RW, lx = i - ly * RW;
-        const int x = rx0 + lx, y = ry0 + ly, g = y * W + x;
-        const double ws = smooth_weight(a, x, y);
-        const int l = ly * LP + lx;
-        s_wr[l] = x < W - 1 ? ws : 0.0;
-        s_wd[l] = y < H - 1 ? ws : 0.0;
-        s_du[l] = a.dUin ? a.dUin[g] : 0.0;
-        s_dv[l] = a.dUin ? a.dUin[n + g] : 0.0;
+    // 1. full flow U + dUf on the region plus one column / row, for E_S
+    {
+        const int ex1 = min(rx1 + 1, W), ey1 = min(ry1 + 1, H);
+        const int EW = ex1 - rx0, EH = ey1 - ry0;
+        double* tu = sm.u.img.t0;
+        double* tv = sm.u.img.t1;
+#pragma unroll 4
+        for (int i = threadIdx.x; i < EW * EH; i += 256) {
+            const int ly = i / EW, lx = i - ly * EW;
+            const size_t g = (size_t)(ry0 + ly) * W + rx0 + lx;
+            tu[ly * IP + lx] = F ? U[g] + F[g] : U[g];
+            tv[ly * IP + lx] = F ? U[n + g] + F[n + g] : U[n + g];
+        }
+    }
+    __syncthreads();
+    // 2. smoothness weight alpha / (2 sqrt(E_S + eps^2)) of every region pixel,
+    //    from forward differences (zero across the last column / row)
+    {
+        const double* tu = sm.u.img.t0;
+        const double* tv = sm.u.img.t1;
+        const double eps2 = a.eps * a.eps;
+        for (int i = threadIdx.x; i < RW * RH; i += 256) {
+            const int ly = i / RW, lx = i - ly * RW;
+            const int x = rx0 + lx, y = ry0 + ly;
+            const int e = ly * IP + lx;
+            const double u0 = tu[e], v0 = tv[e];
+            double dxu = 0.0, dyu = 0.0, dxv = 0.0, dyv = 0.0;
+            if (x < W - 1) { dxu = tu[e + 1] - u0; dxv = tv[e + 1] - v0; }
+            if (y < H - 1) { dyu = tu[e + IP] - u0; dyv = tv[e + IP] - v0; }
+            const double es = ((dxu * dxu + dyu * dyu) + dxv * dxv) + dyv * dyv;
+            const double ws = a.alpha / (2.0 * sqrt(es + eps2));
+            sm.wr[ly * LP + lx] = x < W - 1 ? ws : 0.0;
+            sm.wd[ly * LP + lx] = y < H - 1 ? ws : 0.0;
+        }
+    }
+    __syncthreads();
+    // 3. J0 and the warped J1w on the region plus two pixels
+    const int ix0 = max(rx0 - 2, 0), iy0 = max(ry0 - 2, 0);
+    {
+        const int ix1 = min(rx1 + 2, W), iy1 = min(ry1 + 2, H);
+        const int IW = ix1 - ix0, IH = iy1 - iy0;
+#pragma unroll 4
+        for (int i = threadIdx.x; i < IW * IH; i += 256) {
+            const int ly = i / IW, lx = i - ly * IW;
+            const size_t g = (size_t)(iy0 + ly) * W + ix0 + lx;
+            sm.u.img.t0[ly * IP + lx] = a.J0[g];
+            sm.u.img.t1[ly * IP + lx] = a.J1w[g];
+        }
     }
     __syncthreads();
 
+    // 4. per owned pixel: linearisation (central differences [-1 0 1]/2 with
+    //    replicated borders of (J0+J1w)/2 and of J1w - J0, the normalisations
+    //    beta), robust data weights at the frozen increment, SOR coefficients
     const double om = a.omega, om1 = 1.0 - a.omega;
     const double eps2 = a.eps * a.eps;
     const int npw = (RW + 1) / 2;
-    // per owned pixel: LDS index, neighbour mask, 4 edge weights, A12,
-    // omega/(A11+S), omega/(A22+S), constant parts c1, c2
     int c_l[PPT][2], c_m[PPT][2];
     double c_wr[PPT][2], c_wl[PPT][2], c_wd[PPT][2], c_wu[PPT][2];
     double c_a12[PPT][2], c_i1[PPT][2], c_i2[PPT][2], c_c1[PPT][2], c_c2[PPT][2];
+    {
+        const double* t0 = sm.u.img.t0;
+        const double* t1 = sm.u.img.t1;
+        // image-tile index of a position already clamped to the image
+        auto li = [&](int x, int y) { return (y - iy0) * IP + (x - ix0); };
+        auto Ib = [&](int x, int y) { const int l = li(x, y); return 0.5 * (t0[l] + t1[l]); };
+        auto Ixa = [&](int x, int y) {
+            return (Ib(min(x + 1, W - 1), y) - Ib(max(x - 1, 0), y)) / 2.0;
+        };
+        auto Iya = [&](int x, int y) {
+            return (Ib(x, min(y + 1, H - 1)) - Ib(x, max(y - 1, 0))) / 2.0;
+        };
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int pr = threadIdx.x + k * 256;
+        for (int k = 0; k < PPT; ++k) {
+            const int pr = threadIdx.x + k * 256;
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            c_l[k][c] = -1;
-            c_m[k][c] = 0;
-            c_wr[k][c] = c_wl[k][c] = c_wd[k][c] = c_wu[k][c] = 0.0;
-            c_a12[k][c] = c_i1[k][c] = c_i2[k][c] = c_c1[k][c] = c_c2[k][c] = 0.0;
-            if (pr >= npw * RH) continue;
-            const int ly = pr / npw, m = pr - ly * npw;
-            const int y = ry0 + ly;
-            const int lx = 2 * m + (((rx0 + y) & 1) ^ c);
-            if (lx >= RW) continue;
-            const int x = rx0 + lx, g = y * W + x;
-            const int l = ly * LP + lx;
-            const double* D = a.D;
-            const double Ix = D[g], Iy = D[n + g], Iz = D[2 * n + g];
-            const double Ixx = D[3 * n + g], Ixy = D[4 * n + g], Iyy = D[5 * n + g];
-            const double Ixz = D[6 * n + g], Iyz = D[7 * n + g];
-            const double b0 = D[8 * n + g], bx = D[9 * n + g], by = D[10 * n + g];
-            const double fu = a.dUf ? a.dUf[g] : 0.0, fv = a.dUf ? a.dUf[n + g] : 0.0;
-            const double ri = (Ix * fu + Iy * fv) + Iz;
-            const double ei = b0 * (ri * ri);
-            const double rx = (Ixx * fu + Ixy * fv) + Ixz;
-            const double ry = (Ixy * fu + Iyy * fv) + Iyz;
-            const double eg = bx * (rx * rx) + by * (ry * ry);
-            const double pi_ = a.delta / (2.0 * sqrt(ei + eps2));
-            const double pg = a.gamma / (2.0 * sqrt(eg + eps2));
-            const double A11 = ((pi_ * b0) * Ix) * Ix + pg * (((bx * Ixx) * Ixx) + ((by * Ixy) * Ixy));
-            const double A12 = ((pi_ * b0) * Ix) * Iy + pg * (((bx * Ixx) * Ixy) + ((by * Ixy) * Iyy));
-            const double A22 = ((pi_ * b0) * Iy) * Iy + pg * (((bx * Ixy) * Ixy) + ((by * Iyy) * Iyy));
-            const double B1 = ((pi_ * b0) * Ix) * Iz + pg * (((bx * Ixx) * Ixz) + ((by * Ixy) * Iyz));
-            const double B2 = ((pi_ * b0) * Iy) * Iz + pg * (((bx * Ixy) * Ixz) + ((by * Iyy) * Iyz));
-            // edges: right/down owned by this pixel, left/up by the neighbour;
-            // neighbours outside the region (not the image) are dropped here,
-            // which only disturbs pixels the erosion argument discards
-            const bool hr = x < W - 1 && lx + 1 < RW, hl = x > 0 && lx > 0;
-            const bool hd = y < H - 1 && ly + 1 < RH, hu = y > 0 && ly > 0;
-            const double wr = hr ? s_wr[l] : 0.0, wl = hl ? s_wr[l - 1] : 0.0;
-            const double wd = hd ? s_wd[l] : 0.0, wu = hu ? s_wd[l - LP] : 0.0;
-            const double S = ((wr + wl) + wd) + wu;
-            const double* U = a.U;
-            const double Up = U[g], Vp = U[n + g];
-            const double Ur = hr ? U[g + 1] : 0.0, Ul = hl ? U[g - 1] : 0.0;
-            const double Ud = hd ? U[g + W] : 0.0, Uu = hu ? U[g - W] : 0.0;
-            const double Vr = hr ? U[n + g + 1] : 0.0, Vl = hl ? U[n + g - 1] : 0.0;
-            const double Vd = hd ? U[n + g + W] : 0.0, Vu = hu ? U[n + g - W] : 0.0;
-            const double NU = ((wr * Ur + wl * Ul) + wd * Ud) + wu * Uu;
-            const double NV = ((wr * Vr + wl * Vl) + wd * Vd) + wu * Vu;
-            c_l[k][c] = l;
-            c_m[k][c] = (hr ? 1 : 0) | (hl ? 2 : 0) | (hd ? 4 : 0) | (hu ? 8 : 0);
-            c_wr[k][c] = wr; c_wl[k][c] = wl; c_wd[k][c] = wd; c_wu[k][c] = wu;
-            c_a12[k][c] = A12;
-            c_i1[k][c] = om / (A11 + S);
-            c_i2[k][c] = om / (A22 + S);
-            c_c1[k][c] = (NU - S * Up) - B1;
-            c_c2[k][c] = (NV - S * Vp) - B2;
+            for (int c = 0; c < 2; ++c) {
+                c_l[k][c] = -1;
+                c_m[k][c] = 0;
+                c_wr[k][c] = c_wl[k][c] = c_wd[k][c] = c_wu[k][c] = 0.0;
+                c_a12[k][c] = c_i1[k][c] = c_i2[k][c] = c_c1[k][c] = c_c2[k][c] = 0.0;
+                if (pr >= npw * RH) continue;
+                const int ly = pr / npw, m = pr - ly * npw;
+                const int y = ry0 + ly;
+                const int lx = 2 * m + (((rx0 + y) & 1) ^ c);
+                if (lx >= RW) continue;
+                const int x = rx0 + lx;
+                const size_t g = (size_t)y * W + x;
+                const int l = ly * LP + lx;
+                const int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
+                const int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
+                const double Ix = Ixa(x, y), Iy = Iya(x, y);
+                const int lc = li(x, y);
+                const double Iz = t1[lc] - t0[lc];
+                const double Ixx = (Ixa(xp, y) - Ixa(xm, y)) / 2.0;
+                const double Ixy = (Ixa(x, yp) - Ixa(x, ym)) / 2.0;
+                const double Iyy = (Iya(x, yp) - Iya(x, ym)) / 2.0;
+                const int lxp = li(xp, y), lxm = li(xm, y), lyp = li(x, yp), lym = li(x, ym);
+                const double Ixz = (t1[lxp] - t1[lxm]) / 2.0 - (t0[lxp] - t0[lxm]) / 2.0;
+                const double Iyz = (t1[lyp] - t1[lym]) / 2.0 - (t0[lyp] - t0[lym]) / 2.0;
+                const double b0 = 1.0 / ((Ix * Ix + Iy * Iy) + 0.01);
+                const double bx = 1.0 / ((Ixx * Ixx + Ixy * Ixy) + 0.01);
+                const double by = 1.0 / ((Ixy * Ixy + Iyy * Iyy) + 0.01);
+                const double fu = F ? F[g] : 0.0, fv = F ? F[n + g] : 0.0;
+                const double ri = (Ix * fu + Iy * fv) + Iz;
+                const double ei = b0 * (ri * ri);
+                const double rx = (Ixx * fu + Ixy * fv) + Ixz;
+                const double ry = (Ixy * fu + Iyy * fv) + Iyz;
+                const double eg = bx * (rx * rx) + by * (ry * ry);
+                const double pi_ = a.delta / (2.0 * sqrt(ei + eps2));
+                const double pg = a.gamma / (2.0 * sqrt(eg + eps2));
+                const double A11 = ((pi_ * b0) * Ix) * Ix + pg * (((bx * Ixx) * Ixx) + ((by * Ixy) * Ixy));
+                const double A12 = ((pi_ * b0) * Ix) * Iy + pg * (((bx * Ixx) * Ixy) + ((by * Ixy) * Iyy));
+                const double A22 = ((pi_ * b0) * Iy) * Iy + pg * (((bx * Ixy) * Ixy) + ((by * Iyy) * Iyy));
+                const double B1 = ((pi_ * b0) * Ix) * Iz + pg * (((bx * Ixx) * Ixz) + ((by * Ixy) * Iyz));
+                const double B2 = ((pi_ * b0) * Iy) * Iz + pg * (((bx * Ixy) * Ixz) + ((by * Iyy) * Iyz));
+                // edges: right/down owned by this pixel, left/up by the
+                // neighbour; neighbours outside the region (not the image) are
+                // dropped, which only disturbs pixels the erosion discards
+                const bool hr = x < W - 1 && lx + 1 < RW, hl = x > 0 && lx > 0;
+                const bool hd = y < H - 1 && ly + 1 < RH, hu = y > 0 && ly > 0;
+                const double wr = hr ? sm.wr[l] : 0.0, wl = hl ? sm.wr[l - 1] : 0.0;
+                const double wd = hd ? sm.wd[l] : 0.0, wu = hu ? sm.wd[l - LP] : 0.0;
+                const double Ssum = ((wr + wl) + wd) + wu;
+                const double Up = U[g], Vp = U[n + g];
+                const double Ur = hr ? U[g + 1] : 0.0, Ul = hl ? U[g - 1] : 0.0;
+                const double Ud = hd ? U[g + W] : 0.0, Uu = hu ? U[g - W] : 0.0;
+                const double Vr = hr ? U[n + g + 1] : 0.0, Vl = hl ? U[n + g - 1] : 0.0;
+                const double Vd = hd ? U[n + g + W] : 0.0, Vu = hu ? U[n + g - W] : 0.0;
+                const double NU = ((wr * Ur + wl * Ul) + wd * Ud) + wu * Uu;
+                const double NV = ((wr * Vr + wl * Vl) + wd * Vd) + wu * Vu;
+                c_l[k][c] = l;
+                c_m[k][c] = (hr ? 1 : 0) | (hl ? 2 : 0) | (hd ? 4 : 0) | (hu ? 8 : 0);
+                c_wr[k][c] = wr; c_wl[k][c] = wl; c_wd[k][c] = wd; c_wu[k][c] = wu;
+                c_a12[k][c] = A12;
+                c_i1[k][c] = om / (A11 + Ssum);
+                c_i2[k][c] = om / (A22 + Ssum);
+                c_c1[k][c] = (NU - Ssum * Up) - B1;
+                c_c2[k][c] = (NV - Ssum * Vp) - B2;
+            }
         }
     }
+    __syncthreads();   // the image tile is dead from here on
+    // 5. sweep start
+    {
+        const double* __restrict__ Din = a.dUin;
+#pragma unroll 4
+        for (int i = threadIdx.x; i < RW * RH; i += 256) {
+            const int ly = i / RW, lx = i - ly * RW;
+            const size_t g = (size_t)(ry0 + ly) * W + rx0 + lx;
+            sm.u.inc.du[ly * LP + lx] = Din ? Din[g] : 0.0;
+            sm.u.inc.dv[ly * LP + lx] = Din ? Din[n + g] : 0.0;
+        }
+    }
+    __syncthreads();
 
-    // red-black half sweeps: colour 0 = (x + y) even, first
+    // 6. red-black half sweeps: colour 0 = (x + y) even, first
+    double* du_ = sm.u.inc.du;
+    double* dv_ = sm.u.inc.dv;
     for (int j = 0; j < kh; j += 2) {
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -469,33 +534,42 @@ __global__ __launch_bounds__(256) void k_refine(const RefineArgs a) {
                 const int m = c_m[k][c];
                 const int lr = (m & 1) ? l + 1 : l, ll = (m & 2) ? l - 1 : l;
                 const int ld = (m & 4) ? l + LP : l, lu = (m & 8) ? l - LP : l;
-                const double du = s_du[l], dv = s_dv[l];
-                const double nu = ((c_wr[k][c] * s_du[lr] + c_wl[k][c] * s_du[ll]) + c_wd[k][c] * s_du[ld]) +
-                                  c_wu[k][c] * s_du[lu];
+                const double du = du_[l], dv = dv_[l];
+                const double nu = ((c_wr[k][c] * du_[lr] + c_wl[k][c] * du_[ll]) + c_wd[k][c] * du_[ld]) +
+                                  c_wu[k][c] * du_[lu];
                 const double dun = om1 * du + c_i1[k][c] * ((nu + c_c1[k][c]) - c_a12[k][c] * dv);
-                const double nv = ((c_wr[k][c] * s_dv[lr] + c_wl[k][c] * s_dv[ll]) + c_wd[k][c] * s_dv[ld]) +
-                                  c_wu[k][c] * s_dv[lu];
+                const double nv = ((c_wr[k][c] * dv_[lr] + c_wl[k][c] * dv_[ll]) + c_wd[k][c] * dv_[ld]) +
+                                  c_wu[k][c] * dv_[lu];
                 const double dvn = om1 * dv + c_i2[k][c] * ((nv + c_c2[k][c]) - c_a12[k][c] * dun);
-                s_du[l] = dun;
-                s_dv[l] = dvn;
+                du_[l] = dun;
+                dv_[l] = dvn;
             }
             __syncthreads();
         }
     }
 
+    // 7. the core: increment, and the refined flow after the last step
     const int CW = cx1 - cx0, CH = cy1 - cy0;
     for (int i = threadIdx.x; i < CW * CH; i += 256) {
         const int yy = i / CW, xx = i - yy * CW;
-        const int x = cx0 + xx, y = cy0 + yy, g = y * W + x;
+        const int x = cx0 + xx, y = cy0 + yy;
+        const size_t g = (size_t)y * W + x;
         const int l = (y - ry0) * LP + (x - rx0);
-        const double du = s_du[l], dv = s_dv[l];
+        const double du = du_[l], dv = dv_[l];
         a.dUout[g] = du;
         a.dUout[n + g] = dv;
         if (a.Uout) {
-            a.Uout[g] = a.U[g] + du;
-            a.Uout[n + g] = a.U[n + g] + dv;
+            a.Uout[g] = U[g] + du;
+            a.Uout[n + g] = U[n + g] + dv;
         }
     }
+    __syncthreads();   // LDS is reused by the caller's next tile
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(256) void k_refine(const RefineArgs a) {
+    __shared__ RefineSmem<TW, TH> sm;
+    refine_tile<TW, TH>(a, blockIdx.x, sm);
 }
 
 // ----------------------------------------------------------------- upscale
@@ -519,27 +593,122 @@ __global__ __launch_bounds__(256) void k_upsample(const UpsArgs a) {
     }
 }
 
+// ------------------------------------------------- persistent level kernel
+
+// A waiting block polls at most this many times (about a second) before it
+// flags the launch as failed and moves on; with the queue's ordering a wait
+// always ends long before that.
+constexpr int kSpinLimit = 1 << 21;
+
+// Queue operations of thread 0.  They are kept out of line on purpose: the
+// level kernel's loop holds barriers, and with these thread-0 branches
+// inlined at the loop's edges the compiler's control-flow structurisation
+// can let the other threads run ahead into the next iteration's barrier.
+// Out of line, the loop body the compiler sees is uniform.
+__device__ __attribute__((noinline)) void lane0_take(int* head, int* s_task) {
+    if (threadIdx.x == 0) *s_task = __hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __attribute__((noinline)) void lane0_wait(const int* ctr, int need, int* err, int* s_ok) {
+    if (threadIdx.x == 0) {
+        int ok = 1, spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > kSpinLimit) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+        }
+        *s_ok = ok;
+    }
+}
+
+__device__ __attribute__((noinline)) void lane0_signal(int* ctr) {
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Every pair's work at one level as one launch.  Blocks take tasks from the
+// queue in order; a task of phase p of pair j first waits until phase p-1 of
+// pair j has finished (all those tasks were taken earlier, by running blocks).
+template <int PS, int LPP>
+__global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
+    static_assert(DIS_LEVEL_TILE == 0, "the level kernel refines 32x16 tiles");
+    __shared__ RefineSmem<32, 16> sm;
+    __shared__ int s_task, s_ok;
+    int* head = L.sync;
+    int* err = L.sync + 1;
+    int* done = L.sync + 2;
+    const int nseg = L.nph * L.npairs;
+    // every value steering this loop is made wave-uniform explicitly
+    for (;;) {
+        lane0_take(head, &s_task);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(s_task);
+        __syncthreads();   // s_task is rewritten on the next round
+        if (t >= L.ntasks) break;
+        int lo = 0, hi = nseg;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (__builtin_amdgcn_readfirstlane(L.start[mid]) <= t) lo = mid; else hi = mid;
+        }
+        const int seg = lo;
+        const int phase = seg / L.npairs, pair = seg - phase * L.npairs;
+        const int local = t - __builtin_amdgcn_readfirstlane(L.start[seg]);
+        const int prev = phase > 0 ? seg - L.npairs : seg;
+        const int need = phase > 0 ? __builtin_amdgcn_readfirstlane(L.start[prev + 1] - L.start[prev]) : 0;
+        lane0_wait(done + prev, need, err, &s_ok);
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int ok = __builtin_amdgcn_readfirstlane(s_ok);
+        const LevelPair& P = L.pairs[pair];
+        if (ok) {
+            if (phase == 0) {
+                search_block<PS, LPP>(P.sa, local);
+            } else if (phase == 1) {
+                densify_block(P.da, local % P.dens_bx, local / P.dens_bx);
+            } else {
+                const RefPhase rp = L.rph[phase - 2];
+                RefineArgs ra = P.ra;
+                ra.dUf = rp.f < 0 ? nullptr : P.dU[rp.f];
+                ra.dUin = rp.in < 0 ? nullptr : P.dU[rp.in];
+                ra.dUout = P.dU[rp.out];
+                ra.Uout = rp.last ? P.ra.Uout : nullptr;
+                ra.nhalf = __builtin_amdgcn_readfirstlane(rp.nhalf);
+                refine_tile<32, 16>(ra, local, sm);
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        lane0_signal(done + seg);
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ kernel table
 
 const void* dis_kernel_pyramid() { return (const void*)&k_pyramid; }
 const void* dis_kernel_densify() { return (const void*)&k_densify; }
-const void* dis_kernel_prep() { return (const void*)&k_prep; }
 const void* dis_kernel_upsample() { return (const void*)&k_upsample; }
+
+// instances whose per-lane pixel arrays fit the 256 architectural VGPRs
+#define DIS_FOR_SEARCH_INSTANCES(X) \
+    X(4, 4) X(4, 8) X(4, 16) X(6, 4) X(6, 8) X(6, 16) X(8, 4) X(8, 8) X(8, 16) \
+    X(10, 8) X(10, 16) X(12, 8) X(12, 16) X(14, 16) X(16, 16)
 
 #define DIS_SEARCH_CASE(PS_, LPP_) \
     if (ps == PS_ && lpp == LPP_) return (const void*)&k_search<PS_, LPP_>;
+#define DIS_LEVEL_CASE(PS_, LPP_) \
+    if (ps == PS_ && lpp == LPP_) return (const void*)&k_level<PS_, LPP_>;
 
 const void* dis_kernel_search(int ps, int lpp) {
-    // instances whose per-lane pixel arrays fit the 256 architectural VGPRs
-    DIS_SEARCH_CASE(4, 4) DIS_SEARCH_CASE(4, 8) DIS_SEARCH_CASE(4, 16)
-    DIS_SEARCH_CASE(6, 4) DIS_SEARCH_CASE(6, 8) DIS_SEARCH_CASE(6, 16)
-    DIS_SEARCH_CASE(8, 4) DIS_SEARCH_CASE(8, 8) DIS_SEARCH_CASE(8, 16)
-    DIS_SEARCH_CASE(10, 8) DIS_SEARCH_CASE(10, 16)
-    DIS_SEARCH_CASE(12, 8) DIS_SEARCH_CASE(12, 16)
-    DIS_SEARCH_CASE(14, 16)
-    DIS_SEARCH_CASE(16, 16)
+    DIS_FOR_SEARCH_INSTANCES(DIS_SEARCH_CASE)
+    return nullptr;
+}
+
+const void* dis_kernel_level(int ps, int lpp) {
+    DIS_FOR_SEARCH_INSTANCES(DIS_LEVEL_CASE)
     return nullptr;
 }
 

@@ -149,3 +149,33 @@ def test_size_errors():
         assert e.value.code == _lib.DIS_EINVAL
     finally:
         d.close()
+
+
+@pytest.mark.parametrize("case", ["c2b", "c1", "inner7"])
+def test_launch_choices_are_bitwise_invariant(case):
+    """Persistent vs per-phase launches, lanes per patch and refinement tiles
+    change the schedule, never a bit of the flow."""
+    say(f"[tunables] case {case}")
+    if case == "c2b":
+        pr, p = pair("layered", 1024, 436, 100.0, 2), params(103)
+    elif case == "c1":
+        pr, p = pair("bump", 256, 192, 8.0, 1), params(101)
+    else:   # 7 SOR sweeps: each fixed-point step spans two launches
+        pr, p = pair("bump", 288, 216, 10.0, 13), params(105, var_inner=7)
+    h, w = pr.I0.shape
+    d = DIS(p, w, h)
+    try:
+        t0 = torch.from_numpy(pr.I0).cuda()
+        t1 = torch.from_numpy(pr.I1).cuda()
+        outs = []
+        for lpp, tile, mode in [(None, 0, 0), ([4] * 16, 0, 0), ([8] * 16, 0, 0), (None, 0, 1),
+                                ([4] * 16, 1, 1), ([16] * 16, 2, 1)]:
+            d.set_tunables(lpp, tile, mode)
+            o = d.flow(t0, t1)
+            torch.cuda.synchronize()
+            assert d.debug_level(0, _lib.DIS_DBG_WAIT_ERRORS) == 0
+            outs.append(o.cpu().numpy())
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0])
+    finally:
+        d.close()
