@@ -170,9 +170,9 @@ static int alloc_slot(dis_handle* h, SlotBuf& sb) {
         LevelBuf& L = sb.lv[s];
         const int ws = W >> s, hs = H >> s;
         const size_t px = (size_t)ws * hs;
-        // level images: every level >= 1 (later pyramid passes start from a
-        // stored level); level 0 only when it is processed
-        if (s >= 1 || p.finest_scale == 0) {
+        // level images: the processed levels, and every fifth level (a later
+        // pyramid pass starts from it)
+        if (s >= p.finest_scale || (s > 0 && s % 5 == 0)) {
             DALLOC(h, L.J0, px * sizeof(double));
             DALLOC(h, L.J1, px * sizeof(double));
         }
@@ -287,7 +287,7 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     if (lanes_per_patch)
         for (int s = 0; s < DIS_MAXL; ++s) {
             const int l = lanes_per_patch[s];
-            if (l != 0 && !dis_kernel_search(h->p.patch_size, l))
+            if (l != 0 && !dis_kernel_phase_search(h->p.patch_size, l))
                 return fail(h, DIS_EINVAL, "no search kernel for patch %d with %d lanes", h->p.patch_size, l);
         }
     drop_plans(h);
@@ -321,12 +321,12 @@ void Seq::add(const void* fn, dim3 grid, dim3 block, const void* arg, size_t byt
 
 int dis_pick_lpp(const dis_handle* h, int s, int N) {
     const int ps = h->p.patch_size;
-    if (h->lpp[s] && dis_kernel_search(ps, h->lpp[s])) return h->lpp[s];
+    if (h->lpp[s] && dis_kernel_phase_search(ps, h->lpp[s])) return h->lpp[s];
     // many patches: fewest lanes per patch available (less cross-lane work per
     // pixel); few patches: 16 lanes (shorter dependent chain per patch)
     if (N >= 16384)
         for (int l = 4; l <= 16; l *= 2)
-            if (dis_kernel_search(ps, l)) return l;
+            if (dis_kernel_phase_search(ps, l)) return l;
     return 16;
 }
 
@@ -365,7 +365,7 @@ static double refine_flops(double px, int nhalf) {
 // ------------------------------------------------------- launch sequences
 
 // Pyramid pass(es) of one pair: levels a+1 .. a+5 from level a.
-static int add_pyramid(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, int ss, const void* I0,
+int dis_add_pyramid(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, int ss, const void* I0,
                        const void* I1, Seq& seq) {
     const dis_params& p = h->p;
     const int sf = p.finest_scale;
@@ -415,7 +415,7 @@ static int add_pyramid(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, in
     return DIS_OK;
 }
 
-static void add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, Seq& seq) {
+void dis_add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, Seq& seq) {
     const dis_params& p = h->p;
     const int sf = p.finest_scale;
     const bool f64io = (p.flags & DIS_FLAG_IO_F64) != 0;
@@ -462,25 +462,27 @@ static void refine_phases(const dis_params& p, int s, std::vector<RefPhase>& out
 }
 
 // Search, densification and refinement of every pair at every level.
-// Persistent mode: one k_level launch per level over all pairs; phase mode:
-// one launch per phase and pair.  Both give the same bits.
+// The per-level work is laid out as queue segments (phase-major, then pair)
+// in device tables; launch mode 0 runs each level as one persistent k_level
+// launch over that queue, mode 1 as one launch per phase covering every
+// pair.  Both give the same bits.
 int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs) {
     const dis_params& p = h->p;
     const int ps = p.patch_size, sf = p.finest_scale;
     const int cmap = (p.flags & DIS_FLAG_PIXEL_CENTRE) ? 1 : 0;
     int top = sf;
     for (const PairRef& r : pairs) top = std::max(top, r.ss);
+    const int mode = h->mode_phase;
+    const int tile_id = mode ? h->refine_tile : DIS_LEVEL_TILE;
     int tw = 32, th = 16;
-    const int tile_id = h->mode_phase ? h->refine_tile : DIS_LEVEL_TILE;
     dis_refine_tile(tile_id, &tw, &th);
 
     struct LevelHost {
         std::vector<LevelPair> lp;
         std::vector<RefPhase> rph;
-        std::vector<int> start;
         int lpp;
         int nph;
-        double by[3], fl[3];
+        double by[2], fl[2];
     };
     std::vector<LevelHost> levels;
     for (int s = top; s >= sf; --s) {
@@ -488,14 +490,14 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         refine_phases(p, s, LH.rph);
         if (!p.refine) LH.rph.clear();
         LH.nph = 2 + (int)LH.rph.size();
-        int maxN = 0;
+        long long totN = 0;
         for (const PairRef& r : pairs) {
             if (r.ss < s) continue;
             LevelGrid g;
-            maxN = std::max(maxN, grid_info(h, r.w >> s, r.h >> s, &g));
+            totN += grid_info(h, r.w >> s, r.h >> s, &g);
         }
-        LH.lpp = dis_pick_lpp(h, s, maxN * (int)pairs.size());
-        for (int q = 0; q < 3; ++q) LH.by[q] = LH.fl[q] = 0.0;
+        LH.lpp = dis_pick_lpp(h, s, (int)std::min<long long>(totN, 1 << 30));
+        LH.by[0] = LH.by[1] = LH.fl[0] = LH.fl[1] = 0.0;
         for (const PairRef& r : pairs) {
             if (r.ss < s) continue;
             SlotBuf& sb = *r.sb;
@@ -541,45 +543,14 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         levels.push_back(std::move(LH));
     }
 
-    if (h->mode_phase) {
-        // one launch per phase and pair
-        for (size_t li = 0; li < levels.size(); ++li) {
-            LevelHost& LH = levels[li];
-            const void* fn = dis_kernel_search(ps, LH.lpp);
-            if (!fn) return fail(h, DIS_EINVAL, "no search kernel for patch %d, %d lanes", ps, LH.lpp);
-            for (LevelPair& P : LH.lp) {
-                const int N = P.sa.nx * P.sa.ny, per = 256 / LH.lpp;
-                const double px = (double)P.sa.W * P.sa.H;
-                seq.add(fn, dim3((N + per - 1) / per), dim3(256), &P.sa, sizeof P.sa, 0, "search",
-                        search_bytes(px, P.sa.Un ? (double)P.sa.Wn * P.sa.Hn : 0.0, N),
-                        search_flops(N, (double)ps * ps, p.gn_iters));
-                seq.add(dis_kernel_densify(), dim3(P.dens_bx, (P.da.H + 3) / 4), dim3(256), &P.da, sizeof P.da, 0,
-                        "densify", densify_bytes(px, N, p.refine),
-                        densify_flops(px, std::pow((double)ps / P.da.st, 2.0), p.refine));
-                const int tiles = P.ra.tiles_x * ((P.ra.H + th - 1) / th);
-                for (const RefPhase& rp : LH.rph) {
-                    RefineArgs ra = P.ra;
-                    ra.dUf = rp.f < 0 ? nullptr : P.dU[rp.f];
-                    ra.dUin = rp.in < 0 ? nullptr : P.dU[rp.in];
-                    ra.dUout = P.dU[rp.out];
-                    ra.Uout = rp.last ? P.ra.Uout : nullptr;
-                    ra.nhalf = rp.nhalf;
-                    seq.add(dis_kernel_refine(tile_id), dim3(tiles), dim3(256), &ra, sizeof ra, 0, "refine",
-                            refine_bytes(px, rp.f >= 0, rp.in >= 0, rp.last), refine_flops(px, rp.nhalf));
-                }
-            }
-        }
-        return DIS_OK;
-    }
-
-    // persistent mode: device tables for every level, one allocation
+    // device tables for every level, one allocation
     size_t bytes = 0;
     int nsync = 0;
     std::vector<size_t> off_lp, off_rph, off_start;
     std::vector<int> off_sync;
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     for (LevelHost& LH : levels) {
         const int np = (int)LH.lp.size(), nseg = LH.nph * np;
-        auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
         off_lp.push_back(bytes);
         bytes = al(bytes + sizeof(LevelPair) * np);
         off_rph.push_back(bytes);
@@ -605,8 +576,10 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         // queue segments, phase-major: search blocks, densification blocks,
         // then the refinement phases, each over all pairs
         std::vector<int> start(nseg + 1, 0);
+        std::vector<double> ph_by(LH.nph, 0.0), ph_fl(LH.nph, 0.0);
+        ph_by[0] = LH.by[0]; ph_fl[0] = LH.fl[0];
+        ph_by[1] = LH.by[1]; ph_fl[1] = LH.fl[1];
         int t = 0;
-        double rby = 0.0, rfl = 0.0;
         for (int ph = 0; ph < LH.nph; ++ph) {
             for (int j = 0; j < np; ++j) {
                 const LevelPair& P = LH.lp[j];
@@ -618,8 +591,8 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
                     cnt = P.ra.tiles_x * ((P.ra.H + th - 1) / th);
                     const RefPhase& rp = LH.rph[ph - 2];
                     const double px = (double)P.ra.W * P.ra.H;
-                    rby += refine_bytes(px, rp.f >= 0, rp.in >= 0, rp.last);
-                    rfl += refine_flops(px, rp.nhalf);
+                    ph_by[ph] += refine_bytes(px, rp.f >= 0, rp.in >= 0, rp.last);
+                    ph_fl[ph] += refine_flops(px, rp.nhalf);
                 }
                 t += cnt;
             }
@@ -635,11 +608,33 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         LL.npairs = np;
         LL.nph = LH.nph;
         LL.ntasks = t;
-        const void* fn = dis_kernel_level(ps, LH.lpp);
-        if (!fn) return fail(h, DIS_EINVAL, "no level kernel for patch %d, %d lanes", ps, LH.lpp);
-        const int grid = std::max(1, std::min(t, h->n_cu * 2));
-        seq.add(fn, dim3(grid), dim3(256), &LL, sizeof LL, 0, "level", LH.by[0] + LH.by[1] + rby,
-                LH.fl[0] + LH.fl[1] + rfl);
+        if (mode == 0) {
+            const void* fn = dis_kernel_level(ps, LH.lpp);
+            if (!fn) return fail(h, DIS_EINVAL, "no level kernel for patch %d, %d lanes", ps, LH.lpp);
+            double by = 0.0, fl = 0.0;
+            for (int ph = 0; ph < LH.nph; ++ph) { by += ph_by[ph]; fl += ph_fl[ph]; }
+            const int grid = std::max(1, std::min(t, h->n_cu * 2));
+            seq.add(fn, dim3(grid), dim3(256), &LL, sizeof LL, 0, "level", by, fl);
+        } else {
+            const void* fs = dis_kernel_phase_search(ps, LH.lpp);
+            if (!fs) return fail(h, DIS_EINVAL, "no search kernel for patch %d, %d lanes", ps, LH.lpp);
+            for (int ph = 0; ph < LH.nph; ++ph) {
+                const int n = start[(ph + 1) * np] - start[ph * np];
+                if (ph == 0) {
+                    seq.add(fs, dim3(n), dim3(256), &LL, sizeof LL, 0, "search", ph_by[0], ph_fl[0]);
+                } else if (ph == 1) {
+                    seq.add(dis_kernel_phase_densify(), dim3(n), dim3(256), &LL, sizeof LL, 0, "densify", ph_by[1],
+                            ph_fl[1]);
+                } else {
+                    PhaseLaunch PL;
+                    std::memset(&PL, 0, sizeof PL);
+                    PL.L = LL;
+                    PL.phase = ph;
+                    seq.add(dis_kernel_phase_refine(tile_id), dim3(n), dim3(256), &PL, sizeof PL, 0, "refine",
+                            ph_by[ph], ph_fl[ph]);
+                }
+            }
+        }
     }
     HIPCHK(h, hipMemcpy(tabs.mem, host.data(), bytes, hipMemcpyHostToDevice));
     return DIS_OK;
@@ -656,12 +651,12 @@ int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const 
         return fail(h, DIS_ESIZE, "%dx%d: scale %d is smaller than the %d px patch", w, hgt, sf, ps);
     if (info) { info->ss = ss; info->sf = sf; }
     const size_t first = seq.items.size();
-    int r = add_pyramid(h, sb, w, hgt, pitch, ss, I0, I1, seq);
+    int r = dis_add_pyramid(h, sb, w, hgt, pitch, ss, I0, I1, seq);
     if (r != DIS_OK) return r;
     std::vector<PairRef> pr{PairRef{&sb, w, hgt, ss}};
     r = dis_build_levels(h, pr, seq, tabs);
     if (r != DIS_OK) return r;
-    add_upsample(h, sb, w, hgt, flow, seq);
+    dis_add_upsample(h, sb, w, hgt, flow, seq);
     // the first pyramid launch clears the level launches' queue state
     PyrArgs* pa = (PyrArgs*)seq.items[first].arg.data();
     pa->zero = tabs.sync;
@@ -843,6 +838,8 @@ extern "C" int dis_compute_flow(dis_handle* h, const void* I0, const void* I1, i
         h->last_I1 = I1;
         h->last_pitch = pitch;
         h->last_tabs = &pl->tabs;
+        h->last_call = 1;
+        h->last_flow = flow;
     }
     return r;
 }

@@ -108,7 +108,7 @@ struct dis_handle {
     std::map<std::vector<int>, BatchPlan*> bplans;
     int lpp[DIS_MAXL];
     int refine_tile = 0;
-    int mode_phase = 0;     // 1: one launch per phase instead of persistent level launches
+    int mode_phase = 1;     // 1: one launch per phase, 0: one persistent launch per level
     int n_cu = 256;
     // most recent plain forward call (debug and backward)
     bool have_last = false;
@@ -116,6 +116,13 @@ struct dis_handle {
     const void* last_I0 = nullptr;
     const void* last_I1 = nullptr;
     const PlanTables* last_tabs = nullptr;
+    // the most recent forward call, replayed by the autotuner
+    int last_call = 0;          // 0 none, 1 plain, 2 batched
+    void* last_flow = nullptr;
+    std::vector<const void*> last_batch, last_batch_I1;
+    std::vector<void*> last_batch_flow;
+    std::vector<int> last_batch_w, last_batch_h, last_batch_pitch;
+    double tuned_ms = 0.0;
     // per-kernel event timing (dis_profile_enable)
     bool profiling = false;
     std::vector<ProfPending> prof_pending;
@@ -130,5 +137,8 @@ int dis_pick_lpp(const dis_handle* h, int s, int N);
 int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const void* I0, const void* I1,
                    void* flow, Seq& seq, PairInfo* info, PlanTables& tabs);
 int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs);
+int dis_add_pyramid(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, int ss, const void* I0, const void* I1,
+                    Seq& seq);
+void dis_add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, Seq& seq);
 int dis_fail(dis_handle* h, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 int dis_launch_eager(dis_handle* h, Seq& seq);

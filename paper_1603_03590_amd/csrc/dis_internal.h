@@ -112,12 +112,36 @@ struct LevelLaunch {
     int npairs, nph, ntasks;
 };
 
+// A phase-major refinement launch: phase `phase` of every pair of L.
+struct PhaseLaunch {
+    LevelLaunch L;
+    int phase;
+};
+
+// Table-driven multi-pair launches of the pyramid and the upscaling: entry
+// j covers blocks start[j] .. start[j+1]-1.
+struct PyrTab {
+    const PyrArgs* tab;
+    const int* start;
+    int n;
+    int* zero;              // block 0 clears these ints (queue state of the level launches)
+    int nzero;
+};
+
+struct UpsTab {
+    const UpsArgs* tab;
+    const int* start;
+    int n;
+};
+
 // Kernel entry points, looked up by the host.
 const void* dis_kernel_pyramid();
-const void* dis_kernel_search(int ps, int lpp);   // null when not compiled
-const void* dis_kernel_densify();
-const void* dis_kernel_refine(int tile);          // tile id, see dis_refine_tile
+const void* dis_kernel_pyramid_tab();
 const void* dis_kernel_upsample();
-const void* dis_kernel_level(int ps, int lpp);    // persistent level kernel, null when not compiled
+const void* dis_kernel_upsample_tab();
+const void* dis_kernel_phase_search(int ps, int lpp);   // null when not compiled
+const void* dis_kernel_phase_densify();
+const void* dis_kernel_phase_refine(int tile);          // tile id, see dis_refine_tile
+const void* dis_kernel_level(int ps, int lpp);          // persistent level kernel, null when not compiled
 // refinement core tile (width, height) of a tile id; returns 0 for an unknown id
 int dis_refine_tile(int tile, int* tw, int* th);

@@ -48,13 +48,11 @@ __device__ __forceinline__ double dpp_mov(double v) {
 
 // ------------------------------------------------------------------ pyramid
 
-__global__ __launch_bounds__(256) void k_pyramid(const PyrArgs a) {
+// One 32x32 tile of level a of frame f: the tile's part of levels a+1..a+nlev.
+__device__ __forceinline__ void pyramid_tile(const PyrArgs& a, int tile, int f) {
     __shared__ double t0[32][33];
     __shared__ double t1[16][17];
-    const int f = blockIdx.y;
-    if (blockIdx.x == 0 && f == 0)
-        for (int i = threadIdx.x; i < a.nzero; i += 256) a.zero[i] = 0;
-    const int bx = blockIdx.x % a.tiles_x, by = blockIdx.x / a.tiles_x;
+    const int bx = tile % a.tiles_x, by = tile / a.tiles_x;
     const int X0 = bx * 32, Y0 = by * 32;
     for (int i = threadIdx.x; i < 1024; i += 256) {
         const int ly = i >> 5, lx = i & 31;
@@ -97,6 +95,32 @@ __global__ __launch_bounds__(256) void k_pyramid(const PyrArgs a) {
         }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(256) void k_pyramid(const PyrArgs a) {
+    if (blockIdx.x == 0 && blockIdx.y == 0)
+        for (int i = threadIdx.x; i < a.nzero; i += 256) a.zero[i] = 0;
+    pyramid_tile(a, blockIdx.x, blockIdx.y);
+}
+
+// Index of the segment of a sorted start[] table that holds task t
+// (start[lo] <= t < start[lo+1]), made wave-uniform.
+__device__ __forceinline__ int seg_find(const int* start, int lo, int hi, int t) {
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (__builtin_amdgcn_readfirstlane(start[mid]) <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Pyramid passes of many pairs in one launch (tiles of pair j are
+// start[j] .. start[j+1]-1).
+__global__ __launch_bounds__(256) void k_pyramid_tab(const PyrTab T) {
+    if (blockIdx.x == 0 && blockIdx.y == 0)
+        for (int i = threadIdx.x; i < T.nzero; i += 256) T.zero[i] = 0;
+    const int t = blockIdx.x;
+    const int j = seg_find(T.start, 0, T.n, t);
+    pyramid_tile(T.tab[j], t - __builtin_amdgcn_readfirstlane(T.start[j]), blockIdx.y);
 }
 
 // ------------------------------------------------------------------ search
@@ -261,11 +285,6 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
     }
 }
 
-template <int PS, int LPP>
-__global__ __launch_bounds__(256) void k_search(const SearchArgs a) {
-    search_block<PS, LPP>(a, blockIdx.x);
-}
-
 // ------------------------------------------------------------ densification
 
 __device__ __forceinline__ void cover_range(int x, int n, int ps, int st, int nr, int ntot,
@@ -312,10 +331,6 @@ __device__ __forceinline__ void densify_block(const DensifyArgs& a, int bx, int 
     a.U[g] = U;
     a.U[W * H + g] = V;
     if (a.J1w) a.J1w[g] = bilin(a.J1, W, H, (double)x + U, (double)y + V);
-}
-
-__global__ __launch_bounds__(256) void k_densify(const DensifyArgs a) {
-    densify_block(a, blockIdx.x, blockIdx.y);
 }
 
 // --------------------------------------------------------------- refinement
@@ -566,17 +581,49 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
     __syncthreads();   // LDS is reused by the caller's next tile
 }
 
+// Phase-major launches over the same per-level tables as the persistent
+// kernel: one launch per phase covers every pair (its segments are
+// consecutive in the queue order), no waiting inside the launch.
+template <int PS, int LPP>
+__global__ __launch_bounds__(256) void k_phase_search(const LevelLaunch L) {
+    const int t = blockIdx.x;                       // phase 0 starts at task 0
+    const int j = seg_find(L.start, 0, L.npairs, t);
+    search_block<PS, LPP>(L.pairs[j].sa, t - __builtin_amdgcn_readfirstlane(L.start[j]));
+}
+
+__global__ __launch_bounds__(256) void k_phase_densify(const LevelLaunch L) {
+    const int np = L.npairs;
+    const int t = __builtin_amdgcn_readfirstlane(L.start[np]) + blockIdx.x;
+    const int j = seg_find(L.start, np, 2 * np, t) - np;
+    const LevelPair& P = L.pairs[j];
+    const int local = t - __builtin_amdgcn_readfirstlane(L.start[np + j]);
+    densify_block(P.da, local % P.dens_bx, local / P.dens_bx);
+}
+
 template <int TW, int TH>
-__global__ __launch_bounds__(256) void k_refine(const RefineArgs a) {
+__global__ __launch_bounds__(256) void k_phase_refine(const PhaseLaunch PL) {
     __shared__ RefineSmem<TW, TH> sm;
-    refine_tile<TW, TH>(a, blockIdx.x, sm);
+    const LevelLaunch& L = PL.L;
+    const int phase = PL.phase;
+    const int np = L.npairs, s0 = phase * np;
+    const int t = __builtin_amdgcn_readfirstlane(L.start[s0]) + blockIdx.x;
+    const int j = seg_find(L.start, s0, s0 + np, t) - s0;
+    const LevelPair& P = L.pairs[j];
+    const RefPhase rp = L.rph[phase - 2];
+    RefineArgs ra = P.ra;
+    ra.dUf = rp.f < 0 ? nullptr : P.dU[rp.f];
+    ra.dUin = rp.in < 0 ? nullptr : P.dU[rp.in];
+    ra.dUout = P.dU[rp.out];
+    ra.Uout = rp.last ? P.ra.Uout : nullptr;
+    ra.nhalf = rp.nhalf;
+    refine_tile<TW, TH>(ra, t - __builtin_amdgcn_readfirstlane(L.start[s0 + j]), sm);
 }
 
 // ----------------------------------------------------------------- upscale
 
-__global__ __launch_bounds__(256) void k_upsample(const UpsArgs a) {
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void upsample_block(const UpsArgs& a, int bx, int by) {
+    const int x = bx * 64 + (threadIdx.x & 63);
+    const int y = by * 4 + (threadIdx.x >> 6);
     if (x >= a.W || y >= a.H) return;
     double qx, qy;
     if (a.centre_map) { qx = ((double)x + 0.5) / a.f - 0.5; qy = ((double)y + 0.5) / a.f - 0.5; }
@@ -591,6 +638,20 @@ __global__ __launch_bounds__(256) void k_upsample(const UpsArgs a) {
         ((float*)a.out)[g] = (float)u;
         ((float*)a.out)[n + g] = (float)v;
     }
+}
+
+__global__ __launch_bounds__(256) void k_upsample(const UpsArgs a) {
+    upsample_block(a, blockIdx.x, blockIdx.y);
+}
+
+// Upscaling of many pairs in one launch (blocks of pair j are start[j] ..).
+__global__ __launch_bounds__(256) void k_upsample_tab(const UpsTab T) {
+    const int t = blockIdx.x;
+    const int j = seg_find(T.start, 0, T.n, t);
+    const UpsArgs& a = T.tab[j];
+    const int local = t - __builtin_amdgcn_readfirstlane(T.start[j]);
+    const int bxn = (a.W + 63) / 64;
+    upsample_block(a, local % bxn, local / bxn);
 }
 
 // ------------------------------------------------- persistent level kernel
@@ -647,12 +708,7 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
         const int t = __builtin_amdgcn_readfirstlane(s_task);
         __syncthreads();   // s_task is rewritten on the next round
         if (t >= L.ntasks) break;
-        int lo = 0, hi = nseg;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (__builtin_amdgcn_readfirstlane(L.start[mid]) <= t) lo = mid; else hi = mid;
-        }
-        const int seg = lo;
+        const int seg = seg_find(L.start, 0, nseg, t);
         const int phase = seg / L.npairs, pair = seg - phase * L.npairs;
         const int local = t - __builtin_amdgcn_readfirstlane(L.start[seg]);
         const int prev = phase > 0 ? seg - L.npairs : seg;
@@ -689,8 +745,10 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
 // ------------------------------------------------------------ kernel table
 
 const void* dis_kernel_pyramid() { return (const void*)&k_pyramid; }
-const void* dis_kernel_densify() { return (const void*)&k_densify; }
+const void* dis_kernel_pyramid_tab() { return (const void*)&k_pyramid_tab; }
 const void* dis_kernel_upsample() { return (const void*)&k_upsample; }
+const void* dis_kernel_upsample_tab() { return (const void*)&k_upsample_tab; }
+const void* dis_kernel_phase_densify() { return (const void*)&k_phase_densify; }
 
 // instances whose per-lane pixel arrays fit the 256 architectural VGPRs
 #define DIS_FOR_SEARCH_INSTANCES(X) \
@@ -698,11 +756,11 @@ const void* dis_kernel_upsample() { return (const void*)&k_upsample; }
     X(10, 8) X(10, 16) X(12, 8) X(12, 16) X(14, 16) X(16, 16)
 
 #define DIS_SEARCH_CASE(PS_, LPP_) \
-    if (ps == PS_ && lpp == LPP_) return (const void*)&k_search<PS_, LPP_>;
+    if (ps == PS_ && lpp == LPP_) return (const void*)&k_phase_search<PS_, LPP_>;
 #define DIS_LEVEL_CASE(PS_, LPP_) \
     if (ps == PS_ && lpp == LPP_) return (const void*)&k_level<PS_, LPP_>;
 
-const void* dis_kernel_search(int ps, int lpp) {
+const void* dis_kernel_phase_search(int ps, int lpp) {
     DIS_FOR_SEARCH_INSTANCES(DIS_SEARCH_CASE)
     return nullptr;
 }
@@ -721,11 +779,11 @@ int dis_refine_tile(int tile, int* tw, int* th) {
     }
 }
 
-const void* dis_kernel_refine(int tile) {
+const void* dis_kernel_phase_refine(int tile) {
     switch (tile) {
-        case 0: return (const void*)&k_refine<32, 16>;
-        case 1: return (const void*)&k_refine<16, 16>;
-        case 2: return (const void*)&k_refine<64, 8>;
+        case 0: return (const void*)&k_phase_refine<32, 16>;
+        case 1: return (const void*)&k_phase_refine<16, 16>;
+        case 2: return (const void*)&k_phase_refine<64, 8>;
         default: return nullptr;
     }
 }

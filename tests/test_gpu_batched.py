@@ -1,0 +1,117 @@
+"""Batched flow (many pairs of uneven size per launch) through the C ABI:
+bitwise equal to the plain single-pair path, and at parity with the oracle."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from dis_cases import PARITY_EPE_REL, PARITY_FRAC, oracle_flow, oracle_params, pair, parity
+from paper_1603_03590_amd import DIS, DisError, params, _lib
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(320, 240), (640, 480), (1024, 436), (333, 251), (320, 240), (512, 256)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def batch_pairs():
+    return [pair("layered", w, h, 40.0, 1000 + k) for k, (w, h) in enumerate(SIZES)]
+
+
+def plain(prs, p):
+    outs = []
+    for pr in prs:
+        h, w = pr.I0.shape
+        d = DIS(p, w, h)
+        o = d.flow(torch.from_numpy(pr.I0).cuda(), torch.from_numpy(pr.I1).cuda())
+        torch.cuda.synchronize()
+        outs.append(o.cpu().numpy())
+        d.close()
+    return outs
+
+
+@pytest.mark.parametrize("mode", [1, 0])
+def test_batched_equals_plain_bitwise(mode):
+    say(f"[batched] {len(SIZES)} uneven pairs, launch mode {mode}")
+    prs = batch_pairs()
+    p = params(106)
+    ref = plain(prs, p)
+    d = DIS(p, 1024, 480, max_batch=len(prs))
+    try:
+        d.set_tunables(None, 0, mode)
+        I0 = [torch.from_numpy(pr.I0).cuda() for pr in prs]
+        I1 = [torch.from_numpy(pr.I1).cuda() for pr in prs]
+        outs = d.flow_batched(I0, I1)
+        torch.cuda.synchronize()
+        assert d.debug_level(3, _lib.DIS_DBG_WAIT_ERRORS) == 0
+        for k, o in enumerate(outs):
+            assert np.array_equal(o.cpu().numpy(), ref[k]), f"pair {k}"
+        # same composition again, new output buffers: tables re-pointed, same bits
+        outs2 = d.flow_batched(I0, I1)
+        torch.cuda.synchronize()
+        for k, o in enumerate(outs2):
+            assert np.array_equal(o.cpu().numpy(), ref[k]), f"pair {k} (second call)"
+    finally:
+        d.close()
+
+
+def test_batched_parity_with_oracle():
+    say("[batched] parity of 3 pairs against the oracle")
+    prs = batch_pairs()[:3]
+    p = params(106)
+    d = DIS(p, 1024, 480, max_batch=3)
+    try:
+        outs = d.flow_batched([torch.from_numpy(pr.I0).cuda() for pr in prs],
+                              [torch.from_numpy(pr.I1).cuda() for pr in prs])
+        torch.cuda.synchronize()
+        for k, (pr, o) in enumerate(zip(prs, outs)):
+            U_ref, _ = oracle_flow(f"batch{k}", pr.I0, pr.I1, oracle_params(p))
+            frac, erel, dmax = parity(o.cpu().numpy().astype(np.float64), U_ref, pr.flow)
+            say(f"[batched] pair {k}: within 1e-2 px {frac:.6f}, EPE rel {erel:.2e}, max {dmax:.2e}")
+            assert frac >= PARITY_FRAC and erel <= PARITY_EPE_REL
+    finally:
+        d.close()
+
+
+def test_autotune_keeps_results_and_writes_cache(tmp_path):
+    say("[autotune] batched 3 pairs")
+    prs = batch_pairs()[:3]
+    p = params(106)
+    d = DIS(p, 1024, 480, max_batch=3)
+    try:
+        I0 = [torch.from_numpy(pr.I0).cuda() for pr in prs]
+        I1 = [torch.from_numpy(pr.I1).cuda() for pr in prs]
+        before = [o.cpu().numpy() for o in d.flow_batched(I0, I1)]
+        cache = str(tmp_path / "tune.jsonl")
+        d.autotune(cache)
+        after = d.flow_batched(I0, I1)
+        torch.cuda.synchronize()
+        for a, b in zip(before, after):
+            assert np.array_equal(a, b.cpu().numpy())
+        rec = json.loads(open(cache).read().strip().splitlines()[-1])
+        assert rec["call"] == "batched" and rec["pairs"] == 3 and rec["ms"] > 0
+    finally:
+        d.close()
+
+
+def test_batched_errors():
+    say("[batched] argument errors")
+    d = DIS(params(106), 320, 240, max_batch=2)
+    try:
+        x = torch.zeros(240, 320, device="cuda")
+        with pytest.raises(DisError) as e:
+            d.flow_batched([x, x, x], [x, x, x])
+        assert e.value.code == _lib.DIS_ESIZE
+        y = torch.zeros(250, 320, device="cuda")
+        with pytest.raises(DisError) as e:
+            d.flow_batched([x, y], [x, y])
+        assert e.value.code == _lib.DIS_ESIZE
+    finally:
+        d.close()
