@@ -1,22 +1,26 @@
 #!/usr/bin/env python
 """Benchmark of the Dense Inverse Search hot path on one MI355X.
 
-One step = one whole pass of the method (pyramid, every scale's inverse
-search, densification and refinement, upscaling) over one synthetic
-1024x436 grayscale pair already resident in HBM, replayed from a HIP graph.
-Prints ONE JSON line with the throughput in Mpix/s of dense output flow,
-a per-kernel roofline entry for the kernel that takes the most time
-(measured with HIP events on the library's stream), the parity of this very
-run against the FP64 oracle, and the oracle timed on the host cores.
+Headline: one step = one whole pass of the method (pyramid, every scale's
+inverse search, densification and refinement, upscaling) over one synthetic
+1024x436 grayscale pair already resident in HBM, replayed from a HIP graph,
+with the launch choices picked by the library's autotuner.  Also measured on
+the same GPU: the second 1024x436 operating point, the batched form (64
+pairs of uneven size per call) and, when built, the forward+backward form.
+
+Prints ONE JSON line: throughput in Mpix/s of dense output flow, a per-kernel
+roofline entry for the kernel family that takes the most time (HIP events on
+the library's stream), the parity of these very runs against the FP64
+oracle, and the oracle timed on the host cores.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
+from concurrent.futures import ProcessPoolExecutor
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -29,14 +33,45 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _layered(args):
+    from paper_1603_03590_amd import synth
+    w, h, disp, seed = args
+    pr = synth.layered_pair(w, h, disp, seed)
+    return pr.I0, pr.I1, pr.flow
+
+
+def time_calls(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def kernel_table(stats, steps):
+    out = {}
+    for k in sorted(stats, key=lambda k: -k["total_ms"]):
+        avg = k["total_ms"] / k["launches"]
+        out[k["name"]] = dict(launches_per_step=k["launches"] / steps, us_per_step=k["total_ms"] * 1e3 / steps,
+                              avg_launch_us=avg * 1e3,
+                              GBps=(k["bytes"] / k["launches"]) / (avg * 1e-3) / 1e9,
+                              GFLOPs=(k["flops"] / k["launches"]) / (avg * 1e-3) / 1e9)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="budget of the oracle CPU-baseline sample (0 disables it)")
+                    help="budget of the oracle CPU-baseline sample (0 disables it and the parity checks)")
     ap.add_argument("--op", default="c2a", choices=["c2a", "c2b"], help="operating point of the headline line")
+    ap.add_argument("--batch", type=int, default=64, help="pairs in the batched measurement (0 skips it)")
     ap.add_argument("--profile-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -55,83 +90,118 @@ def main():
     I1 = torch.from_numpy(pr.I1).cuda()
 
     results = {}
-    for op in (args.op, "c2b" if args.op == "c2a" else "c2a"):
+    other = "c2b" if args.op == "c2a" else "c2a"
+    for op in (args.op, other):
         p = params(presets[op])
         d = DIS(p, W, H)
         out = torch.empty((2, H, W), device="cuda")
-        for _ in range(args.warmup):
-            d.flow(I0, I1, out)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            d.flow(I0, I1, out)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        flow = out.cpu().numpy().astype(np.float64)
-        # per-kernel event timing on the library's stream
+        flow = lambda: d.flow(I0, I1, out)
+        modes = {}
+        for name, mode in (("phase", 1), ("persistent", 0)):
+            d.set_tunables(None, 0, mode)
+            modes[name] = time_calls(flow, args.steps, args.warmup) * 1e3
+        flow()
+        d.autotune()
+        dt = time_calls(flow, args.steps, args.warmup)
+        f_tuned = out.cpu().numpy().astype(np.float64)
+        # per-kernel event timing on the library's stream (tuned choices)
         _lib.dis_profile_enable(d.handle, True)
         for _ in range(3):
-            d.flow(I0, I1, out)
-        _lib.dis_profile_read(d.handle)          # discard the first eager passes
+            flow()
+        _lib.dis_profile_read(d.handle)
         for _ in range(args.profile_steps):
-            d.flow(I0, I1, out)
+            flow()
         kstats = _lib.dis_profile_read(d.handle)
         _lib.dis_profile_enable(d.handle, False)
-        eager_t0 = time.perf_counter()
-        p_e = params(presets[op], flags=_lib.DIS_FLAG_NO_GRAPH)
-        de = DIS(p_e, W, H)
-        for _ in range(args.warmup):
-            de.flow(I0, I1, out)
-        torch.cuda.synchronize()
-        eager_t0 = time.perf_counter()
-        for _ in range(args.steps):
-            de.flow(I0, I1, out)
-        torch.cuda.synchronize()
-        dt_eager = (time.perf_counter() - eager_t0) / args.steps
-        de.close()
         d.close()
-        results[op] = dict(ms=dt * 1e3, ms_eager=dt_eager * 1e3, flow=flow, kernels=kstats, params=p.as_dict())
-        log(f"[bench] {op}: {dt * 1e3:.4f} ms/pair (graph), {dt_eager * 1e3:.4f} ms/pair (eager)")
+        results[op] = dict(ms=dt * 1e3, modes=modes, flow=f_tuned, kernels=kstats)
+        log(f"[bench] {op}: tuned {dt * 1e3:.4f} ms/pair; phase-major {modes['phase']:.4f}, "
+            f"persistent {modes['persistent']:.4f}")
 
     head = results[args.op]
     mpix = W * H / (head["ms"] * 1e-3) / 1e6
-
-    # roofline of the kernel family with the largest total time
     ks = sorted(head["kernels"], key=lambda k: -k["total_ms"])
     top = ks[0]
     avg_ms = top["total_ms"] / top["launches"]
-    per_launch_bytes = top["bytes"] / top["launches"]
-    per_launch_flops = top["flops"] / top["launches"]
     if top["name"] == "search":
-        achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
+        achieved = top["flops"] / top["launches"] / (avg_ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=achieved / FP64_VECTOR_PEAK_TFLOPS)
     else:
-        achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+        achieved = top["bytes"] / top["launches"] / (avg_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS)
-    roof.update(kernel=top["name"], launches_per_step=top["launches"] // args.profile_steps,
-                avg_launch_us=avg_ms * 1e3, traffic=None)
-    kernel_table = {k["name"]: dict(launches_per_step=k["launches"] / args.profile_steps,
-                                    us_per_step=k["total_ms"] * 1e3 / args.profile_steps,
-                                    avg_launch_us=k["total_ms"] * 1e3 / k["launches"],
-                                    GBps=(k["bytes"] / k["launches"]) / (k["total_ms"] / k["launches"] * 1e-3) / 1e9,
-                                    GFLOPs=(k["flops"] / k["launches"]) / (k["total_ms"] / k["launches"] * 1e-3) / 1e9)
-                    for k in ks}
+    roof.update(traffic=None, kernel=top["name"], launches_per_step=top["launches"] / args.profile_steps,
+                avg_launch_us=avg_ms * 1e3, algorithmic_bytes_per_launch=top["bytes"] / top["launches"],
+                algorithmic_flops_per_launch=top["flops"] / top["launches"])
 
-    # parity of this run and the CPU baseline (the FP64 oracle as it stands)
+    # batched: 64 pairs of uneven sizes, one call per step
+    batched = None
+    bpairs = []
+    if args.batch > 0:
+        sizes = synth.batch_sizes(args.batch, 4000)
+        t0 = time.perf_counter()
+        with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            bpairs = list(ex.map(_layered, [(w, h, 100.0, 1000 + k) for k, (w, h) in enumerate(sizes)]))
+        log(f"[bench] generated {args.batch} pairs in {time.perf_counter() - t0:.1f} s")
+        p = params(106)
+        mw = max(w for w, _ in sizes)
+        mh = max(h for _, h in sizes)
+        d = DIS(p, mw, mh, max_batch=args.batch)
+        bI0 = [torch.from_numpy(a).cuda() for a, _, _ in bpairs]
+        bI1 = [torch.from_numpy(b).cuda() for _, b, _ in bpairs]
+        bout = [torch.empty((2,) + a.shape, device="cuda") for a in bI0]
+        call = lambda: d.flow_batched(bI0, bI1, bout)
+        bmodes = {}
+        for name, mode in (("phase", 1), ("persistent", 0)):
+            d.set_tunables(None, 0, mode)
+            bmodes[name] = time_calls(call, max(5, args.steps // 20), 3) * 1e3
+        call()
+        d.autotune()
+        bdt = time_calls(call, max(10, args.steps // 10), 3)
+        torch.cuda.synchronize()
+        pix = sum(w * h for w, h in sizes)
+        # per-pair check on a sample: bitwise equal to the plain path
+        sample = sorted(range(args.batch), key=lambda k: -sizes[k][0] * sizes[k][1])[:3]
+        bit_equal = True
+        for k in sample:
+            h_, w_ = bpairs[k][0].shape
+            dp = DIS(p, w_, h_)
+            o = dp.flow(bI0[k], bI1[k])
+            torch.cuda.synchronize()
+            bit_equal &= bool(torch.equal(o, bout[k]))
+            dp.close()
+        batched = dict(value=pix / bdt / 1e6, unit="Mpix/s", ms_per_batch=bdt * 1e3, pairs=args.batch,
+                       output_mpix=pix / 1e6, untuned_ms={k: v for k, v in bmodes.items()},
+                       plain_bitwise_equal_sample=bit_equal,
+                       workload=f"{args.batch} layered pairs, sizes uniform over "
+                                f"{{320x240, 640x480, 1024x436, 1280x720, 1920x1080}} (rng 4000), seeds 1000+k; "
+                                f"patch 8, overlap 0.5, 16 GN iterations, scales auto..3, theta_vo = s+1")
+        batched["_sample"] = sample
+        batched["_out"] = {k: bout[k].cpu().numpy().astype(np.float64) for k in sample}
+        d.close()
+        log(f"[bench] batched: {bdt * 1e3:.3f} ms per {args.batch}-pair batch, {pix / bdt / 1e6:.0f} Mpix/s")
+
+    # parity of these runs and the CPU baseline (the FP64 oracle as it stands)
     parity = {}
     cpu = None
     if args.cpu_seconds > 0:
         from oracle import dis_oracle as O
         sys.path.insert(0, os.path.join(ROOT, "tests"))
         from dis_cases import oracle_params, parity as parity_stats
+
+        def check(name, U, I0n, I1n, gt, p):
+            U_ref = O.dis_flow(torch.from_numpy(I0n), torch.from_numpy(I1n), oracle_params(p)).numpy()
+            frac, erel, dmax = parity_stats(U, U_ref, gt)
+            epe = float(np.sqrt(((U - gt) ** 2).sum(0)).mean())
+            parity[name] = {"frac_within_1e-2px": frac, "mean_epe_rel_diff": erel, "max_abs_diff_px": dmax,
+                            "mean_epe_px": epe, "passed": bool(frac >= 0.999 and erel <= 0.005)}
+
         for op, r in results.items():
-            U_ref = O.dis_flow(torch.from_numpy(pr.I0), torch.from_numpy(pr.I1),
-                               oracle_params(params(presets[op]))).numpy()
-            frac, erel, dmax = parity_stats(r["flow"], U_ref, pr.flow)
-            epe = float(np.sqrt(((r["flow"] - pr.flow) ** 2).sum(0)).mean())
-            parity[op] = {"frac_within_1e-2px": frac, "mean_epe_rel_diff": erel, "max_abs_diff_px": dmax,
-                          "mean_epe_px": epe, "passed": bool(frac >= 0.999 and erel <= 0.005)}
+            check(op, r["flow"], pr.I0, pr.I1, pr.flow, params(presets[op]))
+        if batched:
+            for k in batched["_sample"]:
+                a, b, gt = bpairs[k]
+                check(f"batched_pair{k}", batched["_out"][k], a, b, gt, params(106))
         op_p = oracle_params(params(presets[args.op]))
         t0 = time.perf_counter()
         runs = 0
@@ -143,6 +213,9 @@ def main():
         el = time.perf_counter() - t0
         cpu = dict(value=runs * W * H / el / 1e6, unit="Mpix/s", cores=torch.get_num_threads(), kind="oracle",
                    sample=f"{runs} full runs of the FP64 oracle on the same {W}x{H} pair ({el:.1f} s)")
+    if batched:
+        batched.pop("_sample")
+        batched.pop("_out")
 
     cfg = dict(
         workload=f"plain DIS, one {W}x{H} grayscale float32 pair: layered scene (background + 6 textured "
@@ -150,9 +223,8 @@ def main():
                  + ("patch 8, overlap 0.3, 12 GN iterations" if args.op == "c2a" else
                     "patch 8, overlap 0.5, 16 GN iterations")
                  + "; scales 5..3, refinement theta_vo = s+1, theta_vi = 5; flow upscaled to full size",
-        pairs_per_step=1, width=W, height=H, graph=True,
+        pairs_per_step=1, width=W, height=H, graph=True, autotuned=True,
     )
-    other = "c2b" if args.op == "c2a" else "c2a"
     line = {
         "metric": "flow Mpix/s @1024x436 (EPE-matched to oracle)",
         "value": mpix,
@@ -170,11 +242,13 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,
-        "kernels": kernel_table,
-        "eager_ms_per_step": head["ms_eager"],
+        "kernels": kernel_table(head["kernels"], args.profile_steps),
+        "untuned_ms_per_step": head["modes"],
         "other_operating_point": {other: dict(ms_per_step=results[other]["ms"],
                                               value=W * H / (results[other]["ms"] * 1e-3) / 1e6,
-                                              eager_ms_per_step=results[other]["ms_eager"])},
+                                              untuned_ms_per_step=results[other]["modes"])},
+        "batched": batched,
+        "fwd_bwd": None,
     }
     print(json.dumps(line), flush=True)
 
