@@ -185,6 +185,9 @@ int dis_set_stream(dis_handle* h, void* hip_stream);
  * patch displacements after the reset test, DIS_DBG_UDENSE [2][H_s][W_s]
  * densified flow, DIS_DBG_UREFINED [2][H_s][W_s] flow after refinement,
  * DIS_DBG_INFO int32 {W_s, H_s, N, nx, ny, stride} (24 bytes),
+ * after dis_flow_backward: DIS_DBG_GRAD_J0/J1 [H_s][W_s] dL/d(level image),
+ * DIS_DBG_GRAD_U [2][H_s][W_s] dL/d(refined flow of scale s),
+ * DIS_DBG_GRAD_PATCH [N][4] dL/d(patch u, v, mean residual, unused),
  * DIS_DBG_WAIT_ERRORS int32: how many persistent launches of that call gave
  * up waiting on their task queue (0 unless something is broken).
  * Errors: DIS_EINVAL (bad what/s or NULL), DIS_ESIZE (bytes too small),
@@ -198,6 +201,10 @@ int dis_set_stream(dis_handle* h, void* hip_stream);
 #define DIS_DBG_UREFINED 5
 #define DIS_DBG_INFO 6
 #define DIS_DBG_WAIT_ERRORS 7
+#define DIS_DBG_GRAD_J0 8
+#define DIS_DBG_GRAD_J1 9
+#define DIS_DBG_GRAD_U 10
+#define DIS_DBG_GRAD_PATCH 11
 int dis_debug_level(dis_handle* h, int s, int what, void* dst, size_t bytes);
 
 /*

@@ -13,7 +13,7 @@ from . import _lib
 from ._lib import (DisError, DisLibraryMissing, dis_params, DIS_FLAG_KEEP_FOR_BACKWARD, DIS_FLAG_NO_GRAPH,
                    DIS_FLAG_PIXEL_CENTRE, DIS_FLAG_RAW_RESIDUAL, DIS_FLAG_IO_F64)
 
-__all__ = ["DIS", "params", "compute_flow", "DisError", "DisLibraryMissing", "dis_params",
+__all__ = ["DIS", "params", "compute_flow", "dis_flow", "DisError", "DisLibraryMissing", "dis_params",
            "DIS_FLAG_KEEP_FOR_BACKWARD", "DIS_FLAG_NO_GRAPH", "DIS_FLAG_PIXEL_CENTRE",
            "DIS_FLAG_RAW_RESIDUAL", "DIS_FLAG_IO_F64"]
 
@@ -82,6 +82,7 @@ class DIS:
         if out is None:
             out = torch.empty((2, h, w), dtype=self.dtype, device=I0.device)
         _lib.dis_compute_flow(self.handle, I0.data_ptr(), I1.data_ptr(), w, h, I0.stride(0), out.data_ptr())
+        self._generation = getattr(self, "_generation", 0) + 1
         return out
 
     def flow_batched(self, I0s, I1s, outs=None):
@@ -94,14 +95,24 @@ class DIS:
         _lib.dis_compute_flow_batched(self.handle, [a.data_ptr() for a in I0s], [b.data_ptr() for b in I1s],
                                       [a.shape[1] for a in I0s], [a.shape[0] for a in I0s],
                                       [a.stride(0) for a in I0s], [o.data_ptr() for o in outs])
+        self._generation = getattr(self, "_generation", 0) + 1
         return outs
 
-    def backward(self, grad_flow, shape):
-        """dL/dI0, dL/dI1 for the most recent forward (needs KEEP_FOR_BACKWARD)."""
+    def backward(self, grad_flow, shape=None):
+        """dL/dI0, dL/dI1 ([H, W], dense) for the most recent ``flow`` call on
+        this handle, from dL/dflow [2, H, W]; the handle needs
+        DIS_FLAG_KEEP_FOR_BACKWARD.  Runs on the handle's stream."""
         torch = _torch()
+        if grad_flow.dtype != self.dtype or grad_flow.device.type != "cuda" or grad_flow.dim() != 3:
+            raise ValueError(f"grad_flow must be a [2, H, W] {self.dtype} tensor on the GPU")
+        shape = tuple(shape) if shape is not None else tuple(grad_flow.shape[1:])
+        if tuple(grad_flow.shape) != (2,) + shape:
+            raise ValueError(f"grad_flow has shape {tuple(grad_flow.shape)}, expected {(2,) + shape}")
+        gf = grad_flow.contiguous()
         g0 = torch.empty(shape, dtype=self.dtype, device=grad_flow.device)
         g1 = torch.empty(shape, dtype=self.dtype, device=grad_flow.device)
-        _lib.dis_flow_backward(self.handle, grad_flow.contiguous().data_ptr(), g0.data_ptr(), g1.data_ptr())
+        _lib.dis_flow_backward(self.handle, gf.data_ptr(), g0.data_ptr(), g1.data_ptr())
+        self._keep = gf      # alive until the next call on this handle
         return g0, g1
 
     def set_tunables(self, lanes_per_patch=None, refine_tile=0, launch_mode=0):
@@ -123,10 +134,20 @@ class DIS:
             return info
         shape = {_lib.DIS_DBG_J0: (H, W), _lib.DIS_DBG_J1: (H, W), _lib.DIS_DBG_UINIT: (N, 2),
                  _lib.DIS_DBG_UPATCH: (N, 2), _lib.DIS_DBG_UDENSE: (2, H, W),
-                 _lib.DIS_DBG_UREFINED: (2, H, W)}[what]
+                 _lib.DIS_DBG_UREFINED: (2, H, W), _lib.DIS_DBG_GRAD_J0: (H, W), _lib.DIS_DBG_GRAD_J1: (H, W),
+                 _lib.DIS_DBG_GRAD_U: (2, H, W), _lib.DIS_DBG_GRAD_PATCH: (N, 4)}[what]
         out = np.zeros(shape, np.float64)
         _lib.dis_debug_level(self.handle, s, what, out.ctypes.data, out.nbytes)
         return out
+
+
+def dis_flow(I0, I1, dis: DIS):
+    """Flow of (I0, I1) through ``dis`` as a differentiable torch op: the
+    backward pass runs the hand-written adjoint (dis_flow_backward).  The
+    handle must keep forward state (DIS_FLAG_KEEP_FOR_BACKWARD), and the
+    backward of a result must run before the handle's next forward call."""
+    from .autograd import DISFlow
+    return DISFlow.apply(I0, I1, dis)
 
 
 def compute_flow(I0, I1, p: dis_params | None = None):

@@ -35,6 +35,10 @@ DIS_DBG_UDENSE = 4
 DIS_DBG_UREFINED = 5
 DIS_DBG_INFO = 6
 DIS_DBG_WAIT_ERRORS = 7
+DIS_DBG_GRAD_J0 = 8
+DIS_DBG_GRAD_J1 = 9
+DIS_DBG_GRAD_U = 10
+DIS_DBG_GRAD_PATCH = 11
 
 # every symbol include/dis.h declares
 EXPORTS = (

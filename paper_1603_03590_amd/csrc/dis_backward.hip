@@ -1,0 +1,753 @@
+// Adjoint (reverse-mode) kernels of Dense Inverse Search for gfx950.
+//
+// The forward pipeline (Alg. 1 with the readings of the forward kernels) is
+// differentiated step by step: upscaling, the refinement's fixed-point steps
+// (red-black SOR sweeps replayed in reverse from a tape of their states, then
+// the frozen robust weights and the linearisation), the warped second frame,
+// the densification of Eq. (3), the unrolled inverse-compositional
+// Gauss-Newton iterations with the reset test, the patch initialisation from
+// the coarser flow, and the box pyramid.  float64 throughout; contributions
+// that several threads add to one element use hardware float64 atomics, so
+// gradients can differ between runs in the last bits.
+#include <hip/hip_runtime.h>
+#include "dis_backward.h"
+
+namespace {
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ __forceinline__ void atom(double* p, double v) {
+    if (v != 0.0) unsafeAtomicAdd(p, v);
+}
+
+// Bilinear taps of (x, y) in a W x H image (pixel values at integer
+// coordinates, indices clamped), their weights, and the value's partial
+// derivatives with respect to x and y.
+struct Taps {
+    int i00, i01, i10, i11;
+    double w00, w01, w10, w11;
+    double val, dx, dy;
+};
+
+__device__ __forceinline__ Taps taps_of(const double* img, int W, int H, double x, double y) {
+    double xf = floor(x), yf = floor(y);
+    const double ax = x - xf, ay = y - yf;
+    xf = fmin(fmax(xf, -2.0), (double)W + 1.0);
+    yf = fmin(fmax(yf, -2.0), (double)H + 1.0);
+    const int xi = (int)xf, yi = (int)yf;
+    const int x0 = clampi(xi, 0, W - 1), x1 = clampi(xi + 1, 0, W - 1);
+    const int y0 = clampi(yi, 0, H - 1), y1 = clampi(yi + 1, 0, H - 1);
+    Taps t;
+    t.i00 = y0 * W + x0; t.i01 = y0 * W + x1; t.i10 = y1 * W + x0; t.i11 = y1 * W + x1;
+    t.w00 = (1.0 - ay) * (1.0 - ax); t.w01 = (1.0 - ay) * ax; t.w10 = ay * (1.0 - ax); t.w11 = ay * ax;
+    const double a = img ? img[t.i00] : 0.0, b = img ? img[t.i01] : 0.0;
+    const double c = img ? img[t.i10] : 0.0, d = img ? img[t.i11] : 0.0;
+    const double top = (1.0 - ax) * a + ax * b, bot = (1.0 - ax) * c + ax * d;
+    t.val = (1.0 - ay) * top + ay * bot;
+    t.dx = (1.0 - ay) * (b - a) + ay * (d - c);
+    t.dy = bot - top;
+    return t;
+}
+
+__device__ __forceinline__ void scatter_taps(double* g, const Taps& t, double v) {
+    atom(g + t.i00, v * t.w00);
+    atom(g + t.i01, v * t.w01);
+    atom(g + t.i10, v * t.w10);
+    atom(g + t.i11, v * t.w11);
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- utilities
+
+__global__ __launch_bounds__(256) void k_bzero(const BZeroArgs a) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < a.n) a.p[i] = 0.0;
+}
+
+// dst = src (and dst2 = src when given)
+__global__ __launch_bounds__(256) void k_bcopy(const BCopyArgs a) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    a.dst[i] = a.src[i];
+    if (a.dst2) a.dst2[i] = a.src[i];
+}
+
+// dst += src
+__global__ __launch_bounds__(256) void k_baxpy(const BCopyArgs a) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < a.n) a.dst[i] = a.dst[i] + a.src[i];
+}
+
+// --------------------------------------------------------------- upscaling
+
+// flow(x) = f * bilinear(U, x / f): every output pixel hands f * gF to the
+// four taps it read.
+__global__ __launch_bounds__(256) void k_bwd_upsample(const UpsBwdArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= a.W || y >= a.H) return;
+    double qx, qy;
+    if (a.centre_map) { qx = ((double)x + 0.5) / a.f - 0.5; qy = ((double)y + 0.5) / a.f - 0.5; }
+    else { qx = (double)x / a.f; qy = (double)y / a.f; }
+    const size_t g = (size_t)y * a.W + x, n = (size_t)a.W * a.H;
+    const double gu = a.g_f64 ? ((const double*)a.gF)[g] : (double)((const float*)a.gF)[g];
+    const double gv = a.g_f64 ? ((const double*)a.gF)[n + g] : (double)((const float*)a.gF)[n + g];
+    const Taps t = taps_of(nullptr, a.Ws, a.Hs, qx, qy);
+    const size_t ns = (size_t)a.Ws * a.Hs;
+    scatter_taps(a.gU, t, a.f * gu);
+    scatter_taps(a.gU + ns, t, a.f * gv);
+}
+
+// ------------------------------------------------------------- refinement
+
+namespace {
+
+// Linearisation and SOR coefficients of pixel (x, y) at the frozen increment
+// F (same formulas and order as the forward refinement tile).
+struct Lin {
+    double Ix, Iy, Iz, Ixx, Ixy, Iyy, Ixz, Iyz, b0, bx, by;
+    double fu, fv, ri, rx, ry, ei, eg, pi, pg;
+    double A11, A12, A22, B1, B2;
+};
+
+__device__ __forceinline__ Lin lin_at(const RefBwdArgs& a, int x, int y) {
+    const int W = a.W, H = a.H;
+    const double* A = a.J0;
+    const double* B = a.J1w;
+    auto Ib = [&](int xx, int yy) { return 0.5 * (A[yy * W + xx] + B[yy * W + xx]); };
+    auto Ixa = [&](int xx, int yy) { return (Ib(min(xx + 1, W - 1), yy) - Ib(max(xx - 1, 0), yy)) / 2.0; };
+    auto Iya = [&](int xx, int yy) { return (Ib(xx, min(yy + 1, H - 1)) - Ib(xx, max(yy - 1, 0))) / 2.0; };
+    const int xm = max(x - 1, 0), xp = min(x + 1, W - 1), ym = max(y - 1, 0), yp = min(y + 1, H - 1);
+    const size_t g = (size_t)y * W + x, n = (size_t)W * H;
+    Lin L;
+    L.Ix = Ixa(x, y);
+    L.Iy = Iya(x, y);
+    L.Iz = B[g] - A[g];
+    L.Ixx = (Ixa(xp, y) - Ixa(xm, y)) / 2.0;
+    L.Ixy = (Ixa(x, yp) - Ixa(x, ym)) / 2.0;
+    L.Iyy = (Iya(x, yp) - Iya(x, ym)) / 2.0;
+    L.Ixz = (B[y * W + xp] - B[y * W + xm]) / 2.0 - (A[y * W + xp] - A[y * W + xm]) / 2.0;
+    L.Iyz = (B[yp * W + x] - B[ym * W + x]) / 2.0 - (A[yp * W + x] - A[ym * W + x]) / 2.0;
+    L.b0 = 1.0 / ((L.Ix * L.Ix + L.Iy * L.Iy) + 0.01);
+    L.bx = 1.0 / ((L.Ixx * L.Ixx + L.Ixy * L.Ixy) + 0.01);
+    L.by = 1.0 / ((L.Ixy * L.Ixy + L.Iyy * L.Iyy) + 0.01);
+    L.fu = a.F ? a.F[g] : 0.0;
+    L.fv = a.F ? a.F[n + g] : 0.0;
+    const double eps2 = a.eps * a.eps;
+    L.ri = (L.Ix * L.fu + L.Iy * L.fv) + L.Iz;
+    L.ei = L.b0 * (L.ri * L.ri);
+    L.rx = (L.Ixx * L.fu + L.Ixy * L.fv) + L.Ixz;
+    L.ry = (L.Ixy * L.fu + L.Iyy * L.fv) + L.Iyz;
+    L.eg = L.bx * (L.rx * L.rx) + L.by * (L.ry * L.ry);
+    L.pi = a.delta / (2.0 * sqrt(L.ei + eps2));
+    L.pg = a.gamma / (2.0 * sqrt(L.eg + eps2));
+    const double pi = L.pi, pg = L.pg;
+    L.A11 = ((pi * L.b0) * L.Ix) * L.Ix + pg * (((L.bx * L.Ixx) * L.Ixx) + ((L.by * L.Ixy) * L.Ixy));
+    L.A12 = ((pi * L.b0) * L.Ix) * L.Iy + pg * (((L.bx * L.Ixx) * L.Ixy) + ((L.by * L.Ixy) * L.Iyy));
+    L.A22 = ((pi * L.b0) * L.Iy) * L.Iy + pg * (((L.bx * L.Ixy) * L.Ixy) + ((L.by * L.Iyy) * L.Iyy));
+    L.B1 = ((pi * L.b0) * L.Ix) * L.Iz + pg * (((L.bx * L.Ixx) * L.Ixz) + ((L.by * L.Ixy) * L.Iyz));
+    L.B2 = ((pi * L.b0) * L.Iy) * L.Iz + pg * (((L.bx * L.Ixy) * L.Ixz) + ((L.by * L.Iyy) * L.Iyz));
+    return L;
+}
+
+// Smoothness weight owned by (x, y) from the full flow U + F.
+__device__ __forceinline__ double ws_at(const RefBwdArgs& a, int x, int y, double* E = nullptr) {
+    const int W = a.W, H = a.H;
+    const size_t g = (size_t)y * W + x, n = (size_t)W * H;
+    auto uu = [&](size_t i) { return a.F ? a.U[i] + a.F[i] : a.U[i]; };
+    auto vv = [&](size_t i) { return a.F ? a.U[n + i] + a.F[n + i] : a.U[n + i]; };
+    const double u0 = uu(g), v0 = vv(g);
+    double dxu = 0.0, dyu = 0.0, dxv = 0.0, dyv = 0.0;
+    if (x < W - 1) { dxu = uu(g + 1) - u0; dxv = vv(g + 1) - v0; }
+    if (y < H - 1) { dyu = uu(g + W) - u0; dyv = vv(g + W) - v0; }
+    const double es = ((dxu * dxu + dyu * dyu) + dxv * dxv) + dyv * dyv;
+    if (E) *E = es;
+    return a.alpha / (2.0 * sqrt(es + a.eps * a.eps));
+}
+
+}  // namespace
+
+// Coefficients of one fixed-point step, per pixel: A12, omega/(A11+S),
+// omega/(A22+S), c1, c2 (the constant parts of the SOR updates) and the edge
+// weight ws the pixel owns (right and lower edge).
+__global__ __launch_bounds__(256) void k_bwd_coef(const RefBwdArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int W = a.W, H = a.H;
+    if (x >= W || y >= H) return;
+    const size_t g = (size_t)y * W + x, n = (size_t)W * H;
+    a.coef[5 * n + g] = ws_at(a, x, y);
+}
+
+__global__ __launch_bounds__(256) void k_bwd_coef2(const RefBwdArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int W = a.W, H = a.H;
+    if (x >= W || y >= H) return;
+    const size_t g = (size_t)y * W + x, n = (size_t)W * H;
+    const double* ws = a.coef + 5 * n;
+    const Lin L = lin_at(a, x, y);
+    const double wr = x < W - 1 ? ws[g] : 0.0, wl = x > 0 ? ws[g - 1] : 0.0;
+    const double wd = y < H - 1 ? ws[g] : 0.0, wu = y > 0 ? ws[g - W] : 0.0;
+    const double S = ((wr + wl) + wd) + wu;
+    const double* U = a.U;
+    const double Ur = x < W - 1 ? U[g + 1] : 0.0, Ul = x > 0 ? U[g - 1] : 0.0;
+    const double Ud = y < H - 1 ? U[g + W] : 0.0, Uu = y > 0 ? U[g - W] : 0.0;
+    const double Vr = x < W - 1 ? U[n + g + 1] : 0.0, Vl = x > 0 ? U[n + g - 1] : 0.0;
+    const double Vd = y < H - 1 ? U[n + g + W] : 0.0, Vu = y > 0 ? U[n + g - W] : 0.0;
+    const double NU = ((wr * Ur + wl * Ul) + wd * Ud) + wu * Uu;
+    const double NV = ((wr * Vr + wl * Vl) + wd * Vd) + wu * Vu;
+    a.coef[0 * n + g] = L.A12;
+    a.coef[1 * n + g] = a.omega / (L.A11 + S);
+    a.coef[2 * n + g] = a.omega / (L.A22 + S);
+    a.coef[3 * n + g] = (NU - S * U[g]) - L.B1;
+    a.coef[4 * n + g] = (NV - S * U[n + g]) - L.B2;
+}
+
+// Reverse of one red-black half sweep, part 1: the pixels of colour c
+// (updated by that half sweep).  gd holds the adjoint of the state after the
+// half sweep; on exit it holds the adjoint of the state before it for these
+// pixels, gn the adjoints of their neighbour sums, and acc the adjoints of
+// their coefficients (summed over the step's half sweeps).
+__global__ __launch_bounds__(256) void k_bwd_sweep_a(const SweepBwdArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int W = a.W, H = a.H;
+    if (x >= W || y >= H || ((x + y) & 1) != a.colour) return;
+    const size_t g = (size_t)y * W + x, n = (size_t)W * H;
+    const double* ws = a.coef + 5 * n;
+    const double* st = a.state;        // state before the half sweep, null = zero
+    auto du = [&](size_t i) { return st ? st[i] : 0.0; };
+    auto dv = [&](size_t i) { return st ? st[n + i] : 0.0; };
+    const bool hr = x < W - 1, hl = x > 0, hd = y < H - 1, hu = y > 0;
+    const double wr = hr ? ws[g] : 0.0, wl = hl ? ws[g - 1] : 0.0;
+    const double wd = hd ? ws[g] : 0.0, wu = hu ? ws[g - W] : 0.0;
+    const double A12 = a.coef[g], i1 = a.coef[n + g], i2 = a.coef[2 * n + g];
+    const double c1 = a.coef[3 * n + g], c2 = a.coef[4 * n + g];
+    const double om1 = 1.0 - a.omega;
+    const double dur = hr ? du(g + 1) : 0.0, dul = hl ? du(g - 1) : 0.0;
+    const double dud = hd ? du(g + W) : 0.0, duu = hu ? du(g - W) : 0.0;
+    const double dvr = hr ? dv(g + 1) : 0.0, dvl = hl ? dv(g - 1) : 0.0;
+    const double dvd = hd ? dv(g + W) : 0.0, dvu = hu ? dv(g - W) : 0.0;
+    const double dup = du(g), dvp = dv(g);
+    // forward replay of this pixel's update
+    const double nu = ((wr * dur + wl * dul) + wd * dud) + wu * duu;
+    const double r1 = (nu + c1) - A12 * dvp;
+    const double dun = om1 * dup + i1 * r1;
+    const double nv = ((wr * dvr + wl * dvl) + wd * dvd) + wu * dvu;
+    const double r2 = (nv + c2) - A12 * dun;
+    // adjoint
+    const double adv = a.gd[n + g];
+    const double gr2 = i2 * adv;
+    const double adu = a.gd[g] - A12 * gr2;
+    const double gr1 = i1 * adu;
+    double* acc = a.acc;
+    acc[0 * n + g] += r1 * adu;                    // omega/(A11+S)
+    acc[1 * n + g] += r2 * adv;                    // omega/(A22+S)
+    acc[2 * n + g] += gr1;                         // c1
+    acc[3 * n + g] += gr2;                         // c2
+    acc[4 * n + g] += -dun * gr2 - dvp * gr1;      // A12
+    acc[5 * n + g] += dur * gr1 + dvr * gr2;       // edge weights seen from this pixel: right
+    acc[6 * n + g] += dul * gr1 + dvl * gr2;       // left
+    acc[7 * n + g] += dud * gr1 + dvd * gr2;       // down
+    acc[8 * n + g] += duu * gr1 + dvu * gr2;       // up
+    a.gd[g] = om1 * adu;
+    a.gd[n + g] = om1 * adv - A12 * gr1;
+    a.gn[g] = gr1;
+    a.gn[n + g] = gr2;
+}
+
+// Part 2: the pixels of the other colour collect what their neighbours'
+// updates owe them.
+__global__ __launch_bounds__(256) void k_bwd_sweep_b(const SweepBwdArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int W = a.W, H = a.H;
+    if (x >= W || y >= H || ((x + y) & 1) == a.colour) return;
+    const size_t g = (size_t)y * W + x, n = (size_t)W * H;
+    const double* ws = a.coef + 5 * n;
+    const bool hr = x < W - 1, hl = x > 0, hd = y < H - 1, hu = y > 0;
+    const double wr = hr ? ws[g] : 0.0, wl = hl ? ws[g - 1] : 0.0;
+    const double wd = hd ? ws[g] : 0.0, wu = hu ? ws[g - W] : 0.0;
+    double su = 0.0, sv = 0.0;
+    if (hr) { su += wr * a.gn[g + 1]; sv += wr * a.gn[n + g + 1]; }
+    if (hl) { su += wl * a.gn[g - 1]; sv += wl * a.gn[n + g - 1]; }
+    if (hd) { su += wd * a.gn[g + W]; sv += wd * a.gn[n + g + W]; }
+    if (hu) { su += wu * a.gn[g - W]; sv += wu * a.gn[n + g - W]; }
+    a.gd[g] += su;
+    a.gd[n + g] += sv;
+}
+
+// The coefficient adjoints of one fixed-point step, part 1 (per pixel):
+// through omega/(A+S), c = N - S U - B, the neighbour sums N and S, the
+// robust data weights and the linearisation, down to U, F, J0 and J1w.
+// Edge-weight adjoints as seen from each endpoint go to `edge` for part 2.
+__global__ __launch_bounds__(256) void k_bwd_lin(const RefBwdArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int W = a.W, H = a.H;
+    if (x >= W || y >= H) return;
+    const size_t g = (size_t)y * W + x, n = (size_t)W * H;
+    const double* ws = a.coef + 5 * n;
+    const double* acc = a.acc;
+    const double om = a.omega;
+    const bool hr = x < W - 1, hl = x > 0, hd = y < H - 1, hu = y > 0;
+    const double wr = hr ? ws[g] : 0.0, wl = hl ? ws[g - 1] : 0.0;
+    const double wd = hd ? ws[g] : 0.0, wu = hu ? ws[g - W] : 0.0;
+    const double S = ((wr + wl) + wd) + wu;
+    const double i1 = a.coef[n + g], i2 = a.coef[2 * n + g];
+    const double gi1 = acc[g], gi2 = acc[n + g], gc1 = acc[2 * n + g], gc2 = acc[3 * n + g];
+    const double gA12 = acc[4 * n + g];
+    const double* U = a.U;
+    const double Up = U[g], Vp = U[n + g];
+    // i = omega / (A + S)
+    const double gA11 = -gi1 * i1 * i1 / om, gA22 = -gi2 * i2 * i2 / om;
+    const double gS = gA11 + gA22 - Up * gc1 - Vp * gc2;
+    const double gB1 = -gc1, gB2 = -gc2;
+    // c = N - S U - B: U at the pixel and its neighbours
+    atom(a.gU + g, -S * gc1);
+    atom(a.gU + n + g, -S * gc2);
+    double* E = a.edge;
+    if (hr) { atom(a.gU + g + 1, wr * gc1); atom(a.gU + n + g + 1, wr * gc2); }
+    if (hl) { atom(a.gU + g - 1, wl * gc1); atom(a.gU + n + g - 1, wl * gc2); }
+    if (hd) { atom(a.gU + g + W, wd * gc1); atom(a.gU + n + g + W, wd * gc2); }
+    if (hu) { atom(a.gU + g - W, wu * gc1); atom(a.gU + n + g - W, wu * gc2); }
+    E[0 * n + g] = hr ? acc[5 * n + g] + gS + gc1 * U[g + 1] + gc2 * U[n + g + 1] : 0.0;
+    E[1 * n + g] = hl ? acc[6 * n + g] + gS + gc1 * U[g - 1] + gc2 * U[n + g - 1] : 0.0;
+    E[2 * n + g] = hd ? acc[7 * n + g] + gS + gc1 * U[g + W] + gc2 * U[n + g + W] : 0.0;
+    E[3 * n + g] = hu ? acc[8 * n + g] + gS + gc1 * U[g - W] + gc2 * U[n + g - W] : 0.0;
+
+    // robust data weights and linearisation
+    const Lin L = lin_at(a, x, y);
+    const double b0 = L.b0, bx = L.bx, by = L.by;
+    const double Ix = L.Ix, Iy = L.Iy, Iz = L.Iz, Ixx = L.Ixx, Ixy = L.Ixy, Iyy = L.Iyy, Ixz = L.Ixz, Iyz = L.Iyz;
+    const double pi = L.pi, pg = L.pg;
+    const double gpi = gA11 * (b0 * Ix * Ix) + gA12 * (b0 * Ix * Iy) + gA22 * (b0 * Iy * Iy) + gB1 * (b0 * Ix * Iz) +
+                       gB2 * (b0 * Iy * Iz);
+    const double gpg = gA11 * (bx * Ixx * Ixx + by * Ixy * Ixy) + gA12 * (bx * Ixx * Ixy + by * Ixy * Iyy) +
+                       gA22 * (bx * Ixy * Ixy + by * Iyy * Iyy) + gB1 * (bx * Ixx * Ixz + by * Ixy * Iyz) +
+                       gB2 * (bx * Ixy * Ixz + by * Iyy * Iyz);
+    double gb0 = pi * (gA11 * Ix * Ix + gA12 * Ix * Iy + gA22 * Iy * Iy + gB1 * Ix * Iz + gB2 * Iy * Iz);
+    double gIx = pi * b0 * (2.0 * gA11 * Ix + gA12 * Iy + gB1 * Iz);
+    double gIy = pi * b0 * (gA12 * Ix + 2.0 * gA22 * Iy + gB2 * Iz);
+    double gIz = pi * b0 * (gB1 * Ix + gB2 * Iy);
+    double gbx = pg * (gA11 * Ixx * Ixx + gA12 * Ixx * Ixy + gA22 * Ixy * Ixy + gB1 * Ixx * Ixz + gB2 * Ixy * Ixz);
+    double gby = pg * (gA11 * Ixy * Ixy + gA12 * Ixy * Iyy + gA22 * Iyy * Iyy + gB1 * Ixy * Iyz + gB2 * Iyy * Iyz);
+    double gIxx = pg * bx * (2.0 * gA11 * Ixx + gA12 * Ixy + gB1 * Ixz);
+    double gIxy = pg * (bx * (gA12 * Ixx + 2.0 * gA22 * Ixy + gB2 * Ixz) + by * (2.0 * gA11 * Ixy + gA12 * Iyy + gB1 * Iyz));
+    double gIyy = pg * by * (gA12 * Ixy + 2.0 * gA22 * Iyy + gB2 * Iyz);
+    double gIxz = pg * bx * (gB1 * Ixx + gB2 * Ixy);
+    double gIyz = pg * by * (gB1 * Ixy + gB2 * Iyy);
+    const double eps2 = a.eps * a.eps;
+    // psi = w / (2 sqrt(E + eps^2))
+    const double gei = -gpi * pi / (2.0 * (L.ei + eps2));
+    const double geg = -gpg * pg / (2.0 * (L.eg + eps2));
+    gb0 += gei * L.ri * L.ri;
+    const double gri = 2.0 * b0 * L.ri * gei;
+    gIx += gri * L.fu; gIy += gri * L.fv; gIz += gri;
+    double gfu = gri * Ix, gfv = gri * Iy;
+    gbx += geg * L.rx * L.rx;
+    gby += geg * L.ry * L.ry;
+    const double grx = 2.0 * bx * L.rx * geg, gry = 2.0 * by * L.ry * geg;
+    gIxx += grx * L.fu; gIxy += grx * L.fv + gry * L.fu; gIxz += grx;
+    gIyy += gry * L.fv; gIyz += gry;
+    gfu += grx * Ixx + gry * Ixy;
+    gfv += grx * Ixy + gry * Iyy;
+    if (a.F) { atom(a.gF + g, gfu); atom(a.gF + n + g, gfv); }
+    // beta = 1 / (a^2 + b^2 + 0.01)
+    gIx += gb0 * (-b0 * b0) * 2.0 * Ix; gIy += gb0 * (-b0 * b0) * 2.0 * Iy;
+    gIxx += gbx * (-bx * bx) * 2.0 * Ixx; gIxy += gbx * (-bx * bx) * 2.0 * Ixy;
+    gIxy += gby * (-by * by) * 2.0 * Ixy; gIyy += gby * (-by * by) * 2.0 * Iyy;
+    // derivatives -> images (central differences with replicated borders)
+    const int xm = max(x - 1, 0), xp = min(x + 1, W - 1), ym = max(y - 1, 0), yp = min(y + 1, H - 1);
+    double* G0 = a.gJ0;
+    double* G1 = a.gJ1w;
+    auto addIb = [&](int xx, int yy, double v) {   // Ib = (J0 + J1w)/2
+        atom(G0 + yy * W + xx, 0.5 * v);
+        atom(G1 + yy * W + xx, 0.5 * v);
+    };
+    auto addIxa = [&](int xx, int yy, double v) {  // Ix at (xx, yy)
+        addIb(min(xx + 1, W - 1), yy, v / 2.0);
+        addIb(max(xx - 1, 0), yy, -v / 2.0);
+    };
+    auto addIya = [&](int xx, int yy, double v) {
+        addIb(xx, min(yy + 1, H - 1), v / 2.0);
+        addIb(xx, max(yy - 1, 0), -v / 2.0);
+    };
+    addIxa(x, y, gIx);
+    addIya(x, y, gIy);
+    addIxa(xp, y, gIxx / 2.0);
+    addIxa(xm, y, -gIxx / 2.0);
+    addIxa(x, yp, gIxy / 2.0);
+    addIxa(x, ym, -gIxy / 2.0);
+    addIya(x, yp, gIyy / 2.0);
+    addIya(x, ym, -gIyy / 2.0);
+    atom(G1 + g, gIz);
+    atom(G0 + g, -gIz);
+    atom(G1 + y * W + xp, gIxz / 2.0); atom(G1 + y * W + xm, -gIxz / 2.0);
+    atom(G0 + y * W + xp, -gIxz / 2.0); atom(G0 + y * W + xm, gIxz / 2.0);
+    atom(G1 + yp * W + x, gIyz / 2.0); atom(G1 + ym * W + x, -gIyz / 2.0);
+    atom(G0 + yp * W + x, -gIyz / 2.0); atom(G0 + ym * W + x, gIyz / 2.0);
+}
+
+// Part 2, per owner pixel: the adjoint of its edge weight (both edges, both
+// endpoints), then through ws = alpha / (2 sqrt(E_S + eps^2)) and the forward
+// differences of U + F.
+__global__ __launch_bounds__(256) void k_bwd_ws(const RefBwdArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int W = a.W, H = a.H;
+    if (x >= W || y >= H) return;
+    const size_t g = (size_t)y * W + x, n = (size_t)W * H;
+    const double* E = a.edge;
+    double gws = 0.0;
+    if (x < W - 1) gws += E[0 * n + g] + E[1 * n + g + 1];
+    if (y < H - 1) gws += E[2 * n + g] + E[3 * n + g + W];
+    if (gws == 0.0) return;
+    double es;
+    const double ws = ws_at(a, x, y, &es);
+    const double gE = -gws * ws / (2.0 * (es + a.eps * a.eps));
+    auto uu = [&](size_t i) { return a.F ? a.U[i] + a.F[i] : a.U[i]; };
+    auto vv = [&](size_t i) { return a.F ? a.U[n + i] + a.F[n + i] : a.U[n + i]; };
+    auto add = [&](size_t i, double v) {   // full flow U + F
+        atom(a.gU + i, v);
+        if (a.F) atom(a.gF + i, v);
+    };
+    const double u0 = uu(g), v0 = vv(g);
+    if (x < W - 1) {
+        const double dxu = uu(g + 1) - u0, dxv = vv(g + 1) - v0;
+        add(g + 1, 2.0 * dxu * gE); add(g, -2.0 * dxu * gE);
+        add(n + g + 1, 2.0 * dxv * gE); add(n + g, -2.0 * dxv * gE);
+    }
+    if (y < H - 1) {
+        const double dyu = uu(g + W) - u0, dyv = vv(g + W) - v0;
+        add(g + W, 2.0 * dyu * gE); add(g, -2.0 * dyu * gE);
+        add(n + g + W, 2.0 * dyv * gE); add(n + g, -2.0 * dyv * gE);
+    }
+}
+
+// ----------------------------------------------------------- densification
+
+// Reverse of the warped frame J1w(x) = J1(x + Ud(x)) and of Eq. (3): the
+// adjoint of the dense flow goes to every covering patch's displacement and,
+// through the weights 1/max(1,|d|), to the residuals d, hence to J0, J1 and
+// the patch's mean residual (per-patch sums by atomics).
+__global__ __launch_bounds__(256) void k_bwd_densify(const DensBwdArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int W = a.W, H = a.H;
+    if (x >= W || y >= H) return;
+    const size_t g = (size_t)y * W + x, n = (size_t)W * H;
+    const double Ux = a.Ud[g], Vx = a.Ud[n + g];
+    double gUx = a.gUd[g], gVx = a.gUd[n + g];
+    if (a.gJ1w) {
+        const double gw = a.gJ1w[g];
+        if (gw != 0.0) {
+            const Taps t = taps_of(a.J1, W, H, (double)x + Ux, (double)y + Vx);
+            gUx += gw * t.dx;
+            gVx += gw * t.dy;
+            scatter_taps(a.gJ1, t, gw);
+        }
+    }
+    if (gUx == 0.0 && gVx == 0.0) return;
+    const double Z = a.Z[g];
+    const double j0 = a.J0[g];
+    const int ps = a.ps, st = a.st;
+    int kx0, kx1, ky0, ky1;
+    {
+        const int lo = x - ps + 1;
+        kx0 = lo <= 0 ? 0 : (lo + st - 1) / st;
+        kx1 = min(x / st, a.nrx - 1);
+        const int loy = y - ps + 1;
+        ky0 = loy <= 0 ? 0 : (loy + st - 1) / st;
+        ky1 = min(y / st, a.nry - 1);
+    }
+    const bool fx = (a.nx > a.nrx) && (x >= W - ps), fy = (a.ny > a.nry) && (y >= H - ps);
+    const int kyend = ky1 + (fy ? 1 : 0), kxend = kx1 + (fx ? 1 : 0);
+    double gj0 = 0.0;
+    for (int jy = ky0; jy <= kyend; ++jy) {
+        const int ky = jy <= ky1 ? jy : a.nry;
+        for (int jx = kx0; jx <= kxend; ++jx) {
+            const int kx = jx <= kx1 ? jx : a.nrx;
+            const int i = ky * a.nx + kx;
+            const double* P = a.patch + (size_t)i * 4;
+            const double u = P[0], v = P[1];
+            const Taps t = taps_of(a.J1, W, H, (double)x + u, (double)y + v);
+            const double d = a.raw_residual ? (t.val - j0) : ((t.val - j0) - P[2]);
+            const double ad = fabs(d);
+            const double wgt = 1.0 / fmax(1.0, ad);
+            double* gP = a.gP + (size_t)i * 4;
+            atom(gP + 0, gUx * wgt / Z);
+            atom(gP + 1, gVx * wgt / Z);
+            const double gw = (gUx * (u - Ux) + gVx * (v - Vx)) / Z;
+            const double gd = ad > 1.0 ? gw * (d > 0.0 ? -1.0 : 1.0) / (d * d) : 0.0;
+            if (gd != 0.0) {
+                atom(gP + 0, gd * t.dx);
+                atom(gP + 1, gd * t.dy);
+                scatter_taps(a.gJ1, t, gd);
+                gj0 -= gd;
+                if (!a.raw_residual) atom(gP + 2, -gd);
+            }
+        }
+    }
+    atom(a.gJ0 + g, gj0);
+}
+
+// ------------------------------------------------------------------- pyramid
+
+// I -> J_s = 255 * (2^s x 2^s box mean): each input pixel collects its
+// level pixels' adjoints times 4^-s.
+__global__ __launch_bounds__(256) void k_bwd_pyramid(const PyrBwdArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= a.W || y >= a.H) return;
+    double g0 = 0.0, g1 = 0.0, sc = 1.0;
+    for (int s = 0; s <= a.ss; ++s) {
+        if (s >= a.sf) {
+            const int xs = x >> s, ys = y >> s;
+            if (xs < a.ws[s] && ys < a.hs[s]) {
+                const size_t i = (size_t)ys * a.ws[s] + xs;
+                g0 += sc * a.gJ0[s][i];
+                g1 += sc * a.gJ1[s][i];
+            }
+        }
+        sc *= 0.25;
+    }
+    const size_t g = (size_t)y * a.W + x;
+    if (a.out_f64) {
+        ((double*)a.gI0)[g] = 255.0 * g0;
+        ((double*)a.gI1)[g] = 255.0 * g1;
+    } else {
+        ((float*)a.gI0)[g] = (float)(255.0 * g0);
+        ((float*)a.gI1)[g] = (float)(255.0 * g1);
+    }
+}
+
+// ------------------------------------------------------------------- search
+
+// Reverse of the inverse-compositional search of one block of patches
+// (LPP lanes per patch, as in the forward).  The forward iterates are
+// recomputed and kept in LDS, then the theta_it updates
+// u <- u - M b(u) (M = (H + lambda I)^-1) are reversed; gradients reach the
+// taps of J1, the template and its Sobel gradients in J0, and, through the
+// initialisation 2 U_{s+1}(c/2), the coarser flow.
+template <int PS, int LPP>
+__global__ __launch_bounds__(256) void k_bwd_search(const SearchBwdArgs A) {
+    constexpr int NP = PS * PS;
+    constexpr int PPL = (NP + LPP - 1) / LPP;
+    constexpr int GROUPS = 256 / LPP;
+    extern __shared__ double s_u[];             // [GROUPS][iters + 1][2]
+    const SearchArgs& a = A.sa;
+    const int W = a.W, H = a.H;
+    const int lane = threadIdx.x & (LPP - 1);
+    const int grp = threadIdx.x / LPP;
+    const int N = a.nx * a.ny;
+    int pi = (int)((blockIdx.x * 256u + threadIdx.x) / LPP);
+    const bool valid = pi < N;
+    if (!valid) pi = N - 1;
+    const int ky = pi / a.nx, kx = pi - ky * a.nx;
+    const int x0 = kx < a.nrx ? kx * a.st : W - PS;
+    const int y0 = ky < a.nry ? ky * a.st : H - PS;
+    double qx = 0.0, qy = 0.0, ui = 0.0, vi = 0.0;
+    if (a.Un) {
+        const double c = 0.5 * (PS - 1);
+        qx = (double)x0 + c;
+        qy = (double)y0 + c;
+        if (a.centre_map) { qx = (qx + 0.5) / 2.0 - 0.5; qy = (qy + 0.5) / 2.0 - 0.5; }
+        else { qx = qx / 2.0; qy = qy / 2.0; }
+        ui = 2.0 * taps_of(a.Un, a.Wn, a.Hn, qx, qy).val;
+        vi = 2.0 * taps_of(a.Un + (size_t)a.Wn * a.Hn, a.Wn, a.Hn, qx, qy).val;
+    }
+    const double* J0 = a.J0;
+    const double* J1 = a.J1;
+    // pixels of this lane: p = lane + k * LPP
+    double T[PPL], gx[PPL], gy[PPL];
+    double sgx_l = 0.0, sgy_l = 0.0, h11_l = 0.0, h12_l = 0.0, h22_l = 0.0;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const int p = lane + k * LPP;
+        T[k] = gx[k] = gy[k] = 0.0;
+        if (p < NP) {
+            const int py = p / PS, px = p - py * PS;
+            const int x = x0 + px, y = y0 + py;
+            const int xm = max(x - 1, 0), xp = min(x + 1, W - 1), ym = max(y - 1, 0), yp = min(y + 1, H - 1);
+            T[k] = J0[y * W + x];
+            const double dm = J0[ym * W + xp] - J0[ym * W + xm];
+            const double d0 = J0[y * W + xp] - J0[y * W + xm];
+            const double dp = J0[yp * W + xp] - J0[yp * W + xm];
+            gx[k] = ((dm + 2.0 * d0) + dp) / 8.0;
+            const double em = J0[yp * W + xm] - J0[ym * W + xm];
+            const double e0 = J0[yp * W + x] - J0[ym * W + x];
+            const double ep = J0[yp * W + xp] - J0[ym * W + xp];
+            gy[k] = ((em + 2.0 * e0) + ep) / 8.0;
+        }
+        sgx_l += gx[k]; sgy_l += gy[k];
+        h11_l += gx[k] * gx[k]; h12_l += gx[k] * gy[k]; h22_l += gy[k] * gy[k];
+    }
+    auto red = [&](double v) {
+        for (int off = 1; off < LPP; off <<= 1) v += __shfl_xor(v, off, 64);
+        return v;
+    };
+    const double sgx = red(sgx_l), sgy = red(sgy_l);
+    const double a11 = red(h11_l) + a.lam, a12 = red(h12_l), a22 = red(h22_l) + a.lam;
+    const double idet = 1.0 / (a11 * a22 - a12 * a12);
+    const double m11 = a22 * idet, m12 = -a12 * idet, m22 = a11 * idet;
+    const double inv_n = 1.0 / (double)NP;
+    const double lim = (double)(W + H + 2 * PS + 4);
+    const double* P = a.patch + (size_t)pi * 4;
+    const double uf = P[0], vf = P[1];
+    const bool reset = P[3] > (double)PS;
+    const double* gP = A.gP + (size_t)pi * 4;
+    double gu = gP[0], gv = gP[1];
+    const double gmd = gP[2];
+    double gT[PPL], ggx[PPL], ggy[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) gT[k] = ggx[k] = ggy[k] = 0.0;
+
+    // residual of the patch at displacement (u, v): d_p, and its derivatives
+    auto warp = [&](double u, double v, double (&d)[PPL], double (&dx)[PPL], double (&dy)[PPL], Taps (&tp)[PPL]) {
+        const double fu = floor(u), fv = floor(v);
+        const double cu = fmin(fmax(fu, -lim), lim) + (u - fu), cv = fmin(fmax(fv, -lim), lim) + (v - fv);
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            const int p = lane + k * LPP;
+            d[k] = dx[k] = dy[k] = 0.0;
+            if (p < NP) {
+                const int py = p / PS, px = p - py * PS;
+                tp[k] = taps_of(J1, W, H, (double)(x0 + px) + cu, (double)(y0 + py) + cv);
+                d[k] = tp[k].val - T[k];
+                dx[k] = tp[k].dx;
+                dy[k] = tp[k].dy;
+            }
+        }
+    };
+    double d[PPL], dqx[PPL], dqy[PPL];
+    Taps tp[PPL];
+    // mean residual at the final displacement (used by the densification)
+    if (gmd != 0.0) {
+        warp(uf, vf, d, dqx, dqy, tp);
+        const double q = gmd * inv_n;
+        double su = 0.0, sv = 0.0;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            const int p = lane + k * LPP;
+            if (p < NP && valid) {
+                su += q * dqx[k];
+                sv += q * dqy[k];
+                scatter_taps(A.gJ1, tp[k], q);
+                gT[k] -= q;
+            }
+        }
+        gu += red(su);
+        gv += red(sv);
+    }
+    double gui = gu, gvi = gv;
+    if (!reset && a.iters > 0) {
+        // forward iterates u_0 .. u_iters
+        double* su_ = s_u + (size_t)grp * (a.iters + 1) * 2;
+        double u = ui, v = vi;
+        for (int it = 0; it < a.iters; ++it) {
+            // every lane of the patch holds the same bits of (u, v) (the
+            // butterfly sums are commutative), so each lane keeps its own copy
+            su_[2 * it] = u;
+            su_[2 * it + 1] = v;
+            warp(u, v, d, dqx, dqy, tp);
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) { s0 += d[k]; s1 += gx[k] * d[k]; s2 += gy[k] * d[k]; }
+            const double md = red(s0) * inv_n;
+            const double b1 = red(s1) - md * sgx, b2 = red(s2) - md * sgy;
+            u = u - (m11 * b1 + m12 * b2);
+            v = v - (m12 * b1 + m22 * b2);
+        }
+        double H11 = 0.0, H12 = 0.0, H21 = 0.0, H22 = 0.0;   // adjoint of H
+        for (int it = a.iters - 1; it >= 0; --it) {
+            const double uk = su_[2 * it], vk = su_[2 * it + 1];
+            warp(uk, vk, d, dqx, dqy, tp);
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) { s0 += d[k]; s1 += gx[k] * d[k]; s2 += gy[k] * d[k]; }
+            const double md = red(s0) * inv_n;
+            const double b1 = red(s1) - md * sgx, b2 = red(s2) - md * sgy;
+            // u_{k+1} = u_k - Delta, Delta = M b
+            const double Dl1 = -gu, Dl2 = -gv;                      // adjoint of Delta
+            const double bb1 = m11 * Dl1 + m12 * Dl2, bb2 = m12 * Dl1 + m22 * Dl2;   // adjoint of b
+            const double D1 = m11 * b1 + m12 * b2, D2 = m12 * b1 + m22 * b2;
+            H11 -= bb1 * D1; H12 -= bb1 * D2; H21 -= bb2 * D1; H22 -= bb2 * D2;
+            double su = 0.0, sv = 0.0;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                const int p = lane + k * LPP;
+                if (p < NP) {
+                    // b = sum g (d - md): d(b)/d(d_p) = g_p - sum(g)/n
+                    const double dd = bb1 * (gx[k] - sgx * inv_n) + bb2 * (gy[k] - sgy * inv_n);
+                    ggx[k] += bb1 * (d[k] - md);
+                    ggy[k] += bb2 * (d[k] - md);
+                    gT[k] -= dd;
+                    su += dd * dqx[k];
+                    sv += dd * dqy[k];
+                    if (valid) scatter_taps(A.gJ1, tp[k], dd);
+                }
+            }
+            gu += red(su);
+            gv += red(sv);
+        }
+        gui = gu;
+        gvi = gv;
+        // H = sum g g^T + lambda I
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            ggx[k] += (H11 + H11) * gx[k] + (H12 + H21) * gy[k];
+            ggy[k] += (H12 + H21) * gx[k] + (H22 + H22) * gy[k];
+        }
+    }
+    if (!valid) return;
+    // template and Sobel/8 gradients -> J0
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const int p = lane + k * LPP;
+        if (p >= NP) continue;
+        const int py = p / PS, px = p - py * PS;
+        const int x = x0 + px, y = y0 + py;
+        const int xm = max(x - 1, 0), xp = min(x + 1, W - 1), ym = max(y - 1, 0), yp = min(y + 1, H - 1);
+        double* G = A.gJ0;
+        atom(G + y * W + x, gT[k]);
+        const double ax = ggx[k] / 8.0, ay = ggy[k] / 8.0;
+        atom(G + ym * W + xp, ax); atom(G + ym * W + xm, -ax);
+        atom(G + y * W + xp, 2.0 * ax); atom(G + y * W + xm, -2.0 * ax);
+        atom(G + yp * W + xp, ax); atom(G + yp * W + xm, -ax);
+        atom(G + yp * W + xm, ay); atom(G + ym * W + xm, -ay);
+        atom(G + yp * W + x, 2.0 * ay); atom(G + ym * W + x, -2.0 * ay);
+        atom(G + yp * W + xp, ay); atom(G + ym * W + xp, -ay);
+    }
+    // initialisation u_init = 2 U_{s+1}(q)
+    if (a.Un && lane == 0) {
+        const Taps t = taps_of(nullptr, a.Wn, a.Hn, qx, qy);
+        scatter_taps(A.gUn, t, 2.0 * gui);
+        scatter_taps(A.gUn + (size_t)a.Wn * a.Hn, t, 2.0 * gvi);
+    }
+}
+
+// ------------------------------------------------------------ kernel table
+
+const void* dis_kernel_bzero() { return (const void*)&k_bzero; }
+const void* dis_kernel_bcopy() { return (const void*)&k_bcopy; }
+const void* dis_kernel_baxpy() { return (const void*)&k_baxpy; }
+const void* dis_kernel_bwd_upsample() { return (const void*)&k_bwd_upsample; }
+const void* dis_kernel_bwd_coef() { return (const void*)&k_bwd_coef; }
+const void* dis_kernel_bwd_coef2() { return (const void*)&k_bwd_coef2; }
+const void* dis_kernel_bwd_sweep_a() { return (const void*)&k_bwd_sweep_a; }
+const void* dis_kernel_bwd_sweep_b() { return (const void*)&k_bwd_sweep_b; }
+const void* dis_kernel_bwd_lin() { return (const void*)&k_bwd_lin; }
+const void* dis_kernel_bwd_ws() { return (const void*)&k_bwd_ws; }
+const void* dis_kernel_bwd_densify() { return (const void*)&k_bwd_densify; }
+const void* dis_kernel_bwd_pyramid() { return (const void*)&k_bwd_pyramid; }
+
+#define DIS_BWD_SEARCH_CASE(PS_) \
+    if (ps == PS_) return (const void*)&k_bwd_search<PS_, 16>;
+const void* dis_kernel_bwd_search(int ps) {
+    DIS_BWD_SEARCH_CASE(4) DIS_BWD_SEARCH_CASE(6) DIS_BWD_SEARCH_CASE(8) DIS_BWD_SEARCH_CASE(10)
+    DIS_BWD_SEARCH_CASE(12) DIS_BWD_SEARCH_CASE(14) DIS_BWD_SEARCH_CASE(16)
+    return nullptr;
+}

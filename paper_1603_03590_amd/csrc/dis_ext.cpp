@@ -123,7 +123,7 @@ static int build_batch(dis_handle* h, int n, const int* w, const int* hgt, const
         bp->seq.add(dis_kernel_pyramid_tab(), dim3(pstart[i].back(), 2), dim3(256), &T, sizeof T, 0, "pyramid", by,
                     0.0);
     }
-    int r = dis_build_levels(h, pairs, bp->seq, bp->tabs);
+    int r = dis_build_levels(h, pairs, bp->seq, bp->tabs, nullptr);
     if (r != DIS_OK) return r;
     {
         PyrTab* T0 = (PyrTab*)bp->seq.items[first].arg.data();
@@ -331,9 +331,3 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
     return DIS_OK;
 }
 
-// ---------------------------------------------------------------- backward
-
-extern "C" int dis_flow_backward(dis_handle* h, const void*, void*, void*) {
-    if (!h) return dis_fail(nullptr, DIS_EINVAL, "handle is NULL");
-    return dis_fail(h, DIS_ESTATE, "backward not built yet");
-}

@@ -142,7 +142,7 @@ extern "C" int dis_default_params(int preset, dis_params* out) {
 
 // ------------------------------------------------------------------- arena
 
-static int dalloc(dis_handle* h, void** ptr, size_t bytes) {
+int dis_dalloc(dis_handle* h, void** ptr, size_t bytes) {
     *ptr = nullptr;
     if (bytes == 0) return DIS_OK;
     hipError_t e = hipMalloc(ptr, bytes);
@@ -158,7 +158,7 @@ static int dalloc(dis_handle* h, void** ptr, size_t bytes) {
 
 #define DALLOC(h, ptr, bytes)                                      \
     do {                                                           \
-        int r_ = dalloc((h), (void**)&(ptr), (bytes));             \
+        int r_ = dis_dalloc((h), (void**)&(ptr), (bytes));         \
         if (r_ != DIS_OK) return r_;                               \
     } while (0)
 
@@ -237,6 +237,14 @@ extern "C" int dis_create(const dis_params* p, int max_w, int max_h, int max_bat
             return r;
         }
     }
+    if (p->flags & DIS_FLAG_KEEP_FOR_BACKWARD) {
+        r = dis_alloc_backward(h);
+        if (r != DIS_OK) {
+            g_null_err = h->err;
+            dis_destroy(h);
+            return r;
+        }
+    }
     *out = h;
     return DIS_OK;
 }
@@ -255,6 +263,7 @@ extern "C" void dis_destroy(dis_handle* h) {
         BatchPlan* bp = kv.second;
         dis_batch_plan_free(bp);
     }
+    for (auto& kv : h->bwplans) dis_bwd_plan_free(kv.second);
     for (ProfPending& pp : h->prof_pending) { hipEventDestroy(pp.a); hipEventDestroy(pp.b); }
     for (hipEvent_t e : h->prof_free) hipEventDestroy(e);
     for (void* ptr : h->allocs) hipFree(ptr);
@@ -277,6 +286,8 @@ static void drop_plans(dis_handle* h) {
     h->plans.clear();
     for (auto& kv : h->bplans) dis_batch_plan_free(kv.second);
     h->bplans.clear();
+    for (auto& kv : h->bwplans) dis_bwd_plan_free(kv.second);
+    h->bwplans.clear();
 }
 
 extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int refine_tile, int launch_mode) {
@@ -330,7 +341,7 @@ int dis_pick_lpp(const dis_handle* h, int s, int N) {
     return 16;
 }
 
-static int grid_info(const dis_handle* h, int W, int H, LevelGrid* g) {
+int dis_level_grid(const dis_handle* h, int W, int H, LevelGrid* g) {
     const int ps = h->p.patch_size;
     g->W = W;
     g->H = H;
@@ -437,14 +448,14 @@ void dis_add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, Se
 // Refinement phases of one level: theta_vo fixed-point steps, each split
 // into launches of at most DIS_KMAX half sweeps; three increment buffers
 // rotate so that a phase never writes what it reads.
-static void refine_phases(const dis_params& p, int s, std::vector<RefPhase>& out) {
+void dis_refine_phases(const dis_params& p, int s, std::vector<RefPhase>& out) {
     out.clear();
     const int nouter = p.var_outer < 0 ? s + 1 : p.var_outer;
     if (nouter == 0) {
-        out.push_back(RefPhase{-1, -1, 0, 0, 1});
+        out.push_back(RefPhase{-1, -1, 0, 0, 1, 0});
         return;
     }
-    int cur = -1;
+    int cur = -1, m = 0;
     for (int k = 0; k < nouter; ++k) {
         const int frozen = cur;
         int in = cur;
@@ -454,7 +465,8 @@ static void refine_phases(const dis_params& p, int s, std::vector<RefPhase>& out
             left -= nh;
             int ob = 0;
             while (ob == frozen || ob == in) ++ob;
-            out.push_back(RefPhase{frozen, in, ob, nh, (k == nouter - 1 && left == 0) ? 1 : 0});
+            out.push_back(RefPhase{frozen, in, ob, nh, (k == nouter - 1 && left == 0) ? 1 : 0, m});
+            m += nh;
             in = ob;
         }
         cur = in;
@@ -466,13 +478,14 @@ static void refine_phases(const dis_params& p, int s, std::vector<RefPhase>& out
 // in device tables; launch mode 0 runs each level as one persistent k_level
 // launch over that queue, mode 1 as one launch per phase covering every
 // pair.  Both give the same bits.
-int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs) {
+int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs,
+                     const LevelOpts* opt) {
     const dis_params& p = h->p;
     const int ps = p.patch_size, sf = p.finest_scale;
     const int cmap = (p.flags & DIS_FLAG_PIXEL_CENTRE) ? 1 : 0;
     int top = sf;
     for (const PairRef& r : pairs) top = std::max(top, r.ss);
-    const int mode = h->mode_phase;
+    const int mode = (opt && opt->force_phase) ? 1 : h->mode_phase;
     const int tile_id = mode ? h->refine_tile : DIS_LEVEL_TILE;
     int tw = 32, th = 16;
     dis_refine_tile(tile_id, &tw, &th);
@@ -486,15 +499,16 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     };
     std::vector<LevelHost> levels;
     for (int s = top; s >= sf; --s) {
+        if (opt && opt->only_level >= 0 && s != opt->only_level) continue;
         LevelHost LH;
-        refine_phases(p, s, LH.rph);
+        dis_refine_phases(p, s, LH.rph);
         if (!p.refine) LH.rph.clear();
         LH.nph = 2 + (int)LH.rph.size();
         long long totN = 0;
         for (const PairRef& r : pairs) {
             if (r.ss < s) continue;
             LevelGrid g;
-            totN += grid_info(h, r.w >> s, r.h >> s, &g);
+            totN += dis_level_grid(h, r.w >> s, r.h >> s, &g);
         }
         LH.lpp = dis_pick_lpp(h, s, (int)std::min<long long>(totN, 1 << 30));
         LH.by[0] = LH.by[1] = LH.fl[0] = LH.fl[1] = 0.0;
@@ -503,7 +517,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             SlotBuf& sb = *r.sb;
             LevelBuf& L = sb.lv[s];
             LevelGrid g;
-            const int N = grid_info(h, r.w >> s, r.h >> s, &g);
+            const int N = dis_level_grid(h, r.w >> s, r.h >> s, &g);
             if (N > L.maxN) return fail(h, DIS_ESIZE, "internal: %d patches exceed capacity %d", N, L.maxN);
             const int W = g.W, Hh = g.H;
             LevelPair P;
@@ -524,8 +538,10 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             da.raw_residual = (p.flags & DIS_FLAG_RAW_RESIDUAL) ? 1 : 0;
             da.U = L.Ud;
             da.J1w = p.refine ? sb.J1w : nullptr;
+            da.Z = opt ? opt->Z : nullptr;
             RefineArgs& ra = P.ra;
             ra.U = L.Ud; ra.J0 = L.J0; ra.J1w = sb.J1w; ra.Uout = L.U;
+            ra.tape = opt ? opt->tape : nullptr;
             ra.W = W; ra.H = Hh;
             ra.tiles_x = (W + tw - 1) / tw;
             ra.delta = p.w_intensity; ra.gamma = p.w_gradient; ra.alpha = p.w_smooth;
@@ -621,6 +637,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             for (int ph = 0; ph < LH.nph; ++ph) {
                 const int n = start[(ph + 1) * np] - start[ph * np];
                 if (ph == 0) {
+                    if (opt && opt->skip_search) continue;
                     seq.add(fs, dim3(n), dim3(256), &LL, sizeof LL, 0, "search", ph_by[0], ph_fl[0]);
                 } else if (ph == 1) {
                     seq.add(dis_kernel_phase_densify(), dim3(n), dim3(256), &LL, sizeof LL, 0, "densify", ph_by[1],
@@ -654,7 +671,7 @@ int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const 
     int r = dis_add_pyramid(h, sb, w, hgt, pitch, ss, I0, I1, seq);
     if (r != DIS_OK) return r;
     std::vector<PairRef> pr{PairRef{&sb, w, hgt, ss}};
-    r = dis_build_levels(h, pr, seq, tabs);
+    r = dis_build_levels(h, pr, seq, tabs, nullptr);
     if (r != DIS_OK) return r;
     dis_add_upsample(h, sb, w, hgt, flow, seq);
     // the first pyramid launch clears the level launches' queue state
@@ -699,11 +716,11 @@ int dis_launch_eager(dis_handle* h, Seq& seq) {
             pp.bytes = L.bytes;
             pp.flops = L.flops;
             HIPCHK(h, hipEventRecord(pp.a, h->stream));
-            HIPCHK(h, hipLaunchKernel(L.fn, L.grid, L.block, args, 0, h->stream));
+            HIPCHK(h, hipLaunchKernel(L.fn, L.grid, L.block, args, L.shmem, h->stream));
             HIPCHK(h, hipEventRecord(pp.b, h->stream));
             h->prof_pending.push_back(pp);
         } else {
-            HIPCHK(h, hipLaunchKernel(L.fn, L.grid, L.block, args, 0, h->stream));
+            HIPCHK(h, hipLaunchKernel(L.fn, L.grid, L.block, args, L.shmem, h->stream));
         }
     }
     return DIS_OK;
@@ -748,31 +765,35 @@ extern "C" int dis_profile_read(dis_handle* h, dis_kernel_stat* out, int max, in
     return DIS_OK;
 }
 
-static int build_graph(dis_handle* h, Plan* pl) {
-    HIPCHK(h, hipGraphCreate(&pl->graph, 0));
+// A graph of one kernel node per launch, chained in order.
+int dis_build_graph_seq(dis_handle* h, Seq& seq, hipGraph_t* graph, hipGraphExec_t* exec,
+                        std::vector<hipGraphNode_t>* nodes) {
+    HIPCHK(h, hipGraphCreate(graph, 0));
     hipGraphNode_t prev = nullptr;
-    pl->nodes.resize(pl->seq.items.size());
-    for (size_t i = 0; i < pl->seq.items.size(); ++i) {
-        Launch& L = pl->seq.items[i];
+    nodes->resize(seq.items.size());
+    for (size_t i = 0; i < seq.items.size(); ++i) {
+        Launch& L = seq.items[i];
         hipKernelNodeParams kp;
         std::memset(&kp, 0, sizeof kp);
         void* args[1] = {L.arg.data()};
         kp.func = (void*)L.fn;
         kp.gridDim = L.grid;
         kp.blockDim = L.block;
-        kp.sharedMemBytes = 0;
+        kp.sharedMemBytes = (unsigned)L.shmem;
         kp.kernelParams = args;
         kp.extra = nullptr;
-        HIPCHK(h, hipGraphAddKernelNode(&pl->nodes[i], pl->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
-        prev = pl->nodes[i];
+        HIPCHK(h, hipGraphAddKernelNode(&(*nodes)[i], *graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        prev = (*nodes)[i];
     }
-    HIPCHK(h, hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0));
+    HIPCHK(h, hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0));
     return DIS_OK;
 }
 
-static int update_graph_io(dis_handle* h, Plan* pl) {
-    for (size_t i = 0; i < pl->seq.items.size(); ++i) {
-        Launch& L = pl->seq.items[i];
+// Push the argument blocks of the caller-facing launches (kind != 0) into
+// an instantiated graph.
+int dis_update_graph_seq(dis_handle* h, Seq& seq, hipGraphExec_t exec, const std::vector<hipGraphNode_t>& nodes) {
+    for (size_t i = 0; i < seq.items.size(); ++i) {
+        Launch& L = seq.items[i];
         if (L.kind == 0) continue;
         hipKernelNodeParams kp;
         std::memset(&kp, 0, sizeof kp);
@@ -780,12 +801,16 @@ static int update_graph_io(dis_handle* h, Plan* pl) {
         kp.func = (void*)L.fn;
         kp.gridDim = L.grid;
         kp.blockDim = L.block;
-        kp.sharedMemBytes = 0;
+        kp.sharedMemBytes = (unsigned)L.shmem;
         kp.kernelParams = args;
-        HIPCHK(h, hipGraphExecKernelNodeSetParams(pl->exec, pl->nodes[i], &kp));
+        HIPCHK(h, hipGraphExecKernelNodeSetParams(exec, nodes[i], &kp));
     }
     return DIS_OK;
 }
+
+static int build_graph(dis_handle* h, Plan* pl) { return dis_build_graph_seq(h, pl->seq, &pl->graph, &pl->exec, &pl->nodes); }
+
+static int update_graph_io(dis_handle* h, Plan* pl) { return dis_update_graph_seq(h, pl->seq, pl->exec, pl->nodes); }
 
 extern "C" int dis_compute_flow(dis_handle* h, const void* I0, const void* I1, int w, int hgt, int pitch,
                                 void* flow) {
@@ -867,7 +892,7 @@ extern "C" int dis_debug_level(dis_handle* h, int s, int what, void* dst, size_t
     if (s < h->last_sf || s > h->last_ss) return fail(h, DIS_ESTATE, "scale %d not computed (%d..%d)", s, h->last_sf, h->last_ss);
     LevelBuf& L = h->slots[0].lv[s];
     LevelGrid g;
-    const int N = grid_info(h, h->last_w >> s, h->last_h >> s, &g);
+    const int N = dis_level_grid(h, h->last_w >> s, h->last_h >> s, &g);
     const size_t px = (size_t)g.W * g.H;
     const void* src = nullptr;
     size_t n = 0;
@@ -879,6 +904,10 @@ extern "C" int dis_debug_level(dis_handle* h, int s, int what, void* dst, size_t
         case DIS_DBG_UPATCH: src = nullptr; n = (size_t)N * 16; break;
         case DIS_DBG_UDENSE: src = L.Ud; n = 2 * px * 8; break;
         case DIS_DBG_UREFINED: src = L.U; n = 2 * px * 8; break;
+        case DIS_DBG_GRAD_J0: src = h->bwd.gJ0[s]; n = px * 8; break;
+        case DIS_DBG_GRAD_J1: src = h->bwd.gJ1[s]; n = px * 8; break;
+        case DIS_DBG_GRAD_U: src = h->bwd.gU[s]; n = 2 * px * 8; break;
+        case DIS_DBG_GRAD_PATCH: src = h->bwd.gP[s]; n = (size_t)N * 32; break;
         case DIS_DBG_INFO:
             info[0] = g.W; info[1] = g.H; info[2] = N; info[3] = g.nx; info[4] = g.ny; info[5] = g.st;
             if (bytes < sizeof info) return fail(h, DIS_ESIZE, "need %zu bytes", sizeof info);

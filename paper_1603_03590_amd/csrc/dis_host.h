@@ -39,7 +39,8 @@ struct Launch {
     const void* fn;
     dim3 grid, block;
     std::vector<char> arg;
-    int kind;
+    int kind;           // 3 reads the caller's flow gradient, 4 writes the frame gradients
+    size_t shmem = 0;   // dynamic LDS bytes
     const char* name;   // kernel family, for profiling
     double bytes;       // algorithmic memory traffic of this launch
     double flops;       // algorithmic floating-point work of this launch
@@ -91,8 +92,23 @@ struct Plan {
     const void* bound[3] = {nullptr, nullptr, nullptr};   // frames / flow the graph points at
 };
 
+// Device buffers of the backward pass (slot 0), allocated by dis_create when
+// the handle keeps forward state for it.
+struct BwdBuf {
+    double* gJ0[DIS_MAXL];
+    double* gJ1[DIS_MAXL];
+    double* gU[DIS_MAXL];
+    double* gP[DIS_MAXL];
+    double* Z;
+    double *gUd, *gJ1w, *gd, *gn, *acc, *coef, *edge, *gFacc;
+    double* tape;               // SOR states of one level, [half sweep][2][H][W]
+    size_t tape_len;            // capacity in doubles
+    size_t scratch_px;          // pixels of the largest processed level
+};
 struct BatchPlan;
 void dis_batch_plan_free(BatchPlan* bp);
+struct BwdPlan;
+void dis_bwd_plan_free(BwdPlan* bp);
 
 struct dis_handle {
     dis_params p;
@@ -123,6 +139,9 @@ struct dis_handle {
     std::vector<void*> last_batch_flow;
     std::vector<int> last_batch_w, last_batch_h, last_batch_pitch;
     double tuned_ms = 0.0;
+    // backward pass
+    BwdBuf bwd{};
+    std::map<std::tuple<int, int>, BwdPlan*> bwplans;
     // per-kernel event timing (dis_profile_enable)
     bool profiling = false;
     std::vector<ProfPending> prof_pending;
@@ -136,7 +155,24 @@ void dis_grid(int n, int ps, int st, int* nr, int* ntot);
 int dis_pick_lpp(const dis_handle* h, int s, int N);
 int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const void* I0, const void* I1,
                    void* flow, Seq& seq, PairInfo* info, PlanTables& tabs);
-int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs);
+// Options of dis_build_levels for the backward pass's recomputation.
+struct LevelOpts {
+    int only_level = -1;        // build only this scale
+    double* tape = nullptr;     // record every SOR half sweep's state
+    double* Z = nullptr;        // keep the densification weight sums
+    int skip_search = 0;        // the patch records are kept: recompute from densification on
+    int force_phase = 0;        // one launch per phase whatever the tuned launch mode
+};
+
+int dis_alloc_backward(dis_handle* h);
+int dis_dalloc(dis_handle* h, void** ptr, size_t bytes);
+int dis_build_graph_seq(dis_handle* h, Seq& seq, hipGraph_t* graph, hipGraphExec_t* exec,
+                        std::vector<hipGraphNode_t>* nodes);
+int dis_update_graph_seq(dis_handle* h, Seq& seq, hipGraphExec_t exec, const std::vector<hipGraphNode_t>& nodes);
+int dis_level_grid(const dis_handle* h, int W, int H, LevelGrid* g);   // patch grid of a W x H level; returns N
+int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs,
+                     const LevelOpts* opt);
+void dis_refine_phases(const dis_params& p, int s, std::vector<RefPhase>& out);
 int dis_add_pyramid(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, int ss, const void* I0, const void* I1,
                     Seq& seq);
 void dis_add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, Seq& seq);

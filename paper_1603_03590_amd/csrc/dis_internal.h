@@ -52,6 +52,7 @@ struct DensifyArgs {
     int raw_residual;
     double* U;              // [2][H][W]
     double* J1w;            // [H][W], or null without refinement
+    double* Z;              // [H][W] sum of the weights, or null (kept for the backward pass)
 };
 
 // Part of one fixed-point iteration of the refinement: linearisation from
@@ -66,6 +67,8 @@ struct RefineArgs {
     const double* dUin;     // null = zero
     double* dUout;
     double* Uout;
+    double* tape;           // when non-null: state after half sweep m at tape + m*2*W*H (m >= 1)
+    int tape_m0;            // half sweeps of this level done before this launch
     int W, H;
     int nhalf;
     int tiles_x;
@@ -99,6 +102,7 @@ struct RefPhase {
     int f, in, out;
     int nhalf;
     int last;               // 1: also write U + dU
+    int m0;                 // half sweeps of the level before this phase (tape index)
 };
 
 // A persistent launch over the queue segments of every pair at one level,

@@ -328,6 +328,7 @@ __device__ __forceinline__ void densify_block(const DensifyArgs& a, int bx, int 
     }
     const double U = su / sw, V = sv / sw;
     const int g = y * W + x;
+    if (a.Z) a.Z[g] = sw;
     a.U[g] = U;
     a.U[W * H + g] = V;
     if (a.J1w) a.J1w[g] = bilin(a.J1, W, H, (double)x + U, (double)y + V);
@@ -560,6 +561,20 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
                 dv_[l] = dvn;
             }
             __syncthreads();
+            if (a.tape) {
+                // state after this half sweep, core pixels only (every pixel of
+                // the level is the core of exactly one tile)
+                double* tp = a.tape + (size_t)(a.tape_m0 + j + c + 1) * 2 * n;
+                const int CW = cx1 - cx0, CH = cy1 - cy0;
+                for (int i = threadIdx.x; i < CW * CH; i += 256) {
+                    const int yy = i / CW, xx = i - yy * CW;
+                    const size_t g = (size_t)(cy0 + yy) * W + cx0 + xx;
+                    const int l = (cy0 + yy - ry0) * LP + (cx0 + xx - rx0);
+                    tp[g] = du_[l];
+                    tp[n + g] = dv_[l];
+                }
+                __syncthreads();   // the next half sweep rewrites what was just copied
+            }
         }
     }
 
@@ -616,6 +631,7 @@ __global__ __launch_bounds__(256) void k_phase_refine(const PhaseLaunch PL) {
     ra.dUout = P.dU[rp.out];
     ra.Uout = rp.last ? P.ra.Uout : nullptr;
     ra.nhalf = rp.nhalf;
+    ra.tape_m0 = rp.m0;
     refine_tile<TW, TH>(ra, t - __builtin_amdgcn_readfirstlane(L.start[s0 + j]), sm);
 }
 
@@ -731,6 +747,7 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
                 ra.dUout = P.dU[rp.out];
                 ra.Uout = rp.last ? P.ra.Uout : nullptr;
                 ra.nhalf = __builtin_amdgcn_readfirstlane(rp.nhalf);
+                ra.tape_m0 = rp.m0;
                 refine_tile<32, 16>(ra, local, sm);
             }
         }
