@@ -6,7 +6,8 @@ inverse search, densification and refinement, upscaling) over one synthetic
 1024x436 grayscale pair already resident in HBM, replayed from a HIP graph,
 with the launch choices picked by the library's autotuner.  Also measured on
 the same GPU: the second 1024x436 operating point, the batched form (64
-pairs of uneven size per call) and, when built, the forward+backward form.
+pairs of uneven size per call) and the forward+backward form (8 pairs of
+512x256, mean-EPE loss, gradients with respect to both frames).
 
 Prints ONE JSON line: throughput in Mpix/s of dense output flow, a per-kernel
 roofline entry for the kernel family that takes the most time (HIP events on
@@ -73,6 +74,13 @@ def main():
     ap.add_argument("--op", default="c2a", choices=["c2a", "c2b"], help="operating point of the headline line")
     ap.add_argument("--batch", type=int, default=64, help="pairs in the batched measurement (0 skips it)")
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline operating point (no launch-mode comparison, no second point); "
+                         "for profiler runs")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB five times (calibrates HBM counters)")
+    ap.add_argument("--fwd-bwd-pairs", type=int, default=8,
+                    help="pairs of 512x256 in the forward+backward measurement (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py measures one GPU: this build has no multi-GPU path (pairs would shard across GPUs "
@@ -91,13 +99,21 @@ def main():
 
     results = {}
     other = "c2b" if args.op == "c2a" else "c2a"
-    for op in (args.op, other):
+    if args.copy_probe_mib > 0:
+        src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: 5 copies of {args.copy_probe_mib} MiB")
+        del src, dst
+    for op in ((args.op,) if args.headline_only else (args.op, other)):
         p = params(presets[op])
         d = DIS(p, W, H)
         out = torch.empty((2, H, W), device="cuda")
         flow = lambda: d.flow(I0, I1, out)
         modes = {}
-        for name, mode in (("phase", 1), ("persistent", 0)):
+        for name, mode in ((("phase", 1), ("persistent", 0)) if not args.headline_only else ()):
             d.set_tunables(None, 0, mode)
             modes[name] = time_calls(flow, args.steps, args.warmup) * 1e3
         flow()
@@ -115,8 +131,7 @@ def main():
         _lib.dis_profile_enable(d.handle, False)
         d.close()
         results[op] = dict(ms=dt * 1e3, modes=modes, flow=f_tuned, kernels=kstats)
-        log(f"[bench] {op}: tuned {dt * 1e3:.4f} ms/pair; phase-major {modes['phase']:.4f}, "
-            f"persistent {modes['persistent']:.4f}")
+        log(f"[bench] {op}: tuned {dt * 1e3:.4f} ms/pair; untuned {modes}")
 
     head = results[args.op]
     mpix = W * H / (head["ms"] * 1e-3) / 1e6
@@ -181,6 +196,86 @@ def main():
         d.close()
         log(f"[bench] batched: {bdt * 1e3:.3f} ms per {args.batch}-pair batch, {pix / bdt / 1e6:.0f} Mpix/s")
 
+    # forward + loss + backward: 8 pairs of 512x256 (smooth bumps up to 16 px,
+    # seeds 2000..2007), loss = mean end-point error against the ground truth,
+    # dL/dI0 and dL/dI1 through the hand-written adjoint (autograd Function);
+    # one handle per pair, so each pair's forward and backward replay their
+    # own HIP graphs
+    fwd_bwd = None
+    fb_check = None
+    if args.fwd_bwd_pairs > 0:
+        from paper_1603_03590_amd import dis_flow
+        nfb = args.fwd_bwd_pairs
+        fbp = [synth.smooth_bump_pair(512, 256, 16.0, 2000 + k) for k in range(nfb)]
+        pf = params(105, flags=_lib.DIS_FLAG_KEEP_FOR_BACKWARD)
+        # one handle and one HIP stream per pair: the pairs' launch chains
+        # are independent and run side by side on the GPU
+        streams = [torch.cuda.Stream() for _ in range(nfb)]
+        hs = [DIS(pf, 512, 256, stream=streams[k]) for k in range(nfb)]
+        fI0 = [torch.from_numpy(q.I0).cuda().requires_grad_(True) for q in fbp]
+        fI1 = [torch.from_numpy(q.I1).cuda().requires_grad_(True) for q in fbp]
+        fgt = [torch.from_numpy(q.flow).cuda() for q in fbp]
+        torch.cuda.synchronize()
+        losses = [None] * nfb
+
+        def fb_step():
+            for k in range(nfb):
+                with torch.cuda.stream(streams[k]):
+                    fI0[k].grad = None
+                    fI1[k].grad = None
+                    f = dis_flow(fI0[k], fI1[k], hs[k])
+                    L = torch.sqrt(((f - fgt[k]) ** 2).sum(0)).mean()
+                    L.backward()
+                    losses[k] = L
+
+        def f_step():
+            with torch.no_grad():
+                for k in range(nfb):
+                    with torch.cuda.stream(streams[k]):
+                        f = hs[k].flow(fI0[k].detach(), fI1[k].detach())
+                        losses[k] = torch.sqrt(((f - fgt[k]) ** 2).sum(0)).mean()
+
+        f_step()
+        for d_ in hs:
+            d_.autotune()
+        torch.cuda.synchronize()
+
+        fsteps = max(10, args.steps // 5)
+        t_fb = time_calls(fb_step, fsteps, max(3, args.warmup // 5))
+        t_f = time_calls(f_step, fsteps, max(3, args.warmup // 5))
+        # kernel time of the backward alone (events on the library's stream)
+        for d_ in hs:
+            _lib.dis_profile_enable(d_.handle, True)
+        fb_step()
+        for d_ in hs:
+            _lib.dis_profile_read(d_.handle)
+        for _ in range(3):
+            fb_step()
+        fb_k = {}
+        for d_ in hs:
+            for e in _lib.dis_profile_read(d_.handle):
+                acc = fb_k.setdefault(e["name"], dict(name=e["name"], launches=0, total_ms=0.0, bytes=0.0, flops=0.0))
+                for key in ("launches", "total_ms", "bytes", "flops"):
+                    acc[key] += e[key]
+            _lib.dis_profile_enable(d_.handle, False)
+        torch.cuda.synchronize()
+        fb_check = (fbp[0], fI0[0].grad.double().cpu().numpy(), fI1[0].grad.double().cpu().numpy(),
+                    float(losses[0]))
+        mean_epe = float(torch.stack([l.detach() for l in losses]).mean())
+        pix = nfb * 512 * 256
+        fwd_bwd = dict(value=pix / t_fb / 1e6, unit="Mpix/s", ms_per_step=t_fb * 1e3, pairs=nfb,
+                       forward_only=dict(value=pix / t_f / 1e6, ms_per_step=t_f * 1e3),
+                       mean_epe_px=mean_epe, dtype_io="f32", streams=nfb,
+                       kernels=kernel_table(list(fb_k.values()), 3),
+                       workload=f"{nfb} pairs 512x256 float32, smooth-bump generator (max 16 px, seeds "
+                                f"2000..{2000 + nfb - 1}); patch 8, overlap 0.5, scales 2..0 (3 clamped to the "
+                                f"patch), 16 GN iterations, theta_vo 3, theta_vi 5; loss = mean EPE vs ground truth; "
+                                f"step = forward + loss + backward of every pair, one HIP stream per pair")
+        for d_ in hs:
+            d_.close()
+        log(f"[bench] fwd+bwd: {t_fb * 1e3:.3f} ms per {nfb} pairs ({pix / t_fb / 1e6:.0f} Mpix/s); "
+            f"forward only {t_f * 1e3:.3f} ms")
+
     # parity of these runs and the CPU baseline (the FP64 oracle as it stands)
     parity = {}
     cpu = None
@@ -202,6 +297,18 @@ def main():
             for k in batched["_sample"]:
                 a, b, gt = bpairs[k]
                 check(f"batched_pair{k}", batched["_out"][k], a, b, gt, params(106))
+        if fb_check is not None:
+            q, g0, g1, L = fb_check
+            a = torch.from_numpy(q.I0).to(torch.float64).requires_grad_(True)
+            b = torch.from_numpy(q.I1).to(torch.float64).requires_grad_(True)
+            Lr = torch.sqrt(((O.dis_flow(a, b, oracle_params(params(105))) - torch.from_numpy(q.flow)) ** 2)
+                            .sum(0)).mean()
+            r0, r1 = torch.autograd.grad(Lr, (a, b))
+            rel = lambda x, y: float(np.abs(x - y).max() / np.abs(y).max())
+            parity["fwd_bwd_pair0"] = {"grad_I0_rel_max_err": rel(g0, r0.numpy()),
+                                       "grad_I1_rel_max_err": rel(g1, r1.numpy()),
+                                       "loss_rel_diff": abs(L / float(Lr) - 1.0),
+                                       "passed": bool(rel(g0, r0.numpy()) <= 1e-4 and rel(g1, r1.numpy()) <= 1e-4)}
         op_p = oracle_params(params(presets[args.op]))
         t0 = time.perf_counter()
         runs = 0
@@ -244,11 +351,12 @@ def main():
         "parity": parity,
         "kernels": kernel_table(head["kernels"], args.profile_steps),
         "untuned_ms_per_step": head["modes"],
-        "other_operating_point": {other: dict(ms_per_step=results[other]["ms"],
-                                              value=W * H / (results[other]["ms"] * 1e-3) / 1e6,
-                                              untuned_ms_per_step=results[other]["modes"])},
+        "other_operating_point": ({other: dict(ms_per_step=results[other]["ms"],
+                                               value=W * H / (results[other]["ms"] * 1e-3) / 1e6,
+                                               untuned_ms_per_step=results[other]["modes"])}
+                                  if other in results else None),
         "batched": batched,
-        "fwd_bwd": None,
+        "fwd_bwd": fwd_bwd,
     }
     print(json.dumps(line), flush=True)
 

@@ -163,9 +163,14 @@ int dis_autotune(dis_handle* h, const char* cache_path);
  * autotuner): lanes_per_patch[s] (HOST array of 16, or NULL = automatic for
  * every scale) is the number of lanes sharing one patch in the search on
  * scale s (0 = automatic, else 4, 8 or 16 where compiled for the patch size);
- * refine_tile picks the refinement tile of the per-phase launches (0: 32x16,
- * 1: 16x16, 2: 64x8); launch_mode 0 runs each scale as one persistent launch
- * over a task queue, 1 as one launch per phase.  Every choice gives
+ * refine_tile picks the refinement tile (core width x height, threads) of the
+ * per-phase launches: 0: 32x16/256, 1: 16x16/256, 2: 64x8/256,
+ * 3: 16x16/1024, 4: 32x16/1024, 5: 16x16/512, 6: 32x16/512, 7: 8x8/512,
+ * 8: 16x8/512, 9: 8x8/256.  launch_mode bit 0: 0 runs each scale as one
+ * persistent launch over a task queue, 1 as one launch per phase; bit 1 set
+ * turns on the single-workgroup path: a scale of at most 1024 horizontal
+ * pixel pairs is densified and refined, every fixed-point step, by one
+ * block instead of tiles.  Every choice gives
  * bitwise-identical flow.  Synchronises the stream and drops cached launch
  * plans.  Errors: DIS_EINVAL.
  */

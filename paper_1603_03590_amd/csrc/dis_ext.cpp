@@ -254,13 +254,10 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
     if (!h) return dis_fail(nullptr, DIS_EINVAL, "handle is NULL");
     if (h->last_call == 0) return dis_fail(h, DIS_ESTATE, "autotune replays the last forward call: none yet");
     struct Cand { int lpp, tile, mode; };
-    std::vector<Cand> cands;
-    const int lpps[4] = {0, 4, 8, 16};
-    for (int l : lpps) {
-        if (l && !dis_kernel_phase_search(h->p.patch_size, l)) continue;
-        cands.push_back(Cand{l, 0, 0});
-        for (int t = 0; t < 3; ++t) cands.push_back(Cand{l, t, 1});
-    }
+    // the search's lanes per patch and the refinement tile touch different
+    // kernels of a phase-major launch, so they are tuned one after the other;
+    // the persistent launch (fixed tile) is tried with every lane count
+    const int lpps[3] = {4, 8, 16};
     const int save_flags = (int)h->p.flags;
     h->p.flags &= ~DIS_FLAG_NO_GRAPH;   // time what callers run: graph replay
     auto replay = [&]() -> int {
@@ -288,25 +285,34 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
     XHIPCHK(h, hipEventCreate(&e0));
     XHIPCHK(h, hipEventCreate(&e1));
     double best = 1e30;
-    Cand bestc = cands[0];
+    Cand bestc{0, 0, 1};
     int r = DIS_OK;
-    for (const Cand& c : cands) {
+    auto measure = [&](const Cand& c) -> int {
         int lv[DIS_MAXL];
         for (int s = 0; s < DIS_MAXL; ++s) lv[s] = c.lpp;
-        r = dis_set_tunables(h, lv, c.tile, c.mode);
-        if (r != DIS_OK) break;
-        for (int i = 0; i < 3 && r == DIS_OK; ++i) { restore(); r = replay(); }
-        if (r != DIS_OK) break;
+        int rr = dis_set_tunables(h, lv, c.tile, c.mode);
+        if (rr != DIS_OK) return rr;
+        for (int i = 0; i < 3 && rr == DIS_OK; ++i) { restore(); rr = replay(); }
+        if (rr != DIS_OK) return rr;
         const int reps = 10;
         hipEventRecord(e0, h->stream);
-        for (int i = 0; i < reps && r == DIS_OK; ++i) { restore(); r = replay(); }
+        for (int i = 0; i < reps && rr == DIS_OK; ++i) { restore(); rr = replay(); }
         hipEventRecord(e1, h->stream);
-        if (r != DIS_OK) break;
+        if (rr != DIS_OK) return rr;
         hipEventSynchronize(e1);
         float ms = 0.f;
         hipEventElapsedTime(&ms, e0, e1);
         if (ms / reps < best) { best = ms / reps; bestc = c; }
-    }
+        return DIS_OK;
+    };
+    for (int t = 0; t < DIS_NUM_TILES && r == DIS_OK; ++t) r = measure(Cand{0, t, 1});
+    const int tile = bestc.tile;
+    for (int l : lpps)
+        if (r == DIS_OK && dis_kernel_phase_search(h->p.patch_size, l)) r = measure(Cand{l, tile, 1});
+    if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, 3});   // single-workgroup small scales
+    if (r == DIS_OK) r = measure(Cand{0, 0, 0});
+    for (int l : lpps)
+        if (r == DIS_OK && dis_kernel_level(h->p.patch_size, l)) r = measure(Cand{l, 0, 0});
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     h->p.flags = (uint32_t)save_flags;

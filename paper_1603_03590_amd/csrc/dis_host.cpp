@@ -227,7 +227,7 @@ extern "C" int dis_create(const dis_params* p, int max_w, int max_h, int max_bat
     while (top + 1 < DIS_MAXL && (max_w >> (top + 1)) >= p->patch_size && (max_h >> (top + 1)) >= p->patch_size) ++top;
     h->top = top;
     for (int s = 0; s < DIS_MAXL; ++s) h->lpp[s] = 0;
-    h->refine_tile = 0;
+    h->refine_tile = 7;   // 8x8 cores, 512 threads: the fastest on small scales
     h->slots.resize(max_batch);
     for (int i = 0; i < max_batch; ++i) {
         r = alloc_slot(h, h->slots[i]);
@@ -293,8 +293,9 @@ static void drop_plans(dis_handle* h) {
 extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int refine_tile, int launch_mode) {
     if (!h) return fail(nullptr, DIS_EINVAL, "handle is NULL");
     int tw, th;
-    if (!dis_refine_tile(refine_tile, &tw, &th)) return fail(h, DIS_EINVAL, "unknown refinement tile %d", refine_tile);
-    if (launch_mode != 0 && launch_mode != 1) return fail(h, DIS_EINVAL, "launch mode %d not 0 or 1", launch_mode);
+    if (!dis_refine_tile(refine_tile, &tw, &th, nullptr))
+        return fail(h, DIS_EINVAL, "unknown refinement tile %d", refine_tile);
+    if (launch_mode < 0 || launch_mode > 3) return fail(h, DIS_EINVAL, "launch mode %d outside 0..3", launch_mode);
     if (lanes_per_patch)
         for (int s = 0; s < DIS_MAXL; ++s) {
             const int l = lanes_per_patch[s];
@@ -304,7 +305,8 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     drop_plans(h);
     for (int s = 0; s < DIS_MAXL; ++s) h->lpp[s] = lanes_per_patch ? lanes_per_patch[s] : 0;
     h->refine_tile = refine_tile;
-    h->mode_phase = launch_mode;
+    h->mode_phase = launch_mode & 1;
+    h->small_levels = (launch_mode & 2) ? 1 : 0;
     return DIS_OK;
 }
 
@@ -487,20 +489,25 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     for (const PairRef& r : pairs) top = std::max(top, r.ss);
     const int mode = (opt && opt->force_phase) ? 1 : h->mode_phase;
     const int tile_id = mode ? h->refine_tile : DIS_LEVEL_TILE;
-    int tw = 32, th = 16;
-    dis_refine_tile(tile_id, &tw, &th);
+    int tw = 32, th = 16, nt = 256;
+    dis_refine_tile(tile_id, &tw, &th, &nt);
 
     struct LevelHost {
         std::vector<LevelPair> lp;
         std::vector<RefPhase> rph;
+        std::vector<int> small;     // pairs refined by one single-workgroup launch
+        std::vector<char> is_small;
+        int s;
         int lpp;
         int nph;
-        double by[2], fl[2];
+        double by[2], fl[2], sby, sfl;
     };
     std::vector<LevelHost> levels;
     for (int s = top; s >= sf; --s) {
         if (opt && opt->only_level >= 0 && s != opt->only_level) continue;
         LevelHost LH;
+        LH.s = s;
+        LH.sby = LH.sfl = 0.0;
         dis_refine_phases(p, s, LH.rph);
         if (!p.refine) LH.rph.clear();
         LH.nph = 2 + (int)LH.rph.size();
@@ -548,13 +555,24 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             ra.omega = p.sor_omega; ra.eps = 1e-3;
             for (int q = 0; q < 3; ++q) P.dU[q] = sb.dU[q];
             P.dens_bx = (W + 63) / 64;
+            const bool small = p.refine && h->small_levels && ((W + 1) / 2) * Hh <= DIS_SMALL_PAIRS;
+            if (small) LH.small.push_back((int)LH.lp.size());
+            LH.is_small.push_back(small ? 1 : 0);
             LH.lp.push_back(P);
             const double px = (double)W * Hh;
             const double pxn = s < r.ss ? (double)(r.w >> (s + 1)) * (r.h >> (s + 1)) : 0.0;
             LH.by[0] += search_bytes(px, pxn, N);
             LH.fl[0] += search_flops(N, (double)ps * ps, p.gn_iters);
-            LH.by[1] += densify_bytes(px, N, p.refine);
-            LH.fl[1] += densify_flops(px, std::pow((double)ps / g.st, 2.0), p.refine);
+            const double dby = densify_bytes(px, N, p.refine);
+            const double dfl = densify_flops(px, std::pow((double)ps / g.st, 2.0), p.refine);
+            if (small) {
+                const int nout = p.var_outer < 0 ? s + 1 : p.var_outer;
+                LH.sby += dby + 16.0 * px;
+                LH.sfl += dfl + nout * refine_flops(px, 2 * p.var_inner);
+            } else {
+                LH.by[1] += dby;
+                LH.fl[1] += dfl;
+            }
         }
         levels.push_back(std::move(LH));
     }
@@ -562,7 +580,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     // device tables for every level, one allocation
     size_t bytes = 0;
     int nsync = 0;
-    std::vector<size_t> off_lp, off_rph, off_start;
+    std::vector<size_t> off_lp, off_rph, off_start, off_small;
     std::vector<int> off_sync;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     for (LevelHost& LH : levels) {
@@ -573,6 +591,8 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         bytes = al(bytes + sizeof(RefPhase) * std::max<size_t>(1, LH.rph.size()));
         off_start.push_back(bytes);
         bytes = al(bytes + sizeof(int) * (nseg + 1));
+        off_small.push_back(bytes);
+        bytes = al(bytes + sizeof(int) * std::max<size_t>(1, LH.small.size()));
         off_sync.push_back(nsync);
         tabs.err_index.push_back(nsync + 1);
         nsync += 2 + nseg;
@@ -589,6 +609,8 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         const int np = (int)LH.lp.size(), nseg = LH.nph * np;
         std::memcpy(host.data() + off_lp[li], LH.lp.data(), sizeof(LevelPair) * np);
         if (!LH.rph.empty()) std::memcpy(host.data() + off_rph[li], LH.rph.data(), sizeof(RefPhase) * LH.rph.size());
+        if (!LH.small.empty())
+            std::memcpy(host.data() + off_small[li], LH.small.data(), sizeof(int) * LH.small.size());
         // queue segments, phase-major: search blocks, densification blocks,
         // then the refinement phases, each over all pairs
         std::vector<int> start(nseg + 1, 0);
@@ -602,6 +624,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
                 start[ph * np + j] = t;
                 int cnt;
                 if (ph == 0) cnt = (P.sa.nx * P.sa.ny * LH.lpp + 255) / 256;
+                else if (LH.is_small[j]) cnt = 0;   // densified and refined by the single-workgroup launch
                 else if (ph == 1) cnt = P.dens_bx * ((P.da.H + 3) / 4);
                 else {
                     cnt = P.ra.tiles_x * ((P.ra.H + th - 1) / th);
@@ -636,6 +659,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             if (!fs) return fail(h, DIS_EINVAL, "no search kernel for patch %d, %d lanes", ps, LH.lpp);
             for (int ph = 0; ph < LH.nph; ++ph) {
                 const int n = start[(ph + 1) * np] - start[ph * np];
+                if (n == 0) continue;
                 if (ph == 0) {
                     if (opt && opt->skip_search) continue;
                     seq.add(fs, dim3(n), dim3(256), &LL, sizeof LL, 0, "search", ph_by[0], ph_fl[0]);
@@ -647,10 +671,21 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
                     std::memset(&PL, 0, sizeof PL);
                     PL.L = LL;
                     PL.phase = ph;
-                    seq.add(dis_kernel_phase_refine(tile_id), dim3(n), dim3(256), &PL, sizeof PL, 0, "refine",
+                    seq.add(dis_kernel_phase_refine(tile_id), dim3(n), dim3(nt), &PL, sizeof PL, 0, "refine",
                             ph_by[ph], ph_fl[ph]);
                 }
             }
+        }
+        if (!LH.small.empty()) {
+            SmallLaunch SL;
+            std::memset(&SL, 0, sizeof SL);
+            SL.pairs = LL.pairs;
+            SL.list = (const int*)((char*)tabs.mem + off_small[li]);
+            SL.n = (int)LH.small.size();
+            SL.nouter = p.var_outer < 0 ? LH.s + 1 : p.var_outer;
+            SL.nhalf = 2 * p.var_inner;
+            seq.add(dis_kernel_small_level(), dim3(SL.n), dim3(DIS_SMALL_THREADS), &SL, sizeof SL, 0, "small_level", LH.sby,
+                    LH.sfl);
         }
     }
     HIPCHK(h, hipMemcpy(tabs.mem, host.data(), bytes, hipMemcpyHostToDevice));

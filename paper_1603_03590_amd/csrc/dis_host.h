@@ -123,8 +123,9 @@ struct dis_handle {
     std::map<std::tuple<int, int, int>, Plan*> plans;
     std::map<std::vector<int>, BatchPlan*> bplans;
     int lpp[DIS_MAXL];
-    int refine_tile = 0;
+    int refine_tile = 7;
     int mode_phase = 1;     // 1: one launch per phase, 0: one persistent launch per level
+    int small_levels = 0;   // refine pair-levels that fit one workgroup in a single launch
     int n_cu = 256;
     // most recent plain forward call (debug and backward)
     bool have_last = false;

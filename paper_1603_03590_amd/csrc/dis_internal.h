@@ -122,6 +122,20 @@ struct PhaseLaunch {
     int phase;
 };
 
+// Pair-levels small enough for one workgroup's LDS (at most DIS_SMALL_PAIRS
+// horizontal pixel pairs): densification and every refinement step of the
+// level in one block, without tiles.  Block b handles pairs[list[b]].
+#define DIS_SMALL_PAIRS 1024
+#define DIS_SMALL_PX 2112      // LDS plane capacity (pixels) of that block
+#define DIS_SMALL_THREADS 1024 // threads of that block (one pixel pair each)
+struct SmallLaunch {
+    const LevelPair* pairs;
+    const int* list;
+    int n;
+    int nouter;             // fixed-point steps of the level
+    int nhalf;              // red-black half sweeps per step
+};
+
 // Table-driven multi-pair launches of the pyramid and the upscaling: entry
 // j covers blocks start[j] .. start[j+1]-1.
 struct PyrTab {
@@ -146,6 +160,9 @@ const void* dis_kernel_upsample_tab();
 const void* dis_kernel_phase_search(int ps, int lpp);   // null when not compiled
 const void* dis_kernel_phase_densify();
 const void* dis_kernel_phase_refine(int tile);          // tile id, see dis_refine_tile
+const void* dis_kernel_small_level();                  // SmallLaunch, DIS_SMALL_THREADS threads
 const void* dis_kernel_level(int ps, int lpp);          // persistent level kernel, null when not compiled
-// refinement core tile (width, height) of a tile id; returns 0 for an unknown id
-int dis_refine_tile(int tile, int* tw, int* th);
+// refinement core tile (width, height, threads per block) of a tile id;
+// returns 0 for an unknown id
+int dis_refine_tile(int tile, int* tw, int* th, int* nt);
+#define DIS_NUM_TILES 10

@@ -300,17 +300,17 @@ __device__ __forceinline__ void cover_range(int x, int n, int ps, int st, int nr
 // ascending patch index, weight each displacement by 1 / max(1, |d_i(x)|)
 // with d_i the mean-normalised residual at that patch's displacement; then
 // the second frame warped by the dense flow, for the refinement.
-__device__ __forceinline__ void densify_block(const DensifyArgs& a, int bx, int by) {
-    const int x = bx * 64 + (threadIdx.x & 63);
-    const int y = by * 4 + (threadIdx.x >> 6);
+// Eq. (3) at pixel (x, y): the displacement average U, V and the weight sum.
+__device__ __forceinline__ void densify_pixel(const DensifyArgs& a, int x, int y, double& U, double& V,
+                                              double& sw) {
     const int W = a.W, H = a.H;
-    if (x >= W || y >= H) return;
     int kx0, kx1, ky0, ky1;
     bool fx, fy;
     cover_range(x, W, a.ps, a.st, a.nrx, a.nx, kx0, kx1, fx);
     cover_range(y, H, a.ps, a.st, a.nry, a.ny, ky0, ky1, fy);
     const double j0 = a.J0[y * W + x];
-    double su = 0.0, sv = 0.0, sw = 0.0;
+    double su = 0.0, sv = 0.0;
+    sw = 0.0;
     const int kyend = ky1 + (fy ? 1 : 0), kxend = kx1 + (fx ? 1 : 0);
     for (int jy = ky0; jy <= kyend; ++jy) {
         const int ky = jy <= ky1 ? jy : a.nry;
@@ -326,7 +326,21 @@ __device__ __forceinline__ void densify_block(const DensifyArgs& a, int bx, int 
             sw = sw + wgt;
         }
     }
-    const double U = su / sw, V = sv / sw;
+    U = su / sw;
+    V = sv / sw;
+}
+
+// Eq. (3) on a 64x4 block: per pixel, gather the covering patches in
+// ascending patch index, weight each displacement by 1 / max(1, |d_i(x)|)
+// with d_i the mean-normalised residual at that patch's displacement; then
+// the second frame warped by the dense flow, for the refinement.
+__device__ __forceinline__ void densify_block(const DensifyArgs& a, int bx, int by) {
+    const int x = bx * 64 + (threadIdx.x & 63);
+    const int y = by * 4 + (threadIdx.x >> 6);
+    const int W = a.W, H = a.H;
+    if (x >= W || y >= H) return;
+    double U, V, sw;
+    densify_pixel(a, x, y, U, V, sw);
     const int g = y * W + x;
     if (a.Z) a.Z[g] = sw;
     a.U[g] = U;
@@ -338,8 +352,9 @@ __device__ __forceinline__ void densify_block(const DensifyArgs& a, int bx, int 
 
 // LDS of one refinement tile: the core (TW x TH) grows by up to K = DIS_KMAX
 // pixels per side (the region); the image tile grows by 2 more for the
-// second differences.  The increments share storage with the image tile,
-// which is dead by the time they are loaded.
+// second differences.  The edge-weight planes first hold U + dUf (one more
+// row and column, for the forward differences of E_S); the increments share
+// storage with the image tile, which is dead by the time they are stored.
 template <int TW, int TH>
 struct RefineSmem {
     static constexpr int K = DIS_KMAX;
@@ -347,10 +362,11 @@ struct RefineSmem {
     static constexpr int LP = RWM + 1;               // region row pitch
     static constexpr int IWM = RWM + 4, IHM = RHM + 4;
     static constexpr int IP = IWM + 1;               // image-tile row pitch
-    double wr[RHM * LP];                            // weight of the edge to the right
-    double wd[RHM * LP];                            // weight of the edge below
+    double wr[(RHM + 1) * LP];                      // U + dUf (u), then the weight of the edge to the right
+    double wd[(RHM + 1) * LP];                      // U + dUf (v), then the weight of the edge below
+    double uu[RHM * LP], uv[RHM * LP];              // U on the region
     union {
-        struct { double t0[IHM * IP], t1[IHM * IP]; } img;   // J0 / J1w, first U+dUf
+        struct { double t0[IHM * IP], t1[IHM * IP]; } img;   // J0 / J1w
         struct { double du[RHM * LP], dv[RHM * LP]; } inc;
     } u;
 };
@@ -359,15 +375,19 @@ struct RefineSmem {
 // is extended by nhalf pixels on every side that is not the image border;
 // the sweeps run on that region in LDS, where an update can be wrong only at
 // distance < j from a cut side after j half sweeps, so after nhalf half
-// sweeps the core equals the untiled result exactly.  Each thread owns pairs
-// of horizontally adjacent pixels (one of each colour) and keeps their SOR
-// coefficients in registers; LDS holds the increments and the edge weights.
-template <int TW, int TH>
+// sweeps the core equals the untiled result exactly.  Each of the NT threads
+// owns pairs of horizontally adjacent pixels (one of each colour) and keeps
+// their SOR coefficients in registers; LDS holds the increments, the edge
+// weights and U.  Every global read is issued in one round at the start
+// (with few pairs per thread, the frozen and starting increments of the
+// owned pixels go straight to registers).
+template <int TW, int TH, int NT>
 __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, RefineSmem<TW, TH>& sm) {
     using S = RefineSmem<TW, TH>;
     constexpr int LP = S::LP, IP = S::IP;
     constexpr int PWM = (S::RWM + 1) / 2;
-    constexpr int PPT = (PWM * S::RHM + 255) / 256;
+    constexpr int PPT = (PWM * S::RHM + NT - 1) / NT;
+    constexpr bool kStage = PPT <= 2 && NT <= 512;   // register budget of 1024-thread blocks
 
     const int W = a.W, H = a.H;
     const size_t n = (size_t)W * H;
@@ -378,52 +398,58 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
     const int rx0 = max(cx0 - kh, 0), ry0 = max(cy0 - kh, 0);
     const int rx1 = min(cx1 + kh, W), ry1 = min(cy1 + kh, H);
     const int RW = rx1 - rx0, RH = ry1 - ry0;
+    const int npw = (RW + 1) / 2;
     const double* __restrict__ U = a.U;
     const double* __restrict__ F = a.dUf;
+    const double* __restrict__ Din = a.dUin;
 
-    // 1. full flow U + dUf on the region plus one column / row, for E_S
+    // owned pixels: pair pr = thread + k NT, row ly, pair m of the row; the
+    // pixel of colour c sits at column 2m + ((rx0 + y) & 1) ^ c
+    int c_l[PPT][2];
+    double s_fu[kStage ? PPT : 1][2], s_fv[kStage ? PPT : 1][2];
+    double s_iu[kStage ? PPT : 1][2], s_iv[kStage ? PPT : 1][2];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int pr = threadIdx.x + k * NT;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            c_l[k][c] = -1;
+            if constexpr (kStage) { s_fu[k][c] = s_fv[k][c] = s_iu[k][c] = s_iv[k][c] = 0.0; }
+            if (pr >= npw * RH) continue;
+            const int ly = pr / npw, m = pr - ly * npw;
+            const int lx = 2 * m + (((rx0 + ry0 + ly) & 1) ^ c);
+            if (lx >= RW) continue;
+            c_l[k][c] = ly * LP + lx;
+            if constexpr (kStage) {
+                const size_t g = (size_t)(ry0 + ly) * W + rx0 + lx;
+                if (F) { s_fu[k][c] = F[g]; s_fv[k][c] = F[n + g]; }
+                if (Din) { s_iu[k][c] = Din[g]; s_iv[k][c] = Din[n + g]; }
+            }
+        }
+    }
+
+    // 1. U + dUf on the region plus one column / row (into wr / wd), U on
+    //    the region, J0 and the warped J1w on the region plus two pixels
+    const int ix0 = max(rx0 - 2, 0), iy0 = max(ry0 - 2, 0);
     {
         const int ex1 = min(rx1 + 1, W), ey1 = min(ry1 + 1, H);
         const int EW = ex1 - rx0, EH = ey1 - ry0;
-        double* tu = sm.u.img.t0;
-        double* tv = sm.u.img.t1;
-#pragma unroll 4
-        for (int i = threadIdx.x; i < EW * EH; i += 256) {
+#pragma unroll 2
+        for (int i = threadIdx.x; i < EW * EH; i += NT) {
             const int ly = i / EW, lx = i - ly * EW;
             const size_t g = (size_t)(ry0 + ly) * W + rx0 + lx;
-            tu[ly * IP + lx] = F ? U[g] + F[g] : U[g];
-            tv[ly * IP + lx] = F ? U[n + g] + F[n + g] : U[n + g];
+            const double u0 = U[g], v0 = U[n + g];
+            sm.wr[ly * LP + lx] = F ? u0 + F[g] : u0;
+            sm.wd[ly * LP + lx] = F ? v0 + F[n + g] : v0;
+            if (lx < RW && ly < RH) {
+                sm.uu[ly * LP + lx] = u0;
+                sm.uv[ly * LP + lx] = v0;
+            }
         }
-    }
-    __syncthreads();
-    // 2. smoothness weight alpha / (2 sqrt(E_S + eps^2)) of every region pixel,
-    //    from forward differences (zero across the last column / row)
-    {
-        const double* tu = sm.u.img.t0;
-        const double* tv = sm.u.img.t1;
-        const double eps2 = a.eps * a.eps;
-        for (int i = threadIdx.x; i < RW * RH; i += 256) {
-            const int ly = i / RW, lx = i - ly * RW;
-            const int x = rx0 + lx, y = ry0 + ly;
-            const int e = ly * IP + lx;
-            const double u0 = tu[e], v0 = tv[e];
-            double dxu = 0.0, dyu = 0.0, dxv = 0.0, dyv = 0.0;
-            if (x < W - 1) { dxu = tu[e + 1] - u0; dxv = tv[e + 1] - v0; }
-            if (y < H - 1) { dyu = tu[e + IP] - u0; dyv = tv[e + IP] - v0; }
-            const double es = ((dxu * dxu + dyu * dyu) + dxv * dxv) + dyv * dyv;
-            const double ws = a.alpha / (2.0 * sqrt(es + eps2));
-            sm.wr[ly * LP + lx] = x < W - 1 ? ws : 0.0;
-            sm.wd[ly * LP + lx] = y < H - 1 ? ws : 0.0;
-        }
-    }
-    __syncthreads();
-    // 3. J0 and the warped J1w on the region plus two pixels
-    const int ix0 = max(rx0 - 2, 0), iy0 = max(ry0 - 2, 0);
-    {
         const int ix1 = min(rx1 + 2, W), iy1 = min(ry1 + 2, H);
         const int IW = ix1 - ix0, IH = iy1 - iy0;
-#pragma unroll 4
-        for (int i = threadIdx.x; i < IW * IH; i += 256) {
+#pragma unroll 2
+        for (int i = threadIdx.x; i < IW * IH; i += NT) {
             const int ly = i / IW, lx = i - ly * IW;
             const size_t g = (size_t)(iy0 + ly) * W + ix0 + lx;
             sm.u.img.t0[ly * IP + lx] = a.J0[g];
@@ -431,14 +457,46 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
         }
     }
     __syncthreads();
+    // 2. smoothness weight alpha / (2 sqrt(E_S + eps^2)) of every owned
+    //    pixel, from forward differences (zero across the last column / row)
+    const double eps2 = a.eps * a.eps;
+    double c_ws[PPT][2];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            c_ws[k][c] = 0.0;
+            const int e = c_l[k][c];
+            if (e < 0) continue;
+            const int ly = e / LP, lx = e - ly * LP;
+            const int x = rx0 + lx, y = ry0 + ly;
+            const double u0 = sm.wr[e], v0 = sm.wd[e];
+            double dxu = 0.0, dyu = 0.0, dxv = 0.0, dyv = 0.0;
+            if (x < W - 1) { dxu = sm.wr[e + 1] - u0; dxv = sm.wd[e + 1] - v0; }
+            if (y < H - 1) { dyu = sm.wr[e + LP] - u0; dyv = sm.wd[e + LP] - v0; }
+            const double es = ((dxu * dxu + dyu * dyu) + dxv * dxv) + dyv * dyv;
+            c_ws[k][c] = a.alpha / (2.0 * sqrt(es + eps2));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int e = c_l[k][c];
+            if (e < 0) continue;
+            const int ly = e / LP, lx = e - ly * LP;
+            sm.wr[e] = rx0 + lx < W - 1 ? c_ws[k][c] : 0.0;
+            sm.wd[e] = ry0 + ly < H - 1 ? c_ws[k][c] : 0.0;
+        }
+    }
+    __syncthreads();
 
-    // 4. per owned pixel: linearisation (central differences [-1 0 1]/2 with
+    // 3. per owned pixel: linearisation (central differences [-1 0 1]/2 with
     //    replicated borders of (J0+J1w)/2 and of J1w - J0, the normalisations
     //    beta), robust data weights at the frozen increment, SOR coefficients
     const double om = a.omega, om1 = 1.0 - a.omega;
-    const double eps2 = a.eps * a.eps;
-    const int npw = (RW + 1) / 2;
-    int c_l[PPT][2], c_m[PPT][2];
+    int c_m[PPT][2];
     double c_wr[PPT][2], c_wl[PPT][2], c_wd[PPT][2], c_wu[PPT][2];
     double c_a12[PPT][2], c_i1[PPT][2], c_i2[PPT][2], c_c1[PPT][2], c_c2[PPT][2];
     {
@@ -455,21 +513,16 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
         };
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            const int pr = threadIdx.x + k * 256;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                c_l[k][c] = -1;
                 c_m[k][c] = 0;
                 c_wr[k][c] = c_wl[k][c] = c_wd[k][c] = c_wu[k][c] = 0.0;
                 c_a12[k][c] = c_i1[k][c] = c_i2[k][c] = c_c1[k][c] = c_c2[k][c] = 0.0;
-                if (pr >= npw * RH) continue;
-                const int ly = pr / npw, m = pr - ly * npw;
-                const int y = ry0 + ly;
-                const int lx = 2 * m + (((rx0 + y) & 1) ^ c);
-                if (lx >= RW) continue;
-                const int x = rx0 + lx;
+                const int l = c_l[k][c];
+                if (l < 0) continue;
+                const int ly = l / LP, lx = l - ly * LP;
+                const int x = rx0 + lx, y = ry0 + ly;
                 const size_t g = (size_t)y * W + x;
-                const int l = ly * LP + lx;
                 const int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
                 const int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
                 const double Ix = Ixa(x, y), Iy = Iya(x, y);
@@ -484,7 +537,9 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
                 const double b0 = 1.0 / ((Ix * Ix + Iy * Iy) + 0.01);
                 const double bx = 1.0 / ((Ixx * Ixx + Ixy * Ixy) + 0.01);
                 const double by = 1.0 / ((Ixy * Ixy + Iyy * Iyy) + 0.01);
-                const double fu = F ? F[g] : 0.0, fv = F ? F[n + g] : 0.0;
+                double fu, fv;
+                if constexpr (kStage) { fu = s_fu[k][c]; fv = s_fv[k][c]; }
+                else { fu = F ? F[g] : 0.0; fv = F ? F[n + g] : 0.0; }
                 const double ri = (Ix * fu + Iy * fv) + Iz;
                 const double ei = b0 * (ri * ri);
                 const double rx = (Ixx * fu + Ixy * fv) + Ixz;
@@ -505,14 +560,13 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
                 const double wr = hr ? sm.wr[l] : 0.0, wl = hl ? sm.wr[l - 1] : 0.0;
                 const double wd = hd ? sm.wd[l] : 0.0, wu = hu ? sm.wd[l - LP] : 0.0;
                 const double Ssum = ((wr + wl) + wd) + wu;
-                const double Up = U[g], Vp = U[n + g];
-                const double Ur = hr ? U[g + 1] : 0.0, Ul = hl ? U[g - 1] : 0.0;
-                const double Ud = hd ? U[g + W] : 0.0, Uu = hu ? U[g - W] : 0.0;
-                const double Vr = hr ? U[n + g + 1] : 0.0, Vl = hl ? U[n + g - 1] : 0.0;
-                const double Vd = hd ? U[n + g + W] : 0.0, Vu = hu ? U[n + g - W] : 0.0;
+                const double Up = sm.uu[l], Vp = sm.uv[l];
+                const double Ur = hr ? sm.uu[l + 1] : 0.0, Ul = hl ? sm.uu[l - 1] : 0.0;
+                const double Ud = hd ? sm.uu[l + LP] : 0.0, Uu = hu ? sm.uu[l - LP] : 0.0;
+                const double Vr = hr ? sm.uv[l + 1] : 0.0, Vl = hl ? sm.uv[l - 1] : 0.0;
+                const double Vd = hd ? sm.uv[l + LP] : 0.0, Vu = hu ? sm.uv[l - LP] : 0.0;
                 const double NU = ((wr * Ur + wl * Ul) + wd * Ud) + wu * Uu;
                 const double NV = ((wr * Vr + wl * Vl) + wd * Vd) + wu * Vu;
-                c_l[k][c] = l;
                 c_m[k][c] = (hr ? 1 : 0) | (hl ? 2 : 0) | (hd ? 4 : 0) | (hu ? 8 : 0);
                 c_wr[k][c] = wr; c_wl[k][c] = wl; c_wd[k][c] = wd; c_wu[k][c] = wu;
                 c_a12[k][c] = A12;
@@ -524,22 +578,32 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
         }
     }
     __syncthreads();   // the image tile is dead from here on
-    // 5. sweep start
-    {
-        const double* __restrict__ Din = a.dUin;
+    // 4. sweep start
+    double* du_ = sm.u.inc.du;
+    double* dv_ = sm.u.inc.dv;
+    if constexpr (kStage) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int l = c_l[k][c];
+                if (l < 0) continue;
+                du_[l] = s_iu[k][c];
+                dv_[l] = s_iv[k][c];
+            }
+        }
+    } else {
 #pragma unroll 4
-        for (int i = threadIdx.x; i < RW * RH; i += 256) {
+        for (int i = threadIdx.x; i < RW * RH; i += NT) {
             const int ly = i / RW, lx = i - ly * RW;
             const size_t g = (size_t)(ry0 + ly) * W + rx0 + lx;
-            sm.u.inc.du[ly * LP + lx] = Din ? Din[g] : 0.0;
-            sm.u.inc.dv[ly * LP + lx] = Din ? Din[n + g] : 0.0;
+            du_[ly * LP + lx] = Din ? Din[g] : 0.0;
+            dv_[ly * LP + lx] = Din ? Din[n + g] : 0.0;
         }
     }
     __syncthreads();
 
-    // 6. red-black half sweeps: colour 0 = (x + y) even, first
-    double* du_ = sm.u.inc.du;
-    double* dv_ = sm.u.inc.dv;
+    // 5. red-black half sweeps: colour 0 = (x + y) even, first
     for (int j = 0; j < kh; j += 2) {
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -566,7 +630,7 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
                 // the level is the core of exactly one tile)
                 double* tp = a.tape + (size_t)(a.tape_m0 + j + c + 1) * 2 * n;
                 const int CW = cx1 - cx0, CH = cy1 - cy0;
-                for (int i = threadIdx.x; i < CW * CH; i += 256) {
+                for (int i = threadIdx.x; i < CW * CH; i += NT) {
                     const int yy = i / CW, xx = i - yy * CW;
                     const size_t g = (size_t)(cy0 + yy) * W + cx0 + xx;
                     const int l = (cy0 + yy - ry0) * LP + (cx0 + xx - rx0);
@@ -578,9 +642,9 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
         }
     }
 
-    // 7. the core: increment, and the refined flow after the last step
+    // 6. the core: increment, and the refined flow after the last step
     const int CW = cx1 - cx0, CH = cy1 - cy0;
-    for (int i = threadIdx.x; i < CW * CH; i += 256) {
+    for (int i = threadIdx.x; i < CW * CH; i += NT) {
         const int yy = i / CW, xx = i - yy * CW;
         const int x = cx0 + xx, y = cy0 + yy;
         const size_t g = (size_t)y * W + x;
@@ -589,8 +653,8 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
         a.dUout[g] = du;
         a.dUout[n + g] = dv;
         if (a.Uout) {
-            a.Uout[g] = U[g] + du;
-            a.Uout[n + g] = U[n + g] + dv;
+            a.Uout[g] = sm.uu[l] + du;
+            a.Uout[n + g] = sm.uv[l] + dv;
         }
     }
     __syncthreads();   // LDS is reused by the caller's next tile
@@ -615,8 +679,8 @@ __global__ __launch_bounds__(256) void k_phase_densify(const LevelLaunch L) {
     densify_block(P.da, local % P.dens_bx, local / P.dens_bx);
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(256) void k_phase_refine(const PhaseLaunch PL) {
+template <int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
     __shared__ RefineSmem<TW, TH> sm;
     const LevelLaunch& L = PL.L;
     const int phase = PL.phase;
@@ -632,7 +696,7 @@ __global__ __launch_bounds__(256) void k_phase_refine(const PhaseLaunch PL) {
     ra.Uout = rp.last ? P.ra.Uout : nullptr;
     ra.nhalf = rp.nhalf;
     ra.tape_m0 = rp.m0;
-    refine_tile<TW, TH>(ra, t - __builtin_amdgcn_readfirstlane(L.start[s0 + j]), sm);
+    refine_tile<TW, TH, NT>(ra, t - __builtin_amdgcn_readfirstlane(L.start[s0 + j]), sm);
 }
 
 // ----------------------------------------------------------------- upscale
@@ -676,6 +740,227 @@ __global__ __launch_bounds__(256) void k_upsample_tab(const UpsTab T) {
 // flags the launch as failed and moves on; with the queue's ordering a wait
 // always ends long before that.
 constexpr int kSpinLimit = 1 << 21;
+
+// A whole pair-level in one 1024-thread block (Sec. 2.2 step 3 and Sec. 2.3
+// for levels of at most DIS_SMALL_PAIRS pixel pairs): densification into
+// LDS, then every fixed-point step with its red-black sweeps on the whole
+// level, no tiles and no halo.  Each thread owns one horizontal pixel pair
+// (one pixel of each colour), as in the tiled kernel, and does the same
+// arithmetic in the same order, so the result is the tiled one bit for bit.
+struct SmallSmem {
+    double J0[DIS_SMALL_PX], J1w[DIS_SMALL_PX];
+    double uu[DIS_SMALL_PX], uv[DIS_SMALL_PX];
+    double du[DIS_SMALL_PX], dv[DIS_SMALL_PX];
+    double wr[DIS_SMALL_PX], wd[DIS_SMALL_PX];
+};
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_small_level(const SmallLaunch S) {
+    constexpr int PPT = DIS_SMALL_PAIRS / NT;
+    __shared__ SmallSmem sm;
+    const int j = __builtin_amdgcn_readfirstlane(S.list[blockIdx.x]);
+    const LevelPair& P = S.pairs[j];
+    const DensifyArgs& da = P.da;
+    const RefineArgs& a = P.ra;
+    const int W = a.W, H = a.H;
+    const int npx = W * H;
+    const size_t n = (size_t)npx;
+
+    // 1. densification, the warped second frame, J0
+    for (int i = threadIdx.x; i < npx; i += NT) {
+        const int y = i / W, x = i - y * W;
+        double U, V, sw;
+        densify_pixel(da, x, y, U, V, sw);
+        const double jw = bilin(da.J1, W, H, (double)x + U, (double)y + V);
+        if (da.Z) da.Z[i] = sw;
+        da.U[i] = U;
+        da.U[n + i] = V;
+        da.J1w[i] = jw;
+        sm.uu[i] = U;
+        sm.uv[i] = V;
+        sm.J1w[i] = jw;
+        sm.J0[i] = a.J0[i];
+        sm.du[i] = 0.0;
+        sm.dv[i] = 0.0;
+    }
+    __syncthreads();
+
+    // owned pairs pr = thread + k NT: row ly, pair m; colour c at column
+    // 2m + ((y & 1) ^ c)
+    const int npw = (W + 1) / 2;
+    int c_l[PPT][2];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int pr = threadIdx.x + k * NT;
+        const int ly = pr / npw, m = pr - ly * npw;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int lx = 2 * m + ((ly & 1) ^ c);
+            c_l[k][c] = (pr < npw * H && lx < W) ? ly * W + lx : -1;
+        }
+    }
+    const double om = a.omega, om1 = 1.0 - a.omega;
+    const double eps2 = a.eps * a.eps;
+    const int nouter = __builtin_amdgcn_readfirstlane(S.nouter);
+    const int nhalf = __builtin_amdgcn_readfirstlane(S.nhalf);
+    auto Ib = [&](int x, int y) { const int l = y * W + x; return 0.5 * (sm.J0[l] + sm.J1w[l]); };
+    auto Ixa = [&](int x, int y) { return (Ib(min(x + 1, W - 1), y) - Ib(max(x - 1, 0), y)) / 2.0; };
+    auto Iya = [&](int x, int y) { return (Ib(x, min(y + 1, H - 1)) - Ib(x, max(y - 1, 0))) / 2.0; };
+
+    for (int it = 0; it < nouter; ++it) {
+        // the owned positions, re-derived each step: otherwise the compiler
+        // hoists every neighbour address of the step out of the loop and
+        // spills them (an empty asm makes the copy opaque)
+        int cl[PPT][2];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                int v = c_l[k][c];
+                __asm__ volatile("" : "+v"(v));
+                cl[k][c] = v;
+            }
+        // 2. smoothness weights from U + dU (the frozen increment is the
+        //    current one: the whole level is here)
+        double c_ws[PPT][2];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                c_ws[k][c] = 0.0;
+                const int e = cl[k][c];
+                if (e < 0) continue;
+                const int y = e / W, x = e - y * W;
+                const double u0 = sm.uu[e] + sm.du[e], v0 = sm.uv[e] + sm.dv[e];
+                double dxu = 0.0, dyu = 0.0, dxv = 0.0, dyv = 0.0;
+                if (x < W - 1) {
+                    dxu = (sm.uu[e + 1] + sm.du[e + 1]) - u0;
+                    dxv = (sm.uv[e + 1] + sm.dv[e + 1]) - v0;
+                }
+                if (y < H - 1) {
+                    dyu = (sm.uu[e + W] + sm.du[e + W]) - u0;
+                    dyv = (sm.uv[e + W] + sm.dv[e + W]) - v0;
+                }
+                const double es = ((dxu * dxu + dyu * dyu) + dxv * dxv) + dyv * dyv;
+                c_ws[k][c] = a.alpha / (2.0 * sqrt(es + eps2));
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int e = cl[k][c];
+                if (e < 0) continue;
+                const int y = e / W, x = e - y * W;
+                sm.wr[e] = x < W - 1 ? c_ws[k][c] : 0.0;
+                sm.wd[e] = y < H - 1 ? c_ws[k][c] : 0.0;
+            }
+        }
+        __syncthreads();
+        // 3. coefficients of the owned pixels
+        int c_m[PPT][2];
+        double c_wr[PPT][2], c_wl[PPT][2], c_wd[PPT][2], c_wu[PPT][2];
+        double c_a12[PPT][2], c_i1[PPT][2], c_i2[PPT][2], c_c1[PPT][2], c_c2[PPT][2];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                c_m[k][c] = 0;
+                c_wr[k][c] = c_wl[k][c] = c_wd[k][c] = c_wu[k][c] = 0.0;
+                c_a12[k][c] = c_i1[k][c] = c_i2[k][c] = c_c1[k][c] = c_c2[k][c] = 0.0;
+                const int l = cl[k][c];
+                if (l < 0) continue;
+                const int y = l / W, x = l - y * W;
+                const int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
+                const int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
+                const double* t0 = sm.J0;
+                const double* t1 = sm.J1w;
+                const double Ix = Ixa(x, y), Iy = Iya(x, y);
+                const double Iz = t1[l] - t0[l];
+                const double Ixx = (Ixa(xp, y) - Ixa(xm, y)) / 2.0;
+                const double Ixy = (Ixa(x, yp) - Ixa(x, ym)) / 2.0;
+                const double Iyy = (Iya(x, yp) - Iya(x, ym)) / 2.0;
+                const int lxp = y * W + xp, lxm = y * W + xm, lyp = yp * W + x, lym = ym * W + x;
+                const double Ixz = (t1[lxp] - t1[lxm]) / 2.0 - (t0[lxp] - t0[lxm]) / 2.0;
+                const double Iyz = (t1[lyp] - t1[lym]) / 2.0 - (t0[lyp] - t0[lym]) / 2.0;
+                const double b0 = 1.0 / ((Ix * Ix + Iy * Iy) + 0.01);
+                const double bx = 1.0 / ((Ixx * Ixx + Ixy * Ixy) + 0.01);
+                const double by = 1.0 / ((Ixy * Ixy + Iyy * Iyy) + 0.01);
+                const double fu = it ? sm.du[l] : 0.0, fv = it ? sm.dv[l] : 0.0;
+                const double ri = (Ix * fu + Iy * fv) + Iz;
+                const double ei = b0 * (ri * ri);
+                const double rx = (Ixx * fu + Ixy * fv) + Ixz;
+                const double ry = (Ixy * fu + Iyy * fv) + Iyz;
+                const double eg = bx * (rx * rx) + by * (ry * ry);
+                const double pi_ = a.delta / (2.0 * sqrt(ei + eps2));
+                const double pg = a.gamma / (2.0 * sqrt(eg + eps2));
+                const double A11 = ((pi_ * b0) * Ix) * Ix + pg * (((bx * Ixx) * Ixx) + ((by * Ixy) * Ixy));
+                const double A12 = ((pi_ * b0) * Ix) * Iy + pg * (((bx * Ixx) * Ixy) + ((by * Ixy) * Iyy));
+                const double A22 = ((pi_ * b0) * Iy) * Iy + pg * (((bx * Ixy) * Ixy) + ((by * Iyy) * Iyy));
+                const double B1 = ((pi_ * b0) * Ix) * Iz + pg * (((bx * Ixx) * Ixz) + ((by * Ixy) * Iyz));
+                const double B2 = ((pi_ * b0) * Iy) * Iz + pg * (((bx * Ixy) * Ixz) + ((by * Iyy) * Iyz));
+                const bool hr = x < W - 1, hl = x > 0, hd = y < H - 1, hu = y > 0;
+                const double wr = hr ? sm.wr[l] : 0.0, wl = hl ? sm.wr[l - 1] : 0.0;
+                const double wd = hd ? sm.wd[l] : 0.0, wu = hu ? sm.wd[l - W] : 0.0;
+                const double Ssum = ((wr + wl) + wd) + wu;
+                const double Up = sm.uu[l], Vp = sm.uv[l];
+                const double Ur = hr ? sm.uu[l + 1] : 0.0, Ul = hl ? sm.uu[l - 1] : 0.0;
+                const double Ud = hd ? sm.uu[l + W] : 0.0, Uu = hu ? sm.uu[l - W] : 0.0;
+                const double Vr = hr ? sm.uv[l + 1] : 0.0, Vl = hl ? sm.uv[l - 1] : 0.0;
+                const double Vd = hd ? sm.uv[l + W] : 0.0, Vu = hu ? sm.uv[l - W] : 0.0;
+                const double NU = ((wr * Ur + wl * Ul) + wd * Ud) + wu * Uu;
+                const double NV = ((wr * Vr + wl * Vl) + wd * Vd) + wu * Vu;
+                c_m[k][c] = (hr ? 1 : 0) | (hl ? 2 : 0) | (hd ? 4 : 0) | (hu ? 8 : 0);
+                c_wr[k][c] = wr; c_wl[k][c] = wl; c_wd[k][c] = wd; c_wu[k][c] = wu;
+                c_a12[k][c] = A12;
+                c_i1[k][c] = om / (A11 + Ssum);
+                c_i2[k][c] = om / (A22 + Ssum);
+                c_c1[k][c] = (NU - Ssum * Up) - B1;
+                c_c2[k][c] = (NV - Ssum * Vp) - B2;
+                __builtin_amdgcn_sched_barrier(0);   // one pixel's temporaries at a time
+            }
+        }
+        __syncthreads();   // every frozen increment is read before the sweeps move it
+        // 4. red-black half sweeps: colour 0 = (x + y) even, first
+        for (int jh = 0; jh < nhalf; jh += 2) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    const int l = cl[k][c];
+                    if (l < 0) continue;
+                    const int m = c_m[k][c];
+                    const int lr = (m & 1) ? l + 1 : l, ll = (m & 2) ? l - 1 : l;
+                    const int ld = (m & 4) ? l + W : l, lu = (m & 8) ? l - W : l;
+                    const double du = sm.du[l], dv = sm.dv[l];
+                    const double nu = ((c_wr[k][c] * sm.du[lr] + c_wl[k][c] * sm.du[ll]) + c_wd[k][c] * sm.du[ld]) +
+                                      c_wu[k][c] * sm.du[lu];
+                    const double dun = om1 * du + c_i1[k][c] * ((nu + c_c1[k][c]) - c_a12[k][c] * dv);
+                    const double nv = ((c_wr[k][c] * sm.dv[lr] + c_wl[k][c] * sm.dv[ll]) + c_wd[k][c] * sm.dv[ld]) +
+                                      c_wu[k][c] * sm.dv[lu];
+                    const double dvn = om1 * dv + c_i2[k][c] * ((nv + c_c2[k][c]) - c_a12[k][c] * dun);
+                    sm.du[l] = dun;
+                    sm.dv[l] = dvn;
+                }
+                __syncthreads();
+                if (a.tape) {
+                    double* tp = a.tape + (size_t)(it * nhalf + jh + c + 1) * 2 * n;
+                    for (int i = threadIdx.x; i < npx; i += NT) {
+                        tp[i] = sm.du[i];
+                        tp[n + i] = sm.dv[i];
+                    }
+                    __syncthreads();   // the next half sweep rewrites what was just copied
+                }
+            }
+        }
+        // (the next step's first reads follow the last half sweep's barrier)
+    }
+    // 5. refined flow
+    for (int i = threadIdx.x; i < npx; i += NT) {
+        a.Uout[i] = sm.uu[i] + sm.du[i];
+        a.Uout[n + i] = sm.uv[i] + sm.dv[i];
+    }
+}
 
 // Queue operations of thread 0.  They are kept out of line on purpose: the
 // level kernel's loop holds barriers, and with these thread-0 branches
@@ -748,7 +1033,7 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
                 ra.Uout = rp.last ? P.ra.Uout : nullptr;
                 ra.nhalf = __builtin_amdgcn_readfirstlane(rp.nhalf);
                 ra.tape_m0 = rp.m0;
-                refine_tile<32, 16>(ra, local, sm);
+                refine_tile<32, 16, 256>(ra, local, sm);
             }
         }
         __threadfence();
@@ -766,6 +1051,7 @@ const void* dis_kernel_pyramid_tab() { return (const void*)&k_pyramid_tab; }
 const void* dis_kernel_upsample() { return (const void*)&k_upsample; }
 const void* dis_kernel_upsample_tab() { return (const void*)&k_upsample_tab; }
 const void* dis_kernel_phase_densify() { return (const void*)&k_phase_densify; }
+const void* dis_kernel_small_level() { return (const void*)&k_small_level<DIS_SMALL_THREADS>; }
 
 // instances whose per-lane pixel arrays fit the 256 architectural VGPRs
 #define DIS_FOR_SEARCH_INSTANCES(X) \
@@ -787,20 +1073,23 @@ const void* dis_kernel_level(int ps, int lpp) {
     return nullptr;
 }
 
-int dis_refine_tile(int tile, int* tw, int* th) {
-    switch (tile) {
-        case 0: *tw = 32; *th = 16; return 1;
-        case 1: *tw = 16; *th = 16; return 1;
-        case 2: *tw = 64; *th = 8; return 1;
-        default: return 0;
-    }
+// refinement tile shapes: core width, height, threads per block
+#define DIS_FOR_REFINE_TILES(X) \
+    X(0, 32, 16, 256) X(1, 16, 16, 256) X(2, 64, 8, 256) X(3, 16, 16, 1024) X(4, 32, 16, 1024) \
+    X(5, 16, 16, 512) X(6, 32, 16, 512) X(7, 8, 8, 512) X(8, 16, 8, 512) X(9, 8, 8, 256)
+
+int dis_refine_tile(int tile, int* tw, int* th, int* nt) {
+#define DIS_TILE_SHAPE(ID, TW_, TH_, NT_) \
+    if (tile == ID) { *tw = TW_; *th = TH_; if (nt) *nt = NT_; return 1; }
+    DIS_FOR_REFINE_TILES(DIS_TILE_SHAPE)
+#undef DIS_TILE_SHAPE
+    return 0;
 }
 
 const void* dis_kernel_phase_refine(int tile) {
-    switch (tile) {
-        case 0: return (const void*)&k_phase_refine<32, 16>;
-        case 1: return (const void*)&k_phase_refine<16, 16>;
-        case 2: return (const void*)&k_phase_refine<64, 8>;
-        default: return nullptr;
-    }
+#define DIS_TILE_KERNEL(ID, TW_, TH_, NT_) \
+    if (tile == ID) return (const void*)&k_phase_refine<TW_, TH_, NT_>;
+    DIS_FOR_REFINE_TILES(DIS_TILE_KERNEL)
+#undef DIS_TILE_KERNEL
+    return nullptr;
 }

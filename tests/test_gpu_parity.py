@@ -13,6 +13,8 @@ from paper_1603_03590_amd import DIS, DisError, params, _lib
 
 pytestmark = pytest.mark.gpu
 
+N_TILES = 10   # refinement tile ids the library knows
+
 
 def say(*a):
     print(*a, flush=True)
@@ -168,8 +170,12 @@ def test_launch_choices_are_bitwise_invariant(case):
         t0 = torch.from_numpy(pr.I0).cuda()
         t1 = torch.from_numpy(pr.I1).cuda()
         outs = []
-        for lpp, tile, mode in [(None, 0, 0), ([4] * 16, 0, 0), ([8] * 16, 0, 0), (None, 0, 1),
-                                ([4] * 16, 1, 1), ([16] * 16, 2, 1)]:
+        choices = [(None, 0, 0), ([4] * 16, 0, 0), ([8] * 16, 0, 0), (None, 0, 1)]
+        # every refinement tile shape / block size, with varied lanes per patch
+        choices += [([[4, 8, 16][t % 3]] * 16, t, 1) for t in range(1, N_TILES)]
+        # with the single-workgroup scales (launch mode bit 1)
+        choices += [(None, 0, 3), (None, 3, 3), (None, 0, 2)]
+        for lpp, tile, mode in choices:
             d.set_tunables(lpp, tile, mode)
             o = d.flow(t0, t1)
             torch.cuda.synchronize()
