@@ -170,8 +170,11 @@ int dis_autotune(dis_handle* h, const char* cache_path);
  * persistent launch over a task queue, 1 as one launch per phase; bit 1 set
  * turns on the single-workgroup path: a scale of at most 1024 horizontal
  * pixel pairs is densified and refined, every fixed-point step, by one
- * block instead of tiles.  Every choice gives
- * bitwise-identical flow.  Synchronises the stream and drops cached launch
+ * block instead of tiles; bit 2 set makes dis_flow_backward reverse the SOR
+ * sweeps with one launch per half sweep (a plain reference form) instead of
+ * one tiled launch per fixed-point step.  Every choice gives
+ * bitwise-identical flow (gradients agree to rounding: they are summed with
+ * atomics).  Synchronises the stream and drops cached launch
  * plans.  Errors: DIS_EINVAL.
  */
 int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int refine_tile, int launch_mode);

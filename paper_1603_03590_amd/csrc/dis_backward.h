@@ -8,6 +8,15 @@ struct BZeroArgs {
     size_t n;
 };
 
+// Clear up to 8 buffers in one launch: block b clears part of the buffer
+// whose block range [start[i], start[i+1]) holds b.
+struct BZeroList {
+    double* p[8];
+    size_t n[8];
+    int start[9];
+    int cnt;
+};
+
 struct BCopyArgs {
     double* dst;
     const double* src;
@@ -55,6 +64,26 @@ struct SweepBwdArgs {
     double omega;
 };
 
+// Reverse of the half sweeps j_hi-1 .. j_lo of one fixed-point step of the
+// refinement on one tile (core grown by j_hi - j_lo on every cut side): the
+// step's coefficients are recomputed as in the forward tile, the states
+// before each half sweep come from the tape, the state adjoint lives in LDS.
+// Core pixels write the adjoint of the state before half sweep j_lo, their 9
+// coefficient adjoints (summed over the step's half sweeps) and the
+// coefficients the linearisation adjoint needs.
+struct BwdStepArgs {
+    RefineArgs ra;          // the forward step: U = Ud, J0, J1w, dUf = frozen increment (null = zero), tiles_x
+    const double* tape;     // state before half sweep j at tape + (m0 + j) * 2 W H; zero when m0 + j == 0
+    int m0;
+    int j_lo, j_hi;         // j_hi - j_lo <= DIS_KMAX
+    const double* gd_in;    // adjoint of the state after half sweep j_hi - 1 [2][H][W]
+    const double* gadd;     // added to gd_in, or null
+    double* gd_out;         // adjoint of the state before half sweep j_lo
+    double* coef;           // [6][H][W]: planes 1, 2, 5 (omega/(A11+S), omega/(A22+S), ws) written
+    double* acc;            // [9][H][W] coefficient adjoints
+    int acc_load;           // 1: continue the sums already in acc
+};
+
 struct DensBwdArgs {
     const double* J0;
     const double* J1;
@@ -87,9 +116,16 @@ struct SearchBwdArgs {
     double* gJ0;
     double* gJ1;
     double* gUn;            // adjoint of the coarser flow (null on the coarsest level)
+    int span;               // LDS window of each patch: (PS + 1 + span)^2 cells; patches whose warps spread wider use global atomics
 };
 
 const void* dis_kernel_bzero();
+const void* dis_kernel_bzero_list();
+// reverse refinement tile: 0 = 8x8 cores (small scales), 1 = 16x16 cores
+// (large scales, less halo overlap); 512 threads either way
+const void* dis_kernel_bwd_step(int tile);
+int dis_bwd_step_tile(int tile);        // core side of a reverse tile id
+#define DIS_BWD_THREADS 512
 const void* dis_kernel_bcopy();
 const void* dis_kernel_baxpy();
 const void* dis_kernel_bwd_upsample();

@@ -10,7 +10,10 @@
 // that several threads add to one element use hardware float64 atomics, so
 // gradients can differ between runs in the last bits.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include "dis_backward.h"
+#include "dis_refine_tile.h"
 
 namespace {
 
@@ -25,6 +28,7 @@ __device__ __forceinline__ void atom(double* p, double v) {
 // derivatives with respect to x and y.
 struct Taps {
     int i00, i01, i10, i11;
+    int fx, fy;             // floor of the position before any clamp
     double w00, w01, w10, w11;
     double val, dx, dy;
 };
@@ -32,12 +36,14 @@ struct Taps {
 __device__ __forceinline__ Taps taps_of(const double* img, int W, int H, double x, double y) {
     double xf = floor(x), yf = floor(y);
     const double ax = x - xf, ay = y - yf;
+    Taps t;
+    t.fx = (int)xf;
+    t.fy = (int)yf;
     xf = fmin(fmax(xf, -2.0), (double)W + 1.0);
     yf = fmin(fmax(yf, -2.0), (double)H + 1.0);
     const int xi = (int)xf, yi = (int)yf;
     const int x0 = clampi(xi, 0, W - 1), x1 = clampi(xi + 1, 0, W - 1);
     const int y0 = clampi(yi, 0, H - 1), y1 = clampi(yi + 1, 0, H - 1);
-    Taps t;
     t.i00 = y0 * W + x0; t.i01 = y0 * W + x1; t.i10 = y1 * W + x0; t.i11 = y1 * W + x1;
     t.w00 = (1.0 - ay) * (1.0 - ax); t.w01 = (1.0 - ay) * ax; t.w10 = ay * (1.0 - ax); t.w11 = ay * ax;
     const double a = img ? img[t.i00] : 0.0, b = img ? img[t.i01] : 0.0;
@@ -63,6 +69,13 @@ __device__ __forceinline__ void scatter_taps(double* g, const Taps& t, double v)
 __global__ __launch_bounds__(256) void k_bzero(const BZeroArgs a) {
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (i < a.n) a.p[i] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_bzero_list(const BZeroList L) {
+    int e = 0;
+    while (e + 1 < L.cnt && (int)blockIdx.x >= L.start[e + 1]) ++e;
+    const size_t i = (size_t)(blockIdx.x - L.start[e]) * 256 + threadIdx.x;
+    if (i < L.n[e]) L.p[e][i] = 0.0;
 }
 
 // dst = src (and dst2 = src when given)
@@ -427,6 +440,199 @@ __global__ __launch_bounds__(256) void k_bwd_ws(const RefBwdArgs a) {
     }
 }
 
+// ------------------------------------------------- reverse refinement tile
+
+namespace {
+
+// The reverse of kh half sweeps needs a region one pixel wider than the
+// forward's: within one reverse half sweep an error entering at the cut
+// reaches the pixels of the other colour next to it (part b), so after kh
+// of them it has moved kh + 1 pixels in.
+template <int TW, int TH>
+struct BwdStepSmem {
+    using F = dis_tile::RefineSmem<TW, TH, DIS_KMAX + 1>;
+    F f;                                // forward set-up; its increment planes then hold the tape state
+    static constexpr int RP = F::RHM * F::LP;
+    double gu[RP], gv[RP];              // adjoint of the state
+    double nu[RP], nv[RP];              // adjoints of the neighbour sums of the last reverse half sweep
+    double acc[9][TW * TH];             // coefficient adjoints of the core pixels
+};
+
+}  // namespace
+
+template <int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
+    constexpr int KG = DIS_KMAX + 1;
+    using S = dis_tile::RefineSmem<TW, TH, KG>;
+    using Shape = dis_tile::TileShape<TW, TH, NT, KG>;
+    constexpr int LP = S::LP;
+    constexpr int PPT = Shape::PPT;
+    constexpr int NE = (S::RWM * S::RHM + NT - 1) / NT;   // region elements per thread
+    __shared__ BwdStepSmem<TW, TH> sm;
+    const RefineArgs& a = A.ra;
+    const int kh = __builtin_amdgcn_readfirstlane(A.j_hi - A.j_lo);
+    const dis_tile::TileGeom g = dis_tile::tile_geom<TW, TH>(a.W, a.H, a.tiles_x, blockIdx.x, kh + 1);
+    const int W = g.W;
+    const size_t n = (size_t)W * g.H;
+    const int rx0 = g.rx0, ry0 = g.ry0, RW = g.RW, RH = g.RH;
+    const int cx0 = g.cx0, cy0 = g.cy0, CW = g.cx1 - g.cx0, CH = g.cy1 - g.cy0;
+    const double om1 = 1.0 - a.omega;
+
+    dis_tile::TileCoef<PPT> C;
+    double s_iu[Shape::NS][2], s_iv[Shape::NS][2];
+    dis_tile::refine_setup<TW, TH, NT, KG>(a, g, sm.f, C, s_iu, s_iv);
+    __syncthreads();   // the image tile is dead from here on
+
+    // state adjoint on the region, coefficient adjoints of the core
+    for (int i = threadIdx.x; i < RW * RH; i += NT) {
+        const int ly = i / RW, lx = i - ly * RW;
+        const size_t gi = (size_t)(ry0 + ly) * W + rx0 + lx;
+        double u = A.gd_in[gi], v = A.gd_in[n + gi];
+        if (A.gadd) { u = u + A.gadd[gi]; v = v + A.gadd[n + gi]; }
+        sm.gu[ly * LP + lx] = u;
+        sm.gv[ly * LP + lx] = v;
+    }
+    for (int i = threadIdx.x; i < CW * CH; i += NT) {
+        const int yy = i / CW, xx = i - yy * CW;
+        const size_t gi = (size_t)(cy0 + yy) * W + cx0 + xx;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) sm.acc[q][yy * TW + xx] = A.acc_load ? A.acc[q * n + gi] : 0.0;
+    }
+    // the tape state before a half sweep, region-wide, through registers so
+    // that the next one is in flight while the current one is reversed
+    double* st_u = sm.f.u.inc.du;
+    double* st_v = sm.f.u.inc.dv;
+    double pu[NE], pv[NE];
+    auto fetch = [&](int j) {
+        const int m = A.m0 + j;
+        const double* tp = m ? A.tape + (size_t)m * 2 * n : nullptr;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int i = threadIdx.x + e * NT;
+            pu[e] = pv[e] = 0.0;
+            if (tp && i < RW * RH) {
+                const int ly = i / RW, lx = i - ly * RW;
+                const size_t gi = (size_t)(ry0 + ly) * W + rx0 + lx;
+                pu[e] = tp[gi];
+                pv[e] = tp[n + gi];
+            }
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int i = threadIdx.x + e * NT;
+            if (i < RW * RH) {
+                const int ly = i / RW, lx = i - ly * RW;
+                st_u[ly * LP + lx] = pu[e];
+                st_v[ly * LP + lx] = pv[e];
+            }
+        }
+    };
+    const int jhi = __builtin_amdgcn_readfirstlane(A.j_hi), jlo = __builtin_amdgcn_readfirstlane(A.j_lo);
+    fetch(jhi - 1);
+    stash();
+    __syncthreads();
+    // one reverse half sweep; the colour is a template constant so that the
+    // per-pixel coefficient arrays stay in registers
+    auto reverse = [&](auto colour, int j) {
+        constexpr int c = decltype(colour)::value;   // the colour half sweep j updated
+        if (j > jlo) fetch(j - 1);
+        // (a) pixels of colour c: replay the update, then its adjoint
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int l = C.l[k][c];
+            if (l < 0) continue;
+            const int msk = C.m[k][c];
+            const int lr = (msk & 1) ? l + 1 : l, ll = (msk & 2) ? l - 1 : l;
+            const int ld = (msk & 4) ? l + LP : l, lu = (msk & 8) ? l - LP : l;
+            const double dup = st_u[l], dvp = st_v[l];
+            const double dur = (msk & 1) ? st_u[lr] : 0.0, dul = (msk & 2) ? st_u[ll] : 0.0;
+            const double dud = (msk & 4) ? st_u[ld] : 0.0, duu = (msk & 8) ? st_u[lu] : 0.0;
+            const double dvr = (msk & 1) ? st_v[lr] : 0.0, dvl = (msk & 2) ? st_v[ll] : 0.0;
+            const double dvd = (msk & 4) ? st_v[ld] : 0.0, dvu = (msk & 8) ? st_v[lu] : 0.0;
+            const double wr = C.wr[k][c], wl = C.wl[k][c], wd = C.wd[k][c], wu = C.wu[k][c];
+            const double A12 = C.a12[k][c], i1 = C.i1[k][c], i2 = C.i2[k][c];
+            const double nu = ((wr * dur + wl * dul) + wd * dud) + wu * duu;
+            const double r1 = (nu + C.c1[k][c]) - A12 * dvp;
+            const double dun = om1 * dup + i1 * r1;
+            const double nv = ((wr * dvr + wl * dvl) + wd * dvd) + wu * dvu;
+            const double r2 = (nv + C.c2[k][c]) - A12 * dun;
+            const double adv = sm.gv[l];
+            const double gr2 = i2 * adv;
+            const double adu = sm.gu[l] - A12 * gr2;
+            const double gr1 = i1 * adu;
+            const int ly = l / LP, lx = l - ly * LP;
+            const int xx = rx0 + lx - cx0, yy = ry0 + ly - cy0;
+            if (xx >= 0 && xx < CW && yy >= 0 && yy < CH) {
+                const int q = yy * TW + xx;
+                sm.acc[0][q] += r1 * adu;
+                sm.acc[1][q] += r2 * adv;
+                sm.acc[2][q] += gr1;
+                sm.acc[3][q] += gr2;
+                sm.acc[4][q] += -dun * gr2 - dvp * gr1;
+                sm.acc[5][q] += dur * gr1 + dvr * gr2;
+                sm.acc[6][q] += dul * gr1 + dvl * gr2;
+                sm.acc[7][q] += dud * gr1 + dvd * gr2;
+                sm.acc[8][q] += duu * gr1 + dvu * gr2;
+            }
+            sm.gu[l] = om1 * adu;
+            sm.gv[l] = om1 * adv - A12 * gr1;
+            sm.nu[l] = gr1;
+            sm.nv[l] = gr2;
+        }
+        __syncthreads();
+        // (b) pixels of the other colour collect what their neighbours'
+        // updates owe them; the next state goes to LDS meanwhile
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int l = C.l[k][c ^ 1];
+            if (l < 0) continue;
+            const int msk = C.m[k][c ^ 1];
+            double su = 0.0, sv = 0.0;
+            if (msk & 1) { su += C.wr[k][c ^ 1] * sm.nu[l + 1]; sv += C.wr[k][c ^ 1] * sm.nv[l + 1]; }
+            if (msk & 2) { su += C.wl[k][c ^ 1] * sm.nu[l - 1]; sv += C.wl[k][c ^ 1] * sm.nv[l - 1]; }
+            if (msk & 4) { su += C.wd[k][c ^ 1] * sm.nu[l + LP]; sv += C.wd[k][c ^ 1] * sm.nv[l + LP]; }
+            if (msk & 8) { su += C.wu[k][c ^ 1] * sm.nu[l - LP]; sv += C.wu[k][c ^ 1] * sm.nv[l - LP]; }
+            sm.gu[l] += su;
+            sm.gv[l] += sv;
+        }
+        if (j > jlo) stash();
+        __syncthreads();
+    };
+    for (int j = jhi - 1; j >= jlo; --j) {
+        if (j & 1) reverse(std::integral_constant<int, 1>{}, j);
+        else reverse(std::integral_constant<int, 0>{}, j);
+    }
+
+    // the core: state adjoint, coefficient adjoints, and the coefficients
+    // the linearisation adjoint reads
+    for (int i = threadIdx.x; i < CW * CH; i += NT) {
+        const int yy = i / CW, xx = i - yy * CW;
+        const size_t gi = (size_t)(cy0 + yy) * W + cx0 + xx;
+        const int l = (cy0 + yy - ry0) * LP + (cx0 + xx - rx0);
+        A.gd_out[gi] = sm.gu[l];
+        A.gd_out[n + gi] = sm.gv[l];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) A.acc[q * n + gi] = sm.acc[q][yy * TW + xx];
+    }
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int l = C.l[k][c];
+            if (l < 0) continue;
+            const int ly = l / LP, lx = l - ly * LP;
+            const int x = rx0 + lx, y = ry0 + ly;
+            if (x < cx0 || x >= g.cx1 || y < cy0 || y >= g.cy1) continue;
+            const size_t gi = (size_t)y * W + x;
+            A.coef[n + gi] = C.i1[k][c];
+            A.coef[2 * n + gi] = C.i2[k][c];
+            A.coef[5 * n + gi] = x < W - 1 ? sm.f.wr[l] : sm.f.wd[l];
+        }
+    }
+}
+
 // ----------------------------------------------------------- densification
 
 // Reverse of the warped frame J1w(x) = J1(x + Ud(x)) and of Eq. (3): the
@@ -537,12 +743,19 @@ __global__ __launch_bounds__(256) void k_bwd_search(const SearchBwdArgs A) {
     constexpr int NP = PS * PS;
     constexpr int PPL = (NP + LPP - 1) / LPP;
     constexpr int GROUPS = 256 / LPP;
-    extern __shared__ double s_u[];             // [GROUPS][iters + 1][2]
+    // dynamic LDS: [GROUPS][iters + 1][2] iterates, then [GROUPS][WIN][WIN]
+    // windows collecting each patch's J1 adjoint (WIN = PS + 3 + span: the
+    // taps of every warp plus a pixel on each side, for a position whose
+    // fraction rounds up to the next integer)
+    extern __shared__ double s_dyn[];
     const SearchArgs& a = A.sa;
     const int W = a.W, H = a.H;
     const int lane = threadIdx.x & (LPP - 1);
     const int grp = threadIdx.x / LPP;
     const int N = a.nx * a.ny;
+    const int WIN = PS + 3 + A.span;
+    double* s_u = s_dyn;
+    double* win = s_dyn + (size_t)GROUPS * (a.iters + 1) * 2 + (size_t)grp * WIN * WIN;
     int pi = (int)((blockIdx.x * 256u + threadIdx.x) / LPP);
     const bool valid = pi < N;
     if (!valid) pi = N - 1;
@@ -601,11 +814,14 @@ __global__ __launch_bounds__(256) void k_bwd_search(const SearchBwdArgs A) {
     const double* gP = A.gP + (size_t)pi * 4;
     double gu = gP[0], gv = gP[1];
     const double gmd = gP[2];
+    const bool iterate = !reset && a.iters > 0;
     double gT[PPL], ggx[PPL], ggy[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; ++k) gT[k] = ggx[k] = ggy[k] = 0.0;
 
-    // residual of the patch at displacement (u, v): d_p, and its derivatives
+    // integer part of a warp position (the displacement clamp included)
+    auto ifloor = [&](double u) { return (int)fmin(fmax(floor(u), -lim), lim); };
+    // residual of the patch at displacement (u, v): d_p, its derivatives, taps
     auto warp = [&](double u, double v, double (&d)[PPL], double (&dx)[PPL], double (&dy)[PPL], Taps (&tp)[PPL]) {
         const double fu = floor(u), fv = floor(v);
         const double cu = fmin(fmax(fu, -lim), lim) + (u - fu), cv = fmin(fmax(fv, -lim), lim) + (v - fv);
@@ -622,36 +838,22 @@ __global__ __launch_bounds__(256) void k_bwd_search(const SearchBwdArgs A) {
             }
         }
     };
+
+    // forward iterates u_0 .. u_iters (every lane of the patch holds the same
+    // bits of (u, v): the butterfly sums are commutative), and the integer
+    // extent of every warp the reverse touches
+    double* su_ = s_u + (size_t)grp * (a.iters + 1) * 2;
+    int ix_lo = ifloor(uf), ix_hi = ix_lo, iy_lo = ifloor(vf), iy_hi = iy_lo;
     double d[PPL], dqx[PPL], dqy[PPL];
     Taps tp[PPL];
-    // mean residual at the final displacement (used by the densification)
-    if (gmd != 0.0) {
-        warp(uf, vf, d, dqx, dqy, tp);
-        const double q = gmd * inv_n;
-        double su = 0.0, sv = 0.0;
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-            const int p = lane + k * LPP;
-            if (p < NP && valid) {
-                su += q * dqx[k];
-                sv += q * dqy[k];
-                scatter_taps(A.gJ1, tp[k], q);
-                gT[k] -= q;
-            }
-        }
-        gu += red(su);
-        gv += red(sv);
-    }
-    double gui = gu, gvi = gv;
-    if (!reset && a.iters > 0) {
-        // forward iterates u_0 .. u_iters
-        double* su_ = s_u + (size_t)grp * (a.iters + 1) * 2;
+    if (iterate) {
         double u = ui, v = vi;
         for (int it = 0; it < a.iters; ++it) {
-            // every lane of the patch holds the same bits of (u, v) (the
-            // butterfly sums are commutative), so each lane keeps its own copy
             su_[2 * it] = u;
             su_[2 * it + 1] = v;
+            const int iu = ifloor(u), iv = ifloor(v);
+            ix_lo = min(ix_lo, iu); ix_hi = max(ix_hi, iu);
+            iy_lo = min(iy_lo, iv); iy_hi = max(iy_hi, iv);
             warp(u, v, d, dqx, dqy, tp);
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
@@ -661,6 +863,50 @@ __global__ __launch_bounds__(256) void k_bwd_search(const SearchBwdArgs A) {
             u = u - (m11 * b1 + m12 * b2);
             v = v - (m12 * b1 + m22 * b2);
         }
+    }
+    // the J1 adjoint of this patch goes to its LDS window when every warp
+    // fits; window cell (X, Y) is position (wx0 + X, wy0 + Y) before the tap
+    // clamp, which the flush applies
+    const bool use_win = (ix_hi - ix_lo) <= A.span && (iy_hi - iy_lo) <= A.span;
+    const int wx0 = x0 + ix_lo - 1, wy0 = y0 + iy_lo - 1;
+    const int wdx = PS + 3 + (ix_hi - ix_lo), wdy = PS + 3 + (iy_hi - iy_lo);
+    if (use_win)
+        for (int i = lane; i < WIN * WIN; i += LPP) win[i] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    auto scatter_j1 = [&](int k, double val) {
+        const Taps& t = tp[k];
+        const int X = t.fx - wx0, Y = t.fy - wy0;
+        if (use_win && X >= 0 && Y >= 0 && X + 1 < wdx && Y + 1 < wdy) {
+            double* c = win + Y * WIN + X;
+            if (val * t.w00 != 0.0) unsafeAtomicAdd(c, val * t.w00);
+            if (val * t.w01 != 0.0) unsafeAtomicAdd(c + 1, val * t.w01);
+            if (val * t.w10 != 0.0) unsafeAtomicAdd(c + WIN, val * t.w10);
+            if (val * t.w11 != 0.0) unsafeAtomicAdd(c + WIN + 1, val * t.w11);
+        } else {
+            scatter_taps(A.gJ1, tp[k], val);
+        }
+    };
+
+    // mean residual at the final displacement (used by the densification)
+    if (gmd != 0.0) {
+        warp(uf, vf, d, dqx, dqy, tp);
+        const double q = gmd * inv_n;
+        double su = 0.0, sv = 0.0;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            const int p = lane + k * LPP;
+            if (p < NP) {
+                su += q * dqx[k];
+                sv += q * dqy[k];
+                if (valid) scatter_j1(k, q);
+                gT[k] -= q;
+            }
+        }
+        gu += red(su);
+        gv += red(sv);
+    }
+    double gui = gu, gvi = gv;
+    if (iterate) {
         double H11 = 0.0, H12 = 0.0, H21 = 0.0, H22 = 0.0;   // adjoint of H
         for (int it = a.iters - 1; it >= 0; --it) {
             const double uk = su_[2 * it], vk = su_[2 * it + 1];
@@ -687,7 +933,7 @@ __global__ __launch_bounds__(256) void k_bwd_search(const SearchBwdArgs A) {
                     gT[k] -= dd;
                     su += dd * dqx[k];
                     sv += dd * dqy[k];
-                    if (valid) scatter_taps(A.gJ1, tp[k], dd);
+                    if (valid) scatter_j1(k, dd);
                 }
             }
             gu += red(su);
@@ -702,25 +948,46 @@ __global__ __launch_bounds__(256) void k_bwd_search(const SearchBwdArgs A) {
             ggy[k] += (H12 + H21) * gx[k] + (H22 + H22) * gy[k];
         }
     }
-    if (!valid) return;
-    // template and Sobel/8 gradients -> J0
+    // the window, with the taps' clamp to the image
+    __builtin_amdgcn_wave_barrier();
+    if (use_win && valid) {
+        for (int i = lane; i < wdx * wdy; i += LPP) {
+            const int Y = i / wdx, X = i - Y * wdx;
+            const double v = win[Y * WIN + X];
+            if (v != 0.0) unsafeAtomicAdd(A.gJ1 + (size_t)clampi(wy0 + Y, 0, H - 1) * W + clampi(wx0 + X, 0, W - 1), v);
+        }
+    }
+    // template and Sobel/8 gradients -> J0, through the same window (cells
+    // x0 - 1 .. x0 + PS, y0 - 1 .. y0 + PS before the border clamp)
+    __builtin_amdgcn_wave_barrier();
+    const int jx0 = x0 - 1, jy0 = y0 - 1, JW = PS + 2;
+    for (int i = lane; i < JW * JW; i += LPP) win[(i / JW) * WIN + (i % JW)] = 0.0;
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int p = lane + k * LPP;
         if (p >= NP) continue;
         const int py = p / PS, px = p - py * PS;
-        const int x = x0 + px, y = y0 + py;
-        const int xm = max(x - 1, 0), xp = min(x + 1, W - 1), ym = max(y - 1, 0), yp = min(y + 1, H - 1);
-        double* G = A.gJ0;
-        atom(G + y * W + x, gT[k]);
+        double* c = win + (py + 1) * WIN + (px + 1);   // the pixel itself
         const double ax = ggx[k] / 8.0, ay = ggy[k] / 8.0;
-        atom(G + ym * W + xp, ax); atom(G + ym * W + xm, -ax);
-        atom(G + y * W + xp, 2.0 * ax); atom(G + y * W + xm, -2.0 * ax);
-        atom(G + yp * W + xp, ax); atom(G + yp * W + xm, -ax);
-        atom(G + yp * W + xm, ay); atom(G + ym * W + xm, -ay);
-        atom(G + yp * W + x, 2.0 * ay); atom(G + ym * W + x, -2.0 * ay);
-        atom(G + yp * W + xp, ay); atom(G + ym * W + xp, -ay);
+        unsafeAtomicAdd(c, gT[k]);
+        unsafeAtomicAdd(c - WIN + 1, ax); unsafeAtomicAdd(c - WIN - 1, -ax);
+        unsafeAtomicAdd(c + 1, 2.0 * ax); unsafeAtomicAdd(c - 1, -2.0 * ax);
+        unsafeAtomicAdd(c + WIN + 1, ax); unsafeAtomicAdd(c + WIN - 1, -ax);
+        unsafeAtomicAdd(c + WIN - 1, ay); unsafeAtomicAdd(c - WIN - 1, -ay);
+        unsafeAtomicAdd(c + WIN, 2.0 * ay); unsafeAtomicAdd(c - WIN, -2.0 * ay);
+        unsafeAtomicAdd(c + WIN + 1, ay); unsafeAtomicAdd(c - WIN + 1, -ay);
     }
+    __builtin_amdgcn_wave_barrier();
+    if (valid) {
+        for (int i = lane; i < JW * JW; i += LPP) {
+            const int Y = i / JW, X = i - Y * JW;
+            const double v = win[Y * WIN + X];
+            if (v != 0.0)
+                unsafeAtomicAdd(A.gJ0 + (size_t)clampi(jy0 + Y, 0, H - 1) * W + clampi(jx0 + X, 0, W - 1), v);
+        }
+    }
+    if (!valid) return;
     // initialisation u_init = 2 U_{s+1}(q)
     if (a.Un && lane == 0) {
         const Taps t = taps_of(nullptr, a.Wn, a.Hn, qx, qy);
@@ -732,6 +999,11 @@ __global__ __launch_bounds__(256) void k_bwd_search(const SearchBwdArgs A) {
 // ------------------------------------------------------------ kernel table
 
 const void* dis_kernel_bzero() { return (const void*)&k_bzero; }
+const void* dis_kernel_bzero_list() { return (const void*)&k_bzero_list; }
+const void* dis_kernel_bwd_step(int tile) {
+    return tile ? (const void*)&k_bwd_step<16, 16, DIS_BWD_THREADS> : (const void*)&k_bwd_step<8, 8, DIS_BWD_THREADS>;
+}
+int dis_bwd_step_tile(int tile) { return tile ? 16 : 8; }
 const void* dis_kernel_bcopy() { return (const void*)&k_bcopy; }
 const void* dis_kernel_baxpy() { return (const void*)&k_baxpy; }
 const void* dis_kernel_bwd_upsample() { return (const void*)&k_bwd_upsample; }

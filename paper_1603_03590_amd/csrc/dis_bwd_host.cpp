@@ -81,19 +81,38 @@ int dis_alloc_backward(dis_handle* h) {
         DALLOC(h, B.acc, 9 * pxmax * sizeof(double));
         DALLOC(h, B.coef, 6 * pxmax * sizeof(double));
         DALLOC(h, B.edge, 4 * pxmax * sizeof(double));
-        DALLOC(h, B.gFacc, 2 * pxmax * sizeof(double));
+        int nout_max = 1;
+        for (int s = sf; s <= h->top; ++s) nout_max = std::max(nout_max, outer_steps(p, s));
+        DALLOC(h, B.gFacc, (size_t)nout_max * 2 * pxmax * sizeof(double));
         DALLOC(h, B.tape, tape * sizeof(double));
         B.tape_len = tape;
     }
     return DIS_OK;
 }
 
-static void add_zero(Seq& q, double* p, size_t n) {
-    BZeroArgs z{p, n};
-    q.add(dis_kernel_bzero(), dim3((unsigned)((n + 255) / 256)), dim3(256), &z, sizeof z, 0, "bwd_zero", 8.0 * n, 0.0);
-}
 
 static dim3 grid2d(int W, int H) { return dim3((W + 63) / 64, (H + 3) / 4); }
+
+// Clear many buffers with as few launches as possible (eight per launch).
+static void add_zero_list(Seq& q, const std::vector<std::pair<double*, size_t>>& bufs) {
+    for (size_t i0 = 0; i0 < bufs.size(); i0 += 8) {
+        BZeroList z;
+        std::memset(&z, 0, sizeof z);
+        int blocks = 0;
+        double bytes = 0.0;
+        for (size_t i = i0; i < bufs.size() && i < i0 + 8; ++i) {
+            if (bufs[i].second == 0) continue;
+            z.p[z.cnt] = bufs[i].first;
+            z.n[z.cnt] = bufs[i].second;
+            z.start[z.cnt] = blocks;
+            blocks += (int)((bufs[i].second + 255) / 256);
+            bytes += 8.0 * bufs[i].second;
+            ++z.cnt;
+        }
+        z.start[z.cnt] = blocks;
+        if (z.cnt) q.add(dis_kernel_bzero_list(), dim3(blocks), dim3(256), &z, sizeof z, 0, "bwd_zero", bytes, 0.0);
+    }
+}
 
 static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
     const dis_params& p = h->p;
@@ -103,18 +122,29 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
     const int ss = dis_coarsest(&p, w, hgt);
     const int cmap = (p.flags & DIS_FLAG_PIXEL_CENTRE) ? 1 : 0;
     const bool f64io = (p.flags & DIS_FLAG_IO_F64) != 0;
-    const size_t shmem = (size_t)16 * (p.gn_iters + 1) * 2 * sizeof(double);
-    if (shmem > 65536) return dis_fail(h, DIS_EINVAL, "backward supports at most 255 Gauss-Newton iterations");
+    // search reverse: iterates of 16 patches, then a J1-adjoint window per
+    // patch, as wide as 64 KB of LDS allows (span 0..12 extra pixels)
+    const size_t traj = (size_t)16 * (p.gn_iters + 1) * 2 * sizeof(double);
+    if (traj > 65536 - 16 * 8 * (size_t)(ps + 3) * (ps + 3))
+        return dis_fail(h, DIS_EINVAL, "backward supports at most %d Gauss-Newton iterations for patch %d",
+                        (int)((65536 - 16 * 8 * (ps + 3) * (ps + 3)) / (16 * 2 * 8)) - 1, ps);
+    int span = 12;
+    while (span > 0 && traj + (size_t)16 * 8 * (ps + 3 + span) * (ps + 3 + span) > 65536) --span;
+    const size_t shmem = traj + (size_t)16 * 8 * (ps + 3 + span) * (ps + 3 + span);
     Seq& q = bp->seq;
 
-    for (int s = sf; s <= ss; ++s) {
-        LevelGrid g;
-        const int N = dis_level_grid(h, w >> s, hgt >> s, &g);
-        const size_t n = (size_t)g.W * g.H;
-        add_zero(q, B.gJ0[s], n);
-        add_zero(q, B.gJ1[s], n);
-        add_zero(q, B.gU[s], 2 * n);
-        add_zero(q, B.gP[s], (size_t)N * 4);
+    {
+        std::vector<std::pair<double*, size_t>> z;
+        for (int s = sf; s <= ss; ++s) {
+            LevelGrid g;
+            const int N = dis_level_grid(h, w >> s, hgt >> s, &g);
+            const size_t n = (size_t)g.W * g.H;
+            z.push_back({B.gJ0[s], n});
+            z.push_back({B.gJ1[s], n});
+            z.push_back({B.gU[s], 2 * n});
+            z.push_back({B.gP[s], (size_t)N * 4});
+        }
+        add_zero_list(q, z);
     }
     {
         UpsBwdArgs ua;
@@ -155,14 +185,29 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
         const double* gUd = B.gU[s];
         const double* gJ1w = nullptr;
         if (p.refine) {
+            const int nout = outer_steps(p, s);
+            const int nh = 2 * p.var_inner;
+            const bool tiled = !h->bwd_reference;
             BCopyArgs cp{B.gUd, B.gU[s], B.gd, 2 * n};
             q.add(dis_kernel_bcopy(), dim3((unsigned)((2 * n + 255) / 256)), dim3(256), &cp, sizeof cp, 0, "bwd_copy",
                   48.0 * n, 0.0);
-            add_zero(q, B.gJ1w, n);
+            {
+                std::vector<std::pair<double*, size_t>> z{{B.gJ1w, n}};
+                if (tiled)
+                    for (int k = 1; k < nout; ++k) z.push_back({B.gFacc + (size_t)k * 2 * n, 2 * n});
+                add_zero_list(q, z);
+            }
             gUd = B.gUd;
             gJ1w = B.gJ1w;
-            const int nout = outer_steps(p, s);
-            const int nh = 2 * p.var_inner;
+            // adjoint of the state between half sweeps: ping-pong between gd and gn
+            double* gdb[2] = {B.gd, B.gn};
+            int cur = 0;
+            // 8x8 cores while they give at most two blocks per compute unit,
+            // else 16x16 (a quarter of the blocks, a third of the halo work)
+            const int bt = ((W + 7) / 8) * ((H + 7) / 8) > 2 * h->n_cu ? 1 : 0;
+            const int TS = dis_bwd_step_tile(bt);
+            const int tiles_x = (W + TS - 1) / TS;
+            const int ntiles = tiles_x * ((H + TS - 1) / TS);
             for (int k = nout - 1; k >= 0; --k) {
                 RefBwdArgs ra;
                 std::memset(&ra, 0, sizeof ra);
@@ -174,7 +219,7 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
                 ra.acc = B.acc;
                 ra.edge = B.edge;
                 ra.gU = B.gUd;
-                ra.gF = B.gFacc;
+                ra.gF = tiled ? (k ? B.gFacc + (size_t)k * 2 * n : nullptr) : B.gFacc;
                 ra.gJ0 = B.gJ0[s];
                 ra.gJ1w = B.gJ1w;
                 ra.W = W;
@@ -184,35 +229,78 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
                 ra.alpha = p.w_smooth;
                 ra.omega = p.sor_omega;
                 ra.eps = 1e-3;
-                q.add(dis_kernel_bwd_coef(), grid2d(W, H), dim3(256), &ra, sizeof ra, 0, "bwd_coef", 40.0 * px,
-                      20.0 * px);
-                q.add(dis_kernel_bwd_coef2(), grid2d(W, H), dim3(256), &ra, sizeof ra, 0, "bwd_coef", 88.0 * px,
-                      120.0 * px);
-                add_zero(q, B.acc, 9 * n);
-                if (k) add_zero(q, B.gFacc, 2 * n);
-                for (int j = nh - 1; j >= 0; --j) {
-                    const int m = k * nh + j;
-                    SweepBwdArgs sw;
-                    std::memset(&sw, 0, sizeof sw);
-                    sw.state = m ? B.tape + (size_t)m * 2 * n : nullptr;
-                    sw.coef = B.coef;
-                    sw.gd = B.gd;
-                    sw.gn = B.gn;
-                    sw.acc = B.acc;
-                    sw.W = W;
-                    sw.H = H;
-                    sw.colour = j & 1;
-                    sw.omega = p.sor_omega;
-                    q.add(dis_kernel_bwd_sweep_a(), grid2d(W, H), dim3(256), &sw, sizeof sw, 0, "bwd_sweep",
-                          0.5 * 232.0 * px, 0.5 * 60.0 * px);
-                    q.add(dis_kernel_bwd_sweep_b(), grid2d(W, H), dim3(256), &sw, sizeof sw, 0, "bwd_sweep",
-                          0.5 * 80.0 * px, 0.5 * 16.0 * px);
+                if (tiled) {
+                    // reverse of the step's half sweeps, at most DIS_KMAX per launch
+                    int j_hi = nh;
+                    bool first = true;
+                    while (j_hi > 0) {
+                        const int j_lo = std::max(0, j_hi - DIS_KMAX);
+                        BwdStepArgs st;
+                        std::memset(&st, 0, sizeof st);
+                        RefineArgs& f = st.ra;
+                        f.U = L.Ud;
+                        f.J0 = L.J0;
+                        f.J1w = sb.J1w;
+                        f.dUf = ra.F;
+                        f.W = W;
+                        f.H = H;
+                        f.nhalf = j_hi - j_lo;
+                        f.tiles_x = tiles_x;
+                        f.delta = p.w_intensity;
+                        f.gamma = p.w_gradient;
+                        f.alpha = p.w_smooth;
+                        f.omega = p.sor_omega;
+                        f.eps = 1e-3;
+                        st.tape = B.tape;
+                        st.m0 = k * nh;
+                        st.j_lo = j_lo;
+                        st.j_hi = j_hi;
+                        st.gd_in = gdb[cur];
+                        st.gadd = (first && k < nout - 1) ? B.gFacc + (size_t)(k + 1) * 2 * n : nullptr;
+                        st.gd_out = gdb[cur ^ 1];
+                        st.coef = B.coef;
+                        st.acc = B.acc;
+                        st.acc_load = first ? 0 : 1;
+                        const int kh = j_hi - j_lo;
+                        // in: U, dUf, J0, J1w, state adjoint (+ added), kh tape states;
+                        // out: state adjoint, 9 coefficient adjoints, 3 coefficients
+                        q.add(dis_kernel_bwd_step(bt), dim3(ntiles), dim3(DIS_BWD_THREADS), &st, sizeof st, 0,
+                              "bwd_step", px * (16.0 + 16.0 + 16.0 + 32.0 + 16.0 * kh + 16.0 + 72.0 + 24.0),
+                              px * (155.0 + 20.0 * kh));
+                        cur ^= 1;
+                        first = false;
+                        j_hi = j_lo;
+                    }
+                } else {
+                    q.add(dis_kernel_bwd_coef(), grid2d(W, H), dim3(256), &ra, sizeof ra, 0, "bwd_coef", 40.0 * px,
+                          20.0 * px);
+                    q.add(dis_kernel_bwd_coef2(), grid2d(W, H), dim3(256), &ra, sizeof ra, 0, "bwd_coef", 88.0 * px,
+                          120.0 * px);
+                    add_zero_list(q, {{B.acc, 9 * n}, {B.gFacc, k ? 2 * n : 0}});
+                    for (int j = nh - 1; j >= 0; --j) {
+                        const int m = k * nh + j;
+                        SweepBwdArgs sw;
+                        std::memset(&sw, 0, sizeof sw);
+                        sw.state = m ? B.tape + (size_t)m * 2 * n : nullptr;
+                        sw.coef = B.coef;
+                        sw.gd = B.gd;
+                        sw.gn = B.gn;
+                        sw.acc = B.acc;
+                        sw.W = W;
+                        sw.H = H;
+                        sw.colour = j & 1;
+                        sw.omega = p.sor_omega;
+                        q.add(dis_kernel_bwd_sweep_a(), grid2d(W, H), dim3(256), &sw, sizeof sw, 0, "bwd_sweep",
+                              0.5 * 232.0 * px, 0.5 * 60.0 * px);
+                        q.add(dis_kernel_bwd_sweep_b(), grid2d(W, H), dim3(256), &sw, sizeof sw, 0, "bwd_sweep",
+                              0.5 * 80.0 * px, 0.5 * 16.0 * px);
+                    }
                 }
                 q.add(dis_kernel_bwd_lin(), grid2d(W, H), dim3(256), &ra, sizeof ra, 0, "bwd_lin", 200.0 * px,
                       400.0 * px);
                 q.add(dis_kernel_bwd_ws(), grid2d(W, H), dim3(256), &ra, sizeof ra, 0, "bwd_ws", 96.0 * px,
                       60.0 * px);
-                if (k) {
+                if (!tiled && k) {
                     BCopyArgs ax{B.gd, B.gFacc, nullptr, 2 * n};
                     q.add(dis_kernel_baxpy(), dim3((unsigned)((2 * n + 255) / 256)), dim3(256), &ax, sizeof ax, 0,
                           "bwd_copy", 48.0 * n, 2.0 * n);
@@ -271,6 +359,7 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
         sa.gP = B.gP[s];
         sa.gJ0 = B.gJ0[s];
         sa.gJ1 = B.gJ1[s];
+        sa.span = span;
         const void* fs = dis_kernel_bwd_search(ps);
         if (!fs) return dis_fail(h, DIS_EINVAL, "no backward search kernel for patch %d", ps);
         const unsigned nb = (unsigned)(((size_t)N * 16 + 255) / 256);

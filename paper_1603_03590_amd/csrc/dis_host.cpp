@@ -295,7 +295,7 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     int tw, th;
     if (!dis_refine_tile(refine_tile, &tw, &th, nullptr))
         return fail(h, DIS_EINVAL, "unknown refinement tile %d", refine_tile);
-    if (launch_mode < 0 || launch_mode > 3) return fail(h, DIS_EINVAL, "launch mode %d outside 0..3", launch_mode);
+    if (launch_mode < 0 || launch_mode > 7) return fail(h, DIS_EINVAL, "launch mode %d outside 0..7", launch_mode);
     if (lanes_per_patch)
         for (int s = 0; s < DIS_MAXL; ++s) {
             const int l = lanes_per_patch[s];
@@ -307,6 +307,7 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     h->refine_tile = refine_tile;
     h->mode_phase = launch_mode & 1;
     h->small_levels = (launch_mode & 2) ? 1 : 0;
+    h->bwd_reference = (launch_mode & 4) ? 1 : 0;
     return DIS_OK;
 }
 

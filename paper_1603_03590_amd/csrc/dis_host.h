@@ -126,6 +126,7 @@ struct dis_handle {
     int refine_tile = 7;
     int mode_phase = 1;     // 1: one launch per phase, 0: one persistent launch per level
     int small_levels = 0;   // refine pair-levels that fit one workgroup in a single launch
+    int bwd_reference = 0;  // backward: one launch per reverse half sweep instead of reverse tiles
     int n_cu = 256;
     // most recent plain forward call (debug and backward)
     bool have_last = false;

@@ -14,6 +14,7 @@
 // kernels and the persistent level kernel both call them.
 #include <hip/hip_runtime.h>
 #include "dis_internal.h"
+#include "dis_refine_tile.h"
 
 namespace {
 
@@ -172,6 +173,21 @@ __device__ __forceinline__ double csum_prod(const double (&a)[GS * GPL], const d
     return tree_finish<GS, GPL, LPP>(g);
 }
 
+constexpr int isqrt_floor(int v, int r = 0) { return (r + 1) * (r + 1) > v ? r : isqrt_floor(v, r + 1); }
+
+// LDS copy of the second frame around each patch's initial position: a
+// square of PS + 1 + 2R pixels (indices clamped to the image as the
+// bilinear taps clamp them), R as large as 48 KB per block allows (at most
+// 6).  While the patch's integer displacement stays within R of its start
+// the warps read LDS; beyond, global memory.  Same values either way.
+template <int PS, int LPP>
+struct SearchWin {
+    static constexpr int GROUPS = 256 / LPP;
+    static constexpr int FIT = (isqrt_floor(48 * 1024 / 8 / GROUPS) - PS - 1) / 2;
+    static constexpr int R = LPP < 8 ? 0 : (FIT < 0 ? 0 : (FIT > 6 ? 6 : FIT));
+    static constexpr int WS = PS + 1 + 2 * R;
+};
+
 // One block of 256 threads = 256/LPP patches, LPP lanes per patch.  Patch
 // corners, initialisation (Sec. 2.2 steps 1-2), template and Sobel/8
 // gradients, the precomputed 2x2 Hessian, theta_it inverse-compositional
@@ -240,6 +256,21 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
     const double inv_n = 1.0 / (double)NP;
     const double lim = (double)(W + H + 2 * PS + 4);
 
+    // the window of this patch (see SearchWin)
+    using SW = SearchWin<PS, LPP>;
+    constexpr int R = SW::R, WS = SW::WS;
+    __shared__ double s_win[R > 0 ? SW::GROUPS * WS * WS : 1];
+    const int iu0 = (int)fmin(fmax(floor(ui), -lim), lim), iv0 = (int)fmin(fmax(floor(vi), -lim), lim);
+    double* win = s_win + (size_t)(threadIdx.x / LPP) * WS * WS;
+    if constexpr (R > 0) {
+        const int wx = x0 + iu0 - R, wy = y0 + iv0 - R;
+        for (int i = lane; i < WS * WS; i += LPP) {
+            const int Y = i / WS, X = i - Y * WS;
+            win[i] = J1[clampi(wy + Y, 0, H - 1) * W + clampi(wx + X, 0, W - 1)];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+
     double u = ui, v = vi, md = 0.0, moved = 0.0;
     for (int it = 0; it <= a.iters; ++it) {
         if (it == a.iters) {
@@ -253,19 +284,36 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
         const int iu = (int)fmin(fmax(fu, -lim), lim);
         const int iv = (int)fmin(fmax(fv, -lim), lim);
         double d[PPL];
+        const bool in_win = R > 0 && iu - iu0 >= -R && iu - iu0 <= R && iv - iv0 >= -R && iv - iv0 <= R;
+        if (in_win) {
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-            const int p = lane * PPL + k;
-            if (p < NP) {
-                const int py = p / PS, px = p - py * PS;
-                const int xa = x0 + px + iu, ya = y0 + py + iv;
-                const int c0 = clampi(xa, 0, W - 1), c1 = clampi(xa + 1, 0, W - 1);
-                const int r0 = clampi(ya, 0, H - 1) * W, r1 = clampi(ya + 1, 0, H - 1) * W;
-                const double top = (1.0 - ax) * J1[r0 + c0] + ax * J1[r0 + c1];
-                const double bot = (1.0 - ax) * J1[r1 + c0] + ax * J1[r1 + c1];
-                d[k] = ((1.0 - ay) * top + ay * bot) - T[k];
-            } else {
-                d[k] = 0.0;
+            for (int k = 0; k < PPL; ++k) {
+                const int p = lane * PPL + k;
+                if (p < NP) {
+                    const int py = p / PS, px = p - py * PS;
+                    const double* c = win + (py + iv - iv0 + R) * WS + (px + iu - iu0 + R);
+                    const double top = (1.0 - ax) * c[0] + ax * c[1];
+                    const double bot = (1.0 - ax) * c[WS] + ax * c[WS + 1];
+                    d[k] = ((1.0 - ay) * top + ay * bot) - T[k];
+                } else {
+                    d[k] = 0.0;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                const int p = lane * PPL + k;
+                if (p < NP) {
+                    const int py = p / PS, px = p - py * PS;
+                    const int xa = x0 + px + iu, ya = y0 + py + iv;
+                    const int c0 = clampi(xa, 0, W - 1), c1 = clampi(xa + 1, 0, W - 1);
+                    const int r0 = clampi(ya, 0, H - 1) * W, r1 = clampi(ya + 1, 0, H - 1) * W;
+                    const double top = (1.0 - ax) * J1[r0 + c0] + ax * J1[r0 + c1];
+                    const double bot = (1.0 - ax) * J1[r1 + c0] + ax * J1[r1 + c1];
+                    d[k] = ((1.0 - ay) * top + ay * bot) - T[k];
+                } else {
+                    d[k] = 0.0;
+                }
             }
         }
         const double sd = csum<GS, GPL, LPP>(d);
@@ -350,26 +398,7 @@ __device__ __forceinline__ void densify_block(const DensifyArgs& a, int bx, int 
 
 // --------------------------------------------------------------- refinement
 
-// LDS of one refinement tile: the core (TW x TH) grows by up to K = DIS_KMAX
-// pixels per side (the region); the image tile grows by 2 more for the
-// second differences.  The edge-weight planes first hold U + dUf (one more
-// row and column, for the forward differences of E_S); the increments share
-// storage with the image tile, which is dead by the time they are stored.
-template <int TW, int TH>
-struct RefineSmem {
-    static constexpr int K = DIS_KMAX;
-    static constexpr int RWM = TW + 2 * K, RHM = TH + 2 * K;
-    static constexpr int LP = RWM + 1;               // region row pitch
-    static constexpr int IWM = RWM + 4, IHM = RHM + 4;
-    static constexpr int IP = IWM + 1;               // image-tile row pitch
-    double wr[(RHM + 1) * LP];                      // U + dUf (u), then the weight of the edge to the right
-    double wd[(RHM + 1) * LP];                      // U + dUf (v), then the weight of the edge below
-    double uu[RHM * LP], uv[RHM * LP];              // U on the region
-    union {
-        struct { double t0[IHM * IP], t1[IHM * IP]; } img;   // J0 / J1w
-        struct { double du[RHM * LP], dv[RHM * LP]; } inc;
-    } u;
-};
+using dis_tile::RefineSmem;
 
 // One tile of one fixed-point step of the refinement (Sec. 2.3).  The core
 // is extended by nhalf pixels on every side that is not the image border;
@@ -378,205 +407,26 @@ struct RefineSmem {
 // sweeps the core equals the untiled result exactly.  Each of the NT threads
 // owns pairs of horizontally adjacent pixels (one of each colour) and keeps
 // their SOR coefficients in registers; LDS holds the increments, the edge
-// weights and U.  Every global read is issued in one round at the start
-// (with few pairs per thread, the frozen and starting increments of the
-// owned pixels go straight to registers).
+// weights and U.  Every global read is issued in one round at the start.
 template <int TW, int TH, int NT>
 __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, RefineSmem<TW, TH>& sm) {
     using S = RefineSmem<TW, TH>;
-    constexpr int LP = S::LP, IP = S::IP;
-    constexpr int PWM = (S::RWM + 1) / 2;
-    constexpr int PPT = (PWM * S::RHM + NT - 1) / NT;
-    constexpr bool kStage = PPT <= 2 && NT <= 512;   // register budget of 1024-thread blocks
-
-    const int W = a.W, H = a.H;
-    const size_t n = (size_t)W * H;
+    using Shape = dis_tile::TileShape<TW, TH, NT>;
+    constexpr int LP = S::LP;
+    constexpr int PPT = Shape::PPT;
+    constexpr bool kStage = Shape::kStage;
     const int kh = __builtin_amdgcn_readfirstlane(a.nhalf);   // steers a loop with barriers
-    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int cx0 = tx * TW, cy0 = ty * TH;
-    const int cx1 = min(cx0 + TW, W), cy1 = min(cy0 + TH, H);
-    const int rx0 = max(cx0 - kh, 0), ry0 = max(cy0 - kh, 0);
-    const int rx1 = min(cx1 + kh, W), ry1 = min(cy1 + kh, H);
-    const int RW = rx1 - rx0, RH = ry1 - ry0;
-    const int npw = (RW + 1) / 2;
-    const double* __restrict__ U = a.U;
-    const double* __restrict__ F = a.dUf;
+    const dis_tile::TileGeom g = dis_tile::tile_geom<TW, TH>(a.W, a.H, a.tiles_x, tile, kh);
+    const int W = g.W, H = g.H;
+    const size_t n = (size_t)W * H;
+    const int rx0 = g.rx0, ry0 = g.ry0, RW = g.RW, RH = g.RH;
+    const int cx0 = g.cx0, cy0 = g.cy0, cx1 = g.cx1, cy1 = g.cy1;
     const double* __restrict__ Din = a.dUin;
+    const double om1 = 1.0 - a.omega;
 
-    // owned pixels: pair pr = thread + k NT, row ly, pair m of the row; the
-    // pixel of colour c sits at column 2m + ((rx0 + y) & 1) ^ c
-    int c_l[PPT][2];
-    double s_fu[kStage ? PPT : 1][2], s_fv[kStage ? PPT : 1][2];
-    double s_iu[kStage ? PPT : 1][2], s_iv[kStage ? PPT : 1][2];
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int pr = threadIdx.x + k * NT;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            c_l[k][c] = -1;
-            if constexpr (kStage) { s_fu[k][c] = s_fv[k][c] = s_iu[k][c] = s_iv[k][c] = 0.0; }
-            if (pr >= npw * RH) continue;
-            const int ly = pr / npw, m = pr - ly * npw;
-            const int lx = 2 * m + (((rx0 + ry0 + ly) & 1) ^ c);
-            if (lx >= RW) continue;
-            c_l[k][c] = ly * LP + lx;
-            if constexpr (kStage) {
-                const size_t g = (size_t)(ry0 + ly) * W + rx0 + lx;
-                if (F) { s_fu[k][c] = F[g]; s_fv[k][c] = F[n + g]; }
-                if (Din) { s_iu[k][c] = Din[g]; s_iv[k][c] = Din[n + g]; }
-            }
-        }
-    }
-
-    // 1. U + dUf on the region plus one column / row (into wr / wd), U on
-    //    the region, J0 and the warped J1w on the region plus two pixels
-    const int ix0 = max(rx0 - 2, 0), iy0 = max(ry0 - 2, 0);
-    {
-        const int ex1 = min(rx1 + 1, W), ey1 = min(ry1 + 1, H);
-        const int EW = ex1 - rx0, EH = ey1 - ry0;
-#pragma unroll 2
-        for (int i = threadIdx.x; i < EW * EH; i += NT) {
-            const int ly = i / EW, lx = i - ly * EW;
-            const size_t g = (size_t)(ry0 + ly) * W + rx0 + lx;
-            const double u0 = U[g], v0 = U[n + g];
-            sm.wr[ly * LP + lx] = F ? u0 + F[g] : u0;
-            sm.wd[ly * LP + lx] = F ? v0 + F[n + g] : v0;
-            if (lx < RW && ly < RH) {
-                sm.uu[ly * LP + lx] = u0;
-                sm.uv[ly * LP + lx] = v0;
-            }
-        }
-        const int ix1 = min(rx1 + 2, W), iy1 = min(ry1 + 2, H);
-        const int IW = ix1 - ix0, IH = iy1 - iy0;
-#pragma unroll 2
-        for (int i = threadIdx.x; i < IW * IH; i += NT) {
-            const int ly = i / IW, lx = i - ly * IW;
-            const size_t g = (size_t)(iy0 + ly) * W + ix0 + lx;
-            sm.u.img.t0[ly * IP + lx] = a.J0[g];
-            sm.u.img.t1[ly * IP + lx] = a.J1w[g];
-        }
-    }
-    __syncthreads();
-    // 2. smoothness weight alpha / (2 sqrt(E_S + eps^2)) of every owned
-    //    pixel, from forward differences (zero across the last column / row)
-    const double eps2 = a.eps * a.eps;
-    double c_ws[PPT][2];
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            c_ws[k][c] = 0.0;
-            const int e = c_l[k][c];
-            if (e < 0) continue;
-            const int ly = e / LP, lx = e - ly * LP;
-            const int x = rx0 + lx, y = ry0 + ly;
-            const double u0 = sm.wr[e], v0 = sm.wd[e];
-            double dxu = 0.0, dyu = 0.0, dxv = 0.0, dyv = 0.0;
-            if (x < W - 1) { dxu = sm.wr[e + 1] - u0; dxv = sm.wd[e + 1] - v0; }
-            if (y < H - 1) { dyu = sm.wr[e + LP] - u0; dyv = sm.wd[e + LP] - v0; }
-            const double es = ((dxu * dxu + dyu * dyu) + dxv * dxv) + dyv * dyv;
-            c_ws[k][c] = a.alpha / (2.0 * sqrt(es + eps2));
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int e = c_l[k][c];
-            if (e < 0) continue;
-            const int ly = e / LP, lx = e - ly * LP;
-            sm.wr[e] = rx0 + lx < W - 1 ? c_ws[k][c] : 0.0;
-            sm.wd[e] = ry0 + ly < H - 1 ? c_ws[k][c] : 0.0;
-        }
-    }
-    __syncthreads();
-
-    // 3. per owned pixel: linearisation (central differences [-1 0 1]/2 with
-    //    replicated borders of (J0+J1w)/2 and of J1w - J0, the normalisations
-    //    beta), robust data weights at the frozen increment, SOR coefficients
-    const double om = a.omega, om1 = 1.0 - a.omega;
-    int c_m[PPT][2];
-    double c_wr[PPT][2], c_wl[PPT][2], c_wd[PPT][2], c_wu[PPT][2];
-    double c_a12[PPT][2], c_i1[PPT][2], c_i2[PPT][2], c_c1[PPT][2], c_c2[PPT][2];
-    {
-        const double* t0 = sm.u.img.t0;
-        const double* t1 = sm.u.img.t1;
-        // image-tile index of a position already clamped to the image
-        auto li = [&](int x, int y) { return (y - iy0) * IP + (x - ix0); };
-        auto Ib = [&](int x, int y) { const int l = li(x, y); return 0.5 * (t0[l] + t1[l]); };
-        auto Ixa = [&](int x, int y) {
-            return (Ib(min(x + 1, W - 1), y) - Ib(max(x - 1, 0), y)) / 2.0;
-        };
-        auto Iya = [&](int x, int y) {
-            return (Ib(x, min(y + 1, H - 1)) - Ib(x, max(y - 1, 0))) / 2.0;
-        };
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                c_m[k][c] = 0;
-                c_wr[k][c] = c_wl[k][c] = c_wd[k][c] = c_wu[k][c] = 0.0;
-                c_a12[k][c] = c_i1[k][c] = c_i2[k][c] = c_c1[k][c] = c_c2[k][c] = 0.0;
-                const int l = c_l[k][c];
-                if (l < 0) continue;
-                const int ly = l / LP, lx = l - ly * LP;
-                const int x = rx0 + lx, y = ry0 + ly;
-                const size_t g = (size_t)y * W + x;
-                const int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
-                const int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
-                const double Ix = Ixa(x, y), Iy = Iya(x, y);
-                const int lc = li(x, y);
-                const double Iz = t1[lc] - t0[lc];
-                const double Ixx = (Ixa(xp, y) - Ixa(xm, y)) / 2.0;
-                const double Ixy = (Ixa(x, yp) - Ixa(x, ym)) / 2.0;
-                const double Iyy = (Iya(x, yp) - Iya(x, ym)) / 2.0;
-                const int lxp = li(xp, y), lxm = li(xm, y), lyp = li(x, yp), lym = li(x, ym);
-                const double Ixz = (t1[lxp] - t1[lxm]) / 2.0 - (t0[lxp] - t0[lxm]) / 2.0;
-                const double Iyz = (t1[lyp] - t1[lym]) / 2.0 - (t0[lyp] - t0[lym]) / 2.0;
-                const double b0 = 1.0 / ((Ix * Ix + Iy * Iy) + 0.01);
-                const double bx = 1.0 / ((Ixx * Ixx + Ixy * Ixy) + 0.01);
-                const double by = 1.0 / ((Ixy * Ixy + Iyy * Iyy) + 0.01);
-                double fu, fv;
-                if constexpr (kStage) { fu = s_fu[k][c]; fv = s_fv[k][c]; }
-                else { fu = F ? F[g] : 0.0; fv = F ? F[n + g] : 0.0; }
-                const double ri = (Ix * fu + Iy * fv) + Iz;
-                const double ei = b0 * (ri * ri);
-                const double rx = (Ixx * fu + Ixy * fv) + Ixz;
-                const double ry = (Ixy * fu + Iyy * fv) + Iyz;
-                const double eg = bx * (rx * rx) + by * (ry * ry);
-                const double pi_ = a.delta / (2.0 * sqrt(ei + eps2));
-                const double pg = a.gamma / (2.0 * sqrt(eg + eps2));
-                const double A11 = ((pi_ * b0) * Ix) * Ix + pg * (((bx * Ixx) * Ixx) + ((by * Ixy) * Ixy));
-                const double A12 = ((pi_ * b0) * Ix) * Iy + pg * (((bx * Ixx) * Ixy) + ((by * Ixy) * Iyy));
-                const double A22 = ((pi_ * b0) * Iy) * Iy + pg * (((bx * Ixy) * Ixy) + ((by * Iyy) * Iyy));
-                const double B1 = ((pi_ * b0) * Ix) * Iz + pg * (((bx * Ixx) * Ixz) + ((by * Ixy) * Iyz));
-                const double B2 = ((pi_ * b0) * Iy) * Iz + pg * (((bx * Ixy) * Ixz) + ((by * Iyy) * Iyz));
-                // edges: right/down owned by this pixel, left/up by the
-                // neighbour; neighbours outside the region (not the image) are
-                // dropped, which only disturbs pixels the erosion discards
-                const bool hr = x < W - 1 && lx + 1 < RW, hl = x > 0 && lx > 0;
-                const bool hd = y < H - 1 && ly + 1 < RH, hu = y > 0 && ly > 0;
-                const double wr = hr ? sm.wr[l] : 0.0, wl = hl ? sm.wr[l - 1] : 0.0;
-                const double wd = hd ? sm.wd[l] : 0.0, wu = hu ? sm.wd[l - LP] : 0.0;
-                const double Ssum = ((wr + wl) + wd) + wu;
-                const double Up = sm.uu[l], Vp = sm.uv[l];
-                const double Ur = hr ? sm.uu[l + 1] : 0.0, Ul = hl ? sm.uu[l - 1] : 0.0;
-                const double Ud = hd ? sm.uu[l + LP] : 0.0, Uu = hu ? sm.uu[l - LP] : 0.0;
-                const double Vr = hr ? sm.uv[l + 1] : 0.0, Vl = hl ? sm.uv[l - 1] : 0.0;
-                const double Vd = hd ? sm.uv[l + LP] : 0.0, Vu = hu ? sm.uv[l - LP] : 0.0;
-                const double NU = ((wr * Ur + wl * Ul) + wd * Ud) + wu * Uu;
-                const double NV = ((wr * Vr + wl * Vl) + wd * Vd) + wu * Vu;
-                c_m[k][c] = (hr ? 1 : 0) | (hl ? 2 : 0) | (hd ? 4 : 0) | (hu ? 8 : 0);
-                c_wr[k][c] = wr; c_wl[k][c] = wl; c_wd[k][c] = wd; c_wu[k][c] = wu;
-                c_a12[k][c] = A12;
-                c_i1[k][c] = om / (A11 + Ssum);
-                c_i2[k][c] = om / (A22 + Ssum);
-                c_c1[k][c] = (NU - Ssum * Up) - B1;
-                c_c2[k][c] = (NV - Ssum * Vp) - B2;
-            }
-        }
-    }
+    dis_tile::TileCoef<PPT> C;
+    double s_iu[Shape::NS][2], s_iv[Shape::NS][2];
+    dis_tile::refine_setup<TW, TH, NT>(a, g, sm, C, s_iu, s_iv);
     __syncthreads();   // the image tile is dead from here on
     // 4. sweep start
     double* du_ = sm.u.inc.du;
@@ -586,7 +436,7 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
         for (int k = 0; k < PPT; ++k) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const int l = c_l[k][c];
+                const int l = C.l[k][c];
                 if (l < 0) continue;
                 du_[l] = s_iu[k][c];
                 dv_[l] = s_iv[k][c];
@@ -596,9 +446,9 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
 #pragma unroll 4
         for (int i = threadIdx.x; i < RW * RH; i += NT) {
             const int ly = i / RW, lx = i - ly * RW;
-            const size_t g = (size_t)(ry0 + ly) * W + rx0 + lx;
-            du_[ly * LP + lx] = Din ? Din[g] : 0.0;
-            dv_[ly * LP + lx] = Din ? Din[n + g] : 0.0;
+            const size_t gi = (size_t)(ry0 + ly) * W + rx0 + lx;
+            du_[ly * LP + lx] = Din ? Din[gi] : 0.0;
+            dv_[ly * LP + lx] = Din ? Din[n + gi] : 0.0;
         }
     }
     __syncthreads();
@@ -609,18 +459,18 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
         for (int c = 0; c < 2; ++c) {
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                const int l = c_l[k][c];
+                const int l = C.l[k][c];
                 if (l < 0) continue;
-                const int m = c_m[k][c];
+                const int m = C.m[k][c];
                 const int lr = (m & 1) ? l + 1 : l, ll = (m & 2) ? l - 1 : l;
                 const int ld = (m & 4) ? l + LP : l, lu = (m & 8) ? l - LP : l;
                 const double du = du_[l], dv = dv_[l];
-                const double nu = ((c_wr[k][c] * du_[lr] + c_wl[k][c] * du_[ll]) + c_wd[k][c] * du_[ld]) +
-                                  c_wu[k][c] * du_[lu];
-                const double dun = om1 * du + c_i1[k][c] * ((nu + c_c1[k][c]) - c_a12[k][c] * dv);
-                const double nv = ((c_wr[k][c] * dv_[lr] + c_wl[k][c] * dv_[ll]) + c_wd[k][c] * dv_[ld]) +
-                                  c_wu[k][c] * dv_[lu];
-                const double dvn = om1 * dv + c_i2[k][c] * ((nv + c_c2[k][c]) - c_a12[k][c] * dun);
+                const double nu = ((C.wr[k][c] * du_[lr] + C.wl[k][c] * du_[ll]) + C.wd[k][c] * du_[ld]) +
+                                  C.wu[k][c] * du_[lu];
+                const double dun = om1 * du + C.i1[k][c] * ((nu + C.c1[k][c]) - C.a12[k][c] * dv);
+                const double nv = ((C.wr[k][c] * dv_[lr] + C.wl[k][c] * dv_[ll]) + C.wd[k][c] * dv_[ld]) +
+                                  C.wu[k][c] * dv_[lu];
+                const double dvn = om1 * dv + C.i2[k][c] * ((nv + C.c2[k][c]) - C.a12[k][c] * dun);
                 du_[l] = dun;
                 dv_[l] = dvn;
             }
@@ -632,10 +482,10 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
                 const int CW = cx1 - cx0, CH = cy1 - cy0;
                 for (int i = threadIdx.x; i < CW * CH; i += NT) {
                     const int yy = i / CW, xx = i - yy * CW;
-                    const size_t g = (size_t)(cy0 + yy) * W + cx0 + xx;
+                    const size_t gi = (size_t)(cy0 + yy) * W + cx0 + xx;
                     const int l = (cy0 + yy - ry0) * LP + (cx0 + xx - rx0);
-                    tp[g] = du_[l];
-                    tp[n + g] = dv_[l];
+                    tp[gi] = du_[l];
+                    tp[n + gi] = dv_[l];
                 }
                 __syncthreads();   // the next half sweep rewrites what was just copied
             }
@@ -647,14 +497,14 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
     for (int i = threadIdx.x; i < CW * CH; i += NT) {
         const int yy = i / CW, xx = i - yy * CW;
         const int x = cx0 + xx, y = cy0 + yy;
-        const size_t g = (size_t)y * W + x;
+        const size_t gi = (size_t)y * W + x;
         const int l = (y - ry0) * LP + (x - rx0);
         const double du = du_[l], dv = dv_[l];
-        a.dUout[g] = du;
-        a.dUout[n + g] = dv;
+        a.dUout[gi] = du;
+        a.dUout[n + gi] = dv;
         if (a.Uout) {
-            a.Uout[g] = sm.uu[l] + du;
-            a.Uout[n + g] = sm.uv[l] + dv;
+            a.Uout[gi] = sm.uu[l] + du;
+            a.Uout[n + gi] = sm.uv[l] + dv;
         }
     }
     __syncthreads();   // LDS is reused by the caller's next tile

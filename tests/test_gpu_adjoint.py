@@ -176,6 +176,35 @@ def test_backward_repeat_and_graph_agree_with_eager():
         d.close()
 
 
+@pytest.mark.parametrize("name,cr,over", [
+    ("c5_crop6", (6, 32, 32), {}),
+    ("ragged_45x37", (5, 45, 37), {}),
+    ("vi7_two_launches_per_step", (2, 40, 32), dict(var_inner=7)),
+    ("vo_auto_sf1", (4, 48, 40), dict(var_outer=-1, finest_scale=1, coarsest_scale=2)),
+])
+def test_tiled_reverse_sweeps_match_reference_form(name, cr, over):
+    """The tiled reverse of each fixed-point step against one launch per
+    reverse half sweep (launch mode bit 2), and both against the oracle."""
+    say(f"[adjoint] case tiled vs reference {name}")
+    I0, I1, gt = crop(*cr)
+    h, w = I0.shape
+    p = params(105, flags=F64 | KEEP, **over)
+    grads = []
+    for mode in (1, 1 | 4):
+        d = DIS(p, w, h)
+        try:
+            d.set_tunables(None, 7, mode)
+            grads.append(gpu_grad(I0, I1, gt, p, d))
+        finally:
+            d.close()
+    _, r0, r1 = oracle_grad(I0, I1, gt, p)
+    (_, t0, t1), (_, f0, f1) = grads
+    say(f"[adjoint] {name}: tiled vs reference {rel_err(t0, f0):.2e} {rel_err(t1, f1):.2e}, "
+        f"tiled vs oracle {rel_err(t0, r0):.2e}")
+    assert rel_err(t0, f0) <= 1e-11 and rel_err(t1, f1) <= 1e-11
+    assert rel_err(t0, r0) <= 1e-7 and rel_err(t1, r1) <= 1e-7
+
+
 def test_backward_after_other_size_forward():
     """One handle, two sizes: each backward differentiates its own forward."""
     say("[adjoint] case two sizes on one handle")
