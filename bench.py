@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline operating point (no launch-mode comparison, no second point); "
                          "for profiler runs")
+    ap.add_argument("--tunables", default="",
+                    help="skip the autotuner and fix the launch choices of the headline, e.g. 'tile=7,mode=1,lanes=16' "
+                         "(for counter runs, where the profiler's serialisation would mislead the autotuner)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB five times (calibrates HBM counters)")
     ap.add_argument("--fwd-bwd-pairs", type=int, default=8,
@@ -117,7 +120,13 @@ def main():
             d.set_tunables(None, 0, mode)
             modes[name] = time_calls(flow, args.steps, args.warmup) * 1e3
         flow()
-        d.autotune()
+        if args.tunables:
+            kv = dict(x.split("=") for x in args.tunables.split(","))
+            lanes = int(kv.get("lanes", 0))
+            d.set_tunables([lanes] * 16 if lanes else None, int(kv.get("tile", 7)), int(kv.get("mode", 1)))
+        else:
+            d.autotune()
+        tuned = d.tunables()
         dt = time_calls(flow, args.steps, args.warmup)
         f_tuned = out.cpu().numpy().astype(np.float64)
         # per-kernel event timing on the library's stream (tuned choices)
@@ -130,7 +139,7 @@ def main():
         kstats = _lib.dis_profile_read(d.handle)
         _lib.dis_profile_enable(d.handle, False)
         d.close()
-        results[op] = dict(ms=dt * 1e3, modes=modes, flow=f_tuned, kernels=kstats)
+        results[op] = dict(ms=dt * 1e3, modes=modes, flow=f_tuned, kernels=kstats, tuned=tuned)
         log(f"[bench] {op}: tuned {dt * 1e3:.4f} ms/pair; untuned {modes}")
 
     head = results[args.op]
@@ -145,7 +154,19 @@ def main():
     else:
         achieved = top["bytes"] / top["launches"] / (avg_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS)
-    roof.update(traffic=None, kernel=top["name"], launches_per_step=top["launches"] / args.profile_steps,
+    # HBM traffic per launch of that kernel family, from the committed
+    # counter summary when it was taken on these kernel sources with this
+    # refinement tile (else null)
+    traffic = None
+    traffic_src = None
+    from paper_1603_03590_amd import profsum
+    rec = profsum.read_traffic(os.path.join(ROOT, "profiles", f"{top['name']}_c2a_1024x436_hbm_traffic.md"))
+    if rec and rec.get("source_sha") == profsum.source_hash() and (
+            top["name"] != "refine" or int(rec.get("tile", -1)) == head["tuned"]["refine_tile"]):
+        traffic = float(rec["bytes_per_launch"])
+        traffic_src = f"profiles/{top['name']}_c2a_1024x436_hbm_traffic.md"
+    roof.update(traffic=traffic, traffic_source=traffic_src, kernel=top["name"],
+                launches_per_step=top["launches"] / args.profile_steps,
                 avg_launch_us=avg_ms * 1e3, algorithmic_bytes_per_launch=top["bytes"] / top["launches"],
                 algorithmic_flops_per_launch=top["flops"] / top["launches"])
 
@@ -351,6 +372,7 @@ def main():
         "parity": parity,
         "kernels": kernel_table(head["kernels"], args.profile_steps),
         "untuned_ms_per_step": head["modes"],
+        "tunables": head["tuned"],
         "other_operating_point": ({other: dict(ms_per_step=results[other]["ms"],
                                                value=W * H / (results[other]["ms"] * 1e-3) / 1e6,
                                                untuned_ms_per_step=results[other]["modes"])}

@@ -179,6 +179,13 @@ int dis_autotune(dis_handle* h, const char* cache_path);
  */
 int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int refine_tile, int launch_mode);
 
+/*
+ * Read back the launch choices in force (after dis_autotune, say): any of
+ * the HOST pointers may be NULL; lanes_per_patch receives 16 ints.
+ * Errors: DIS_EINVAL (h NULL).
+ */
+int dis_get_tunables(const dis_handle* h, int* lanes_per_patch, int* refine_tile, int* launch_mode);
+
 /* Message for the most recent failing call on h (or on a NULL handle). */
 const char* dis_last_error(const dis_handle* h);
 

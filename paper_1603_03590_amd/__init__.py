@@ -118,6 +118,9 @@ class DIS:
     def set_tunables(self, lanes_per_patch=None, refine_tile=0, launch_mode=0):
         _lib.dis_set_tunables(self.handle, lanes_per_patch, refine_tile, launch_mode)
 
+    def tunables(self) -> dict:
+        return _lib.dis_get_tunables(self.handle)
+
     def autotune(self, cache_path=None):
         _lib.dis_autotune(self.handle, cache_path)
 

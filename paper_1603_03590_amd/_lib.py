@@ -45,6 +45,7 @@ EXPORTS = (
     "dis_default_params", "dis_create", "dis_compute_flow", "dis_compute_flow_batched",
     "dis_flow_backward", "dis_autotune", "dis_last_error", "dis_set_stream",
     "dis_debug_level", "dis_destroy", "dis_profile_enable", "dis_profile_read", "dis_set_tunables",
+    "dis_get_tunables",
 )
 
 
@@ -115,6 +116,7 @@ def load(path: str = LIB_PATH):
     lib.dis_profile_enable.argtypes = [H, c_int]
     lib.dis_profile_read.argtypes = [H, POINTER(dis_kernel_stat), c_int, POINTER(c_int)]
     lib.dis_set_tunables.argtypes = [H, POINTER(c_int), c_int, c_int]
+    lib.dis_get_tunables.argtypes = [H, POINTER(c_int), POINTER(c_int), POINTER(c_int)]
     lib.dis_destroy.argtypes = [H]
     lib.dis_destroy.restype = None
     for name in EXPORTS:
@@ -192,6 +194,15 @@ def dis_profile_read(handle: int, max_kernels: int = 32):
     _check(load().dis_profile_read(c_void_p(handle), arr, max_kernels, ctypes.byref(n)), c_void_p(handle))
     return [dict(name=arr[i].name.decode(), launches=arr[i].launches, total_ms=arr[i].total_ms,
                  bytes=arr[i].bytes, flops=arr[i].flops) for i in range(min(n.value, max_kernels))]
+
+
+def dis_get_tunables(handle: int) -> dict:
+    """{lanes_per_patch: [16 ints], refine_tile, launch_mode} in force on the handle."""
+    arr = (c_int * 16)()
+    tile = c_int()
+    mode = c_int()
+    _check(load().dis_get_tunables(c_void_p(handle), arr, ctypes.byref(tile), ctypes.byref(mode)), c_void_p(handle))
+    return {"lanes_per_patch": list(arr), "refine_tile": tile.value, "launch_mode": mode.value}
 
 
 def dis_set_tunables(handle: int, lanes_per_patch=None, refine_tile: int = 0, launch_mode: int = 0) -> None:

@@ -471,7 +471,8 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
     __shared__ BwdStepSmem<TW, TH> sm;
     const RefineArgs& a = A.ra;
     const int kh = __builtin_amdgcn_readfirstlane(A.j_hi - A.j_lo);
-    const dis_tile::TileGeom g = dis_tile::tile_geom<TW, TH>(a.W, a.H, a.tiles_x, blockIdx.x, kh + 1);
+    const dis_tile::TileGeom g =
+        dis_tile::tile_geom<TW, TH>(a.W, a.H, a.tiles_x, dis_xcd_tile(blockIdx.x, gridDim.x), kh + 1);
     const int W = g.W;
     const size_t n = (size_t)W * g.H;
     const int rx0 = g.rx0, ry0 = g.ry0, RW = g.RW, RH = g.RH;

@@ -311,6 +311,15 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     return DIS_OK;
 }
 
+extern "C" int dis_get_tunables(const dis_handle* h, int* lanes_per_patch, int* refine_tile, int* launch_mode) {
+    if (!h) return fail(nullptr, DIS_EINVAL, "handle is NULL");
+    if (lanes_per_patch)
+        for (int s = 0; s < DIS_MAXL; ++s) lanes_per_patch[s] = h->lpp[s];
+    if (refine_tile) *refine_tile = h->refine_tile;
+    if (launch_mode) *launch_mode = h->mode_phase | (h->small_levels ? 2 : 0) | (h->bwd_reference ? 4 : 0);
+    return DIS_OK;
+}
+
 extern "C" int dis_set_stream(dis_handle* h, void* stream) {
     if (!h) return fail(nullptr, DIS_EINVAL, "handle is NULL");
     h->stream = (hipStream_t)stream;
@@ -740,24 +749,36 @@ static int prof_event(dis_handle* h, hipEvent_t* e) {
     return DIS_OK;
 }
 
+// Launch a sequence kernel by kernel.  With profiling on, each run of
+// consecutive launches of one kernel family sits between one pair of events
+// (so the per-launch average carries one event gap per run, not per launch).
 int dis_launch_eager(dis_handle* h, Seq& seq) {
-    for (Launch& L : seq.items) {
-        void* args[1] = {L.arg.data()};
+    const size_t n = seq.items.size();
+    for (size_t i = 0; i < n;) {
+        size_t j = i + 1;
+        if (h->profiling)
+            while (j < n && std::strcmp(seq.items[j].name, seq.items[i].name) == 0) ++j;
+        ProfPending pp{};
         if (h->profiling) {
-            ProfPending pp;
             int r = prof_event(h, &pp.a);
             if (r == DIS_OK) r = prof_event(h, &pp.b);
             if (r != DIS_OK) return r;
-            pp.name = L.name;
-            pp.bytes = L.bytes;
-            pp.flops = L.flops;
+            pp.name = seq.items[i].name;
+            pp.launches = (int)(j - i);
             HIPCHK(h, hipEventRecord(pp.a, h->stream));
+        }
+        for (size_t k = i; k < j; ++k) {
+            Launch& L = seq.items[k];
+            void* args[1] = {L.arg.data()};
             HIPCHK(h, hipLaunchKernel(L.fn, L.grid, L.block, args, L.shmem, h->stream));
+            pp.bytes += L.bytes;
+            pp.flops += L.flops;
+        }
+        if (h->profiling) {
             HIPCHK(h, hipEventRecord(pp.b, h->stream));
             h->prof_pending.push_back(pp);
-        } else {
-            HIPCHK(h, hipLaunchKernel(L.fn, L.grid, L.block, args, L.shmem, h->stream));
         }
+        i = j;
     }
     return DIS_OK;
 }
@@ -776,7 +797,7 @@ extern "C" int dis_profile_read(dis_handle* h, dis_kernel_stat* out, int max, in
         float ms = 0.f;
         HIPCHK(h, hipEventElapsedTime(&ms, pp.a, pp.b));
         ProfStat& st = h->prof[pp.name];
-        st.launches += 1;
+        st.launches += pp.launches;
         st.ms += ms;
         st.bytes += pp.bytes;
         st.flops += pp.flops;

@@ -60,6 +60,7 @@ struct ProfStat {
 struct ProfPending {
     hipEvent_t a, b;
     const char* name;
+    int launches;           // consecutive launches of one family between the two events
     double bytes, flops;
 };
 

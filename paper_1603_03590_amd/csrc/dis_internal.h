@@ -152,6 +152,15 @@ struct UpsTab {
     int n;
 };
 
+// Workgroups are handed to the 8 XCDs round-robin (block b to XCD b mod 8),
+// and each XCD has its own L2.  Blocks whose tiles share halo should sit on
+// one XCD: this maps the blocks XCD x receives to the x-th contiguous run of
+// n / 8 (or one more) tile indices.  A bijection on [0, n).
+__device__ __forceinline__ int dis_xcd_tile(int b, int n) {
+    const int x = b & 7, j = b >> 3, per = n >> 3, rem = n & 7;
+    return x * per + (x < rem ? x : rem) + j;
+}
+
 // Kernel entry points, looked up by the host.
 const void* dis_kernel_pyramid();
 const void* dis_kernel_pyramid_tab();

@@ -535,7 +535,7 @@ __global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
     const LevelLaunch& L = PL.L;
     const int phase = PL.phase;
     const int np = L.npairs, s0 = phase * np;
-    const int t = __builtin_amdgcn_readfirstlane(L.start[s0]) + blockIdx.x;
+    const int t = __builtin_amdgcn_readfirstlane(L.start[s0]) + dis_xcd_tile(blockIdx.x, gridDim.x);
     const int j = seg_find(L.start, s0, s0 + np, t) - s0;
     const LevelPair& P = L.pairs[j];
     const RefPhase rp = L.rph[phase - 2];
