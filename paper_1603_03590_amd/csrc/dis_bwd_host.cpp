@@ -241,6 +241,8 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
                         f.U = L.Ud;
                         f.J0 = L.J0;
                         f.J1w = sb.J1w;
+                        f.lin = sb.lin;
+                        f.lin_mode = 2;   // filled by the recomputation's first refinement launch
                         f.dUf = ra.F;
                         f.W = W;
                         f.H = H;

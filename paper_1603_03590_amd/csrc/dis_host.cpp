@@ -190,6 +190,7 @@ static int alloc_slot(dis_handle* h, SlotBuf& sb) {
     const size_t pf = (size_t)(W >> sf) * (H >> sf);
     if (p.refine) {
         DALLOC(h, sb.J1w, pf * sizeof(double));
+        DALLOC(h, sb.lin, 11 * pf * sizeof(double));
         for (int i = 0; i < 3; ++i) DALLOC(h, sb.dU[i], 2 * pf * sizeof(double));
     }
     return DIS_OK;
@@ -558,6 +559,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             da.Z = opt ? opt->Z : nullptr;
             RefineArgs& ra = P.ra;
             ra.U = L.Ud; ra.J0 = L.J0; ra.J1w = sb.J1w; ra.Uout = L.U;
+            ra.lin = sb.lin;
             ra.tape = opt ? opt->tape : nullptr;
             ra.W = W; ra.H = Hh;
             ra.tiles_x = (W + tw - 1) / tw;

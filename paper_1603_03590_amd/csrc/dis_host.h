@@ -26,6 +26,7 @@ struct LevelBuf {
 struct SlotBuf {
     LevelBuf lv[DIS_MAXL];
     double* J1w;     // warped frame 1 of the level being refined
+    double* lin;     // [11][H][W] linearisation of the level being refined
     double* dU[3];   // refinement increments (frozen / in / out rotation)
 };
 

@@ -69,6 +69,12 @@ struct RefineArgs {
     double* Uout;
     double* tape;           // when non-null: state after half sweep m at tape + m*2*W*H (m >= 1)
     int tape_m0;            // half sweeps of this level done before this launch
+    // linearisation of the level (Ix, Iy, Iz, Ixx, Ixy, Iyy, Ixz, Iyz and the
+    // three normalisers: [11][H][W]); it depends on J0 and J1w only, so the
+    // level's first launch writes it (lin_mode 1, core pixels) and later
+    // launches read it for their pixels instead of recomputing (lin_mode 2)
+    double* lin;
+    int lin_mode;           // 0 compute, 1 compute and store, 2 load
     int W, H;
     int nhalf;
     int tiles_x;

@@ -546,6 +546,7 @@ __global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
     ra.Uout = rp.last ? P.ra.Uout : nullptr;
     ra.nhalf = rp.nhalf;
     ra.tape_m0 = rp.m0;
+    ra.lin_mode = rp.m0 == 0 ? 1 : 2;   // the level's first launch fills the linearisation cache
     refine_tile<TW, TH, NT>(ra, t - __builtin_amdgcn_readfirstlane(L.start[s0 + j]), sm);
 }
 
@@ -883,6 +884,7 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
                 ra.Uout = rp.last ? P.ra.Uout : nullptr;
                 ra.nhalf = __builtin_amdgcn_readfirstlane(rp.nhalf);
                 ra.tape_m0 = rp.m0;
+                ra.lin_mode = rp.m0 == 0 ? 1 : 2;
                 refine_tile<32, 16, 256>(ra, local, sm);
             }
         }

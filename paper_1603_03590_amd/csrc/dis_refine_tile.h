@@ -76,6 +76,8 @@ struct TileShape {
     static constexpr int PPT = ((S::RWM + 1) / 2 * S::RHM + NT - 1) / NT;
     static constexpr bool kStage = PPT <= 2 && NT <= 512;   // register budget of 1024-thread blocks
     static constexpr int NS = kStage ? PPT : 1;
+    static constexpr bool kLin = PPT <= 2 && NT <= 512;     // linearisation may come from the level's cache
+    static constexpr int NL = kLin ? PPT : 1;
 };
 
 // Steps 1-3 of a tile: one round of global loads (U + dUf on the region plus
@@ -101,7 +103,11 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
     const double* __restrict__ F = a.dUf;
     const double* __restrict__ Din = a.dUin;
 
+    constexpr bool kLin = TileShape<TW, TH, NT, KG>::kLin;
+    constexpr int NL = TileShape<TW, TH, NT, KG>::NL;
+    const bool lin_load = kLin && a.lin_mode == 2;
     double s_fu[kStage ? PPT : 1][2], s_fv[kStage ? PPT : 1][2];
+    double s_lin[NL][2][11];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int pr = threadIdx.x + k * NT;
@@ -114,10 +120,16 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
             const int lx = 2 * m + (((rx0 + ry0 + ly) & 1) ^ c);
             if (lx >= RW) continue;
             C.l[k][c] = ly * LP + lx;
+            const size_t gi = (size_t)(ry0 + ly) * W + rx0 + lx;
             if constexpr (kStage) {
-                const size_t gi = (size_t)(ry0 + ly) * W + rx0 + lx;
                 if (F) { s_fu[k][c] = F[gi]; s_fv[k][c] = F[n + gi]; }
                 if (Din) { s_iu[k][c] = Din[gi]; s_iv[k][c] = Din[n + gi]; }
+            }
+            if constexpr (kLin) {
+                if (lin_load) {
+#pragma unroll
+                    for (int q = 0; q < 11; ++q) s_lin[k][c][q] = a.lin[q * n + gi];
+                }
             }
         }
     }
@@ -139,7 +151,7 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
             }
         }
         const int ix1 = min(rx0 + RW + 2, W), iy1 = min(ry0 + RH + 2, H);
-        const int IW = ix1 - ix0, IH = iy1 - iy0;
+        const int IW = ix1 - ix0, IH = lin_load ? 0 : iy1 - iy0;
 #pragma unroll 2
         for (int i = threadIdx.x; i < IW * IH; i += NT) {
             const int ly = i / IW, lx = i - ly * IW;
@@ -212,20 +224,41 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
                 const int ly = l / LP, lx = l - ly * LP;
                 const int x = rx0 + lx, y = ry0 + ly;
                 const size_t gi = (size_t)y * W + x;
-                const int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
-                const int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
-                const double Ix = Ixa(x, y), Iy = Iya(x, y);
-                const int lc = li(x, y);
-                const double Iz = t1[lc] - t0[lc];
-                const double Ixx = (Ixa(xp, y) - Ixa(xm, y)) / 2.0;
-                const double Ixy = (Ixa(x, yp) - Ixa(x, ym)) / 2.0;
-                const double Iyy = (Iya(x, yp) - Iya(x, ym)) / 2.0;
-                const int lxp = li(xp, y), lxm = li(xm, y), lyp = li(x, yp), lym = li(x, ym);
-                const double Ixz = (t1[lxp] - t1[lxm]) / 2.0 - (t0[lxp] - t0[lxm]) / 2.0;
-                const double Iyz = (t1[lyp] - t1[lym]) / 2.0 - (t0[lyp] - t0[lym]) / 2.0;
-                const double b0 = 1.0 / ((Ix * Ix + Iy * Iy) + 0.01);
-                const double bx = 1.0 / ((Ixx * Ixx + Ixy * Ixy) + 0.01);
-                const double by = 1.0 / ((Ixy * Ixy + Iyy * Iyy) + 0.01);
+                double Ix = 0.0, Iy = 0.0, Iz = 0.0, Ixx = 0.0, Ixy = 0.0, Iyy = 0.0, Ixz = 0.0, Iyz = 0.0;
+                double b0 = 0.0, bx = 0.0, by = 0.0;
+                bool cached = false;
+                if constexpr (kLin) {
+                    if (lin_load) {
+                        Ix = s_lin[k][c][0]; Iy = s_lin[k][c][1]; Iz = s_lin[k][c][2];
+                        Ixx = s_lin[k][c][3]; Ixy = s_lin[k][c][4]; Iyy = s_lin[k][c][5];
+                        Ixz = s_lin[k][c][6]; Iyz = s_lin[k][c][7];
+                        b0 = s_lin[k][c][8]; bx = s_lin[k][c][9]; by = s_lin[k][c][10];
+                        cached = true;
+                    }
+                }
+                if (!cached) {
+                    const int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
+                    const int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
+                    Ix = Ixa(x, y);
+                    Iy = Iya(x, y);
+                    const int lc = li(x, y);
+                    Iz = t1[lc] - t0[lc];
+                    Ixx = (Ixa(xp, y) - Ixa(xm, y)) / 2.0;
+                    Ixy = (Ixa(x, yp) - Ixa(x, ym)) / 2.0;
+                    Iyy = (Iya(x, yp) - Iya(x, ym)) / 2.0;
+                    const int lxp = li(xp, y), lxm = li(xm, y), lyp = li(x, yp), lym = li(x, ym);
+                    Ixz = (t1[lxp] - t1[lxm]) / 2.0 - (t0[lxp] - t0[lxm]) / 2.0;
+                    Iyz = (t1[lyp] - t1[lym]) / 2.0 - (t0[lyp] - t0[lym]) / 2.0;
+                    b0 = 1.0 / ((Ix * Ix + Iy * Iy) + 0.01);
+                    bx = 1.0 / ((Ixx * Ixx + Ixy * Ixy) + 0.01);
+                    by = 1.0 / ((Ixy * Ixy + Iyy * Iyy) + 0.01);
+                    if (a.lin_mode == 1 && x >= g.cx0 && x < g.cx1 && y >= g.cy0 && y < g.cy1) {
+                        double* Lo = a.lin + gi;
+                        Lo[0] = Ix; Lo[n] = Iy; Lo[2 * n] = Iz; Lo[3 * n] = Ixx; Lo[4 * n] = Ixy;
+                        Lo[5 * n] = Iyy; Lo[6 * n] = Ixz; Lo[7 * n] = Iyz; Lo[8 * n] = b0; Lo[9 * n] = bx;
+                        Lo[10 * n] = by;
+                    }
+                }
                 double fu, fv;
                 if constexpr (kStage) { fu = s_fu[k][c]; fv = s_fv[k][c]; }
                 else { fu = F ? F[gi] : 0.0; fv = F ? F[n + gi] : 0.0; }
