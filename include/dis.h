@@ -67,6 +67,14 @@ extern "C" {
  *   sor_omega       SOR relaxation factor in (0, 2)
  *   refine          1 = run the variational refinement (Sec. 2.3), 0 = skip it
  *   flags           DIS_FLAG_* bits
+ *   norm            error norm of the inverse search (App. B iii): DIS_NORM_L2
+ *                   (the method of Sec. 2.1), DIS_NORM_L1 or DIS_NORM_HUBER -- in
+ *                   every Gauss-Newton iteration each pixel's mean-normalised
+ *                   residual e is replaced by sign(e) sqrt|e| (L1) or, for
+ *                   |e| >= huber_b, by sign(e) sqrt(2 huber_b |e| - huber_b^2)
+ *                   (Huber), before the least-squares step; the densification
+ *                   weights of Eq. (3) keep the untransformed residual
+ *   huber_b         Huber threshold on the 0..255 intensity scale (> 0)
  */
 typedef struct dis_params {
     int32_t patch_size;
@@ -82,7 +90,13 @@ typedef struct dis_params {
     double sor_omega;
     int32_t refine;
     uint32_t flags;
+    int32_t norm;
+    double huber_b;
 } dis_params;
+
+#define DIS_NORM_L2 0
+#define DIS_NORM_L1 1
+#define DIS_NORM_HUBER 2
 
 typedef struct dis_handle dis_handle;
 
@@ -96,7 +110,8 @@ typedef struct dis_handle dis_handle;
  * 1); 102/103 the 1024x436 operating points (8, 0.3, 12 it) and (8, 0.5,
  * 16 it) over scales 5..3; 104 high quality (12, 0.75, scales 4..0, 128 it,
  * theta_vo 5); 105 the differentiable batch (8, 0.5, scales 3..0, 16 it,
- * theta_vo 3).  Returns DIS_EINVAL for an unknown preset or NULL out.
+ * theta_vo 3).  Every preset uses the L2 search (norm DIS_NORM_L2, huber_b 1).
+ * Returns DIS_EINVAL for an unknown preset or NULL out.
  */
 int dis_default_params(int preset, dis_params* out);
 

@@ -46,6 +46,13 @@ R15 the refinement energy (Sec. 2.3) is linearised once per level around
 R16 each fixed-point iteration freezes the robust weights, then runs
     theta_vi red-black SOR sweeps (red: x+y even, first; omega = 1.6); the
     smoothness weight of pixel p sits on its right and lower edges.
+R17 robust error norms (App. B iii, an extension): in every Gauss-Newton
+    iteration each pixel's mean-normalised residual e becomes
+    sign(e) sqrt|e| (L1) or, when |e| >= b, sign(e) sqrt(2 b |e| - b^2)
+    (Huber; the printed condition "e < b" is read as |e| < b, the only
+    reading under which the transform is odd like the other one); the
+    threshold b is not given and defaults to 1 on the 0..255 scale, the
+    inlier bound of Eq. (3); the densification keeps the plain residual.
 """
 from __future__ import annotations
 
@@ -80,6 +87,8 @@ class OracleParams:
     residual: str = "normalised"       # R13: "normalised" | "raw"
     init_map: str = "literal"          # R7: "literal" x/2 | "pixel_centre" (x+0.5)/2-0.5
     grid: str = "inside"               # R6: "inside" | "overhang" (count only)
+    norm: str = "l2"                   # R17: "l2" | "l1" | "huber"
+    huber_b: float = 1.0               # R17
     eps: float = 1e-3                  # robust penaliser epsilon (Sec. 2.3)
 
 
@@ -226,6 +235,21 @@ def init_displacements(U_next: Optional[torch.Tensor], x0, y0, p: OracleParams):
 
 # --------------------------------------------------------- inverse search ----
 
+def robust_residual(e: torch.Tensor, p: OracleParams) -> torch.Tensor:
+    """App. B iii (R17): the residual whose square is the chosen penalty of e."""
+    if p.norm == "l2":
+        return e
+    a = e.abs()
+    if p.norm == "l1":
+        t = torch.sqrt(a)
+    elif p.norm == "huber":
+        b = p.huber_b
+        t = torch.where(a < b, a, torch.sqrt(torch.clamp(2.0 * b * a - b * b, min=0.0)))
+    else:
+        raise ValueError(f"unknown norm {p.norm}")
+    return torch.sign(e) * t
+
+
 @dataclass
 class SearchResult:
     u: torch.Tensor            # [N, 2] after the reset test
@@ -267,7 +291,7 @@ def inverse_search(J0, Gx, Gy, J1, x0, y0, u_init, p: OracleParams,
     history = []
     for _ in range(p.gn_iters):                      # R11
         Q = bilinear(J1, Xf + u[:, 0:1], Yf + u[:, 1:2])
-        r = (Q - Q.mean(dim=1, keepdim=True)) - Tn
+        r = robust_residual((Q - Q.mean(dim=1, keepdim=True)) - Tn, p)
         b1 = (gx * r).sum(1)
         b2 = (gy * r).sum(1)
         du = (a22 * b1 - a12 * b2) / det

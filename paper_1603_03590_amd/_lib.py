@@ -27,6 +27,10 @@ DIS_FLAG_PIXEL_CENTRE = 0x4
 DIS_FLAG_RAW_RESIDUAL = 0x8
 DIS_FLAG_IO_F64 = 0x10
 
+DIS_NORM_L2 = 0
+DIS_NORM_L1 = 1
+DIS_NORM_HUBER = 2
+
 DIS_DBG_J0 = 0
 DIS_DBG_J1 = 1
 DIS_DBG_UINIT = 2
@@ -74,6 +78,8 @@ class dis_params(ctypes.Structure):
         ("sor_omega", c_double),
         ("refine", c_int32),
         ("flags", c_uint32),
+        ("norm", c_int32),
+        ("huber_b", c_double),
     ]
 
     def as_dict(self):

@@ -98,6 +98,8 @@ static int validate_params(const dis_params* p) {
             return fail(nullptr, DIS_EINVAL, "refinement weights must be >= 0");
     }
     if (p->refine != 0 && p->refine != 1) return fail(nullptr, DIS_EINVAL, "refine must be 0 or 1");
+    if (p->norm < DIS_NORM_L2 || p->norm > DIS_NORM_HUBER) return fail(nullptr, DIS_EINVAL, "norm %d unknown", p->norm);
+    if (!(p->huber_b > 0.0)) return fail(nullptr, DIS_EINVAL, "huber_b %g must be > 0", p->huber_b);
     const uint32_t known = DIS_FLAG_KEEP_FOR_BACKWARD | DIS_FLAG_NO_GRAPH | DIS_FLAG_PIXEL_CENTRE |
                            DIS_FLAG_RAW_RESIDUAL | DIS_FLAG_IO_F64;
     if (p->flags & ~known) return fail(nullptr, DIS_EINVAL, "unknown flag bits 0x%x", p->flags & ~known);
@@ -119,6 +121,8 @@ extern "C" int dis_default_params(int preset, dis_params* out) {
     p.sor_omega = 1.6;
     p.refine = 1;
     p.flags = 0;
+    p.norm = DIS_NORM_L2;
+    p.huber_b = 1.0;
     switch (preset) {
         case 1: p.finest_scale = 3; p.gn_iters = 16; p.patch_size = 8; p.overlap = 0.3; p.refine = 0; break;
         case 2: p.finest_scale = 3; p.gn_iters = 12; p.patch_size = 8; p.overlap = 0.4; break;
@@ -546,6 +550,8 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             sa.st = g.st; sa.nrx = g.nrx; sa.nry = g.nry; sa.nx = g.nx; sa.ny = g.ny;
             sa.iters = p.gn_iters;
             sa.lam = 1e-3;
+            sa.norm = p.norm;
+            sa.huber_b = p.huber_b;
             sa.centre_map = cmap;
             sa.patch = L.patch;
             sa.uinit = L.uinit;

@@ -37,6 +37,8 @@ struct SearchArgs {
     int st, nrx, nry, nx, ny;   // stride; regular corners per axis; total corners per axis
     int iters;
     double lam;
+    int norm;               // 0 L2, 1 L1, 2 Huber (App. B iii)
+    double huber_b;
     int centre_map;
     double* patch;          // [N][4]: u, v, mean residual at u, distance moved
     double* uinit;          // [N][2]

@@ -319,9 +319,28 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
         const double sd = csum<GS, GPL, LPP>(d);
         md = sd * inv_n;
         if (it == a.iters) break;
-        // b = sum grad(T) (d - mean d): the mean-normalised residual (Sec. 2.1)
-        const double b1 = csum_prod<GS, GPL, LPP>(gx, d) - md * sgx;
-        const double b2 = csum_prod<GS, GPL, LPP>(gy, d) - md * sgy;
+        double b1, b2;
+        if (a.norm == 0) {
+            // b = sum grad(T) (d - mean d): the mean-normalised residual (Sec. 2.1)
+            b1 = csum_prod<GS, GPL, LPP>(gx, d) - md * sgx;
+            b2 = csum_prod<GS, GPL, LPP>(gy, d) - md * sgy;
+        } else {
+            // App. B iii: each mean-normalised residual e is transformed so
+            // that its square is the L1 or the Huber penalty of e
+            double r[PPL];
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                const int p = lane * PPL + k;
+                const double e = d[k] - md;
+                const double ae = fabs(e);
+                double t;
+                if (a.norm == 1) t = sqrt(ae);
+                else t = ae < a.huber_b ? ae : sqrt(2.0 * a.huber_b * ae - a.huber_b * a.huber_b);
+                r[k] = p < NP ? copysign(t, e) : 0.0;
+            }
+            b1 = csum_prod<GS, GPL, LPP>(gx, r);
+            b2 = csum_prod<GS, GPL, LPP>(gy, r);
+        }
         u = u - (m11 * b1 + m12 * b2);
         v = v - (m12 * b1 + m22 * b2);
     }

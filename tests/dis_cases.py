@@ -30,7 +30,8 @@ def oracle_params(p) -> O.OracleParams:
         var_inner=int(p.var_inner), delta=float(p.w_intensity), gamma=float(p.w_gradient),
         alpha=float(p.w_smooth), sor_omega=float(p.sor_omega), refine=bool(p.refine),
         residual="raw" if flags & 0x8 else "normalised",
-        init_map="pixel_centre" if flags & 0x4 else "literal")
+        init_map="pixel_centre" if flags & 0x4 else "literal",
+        norm={0: "l2", 1: "l1", 2: "huber"}[int(p.norm)], huber_b=float(p.huber_b))
 
 
 @functools.lru_cache(maxsize=None)

@@ -26,8 +26,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_params_struct_layout_matches_header():
-    # double fields are 8-byte aligned: 4+4(pad)+8 +4*5 +4(pad) +8*4 +4+4 = 80
-    assert ctypes.sizeof(_lib.dis_params) == 80
+    # double fields are 8-byte aligned: 4+4(pad)+8 +4*5 +4(pad) +8*4 +4+4 +4+4(pad)+8 = 96
+    assert ctypes.sizeof(_lib.dis_params) == 96
 
 
 @pytest.mark.parametrize("preset", [1, 2, 3, 4, 101, 102, 103, 104, 105, 106])

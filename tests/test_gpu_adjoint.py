@@ -247,6 +247,15 @@ def test_backward_errors():
         with pytest.raises(DisError) as e:
             d.backward(g)
         assert e.value.code == _lib.DIS_ESTATE
+        # the adjoint covers the L2 search only
+        dn = DIS(params(105, flags=F64 | KEEP, norm=1), 32, 32)
+        try:
+            dn.flow(a, b)
+            with pytest.raises(DisError) as e:
+                dn.backward(g)
+            assert e.value.code == _lib.DIS_EINVAL
+        finally:
+            dn.close()
         # the autograd Function refuses a stale forward
         a2 = a.clone().requires_grad_(True)
         f = dis_flow(a2, b, d)

@@ -54,6 +54,10 @@ CASES = [
     ("ps6_ov0_auto_320x96", ("layered", 320, 96, 12.0, 14), 103,
      dict(patch_size=6, overlap=0.0, coarsest_scale=-1, finest_scale=0)),
     ("op3_1024x436", ("layered", 1024, 436, 100.0, 15), 3, dict(gn_iters=16)),
+    # robust error norms of the search (App. B iii)
+    ("l1_bump_256x192", ("bump", 256, 192, 8.0, 1), 101, dict(norm=1)),
+    ("huber_layered_512x256", ("layered", 512, 256, 40.0, 16), 103, dict(norm=2, huber_b=1.0,
+                                                                         coarsest_scale=4, finest_scale=1)),
 ]
 
 
@@ -153,7 +157,7 @@ def test_size_errors():
         d.close()
 
 
-@pytest.mark.parametrize("case", ["c2b", "c1", "inner7"])
+@pytest.mark.parametrize("case", ["c2b", "c1", "inner7", "l1"])
 def test_launch_choices_are_bitwise_invariant(case):
     """Persistent vs per-phase launches, lanes per patch and refinement tiles
     change the schedule, never a bit of the flow."""
@@ -162,6 +166,8 @@ def test_launch_choices_are_bitwise_invariant(case):
         pr, p = pair("layered", 1024, 436, 100.0, 2), params(103)
     elif case == "c1":
         pr, p = pair("bump", 256, 192, 8.0, 1), params(101)
+    elif case == "l1":
+        pr, p = pair("bump", 256, 192, 8.0, 1), params(101, norm=1)
     else:   # 7 SOR sweeps: each fixed-point step spans two launches
         pr, p = pair("bump", 288, 216, 10.0, 13), params(105, var_inner=7)
     h, w = pr.I0.shape

@@ -534,3 +534,53 @@ def test_refinement_pulls_a_perturbed_flow_towards_the_truth():
         R = O.refine(J0, J1, U, n_outer, params())
         errs.append(float(torch.sqrt((R[0] - t[0]) ** 2 + (R[1] - t[1]) ** 2)[6:-6, 6:-6].mean()))
     assert errs[0] < e0 and errs[1] < errs[0] and errs[2] < 0.6 * e0, errs
+
+
+# --------------------------------------------- robust norms (App. B iii) ----
+def test_r17_squared_transform_is_the_l1_and_huber_penalty():
+    """App. B iii: after squaring, the transformed residual is the L1 norm
+    |e|, or the Huber penalty (quadratic inside b, linear outside, C1 at b;
+    here twice the textbook Huber function b |e| - b^2/2 beyond b)."""
+    pos = torch.linspace(0.0, 30.0, 3001, dtype=F64)
+    e = torch.cat([-pos.flip(0), pos[1:]])           # exactly symmetric grid
+    l1 = O.robust_residual(e, params(norm="l1"))
+    assert torch.allclose(l1 ** 2, e.abs(), rtol=0, atol=1e-12)
+    b = 2.5
+    hub = O.robust_residual(e, params(norm="huber", huber_b=b))
+    textbook = torch.where(e.abs() <= b, 0.5 * e * e, b * (e.abs() - 0.5 * b))
+    assert torch.allclose(hub ** 2, 2.0 * textbook, rtol=0, atol=1e-10)
+    # odd, sign-preserving, continuous at the threshold; L2 untouched
+    for r in (l1, hub):
+        assert torch.allclose(r, -torch.flip(r, [0]), atol=1e-12)
+        assert bool(((r >= 0) == (e >= 0)).all())
+    near = torch.tensor([b - 1e-9, b + 1e-9], dtype=F64)
+    h = O.robust_residual(near, params(norm="huber", huber_b=b))
+    assert abs(float(h[1] - h[0])) < 1e-6
+    assert torch.equal(O.robust_residual(e, params()), e)
+
+
+def test_r17_zero_residual_is_a_fixed_point_and_wide_huber_is_l2():
+    """A zero residual is a fixed point of every transform (an integer shift
+    makes the bilinear warp exact), and a Huber threshold above every
+    residual leaves the search exactly the L2 one of Sec. 2.1.  (Whether the
+    transformed iteration is more robust to outliers depends on the case --
+    the mean normalisation spreads an outlier's offset over the patch; the
+    paper found the gain not worth the slower convergence.)"""
+    t = (2.0, -1.0)
+    J0 = 255 * analytic_texture(64, 64, seed=21, min_period=14.0, n=8)
+    J1 = 255 * analytic_texture(64, 64, shift=t, seed=21, min_period=14.0, n=8)
+    Gx, Gy = O.sobel8(J0)
+    x0, y0 = torch.tensor([24, 8]), torch.tensor([24, 30])
+    exact = torch.tensor([[t[0], t[1]], [t[0], t[1]]], dtype=F64)
+    for norm in ("l2", "l1", "huber"):
+        res = O.inverse_search(J0, Gx, Gy, J1, x0, y0, exact.clone(), params(norm=norm, huber_b=1.0, gn_iters=3))
+        assert float((res.u - exact).norm()) < 1e-12, norm
+    init = torch.zeros(2, 2, dtype=F64)
+    l2 = O.inverse_search(J0, Gx, Gy, J1, x0, y0, init, params(gn_iters=10))
+    wide = O.inverse_search(J0, Gx, Gy, J1, x0, y0, init, params(norm="huber", huber_b=1e9, gn_iters=10))
+    assert torch.equal(l2.u_search, wide.u_search)
+    # the L1 search closes most of a one-pixel start error, then hovers
+    # around the shift: sqrt|e| has an unbounded slope at zero, so the
+    # least-squares step overshoots small residuals
+    l1 = O.inverse_search(J0, Gx, Gy, J1, x0, y0, exact + 1.0, params(norm="l1", gn_iters=60))
+    assert float((l1.u_search - exact).abs().max()) < 0.25
