@@ -52,6 +52,7 @@ extern "C" {
 #define DIS_FLAG_PIXEL_CENTRE 0x4u      /* map coarse<->fine positions through pixel centres, (x+0.5)/2-0.5 */
 #define DIS_FLAG_RAW_RESIDUAL 0x8u      /* Eq. (3) residual without mean normalisation */
 #define DIS_FLAG_IO_F64 0x10u           /* frames, flow and gradients are float64 */
+#define DIS_FLAG_STEREO 0x20u           /* rectified stereo (App. I): horizontal displacement only, v = 0 */
 
 /*
  * Method parameters: Table 1 of the paper and the fixed values of Sec. 3.1.

@@ -53,6 +53,10 @@ R17 robust error norms (App. B iii, an extension): in every Gauss-Newton
     reading under which the transform is odd like the other one); the
     threshold b is not given and defaults to 1 on the 0..255 scale, the
     inlier bound of Eq. (3); the densification keeps the plain residual.
+R18 stereo (App. I, an extension): the vertical degree of freedom is
+    removed everywhere -- the search solves the 1-D least-squares step
+    du = sum S'_x r / (H'_xx + lambda) and keeps v = 0, and the refinement
+    relaxes du only (dv stays 0), so the flow's second plane is zero.
 """
 from __future__ import annotations
 
@@ -89,6 +93,7 @@ class OracleParams:
     grid: str = "inside"               # R6: "inside" | "overhang" (count only)
     norm: str = "l2"                   # R17: "l2" | "l1" | "huber"
     huber_b: float = 1.0               # R17
+    stereo: bool = False               # R18: horizontal displacement only
     eps: float = 1e-3                  # robust penaliser epsilon (Sec. 2.3)
 
 
@@ -294,8 +299,12 @@ def inverse_search(J0, Gx, Gy, J1, x0, y0, u_init, p: OracleParams,
         r = robust_residual((Q - Q.mean(dim=1, keepdim=True)) - Tn, p)
         b1 = (gx * r).sum(1)
         b2 = (gy * r).sum(1)
-        du = (a22 * b1 - a12 * b2) / det
-        dv = (a11 * b2 - a12 * b1) / det
+        if p.stereo:                                 # R18: one degree of freedom
+            du = b1 / a11
+            dv = torch.zeros_like(du)
+        else:
+            du = (a22 * b1 - a12 * b2) / det
+            dv = (a11 * b2 - a12 * b1) / det
         u = u - torch.stack([du, dv], dim=1)
         if keep_history:
             history.append(u.detach().clone())
@@ -470,7 +479,7 @@ def _neighbour_sums(ws, f):
 
 
 def sor_sweeps(sys: SorSystem, U, du, dv, n_sweeps: int, omega: float,
-               on_half_sweep: Optional[Callable] = None):
+               on_half_sweep: Optional[Callable] = None, stereo: bool = False):
     """``n_sweeps`` red-black SOR sweeps on the frozen system (R16).
 
     For the pixels of one colour (all independent, their 4-neighbours have the
@@ -489,10 +498,11 @@ def sor_sweeps(sys: SorSystem, U, du, dv, n_sweeps: int, omega: float,
             num = NUu + Ndu - S * Uu - sys.b1 - sys.A12 * dv
             du_new = (1 - omega) * du + omega * num / (sys.A11 + S)
             du = torch.where(m, du_new, du)
-            _, Ndv = _neighbour_sums(sys.ws, dv)
-            num = NUv + Ndv - S * Uv - sys.b2 - sys.A12 * du
-            dv_new = (1 - omega) * dv + omega * num / (sys.A22 + S)
-            dv = torch.where(m, dv_new, dv)
+            if not stereo:                           # R18: dv stays 0
+                _, Ndv = _neighbour_sums(sys.ws, dv)
+                num = NUv + Ndv - S * Uv - sys.b2 - sys.A12 * du
+                dv_new = (1 - omega) * dv + omega * num / (sys.A22 + S)
+                dv = torch.where(m, dv_new, dv)
             if on_half_sweep is not None:
                 on_half_sweep(du, dv)
     return du, dv
@@ -515,7 +525,7 @@ def refine(J0, J1, U, n_outer: int, p: OracleParams, trace: Optional[Callable] =
             cb = lambda a, b, k=k, sys=sys: trace("half", k, t, sys, a, b)
         else:
             cb = None
-        du, dv = sor_sweeps(sys, U, du, dv, p.var_inner, p.sor_omega, cb)
+        du, dv = sor_sweeps(sys, U, du, dv, p.var_inner, p.sor_omega, cb, stereo=p.stereo)
     return torch.stack([U[0] + du, U[1] + dv])
 
 

@@ -26,6 +26,7 @@ DIS_FLAG_NO_GRAPH = 0x2
 DIS_FLAG_PIXEL_CENTRE = 0x4
 DIS_FLAG_RAW_RESIDUAL = 0x8
 DIS_FLAG_IO_F64 = 0x10
+DIS_FLAG_STEREO = 0x20
 
 DIS_NORM_L2 = 0
 DIS_NORM_L1 = 1

@@ -409,6 +409,8 @@ extern "C" int dis_flow_backward(dis_handle* h, const void* grad_flow, void* gra
     if (!grad_flow || !grad_I0 || !grad_I1) return dis_fail(h, DIS_EINVAL, "NULL gradient pointer");
     if (!(h->p.flags & DIS_FLAG_KEEP_FOR_BACKWARD))
         return dis_fail(h, DIS_ESTATE, "the handle was created without DIS_FLAG_KEEP_FOR_BACKWARD");
+    if (h->p.flags & DIS_FLAG_STEREO)
+        return dis_fail(h, DIS_EINVAL, "the adjoint covers two-dimensional flow, not the stereo form");
     if (h->p.norm != DIS_NORM_L2)
         return dis_fail(h, DIS_EINVAL, "the adjoint covers the L2 inverse search (norm %d requested)", h->p.norm);
     if (!h->have_last || h->last_call != 1)

@@ -101,7 +101,7 @@ static int validate_params(const dis_params* p) {
     if (p->norm < DIS_NORM_L2 || p->norm > DIS_NORM_HUBER) return fail(nullptr, DIS_EINVAL, "norm %d unknown", p->norm);
     if (!(p->huber_b > 0.0)) return fail(nullptr, DIS_EINVAL, "huber_b %g must be > 0", p->huber_b);
     const uint32_t known = DIS_FLAG_KEEP_FOR_BACKWARD | DIS_FLAG_NO_GRAPH | DIS_FLAG_PIXEL_CENTRE |
-                           DIS_FLAG_RAW_RESIDUAL | DIS_FLAG_IO_F64;
+                           DIS_FLAG_RAW_RESIDUAL | DIS_FLAG_IO_F64 | DIS_FLAG_STEREO;
     if (p->flags & ~known) return fail(nullptr, DIS_EINVAL, "unknown flag bits 0x%x", p->flags & ~known);
     return DIS_OK;
 }
@@ -552,6 +552,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             sa.lam = 1e-3;
             sa.norm = p.norm;
             sa.huber_b = p.huber_b;
+            sa.stereo = (p.flags & DIS_FLAG_STEREO) ? 1 : 0;
             sa.centre_map = cmap;
             sa.patch = L.patch;
             sa.uinit = L.uinit;
@@ -566,6 +567,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             RefineArgs& ra = P.ra;
             ra.U = L.Ud; ra.J0 = L.J0; ra.J1w = sb.J1w; ra.Uout = L.U;
             ra.lin = sb.lin;
+            ra.stereo = (p.flags & DIS_FLAG_STEREO) ? 1 : 0;
             ra.tape = opt ? opt->tape : nullptr;
             ra.W = W; ra.H = Hh;
             ra.tiles_x = (W + tw - 1) / tw;

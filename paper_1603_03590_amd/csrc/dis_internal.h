@@ -39,6 +39,7 @@ struct SearchArgs {
     double lam;
     int norm;               // 0 L2, 1 L1, 2 Huber (App. B iii)
     double huber_b;
+    int stereo;             // 1: horizontal displacement only (App. I)
     int centre_map;
     double* patch;          // [N][4]: u, v, mean residual at u, distance moved
     double* uinit;          // [N][2]
@@ -77,6 +78,7 @@ struct RefineArgs {
     // launches read it for their pixels instead of recomputing (lin_mode 2)
     double* lin;
     int lin_mode;           // 0 compute, 1 compute and store, 2 load
+    int stereo;             // 1: relax du only, dv stays zero (App. I)
     int W, H;
     int nhalf;
     int tiles_x;

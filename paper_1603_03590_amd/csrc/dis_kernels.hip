@@ -341,8 +341,12 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
             b1 = csum_prod<GS, GPL, LPP>(gx, r);
             b2 = csum_prod<GS, GPL, LPP>(gy, r);
         }
-        u = u - (m11 * b1 + m12 * b2);
-        v = v - (m12 * b1 + m22 * b2);
+        if (a.stereo) {
+            u = u - b1 / a11;   // App. I: one degree of freedom, v stays at its start (zero)
+        } else {
+            u = u - (m11 * b1 + m12 * b2);
+            v = v - (m12 * b1 + m22 * b2);
+        }
     }
     if (valid && lane == 0) {
         double* P = a.patch + (size_t)pi * 4;
@@ -442,6 +446,7 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
     const int cx0 = g.cx0, cy0 = g.cy0, cx1 = g.cx1, cy1 = g.cy1;
     const double* __restrict__ Din = a.dUin;
     const double om1 = 1.0 - a.omega;
+    const bool stereo = a.stereo != 0;
 
     dis_tile::TileCoef<PPT> C;
     double s_iu[Shape::NS][2], s_iv[Shape::NS][2];
@@ -487,11 +492,12 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
                 const double nu = ((C.wr[k][c] * du_[lr] + C.wl[k][c] * du_[ll]) + C.wd[k][c] * du_[ld]) +
                                   C.wu[k][c] * du_[lu];
                 const double dun = om1 * du + C.i1[k][c] * ((nu + C.c1[k][c]) - C.a12[k][c] * dv);
-                const double nv = ((C.wr[k][c] * dv_[lr] + C.wl[k][c] * dv_[ll]) + C.wd[k][c] * dv_[ld]) +
-                                  C.wu[k][c] * dv_[lu];
-                const double dvn = om1 * dv + C.i2[k][c] * ((nv + C.c2[k][c]) - C.a12[k][c] * dun);
                 du_[l] = dun;
-                dv_[l] = dvn;
+                if (!stereo) {
+                    const double nv = ((C.wr[k][c] * dv_[lr] + C.wl[k][c] * dv_[ll]) + C.wd[k][c] * dv_[ld]) +
+                                      C.wu[k][c] * dv_[lu];
+                    dv_[l] = om1 * dv + C.i2[k][c] * ((nv + C.c2[k][c]) - C.a12[k][c] * dun);
+                }
             }
             __syncthreads();
             if (a.tape) {
@@ -806,11 +812,12 @@ __global__ __launch_bounds__(NT) void k_small_level(const SmallLaunch S) {
                     const double nu = ((c_wr[k][c] * sm.du[lr] + c_wl[k][c] * sm.du[ll]) + c_wd[k][c] * sm.du[ld]) +
                                       c_wu[k][c] * sm.du[lu];
                     const double dun = om1 * du + c_i1[k][c] * ((nu + c_c1[k][c]) - c_a12[k][c] * dv);
-                    const double nv = ((c_wr[k][c] * sm.dv[lr] + c_wl[k][c] * sm.dv[ll]) + c_wd[k][c] * sm.dv[ld]) +
-                                      c_wu[k][c] * sm.dv[lu];
-                    const double dvn = om1 * dv + c_i2[k][c] * ((nv + c_c2[k][c]) - c_a12[k][c] * dun);
                     sm.du[l] = dun;
-                    sm.dv[l] = dvn;
+                    if (!a.stereo) {
+                        const double nv = ((c_wr[k][c] * sm.dv[lr] + c_wl[k][c] * sm.dv[ll]) +
+                                           c_wd[k][c] * sm.dv[ld]) + c_wu[k][c] * sm.dv[lu];
+                        sm.dv[l] = om1 * dv + c_i2[k][c] * ((nv + c_c2[k][c]) - c_a12[k][c] * dun);
+                    }
                 }
                 __syncthreads();
                 if (a.tape) {

@@ -92,12 +92,13 @@ def _sample_bilinear(img: np.ndarray, x: np.ndarray, y: np.ndarray) -> np.ndarra
 
 
 def smooth_bump_pair(w: int, h: int, max_disp: float, seed: int,
-                     noise_sigma: float = 0.01, n_bumps: int = 4) -> FramePair:
+                     noise_sigma: float = 0.01, n_bumps: int = 4, horizontal: bool = False) -> FramePair:
     """I0 = texture; I1(y) = I0(y - v(y)) + noise, with v a sum of Gaussian bumps.
 
     The bump centres are uniform in the frame, widths uniform in
     [0.10, 0.25] * min(w, h), directions uniform; the field is rescaled so its
-    largest displacement is ``max_disp`` px.  Ground truth u solves
+    largest displacement is ``max_disp`` px (``horizontal``: every bump
+    points left or right, a rectified stereo pair).  Ground truth u solves
     u(x) = v(x + u(x)) (then I1(x + u) = I0(x)), by fixed-point iteration.
     """
     rng = np.random.default_rng(seed)
@@ -109,14 +110,17 @@ def smooth_bump_pair(w: int, h: int, max_disp: float, seed: int,
     cy = rng.uniform(0, h, n_bumps)
     sig = rng.uniform(0.10, 0.25, n_bumps) * min(w, h)
     ang = rng.uniform(0, 2 * math.pi, n_bumps)
+    dir_x, dir_y = np.cos(ang), np.sin(ang)
+    if horizontal:
+        dir_x, dir_y = np.where(dir_x >= 0, 1.0, -1.0), np.zeros(n_bumps)
 
     def field(x, y):
         vx = np.zeros_like(x)
         vy = np.zeros_like(y)
         for k in range(n_bumps):
             g = np.exp(-((x - cx[k]) ** 2 + (y - cy[k]) ** 2) / (2 * sig[k] ** 2))
-            vx += g * math.cos(ang[k])
-            vy += g * math.sin(ang[k])
+            vx += g * dir_x[k]
+            vy += g * dir_y[k]
         return vx, vy
 
     vx, vy = field(xx, yy)

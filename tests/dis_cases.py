@@ -31,13 +31,16 @@ def oracle_params(p) -> O.OracleParams:
         alpha=float(p.w_smooth), sor_omega=float(p.sor_omega), refine=bool(p.refine),
         residual="raw" if flags & 0x8 else "normalised",
         init_map="pixel_centre" if flags & 0x4 else "literal",
-        norm={0: "l2", 1: "l1", 2: "huber"}[int(p.norm)], huber_b=float(p.huber_b))
+        norm={0: "l2", 1: "l1", 2: "huber"}[int(p.norm)], huber_b=float(p.huber_b),
+        stereo=bool(flags & 0x20))
 
 
 @functools.lru_cache(maxsize=None)
 def pair(kind: str, w: int, h: int, disp: float, seed: int):
     if kind == "bump":
         return synth.smooth_bump_pair(w, h, disp, seed)
+    if kind == "hbump":   # rectified stereo: horizontal displacements only
+        return synth.smooth_bump_pair(w, h, disp, seed, horizontal=True)
     return synth.layered_pair(w, h, disp, seed)
 
 

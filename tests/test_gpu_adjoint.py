@@ -247,15 +247,18 @@ def test_backward_errors():
         with pytest.raises(DisError) as e:
             d.backward(g)
         assert e.value.code == _lib.DIS_ESTATE
-        # the adjoint covers the L2 search only
-        dn = DIS(params(105, flags=F64 | KEEP, norm=1), 32, 32)
-        try:
-            dn.flow(a, b)
-            with pytest.raises(DisError) as e:
-                dn.backward(g)
-            assert e.value.code == _lib.DIS_EINVAL
-        finally:
-            dn.close()
+        # the adjoint covers the two-dimensional L2 search only
+        for extra in (dict(norm=1), dict(flags=F64 | KEEP | 0x20)):
+            over = dict(flags=F64 | KEEP)
+            over.update(extra)
+            dn = DIS(params(105, **over), 32, 32)
+            try:
+                dn.flow(a, b)
+                with pytest.raises(DisError) as e:
+                    dn.backward(g)
+                assert e.value.code == _lib.DIS_EINVAL
+            finally:
+                dn.close()
         # the autograd Function refuses a stale forward
         a2 = a.clone().requires_grad_(True)
         f = dis_flow(a2, b, d)

@@ -54,6 +54,9 @@ CASES = [
     ("ps6_ov0_auto_320x96", ("layered", 320, 96, 12.0, 14), 103,
      dict(patch_size=6, overlap=0.0, coarsest_scale=-1, finest_scale=0)),
     ("op3_1024x436", ("layered", 1024, 436, 100.0, 15), 3, dict(gn_iters=16)),
+    # rectified stereo, horizontal displacement only (App. I; theta_it halved)
+    ("stereo_hbump_256x192", ("hbump", 256, 192, 8.0, 17), 101, dict(flags=0x20, gn_iters=4)),
+    ("stereo_hbump_640x480_op2", ("hbump", 640, 480, 20.0, 18), 2, dict(flags=0x20, gn_iters=6)),
     # robust error norms of the search (App. B iii)
     ("l1_bump_256x192", ("bump", 256, 192, 8.0, 1), 101, dict(norm=1)),
     ("huber_layered_512x256", ("layered", 512, 256, 40.0, 16), 103, dict(norm=2, huber_b=1.0,
@@ -70,6 +73,8 @@ def test_end_to_end_parity(name, gen, preset, over):
     U = gpu_flow(pr.I0, pr.I1, p)
     frac, erel, dmax = parity(U, U_ref, pr.flow)
     say(f"[parity] {name}: within 1e-2 px {frac:.6f}, mean EPE rel diff {erel:.2e}, max diff {dmax:.2e}")
+    if int(p.flags) & 0x20:
+        assert np.all(U[1] == 0.0)
     assert frac >= PARITY_FRAC
     assert erel <= PARITY_EPE_REL
 
@@ -157,7 +162,7 @@ def test_size_errors():
         d.close()
 
 
-@pytest.mark.parametrize("case", ["c2b", "c1", "inner7", "l1"])
+@pytest.mark.parametrize("case", ["c2b", "c1", "inner7", "l1", "stereo"])
 def test_launch_choices_are_bitwise_invariant(case):
     """Persistent vs per-phase launches, lanes per patch and refinement tiles
     change the schedule, never a bit of the flow."""
@@ -168,6 +173,8 @@ def test_launch_choices_are_bitwise_invariant(case):
         pr, p = pair("bump", 256, 192, 8.0, 1), params(101)
     elif case == "l1":
         pr, p = pair("bump", 256, 192, 8.0, 1), params(101, norm=1)
+    elif case == "stereo":
+        pr, p = pair("hbump", 256, 192, 8.0, 17), params(101, flags=0x20)
     else:   # 7 SOR sweeps: each fixed-point step spans two launches
         pr, p = pair("bump", 288, 216, 10.0, 13), params(105, var_inner=7)
     h, w = pr.I0.shape

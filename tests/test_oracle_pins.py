@@ -584,3 +584,30 @@ def test_r17_zero_residual_is_a_fixed_point_and_wide_huber_is_l2():
     # least-squares step overshoots small residuals
     l1 = O.inverse_search(J0, Gx, Gy, J1, x0, y0, exact + 1.0, params(norm="l1", gn_iters=60))
     assert float((l1.u_search - exact).abs().max()) < 0.25
+
+
+# ------------------------------------------------------ stereo (App. I) -----
+def test_r18_stereo_recovers_horizontal_shifts_with_a_zero_vertical_plane():
+    """With the vertical degree of freedom removed, an integer horizontal
+    shift is a fixed point of the search, the 1-D step from a nearby start
+    closes the gap like the 2-D one on the same pair, and the whole pipeline
+    returns a flow whose vertical plane is exactly zero."""
+    t = (3.0, 0.0)
+    J0 = 255 * analytic_texture(64, 64, seed=31, min_period=14.0, n=8)
+    J1 = 255 * analytic_texture(64, 64, shift=t, seed=31, min_period=14.0, n=8)
+    Gx, Gy = O.sobel8(J0)
+    x0, y0 = torch.tensor([24, 8, 40]), torch.tensor([24, 30, 12])
+    exact = torch.tensor([[3.0, 0.0]] * 3, dtype=F64)
+    res = O.inverse_search(J0, Gx, Gy, J1, x0, y0, exact.clone(), params(stereo=True, gn_iters=3))
+    assert float((res.u - exact).norm()) < 1e-12
+    start = exact + torch.tensor([[0.6, 0.0]] * 3, dtype=F64)
+    r1 = O.inverse_search(J0, Gx, Gy, J1, x0, y0, start, params(stereo=True, gn_iters=30))
+    assert float((r1.u_search - exact).abs().max()) < 1e-6
+    assert bool((r1.u_search[:, 1] == 0).all())
+    from paper_1603_03590_amd import synth
+    pr = synth.smooth_bump_pair(96, 80, 4.0, 32, horizontal=True)
+    assert np.abs(pr.flow[1]).max() == 0.0
+    U = O.dis_flow(torch.from_numpy(pr.I0), torch.from_numpy(pr.I1),
+                   params(stereo=True, coarsest_scale=2, finest_scale=0, gn_iters=8, var_outer=2))
+    assert bool((U[1] == 0).all())
+    assert float(O.endpoint_error(U, torch.from_numpy(pr.flow)).mean()) < 0.5
