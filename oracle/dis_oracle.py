@@ -57,6 +57,8 @@ R18 stereo (App. I, an extension): the vertical degree of freedom is
     removed everywhere -- the search solves the 1-D least-squares step
     du = sum S'_x r / (H'_xx + lambda) and keeps v = 0, and the refinement
     relaxes du only (dv stays 0), so the flow's second plane is zero.
+R19 forward-backward consistency (App. B ii, an extension): see
+    merged_densify below for the reading of the merged Eq. (3).
 """
 from __future__ import annotations
 
@@ -599,3 +601,110 @@ def endpoint_error(flow, gt):
 
 def with_params(p: OracleParams, **kw) -> OracleParams:
     return replace(p, **kw)
+
+
+# ------------------------------------- forward-backward consistency (App. B ii)
+#
+# R19 (an extension): both directions run the whole method; only the
+# densification merges them.  For the flow of frame A (reference) the patches
+# of A's own search vote as in Eq. (3); every patch j of the other direction's
+# search, found on B's grid and displaced by its u_j into A, votes -u_j at the
+# pixels x of A with x - u_j inside its template square [x0_j, x0_j+ps-1]^2
+# (closed, continuous), with the residual A(x) - T_j(x - u_j) (T_j sampled
+# bilinearly in B), mean-normalised by that patch's mean residual at its final
+# u_j (as R13), weighted 1 / max(1, |d|).  Own patches are summed first in
+# ascending index, then the other direction's in ascending index.  Each
+# direction is refined on its own, and the next scale initialises each
+# direction from its own flow.
+
+def patch_mean_residual(Jref, Jother, x0, y0, u, p: OracleParams):
+    """Mean over the template of Jother(x + u) - Jref(x) at the patches' final u."""
+    ps = p.patch_size
+    px, py = patch_offsets(ps)
+    X = (x0[:, None] + px[None, :]).to(F64)
+    Y = (y0[:, None] + py[None, :]).to(F64)
+    Q = bilinear(Jother, X + u[:, 0:1], Y + u[:, 1:2])
+    T = Jref[(y0[:, None] + py[None, :]), (x0[:, None] + px[None, :])]
+    return (Q - T).mean(dim=1)
+
+
+def merged_densify(Jref, Jother, x0, y0, u_own, d_own, u_other, md_other, p: OracleParams,
+                   merge: bool = True):
+    """The densification of App. B ii for the flow of frame Jref: Eq. (3) over
+    the own patches plus the other direction's displaced patches (R19); both
+    directions use the same grid."""
+    return merged_densify_pairs(Jref, Jother, x0, y0, u_own, d_own, x0 if merge else x0[:0],
+                                y0 if merge else y0[:0], u_other if merge else u_other[:0],
+                                md_other if merge else md_other[:0], p)
+
+
+def merged_densify_pairs(Jref, Jother, x0, y0, u_own, d_own, xo, yo, u_other, md_other, p: OracleParams,
+                         want_z: bool = False):
+    """merged_densify with the other direction's patch corners (xo, yo) given
+    separately; returns U [2, h, w] (or Z when want_z)."""
+    h, w = Jref.shape
+    ps = p.patch_size
+    px, py = patch_offsets(ps)
+    # own patches, ascending i
+    lin = ((y0[:, None] + py[None, :]) * w + (x0[:, None] + px[None, :])).reshape(-1)
+    wgt = 1.0 / torch.clamp(d_own.abs(), min=1.0)
+    num_u = torch.zeros(h * w, dtype=F64).index_add(0, lin, (wgt * u_own[:, 0:1]).reshape(-1))
+    num_v = torch.zeros(h * w, dtype=F64).index_add(0, lin, (wgt * u_own[:, 1:2]).reshape(-1))
+    Z = torch.zeros(h * w, dtype=F64).index_add(0, lin, wgt.reshape(-1))
+    # the other direction's patches, ascending j, each over the pixels of
+    # Jref its displaced square covers
+    if u_other.shape[0]:
+        for j in range(u_other.shape[0]):
+            uj, vj = float(u_other[j, 0]), float(u_other[j, 1])
+            xa, xb = float(xo[j]) + uj, float(xo[j]) + ps - 1 + uj
+            ya, yb = float(yo[j]) + vj, float(yo[j]) + ps - 1 + vj
+            cx = torch.arange(max(0, math.ceil(xa)), min(w - 1, math.floor(xb)) + 1)
+            cy = torch.arange(max(0, math.ceil(ya)), min(h - 1, math.floor(yb)) + 1)
+            if cx.numel() == 0 or cy.numel() == 0:
+                continue
+            YY, XX = torch.meshgrid(cy, cx, indexing="ij")
+            tv = bilinear(Jother, XX.to(F64) - uj, YY.to(F64) - vj)
+            d = Jref[YY, XX] - tv
+            if p.residual == "normalised":
+                d = d - md_other[j]
+            wj = 1.0 / torch.clamp(d.abs(), min=1.0)
+            li = (YY * w + XX).reshape(-1)
+            num_u = num_u.index_add(0, li, (-uj * wj).reshape(-1))
+            num_v = num_v.index_add(0, li, (-vj * wj).reshape(-1))
+            Z = Z.index_add(0, li, wj.reshape(-1))
+    if want_z:
+        return Z.reshape(h, w)
+    return torch.stack([num_u / Z, num_v / Z]).reshape(2, h, w)
+
+
+def dis_flow_fb(I0, I1, p: OracleParams, merge: bool = True):
+    """Forward and backward flow with forward-backward consistent
+    densification (App. B ii, R19).  Returns (U forward [2,H,W], U backward)."""
+    I0 = torch.as_tensor(I0).to(F64)
+    I1 = torch.as_tensor(I1).to(F64)
+    h, w = I0.shape
+    ss = coarsest_scale(w, h, p)
+    sf = p.finest_scale
+    if sf > ss:
+        raise ValueError(f"finest scale {sf} above coarsest scale {ss}")
+    P0 = build_pyramid(p.intensity_scale * I0, ss)
+    P1 = build_pyramid(p.intensity_scale * I1, ss)
+    Uf = Ub = None
+    for s in range(ss, sf - 1, -1):
+        hs, ws_ = P0[s].shape
+        x0, y0, _, _ = patch_grid(ws_, hs, p)
+        res = []
+        for Ja, Jb, Uprev in ((P0[s], P1[s], Uf), (P1[s], P0[s], Ub)):
+            Gx, Gy = sobel8(Ja)
+            r = inverse_search(Ja, Gx, Gy, Jb, x0, y0, init_displacements(Uprev, x0, y0, p), p)
+            res.append((r, patch_mean_residual(Ja, Jb, x0, y0, r.u, p)))
+        (rf, mdf), (rb, mdb) = res
+        Udf = merged_densify(P0[s], P1[s], x0, y0, rf.u, rf.d, rb.u, mdb, p, merge)
+        Udb = merged_densify(P1[s], P0[s], x0, y0, rb.u, rb.d, rf.u, mdf, p, merge)
+        n_outer = outer_iterations(s, p)
+        if p.refine:
+            Uf = refine(P0[s], P1[s], Udf, n_outer, p)
+            Ub = refine(P1[s], P0[s], Udb, n_outer, p)
+        else:
+            Uf, Ub = Udf, Udb
+    return upsample(Uf, w, h, sf, p), upsample(Ub, w, h, sf, p)

@@ -611,3 +611,62 @@ def test_r18_stereo_recovers_horizontal_shifts_with_a_zero_vertical_plane():
                    params(stereo=True, coarsest_scale=2, finest_scale=0, gn_iters=8, var_outer=2))
     assert bool((U[1] == 0).all())
     assert float(O.endpoint_error(U, torch.from_numpy(pr.flow)).mean()) < 0.5
+
+
+# ------------------------ forward-backward consistency (App. B ii, R19) ----
+def test_r19_swap_symmetry_and_reduction_to_the_plain_method():
+    """Swapping the frames swaps the two flows bit for bit, and without the
+    other direction's votes the forward flow is the plain method's."""
+    from paper_1603_03590_amd import synth
+    pr = synth.smooth_bump_pair(96, 80, 4.0, 40)
+    a, b = torch.from_numpy(pr.I0), torch.from_numpy(pr.I1)
+    p = params(coarsest_scale=2, finest_scale=0, gn_iters=8, var_outer=2)
+    Uf, Ub = O.dis_flow_fb(a, b, p)
+    Ub2, Uf2 = O.dis_flow_fb(b, a, p)
+    assert torch.equal(Uf, Uf2) and torch.equal(Ub, Ub2)
+    Un, _ = O.dis_flow_fb(a, b, p, merge=False)
+    assert torch.equal(Un, O.dis_flow(a, b, p))
+    # consistent votes help a little on this pair (the paper's extension)
+    gt = torch.from_numpy(pr.flow)
+    assert float(O.endpoint_error(Uf, gt).mean()) < float(O.endpoint_error(Un, gt).mean())
+
+
+def test_r19_merged_votes_of_a_consistent_translation():
+    """Own patches at u = t and the other direction's patches at -t (zero
+    residuals) densify to exactly t wherever they vote."""
+    J = 255 * analytic_texture(40, 48, seed=41, min_period=10.0, n=6)
+    p = params(patch_size=8, overlap=0.5)
+    x0, y0, nx, ny = O.patch_grid(48, 40, p)
+    N = x0.numel()
+    t = torch.tensor([2.0, -1.0], dtype=F64)
+    u_own = t.expand(N, 2).clone()
+    u_oth = (-t).expand(N, 2).clone()
+    d_own = torch.zeros(N, 64, dtype=F64)
+    md = torch.zeros(N, dtype=F64)
+    U = O.merged_densify(J, J, x0, y0, u_own, d_own, u_oth, md, p)
+    assert torch.equal(U[0], torch.full_like(U[0], 2.0)) and torch.equal(U[1], torch.full_like(U[1], -1.0))
+
+
+def test_r19_displaced_patch_coverage_and_residual_by_hand():
+    """One other-direction patch at corner (8, 8) displaced by (0.5, 0): it
+    votes on the pixels x with x - 0.5 in [8, 15] (columns 9..15, rows 8..15)
+    with the residual Jref(x) - T(x - 0.5) - md; on a linear ramp both frames
+    equal, T(x - 0.5) is the ramp half a pixel back."""
+    H, Wd = 32, 32
+    ramp = torch.arange(Wd, dtype=F64).expand(H, Wd).clone() * 3.0    # Jother(x, y) = 3x
+    Jref = ramp.clone()
+    p = params(patch_size=8, overlap=0.5)
+    x0 = torch.tensor([0]); y0 = torch.tensor([0])              # one own patch far away
+    u_own = torch.zeros(1, 2, dtype=F64); d_own = torch.zeros(1, 64, dtype=F64)
+    xo, yo = torch.tensor([8]), torch.tensor([8])
+    u_oth = torch.tensor([[0.5, 0.0]], dtype=F64)
+    md = torch.tensor([0.25], dtype=F64)
+    # own patch covers rows/cols 0..7 only: elsewhere only the other patch votes
+    U = O.merged_densify_pairs(Jref, ramp, x0, y0, u_own, d_own, xo, yo, u_oth, md, p)
+    covered = torch.zeros(H, Wd, dtype=torch.bool)
+    covered[8:16, 9:16] = True
+    assert torch.equal(U[0][covered], torch.full((int(covered.sum()),), -0.5, dtype=F64))
+    assert bool(torch.isnan(U[0][~covered & (torch.arange(H)[:, None] > 7)]).all())
+    # the weight of a covered pixel: d = 3x - 3(x - 0.5) - 0.25 = 1.25 -> 1/1.25
+    Z = O.merged_densify_pairs(Jref, ramp, x0, y0, u_own, d_own, xo, yo, u_oth, md, p, want_z=True)
+    assert torch.allclose(Z[covered], torch.full((int(covered.sum()),), 1 / 1.25, dtype=F64), rtol=0, atol=1e-15)
