@@ -658,10 +658,12 @@ def merged_densify_pairs(Jref, Jother, x0, y0, u_own, d_own, xo, yo, u_other, md
             uj, vj = float(u_other[j, 0]), float(u_other[j, 1])
             xa, xb = float(xo[j]) + uj, float(xo[j]) + ps - 1 + uj
             ya, yb = float(yo[j]) + vj, float(yo[j]) + ps - 1 + vj
-            cx = torch.arange(max(0, math.ceil(xa)), min(w - 1, math.floor(xb)) + 1)
-            cy = torch.arange(max(0, math.ceil(ya)), min(h - 1, math.floor(yb)) + 1)
-            if cx.numel() == 0 or cy.numel() == 0:
+            xl, xh = max(0, math.ceil(xa)), min(w - 1, math.floor(xb))
+            yl, yh = max(0, math.ceil(ya)), min(h - 1, math.floor(yb))
+            if xl > xh or yl > yh:      # displaced square misses the level
                 continue
+            cx = torch.arange(xl, xh + 1)
+            cy = torch.arange(yl, yh + 1)
             YY, XX = torch.meshgrid(cy, cx, indexing="ij")
             tv = bilinear(Jother, XX.to(F64) - uj, YY.to(F64) - vj)
             d = Jref[YY, XX] - tv

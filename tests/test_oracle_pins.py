@@ -670,3 +670,29 @@ def test_r19_displaced_patch_coverage_and_residual_by_hand():
     # the weight of a covered pixel: d = 3x - 3(x - 0.5) - 0.25 = 1.25 -> 1/1.25
     Z = O.merged_densify_pairs(Jref, ramp, x0, y0, u_own, d_own, xo, yo, u_oth, md, p, want_z=True)
     assert torch.allclose(Z[covered], torch.full((int(covered.sum()),), 1 / 1.25, dtype=F64), rtol=0, atol=1e-15)
+
+
+def test_r19_patches_displaced_off_the_level_vote_nowhere():
+    """Other-direction patches whose displaced squares lie wholly outside the
+    level (right, below, left, above) leave Eq. (3) over the own patches
+    unchanged, bit for bit; one that overlaps the border by a column votes on
+    that column only."""
+    H, Wd = 24, 24
+    J = 255 * analytic_texture(H, Wd, seed=42, min_period=8.0, n=5)
+    p = params(patch_size=8, overlap=0.5)
+    x0, y0, _, _ = O.patch_grid(Wd, H, p)
+    N = x0.numel()
+    g = torch.Generator().manual_seed(5)
+    u_own = torch.rand(N, 2, generator=g, dtype=F64)
+    d_own = torch.rand(N, 64, generator=g, dtype=F64) * 4 - 2
+    xo = torch.tensor([0, 0, 16, 16]); yo = torch.tensor([0, 16, 0, 16])
+    u_oth = torch.tensor([[30.0, 0.0], [0.0, 9.5], [-24.2, 0.0], [0.0, -23.01]], dtype=F64)
+    md = torch.zeros(4, dtype=F64)
+    ref = O.merged_densify_pairs(J, J, x0, y0, u_own, d_own, xo[:0], yo[:0], u_oth[:0], md[:0], p)
+    U = O.merged_densify_pairs(J, J, x0, y0, u_own, d_own, xo, yo, u_oth, md, p)
+    assert torch.equal(U, ref)
+    # corner (16, 0) displaced by (-23, 0): x - (-23) in [16, 23] -> column 0 only
+    U1 = O.merged_densify_pairs(J, J, x0, y0, u_own, d_own, xo[2:3], yo[2:3],
+                                torch.tensor([[-23.0, 0.0]], dtype=F64), md[:1], p)
+    changed = (U1 != ref).any(0)
+    assert bool(changed[:8, 0].all()) and not bool(changed[:, 1:].any()) and not bool(changed[8:, :].any())
