@@ -53,6 +53,7 @@ extern "C" {
 #define DIS_FLAG_RAW_RESIDUAL 0x8u      /* Eq. (3) residual without mean normalisation */
 #define DIS_FLAG_IO_F64 0x10u           /* frames, flow and gradients are float64 */
 #define DIS_FLAG_STEREO 0x20u           /* rectified stereo (App. I): horizontal displacement only, v = 0 */
+#define DIS_FLAG_FB_CONSISTENCY 0x40u   /* forward-backward consistent densification (App. B ii), plain calls */
 
 /*
  * Method parameters: Table 1 of the paper and the fixed values of Sec. 3.1.
@@ -135,7 +136,13 @@ int dis_create(const dis_params* p, int max_w, int max_h, int max_batch,
  * DIS_ESIZE (w > max_w, h > max_h, or the finest scale smaller than the
  * patch), DIS_EHIP.  With DIS_FLAG_KEEP_FOR_BACKWARD the handle keeps the
  * frames' pointers and per-scale flows for dis_flow_backward; the frames must
- * then stay unchanged until the backward call has run.
+ * then stay unchanged until the backward call has run.  With
+ * DIS_FLAG_FB_CONSISTENCY both directions run (App. B ii): each scale
+ * searches I0 -> I1 and I1 -> I0, densifies each direction from its own
+ * patches and the other direction's displaced patches (votes -u, residual of
+ * the displaced template sampled bilinearly), refines each direction on its
+ * own, and `flow` receives the I0 -> I1 flow (the other direction through
+ * DIS_DBG_UREFINED_BWD).  The handle then holds two pair slots.
  */
 int dis_compute_flow(dis_handle* h, const void* I0, const void* I1, int w, int hgt,
                      int pitch, void* flow);
@@ -219,6 +226,8 @@ int dis_set_stream(dis_handle* h, void* hip_stream);
  * after dis_flow_backward: DIS_DBG_GRAD_J0/J1 [H_s][W_s] dL/d(level image),
  * DIS_DBG_GRAD_U [2][H_s][W_s] dL/d(refined flow of scale s),
  * DIS_DBG_GRAD_PATCH [N][4] dL/d(patch u, v, mean residual, unused),
+ * DIS_DBG_UREFINED_BWD [2][H_s][W_s] the backward (frame 1 -> 0) flow of a
+ * forward-backward consistent call,
  * DIS_DBG_WAIT_ERRORS int32: how many persistent launches of that call gave
  * up waiting on their task queue (0 unless something is broken).
  * Errors: DIS_EINVAL (bad what/s or NULL), DIS_ESIZE (bytes too small),
@@ -236,6 +245,7 @@ int dis_set_stream(dis_handle* h, void* hip_stream);
 #define DIS_DBG_GRAD_J1 9
 #define DIS_DBG_GRAD_U 10
 #define DIS_DBG_GRAD_PATCH 11
+#define DIS_DBG_UREFINED_BWD 12   /* with DIS_FLAG_FB_CONSISTENCY: the backward direction's refined flow */
 int dis_debug_level(dis_handle* h, int s, int what, void* dst, size_t bytes);
 
 /*

@@ -138,7 +138,8 @@ class DIS:
         shape = {_lib.DIS_DBG_J0: (H, W), _lib.DIS_DBG_J1: (H, W), _lib.DIS_DBG_UINIT: (N, 2),
                  _lib.DIS_DBG_UPATCH: (N, 2), _lib.DIS_DBG_UDENSE: (2, H, W),
                  _lib.DIS_DBG_UREFINED: (2, H, W), _lib.DIS_DBG_GRAD_J0: (H, W), _lib.DIS_DBG_GRAD_J1: (H, W),
-                 _lib.DIS_DBG_GRAD_U: (2, H, W), _lib.DIS_DBG_GRAD_PATCH: (N, 4)}[what]
+                 _lib.DIS_DBG_GRAD_U: (2, H, W), _lib.DIS_DBG_GRAD_PATCH: (N, 4),
+                 _lib.DIS_DBG_UREFINED_BWD: (2, H, W)}[what]
         out = np.zeros(shape, np.float64)
         _lib.dis_debug_level(self.handle, s, what, out.ctypes.data, out.nbytes)
         return out

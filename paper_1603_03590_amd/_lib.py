@@ -27,6 +27,7 @@ DIS_FLAG_PIXEL_CENTRE = 0x4
 DIS_FLAG_RAW_RESIDUAL = 0x8
 DIS_FLAG_IO_F64 = 0x10
 DIS_FLAG_STEREO = 0x20
+DIS_FLAG_FB_CONSISTENCY = 0x40
 
 DIS_NORM_L2 = 0
 DIS_NORM_L1 = 1
@@ -44,6 +45,7 @@ DIS_DBG_GRAD_J0 = 8
 DIS_DBG_GRAD_J1 = 9
 DIS_DBG_GRAD_U = 10
 DIS_DBG_GRAD_PATCH = 11
+DIS_DBG_UREFINED_BWD = 12
 
 # every symbol include/dis.h declares
 EXPORTS = (

@@ -101,7 +101,8 @@ static int validate_params(const dis_params* p) {
     if (p->norm < DIS_NORM_L2 || p->norm > DIS_NORM_HUBER) return fail(nullptr, DIS_EINVAL, "norm %d unknown", p->norm);
     if (!(p->huber_b > 0.0)) return fail(nullptr, DIS_EINVAL, "huber_b %g must be > 0", p->huber_b);
     const uint32_t known = DIS_FLAG_KEEP_FOR_BACKWARD | DIS_FLAG_NO_GRAPH | DIS_FLAG_PIXEL_CENTRE |
-                           DIS_FLAG_RAW_RESIDUAL | DIS_FLAG_IO_F64 | DIS_FLAG_STEREO;
+                           DIS_FLAG_RAW_RESIDUAL | DIS_FLAG_IO_F64 | DIS_FLAG_STEREO |
+                           DIS_FLAG_FB_CONSISTENCY;
     if (p->flags & ~known) return fail(nullptr, DIS_EINVAL, "unknown flag bits 0x%x", p->flags & ~known);
     return DIS_OK;
 }
@@ -233,13 +234,22 @@ extern "C" int dis_create(const dis_params* p, int max_w, int max_h, int max_bat
     h->top = top;
     for (int s = 0; s < DIS_MAXL; ++s) h->lpp[s] = 0;
     h->refine_tile = 7;   // 8x8 cores, 512 threads: the fastest on small scales
-    h->slots.resize(max_batch);
-    for (int i = 0; i < max_batch; ++i) {
+    const bool fb = (p->flags & DIS_FLAG_FB_CONSISTENCY) != 0;
+    const int nslots = fb ? std::max(max_batch, 2) : max_batch;
+    h->slots.resize(nslots);
+    for (int i = 0; i < nslots; ++i) {
         r = alloc_slot(h, h->slots[i]);
         if (r != DIS_OK) {
             g_null_err = h->err;
             dis_destroy(h);
             return r;
+        }
+    }
+    if (fb) {
+        // the backward direction (slot 1) reads the same pyramid, frames swapped
+        for (int s = 0; s < DIS_MAXL; ++s) {
+            h->slots[1].lv[s].J0 = h->slots[0].lv[s].J1;
+            h->slots[1].lv[s].J1 = h->slots[0].lv[s].J0;
         }
     }
     if (p->flags & DIS_FLAG_KEEP_FOR_BACKWARD) {
@@ -502,7 +512,8 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     const int cmap = (p.flags & DIS_FLAG_PIXEL_CENTRE) ? 1 : 0;
     int top = sf;
     for (const PairRef& r : pairs) top = std::max(top, r.ss);
-    const int mode = (opt && opt->force_phase) ? 1 : h->mode_phase;
+    const bool fbm = (p.flags & DIS_FLAG_FB_CONSISTENCY) && !opt && pairs.size() == 2;
+    const int mode = ((opt && opt->force_phase) || fbm) ? 1 : h->mode_phase;
     const int tile_id = mode ? h->refine_tile : DIS_LEVEL_TILE;
     int tw = 32, th = 16, nt = 256;
     dis_refine_tile(tile_id, &tw, &th, &nt);
@@ -575,7 +586,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             ra.omega = p.sor_omega; ra.eps = 1e-3;
             for (int q = 0; q < 3; ++q) P.dU[q] = sb.dU[q];
             P.dens_bx = (W + 63) / 64;
-            const bool small = p.refine && h->small_levels && ((W + 1) / 2) * Hh <= DIS_SMALL_PAIRS;
+            const bool small = p.refine && h->small_levels && !fbm && ((W + 1) / 2) * Hh <= DIS_SMALL_PAIRS;
             if (small) LH.small.push_back((int)LH.lp.size());
             LH.is_small.push_back(small ? 1 : 0);
             LH.lp.push_back(P);
@@ -600,7 +611,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     // device tables for every level, one allocation
     size_t bytes = 0;
     int nsync = 0;
-    std::vector<size_t> off_lp, off_rph, off_start, off_small;
+    std::vector<size_t> off_lp, off_rph, off_start, off_small, off_fb;
     std::vector<int> off_sync;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     for (LevelHost& LH : levels) {
@@ -613,6 +624,13 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         bytes = al(bytes + sizeof(int) * (nseg + 1));
         off_small.push_back(bytes);
         bytes = al(bytes + sizeof(int) * std::max<size_t>(1, LH.small.size()));
+        off_fb.push_back(bytes);
+        if (fbm) {
+            const LevelPair& P0 = LH.lp[0];
+            const size_t ncell = (size_t)((P0.da.W - 1) / ps + 2) * ((P0.da.H - 1) / ps + 2);
+            const size_t nlist = (size_t)P0.da.nx * P0.da.ny;
+            bytes = al(bytes + 2 * sizeof(int) * (3 * ncell + 1 + nlist));
+        }
         off_sync.push_back(nsync);
         tabs.err_index.push_back(nsync + 1);
         nsync += 2 + nseg;
@@ -683,6 +701,31 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
                 if (ph == 0) {
                     if (opt && opt->skip_search) continue;
                     seq.add(fs, dim3(n), dim3(256), &LL, sizeof LL, 0, "search", ph_by[0], ph_fl[0]);
+                } else if (ph == 1 && fbm) {
+                    // merged densification of both directions (App. B ii):
+                    // bin each direction's patches by displaced corner, then gather
+                    FbLaunch F;
+                    std::memset(&F, 0, sizeof F);
+                    F.L = LL;
+                    const LevelPair& P0 = LH.lp[0];
+                    F.Wc = (P0.da.W - 1) / ps + 2;
+                    F.Hc = (P0.da.H - 1) / ps + 2;
+                    const size_t ncell = (size_t)F.Wc * F.Hc;
+                    const int N = P0.da.nx * P0.da.ny;
+                    int* base = (int*)((char*)tabs.mem + off_fb[li]);
+                    for (int d = 0; d < 2; ++d) {
+                        int* b = base + (size_t)d * (3 * ncell + 1 + N);
+                        F.bins[d].count = b;
+                        F.bins[d].start = b + ncell;
+                        F.bins[d].cursor = b + 2 * ncell + 1;
+                        F.bins[d].list = b + 3 * ncell + 1;
+                    }
+                    const unsigned pb = (unsigned)((N + 255) / 256);
+                    seq.add(dis_kernel_fb_count(), dim3(pb, 2), dim3(256), &F, sizeof F, 0, "fb_bin", 16.0 * N, 0.0);
+                    seq.add(dis_kernel_fb_scan(), dim3(1, 2), dim3(1024), &F, sizeof F, 0, "fb_bin", 24.0 * ncell, 0.0);
+                    seq.add(dis_kernel_fb_scatter(), dim3(pb, 2), dim3(256), &F, sizeof F, 0, "fb_bin", 24.0 * N, 0.0);
+                    seq.add(dis_kernel_fb_densify(), dim3((P0.da.W + 63) / 64, (P0.da.H + 3) / 4, 2), dim3(256), &F,
+                            sizeof F, 0, "densify", 2.0 * ph_by[1], 2.0 * ph_fl[1]);
                 } else if (ph == 1) {
                     seq.add(dis_kernel_phase_densify(), dim3(n), dim3(256), &LL, sizeof LL, 0, "densify", ph_by[1],
                             ph_fl[1]);
@@ -726,6 +769,7 @@ int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const 
     int r = dis_add_pyramid(h, sb, w, hgt, pitch, ss, I0, I1, seq);
     if (r != DIS_OK) return r;
     std::vector<PairRef> pr{PairRef{&sb, w, hgt, ss}};
+    if (p.flags & DIS_FLAG_FB_CONSISTENCY) pr.push_back(PairRef{&h->slots[1], w, hgt, ss});
     r = dis_build_levels(h, pr, seq, tabs, nullptr);
     if (r != DIS_OK) return r;
     dis_add_upsample(h, sb, w, hgt, flow, seq);
@@ -975,6 +1019,9 @@ extern "C" int dis_debug_level(dis_handle* h, int s, int what, void* dst, size_t
         case DIS_DBG_GRAD_J1: src = h->bwd.gJ1[s]; n = px * 8; break;
         case DIS_DBG_GRAD_U: src = h->bwd.gU[s]; n = 2 * px * 8; break;
         case DIS_DBG_GRAD_PATCH: src = h->bwd.gP[s]; n = (size_t)N * 32; break;
+        case DIS_DBG_UREFINED_BWD:
+            if (!(h->p.flags & DIS_FLAG_FB_CONSISTENCY)) return fail(h, DIS_ESTATE, "not a forward-backward handle");
+            src = h->slots[1].lv[s].U; n = 2 * px * 8; break;
         case DIS_DBG_INFO:
             info[0] = g.W; info[1] = g.H; info[2] = N; info[3] = g.nx; info[4] = g.ny; info[5] = g.st;
             if (bytes < sizeof info) return fail(h, DIS_ESIZE, "need %zu bytes", sizeof info);

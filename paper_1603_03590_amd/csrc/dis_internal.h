@@ -146,6 +146,25 @@ struct SmallLaunch {
     int nhalf;              // red-black half sweeps per step
 };
 
+// Forward-backward consistent densification (App. B ii): the two
+// directions are pairs 0 (frame 0 -> 1) and 1 (1 -> 0) of one level launch.
+// For direction d the other direction's patches are binned by the cell of
+// their displaced corner floor(corner + u) (cells of ps x ps pixels, cell
+// index offset by one so that corners down to -ps are kept); a pixel then
+// looks at the 2 x 2 cells its covering patches can come from.
+struct FbBins {
+    int* count;             // [Wc * Hc], zero between uses (the scan clears it)
+    int* start;             // [Wc * Hc + 1]
+    int* cursor;            // [Wc * Hc]
+    int* list;              // [N] patch indices grouped by cell
+};
+struct FbLaunch {
+    LevelLaunch L;          // pairs 0 and 1 of this level
+    FbBins bins[2];         // bins[d]: patches of direction 1 - d, displaced into frame d
+    int Wc, Hc;
+};
+#define DIS_FB_MAXCAND 32     // covering candidates a pixel sorts in registers
+
 // Table-driven multi-pair launches of the pyramid and the upscaling: entry
 // j covers blocks start[j] .. start[j+1]-1.
 struct PyrTab {
@@ -180,6 +199,10 @@ const void* dis_kernel_phase_search(int ps, int lpp);   // null when not compile
 const void* dis_kernel_phase_densify();
 const void* dis_kernel_phase_refine(int tile);          // tile id, see dis_refine_tile
 const void* dis_kernel_small_level();                  // SmallLaunch, DIS_SMALL_THREADS threads
+const void* dis_kernel_fb_count();                     // FbLaunch, grid (patch blocks, 2)
+const void* dis_kernel_fb_scan();                      // FbLaunch, grid (1, 2), 1024 threads
+const void* dis_kernel_fb_scatter();                   // FbLaunch, grid (patch blocks, 2)
+const void* dis_kernel_fb_densify();                   // FbLaunch, grid (W/64, H/4, 2)
 const void* dis_kernel_level(int ps, int lpp);          // persistent level kernel, null when not compiled
 // refinement core tile (width, height, threads per block) of a tile id;
 // returns 0 for an unknown id

@@ -419,6 +419,177 @@ __device__ __forceinline__ void densify_block(const DensifyArgs& a, int bx, int 
     if (a.J1w) a.J1w[g] = bilin(a.J1, W, H, (double)x + U, (double)y + V);
 }
 
+// ------------------------------------------- forward-backward densification
+
+// Displaced-corner cell of patch j of a direction, or -1 when its displaced
+// square cannot reach the level (floor division by the patch size).
+__device__ __forceinline__ int fb_cell(const DensifyArgs& o, int j, int Wc, int Hc) {
+    const int ky = j / o.nx, kx = j - ky * o.nx;
+    const int x0 = kx < o.nrx ? kx * o.st : o.W - o.ps;
+    const int y0 = ky < o.nry ? ky * o.st : o.H - o.ps;
+    const double* P = o.patch + (size_t)j * 4;
+    const double fx = floor((double)x0 + P[0]), fy = floor((double)y0 + P[1]);
+    const double cxd = floor(fx / o.ps) + 1.0, cyd = floor(fy / o.ps) + 1.0;
+    if (!(cxd >= 0.0 && cxd < (double)Wc && cyd >= 0.0 && cyd < (double)Hc)) return -1;
+    return (int)cyd * Wc + (int)cxd;
+}
+
+__global__ __launch_bounds__(256) void k_fb_count(const FbLaunch F) {
+    const int d = blockIdx.y;
+    const DensifyArgs& o = F.L.pairs[1 - d].da;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= o.nx * o.ny) return;
+    const int c = fb_cell(o, j, F.Wc, F.Hc);
+    if (c >= 0) atomicAdd(F.bins[d].count + c, 1);
+}
+
+// exclusive prefix sum of the counts (one block per direction); clears the
+// counts for the next use
+__global__ __launch_bounds__(1024) void k_fb_scan(const FbLaunch F) {
+    __shared__ int part[1024];
+    const FbBins& B = F.bins[blockIdx.y];
+    const int n = F.Wc * F.Hc;
+    const int per = (n + 1023) / 1024;
+    const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
+    int sum = 0;
+    for (int i = lo; i < hi; ++i) sum += B.count[i];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int i = lo; i < hi; ++i) {
+        const int c = B.count[i];
+        B.start[i] = run;
+        B.cursor[i] = run;
+        B.count[i] = 0;
+        run += c;
+    }
+    if (threadIdx.x == 1023) B.start[n] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_fb_scatter(const FbLaunch F) {
+    const int d = blockIdx.y;
+    const DensifyArgs& o = F.L.pairs[1 - d].da;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= o.nx * o.ny) return;
+    const int c = fb_cell(o, j, F.Wc, F.Hc);
+    if (c >= 0) F.bins[d].list[atomicAdd(F.bins[d].cursor + c, 1)] = j;
+}
+
+// Eq. (3) merged over both directions (App. B ii) for the flow of direction
+// d: its own covering patches in ascending index, then the other
+// direction's patches whose displaced square covers the pixel, in ascending
+// index (sorted here, the bins hold them in arrival order), each voting -u
+// with the residual of its template sampled bilinearly at x - u.
+__global__ __launch_bounds__(256) void k_fb_densify(const FbLaunch F) {
+    const int d = blockIdx.z;
+    const DensifyArgs& a = F.L.pairs[d].da;
+    const DensifyArgs& o = F.L.pairs[1 - d].da;
+    const FbBins& B = F.bins[d];
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int W = a.W, H = a.H;
+    if (x >= W || y >= H) return;
+    double su = 0.0, sv = 0.0, sw = 0.0;
+    {
+        // own patches, as Eq. (3) (the sums, not yet divided)
+        int kx0, kx1, ky0, ky1;
+        bool fx, fy;
+        cover_range(x, W, a.ps, a.st, a.nrx, a.nx, kx0, kx1, fx);
+        cover_range(y, H, a.ps, a.st, a.nry, a.ny, ky0, ky1, fy);
+        const double j0 = a.J0[y * W + x];
+        const int kyend = ky1 + (fy ? 1 : 0), kxend = kx1 + (fx ? 1 : 0);
+        for (int jy = ky0; jy <= kyend; ++jy) {
+            const int ky = jy <= ky1 ? jy : a.nry;
+            for (int jx = kx0; jx <= kxend; ++jx) {
+                const int kx = jx <= kx1 ? jx : a.nrx;
+                const double* P = a.patch + (size_t)(ky * a.nx + kx) * 4;
+                const double u = P[0], v = P[1];
+                const double q = bilin(a.J1, W, H, (double)x + u, (double)y + v);
+                const double dd = a.raw_residual ? (q - j0) : ((q - j0) - P[2]);
+                const double wgt = 1.0 / fmax(1.0, fabs(dd));
+                su = su + wgt * u;
+                sv = sv + wgt * v;
+                sw = sw + wgt;
+            }
+        }
+    }
+    // candidates of the other direction: 2 x 2 cells
+    const int ps = o.ps;
+    const double xr = (double)x, yr = (double)y;
+    const double j0 = a.J0[y * W + x];
+    auto covers = [&](int j, double& uj, double& vj, double& md) {
+        const int ky = j / o.nx, kx = j - ky * o.nx;
+        const int x0 = kx < o.nrx ? kx * o.st : o.W - ps;
+        const int y0 = ky < o.nry ? ky * o.st : o.H - ps;
+        const double* P = o.patch + (size_t)j * 4;
+        uj = P[0]; vj = P[1]; md = P[2];
+        const double xa = (double)x0 + uj, ya = (double)y0 + vj;
+        return xa <= xr && xr <= (double)x0 + (double)(ps - 1) + uj && ya <= yr &&
+               yr <= (double)y0 + (double)(ps - 1) + vj;
+    };
+    const int cx1 = x / ps + 1, cy1 = y / ps + 1;
+    int cand[DIS_FB_MAXCAND];
+    int nc = 0;
+    bool overflow = false;
+    for (int cy = cy1 - 1; cy <= cy1; ++cy)
+        for (int cx = cx1 - 1; cx <= cx1; ++cx) {
+            const int c = cy * F.Wc + cx;
+            for (int t = B.start[c]; t < B.start[c + 1]; ++t) {
+                const int j = B.list[t];
+                double uj, vj, md;
+                if (!covers(j, uj, vj, md)) continue;
+                if (nc == DIS_FB_MAXCAND) { overflow = true; continue; }
+                // insertion into the ascending list
+                int q = nc++;
+                while (q > 0 && cand[q - 1] > j) { cand[q] = cand[q - 1]; --q; }
+                cand[q] = j;
+            }
+        }
+    auto vote = [&](int j) {
+        double uj, vj, md;
+        covers(j, uj, vj, md);
+        const double tv = bilin(o.J0, W, H, xr - uj, yr - vj);   // the other direction's template frame
+        const double dd = a.raw_residual ? (j0 - tv) : ((j0 - tv) - md);
+        const double wgt = 1.0 / fmax(1.0, fabs(dd));
+        su = su - wgt * uj;
+        sv = sv - wgt * vj;
+        sw = sw + wgt;
+    };
+    if (!overflow) {
+        for (int q = 0; q < nc; ++q) vote(cand[q]);
+    } else {
+        // more covering patches than the sorted list holds: ascending order by
+        // repeated selection over the cells
+        int prev = -1;
+        for (;;) {
+            int best = 0x7fffffff;
+            for (int cy = cy1 - 1; cy <= cy1; ++cy)
+                for (int cx = cx1 - 1; cx <= cx1; ++cx) {
+                    const int c = cy * F.Wc + cx;
+                    for (int t = B.start[c]; t < B.start[c + 1]; ++t) {
+                        const int j = B.list[t];
+                        double uj, vj, md;
+                        if (j > prev && j < best && covers(j, uj, vj, md)) best = j;
+                    }
+                }
+            if (best == 0x7fffffff) break;
+            vote(best);
+            prev = best;
+        }
+    }
+    const double Uo = su / sw, Vo = sv / sw;
+    const int g = y * W + x;
+    a.U[g] = Uo;
+    a.U[W * H + g] = Vo;
+    if (a.J1w) a.J1w[g] = bilin(a.J1, W, H, xr + Uo, yr + Vo);
+}
+
 // --------------------------------------------------------------- refinement
 
 using dis_tile::RefineSmem;
@@ -930,6 +1101,10 @@ const void* dis_kernel_upsample() { return (const void*)&k_upsample; }
 const void* dis_kernel_upsample_tab() { return (const void*)&k_upsample_tab; }
 const void* dis_kernel_phase_densify() { return (const void*)&k_phase_densify; }
 const void* dis_kernel_small_level() { return (const void*)&k_small_level<DIS_SMALL_THREADS>; }
+const void* dis_kernel_fb_count() { return (const void*)&k_fb_count; }
+const void* dis_kernel_fb_scan() { return (const void*)&k_fb_scan; }
+const void* dis_kernel_fb_scatter() { return (const void*)&k_fb_scatter; }
+const void* dis_kernel_fb_densify() { return (const void*)&k_fb_densify; }
 
 // instances whose per-lane pixel arrays fit the 256 architectural VGPRs
 #define DIS_FOR_SEARCH_INSTANCES(X) \

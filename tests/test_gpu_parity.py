@@ -162,7 +162,7 @@ def test_size_errors():
         d.close()
 
 
-@pytest.mark.parametrize("case", ["c2b", "c1", "inner7", "l1", "stereo"])
+@pytest.mark.parametrize("case", ["c2b", "c1", "inner7", "l1", "stereo", "fb"])
 def test_launch_choices_are_bitwise_invariant(case):
     """Persistent vs per-phase launches, lanes per patch and refinement tiles
     change the schedule, never a bit of the flow."""
@@ -175,6 +175,8 @@ def test_launch_choices_are_bitwise_invariant(case):
         pr, p = pair("bump", 256, 192, 8.0, 1), params(101, norm=1)
     elif case == "stereo":
         pr, p = pair("hbump", 256, 192, 8.0, 17), params(101, flags=0x20)
+    elif case == "fb":
+        pr, p = pair("bump", 256, 192, 8.0, 1), params(101, flags=0x40)
     else:   # 7 SOR sweeps: each fixed-point step spans two launches
         pr, p = pair("bump", 288, 216, 10.0, 13), params(105, var_inner=7)
     h, w = pr.I0.shape
@@ -196,5 +198,70 @@ def test_launch_choices_are_bitwise_invariant(case):
             outs.append(o.cpu().numpy())
         for o in outs[1:]:
             assert np.array_equal(o, outs[0])
+    finally:
+        d.close()
+
+
+FB_CASES = [
+    # name, generator, preset, overrides (finest scale 0: both directions at full resolution)
+    ("fb_bump_256x192", ("bump", 256, 192, 8.0, 1), 101, dict(finest_scale=0)),
+    ("fb_layered_320x240", ("layered", 320, 240, 30.0, 21), 103, dict(coarsest_scale=3, finest_scale=0)),
+    ("fb_norefine_raw_203x149", ("layered", 203, 149, 20.0, 22), 103,
+     dict(coarsest_scale=3, finest_scale=0, refine=0, flags=0x8)),
+    # stride 1: more than 32 covering patches of the other direction per pixel
+    ("fb_dense_96x64", ("bump", 96, 64, 4.0, 23), 101, dict(overlap=0.875, coarsest_scale=1, finest_scale=0)),
+]
+
+
+@pytest.mark.parametrize("name,gen,preset,over", FB_CASES, ids=[c[0] for c in FB_CASES])
+def test_fb_consistency_parity(name, gen, preset, over):
+    """Forward-backward consistent densification (App. B ii): both
+    directions' flows against the oracle's two-direction driver."""
+    say(f"[fb] case {name}")
+    from oracle import dis_oracle as O
+    pr = pair(*gen)
+    p = params(preset, **over)
+    p.flags = int(p.flags) | _lib.DIS_FLAG_FB_CONSISTENCY
+    op = oracle_params(p)
+    Uf_ref, Ub_ref = (t.numpy() for t in O.dis_flow_fb(torch.from_numpy(pr.I0), torch.from_numpy(pr.I1), op))
+    Uf, d = gpu_flow(pr.I0, pr.I1, p, keep=True)
+    try:
+        Ub = d.debug_level(0, _lib.DIS_DBG_UREFINED_BWD)
+    finally:
+        d.close()
+    for tag, U, R, gt in (("forward", Uf, Uf_ref, pr.flow), ("backward", Ub, Ub_ref, None)):
+        dd = np.sqrt(((U - R) ** 2).sum(0))
+        frac = float((dd <= 1e-2).mean())
+        say(f"[fb] {name} {tag}: within 1e-2 px {frac:.6f}, max diff {dd.max():.2e}")
+        assert frac >= PARITY_FRAC
+        if gt is not None:
+            _, erel, _ = parity(U, R, gt)
+            assert erel <= PARITY_EPE_REL
+
+
+def test_fb_differs_from_plain_and_refusals():
+    """With the merge on, the flow differs from the plain forward run, and
+    the batched and backward calls refuse the merged handle."""
+    say("[fb] c1 bump 256x192 plain vs merged; refusals")
+    pr = pair("bump", 256, 192, 8.0, 1)
+    plain = gpu_flow(pr.I0, pr.I1, params(101))
+    p = params(101, flags=_lib.DIS_FLAG_FB_CONSISTENCY)
+    merged, d = gpu_flow(pr.I0, pr.I1, p, keep=True)
+    try:
+        assert not np.array_equal(plain, merged)
+        t0 = torch.from_numpy(pr.I0).cuda()
+        with pytest.raises(DisError) as e:
+            d.flow_batched([t0], [t0])
+        assert e.value.code == _lib.DIS_EINVAL
+    finally:
+        d.close()
+    d = DIS(params(101, flags=_lib.DIS_FLAG_FB_CONSISTENCY | _lib.DIS_FLAG_KEEP_FOR_BACKWARD), 256, 192)
+    try:
+        t0 = torch.from_numpy(pr.I0).cuda()
+        t1 = torch.from_numpy(pr.I1).cuda()
+        out = d.flow(t0, t1)
+        with pytest.raises(DisError) as e:
+            d.backward(torch.ones_like(out))
+        assert e.value.code == _lib.DIS_EINVAL
     finally:
         d.close()
