@@ -59,6 +59,7 @@ R18 stereo (App. I, an extension): the vertical degree of freedom is
     relaxes du only (dv stays 0), so the flow's second plane is zero.
 R19 forward-backward consistency (App. B ii, an extension): see
     merged_densify below for the reading of the merged Eq. (3).
+R20 colour (App. B i, an extension): see colour_search below.
 """
 from __future__ import annotations
 
@@ -710,3 +711,146 @@ def dis_flow_fb(I0, I1, p: OracleParams, merge: bool = True):
         else:
             Uf, Ub = Udf, Udb
     return upsample(Uf, w, h, sf, p), upsample(Ub, w, h, sf, p)
+
+
+# ------------------------------------------------------------ colour (App. B i)
+#
+# R20 (an extension): frames have C channels (RGB: 3), each scaled to 0..255
+# with a pyramid of its own (R1, R2 per channel).  The search minimises the
+# patch error summed over the channels: every channel is mean-normalised on
+# its own (R9), S'^c is the Sobel/8 gradient of channel c of the template, and
+# H' and the right-hand side are sums over channels of the grey ones (R10's
+# lambda is added once); R17's transform acts on each channel's residual.  The
+# densification weight of Eq. (3) takes |d_i(x)| as the Euclidean norm over
+# channels of the per-channel residuals of R13 (one channel: |d|).  The
+# refinement uses all channels jointly, in the multi-channel form of the
+# variational method the paper cites: the brightness and gradient data terms
+# are sums over channels of the grey terms, each channel with its own
+# linearisation and normalisers (R15), and one robust function per term
+# applied to the channel sum; the smoothness term is unchanged.
+
+def colour_search(J0s, J1s, x0, y0, u_init, p: OracleParams) -> SearchResult:
+    """Inverse search on C-channel levels ([C, h, w]); ``d`` of the result
+    is [C, N, P] (the per-channel residual at the final u)."""
+    ps = p.patch_size
+    px, py = patch_offsets(ps)
+    X = x0[:, None] + px[None, :]
+    Y = y0[:, None] + py[None, :]
+    C = J0s.shape[0]
+    T, Tn, gx, gy = [], [], [], []
+    for c in range(C):
+        Gx, Gy = sobel8(J0s[c])
+        T.append(J0s[c][Y, X])
+        Tn.append(T[c] - T[c].mean(dim=1, keepdim=True))
+        gx.append(Gx[Y, X])
+        gy.append(Gy[Y, X])
+    h11 = sum((gx[c] * gx[c]).sum(1) for c in range(C))
+    h12 = sum((gx[c] * gy[c]).sum(1) for c in range(C))
+    h22 = sum((gy[c] * gy[c]).sum(1) for c in range(C))
+    lam = p.hessian_lambda
+    a11, a12, a22 = h11 + lam, h12, h22 + lam
+    det = a11 * a22 - a12 * a12
+    Xf = X.to(F64)
+    Yf = Y.to(F64)
+
+    u = u_init.clone()
+    for _ in range(p.gn_iters):
+        b1 = torch.zeros_like(h11)
+        b2 = torch.zeros_like(h11)
+        for c in range(C):
+            Q = bilinear(J1s[c], Xf + u[:, 0:1], Yf + u[:, 1:2])
+            r = robust_residual((Q - Q.mean(dim=1, keepdim=True)) - Tn[c], p)
+            b1 = b1 + (gx[c] * r).sum(1)
+            b2 = b2 + (gy[c] * r).sum(1)
+        if p.stereo:
+            du = b1 / a11
+            dv = torch.zeros_like(du)
+        else:
+            du = (a22 * b1 - a12 * b2) / det
+            dv = (a11 * b2 - a12 * b1) / det
+        u = u - torch.stack([du, dv], dim=1)
+
+    moved = torch.sqrt(((u - u_init) ** 2).sum(1))
+    reset = moved > ps
+    u_final = torch.where(reset[:, None], u_init, u)
+    d = []
+    for c in range(C):
+        Q = bilinear(J1s[c], Xf + u_final[:, 0:1], Yf + u_final[:, 1:2])
+        d.append((Q - Q.mean(dim=1, keepdim=True)) - Tn[c] if p.residual == "normalised" else Q - T[c])
+    H = torch.stack([torch.stack([h11, h12], -1), torch.stack([h12, h22], -1)], -2)
+    return SearchResult(u_final, u, u_init, reset, torch.stack(d), H, [])
+
+
+def colour_densify(w: int, h: int, x0, y0, u, d, p: OracleParams):
+    """Eq. (3) with |d_i(x)| the norm over channels of d [C, N, P]."""
+    return densify(w, h, x0, y0, u, torch.sqrt((d * d).sum(0)), p)
+
+
+def colour_linearise(J0s, J1s, U):
+    """R15 per channel: one RefineTerms per channel."""
+    return [refine_linearise(J0s[c], J1s[c], U) for c in range(J0s.shape[0])]
+
+
+def colour_data_energies(ts, du, dv):
+    """Channel sums of the grey E_I and E_G at increment (du, dv)."""
+    ei, eg = 0.0, 0.0
+    for t in ts:
+        a, b = data_energies(t, du, dv)
+        ei = ei + a
+        eg = eg + b
+    return ei, eg
+
+
+def colour_sor_system(ts, U, du, dv, p: OracleParams) -> SorSystem:
+    """One robust weight per data term over the channel sum; the matrix and
+    vector are channel sums of the grey ones at those weights."""
+    ei, eg = colour_data_energies(ts, du, dv)
+    pi = p.delta / (2.0 * robust(ei, p.eps))
+    pg = p.gamma / (2.0 * robust(eg, p.eps))
+    ws = p.alpha / (2.0 * robust(smooth_energy(U[0] + du, U[1] + dv), p.eps))
+    A11 = A12 = A22 = b1 = b2 = 0.0
+    for t in ts:
+        A11 = A11 + pi * t.b0 * t.Ix * t.Ix + pg * (t.bx * t.Ixx * t.Ixx + t.by * t.Ixy * t.Ixy)
+        A12 = A12 + pi * t.b0 * t.Ix * t.Iy + pg * (t.bx * t.Ixx * t.Ixy + t.by * t.Ixy * t.Iyy)
+        A22 = A22 + pi * t.b0 * t.Iy * t.Iy + pg * (t.bx * t.Ixy * t.Ixy + t.by * t.Iyy * t.Iyy)
+        b1 = b1 + pi * t.b0 * t.Ix * t.Iz + pg * (t.bx * t.Ixx * t.Ixz + t.by * t.Ixy * t.Iyz)
+        b2 = b2 + pi * t.b0 * t.Iy * t.Iz + pg * (t.bx * t.Ixy * t.Ixz + t.by * t.Iyy * t.Iyz)
+    return SorSystem(A11, A12, A22, b1, b2, ws)
+
+
+def colour_refine(J0s, J1s, U, n_outer: int, p: OracleParams):
+    ts = colour_linearise(J0s, J1s, U)
+    du = torch.zeros_like(U[0])
+    dv = torch.zeros_like(U[1])
+    for _ in range(n_outer):
+        sys = colour_sor_system(ts, U, du, dv, p)
+        du, dv = sor_sweeps(sys, U, du, dv, p.var_inner, p.sor_omega, stereo=p.stereo)
+    return torch.stack([U[0] + du, U[1] + dv])
+
+
+def dis_flow_colour(I0: torch.Tensor, I1: torch.Tensor, p: OracleParams, records: Optional[list] = None):
+    """Alg. 1 on C-channel frames [C, H, W] (R20).  Returns the flow [2, H, W]."""
+    I0 = torch.as_tensor(I0).to(F64)
+    I1 = torch.as_tensor(I1).to(F64)
+    C, h, w = I0.shape
+    ss = coarsest_scale(w, h, p)
+    sf = p.finest_scale
+    if sf > ss:
+        raise ValueError(f"finest scale {sf} above coarsest scale {ss}")
+    P0 = [build_pyramid(p.intensity_scale * I0[c], ss) for c in range(C)]
+    P1 = [build_pyramid(p.intensity_scale * I1[c], ss) for c in range(C)]
+    U = None
+    for s in range(ss, sf - 1, -1):
+        J0s = torch.stack([P0[c][s] for c in range(C)])
+        J1s = torch.stack([P1[c][s] for c in range(C)])
+        hs, ws_ = J0s.shape[1:]
+        x0, y0, _, _ = patch_grid(ws_, hs, p)
+        u_init = init_displacements(U, x0, y0, p)
+        res = colour_search(J0s, J1s, x0, y0, u_init, p)
+        Ud, _ = colour_densify(ws_, hs, x0, y0, res.u, res.d, p)
+        n_outer = outer_iterations(s, p)
+        Ur = colour_refine(J0s, J1s, Ud, n_outer, p) if p.refine else Ud
+        if records is not None:
+            records.append(LevelRecord(s, u_init, res, Ud, Ur, n_outer))
+        U = Ur
+    return upsample(U, w, h, sf, p)

@@ -37,8 +37,8 @@ __all__ = [
 
 @dataclass
 class FramePair:
-    I0: np.ndarray          # float32 [H][W]
-    I1: np.ndarray          # float32 [H][W]
+    I0: np.ndarray          # float32 [H][W] (colour: [C][H][W])
+    I1: np.ndarray          # float32 [H][W] (colour: [C][H][W])
     flow: np.ndarray        # float64 [2][H][W], ground truth
     occluded: np.ndarray    # bool [H][W], True where x+flow is hidden or off-frame
 
@@ -92,7 +92,8 @@ def _sample_bilinear(img: np.ndarray, x: np.ndarray, y: np.ndarray) -> np.ndarra
 
 
 def smooth_bump_pair(w: int, h: int, max_disp: float, seed: int,
-                     noise_sigma: float = 0.01, n_bumps: int = 4, horizontal: bool = False) -> FramePair:
+                     noise_sigma: float = 0.01, n_bumps: int = 4, horizontal: bool = False,
+                     channels: int = 1) -> FramePair:
     """I0 = texture; I1(y) = I0(y - v(y)) + noise, with v a sum of Gaussian bumps.
 
     The bump centres are uniform in the frame, widths uniform in
@@ -100,6 +101,12 @@ def smooth_bump_pair(w: int, h: int, max_disp: float, seed: int,
     largest displacement is ``max_disp`` px (``horizontal``: every bump
     points left or right, a rectified stereo pair).  Ground truth u solves
     u(x) = v(x + u(x)) (then I1(x + u) = I0(x)), by fixed-point iteration.
+
+    ``channels`` > 1 gives colour frames ``[C][H][W]`` (planar): channel 0 is
+    the grey pair above, drawn identically; channel c > 0 mixes that texture
+    (weight 0.6) with a texture of its own (0.4), so the channels correlate
+    as natural colour channels do, and carries noise of its own.  The extra
+    draws come after every draw of the grey pair.
     """
     rng = np.random.default_rng(seed)
     pad = int(math.ceil(max_disp)) + 4
@@ -145,6 +152,14 @@ def smooth_bump_pair(w: int, h: int, max_disp: float, seed: int,
         if delta < 1e-10:
             break
     occ = (xx + ux < 0) | (xx + ux > w - 1) | (yy + uy < 0) | (yy + uy > h - 1)
+    if channels > 1:
+        c0, c1 = [I0], [I1]
+        for _ in range(1, channels):
+            cv = 0.6 * canvas + 0.4 * texture(h + 2 * pad, w + 2 * pad, rng)
+            c0.append(cv[pad:pad + h, pad:pad + w])
+            J1 = _sample_bilinear(cv, xx - vx + pad, yy - vy + pad)
+            c1.append(J1 + rng.normal(0.0, noise_sigma, J1.shape))
+        I0, I1 = np.stack(c0), np.stack(c1)
     return FramePair(np.clip(I0, 0, 1).astype(np.float32),
                      np.clip(I1, 0, 1).astype(np.float32),
                      np.stack([ux, uy]), occ)

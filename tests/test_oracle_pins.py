@@ -696,3 +696,110 @@ def test_r19_patches_displaced_off_the_level_vote_nowhere():
                                 torch.tensor([[-23.0, 0.0]], dtype=F64), md[:1], p)
     changed = (U1 != ref).any(0)
     assert bool(changed[:8, 0].all()) and not bool(changed[:, 1:].any()) and not bool(changed[8:, :].any())
+
+
+# ------------------------------------------------------------------ R20 ------
+def _colour_pair(w, h, seed, disp=4.0):
+    from paper_1603_03590_amd import synth
+    pr = synth.smooth_bump_pair(w, h, disp, seed, channels=3)
+    return torch.from_numpy(pr.I0).double(), torch.from_numpy(pr.I1).double(), pr
+
+
+def test_r20_zero_channels_reduce_to_the_grey_method():
+    """Two all-zero channels add exact zeros to H', to the right-hand side
+    and to both data terms of the refinement, and the channel norm of Eq. (3)
+    is then sqrt(d^2) = |d| (torch's vectorised CPU sqrt is not always
+    correctly rounded, so the norm may differ from |d| in the last bit): the
+    colour method is the grey one to rounding."""
+    a, b, _ = _colour_pair(96, 80, 50)
+    z = torch.zeros_like(a[0])
+    for kw in (dict(), dict(norm="l1"), dict(refine=False, residual="raw")):
+        p = params(coarsest_scale=2, gn_iters=8, var_outer=2, **kw)
+        Uc = O.dis_flow_colour(torch.stack([a[0], z, z]), torch.stack([b[0], z, z]), p)
+        assert torch.allclose(Uc, O.dis_flow(a[0], b[0], p), rtol=0, atol=1e-12), kw
+    # the search alone involves no square root: bit for bit
+    p = params(gn_iters=8, norm="l1")
+    x0, y0, _, _ = O.patch_grid(96, 80, p)
+    ui = torch.full((x0.numel(), 2), 0.3, dtype=F64)
+    J0, J1 = 255 * a[0], 255 * b[0]
+    rc = O.colour_search(torch.stack([J0, z, z]), torch.stack([J1, z, z]), x0, y0, ui, p)
+    Gx, Gy = O.sobel8(J0)
+    rg = O.inverse_search(J0, Gx, Gy, J1, x0, y0, ui, p)
+    assert torch.equal(rc.u, rg.u) and torch.equal(rc.d[0], rg.d) and not bool(rc.d[1:].any())
+
+
+def test_r20_three_equal_channels_triple_the_normal_equations():
+    """Channels (J, J, J): H' and the right-hand side are three times the
+    grey ones, so the step solves (3H + lambda I) du = 3b, the grey step with
+    lambda / 3.  A search that dropped or doubled a channel fails this."""
+    a, b, _ = _colour_pair(64, 64, 51)
+    J0, J1 = 255 * a[0], 255 * b[0]
+    p = params(gn_iters=6)
+    x0, y0, _, _ = O.patch_grid(64, 64, p)
+    g = torch.Generator().manual_seed(3)
+    ui = torch.rand(x0.numel(), 2, generator=g, dtype=F64) * 2 - 1
+    rc = O.colour_search(torch.stack([J0, J0, J0]), torch.stack([J1, J1, J1]), x0, y0, ui, p)
+    Gx, Gy = O.sobel8(J0)
+    rg = O.inverse_search(J0, Gx, Gy, J1, x0, y0, ui, O.with_params(p, hessian_lambda=p.hessian_lambda / 3))
+    assert torch.allclose(rc.u, rg.u, rtol=0, atol=1e-9)
+    assert torch.allclose(rc.hessian, 3 * rg.hessian, rtol=1e-15, atol=0)
+    for c in range(3):
+        assert torch.allclose(rc.d[c], rg.d, rtol=0, atol=1e-9)
+
+
+def test_r20_channel_norm_of_the_densification_weight_by_hand():
+    """Two patches on the same square; per-channel residuals (3, 4, 0) and
+    (0.5, 0, 0): weights 1/5 and 1, so U = (u1/5 + u2) / (1/5 + 1)."""
+    p = params(patch_size=4)
+    x0 = torch.tensor([0, 0]); y0 = torch.tensor([0, 0])
+    u = torch.tensor([[2.0, -1.0], [0.5, 0.25]], dtype=F64)
+    d = torch.zeros(3, 2, 16, dtype=F64)
+    d[0, 0], d[1, 0] = 3.0, 4.0
+    d[0, 1] = 0.5
+    U, Z = O.colour_densify(4, 4, x0, y0, u, d, p)
+    assert torch.allclose(Z, torch.full((4, 4), 1.2, dtype=F64), rtol=0, atol=1e-15)
+    assert torch.allclose(U[0], torch.full((4, 4), (2.0 / 5 + 0.5) / 1.2, dtype=F64), rtol=0, atol=1e-15)
+    assert torch.allclose(U[1], torch.full((4, 4), (-1.0 / 5 + 0.25) / 1.2, dtype=F64), rtol=0, atol=1e-15)
+
+
+def test_r20_one_robust_function_over_the_channel_sum():
+    """Channels (J, J, J) in the refinement: each data energy triples inside
+    one robust function, so the frozen system is the grey one with delta and
+    gamma times sqrt(3) and eps / sqrt(3) (the data part; the smoothness
+    weight keeps eps).  A robust function per channel would give 3 delta and
+    eps instead."""
+    a, b, _ = _colour_pair(48, 40, 52)
+    J0, J1 = 255 * a[0], 255 * b[0]
+    g = torch.Generator().manual_seed(4)
+    U = torch.rand(2, 40, 48, generator=g, dtype=F64) * 2 - 1
+    du = torch.rand(40, 48, generator=g, dtype=F64) * 0.2
+    dv = torch.rand(40, 48, generator=g, dtype=F64) * 0.2
+    p = params()
+    t = O.refine_linearise(J0, J1, U)
+    ts = O.colour_linearise(torch.stack([J0, J0, J0]), torch.stack([J1, J1, J1]), U)
+    sc = O.colour_sor_system(ts, U, du, dv, p)
+    r3 = math.sqrt(3.0)
+    sg = O.sor_system(t, U, du, dv, O.with_params(p, delta=r3 * p.delta, gamma=r3 * p.gamma, eps=p.eps / r3))
+    for name in ("A11", "A12", "A22", "b1", "b2"):
+        x, y = getattr(sc, name), getattr(sg, name)
+        assert torch.allclose(x, y, rtol=1e-12, atol=1e-12 * float(y.abs().max())), name
+
+
+def test_r20_channel_order_does_not_matter_and_integer_shift_is_fixed():
+    """Permuting the channels permutes only the order of the channel sums;
+    an integer shift of all channels is a fixed point of the colour search."""
+    a, b, pr = _colour_pair(96, 80, 53)
+    p = params(coarsest_scale=2, gn_iters=8, var_outer=2)
+    U = O.dis_flow_colour(a, b, p)
+    Up = O.dis_flow_colour(a[[2, 0, 1]], b[[2, 0, 1]], p)
+    assert torch.allclose(U, Up, rtol=0, atol=1e-6)
+    # using one channel only (or the grey frame) is a different method
+    assert float((U - O.dis_flow(a[0], b[0], p)).abs().max()) > 1e-3
+    J0 = 255 * a
+    J1 = torch.roll(J0, shifts=(1, 2), dims=(1, 2))        # J1(x + (2, 1)) = J0(x) away from the wrap
+    p8 = params(patch_size=8, overlap=0.5)
+    x0, y0, _, _ = O.patch_grid(96, 80, p8)
+    keep = (x0 >= 2) & (x0 + 8 + 2 <= 96) & (y0 >= 1) & (y0 + 8 + 1 <= 80)
+    ui = torch.tensor([[2.0, 1.0]], dtype=F64).expand(int(keep.sum()), 2).clone()
+    r = O.colour_search(J0, J1, x0[keep], y0[keep], ui, p8)
+    assert torch.equal(r.u, ui)
