@@ -82,6 +82,8 @@ def main():
                          "(for counter runs, where the profiler's serialisation would mislead the autotuner)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB five times (calibrates HBM counters)")
+    ap.add_argument("--ext-steps", type=int, default=100,
+                    help="timed steps of each extension (robust norms, stereo, forward-backward, colour); 0 skips")
     ap.add_argument("--fwd-bwd-pairs", type=int, default=8,
                     help="pairs of 512x256 in the forward+backward measurement (0 skips it)")
     args = ap.parse_args()
@@ -297,6 +299,40 @@ def main():
         log(f"[bench] fwd+bwd: {t_fb * 1e3:.3f} ms per {nfb} pairs ({pix / t_fb / 1e6:.0f} Mpix/s); "
             f"forward only {t_f * 1e3:.3f} ms")
 
+    # the paper's extensions (App. B, App. I) on the headline's frame size and
+    # operating point: robust norms, stereo, forward-backward consistency,
+    # colour frames; autotuned, graph replay, frames resident in HBM
+    ext = {}
+    if not args.headline_only and args.ext_steps > 0:
+        hb = synth.smooth_bump_pair(W, H, 40.0, 2, horizontal=True)
+        cb = synth.smooth_bump_pair(W, H, 40.0, 2, channels=3)
+        cases = [
+            ("l1", pr, dict(norm=_lib.DIS_NORM_L1), "layered pair of the headline, L1 search norm (App. B iii)"),
+            ("huber", pr, dict(norm=_lib.DIS_NORM_HUBER),
+             "layered pair of the headline, Huber search norm, b = 1 (App. B iii)"),
+            ("stereo", hb, dict(flags=_lib.DIS_FLAG_STEREO),
+             "smooth-bump pair 1024x436, horizontal motion up to 40 px (seed 2), 1-D search and refinement (App. I)"),
+            ("fb_consistency", pr, dict(flags=_lib.DIS_FLAG_FB_CONSISTENCY),
+             "layered pair of the headline, both directions with the merged densification (App. B ii)"),
+            ("colour", cb, dict(flags=_lib.DIS_FLAG_COLOUR),
+             "smooth-bump pair 1024x436, 3 correlated colour channels, motion up to 40 px (seed 2) (App. B i)"),
+        ]
+        for name, q, over, what in cases:
+            pe = params(presets[args.op], **over)
+            d = DIS(pe, W, H)
+            a = torch.from_numpy(q.I0).cuda()
+            b = torch.from_numpy(q.I1).cuda()
+            o = torch.empty((2, H, W), device="cuda")
+            call = lambda: d.flow(a, b, o)
+            call()
+            d.autotune()
+            t = time_calls(call, args.ext_steps, max(3, args.warmup // 3))
+            ext[name] = dict(value=W * H / t / 1e6, unit="Mpix/s", ms_per_step=t * 1e3,
+                             workload=what + f"; operating point {args.op}", _flow=o.cpu().numpy().astype(np.float64),
+                             _case=(q, pe))
+            d.close()
+            log(f"[bench] extension {name}: {t * 1e3:.4f} ms/pair")
+
     # parity of these runs and the CPU baseline (the FP64 oracle as it stands)
     parity = {}
     cpu = None
@@ -330,6 +366,18 @@ def main():
                                        "grad_I1_rel_max_err": rel(g1, r1.numpy()),
                                        "loss_rel_diff": abs(L / float(Lr) - 1.0),
                                        "passed": bool(rel(g0, r0.numpy()) <= 1e-4 and rel(g1, r1.numpy()) <= 1e-4)}
+        for name, e in ext.items():
+            q, pe = e["_case"]
+            op_e = oracle_params(pe)
+            if name == "colour":
+                U_ref = O.dis_flow_colour(torch.from_numpy(q.I0), torch.from_numpy(q.I1), op_e).numpy()
+            elif name == "fb_consistency":
+                U_ref = O.dis_flow_fb(torch.from_numpy(q.I0), torch.from_numpy(q.I1), op_e)[0].numpy()
+            else:
+                U_ref = O.dis_flow(torch.from_numpy(q.I0), torch.from_numpy(q.I1), op_e).numpy()
+            frac, erel, dmax = parity_stats(e["_flow"], U_ref, q.flow)
+            parity[f"ext_{name}"] = {"frac_within_1e-2px": frac, "mean_epe_rel_diff": erel, "max_abs_diff_px": dmax,
+                                     "passed": bool(frac >= 0.999 and erel <= 0.005)}
         op_p = oracle_params(params(presets[args.op]))
         t0 = time.perf_counter()
         runs = 0
@@ -344,6 +392,9 @@ def main():
     if batched:
         batched.pop("_sample")
         batched.pop("_out")
+    for e in ext.values():
+        e.pop("_flow")
+        e.pop("_case")
 
     cfg = dict(
         workload=f"plain DIS, one {W}x{H} grayscale float32 pair: layered scene (background + 6 textured "
@@ -379,6 +430,7 @@ def main():
                                   if other in results else None),
         "batched": batched,
         "fwd_bwd": fwd_bwd,
+        "extensions": ext or None,
     }
     print(json.dumps(line), flush=True)
 

@@ -54,6 +54,7 @@ extern "C" {
 #define DIS_FLAG_IO_F64 0x10u           /* frames, flow and gradients are float64 */
 #define DIS_FLAG_STEREO 0x20u           /* rectified stereo (App. I): horizontal displacement only, v = 0 */
 #define DIS_FLAG_FB_CONSISTENCY 0x40u   /* forward-backward consistent densification (App. B ii), plain calls */
+#define DIS_FLAG_COLOUR 0x80u           /* RGB frames (App. B i): 3 planar channels, plain calls, patch 4..12 */
 
 /*
  * Method parameters: Table 1 of the paper and the fixed values of Sec. 3.1.
@@ -142,7 +143,13 @@ int dis_create(const dis_params* p, int max_w, int max_h, int max_batch,
  * patches and the other direction's displaced patches (votes -u, residual of
  * the displaced template sampled bilinearly), refines each direction on its
  * own, and `flow` receives the I0 -> I1 flow (the other direction through
- * DIS_DBG_UREFINED_BWD).  The handle then holds two pair slots.
+ * DIS_DBG_UREFINED_BWD).  The handle then holds two pair slots.  With
+ * DIS_FLAG_COLOUR the frames are planar [3][h][pitch] (channel c at element
+ * offset c * h * pitch); the search sums its normal equations over the
+ * channels, Eq. (3) weighs by the norm over channels of the residuals, and
+ * the refinement sums both data terms over the channels inside one robust
+ * function each (App. B i).  It does not combine with
+ * DIS_FLAG_FB_CONSISTENCY, batched calls or dis_flow_backward (DIS_EINVAL).
  */
 int dis_compute_flow(dis_handle* h, const void* I0, const void* I1, int w, int hgt,
                      int pitch, void* flow);

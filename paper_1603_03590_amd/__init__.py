@@ -11,11 +11,12 @@ import numpy as np
 
 from . import _lib
 from ._lib import (DisError, DisLibraryMissing, dis_params, DIS_FLAG_KEEP_FOR_BACKWARD, DIS_FLAG_NO_GRAPH,
-                   DIS_FLAG_PIXEL_CENTRE, DIS_FLAG_RAW_RESIDUAL, DIS_FLAG_IO_F64)
+                   DIS_FLAG_PIXEL_CENTRE, DIS_FLAG_RAW_RESIDUAL, DIS_FLAG_IO_F64, DIS_FLAG_STEREO,
+                   DIS_FLAG_FB_CONSISTENCY, DIS_FLAG_COLOUR)
 
 __all__ = ["DIS", "params", "compute_flow", "dis_flow", "DisError", "DisLibraryMissing", "dis_params",
            "DIS_FLAG_KEEP_FOR_BACKWARD", "DIS_FLAG_NO_GRAPH", "DIS_FLAG_PIXEL_CENTRE",
-           "DIS_FLAG_RAW_RESIDUAL", "DIS_FLAG_IO_F64"]
+           "DIS_FLAG_RAW_RESIDUAL", "DIS_FLAG_IO_F64", "DIS_FLAG_STEREO", "DIS_FLAG_FB_CONSISTENCY", "DIS_FLAG_COLOUR"]
 
 PRESETS = {"op1": 1, "op2": 2, "op3": 3, "op4": 4, "c1": 101, "c2a": 102, "c2b": 103, "c3": 104,
            "c5": 105, "c4": 106}
@@ -64,11 +65,15 @@ class DIS:
             pass
 
     def _frame(self, I):
-        torch = _torch()
-        if I.dtype != self.dtype or I.device.type != "cuda" or I.dim() != 2:
-            raise ValueError(f"frames must be 2-D {self.dtype} tensors on the GPU")
-        if I.stride(1) != 1:
+        colour = bool(int(self.p.flags) & _lib.DIS_FLAG_COLOUR)
+        dims = 3 if colour else 2
+        if I.dtype != self.dtype or I.device.type != "cuda" or I.dim() != dims:
+            kind = "[3, H, W]" if colour else "[H, W]"
+            raise ValueError(f"frames must be {kind} {self.dtype} tensors on the GPU")
+        if I.stride(-1) != 1:
             raise ValueError("frames must have unit column stride")
+        if colour and (I.shape[0] != 3 or I.stride(0) != I.shape[1] * I.stride(1)):
+            raise ValueError("colour frames must hold 3 planes, channel stride = height x row pitch")
         return I
 
     def flow(self, I0, I1, out=None):
@@ -78,10 +83,10 @@ class DIS:
         I1 = self._frame(I1)
         if I0.shape != I1.shape or I0.stride() != I1.stride():
             raise ValueError("frames must have the same shape and strides")
-        h, w = I0.shape
+        h, w = I0.shape[-2:]
         if out is None:
             out = torch.empty((2, h, w), dtype=self.dtype, device=I0.device)
-        _lib.dis_compute_flow(self.handle, I0.data_ptr(), I1.data_ptr(), w, h, I0.stride(0), out.data_ptr())
+        _lib.dis_compute_flow(self.handle, I0.data_ptr(), I1.data_ptr(), w, h, I0.stride(-2), out.data_ptr())
         self._generation = getattr(self, "_generation", 0) + 1
         return out
 

@@ -28,6 +28,7 @@ DIS_FLAG_RAW_RESIDUAL = 0x8
 DIS_FLAG_IO_F64 = 0x10
 DIS_FLAG_STEREO = 0x20
 DIS_FLAG_FB_CONSISTENCY = 0x40
+DIS_FLAG_COLOUR = 0x80
 
 DIS_NORM_L2 = 0
 DIS_NORM_L1 = 1

@@ -413,6 +413,7 @@ extern "C" int dis_flow_backward(dis_handle* h, const void* grad_flow, void* gra
         return dis_fail(h, DIS_EINVAL, "the adjoint covers two-dimensional flow, not the stereo form");
     if (h->p.flags & DIS_FLAG_FB_CONSISTENCY)
         return dis_fail(h, DIS_EINVAL, "the adjoint covers the one-directional densification, not the merged one");
+    if (h->p.flags & DIS_FLAG_COLOUR) return dis_fail(h, DIS_EINVAL, "the adjoint covers grey frames");
     if (h->p.norm != DIS_NORM_L2)
         return dis_fail(h, DIS_EINVAL, "the adjoint covers the L2 inverse search (norm %d requested)", h->p.norm);
     if (!h->have_last || h->last_call != 1)

@@ -176,8 +176,8 @@ extern "C" int dis_compute_flow_batched(dis_handle* h, int n, const void* const*
     if (n < 1 || !I0 || !I1 || !w || !hgt || !pitch || !flow)
         return dis_fail(h, DIS_EINVAL, "batch of %d pairs: NULL array or n < 1", n);
     if (n > h->max_batch) return dis_fail(h, DIS_ESIZE, "batch of %d pairs exceeds max_batch %d", n, h->max_batch);
-    if (h->p.flags & DIS_FLAG_FB_CONSISTENCY)
-        return dis_fail(h, DIS_EINVAL, "forward-backward consistency runs through dis_compute_flow only");
+    if (h->p.flags & (DIS_FLAG_FB_CONSISTENCY | DIS_FLAG_COLOUR))
+        return dis_fail(h, DIS_EINVAL, "forward-backward consistency and colour frames run through dis_compute_flow only");
     for (int k = 0; k < n; ++k) {
         if (!I0[k] || !I1[k] || !flow[k]) return dis_fail(h, DIS_EINVAL, "pair %d: NULL frame or flow pointer", k);
         if (w[k] < 1 || hgt[k] < 1) return dis_fail(h, DIS_EINVAL, "pair %d: size %dx%d invalid", k, w[k], hgt[k]);

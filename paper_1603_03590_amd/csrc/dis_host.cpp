@@ -102,8 +102,14 @@ static int validate_params(const dis_params* p) {
     if (!(p->huber_b > 0.0)) return fail(nullptr, DIS_EINVAL, "huber_b %g must be > 0", p->huber_b);
     const uint32_t known = DIS_FLAG_KEEP_FOR_BACKWARD | DIS_FLAG_NO_GRAPH | DIS_FLAG_PIXEL_CENTRE |
                            DIS_FLAG_RAW_RESIDUAL | DIS_FLAG_IO_F64 | DIS_FLAG_STEREO |
-                           DIS_FLAG_FB_CONSISTENCY;
+                           DIS_FLAG_FB_CONSISTENCY | DIS_FLAG_COLOUR;
     if (p->flags & ~known) return fail(nullptr, DIS_EINVAL, "unknown flag bits 0x%x", p->flags & ~known);
+    if (p->flags & DIS_FLAG_COLOUR) {
+        if (p->flags & DIS_FLAG_FB_CONSISTENCY)
+            return fail(nullptr, DIS_EINVAL, "colour frames and forward-backward consistency do not combine");
+        if (!dis_kernel_phase_search_colour(p->patch_size))
+            return fail(nullptr, DIS_EINVAL, "colour frames support patch sizes 4..12, not %d", p->patch_size);
+    }
     return DIS_OK;
 }
 
@@ -170,6 +176,7 @@ int dis_dalloc(dis_handle* h, void** ptr, size_t bytes) {
 static int alloc_slot(dis_handle* h, SlotBuf& sb) {
     const dis_params& p = h->p;
     const int W = h->max_w, H = h->max_h, ps = p.patch_size, st = h->st;
+    const int nc = dis_channels(&p);
     std::memset(&sb, 0, sizeof sb);
     for (int s = 0; s <= h->top; ++s) {
         LevelBuf& L = sb.lv[s];
@@ -178,14 +185,15 @@ static int alloc_slot(dis_handle* h, SlotBuf& sb) {
         // level images: the processed levels, and every fifth level (a later
         // pyramid pass starts from it)
         if (s >= p.finest_scale || (s > 0 && s % 5 == 0)) {
-            DALLOC(h, L.J0, px * sizeof(double));
-            DALLOC(h, L.J1, px * sizeof(double));
+            DALLOC(h, L.J0, nc * px * sizeof(double));
+            DALLOC(h, L.J1, nc * px * sizeof(double));
         }
         if (s >= p.finest_scale && ws >= ps && hs >= ps) {
             const int nx = (ws - ps) / st + 2, ny = (hs - ps) / st + 2;
             L.maxN = nx * ny;
             DALLOC(h, L.patch, (size_t)L.maxN * 4 * sizeof(double));
             DALLOC(h, L.uinit, (size_t)L.maxN * 2 * sizeof(double));
+            if (nc > 1) DALLOC(h, L.mdc, (size_t)L.maxN * nc * sizeof(double));
             DALLOC(h, L.U, 2 * px * sizeof(double));
             if (p.refine) DALLOC(h, L.Ud, 2 * px * sizeof(double));
             else L.Ud = L.U;
@@ -194,8 +202,8 @@ static int alloc_slot(dis_handle* h, SlotBuf& sb) {
     const int sf = p.finest_scale;
     const size_t pf = (size_t)(W >> sf) * (H >> sf);
     if (p.refine) {
-        DALLOC(h, sb.J1w, pf * sizeof(double));
-        DALLOC(h, sb.lin, 11 * pf * sizeof(double));
+        DALLOC(h, sb.J1w, nc * pf * sizeof(double));
+        DALLOC(h, sb.lin, 11 * nc * pf * sizeof(double));
         for (int i = 0; i < 3; ++i) DALLOC(h, sb.dU[i], 2 * pf * sizeof(double));
     }
     return DIS_OK;
@@ -408,10 +416,13 @@ int dis_add_pyramid(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, int s
     const dis_params& p = h->p;
     const int sf = p.finest_scale;
     const bool f64io = (p.flags & DIS_FLAG_IO_F64) != 0;
+    const int nc = dis_channels(&p);
     for (int a = 0; a < ss || (a == 0 && ss == 0); a += 5) {
         PyrArgs pa;
         std::memset(&pa, 0, sizeof pa);
         const int w0 = w >> a, h0 = hgt >> a;
+        pa.nc = nc;
+        pa.src_cstride = a == 0 ? (long long)hgt * pitch : (long long)w0 * h0;
         pa.a = a;
         pa.nlev = std::min(5, ss - a);
         pa.w0 = w0;
@@ -447,7 +458,8 @@ int dis_add_pyramid(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, int s
             fl += 2.0 * 4.0 * px;
             if (pa.dst[0][k]) by += 16.0 * px;
         }
-        seq.add(dis_kernel_pyramid(), dim3(tiles, 2), dim3(256), &pa, sizeof pa, a == 0 ? 1 : 0, "pyramid", by, fl);
+        seq.add(dis_kernel_pyramid(), dim3(tiles, 2 * nc), dim3(256), &pa, sizeof pa, a == 0 ? 1 : 0, "pyramid",
+                nc * by, nc * fl);
         if (ss == 0) break;
     }
     return DIS_OK;
@@ -513,7 +525,9 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     int top = sf;
     for (const PairRef& r : pairs) top = std::max(top, r.ss);
     const bool fbm = (p.flags & DIS_FLAG_FB_CONSISTENCY) && !opt && pairs.size() == 2;
-    const int mode = ((opt && opt->force_phase) || fbm) ? 1 : h->mode_phase;
+    const int nc = dis_channels(&p);
+    // colour frames and the merged densification run phase-major only
+    const int mode = ((opt && opt->force_phase) || fbm || nc > 1) ? 1 : h->mode_phase;
     const int tile_id = mode ? h->refine_tile : DIS_LEVEL_TILE;
     int tw = 32, th = 16, nt = 256;
     dis_refine_tile(tile_id, &tw, &th, &nt);
@@ -543,7 +557,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             LevelGrid g;
             totN += dis_level_grid(h, r.w >> s, r.h >> s, &g);
         }
-        LH.lpp = dis_pick_lpp(h, s, (int)std::min<long long>(totN, 1 << 30));
+        LH.lpp = nc > 1 ? 16 : dis_pick_lpp(h, s, (int)std::min<long long>(totN, 1 << 30));
         LH.by[0] = LH.by[1] = LH.fl[0] = LH.fl[1] = 0.0;
         for (const PairRef& r : pairs) {
             if (r.ss < s) continue;
@@ -567,6 +581,8 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             sa.centre_map = cmap;
             sa.patch = L.patch;
             sa.uinit = L.uinit;
+            sa.nc = nc;
+            sa.mdc = L.mdc;
             DensifyArgs& da = P.da;
             da.J0 = L.J0; da.J1 = L.J1; da.W = W; da.H = Hh;
             da.patch = L.patch;
@@ -575,10 +591,13 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             da.U = L.Ud;
             da.J1w = p.refine ? sb.J1w : nullptr;
             da.Z = opt ? opt->Z : nullptr;
+            da.nc = nc;
+            da.mdc = L.mdc;
             RefineArgs& ra = P.ra;
             ra.U = L.Ud; ra.J0 = L.J0; ra.J1w = sb.J1w; ra.Uout = L.U;
             ra.lin = sb.lin;
             ra.stereo = (p.flags & DIS_FLAG_STEREO) ? 1 : 0;
+            ra.nc = nc;
             ra.tape = opt ? opt->tape : nullptr;
             ra.W = W; ra.H = Hh;
             ra.tiles_x = (W + tw - 1) / tw;
@@ -586,7 +605,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             ra.omega = p.sor_omega; ra.eps = 1e-3;
             for (int q = 0; q < 3; ++q) P.dU[q] = sb.dU[q];
             P.dens_bx = (W + 63) / 64;
-            const bool small = p.refine && h->small_levels && !fbm && ((W + 1) / 2) * Hh <= DIS_SMALL_PAIRS;
+            const bool small = p.refine && h->small_levels && !fbm && nc == 1 && ((W + 1) / 2) * Hh <= DIS_SMALL_PAIRS;
             if (small) LH.small.push_back((int)LH.lp.size());
             LH.is_small.push_back(small ? 1 : 0);
             LH.lp.push_back(P);
@@ -693,7 +712,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             const int grid = std::max(1, std::min(t, h->n_cu * 2));
             seq.add(fn, dim3(grid), dim3(256), &LL, sizeof LL, 0, "level", by, fl);
         } else {
-            const void* fs = dis_kernel_phase_search(ps, LH.lpp);
+            const void* fs = nc > 1 ? dis_kernel_phase_search_colour(ps) : dis_kernel_phase_search(ps, LH.lpp);
             if (!fs) return fail(h, DIS_EINVAL, "no search kernel for patch %d, %d lanes", ps, LH.lpp);
             for (int ph = 0; ph < LH.nph; ++ph) {
                 const int n = start[(ph + 1) * np] - start[ph * np];
@@ -727,14 +746,22 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
                     seq.add(dis_kernel_fb_densify(), dim3((P0.da.W + 63) / 64, (P0.da.H + 3) / 4, 2), dim3(256), &F,
                             sizeof F, 0, "densify", 2.0 * ph_by[1], 2.0 * ph_fl[1]);
                 } else if (ph == 1) {
-                    seq.add(dis_kernel_phase_densify(), dim3(n), dim3(256), &LL, sizeof LL, 0, "densify", ph_by[1],
-                            ph_fl[1]);
+                    seq.add(nc > 1 ? dis_kernel_phase_densify_colour() : dis_kernel_phase_densify(), dim3(n), dim3(256),
+                            &LL, sizeof LL, 0, "densify", ph_by[1], ph_fl[1]);
+                    if (nc > 1 && p.refine && LH.nph > 2) {
+                        // per-channel linearisation of the refinement (one pair per plan)
+                        const LevelPair& P0 = LH.lp[0];
+                        const double px = (double)P0.ra.W * P0.ra.H;
+                        seq.add(dis_kernel_colour_lin(), dim3(P0.dens_bx, (P0.ra.H + 3) / 4), dim3(256), &LL,
+                                sizeof LL, 0, "colour_lin", nc * 96.0 * px, nc * 60.0 * px);
+                    }
                 } else {
                     PhaseLaunch PL;
                     std::memset(&PL, 0, sizeof PL);
                     PL.L = LL;
                     PL.phase = ph;
-                    seq.add(dis_kernel_phase_refine(tile_id), dim3(n), dim3(nt), &PL, sizeof PL, 0, "refine",
+                    seq.add(nc > 1 ? dis_kernel_phase_refine_colour(tile_id) : dis_kernel_phase_refine(tile_id), dim3(n),
+                            dim3(nt), &PL, sizeof PL, 0, "refine",
                             ph_by[ph], ph_fl[ph]);
                 }
             }

@@ -13,20 +13,21 @@
 
 // Device buffers of one pyramid level of one pair slot (float64, dense).
 struct LevelBuf {
-    double* J0;      // level image of frame 0 (0..255 scale)
+    double* J0;      // level image of frame 0 (0..255 scale; [nc][H][W] for colour frames)
     double* J1;      // level image of frame 1
     double* Ud;      // densified flow [2][H][W] (aliases U without refinement)
     double* U;       // flow after refinement [2][H][W]
     double* patch;   // [maxN][4]: u, v, mean residual, distance moved
     double* uinit;   // [maxN][2]
+    double* mdc;     // [maxN][3] per-channel mean residuals (colour frames only)
     int maxN;
 };
 
 // Everything one frame pair needs; a handle owns max_batch of them.
 struct SlotBuf {
     LevelBuf lv[DIS_MAXL];
-    double* J1w;     // warped frame 1 of the level being refined
-    double* lin;     // [11][H][W] linearisation of the level being refined
+    double* J1w;     // warped frame 1 of the level being refined ([nc][H][W])
+    double* lin;     // [nc][11][H][W] linearisation of the level being refined
     double* dU[3];   // refinement increments (frozen / in / out rotation)
 };
 
@@ -154,6 +155,8 @@ struct dis_handle {
 };
 
 int dis_stride(const dis_params* p);
+// image channels of a parameter block: 3 with DIS_FLAG_COLOUR, else 1
+inline int dis_channels(const dis_params* p) { return (p->flags & DIS_FLAG_COLOUR) ? 3 : 1; }
 int dis_coarsest(const dis_params* p, int w, int h);
 void dis_grid(int n, int ps, int st, int* nr, int* ntot);
 int dis_pick_lpp(const dis_handle* h, int s, int N);

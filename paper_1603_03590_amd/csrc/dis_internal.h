@@ -16,6 +16,8 @@ struct PyrArgs {
     int src_kind;           // 0 = float64 plane, 1 = float32 frame, 2 = float64 frame
     int src_pitch;          // elements
     double scale;           // 255 for frames, 1 for planes
+    long long src_cstride;  // elements between the colour channels of src
+    int nc;                 // channels (grid y = 2 nc: frame = y & 1, channel = y >> 1)
     int a, nlev;
     int w0, h0;             // size of level a
     int tiles_x;
@@ -41,8 +43,10 @@ struct SearchArgs {
     double huber_b;
     int stereo;             // 1: horizontal displacement only (App. I)
     int centre_map;
-    double* patch;          // [N][4]: u, v, mean residual at u, distance moved
+    double* patch;          // [N][4]: u, v, mean residual at u (channel 0), distance moved
     double* uinit;          // [N][2]
+    int nc;                 // colour channels (App. B i); J0, J1 hold nc planes of W x H
+    double* mdc;            // [N][nc] mean residual of every channel (nc > 1)
 };
 
 // Densification (Eq. 3) and the warped second frame for the refinement.
@@ -54,8 +58,10 @@ struct DensifyArgs {
     int ps, st, nrx, nry, nx, ny;
     int raw_residual;
     double* U;              // [2][H][W]
-    double* J1w;            // [H][W], or null without refinement
+    double* J1w;            // [nc][H][W], or null without refinement
     double* Z;              // [H][W] sum of the weights, or null (kept for the backward pass)
+    int nc;                 // colour channels: J0, J1 hold nc planes
+    const double* mdc;      // [N][nc] per-channel mean residuals (nc > 1)
 };
 
 // Part of one fixed-point iteration of the refinement: linearisation from
@@ -76,8 +82,12 @@ struct RefineArgs {
     // three normalisers: [11][H][W]); it depends on J0 and J1w only, so the
     // level's first launch writes it (lin_mode 1, core pixels) and later
     // launches read it for their pixels instead of recomputing (lin_mode 2)
+    // With colour frames (lin_mode 3) the lin planes hold these 11 terms of
+    // every channel ([nc][11][H][W]), written by k_colour_lin, and the tile
+    // sums the data terms over the channels.
     double* lin;
-    int lin_mode;           // 0 compute, 1 compute and store, 2 load
+    int lin_mode;           // 0 compute, 1 compute and store, 2 load, 3 colour (load every channel)
+    int nc;
     int stereo;             // 1: relax du only, dv stays zero (App. I)
     int W, H;
     int nhalf;
@@ -198,11 +208,15 @@ const void* dis_kernel_upsample_tab();
 const void* dis_kernel_phase_search(int ps, int lpp);   // null when not compiled
 const void* dis_kernel_phase_densify();
 const void* dis_kernel_phase_refine(int tile);          // tile id, see dis_refine_tile
+const void* dis_kernel_phase_refine_colour(int tile);   // colour frames (lin_mode 3)
+const void* dis_kernel_phase_densify_colour();
 const void* dis_kernel_small_level();                  // SmallLaunch, DIS_SMALL_THREADS threads
 const void* dis_kernel_fb_count();                     // FbLaunch, grid (patch blocks, 2)
 const void* dis_kernel_fb_scan();                      // FbLaunch, grid (1, 2), 1024 threads
 const void* dis_kernel_fb_scatter();                   // FbLaunch, grid (patch blocks, 2)
 const void* dis_kernel_fb_densify();                   // FbLaunch, grid (W/64, H/4, 2)
+const void* dis_kernel_colour_lin();                   // LevelLaunch of one pair, grid of the densification
+const void* dis_kernel_phase_search_colour(int ps);    // 3 channels, 16 lanes per patch; null when not compiled
 const void* dis_kernel_level(int ps, int lpp);          // persistent level kernel, null when not compiled
 // refinement core tile (width, height, threads per block) of a tile id;
 // returns 0 for an unknown id

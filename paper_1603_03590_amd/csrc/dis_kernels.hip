@@ -49,8 +49,9 @@ __device__ __forceinline__ double dpp_mov(double v) {
 
 // ------------------------------------------------------------------ pyramid
 
-// One 32x32 tile of level a of frame f: the tile's part of levels a+1..a+nlev.
-__device__ __forceinline__ void pyramid_tile(const PyrArgs& a, int tile, int f) {
+// One 32x32 tile of level a of frame f, channel c: the tile's part of levels
+// a+1..a+nlev.
+__device__ __forceinline__ void pyramid_tile(const PyrArgs& a, int tile, int f, int c) {
     __shared__ double t0[32][33];
     __shared__ double t1[16][17];
     const int bx = tile % a.tiles_x, by = tile / a.tiles_x;
@@ -60,12 +61,12 @@ __device__ __forceinline__ void pyramid_tile(const PyrArgs& a, int tile, int f) 
         const int x = X0 + lx, y = Y0 + ly;
         double v = 0.0;
         if (x < a.w0 && y < a.h0) {
-            const size_t g = (size_t)y * a.src_pitch + x;
+            const size_t g = (size_t)c * a.src_cstride + (size_t)y * a.src_pitch + x;
             if (a.src_kind == 1)
                 v = a.scale * (double)((const float*)a.src[f])[g];
             else
                 v = a.scale * ((const double*)a.src[f])[g];
-            if (a.lvl0[f]) a.lvl0[f][(size_t)y * a.w0 + x] = v;
+            if (a.lvl0[f]) a.lvl0[f][((size_t)c * a.h0 + y) * a.w0 + x] = v;
         }
         t0[ly][lx] = v;
     }
@@ -88,7 +89,7 @@ __device__ __forceinline__ void pyramid_tile(const PyrArgs& a, int tile, int f) 
                             t1[2 * ly + 1][2 * lx + 1]);
             const int xs = (X0 >> k) + lx, ys = (Y0 >> k) + ly;
             double* d = a.dst[f][k];
-            if (d && xs < a.ws[k] && ys < a.hs[k]) d[(size_t)ys * a.ws[k] + xs] = v;
+            if (d && xs < a.ws[k] && ys < a.hs[k]) d[((size_t)c * a.hs[k] + ys) * a.ws[k] + xs] = v;
         }
         __syncthreads();   // every read of the source buffer precedes the overwrite
         if (act) {
@@ -101,7 +102,7 @@ __device__ __forceinline__ void pyramid_tile(const PyrArgs& a, int tile, int f) 
 __global__ __launch_bounds__(256) void k_pyramid(const PyrArgs a) {
     if (blockIdx.x == 0 && blockIdx.y == 0)
         for (int i = threadIdx.x; i < a.nzero; i += 256) a.zero[i] = 0;
-    pyramid_tile(a, blockIdx.x, blockIdx.y);
+    pyramid_tile(a, blockIdx.x, blockIdx.y & 1, blockIdx.y >> 1);
 }
 
 // Index of the segment of a sorted start[] table that holds task t
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(256) void k_pyramid_tab(const PyrTab T) {
         for (int i = threadIdx.x; i < T.nzero; i += 256) T.zero[i] = 0;
     const int t = blockIdx.x;
     const int j = seg_find(T.start, 0, T.n, t);
-    pyramid_tile(T.tab[j], t - __builtin_amdgcn_readfirstlane(T.start[j]), blockIdx.y);
+    pyramid_tile(T.tab[j], t - __builtin_amdgcn_readfirstlane(T.start[j]), blockIdx.y, 0);
 }
 
 // ------------------------------------------------------------------ search
@@ -176,14 +177,14 @@ __device__ __forceinline__ double csum_prod(const double (&a)[GS * GPL], const d
 constexpr int isqrt_floor(int v, int r = 0) { return (r + 1) * (r + 1) > v ? r : isqrt_floor(v, r + 1); }
 
 // LDS copy of the second frame around each patch's initial position: a
-// square of PS + 1 + 2R pixels (indices clamped to the image as the
-// bilinear taps clamp them), R as large as 48 KB per block allows (at most
-// 6).  While the patch's integer displacement stays within R of its start
-// the warps read LDS; beyond, global memory.  Same values either way.
-template <int PS, int LPP>
+// square of PS + 1 + 2R pixels per channel (indices clamped to the image as
+// the bilinear taps clamp them), R as large as 48 KB per block allows (at
+// most 6).  While the patch's integer displacement stays within R of its
+// start the warps read LDS; beyond, global memory.  Same values either way.
+template <int PS, int LPP, int NC = 1>
 struct SearchWin {
     static constexpr int GROUPS = 256 / LPP;
-    static constexpr int FIT = (isqrt_floor(48 * 1024 / 8 / GROUPS) - PS - 1) / 2;
+    static constexpr int FIT = (isqrt_floor(48 * 1024 / 8 / GROUPS / NC) - PS - 1) / 2;
     static constexpr int R = LPP < 8 ? 0 : (FIT < 0 ? 0 : (FIT > 6 ? 6 : FIT));
     static constexpr int WS = PS + 1 + 2 * R;
 };
@@ -192,14 +193,18 @@ struct SearchWin {
 // corners, initialisation (Sec. 2.2 steps 1-2), template and Sobel/8
 // gradients, the precomputed 2x2 Hessian, theta_it inverse-compositional
 // updates u <- u - H^-1 sum grad(T) r (Suppl. A), the reset test of step 4,
-// and the mean residual at the final u, which densification needs.
-template <int PS, int LPP>
+// and the mean residual at the final u, which densification needs.  With NC
+// colour channels (App. B i) the Hessian and the right-hand side are sums of
+// the per-channel ones (channel 0 first), each channel mean-normalised on
+// its own.
+template <int PS, int LPP, int NC = 1>
 __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
     constexpr int NP = PS * PS;
     constexpr int GS = (NP + 15) / 16;
     constexpr int GPL = 16 / LPP;
     constexpr int PPL = GS * GPL;
     const int W = a.W, H = a.H;
+    const size_t n = (size_t)W * H;
     const int lane = threadIdx.x & (LPP - 1);
     const int N = a.nx * a.ny;
     int pi = (int)((block * 256u + threadIdx.x) / LPP);
@@ -220,35 +225,46 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
         vi = 2.0 * bilin(a.Un + (size_t)a.Wn * a.Hn, a.Wn, a.Hn, qx, qy);
     }
 
-    const double* __restrict__ J0 = a.J0;
-    const double* __restrict__ J1 = a.J1;
-    double T[PPL], gx[PPL], gy[PPL];
+    double T[NC][PPL], gx[NC][PPL], gy[NC][PPL];
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) {
-        const int p = lane * PPL + k;
-        if (p < NP) {
-            const int py = p / PS, px = p - py * PS;
-            const int x = x0 + px, y = y0 + py;
-            const int xm = x > 0 ? x - 1 : 0, xp = x < W - 1 ? x + 1 : W - 1;
-            const int ym = y > 0 ? y - 1 : 0, yp = y < H - 1 ? y + 1 : H - 1;
-            T[k] = J0[y * W + x];
-            const double dm = J0[ym * W + xp] - J0[ym * W + xm];
-            const double d0 = J0[y * W + xp] - J0[y * W + xm];
-            const double dp = J0[yp * W + xp] - J0[yp * W + xm];
-            gx[k] = ((dm + 2.0 * d0) + dp) / 8.0;
-            const double em = J0[yp * W + xm] - J0[ym * W + xm];
-            const double e0 = J0[yp * W + x] - J0[ym * W + x];
-            const double ep = J0[yp * W + xp] - J0[ym * W + xp];
-            gy[k] = ((em + 2.0 * e0) + ep) / 8.0;
-        } else {
-            T[k] = 0.0; gx[k] = 0.0; gy[k] = 0.0;
+    for (int ch = 0; ch < NC; ++ch) {
+        const double* __restrict__ J0 = a.J0 + ch * n;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            const int p = lane * PPL + k;
+            if (p < NP) {
+                const int py = p / PS, px = p - py * PS;
+                const int x = x0 + px, y = y0 + py;
+                const int xm = x > 0 ? x - 1 : 0, xp = x < W - 1 ? x + 1 : W - 1;
+                const int ym = y > 0 ? y - 1 : 0, yp = y < H - 1 ? y + 1 : H - 1;
+                T[ch][k] = J0[y * W + x];
+                const double dm = J0[ym * W + xp] - J0[ym * W + xm];
+                const double d0 = J0[y * W + xp] - J0[y * W + xm];
+                const double dp = J0[yp * W + xp] - J0[yp * W + xm];
+                gx[ch][k] = ((dm + 2.0 * d0) + dp) / 8.0;
+                const double em = J0[yp * W + xm] - J0[ym * W + xm];
+                const double e0 = J0[yp * W + x] - J0[ym * W + x];
+                const double ep = J0[yp * W + xp] - J0[ym * W + xp];
+                gy[ch][k] = ((em + 2.0 * e0) + ep) / 8.0;
+            } else {
+                T[ch][k] = 0.0; gx[ch][k] = 0.0; gy[ch][k] = 0.0;
+            }
         }
     }
-    const double h11 = csum_prod<GS, GPL, LPP>(gx, gx);
-    const double h12 = csum_prod<GS, GPL, LPP>(gx, gy);
-    const double h22 = csum_prod<GS, GPL, LPP>(gy, gy);
-    const double sgx = csum<GS, GPL, LPP>(gx);
-    const double sgy = csum<GS, GPL, LPP>(gy);
+    double h11 = csum_prod<GS, GPL, LPP>(gx[0], gx[0]);
+    double h12 = csum_prod<GS, GPL, LPP>(gx[0], gy[0]);
+    double h22 = csum_prod<GS, GPL, LPP>(gy[0], gy[0]);
+    double sgx[NC], sgy[NC];
+    sgx[0] = csum<GS, GPL, LPP>(gx[0]);
+    sgy[0] = csum<GS, GPL, LPP>(gy[0]);
+#pragma unroll
+    for (int ch = 1; ch < NC; ++ch) {
+        h11 = h11 + csum_prod<GS, GPL, LPP>(gx[ch], gx[ch]);
+        h12 = h12 + csum_prod<GS, GPL, LPP>(gx[ch], gy[ch]);
+        h22 = h22 + csum_prod<GS, GPL, LPP>(gy[ch], gy[ch]);
+        sgx[ch] = csum<GS, GPL, LPP>(gx[ch]);
+        sgy[ch] = csum<GS, GPL, LPP>(gy[ch]);
+    }
     const double a11 = h11 + a.lam, a22 = h22 + a.lam, a12 = h12;
     const double idet = 1.0 / (a11 * a22 - a12 * a12);
     // H^-1 b = (m11 b1 + m12 b2, m12 b1 + m22 b2)
@@ -256,22 +272,24 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
     const double inv_n = 1.0 / (double)NP;
     const double lim = (double)(W + H + 2 * PS + 4);
 
-    // the window of this patch (see SearchWin)
-    using SW = SearchWin<PS, LPP>;
+    // the window of this patch (see SearchWin), one per channel
+    using SW = SearchWin<PS, LPP, NC>;
     constexpr int R = SW::R, WS = SW::WS;
-    __shared__ double s_win[R > 0 ? SW::GROUPS * WS * WS : 1];
+    __shared__ double s_win[R > 0 ? NC * SW::GROUPS * WS * WS : 1];
     const int iu0 = (int)fmin(fmax(floor(ui), -lim), lim), iv0 = (int)fmin(fmax(floor(vi), -lim), lim);
-    double* win = s_win + (size_t)(threadIdx.x / LPP) * WS * WS;
+    double* win = s_win + (size_t)(threadIdx.x / LPP) * NC * WS * WS;
     if constexpr (R > 0) {
         const int wx = x0 + iu0 - R, wy = y0 + iv0 - R;
-        for (int i = lane; i < WS * WS; i += LPP) {
-            const int Y = i / WS, X = i - Y * WS;
-            win[i] = J1[clampi(wy + Y, 0, H - 1) * W + clampi(wx + X, 0, W - 1)];
-        }
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch)
+            for (int i = lane; i < WS * WS; i += LPP) {
+                const int Y = i / WS, X = i - Y * WS;
+                win[ch * WS * WS + i] = a.J1[ch * n + clampi(wy + Y, 0, H - 1) * W + clampi(wx + X, 0, W - 1)];
+            }
         __builtin_amdgcn_wave_barrier();
     }
 
-    double u = ui, v = vi, md = 0.0, moved = 0.0;
+    double u = ui, v = vi, md0 = 0.0, moved = 0.0;
     for (int it = 0; it <= a.iters; ++it) {
         if (it == a.iters) {
             // reset test (Sec. 2.2 step 4), then one more warp at the final u
@@ -283,64 +301,77 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
         const double ax = u - fu, ay = v - fv;
         const int iu = (int)fmin(fmax(fu, -lim), lim);
         const int iv = (int)fmin(fmax(fv, -lim), lim);
-        double d[PPL];
         const bool in_win = R > 0 && iu - iu0 >= -R && iu - iu0 <= R && iv - iv0 >= -R && iv - iv0 <= R;
-        if (in_win) {
+        double b1 = 0.0, b2 = 0.0;
 #pragma unroll
-            for (int k = 0; k < PPL; ++k) {
-                const int p = lane * PPL + k;
-                if (p < NP) {
-                    const int py = p / PS, px = p - py * PS;
-                    const double* c = win + (py + iv - iv0 + R) * WS + (px + iu - iu0 + R);
-                    const double top = (1.0 - ax) * c[0] + ax * c[1];
-                    const double bot = (1.0 - ax) * c[WS] + ax * c[WS + 1];
-                    d[k] = ((1.0 - ay) * top + ay * bot) - T[k];
-                } else {
-                    d[k] = 0.0;
+        for (int ch = 0; ch < NC; ++ch) {
+            double d[PPL];
+            if (in_win) {
+                const double* wc = win + ch * WS * WS;
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) {
+                    const int p = lane * PPL + k;
+                    if (p < NP) {
+                        const int py = p / PS, px = p - py * PS;
+                        const double* c = wc + (py + iv - iv0 + R) * WS + (px + iu - iu0 + R);
+                        const double top = (1.0 - ax) * c[0] + ax * c[1];
+                        const double bot = (1.0 - ax) * c[WS] + ax * c[WS + 1];
+                        d[k] = ((1.0 - ay) * top + ay * bot) - T[ch][k];
+                    } else {
+                        d[k] = 0.0;
+                    }
+                }
+            } else {
+                const double* __restrict__ J1 = a.J1 + ch * n;
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) {
+                    const int p = lane * PPL + k;
+                    if (p < NP) {
+                        const int py = p / PS, px = p - py * PS;
+                        const int xa = x0 + px + iu, ya = y0 + py + iv;
+                        const int c0 = clampi(xa, 0, W - 1), c1 = clampi(xa + 1, 0, W - 1);
+                        const int r0 = clampi(ya, 0, H - 1) * W, r1 = clampi(ya + 1, 0, H - 1) * W;
+                        const double top = (1.0 - ax) * J1[r0 + c0] + ax * J1[r0 + c1];
+                        const double bot = (1.0 - ax) * J1[r1 + c0] + ax * J1[r1 + c1];
+                        d[k] = ((1.0 - ay) * top + ay * bot) - T[ch][k];
+                    } else {
+                        d[k] = 0.0;
+                    }
                 }
             }
-        } else {
-#pragma unroll
-            for (int k = 0; k < PPL; ++k) {
-                const int p = lane * PPL + k;
-                if (p < NP) {
-                    const int py = p / PS, px = p - py * PS;
-                    const int xa = x0 + px + iu, ya = y0 + py + iv;
-                    const int c0 = clampi(xa, 0, W - 1), c1 = clampi(xa + 1, 0, W - 1);
-                    const int r0 = clampi(ya, 0, H - 1) * W, r1 = clampi(ya + 1, 0, H - 1) * W;
-                    const double top = (1.0 - ax) * J1[r0 + c0] + ax * J1[r0 + c1];
-                    const double bot = (1.0 - ax) * J1[r1 + c0] + ax * J1[r1 + c1];
-                    d[k] = ((1.0 - ay) * top + ay * bot) - T[k];
-                } else {
-                    d[k] = 0.0;
-                }
+            const double sd = csum<GS, GPL, LPP>(d);
+            const double md = sd * inv_n;
+            if (it == a.iters) {
+                if (ch == 0) md0 = md;
+                if (NC > 1 && valid && lane == 0) a.mdc[(size_t)pi * NC + ch] = md;
+                continue;
             }
+            double c1, c2;
+            if (a.norm == 0) {
+                // b = sum grad(T) (d - mean d): the mean-normalised residual (Sec. 2.1)
+                c1 = csum_prod<GS, GPL, LPP>(gx[ch], d) - md * sgx[ch];
+                c2 = csum_prod<GS, GPL, LPP>(gy[ch], d) - md * sgy[ch];
+            } else {
+                // App. B iii: each mean-normalised residual e is transformed so
+                // that its square is the L1 or the Huber penalty of e
+                double r[PPL];
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) {
+                    const int p = lane * PPL + k;
+                    const double e = d[k] - md;
+                    const double ae = fabs(e);
+                    double t;
+                    if (a.norm == 1) t = sqrt(ae);
+                    else t = ae < a.huber_b ? ae : sqrt(2.0 * a.huber_b * ae - a.huber_b * a.huber_b);
+                    r[k] = p < NP ? copysign(t, e) : 0.0;
+                }
+                c1 = csum_prod<GS, GPL, LPP>(gx[ch], r);
+                c2 = csum_prod<GS, GPL, LPP>(gy[ch], r);
+            }
+            if (ch == 0) { b1 = c1; b2 = c2; }
+            else { b1 = b1 + c1; b2 = b2 + c2; }
         }
-        const double sd = csum<GS, GPL, LPP>(d);
-        md = sd * inv_n;
         if (it == a.iters) break;
-        double b1, b2;
-        if (a.norm == 0) {
-            // b = sum grad(T) (d - mean d): the mean-normalised residual (Sec. 2.1)
-            b1 = csum_prod<GS, GPL, LPP>(gx, d) - md * sgx;
-            b2 = csum_prod<GS, GPL, LPP>(gy, d) - md * sgy;
-        } else {
-            // App. B iii: each mean-normalised residual e is transformed so
-            // that its square is the L1 or the Huber penalty of e
-            double r[PPL];
-#pragma unroll
-            for (int k = 0; k < PPL; ++k) {
-                const int p = lane * PPL + k;
-                const double e = d[k] - md;
-                const double ae = fabs(e);
-                double t;
-                if (a.norm == 1) t = sqrt(ae);
-                else t = ae < a.huber_b ? ae : sqrt(2.0 * a.huber_b * ae - a.huber_b * a.huber_b);
-                r[k] = p < NP ? copysign(t, e) : 0.0;
-            }
-            b1 = csum_prod<GS, GPL, LPP>(gx, r);
-            b2 = csum_prod<GS, GPL, LPP>(gy, r);
-        }
         if (a.stereo) {
             u = u - b1 / a11;   // App. I: one degree of freedom, v stays at its start (zero)
         } else {
@@ -350,7 +381,7 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
     }
     if (valid && lane == 0) {
         double* P = a.patch + (size_t)pi * 4;
-        P[0] = u; P[1] = v; P[2] = md; P[3] = moved;
+        P[0] = u; P[1] = v; P[2] = md0; P[3] = moved;
         a.uinit[(size_t)pi * 2] = ui;
         a.uinit[(size_t)pi * 2 + 1] = vi;
     }
@@ -367,14 +398,16 @@ __device__ __forceinline__ void cover_range(int x, int n, int ps, int st, int nr
     flush = (ntot > nr) && (x >= n - ps);
 }
 
-// Eq. (3) on a 64x4 block: per pixel, gather the covering patches in
-// ascending patch index, weight each displacement by 1 / max(1, |d_i(x)|)
-// with d_i the mean-normalised residual at that patch's displacement; then
-// the second frame warped by the dense flow, for the refinement.
-// Eq. (3) at pixel (x, y): the displacement average U, V and the weight sum.
+// Eq. (3) at pixel (x, y): the covering patches in ascending patch index,
+// each displacement weighted by 1 / max(1, |d_i(x)|) with d_i the
+// mean-normalised residual at that patch's displacement (with colour
+// frames, App. B i: the Euclidean norm over the channels of the per-channel
+// residuals).  Returns the displacement average U, V and the weight sum.
+template <bool COLOUR = false>
 __device__ __forceinline__ void densify_pixel(const DensifyArgs& a, int x, int y, double& U, double& V,
                                               double& sw) {
     const int W = a.W, H = a.H;
+    const size_t n = (size_t)W * H;
     int kx0, kx1, ky0, ky1;
     bool fx, fy;
     cover_range(x, W, a.ps, a.st, a.nrx, a.nx, kx0, kx1, fx);
@@ -387,11 +420,24 @@ __device__ __forceinline__ void densify_pixel(const DensifyArgs& a, int x, int y
         const int ky = jy <= ky1 ? jy : a.nry;
         for (int jx = kx0; jx <= kxend; ++jx) {
             const int kx = jx <= kx1 ? jx : a.nrx;
-            const double* P = a.patch + (size_t)(ky * a.nx + kx) * 4;
+            const int i = ky * a.nx + kx;
+            const double* P = a.patch + (size_t)i * 4;
             const double u = P[0], v = P[1];
             const double q = bilin(a.J1, W, H, (double)x + u, (double)y + v);
-            const double d = a.raw_residual ? (q - j0) : ((q - j0) - P[2]);
-            const double wgt = 1.0 / fmax(1.0, fabs(d));
+            double ad;
+            if constexpr (!COLOUR) {
+                ad = fabs(a.raw_residual ? (q - j0) : ((q - j0) - P[2]));
+            } else {
+                double ss = 0.0;
+                for (int ch = 0; ch < a.nc; ++ch) {
+                    const double qc = ch ? bilin(a.J1 + ch * n, W, H, (double)x + u, (double)y + v) : q;
+                    const double jc = a.J0[ch * n + (size_t)y * W + x];
+                    const double dc = a.raw_residual ? (qc - jc) : ((qc - jc) - a.mdc[(size_t)i * a.nc + ch]);
+                    ss = ch ? ss + dc * dc : dc * dc;
+                }
+                ad = sqrt(ss);
+            }
+            const double wgt = 1.0 / fmax(1.0, ad);
             su = su + wgt * u;
             sv = sv + wgt * v;
             sw = sw + wgt;
@@ -401,22 +447,66 @@ __device__ __forceinline__ void densify_pixel(const DensifyArgs& a, int x, int y
     V = sv / sw;
 }
 
-// Eq. (3) on a 64x4 block: per pixel, gather the covering patches in
-// ascending patch index, weight each displacement by 1 / max(1, |d_i(x)|)
-// with d_i the mean-normalised residual at that patch's displacement; then
-// the second frame warped by the dense flow, for the refinement.
+// Eq. (3) on a 64x4 block, then the second frame (every channel) warped by
+// the dense flow, for the refinement.
+template <bool COLOUR = false>
 __device__ __forceinline__ void densify_block(const DensifyArgs& a, int bx, int by) {
     const int x = bx * 64 + (threadIdx.x & 63);
     const int y = by * 4 + (threadIdx.x >> 6);
     const int W = a.W, H = a.H;
     if (x >= W || y >= H) return;
     double U, V, sw;
-    densify_pixel(a, x, y, U, V, sw);
+    densify_pixel<COLOUR>(a, x, y, U, V, sw);
     const int g = y * W + x;
     if (a.Z) a.Z[g] = sw;
     a.U[g] = U;
     a.U[W * H + g] = V;
-    if (a.J1w) a.J1w[g] = bilin(a.J1, W, H, (double)x + U, (double)y + V);
+    if (a.J1w) {
+        if constexpr (!COLOUR) {
+            a.J1w[g] = bilin(a.J1, W, H, (double)x + U, (double)y + V);
+        } else {
+            for (int ch = 0; ch < a.nc; ++ch)
+                a.J1w[(size_t)ch * W * H + g] = bilin(a.J1 + (size_t)ch * W * H, W, H, (double)x + U, (double)y + V);
+        }
+    }
+}
+
+// Linearisation of the refinement (Sec. 2.3) for colour frames: per pixel
+// and channel the central differences of (J0 + J1w)/2 and of J1w - J0 with
+// replicated borders, and the three normalisers, as [nc][11][H][W].  The
+// refinement tile then sums the data terms over the channels.
+__global__ __launch_bounds__(256) void k_colour_lin(const LevelLaunch L) {
+    const RefineArgs& a = L.pairs[0].ra;
+    const int W = a.W, H = a.H;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= W || y >= H) return;
+    const size_t n = (size_t)W * H;
+    const int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
+    const int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
+    for (int ch = 0; ch < a.nc; ++ch) {
+        const double* t0 = a.J0 + ch * n;
+        const double* t1 = a.J1w + ch * n;
+        auto Ib = [&](int xx, int yy) { const size_t l = (size_t)yy * W + xx; return 0.5 * (t0[l] + t1[l]); };
+        auto Ixa = [&](int xx, int yy) { return (Ib(min(xx + 1, W - 1), yy) - Ib(max(xx - 1, 0), yy)) / 2.0; };
+        auto Iya = [&](int xx, int yy) { return (Ib(xx, min(yy + 1, H - 1)) - Ib(xx, max(yy - 1, 0))) / 2.0; };
+        const size_t gi = (size_t)y * W + x;
+        const double Ix = Ixa(x, y), Iy = Iya(x, y);
+        const double Iz = t1[gi] - t0[gi];
+        const double Ixx = (Ixa(xp, y) - Ixa(xm, y)) / 2.0;
+        const double Ixy = (Ixa(x, yp) - Ixa(x, ym)) / 2.0;
+        const double Iyy = (Iya(x, yp) - Iya(x, ym)) / 2.0;
+        const size_t lxp = (size_t)y * W + xp, lxm = (size_t)y * W + xm;
+        const size_t lyp = (size_t)yp * W + x, lym = (size_t)ym * W + x;
+        const double Ixz = (t1[lxp] - t1[lxm]) / 2.0 - (t0[lxp] - t0[lxm]) / 2.0;
+        const double Iyz = (t1[lyp] - t1[lym]) / 2.0 - (t0[lyp] - t0[lym]) / 2.0;
+        double* Lo = a.lin + (size_t)ch * 11 * n + gi;
+        Lo[0] = Ix; Lo[n] = Iy; Lo[2 * n] = Iz; Lo[3 * n] = Ixx; Lo[4 * n] = Ixy; Lo[5 * n] = Iyy;
+        Lo[6 * n] = Ixz; Lo[7 * n] = Iyz;
+        Lo[8 * n] = 1.0 / ((Ix * Ix + Iy * Iy) + 0.01);
+        Lo[9 * n] = 1.0 / ((Ixx * Ixx + Ixy * Ixy) + 0.01);
+        Lo[10 * n] = 1.0 / ((Ixy * Ixy + Iyy * Iyy) + 0.01);
+    }
 }
 
 // ------------------------------------------- forward-backward densification
@@ -602,7 +692,7 @@ using dis_tile::RefineSmem;
 // owns pairs of horizontally adjacent pixels (one of each colour) and keeps
 // their SOR coefficients in registers; LDS holds the increments, the edge
 // weights and U.  Every global read is issued in one round at the start.
-template <int TW, int TH, int NT>
+template <int TW, int TH, int NT, bool COLOUR = false>
 __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, RefineSmem<TW, TH>& sm) {
     using S = RefineSmem<TW, TH>;
     using Shape = dis_tile::TileShape<TW, TH, NT>;
@@ -621,7 +711,7 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
 
     dis_tile::TileCoef<PPT> C;
     double s_iu[Shape::NS][2], s_iv[Shape::NS][2];
-    dis_tile::refine_setup<TW, TH, NT>(a, g, sm, C, s_iu, s_iv);
+    dis_tile::refine_setup<TW, TH, NT, DIS_KMAX, COLOUR>(a, g, sm, C, s_iu, s_iv);
     __syncthreads();   // the image tile is dead from here on
     // 4. sweep start
     double* du_ = sm.u.inc.du;
@@ -709,23 +799,24 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
 // Phase-major launches over the same per-level tables as the persistent
 // kernel: one launch per phase covers every pair (its segments are
 // consecutive in the queue order), no waiting inside the launch.
-template <int PS, int LPP>
+template <int PS, int LPP, int NC = 1>
 __global__ __launch_bounds__(256) void k_phase_search(const LevelLaunch L) {
     const int t = blockIdx.x;                       // phase 0 starts at task 0
     const int j = seg_find(L.start, 0, L.npairs, t);
-    search_block<PS, LPP>(L.pairs[j].sa, t - __builtin_amdgcn_readfirstlane(L.start[j]));
+    search_block<PS, LPP, NC>(L.pairs[j].sa, t - __builtin_amdgcn_readfirstlane(L.start[j]));
 }
 
+template <bool COLOUR = false>
 __global__ __launch_bounds__(256) void k_phase_densify(const LevelLaunch L) {
     const int np = L.npairs;
     const int t = __builtin_amdgcn_readfirstlane(L.start[np]) + blockIdx.x;
     const int j = seg_find(L.start, np, 2 * np, t) - np;
     const LevelPair& P = L.pairs[j];
     const int local = t - __builtin_amdgcn_readfirstlane(L.start[np + j]);
-    densify_block(P.da, local % P.dens_bx, local / P.dens_bx);
+    densify_block<COLOUR>(P.da, local % P.dens_bx, local / P.dens_bx);
 }
 
-template <int TW, int TH, int NT>
+template <int TW, int TH, int NT, bool COLOUR = false>
 __global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
     __shared__ RefineSmem<TW, TH> sm;
     const LevelLaunch& L = PL.L;
@@ -742,8 +833,10 @@ __global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
     ra.Uout = rp.last ? P.ra.Uout : nullptr;
     ra.nhalf = rp.nhalf;
     ra.tape_m0 = rp.m0;
-    ra.lin_mode = rp.m0 == 0 ? 1 : 2;   // the level's first launch fills the linearisation cache
-    refine_tile<TW, TH, NT>(ra, t - __builtin_amdgcn_readfirstlane(L.start[s0 + j]), sm);
+    // the level's first launch fills the linearisation cache; colour frames
+    // read the per-channel linearisation of k_colour_lin
+    ra.lin_mode = COLOUR ? 3 : (rp.m0 == 0 ? 1 : 2);
+    refine_tile<TW, TH, NT, COLOUR>(ra, t - __builtin_amdgcn_readfirstlane(L.start[s0 + j]), sm);
 }
 
 // ----------------------------------------------------------------- upscale
@@ -1099,12 +1192,27 @@ const void* dis_kernel_pyramid() { return (const void*)&k_pyramid; }
 const void* dis_kernel_pyramid_tab() { return (const void*)&k_pyramid_tab; }
 const void* dis_kernel_upsample() { return (const void*)&k_upsample; }
 const void* dis_kernel_upsample_tab() { return (const void*)&k_upsample_tab; }
-const void* dis_kernel_phase_densify() { return (const void*)&k_phase_densify; }
+const void* dis_kernel_phase_densify() { return (const void*)&k_phase_densify<false>; }
+const void* dis_kernel_phase_densify_colour() { return (const void*)&k_phase_densify<true>; }
 const void* dis_kernel_small_level() { return (const void*)&k_small_level<DIS_SMALL_THREADS>; }
 const void* dis_kernel_fb_count() { return (const void*)&k_fb_count; }
 const void* dis_kernel_fb_scan() { return (const void*)&k_fb_scan; }
 const void* dis_kernel_fb_scatter() { return (const void*)&k_fb_scatter; }
 const void* dis_kernel_fb_densify() { return (const void*)&k_fb_densify; }
+const void* dis_kernel_colour_lin() { return (const void*)&k_colour_lin; }
+
+// colour search instances: 16 lanes per patch keep the three channels'
+// per-lane pixel arrays within the register file
+const void* dis_kernel_phase_search_colour(int ps) {
+    switch (ps) {
+        case 4: return (const void*)&k_phase_search<4, 16, 3>;
+        case 6: return (const void*)&k_phase_search<6, 16, 3>;
+        case 8: return (const void*)&k_phase_search<8, 16, 3>;
+        case 10: return (const void*)&k_phase_search<10, 16, 3>;
+        case 12: return (const void*)&k_phase_search<12, 16, 3>;
+        default: return nullptr;
+    }
+}
 
 // instances whose per-lane pixel arrays fit the 256 architectural VGPRs
 #define DIS_FOR_SEARCH_INSTANCES(X) \
@@ -1142,6 +1250,14 @@ int dis_refine_tile(int tile, int* tw, int* th, int* nt) {
 const void* dis_kernel_phase_refine(int tile) {
 #define DIS_TILE_KERNEL(ID, TW_, TH_, NT_) \
     if (tile == ID) return (const void*)&k_phase_refine<TW_, TH_, NT_>;
+    DIS_FOR_REFINE_TILES(DIS_TILE_KERNEL)
+#undef DIS_TILE_KERNEL
+    return nullptr;
+}
+
+const void* dis_kernel_phase_refine_colour(int tile) {
+#define DIS_TILE_KERNEL(ID, TW_, TH_, NT_) \
+    if (tile == ID) return (const void*)&k_phase_refine<TW_, TH_, NT_, true>;
     DIS_FOR_REFINE_TILES(DIS_TILE_KERNEL)
 #undef DIS_TILE_KERNEL
     return nullptr;

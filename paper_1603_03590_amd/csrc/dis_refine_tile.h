@@ -86,7 +86,7 @@ struct TileShape {
 // increments of the owned pixels go to registers), the smoothness weights,
 // and the coefficients.  Ends with the image tile still live; the caller
 // places a barrier before reusing it.
-template <int TW, int TH, int NT, int KG = DIS_KMAX>
+template <int TW, int TH, int NT, int KG = DIS_KMAX, bool COLOUR = false>
 __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom& g, RefineSmem<TW, TH, KG>& sm,
                                              TileCoef<TileShape<TW, TH, NT, KG>::PPT>& C,
                                              double (&s_iu)[TileShape<TW, TH, NT, KG>::NS][2],
@@ -106,6 +106,7 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
     constexpr bool kLin = TileShape<TW, TH, NT, KG>::kLin;
     constexpr int NL = TileShape<TW, TH, NT, KG>::NL;
     const bool lin_load = kLin && a.lin_mode == 2;
+    constexpr bool colour = COLOUR;   // lin_mode 3: per-channel linearisation
     double s_fu[kStage ? PPT : 1][2], s_fv[kStage ? PPT : 1][2];
     double s_lin[NL][2][11];
 #pragma unroll
@@ -151,7 +152,7 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
             }
         }
         const int ix1 = min(rx0 + RW + 2, W), iy1 = min(ry0 + RH + 2, H);
-        const int IW = ix1 - ix0, IH = lin_load ? 0 : iy1 - iy0;
+        const int IW = ix1 - ix0, IH = (lin_load || colour) ? 0 : iy1 - iy0;
 #pragma unroll 2
         for (int i = threadIdx.x; i < IW * IH; i += NT) {
             const int ly = i / IW, lx = i - ly * IW;
@@ -224,6 +225,38 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
                 const int ly = l / LP, lx = l - ly * LP;
                 const int x = rx0 + lx, y = ry0 + ly;
                 const size_t gi = (size_t)y * W + x;
+                double fu, fv;
+                if constexpr (kStage) { fu = s_fu[k][c]; fv = s_fv[k][c]; }
+                else { fu = F ? F[gi] : 0.0; fv = F ? F[n + gi] : 0.0; }
+                double A11, A12, A22, B1, B2;
+                if constexpr (colour) {
+                    // App. B i: both data energies are channel sums inside one
+                    // robust function each; the system sums the channels'
+                    // terms at those weights (channel 0 first)
+                    double ei = 0.0, eg = 0.0;
+                    for (int ch = 0; ch < a.nc; ++ch) {
+                        const double* Lc = a.lin + (size_t)ch * 11 * n + gi;
+                        const double cri = (Lc[0] * fu + Lc[n] * fv) + Lc[2 * n];
+                        const double crx = (Lc[3 * n] * fu + Lc[4 * n] * fv) + Lc[6 * n];
+                        const double cry = (Lc[4 * n] * fu + Lc[5 * n] * fv) + Lc[7 * n];
+                        ei = ei + Lc[8 * n] * (cri * cri);
+                        eg = eg + (Lc[9 * n] * (crx * crx) + Lc[10 * n] * (cry * cry));
+                    }
+                    const double pi_ = a.delta / (2.0 * sqrt(ei + eps2));
+                    const double pg = a.gamma / (2.0 * sqrt(eg + eps2));
+                    A11 = A12 = A22 = B1 = B2 = 0.0;
+                    for (int ch = 0; ch < a.nc; ++ch) {
+                        const double* Lc = a.lin + (size_t)ch * 11 * n + gi;
+                        const double cIx = Lc[0], cIy = Lc[n], cIz = Lc[2 * n], cIxx = Lc[3 * n], cIxy = Lc[4 * n];
+                        const double cIyy = Lc[5 * n], cIxz = Lc[6 * n], cIyz = Lc[7 * n];
+                        const double cb0 = Lc[8 * n], cbx = Lc[9 * n], cby = Lc[10 * n];
+                        A11 = (A11 + ((pi_ * cb0) * cIx) * cIx) + pg * (((cbx * cIxx) * cIxx) + ((cby * cIxy) * cIxy));
+                        A12 = (A12 + ((pi_ * cb0) * cIx) * cIy) + pg * (((cbx * cIxx) * cIxy) + ((cby * cIxy) * cIyy));
+                        A22 = (A22 + ((pi_ * cb0) * cIy) * cIy) + pg * (((cbx * cIxy) * cIxy) + ((cby * cIyy) * cIyy));
+                        B1 = (B1 + ((pi_ * cb0) * cIx) * cIz) + pg * (((cbx * cIxx) * cIxz) + ((cby * cIxy) * cIyz));
+                        B2 = (B2 + ((pi_ * cb0) * cIy) * cIz) + pg * (((cbx * cIxy) * cIxz) + ((cby * cIyy) * cIyz));
+                    }
+                } else {
                 double Ix = 0.0, Iy = 0.0, Iz = 0.0, Ixx = 0.0, Ixy = 0.0, Iyy = 0.0, Ixz = 0.0, Iyz = 0.0;
                 double b0 = 0.0, bx = 0.0, by = 0.0;
                 bool cached = false;
@@ -259,9 +292,6 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
                         Lo[10 * n] = by;
                     }
                 }
-                double fu, fv;
-                if constexpr (kStage) { fu = s_fu[k][c]; fv = s_fv[k][c]; }
-                else { fu = F ? F[gi] : 0.0; fv = F ? F[n + gi] : 0.0; }
                 const double ri = (Ix * fu + Iy * fv) + Iz;
                 const double ei = b0 * (ri * ri);
                 const double rx = (Ixx * fu + Ixy * fv) + Ixz;
@@ -269,11 +299,12 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
                 const double eg = bx * (rx * rx) + by * (ry * ry);
                 const double pi_ = a.delta / (2.0 * sqrt(ei + eps2));
                 const double pg = a.gamma / (2.0 * sqrt(eg + eps2));
-                const double A11 = ((pi_ * b0) * Ix) * Ix + pg * (((bx * Ixx) * Ixx) + ((by * Ixy) * Ixy));
-                const double A12 = ((pi_ * b0) * Ix) * Iy + pg * (((bx * Ixx) * Ixy) + ((by * Ixy) * Iyy));
-                const double A22 = ((pi_ * b0) * Iy) * Iy + pg * (((bx * Ixy) * Ixy) + ((by * Iyy) * Iyy));
-                const double B1 = ((pi_ * b0) * Ix) * Iz + pg * (((bx * Ixx) * Ixz) + ((by * Ixy) * Iyz));
-                const double B2 = ((pi_ * b0) * Iy) * Iz + pg * (((bx * Ixy) * Ixz) + ((by * Iyy) * Iyz));
+                A11 = ((pi_ * b0) * Ix) * Ix + pg * (((bx * Ixx) * Ixx) + ((by * Ixy) * Ixy));
+                A12 = ((pi_ * b0) * Ix) * Iy + pg * (((bx * Ixx) * Ixy) + ((by * Ixy) * Iyy));
+                A22 = ((pi_ * b0) * Iy) * Iy + pg * (((bx * Ixy) * Ixy) + ((by * Iyy) * Iyy));
+                B1 = ((pi_ * b0) * Ix) * Iz + pg * (((bx * Ixx) * Ixz) + ((by * Ixy) * Iyz));
+                B2 = ((pi_ * b0) * Iy) * Iz + pg * (((bx * Ixy) * Ixz) + ((by * Iyy) * Iyz));
+                }
                 // edges: right/down owned by this pixel, left/up by the
                 // neighbour; neighbours outside the region (not the image) are
                 // dropped, which only disturbs pixels the erosion discards

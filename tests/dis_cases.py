@@ -41,6 +41,10 @@ def pair(kind: str, w: int, h: int, disp: float, seed: int):
         return synth.smooth_bump_pair(w, h, disp, seed)
     if kind == "hbump":   # rectified stereo: horizontal displacements only
         return synth.smooth_bump_pair(w, h, disp, seed, horizontal=True)
+    if kind == "cbump":   # colour frames [3][H][W]
+        return synth.smooth_bump_pair(w, h, disp, seed, channels=3)
+    if kind == "chbump":  # colour stereo
+        return synth.smooth_bump_pair(w, h, disp, seed, horizontal=True, channels=3)
     return synth.layered_pair(w, h, disp, seed)
 
 
@@ -51,7 +55,8 @@ def oracle_flow(key, I0, I1, op: O.OracleParams, records=False):
     ck = (key, repr(op), records)
     if ck not in _oracle_cache:
         recs = [] if records else None
-        U = O.dis_flow(torch.from_numpy(I0), torch.from_numpy(I1), op, recs)
+        run = O.dis_flow_colour if I0.ndim == 3 else O.dis_flow
+        U = run(torch.from_numpy(I0), torch.from_numpy(I1), op, recs)
         _oracle_cache[ck] = (U.numpy(), recs)
     return _oracle_cache[ck]
 

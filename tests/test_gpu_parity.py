@@ -22,7 +22,7 @@ def say(*a):
 
 
 def gpu_flow(I0, I1, p, max_wh=None, keep=False):
-    h, w = I0.shape
+    h, w = I0.shape[-2:]
     mw, mh = max_wh or (w, h)
     d = DIS(p, mw, mh)
     dt = d.dtype
@@ -61,6 +61,14 @@ CASES = [
     ("l1_bump_256x192", ("bump", 256, 192, 8.0, 1), 101, dict(norm=1)),
     ("huber_layered_512x256", ("layered", 512, 256, 40.0, 16), 103, dict(norm=2, huber_b=1.0,
                                                                          coarsest_scale=4, finest_scale=1)),
+    # colour frames (App. B i)
+    ("colour_bump_256x192", ("cbump", 256, 192, 8.0, 31), 101, dict(flags=0x80)),
+    ("colour_bump_512x256_c5", ("cbump", 512, 256, 16.0, 32), 105, dict(flags=0x80)),
+    ("colour_ps12_raw_norefine_300x200", ("cbump", 300, 200, 10.0, 33), 105,
+     dict(flags=0x80 | 0x8, patch_size=12, refine=0, finest_scale=0, coarsest_scale=3)),
+    ("colour_ps4_l1_inner7_203x149", ("cbump", 203, 149, 6.0, 34), 103,
+     dict(flags=0x80, patch_size=4, norm=1, var_inner=7, coarsest_scale=3, finest_scale=0)),
+    ("colour_stereo_256x192", ("chbump", 256, 192, 8.0, 35), 101, dict(flags=0x80 | 0x20, gn_iters=4)),
 ]
 
 
@@ -162,7 +170,7 @@ def test_size_errors():
         d.close()
 
 
-@pytest.mark.parametrize("case", ["c2b", "c1", "inner7", "l1", "stereo", "fb"])
+@pytest.mark.parametrize("case", ["c2b", "c1", "inner7", "l1", "stereo", "fb", "colour"])
 def test_launch_choices_are_bitwise_invariant(case):
     """Persistent vs per-phase launches, lanes per patch and refinement tiles
     change the schedule, never a bit of the flow."""
@@ -177,9 +185,11 @@ def test_launch_choices_are_bitwise_invariant(case):
         pr, p = pair("hbump", 256, 192, 8.0, 17), params(101, flags=0x20)
     elif case == "fb":
         pr, p = pair("bump", 256, 192, 8.0, 1), params(101, flags=0x40)
+    elif case == "colour":
+        pr, p = pair("cbump", 288, 216, 10.0, 36), params(105, flags=0x80, var_inner=7)
     else:   # 7 SOR sweeps: each fixed-point step spans two launches
         pr, p = pair("bump", 288, 216, 10.0, 13), params(105, var_inner=7)
-    h, w = pr.I0.shape
+    h, w = pr.I0.shape[-2:]
     d = DIS(p, w, h)
     try:
         t0 = torch.from_numpy(pr.I0).cuda()
@@ -260,6 +270,43 @@ def test_fb_differs_from_plain_and_refusals():
         t0 = torch.from_numpy(pr.I0).cuda()
         t1 = torch.from_numpy(pr.I1).cuda()
         out = d.flow(t0, t1)
+        with pytest.raises(DisError) as e:
+            d.backward(torch.ones_like(out))
+        assert e.value.code == _lib.DIS_EINVAL
+    finally:
+        d.close()
+
+
+def test_colour_refusals_and_padded_rows():
+    """Colour frames: padded rows (channel stride = height x pitch) give the
+    same flow as packed ones; batched and backward calls refuse them."""
+    say("[colour] 256x192 padded rows, refusals")
+    pr = pair("cbump", 256, 192, 8.0, 31)
+    p = params(101, flags=_lib.DIS_FLAG_COLOUR)
+    ref = gpu_flow(pr.I0, pr.I1, p)
+    d = DIS(p, 256, 192)
+    try:
+        b0 = torch.zeros(3, 192, 300, device="cuda")
+        b1 = torch.zeros(3, 192, 300, device="cuda")
+        b0[:, :, :256] = torch.from_numpy(pr.I0).cuda()
+        b1[:, :, :256] = torch.from_numpy(pr.I1).cuda()
+        out = d.flow(b0[:, :, :256], b1[:, :, :256])
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
+        with pytest.raises(DisError) as e:
+            d.flow_batched([b0[:, :, :256]], [b1[:, :, :256]])
+        assert e.value.code == _lib.DIS_EINVAL
+    finally:
+        d.close()
+    with pytest.raises(DisError) as e:
+        DIS(params(101, flags=_lib.DIS_FLAG_COLOUR | _lib.DIS_FLAG_FB_CONSISTENCY), 256, 192)
+    assert e.value.code == _lib.DIS_EINVAL
+    with pytest.raises(DisError) as e:
+        DIS(params(101, flags=_lib.DIS_FLAG_COLOUR, patch_size=14), 256, 192)
+    assert e.value.code == _lib.DIS_EINVAL
+    d = DIS(params(101, flags=_lib.DIS_FLAG_COLOUR | _lib.DIS_FLAG_KEEP_FOR_BACKWARD), 256, 192)
+    try:
+        out = d.flow(torch.from_numpy(pr.I0).cuda(), torch.from_numpy(pr.I1).cuda())
         with pytest.raises(DisError) as e:
             d.backward(torch.ones_like(out))
         assert e.value.code == _lib.DIS_EINVAL
