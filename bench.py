@@ -53,6 +53,22 @@ def time_calls(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def roofline_of(stats):
+    """Roofline entry of the kernel family with the largest summed event time:
+    algorithmic bytes (flops for the search) per launch over its average
+    launch duration, against the HBM (fp64 vector) peak."""
+    top = sorted(stats, key=lambda k: -k["total_ms"])[0]
+    avg_ms = top["total_ms"] / top["launches"]
+    if top["name"] == "search":
+        achieved = top["flops"] / top["launches"] / (avg_ms * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=achieved / FP64_VECTOR_PEAK_TFLOPS)
+    else:
+        achieved = top["bytes"] / top["launches"] / (avg_ms * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS)
+    return roof, top, avg_ms
+
+
 def kernel_table(stats, steps):
     out = {}
     for k in sorted(stats, key=lambda k: -k["total_ms"]):
@@ -146,16 +162,7 @@ def main():
 
     head = results[args.op]
     mpix = W * H / (head["ms"] * 1e-3) / 1e6
-    ks = sorted(head["kernels"], key=lambda k: -k["total_ms"])
-    top = ks[0]
-    avg_ms = top["total_ms"] / top["launches"]
-    if top["name"] == "search":
-        achieved = top["flops"] / top["launches"] / (avg_ms * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / FP64_VECTOR_PEAK_TFLOPS)
-    else:
-        achieved = top["bytes"] / top["launches"] / (avg_ms * 1e-3) / 1e9
-        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS)
+    roof, top, avg_ms = roofline_of(head["kernels"])
     # HBM traffic per launch of that kernel family, from the committed
     # counter summary when it was taken on these kernel sources with this
     # refinement tile (else null)
@@ -164,7 +171,8 @@ def main():
     from paper_1603_03590_amd import profsum
     rec = profsum.read_traffic(os.path.join(ROOT, "profiles", f"{top['name']}_c2a_1024x436_hbm_traffic.md"))
     if rec and rec.get("source_sha") == profsum.source_hash() and (
-            top["name"] != "refine" or int(rec.get("tile", -1)) == head["tuned"]["refine_tile"]):
+            top["name"] != "refine" or (int(rec.get("tile", -1)) == head["tuned"]["refine_tile"]
+                                        and int(rec.get("mode", -1)) == head["tuned"]["launch_mode"])):
         traffic = float(rec["bytes_per_launch"])
         traffic_src = f"profiles/{top['name']}_c2a_1024x436_hbm_traffic.md"
     roof.update(traffic=traffic, traffic_source=traffic_src, kernel=top["name"],
@@ -197,6 +205,18 @@ def main():
         d.autotune()
         bdt = time_calls(call, max(10, args.steps // 10), 3)
         torch.cuda.synchronize()
+        # per-kernel event timing of the tuned batch (launches one by one)
+        _lib.dis_profile_enable(d.handle, True)
+        call()
+        _lib.dis_profile_read(d.handle)
+        for _ in range(3):
+            call()
+        bstats = _lib.dis_profile_read(d.handle)
+        _lib.dis_profile_enable(d.handle, False)
+        broof, btop, bavg = roofline_of(bstats)
+        broof.update(kernel=btop["name"], avg_launch_us=bavg * 1e3,
+                     algorithmic_bytes_per_launch=btop["bytes"] / btop["launches"],
+                     algorithmic_flops_per_launch=btop["flops"] / btop["launches"])
         pix = sum(w * h for w, h in sizes)
         # per-pair check on a sample: bitwise equal to the plain path
         sample = sorted(range(args.batch), key=lambda k: -sizes[k][0] * sizes[k][1])[:3]
@@ -210,7 +230,8 @@ def main():
             dp.close()
         batched = dict(value=pix / bdt / 1e6, unit="Mpix/s", ms_per_batch=bdt * 1e3, pairs=args.batch,
                        output_mpix=pix / 1e6, untuned_ms={k: v for k, v in bmodes.items()},
-                       plain_bitwise_equal_sample=bit_equal,
+                       plain_bitwise_equal_sample=bit_equal, tunables=d.tunables(),
+                       kernels=kernel_table(bstats, 3), roofline=broof,
                        workload=f"{args.batch} layered pairs, sizes uniform over "
                                 f"{{320x240, 640x480, 1024x436, 1280x720, 1920x1080}} (rng 4000), seeds 1000+k; "
                                 f"patch 8, overlap 0.5, 16 GN iterations, scales auto..3, theta_vo = s+1")

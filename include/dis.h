@@ -202,7 +202,10 @@ int dis_autotune(dis_handle* h, const char* cache_path);
  * pixel pairs is densified and refined, every fixed-point step, by one
  * block instead of tiles; bit 2 set makes dis_flow_backward reverse the SOR
  * sweeps with one launch per half sweep (a plain reference form) instead of
- * one tiled launch per fixed-point step.  Every choice gives
+ * one tiled launch per fixed-point step; bit 3 set makes every forward
+ * refinement launch recompute the linearisation from the level images
+ * instead of the scale's first launch storing it for the later ones (less
+ * HBM traffic, more arithmetic per launch).  Every choice gives
  * bitwise-identical flow (gradients agree to rounding: they are summed with
  * atomics).  Synchronises the stream and drops cached launch
  * plans.  Errors: DIS_EINVAL.

@@ -312,6 +312,7 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
     for (int l : lpps)
         if (r == DIS_OK && dis_kernel_phase_search(h->p.patch_size, l)) r = measure(Cand{l, tile, 1});
     if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, 3});   // single-workgroup small scales
+    if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, bestc.mode | 8});   // no linearisation cache
     if (r == DIS_OK) r = measure(Cand{0, 0, 0});
     for (int l : lpps)
         if (r == DIS_OK && dis_kernel_level(h->p.patch_size, l)) r = measure(Cand{l, 0, 0});

@@ -318,7 +318,7 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     int tw, th;
     if (!dis_refine_tile(refine_tile, &tw, &th, nullptr))
         return fail(h, DIS_EINVAL, "unknown refinement tile %d", refine_tile);
-    if (launch_mode < 0 || launch_mode > 7) return fail(h, DIS_EINVAL, "launch mode %d outside 0..7", launch_mode);
+    if (launch_mode < 0 || launch_mode > 15) return fail(h, DIS_EINVAL, "launch mode %d outside 0..15", launch_mode);
     if (lanes_per_patch)
         for (int s = 0; s < DIS_MAXL; ++s) {
             const int l = lanes_per_patch[s];
@@ -331,6 +331,7 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     h->mode_phase = launch_mode & 1;
     h->small_levels = (launch_mode & 2) ? 1 : 0;
     h->bwd_reference = (launch_mode & 4) ? 1 : 0;
+    h->no_lin_cache = (launch_mode & 8) ? 1 : 0;
     return DIS_OK;
 }
 
@@ -339,7 +340,8 @@ extern "C" int dis_get_tunables(const dis_handle* h, int* lanes_per_patch, int* 
     if (lanes_per_patch)
         for (int s = 0; s < DIS_MAXL; ++s) lanes_per_patch[s] = h->lpp[s];
     if (refine_tile) *refine_tile = h->refine_tile;
-    if (launch_mode) *launch_mode = h->mode_phase | (h->small_levels ? 2 : 0) | (h->bwd_reference ? 4 : 0);
+    if (launch_mode)
+        *launch_mode = h->mode_phase | (h->small_levels ? 2 : 0) | (h->bwd_reference ? 4 : 0) | (h->no_lin_cache ? 8 : 0);
     return DIS_OK;
 }
 
@@ -704,6 +706,8 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         LL.npairs = np;
         LL.nph = LH.nph;
         LL.ntasks = t;
+        // the adjoint's reverse tiles read the cache the recomputation fills
+        LL.lin_cache = (opt || !h->no_lin_cache) ? 1 : 0;
         if (mode == 0) {
             const void* fn = dis_kernel_level(ps, LH.lpp);
             if (!fn) return fail(h, DIS_EINVAL, "no level kernel for patch %d, %d lanes", ps, LH.lpp);

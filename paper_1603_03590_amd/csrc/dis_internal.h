@@ -134,6 +134,7 @@ struct LevelLaunch {
     const int* start;       // [nph * npairs + 1] first task of each segment
     int* sync;              // [0] queue head, [1] wait-timeout flag, [2 + seg] finished tasks
     int npairs, nph, ntasks;
+    int lin_cache;          // 1: a level's first refinement launch stores the linearisation, later ones load it
 };
 
 // A phase-major refinement launch: phase `phase` of every pair of L.
@@ -198,6 +199,29 @@ struct UpsTab {
 __device__ __forceinline__ int dis_xcd_tile(int b, int n) {
     const int x = b & 7, j = b >> 3, per = n >> 3, rem = n & 7;
     return x * per + (x < rem ? x : rem) + j;
+}
+
+// Order of the tiles of one pair inside its run of blocks: vertical bands
+// bw tiles wide (bw ~ sqrt(n / 8), so that the n / 8 consecutive tiles one
+// XCD receives form a near-square block), row-major inside a band, the last
+// band narrower when bw does not divide tiles_x.  A bijection on [0, n) for
+// n = tiles_x * tiles_y.
+__device__ __forceinline__ int dis_band_tile(int q, int tiles_x, int n) {
+    const int ty = n / tiles_x;
+    int bw = 1;
+    while ((bw + 1) * (bw + 1) * 8 <= n && bw + 1 <= tiles_x) ++bw;
+    const int full = tiles_x / bw, span = bw * ty;
+    int row, col;
+    if (q < full * span) {
+        const int band = q / span, r = q - band * span;
+        row = r / bw;
+        col = band * bw + (r - row * bw);
+    } else {
+        const int rw = tiles_x - full * bw, r = q - full * span;
+        row = r / rw;
+        col = full * bw + (r - row * rw);
+    }
+    return row * tiles_x + col;
 }
 
 // Kernel entry points, looked up by the host.

@@ -835,8 +835,10 @@ __global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
     ra.tape_m0 = rp.m0;
     // the level's first launch fills the linearisation cache; colour frames
     // read the per-channel linearisation of k_colour_lin
-    ra.lin_mode = COLOUR ? 3 : (rp.m0 == 0 ? 1 : 2);
-    refine_tile<TW, TH, NT, COLOUR>(ra, t - __builtin_amdgcn_readfirstlane(L.start[s0 + j]), sm);
+    ra.lin_mode = COLOUR ? 3 : (L.lin_cache ? (rp.m0 == 0 ? 1 : 2) : 0);
+    const int t0 = __builtin_amdgcn_readfirstlane(L.start[s0 + j]);
+    const int nt = __builtin_amdgcn_readfirstlane(L.start[s0 + j + 1]) - t0;
+    refine_tile<TW, TH, NT, COLOUR>(ra, dis_band_tile(t - t0, ra.tiles_x, nt), sm);
 }
 
 // ----------------------------------------------------------------- upscale
@@ -1174,7 +1176,7 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
                 ra.Uout = rp.last ? P.ra.Uout : nullptr;
                 ra.nhalf = __builtin_amdgcn_readfirstlane(rp.nhalf);
                 ra.tape_m0 = rp.m0;
-                ra.lin_mode = rp.m0 == 0 ? 1 : 2;
+                ra.lin_mode = L.lin_cache ? (rp.m0 == 0 ? 1 : 2) : 0;
                 refine_tile<32, 16, 256>(ra, local, sm);
             }
         }

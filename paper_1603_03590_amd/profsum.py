@@ -4,14 +4,17 @@
 markdown table of per-kernel dispatch counts and durations from
 ``<dir>/run_kernel_trace.csv``.
 
+``python -m paper_1603_03590_amd.profsum util <dir>`` prints the mean per
+dispatch of every counter of a ``--pmc`` run, per kernel family.
+
 ``python -m paper_1603_03590_amd.profsum traffic <fetch_dir> <write_dir>
---kernel REGEX --copy-mib M --tile T`` prints the HBM traffic per launch of
+--kernel REGEX --copy-mib M --tile T --mode L`` prints the HBM traffic per launch of
 the kernels matching REGEX, from two ``--pmc FETCH_SIZE`` / ``--pmc
 WRITE_SIZE`` runs (``run_counter_collection.csv``, KiB per dispatch), each
 counter scaled by what it reads for the run's plain device copy of M MiB
 (the largest ``__amd_rocclr_copyBuffer`` dispatches), and a machine-readable
 ``traffic:`` line that bench.py matches against the kernel family, the
-refinement tile and the hash of the kernel sources.
+refinement tile, the launch mode and the hash of the kernel sources.
 
 Only dispatches after the last persistent-level or single-workgroup launch
 are used (``--after``): the autotuner's trials run first, then the timed
@@ -70,7 +73,7 @@ def _counters(d):
     return list(csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))))
 
 
-def traffic_record(fetch_dir: str, write_dir: str, kernel: str, copy_mib: int, tile: int,
+def traffic_record(fetch_dir: str, write_dir: str, kernel: str, copy_mib: int, tile: int, mode: int,
                    after: str = AFTER_DEFAULT) -> tuple[str, dict]:
     F, Wr = _counters(fetch_dir), _counters(write_dir)
     expect = copy_mib * 1024.0   # KiB read and written by one copy
@@ -86,11 +89,28 @@ def traffic_record(fetch_dir: str, write_dir: str, kernel: str, copy_mib: int, t
     n = min(len(f_sel), len(w_sel))
     fetch = sum(float(r["Counter_Value"]) for r in f_sel[:n]) / n * ff * 1024.0
     write = sum(float(r["Counter_Value"]) for r in w_sel[:n]) / n * fw * 1024.0
-    rec = dict(kernel=kernel, tile=tile, launches=n, fetch_bytes_per_launch=fetch,
+    rec = dict(kernel=kernel, tile=tile, mode=mode, launches=n, fetch_bytes_per_launch=fetch,
                write_bytes_per_launch=write, bytes_per_launch=fetch + write, fetch_scale=ff, write_scale=fw,
                source_sha=source_hash())
     line = "traffic: " + " ".join(f"{k}={v:.6g}" if isinstance(v, float) else f"{k}={v}" for k, v in rec.items())
     return line, rec
+
+
+def util_table(d: str, after: str = AFTER_DEFAULT) -> str:
+    """Mean per dispatch of every collected counter, per kernel family
+    (``--pmc`` run; derived metrics such as VALUBusy come computed)."""
+    rows = _after(_counters(d), after)
+    agg = {}
+    for r in rows:
+        k = family(r["Kernel_Name"])
+        agg.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    names = sorted({c for v in agg.values() for c in v})
+    out = ["| Kernel | dispatches | " + " | ".join(names) + " |", "|:--|--:|" + "--:|" * len(names)]
+    for k, v in sorted(agg.items(), key=lambda kv: -len(next(iter(kv[1].values())))):
+        n = max(len(x) for x in v.values())
+        cells = [f"{statistics.mean(v[c]):.4g}" if c in v else "" for c in names]
+        out.append(f"| `{k}` | {n} | " + " | ".join(cells) + " |")
+    return "\n".join(out)
 
 
 def read_traffic(path: str) -> dict | None:
@@ -101,7 +121,7 @@ def read_traffic(path: str) -> dict | None:
                 rec = {}
                 for kv in ln[len("traffic: "):].split():
                     k, v = kv.split("=", 1)
-                    if k in ("tile", "launches"):
+                    if k in ("tile", "mode", "launches"):
                         rec[k] = int(v)
                     elif k.endswith("_launch") or k.endswith("_scale"):
                         rec[k] = float(v)
@@ -125,12 +145,18 @@ def main(argv=None):
     c.add_argument("--kernel", required=True)
     c.add_argument("--copy-mib", type=int, required=True)
     c.add_argument("--tile", type=int, required=True)
+    c.add_argument("--mode", type=int, required=True, help="launch mode of the measured run")
     c.add_argument("--after", default=AFTER_DEFAULT)
+    u = sub.add_parser("util")
+    u.add_argument("dir")
+    u.add_argument("--after", default=AFTER_DEFAULT)
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         print(trace_table(a.dir, a.after))
+    elif a.cmd == "util":
+        print(util_table(a.dir, a.after))
     else:
-        line, rec = traffic_record(a.fetch_dir, a.write_dir, a.kernel, a.copy_mib, a.tile, a.after)
+        line, rec = traffic_record(a.fetch_dir, a.write_dir, a.kernel, a.copy_mib, a.tile, a.mode, a.after)
         print(f"| counter | scale (copy probe) | KiB-scaled bytes per launch |\n|:--|--:|--:|\n"
               f"| FETCH_SIZE | {rec['fetch_scale']:.4f} | {rec['fetch_bytes_per_launch']:.0f} |\n"
               f"| WRITE_SIZE | {rec['write_scale']:.4f} | {rec['write_bytes_per_launch']:.0f} |\n")

@@ -200,6 +200,8 @@ def test_launch_choices_are_bitwise_invariant(case):
         choices += [([[4, 8, 16][t % 3]] * 16, t, 1) for t in range(1, N_TILES)]
         # with the single-workgroup scales (launch mode bit 1)
         choices += [(None, 0, 3), (None, 3, 3), (None, 0, 2)]
+        # without the linearisation cache (launch mode bit 3)
+        choices += [(None, 7, 9), (None, 0, 8), (None, 2, 11)]
         for lpp, tile, mode in choices:
             d.set_tunables(lpp, tile, mode)
             o = d.flow(t0, t1)
