@@ -215,14 +215,29 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
     const int x0 = kx < a.nrx ? kx * a.st : W - PS;
     const int y0 = ky < a.nry ? ky * a.st : H - PS;
 
-    double ui = 0.0, vi = 0.0;
-    if (a.Un) {
+    // taps of the coarser flow at the patch centre, requested before the
+    // template so that both rounds of loads are in flight together (the
+    // value is bilin() of the coarser flow, combined below in the same order)
+    const bool has_un = a.Un != nullptr;
+    double u00, u01, u10, u11, v00, v01, v10, v11, bax, bay;
+    {
+        const double* Up = has_un ? a.Un : a.J0;
+        const int Wn = has_un ? a.Wn : W, Hn = has_un ? a.Hn : H;
         const double c = 0.5 * (PS - 1);
         double qx = (double)x0 + c, qy = (double)y0 + c;
         if (a.centre_map) { qx = (qx + 0.5) / 2.0 - 0.5; qy = (qy + 0.5) / 2.0 - 0.5; }
         else { qx = qx / 2.0; qy = qy / 2.0; }
-        ui = 2.0 * bilin(a.Un, a.Wn, a.Hn, qx, qy);
-        vi = 2.0 * bilin(a.Un + (size_t)a.Wn * a.Hn, a.Wn, a.Hn, qx, qy);
+        double xf = floor(qx), yf = floor(qy);
+        bax = qx - xf;
+        bay = qy - yf;
+        xf = fmin(fmax(xf, -2.0), (double)Wn + 1.0);
+        yf = fmin(fmax(yf, -2.0), (double)Hn + 1.0);
+        const int xi = (int)xf, yi = (int)yf;
+        const int c0 = clampi(xi, 0, Wn - 1), c1 = clampi(xi + 1, 0, Wn - 1);
+        const int r0 = clampi(yi, 0, Hn - 1) * Wn, r1 = clampi(yi + 1, 0, Hn - 1) * Wn;
+        const double* Vp = Up + (has_un ? (size_t)Wn * Hn : 0);
+        u00 = Up[r0 + c0]; u01 = Up[r0 + c1]; u10 = Up[r1 + c0]; u11 = Up[r1 + c1];
+        v00 = Vp[r0 + c0]; v01 = Vp[r0 + c1]; v10 = Vp[r1 + c0]; v11 = Vp[r1 + c1];
     }
 
     double T[NC][PPL], gx[NC][PPL], gy[NC][PPL];
@@ -265,6 +280,11 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
         sgx[ch] = csum<GS, GPL, LPP>(gx[ch]);
         sgy[ch] = csum<GS, GPL, LPP>(gy[ch]);
     }
+    double ui = 0.0, vi = 0.0;
+    if (has_un) {
+        ui = 2.0 * ((1.0 - bay) * ((1.0 - bax) * u00 + bax * u01) + bay * ((1.0 - bax) * u10 + bax * u11));
+        vi = 2.0 * ((1.0 - bay) * ((1.0 - bax) * v00 + bax * v01) + bay * ((1.0 - bax) * v10 + bax * v11));
+    }
     const double a11 = h11 + a.lam, a22 = h22 + a.lam, a12 = h12;
     const double idet = 1.0 / (a11 * a22 - a12 * a12);
     // H^-1 b = (m11 b1 + m12 b2, m12 b1 + m22 b2)
@@ -280,12 +300,24 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
     double* win = s_win + (size_t)(threadIdx.x / LPP) * NC * WS * WS;
     if constexpr (R > 0) {
         const int wx = x0 + iu0 - R, wy = y0 + iv0 - R;
+        // every load of a lane is issued before the first store, so the
+        // window costs one round of memory latency, not one per element
+        constexpr int NW = (WS * WS + LPP - 1) / LPP;
 #pragma unroll
-        for (int ch = 0; ch < NC; ++ch)
-            for (int i = lane; i < WS * WS; i += LPP) {
+        for (int ch = 0; ch < NC; ++ch) {
+            double wv[NW];
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                const int i = lane + k * LPP;
                 const int Y = i / WS, X = i - Y * WS;
-                win[ch * WS * WS + i] = a.J1[ch * n + clampi(wy + Y, 0, H - 1) * W + clampi(wx + X, 0, W - 1)];
+                wv[k] = i < WS * WS ? a.J1[ch * n + clampi(wy + Y, 0, H - 1) * W + clampi(wx + X, 0, W - 1)] : 0.0;
             }
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                const int i = lane + k * LPP;
+                if (i < WS * WS) win[ch * WS * WS + i] = wv[k];
+            }
+        }
         __builtin_amdgcn_wave_barrier();
     }
 
