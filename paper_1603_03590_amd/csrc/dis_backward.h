@@ -98,6 +98,7 @@ struct DensBwdArgs {
     double* gJ0;
     double* gJ1;
     double* gP;             // [N][4]: adjoints of u, v, mean residual
+    double* gq;             // [2][H][W] scratch: the flow adjoint pass 1 hands to pass 2
 };
 
 struct PyrBwdArgs {
@@ -135,6 +136,7 @@ const void* dis_kernel_bwd_sweep_a();
 const void* dis_kernel_bwd_sweep_b();
 const void* dis_kernel_bwd_lin();
 const void* dis_kernel_bwd_ws();
-const void* dis_kernel_bwd_densify();
+const void* dis_kernel_bwd_densify();         // pass 1, per pixel
+const void* dis_kernel_bwd_densify_patch();   // pass 2, 16 lanes per patch
 const void* dis_kernel_bwd_pyramid();
 const void* dis_kernel_bwd_search(int ps);

@@ -636,10 +636,18 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
 
 // ----------------------------------------------------------- densification
 
-// Reverse of the warped frame J1w(x) = J1(x + Ud(x)) and of Eq. (3): the
-// adjoint of the dense flow goes to every covering patch's displacement and,
-// through the weights 1/max(1,|d|), to the residuals d, hence to J0, J1 and
-// the patch's mean residual (per-patch sums by atomics).
+// Reverse of the warped frame J1w(x) = J1(x + Ud(x)) and of Eq. (3), in two
+// passes so that no per-patch sum needs atomics.  Pass 1, per pixel: the
+// dense flow's adjoint (plus the warped frame's, through the bilinear
+// derivative) is stored for pass 2, and the residual adjoints of the
+// covering patches go to J0 (a gather: plain add) and to J1's bilinear taps
+// (atomics, spread over the frame).
+__device__ __forceinline__ int bwd_cover(int x, int n, int ps, int st, int nr, int& k0) {
+    const int lo = x - ps + 1;
+    k0 = lo <= 0 ? 0 : (lo + st - 1) / st;
+    return min(x / st, nr - 1);
+}
+
 __global__ __launch_bounds__(256) void k_bwd_densify(const DensBwdArgs a) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -657,19 +665,14 @@ __global__ __launch_bounds__(256) void k_bwd_densify(const DensBwdArgs a) {
             scatter_taps(a.gJ1, t, gw);
         }
     }
+    a.gq[g] = gUx;
+    a.gq[n + g] = gVx;
     if (gUx == 0.0 && gVx == 0.0) return;
     const double Z = a.Z[g];
     const double j0 = a.J0[g];
     const int ps = a.ps, st = a.st;
-    int kx0, kx1, ky0, ky1;
-    {
-        const int lo = x - ps + 1;
-        kx0 = lo <= 0 ? 0 : (lo + st - 1) / st;
-        kx1 = min(x / st, a.nrx - 1);
-        const int loy = y - ps + 1;
-        ky0 = loy <= 0 ? 0 : (loy + st - 1) / st;
-        ky1 = min(y / st, a.nry - 1);
-    }
+    int kx0, ky0;
+    const int kx1 = bwd_cover(x, W, ps, st, a.nrx, kx0), ky1 = bwd_cover(y, H, ps, st, a.nry, ky0);
     const bool fx = (a.nx > a.nrx) && (x >= W - ps), fy = (a.ny > a.nry) && (y >= H - ps);
     const int kyend = ky1 + (fy ? 1 : 0), kxend = kx1 + (fx ? 1 : 0);
     double gj0 = 0.0;
@@ -677,28 +680,74 @@ __global__ __launch_bounds__(256) void k_bwd_densify(const DensBwdArgs a) {
         const int ky = jy <= ky1 ? jy : a.nry;
         for (int jx = kx0; jx <= kxend; ++jx) {
             const int kx = jx <= kx1 ? jx : a.nrx;
-            const int i = ky * a.nx + kx;
-            const double* P = a.patch + (size_t)i * 4;
+            const double* P = a.patch + (size_t)(ky * a.nx + kx) * 4;
             const double u = P[0], v = P[1];
             const Taps t = taps_of(a.J1, W, H, (double)x + u, (double)y + v);
             const double d = a.raw_residual ? (t.val - j0) : ((t.val - j0) - P[2]);
             const double ad = fabs(d);
-            const double wgt = 1.0 / fmax(1.0, ad);
-            double* gP = a.gP + (size_t)i * 4;
-            atom(gP + 0, gUx * wgt / Z);
-            atom(gP + 1, gVx * wgt / Z);
             const double gw = (gUx * (u - Ux) + gVx * (v - Vx)) / Z;
             const double gd = ad > 1.0 ? gw * (d > 0.0 ? -1.0 : 1.0) / (d * d) : 0.0;
             if (gd != 0.0) {
-                atom(gP + 0, gd * t.dx);
-                atom(gP + 1, gd * t.dy);
                 scatter_taps(a.gJ1, t, gd);
                 gj0 -= gd;
-                if (!a.raw_residual) atom(gP + 2, -gd);
             }
         }
     }
-    atom(a.gJ0 + g, gj0);
+    a.gJ0[g] += gj0;
+}
+
+// Pass 2, per patch (16 lanes, a lane's pixels strided by 16): the patch's
+// sums over its template square of the displacement adjoints (weight times
+// the flow adjoint over Z, and the residual adjoint times the bilinear
+// derivative) and of the mean residual's adjoint; one plain add per entry.
+__global__ __launch_bounds__(256) void k_bwd_densify_patch(const DensBwdArgs a) {
+    const int W = a.W, H = a.H;
+    const size_t n = (size_t)W * H;
+    const int N = a.nx * a.ny;
+    const int lane = threadIdx.x & 15;
+    int i = (int)((blockIdx.x * 256u + threadIdx.x) >> 4);
+    const bool valid = i < N;
+    if (!valid) i = N - 1;          // idle lanes shadow the last patch and store nothing
+    const int ps = a.ps;
+    const int ky = i / a.nx, kx = i - ky * a.nx;
+    const int x0 = kx < a.nrx ? kx * a.st : W - ps;
+    const int y0 = ky < a.nry ? ky * a.st : H - ps;
+    const double* P = a.patch + (size_t)i * 4;
+    const double u = P[0], v = P[1], md = P[2];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int p = lane; p < ps * ps; p += 16) {
+        const int py = p / ps, px = p - py * ps;
+        const int x = x0 + px, y = y0 + py;
+        const size_t g = (size_t)y * W + x;
+        const double gUx = a.gq[g], gVx = a.gq[n + g];
+        if (gUx == 0.0 && gVx == 0.0) continue;
+        const double Ux = a.Ud[g], Vx = a.Ud[n + g];
+        const double Z = a.Z[g];
+        const double j0 = a.J0[g];
+        const Taps t = taps_of(a.J1, W, H, (double)x + u, (double)y + v);
+        const double d = a.raw_residual ? (t.val - j0) : ((t.val - j0) - md);
+        const double ad = fabs(d);
+        const double wgt = 1.0 / fmax(1.0, ad);
+        s0 += gUx * wgt / Z;
+        s1 += gVx * wgt / Z;
+        const double gw = (gUx * (u - Ux) + gVx * (v - Vx)) / Z;
+        const double gd = ad > 1.0 ? gw * (d > 0.0 ? -1.0 : 1.0) / (d * d) : 0.0;
+        s0 += gd * t.dx;
+        s1 += gd * t.dy;
+        if (!a.raw_residual) s2 -= gd;
+    }
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) {
+        s0 += __shfl_xor(s0, m, 16);
+        s1 += __shfl_xor(s1, m, 16);
+        s2 += __shfl_xor(s2, m, 16);
+    }
+    if (valid && lane == 0) {
+        double* gP = a.gP + (size_t)i * 4;
+        gP[0] += s0;
+        gP[1] += s1;
+        gP[2] += s2;
+    }
 }
 
 // ------------------------------------------------------------------- pyramid
@@ -1014,6 +1063,7 @@ const void* dis_kernel_bwd_sweep_a() { return (const void*)&k_bwd_sweep_a; }
 const void* dis_kernel_bwd_sweep_b() { return (const void*)&k_bwd_sweep_b; }
 const void* dis_kernel_bwd_lin() { return (const void*)&k_bwd_lin; }
 const void* dis_kernel_bwd_ws() { return (const void*)&k_bwd_ws; }
+const void* dis_kernel_bwd_densify_patch() { return (const void*)&k_bwd_densify_patch; }
 const void* dis_kernel_bwd_densify() { return (const void*)&k_bwd_densify; }
 const void* dis_kernel_bwd_pyramid() { return (const void*)&k_bwd_pyramid; }
 

@@ -73,6 +73,7 @@ int dis_alloc_backward(dis_handle* h) {
     }
     B.scratch_px = pxmax;
     DALLOC(h, B.Z, pxmax * sizeof(double));
+    DALLOC(h, B.gq, 2 * pxmax * sizeof(double));
     if (p.refine) {
         DALLOC(h, B.gUd, 2 * pxmax * sizeof(double));
         DALLOC(h, B.gJ1w, pxmax * sizeof(double));
@@ -331,9 +332,12 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
         da.gJ0 = B.gJ0[s];
         da.gJ1 = B.gJ1[s];
         da.gP = B.gP[s];
+        da.gq = B.gq;
         const double cover = std::pow((double)ps / g.st, 2.0);
         q.add(dis_kernel_bwd_densify(), grid2d(W, H), dim3(256), &da, sizeof da, 0, "bwd_densify",
-              72.0 * px + 32.0 * N, cover * 60.0 * px);
+              72.0 * px, cover * 40.0 * px);
+        q.add(dis_kernel_bwd_densify_patch(), dim3((unsigned)((N * 16 + 255) / 256)), dim3(256), &da, sizeof da, 0,
+              "bwd_densify", 64.0 * px + 32.0 * N, cover * 40.0 * px);
 
         SearchBwdArgs sa;
         std::memset(&sa, 0, sizeof sa);
