@@ -198,9 +198,9 @@ int dis_autotune(dis_handle* h, const char* cache_path);
  * 3: 16x16/1024, 4: 32x16/1024, 5: 16x16/512, 6: 32x16/512, 7: 8x8/512,
  * 8: 16x8/512, 9: 8x8/256.  launch_mode bit 0: 0 runs each scale as one
  * persistent launch over a task queue, 1 as one launch per phase; bit 1 set
- * turns on the single-workgroup path: a scale of at most 1024 horizontal
- * pixel pairs is densified and refined, every fixed-point step, by one
- * block instead of tiles; bit 2 set makes dis_flow_backward reverse the SOR
+ * turns on the single-workgroup path: a scale of at most 256 horizontal
+ * pixel pairs (1024 with bit 4 also set) is densified and refined, every
+ * fixed-point step, by one block instead of tiles; bit 2 set makes dis_flow_backward reverse the SOR
  * sweeps with one launch per half sweep (a plain reference form) instead of
  * one tiled launch per fixed-point step; bit 3 set makes every forward
  * refinement launch recompute the linearisation from the level images

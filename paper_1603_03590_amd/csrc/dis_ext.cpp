@@ -311,7 +311,8 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
     const int tile = bestc.tile;
     for (int l : lpps)
         if (r == DIS_OK && dis_kernel_phase_search(h->p.patch_size, l)) r = measure(Cand{l, tile, 1});
-    if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, 3});   // single-workgroup small scales
+    if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, 3});    // single-workgroup scales of <= 256 pairs
+    if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, 19});   // ... of <= 1024 pairs
     if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, bestc.mode | 8});   // no linearisation cache
     if (r == DIS_OK) r = measure(Cand{0, 0, 0});
     for (int l : lpps)

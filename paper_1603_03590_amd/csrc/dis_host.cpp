@@ -318,7 +318,7 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     int tw, th;
     if (!dis_refine_tile(refine_tile, &tw, &th, nullptr))
         return fail(h, DIS_EINVAL, "unknown refinement tile %d", refine_tile);
-    if (launch_mode < 0 || launch_mode > 15) return fail(h, DIS_EINVAL, "launch mode %d outside 0..15", launch_mode);
+    if (launch_mode < 0 || launch_mode > 31) return fail(h, DIS_EINVAL, "launch mode %d outside 0..31", launch_mode);
     if (lanes_per_patch)
         for (int s = 0; s < DIS_MAXL; ++s) {
             const int l = lanes_per_patch[s];
@@ -329,7 +329,7 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     for (int s = 0; s < DIS_MAXL; ++s) h->lpp[s] = lanes_per_patch ? lanes_per_patch[s] : 0;
     h->refine_tile = refine_tile;
     h->mode_phase = launch_mode & 1;
-    h->small_levels = (launch_mode & 2) ? 1 : 0;
+    h->small_levels = (launch_mode & 2) ? ((launch_mode & 16) ? 2 : 1) : 0;
     h->bwd_reference = (launch_mode & 4) ? 1 : 0;
     h->no_lin_cache = (launch_mode & 8) ? 1 : 0;
     return DIS_OK;
@@ -341,7 +341,8 @@ extern "C" int dis_get_tunables(const dis_handle* h, int* lanes_per_patch, int* 
         for (int s = 0; s < DIS_MAXL; ++s) lanes_per_patch[s] = h->lpp[s];
     if (refine_tile) *refine_tile = h->refine_tile;
     if (launch_mode)
-        *launch_mode = h->mode_phase | (h->small_levels ? 2 : 0) | (h->bwd_reference ? 4 : 0) | (h->no_lin_cache ? 8 : 0);
+        *launch_mode = h->mode_phase | (h->small_levels ? 2 : 0) | (h->bwd_reference ? 4 : 0) | (h->no_lin_cache ? 8 : 0) |
+                       (h->small_levels == 2 ? 16 : 0);
     return DIS_OK;
 }
 
@@ -607,7 +608,12 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             ra.omega = p.sor_omega; ra.eps = 1e-3;
             for (int q = 0; q < 3; ++q) P.dU[q] = sb.dU[q];
             P.dens_bx = (W + 63) / 64;
-            const bool small = p.refine && h->small_levels && !fbm && nc == 1 && ((W + 1) / 2) * Hh <= DIS_SMALL_PAIRS;
+            // single-workgroup scales: up to 256 pixel pairs, or up to the
+            // block's capacity with the wider setting
+            const int small_max = h->small_levels == 2 ? DIS_SMALL_PAIRS : DIS_SMALL_PAIRS / 4;
+            // (not in the adjoint's recomputation: its reverse tiles read the
+            // linearisation cache, which only the tiled refinement fills)
+            const bool small = p.refine && h->small_levels && !opt && !fbm && nc == 1 && ((W + 1) / 2) * Hh <= small_max;
             if (small) LH.small.push_back((int)LH.lp.size());
             LH.is_small.push_back(small ? 1 : 0);
             LH.lp.push_back(P);

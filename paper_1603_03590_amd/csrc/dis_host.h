@@ -129,7 +129,7 @@ struct dis_handle {
     int lpp[DIS_MAXL];
     int refine_tile = 7;
     int mode_phase = 1;     // 1: one launch per phase, 0: one persistent launch per level
-    int small_levels = 0;   // refine pair-levels that fit one workgroup in a single launch
+    int small_levels = 0;   // single-launch refinement of scales of <= 256 (1) or <= 1024 (2) pixel pairs
     int bwd_reference = 0;  // backward: one launch per reverse half sweep instead of reverse tiles
     int no_lin_cache = 0;   // forward refinement recomputes the linearisation in every launch
     int n_cu = 256;

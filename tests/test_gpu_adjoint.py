@@ -184,13 +184,15 @@ def test_backward_repeat_and_graph_agree_with_eager():
 ])
 def test_tiled_reverse_sweeps_match_reference_form(name, cr, over):
     """The tiled reverse of each fixed-point step against one launch per
-    reverse half sweep (launch mode bit 2), and both against the oracle."""
+    reverse half sweep (launch mode bit 2) and against a forward whose
+    scales run as single workgroups (bits 1 and 4, tape written by that
+    kernel), and all against the oracle."""
     say(f"[adjoint] case tiled vs reference {name}")
     I0, I1, gt = crop(*cr)
     h, w = I0.shape
     p = params(105, flags=F64 | KEEP, **over)
     grads = []
-    for mode in (1, 1 | 4):
+    for mode in (1, 1 | 4, 1 | 2 | 16):
         d = DIS(p, w, h)
         try:
             d.set_tunables(None, 7, mode)
@@ -198,10 +200,11 @@ def test_tiled_reverse_sweeps_match_reference_form(name, cr, over):
         finally:
             d.close()
     _, r0, r1 = oracle_grad(I0, I1, gt, p)
-    (_, t0, t1), (_, f0, f1) = grads
+    (_, t0, t1), (_, f0, f1), (_, s0, s1) = grads
     say(f"[adjoint] {name}: tiled vs reference {rel_err(t0, f0):.2e} {rel_err(t1, f1):.2e}, "
-        f"tiled vs oracle {rel_err(t0, r0):.2e}")
+        f"single-workgroup {rel_err(s0, t0):.2e}, tiled vs oracle {rel_err(t0, r0):.2e}")
     assert rel_err(t0, f0) <= 1e-11 and rel_err(t1, f1) <= 1e-11
+    assert rel_err(s0, t0) <= 1e-11 and rel_err(s1, t1) <= 1e-11
     assert rel_err(t0, r0) <= 1e-7 and rel_err(t1, r1) <= 1e-7
 
 

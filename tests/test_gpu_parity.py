@@ -199,7 +199,7 @@ def test_launch_choices_are_bitwise_invariant(case):
         # every refinement tile shape / block size, with varied lanes per patch
         choices += [([[4, 8, 16][t % 3]] * 16, t, 1) for t in range(1, N_TILES)]
         # with the single-workgroup scales (launch mode bit 1)
-        choices += [(None, 0, 3), (None, 3, 3), (None, 0, 2)]
+        choices += [(None, 0, 3), (None, 3, 3), (None, 0, 2), (None, 7, 19), (None, 0, 18)]
         # without the linearisation cache (launch mode bit 3)
         choices += [(None, 7, 9), (None, 0, 8), (None, 2, 11)]
         for lpp, tile, mode in choices:
