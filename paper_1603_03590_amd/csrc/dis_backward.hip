@@ -296,11 +296,9 @@ __global__ __launch_bounds__(256) void k_bwd_sweep_b(const SweepBwdArgs a) {
 // through omega/(A+S), c = N - S U - B, the neighbour sums N and S, the
 // robust data weights and the linearisation, down to U, F, J0 and J1w.
 // Edge-weight adjoints as seen from each endpoint go to `edge` for part 2.
-__global__ __launch_bounds__(256) void k_bwd_lin(const RefBwdArgs a) {
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void bwd_lin_pixel(const RefBwdArgs& a, int x, int y, double (&simg)[2][8][68], int ox,
+                                              int oy) {
     const int W = a.W, H = a.H;
-    if (x >= W || y >= H) return;
     const size_t g = (size_t)y * W + x, n = (size_t)W * H;
     const double* ws = a.coef + 5 * n;
     const double* acc = a.acc;
@@ -374,11 +372,13 @@ __global__ __launch_bounds__(256) void k_bwd_lin(const RefBwdArgs a) {
     gIxy += gby * (-by * by) * 2.0 * Ixy; gIyy += gby * (-by * by) * 2.0 * Iyy;
     // derivatives -> images (central differences with replicated borders)
     const int xm = max(x - 1, 0), xp = min(x + 1, W - 1), ym = max(y - 1, 0), yp = min(y + 1, H - 1);
-    double* G0 = a.gJ0;
-    double* G1 = a.gJ1w;
+    // image adjoints into the block's LDS cells (J0: 0, J1w: 1)
+    auto lds = [&](int f, int xx, int yy, double v) {
+        if (v != 0.0) unsafeAtomicAdd(&simg[f][yy - oy][xx - ox], v);
+    };
     auto addIb = [&](int xx, int yy, double v) {   // Ib = (J0 + J1w)/2
-        atom(G0 + yy * W + xx, 0.5 * v);
-        atom(G1 + yy * W + xx, 0.5 * v);
+        lds(0, xx, yy, 0.5 * v);
+        lds(1, xx, yy, 0.5 * v);
     };
     auto addIxa = [&](int xx, int yy, double v) {  // Ix at (xx, yy)
         addIb(min(xx + 1, W - 1), yy, v / 2.0);
@@ -396,12 +396,34 @@ __global__ __launch_bounds__(256) void k_bwd_lin(const RefBwdArgs a) {
     addIxa(x, ym, -gIxy / 2.0);
     addIya(x, yp, gIyy / 2.0);
     addIya(x, ym, -gIyy / 2.0);
-    atom(G1 + g, gIz);
-    atom(G0 + g, -gIz);
-    atom(G1 + y * W + xp, gIxz / 2.0); atom(G1 + y * W + xm, -gIxz / 2.0);
-    atom(G0 + y * W + xp, -gIxz / 2.0); atom(G0 + y * W + xm, gIxz / 2.0);
-    atom(G1 + yp * W + x, gIyz / 2.0); atom(G1 + ym * W + x, -gIyz / 2.0);
-    atom(G0 + yp * W + x, -gIyz / 2.0); atom(G0 + ym * W + x, gIyz / 2.0);
+    lds(1, x, y, gIz);
+    lds(0, x, y, -gIz);
+    lds(1, xp, y, gIxz / 2.0); lds(1, xm, y, -gIxz / 2.0);
+    lds(0, xp, y, -gIxz / 2.0); lds(0, xm, y, gIxz / 2.0);
+    lds(1, x, yp, gIyz / 2.0); lds(1, x, ym, -gIyz / 2.0);
+    lds(0, x, yp, -gIyz / 2.0); lds(0, x, ym, gIyz / 2.0);
+}
+
+__global__ __launch_bounds__(256) void k_bwd_lin(const RefBwdArgs a) {
+    // the image adjoints of a 64x4 block land within 2 pixels of it: they are
+    // summed in LDS first (68x8 cells per image), then added to memory once
+    // per cell, which takes most of the float64 atomics off the memory side
+    __shared__ double simg[2][8][68];
+    for (int i = threadIdx.x; i < 2 * 8 * 68; i += 256) (&simg[0][0][0])[i] = 0.0;
+    __syncthreads();
+    const int ox = (int)blockIdx.x * 64 - 2, oy = (int)blockIdx.y * 4 - 2;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int W = a.W, H = a.H;
+    if (x < W && y < H) bwd_lin_pixel(a, x, y, simg, ox, oy);
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * 8 * 68; i += 256) {
+        const int f = i / (8 * 68), r = i - f * (8 * 68), cy = r / 68, cx = r - cy * 68;
+        const int gx = ox + cx, gy = oy + cy;
+        const double v = simg[f][cy][cx];
+        if (v != 0.0 && gx >= 0 && gx < W && gy >= 0 && gy < H)
+            unsafeAtomicAdd((f ? a.gJ1w : a.gJ0) + (size_t)gy * W + gx, v);
+    }
 }
 
 // Part 2, per owner pixel: the adjoint of its edge weight (both edges, both
