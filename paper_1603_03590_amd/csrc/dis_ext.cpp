@@ -91,22 +91,37 @@ static int build_batch(dis_handle* h, int n, const int* w, const int* hgt, const
         dis_add_upsample(h, *pairs[k].sb, w[k], hgt[k], nullptr, tmp);
         const UpsArgs ua = *(const UpsArgs*)tmp.items[0].arg.data();
         bp->ups.push_back(ua);
-        ust.push_back(ust.back() + ((w[k] + 63) / 64) * ((hgt[k] + 3) / 4));
+        ust.push_back(ust.back() + ((w[k] + 255) / 256) * ((hgt[k] + 3) / 4));
     }
     // device layout of the pyramid and upscaling tables
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     size_t bytes = 0;
     std::vector<size_t> off_tab, off_st;
+    // block -> pair maps (one load per block instead of a search of start[])
+    auto block_map = [](const std::vector<int>& st) {
+        std::vector<int> m(st.back());
+        for (size_t j = 0; j + 1 < st.size(); ++j)
+            for (int t = st[j]; t < st[j + 1]; ++t) m[t] = (int)j;
+        return m;
+    };
+    std::vector<size_t> off_map;
+    std::vector<std::vector<int>> pmaps;
     for (size_t i = 0; i < passes.size(); ++i) {
         off_tab.push_back(bytes);
         bytes = al(bytes + sizeof(PyrArgs) * passes[i].size());
         off_st.push_back(bytes);
         bytes = al(bytes + sizeof(int) * pstart[i].size());
+        pmaps.push_back(block_map(pstart[i]));
+        off_map.push_back(bytes);
+        bytes = al(bytes + sizeof(int) * pmaps.back().size());
     }
     bp->ups_off = bytes;
     bytes = al(bytes + sizeof(UpsArgs) * n);
     const size_t ust_off = bytes;
     bytes = al(bytes + sizeof(int) * (n + 1));
+    const std::vector<int> umap = block_map(ust);
+    const size_t umap_off = bytes;
+    bytes = al(bytes + sizeof(int) * umap.size());
     XHIPCHK(h, hipMalloc(&bp->io, bytes));
     bp->pyr0_off = off_tab[0];
 
@@ -117,6 +132,7 @@ static int build_batch(dis_handle* h, int n, const int* w, const int* hgt, const
         std::memset(&T, 0, sizeof T);
         T.tab = (const PyrArgs*)((char*)bp->io + off_tab[i]);
         T.start = (const int*)((char*)bp->io + off_st[i]);
+        T.blk = (const int*)((char*)bp->io + off_map[i]);
         T.n = (int)passes[i].size();
         double by = 0.0;
         for (const PyrArgs& pa : passes[i]) by += 2.0 * pa.w0 * pa.h0 * (i == 0 ? (f64io ? 8 : 4) : 8);
@@ -131,8 +147,10 @@ static int build_batch(dis_handle* h, int n, const int* w, const int* hgt, const
         T0->nzero = bp->tabs.nsync;
     }
     UpsTab UT;
+    std::memset(&UT, 0, sizeof UT);
     UT.tab = (const UpsArgs*)((char*)bp->io + bp->ups_off);
     UT.start = (const int*)((char*)bp->io + ust_off);
+    UT.blk = (const int*)((char*)bp->io + umap_off);
     UT.n = n;
     double uby = 0.0;
     for (int k = 0; k < n; ++k) uby += (f64io ? 16.0 : 8.0) * w[k] * hgt[k];
@@ -143,7 +161,9 @@ static int build_batch(dis_handle* h, int n, const int* w, const int* hgt, const
     for (size_t i = 0; i < passes.size(); ++i) {
         std::memcpy(host.data() + off_tab[i], passes[i].data(), sizeof(PyrArgs) * passes[i].size());
         std::memcpy(host.data() + off_st[i], pstart[i].data(), sizeof(int) * pstart[i].size());
+        std::memcpy(host.data() + off_map[i], pmaps[i].data(), sizeof(int) * pmaps[i].size());
     }
+    std::memcpy(host.data() + umap_off, umap.data(), sizeof(int) * umap.size());
     std::memcpy(host.data() + bp->ups_off, bp->ups.data(), sizeof(UpsArgs) * n);
     std::memcpy(host.data() + ust_off, ust.data(), sizeof(int) * (n + 1));
     XHIPCHK(h, hipMemcpy(bp->io, host.data(), bytes, hipMemcpyHostToDevice));

@@ -483,7 +483,7 @@ void dis_add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, Se
     ua.centre_map = (p.flags & DIS_FLAG_PIXEL_CENTRE) ? 1 : 0;
     ua.out = flow;
     ua.out_f64 = f64io ? 1 : 0;
-    seq.add(dis_kernel_upsample(), dim3((w + 63) / 64, (hgt + 3) / 4), dim3(256), &ua, sizeof ua, 2, "upsample",
+    seq.add(dis_kernel_upsample(), dim3((w + 255) / 256, (hgt + 3) / 4), dim3(256), &ua, sizeof ua, 2, "upsample",
             16.0 * ua.Ws * ua.Hs + (f64io ? 16.0 : 8.0) * w * hgt, 20.0 * w * hgt);
 }
 

@@ -181,6 +181,7 @@ struct FbLaunch {
 struct PyrTab {
     const PyrArgs* tab;
     const int* start;
+    const int* blk;         // [blocks]: the entry each block belongs to
     int n;
     int* zero;              // block 0 clears these ints (queue state of the level launches)
     int nzero;
@@ -189,6 +190,7 @@ struct PyrTab {
 struct UpsTab {
     const UpsArgs* tab;
     const int* start;
+    const int* blk;         // [blocks]: the entry each block belongs to
     int n;
 };
 

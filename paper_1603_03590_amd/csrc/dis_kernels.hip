@@ -50,30 +50,61 @@ __device__ __forceinline__ double dpp_mov(double v) {
 // ------------------------------------------------------------------ pyramid
 
 // One 32x32 tile of level a of frame f, channel c: the tile's part of levels
-// a+1..a+nlev.
-__device__ __forceinline__ void pyramid_tile(const PyrArgs& a, int tile, int f, int c) {
+// a+1..a+nlev.  The argument block is read once, before the tile's loads
+// (in the table-driven launch it sits in memory, and the barriers between
+// levels would otherwise make every level read it again).
+__device__ __forceinline__ void pyramid_tile(const PyrArgs& A, int tile, int f, int c) {
     __shared__ double t0[32][33];
     __shared__ double t1[16][17];
-    const int bx = tile % a.tiles_x, by = tile / a.tiles_x;
+    const int tiles_x = A.tiles_x, w0 = A.w0, h0 = A.h0, nlev = A.nlev, kind = A.src_kind, pitch = A.src_pitch;
+    const double scale = A.scale;
+    const size_t cs = (size_t)c * A.src_cstride;
+    const void* src = f ? A.src[1] : A.src[0];
+    double* lvl0 = f ? A.lvl0[1] : A.lvl0[0];
+    double* dst[6];
+    int ws[6], hs[6];
+#pragma unroll
+    for (int k = 1; k < 6; ++k) {
+        dst[k] = f ? A.dst[1][k] : A.dst[0][k];
+        ws[k] = A.ws[k];
+        hs[k] = A.hs[k];
+    }
+    const int bx = tile % tiles_x, by = tile / tiles_x;
     const int X0 = bx * 32, Y0 = by * 32;
-    for (int i = threadIdx.x; i < 1024; i += 256) {
+    // the four loads of a thread are issued before any is used, so the tile
+    // costs one round of memory latency
+    double v4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = threadIdx.x + k * 256;
+        const int ly = i >> 5, lx = i & 31;
+        const int x = X0 + lx, y = Y0 + ly;
+        v4[k] = 0.0;
+        if (x < w0 && y < h0) {
+            const size_t g = cs + (size_t)y * pitch + x;
+            if (kind == 1)
+                v4[k] = (double)((const float*)src)[g];
+            else
+                v4[k] = ((const double*)src)[g];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = threadIdx.x + k * 256;
         const int ly = i >> 5, lx = i & 31;
         const int x = X0 + lx, y = Y0 + ly;
         double v = 0.0;
-        if (x < a.w0 && y < a.h0) {
-            const size_t g = (size_t)c * a.src_cstride + (size_t)y * a.src_pitch + x;
-            if (a.src_kind == 1)
-                v = a.scale * (double)((const float*)a.src[f])[g];
-            else
-                v = a.scale * ((const double*)a.src[f])[g];
-            if (a.lvl0[f]) a.lvl0[f][((size_t)c * a.h0 + y) * a.w0 + x] = v;
+        if (x < w0 && y < h0) {
+            v = scale * v4[k];
+            if (lvl0) lvl0[((size_t)c * h0 + y) * w0 + x] = v;
         }
         t0[ly][lx] = v;
     }
     __syncthreads();
-    int n = 32;
-    for (int k = 1; k <= a.nlev; ++k) {
-        n >>= 1;
+#pragma unroll
+    for (int k = 1; k < 6; ++k) {
+        if (k > nlev) break;
+        const int n = 32 >> k;
         // level k of the tile (n x n <= 256, one pixel per thread): mean of a
         // 2x2 block of level k-1, summed row-major ((a+b)+c)+d, then scaled
         const bool from0 = (k & 1);
@@ -88,8 +119,8 @@ __device__ __forceinline__ void pyramid_tile(const PyrArgs& a, int tile, int f, 
                 v = 0.25 * (((t1[2 * ly][2 * lx] + t1[2 * ly][2 * lx + 1]) + t1[2 * ly + 1][2 * lx]) +
                             t1[2 * ly + 1][2 * lx + 1]);
             const int xs = (X0 >> k) + lx, ys = (Y0 >> k) + ly;
-            double* d = a.dst[f][k];
-            if (d && xs < a.ws[k] && ys < a.hs[k]) d[((size_t)c * a.hs[k] + ys) * a.ws[k] + xs] = v;
+            double* d = dst[k];
+            if (d && xs < ws[k] && ys < hs[k]) d[((size_t)c * hs[k] + ys) * ws[k] + xs] = v;
         }
         __syncthreads();   // every read of the source buffer precedes the overwrite
         if (act) {
@@ -121,7 +152,7 @@ __global__ __launch_bounds__(256) void k_pyramid_tab(const PyrTab T) {
     if (blockIdx.x == 0 && blockIdx.y == 0)
         for (int i = threadIdx.x; i < T.nzero; i += 256) T.zero[i] = 0;
     const int t = blockIdx.x;
-    const int j = seg_find(T.start, 0, T.n, t);
+    const int j = __builtin_amdgcn_readfirstlane(T.blk[t]);
     pyramid_tile(T.tab[j], t - __builtin_amdgcn_readfirstlane(T.start[j]), blockIdx.y, 0);
 }
 
@@ -875,22 +906,35 @@ __global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
 
 // ----------------------------------------------------------------- upscale
 
+// A 256x4 block of the output: each thread computes four pixels 64 apart in
+// a row (every store instruction writes 64 consecutive elements), with all
+// their taps requested together.
 __device__ __forceinline__ void upsample_block(const UpsArgs& a, int bx, int by) {
-    const int x = bx * 64 + (threadIdx.x & 63);
     const int y = by * 4 + (threadIdx.x >> 6);
-    if (x >= a.W || y >= a.H) return;
-    double qx, qy;
-    if (a.centre_map) { qx = ((double)x + 0.5) / a.f - 0.5; qy = ((double)y + 0.5) / a.f - 0.5; }
-    else { qx = (double)x / a.f; qy = (double)y / a.f; }
-    const double u = a.f * bilin(a.U, a.Ws, a.Hs, qx, qy);
-    const double v = a.f * bilin(a.U + (size_t)a.Ws * a.Hs, a.Ws, a.Hs, qx, qy);
-    const size_t g = (size_t)y * a.W + x, n = (size_t)a.W * a.H;
-    if (a.out_f64) {
-        ((double*)a.out)[g] = u;
-        ((double*)a.out)[n + g] = v;
-    } else {
-        ((float*)a.out)[g] = (float)u;
-        ((float*)a.out)[n + g] = (float)v;
+    if (y >= a.H) return;
+    const size_t n = (size_t)a.W * a.H;
+    double u4[4], v4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = min(bx * 256 + k * 64 + (int)(threadIdx.x & 63), a.W - 1);
+        double qx, qy;
+        if (a.centre_map) { qx = ((double)x + 0.5) / a.f - 0.5; qy = ((double)y + 0.5) / a.f - 0.5; }
+        else { qx = (double)x / a.f; qy = (double)y / a.f; }
+        u4[k] = a.f * bilin(a.U, a.Ws, a.Hs, qx, qy);
+        v4[k] = a.f * bilin(a.U + (size_t)a.Ws * a.Hs, a.Ws, a.Hs, qx, qy);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = bx * 256 + k * 64 + (int)(threadIdx.x & 63);
+        if (x >= a.W) continue;
+        const size_t g = (size_t)y * a.W + x;
+        if (a.out_f64) {
+            ((double*)a.out)[g] = u4[k];
+            ((double*)a.out)[n + g] = v4[k];
+        } else {
+            ((float*)a.out)[g] = (float)u4[k];
+            ((float*)a.out)[n + g] = (float)v4[k];
+        }
     }
 }
 
@@ -901,10 +945,10 @@ __global__ __launch_bounds__(256) void k_upsample(const UpsArgs a) {
 // Upscaling of many pairs in one launch (blocks of pair j are start[j] ..).
 __global__ __launch_bounds__(256) void k_upsample_tab(const UpsTab T) {
     const int t = blockIdx.x;
-    const int j = seg_find(T.start, 0, T.n, t);
+    const int j = __builtin_amdgcn_readfirstlane(T.blk[t]);
     const UpsArgs& a = T.tab[j];
     const int local = t - __builtin_amdgcn_readfirstlane(T.start[j]);
-    const int bxn = (a.W + 63) / 64;
+    const int bxn = (a.W + 255) / 256;
     upsample_block(a, local % bxn, local / bxn);
 }
 
