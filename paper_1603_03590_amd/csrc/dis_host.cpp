@@ -638,11 +638,24 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     // device tables for every level, one allocation
     size_t bytes = 0;
     int nsync = 0;
-    std::vector<size_t> off_lp, off_rph, off_start, off_small, off_fb;
+    std::vector<size_t> off_lp, off_rph, off_start, off_small, off_fb, off_tseg;
     std::vector<int> off_sync;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    // tasks (blocks) of segment (phase ph, pair j) of a level
+    auto seg_count = [&](const LevelHost& LH, int ph, int j) {
+        const LevelPair& P = LH.lp[j];
+        if (ph == 0) return (P.sa.nx * P.sa.ny * LH.lpp + 255) / 256;
+        if (LH.is_small[j]) return 0;   // densified and refined by the single-workgroup launch
+        if (ph == 1) return P.dens_bx * ((P.da.H + 3) / 4);
+        return P.ra.tiles_x * ((P.ra.H + th - 1) / th);
+    };
     for (LevelHost& LH : levels) {
         const int np = (int)LH.lp.size(), nseg = LH.nph * np;
+        size_t ntask = 0;
+        for (int ph = 0; ph < LH.nph; ++ph)
+            for (int j = 0; j < np; ++j) ntask += (size_t)seg_count(LH, ph, j);
+        off_tseg.push_back(bytes);
+        bytes = al(bytes + sizeof(int) * std::max<size_t>(1, ntask));
         off_lp.push_back(bytes);
         bytes = al(bytes + sizeof(LevelPair) * np);
         off_rph.push_back(bytes);
@@ -687,12 +700,10 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             for (int j = 0; j < np; ++j) {
                 const LevelPair& P = LH.lp[j];
                 start[ph * np + j] = t;
-                int cnt;
-                if (ph == 0) cnt = (P.sa.nx * P.sa.ny * LH.lpp + 255) / 256;
-                else if (LH.is_small[j]) cnt = 0;   // densified and refined by the single-workgroup launch
-                else if (ph == 1) cnt = P.dens_bx * ((P.da.H + 3) / 4);
-                else {
-                    cnt = P.ra.tiles_x * ((P.ra.H + th - 1) / th);
+                const int cnt = seg_count(LH, ph, j);
+                int* tseg = (int*)(host.data() + off_tseg[li]) + t;
+                for (int q = 0; q < cnt; ++q) tseg[q] = ph * np + j;
+                if (ph >= 2 && cnt > 0) {
                     const RefPhase& rp = LH.rph[ph - 2];
                     const double px = (double)P.ra.W * P.ra.H;
                     ph_by[ph] += refine_bytes(px, rp.f >= 0, rp.in >= 0, rp.last);
@@ -708,6 +719,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         LL.pairs = (const LevelPair*)((char*)tabs.mem + off_lp[li]);
         LL.rph = (const RefPhase*)((char*)tabs.mem + off_rph[li]);
         LL.start = (const int*)((char*)tabs.mem + off_start[li]);
+        LL.task_seg = (const int*)((char*)tabs.mem + off_tseg[li]);
         LL.sync = tabs.sync + off_sync[li];
         LL.npairs = np;
         LL.nph = LH.nph;

@@ -132,6 +132,7 @@ struct LevelLaunch {
     const LevelPair* pairs;
     const RefPhase* rph;
     const int* start;       // [nph * npairs + 1] first task of each segment
+    const int* task_seg;    // [ntasks] segment of each task (phase * npairs + pair)
     int* sync;              // [0] queue head, [1] wait-timeout flag, [2 + seg] finished tasks
     int npairs, nph, ntasks;
     int lin_cache;          // 1: a level's first refinement launch stores the linearisation, later ones load it

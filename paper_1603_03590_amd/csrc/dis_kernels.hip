@@ -136,16 +136,6 @@ __global__ __launch_bounds__(256) void k_pyramid(const PyrArgs a) {
     pyramid_tile(a, blockIdx.x, blockIdx.y & 1, blockIdx.y >> 1);
 }
 
-// Index of the segment of a sorted start[] table that holds task t
-// (start[lo] <= t < start[lo+1]), made wave-uniform.
-__device__ __forceinline__ int seg_find(const int* start, int lo, int hi, int t) {
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (__builtin_amdgcn_readfirstlane(start[mid]) <= t) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 // Pyramid passes of many pairs in one launch (tiles of pair j are
 // start[j] .. start[j+1]-1).
 __global__ __launch_bounds__(256) void k_pyramid_tab(const PyrTab T) {
@@ -865,7 +855,7 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
 template <int PS, int LPP, int NC = 1>
 __global__ __launch_bounds__(256) void k_phase_search(const LevelLaunch L) {
     const int t = blockIdx.x;                       // phase 0 starts at task 0
-    const int j = seg_find(L.start, 0, L.npairs, t);
+    const int j = __builtin_amdgcn_readfirstlane(L.task_seg[t]);
     search_block<PS, LPP, NC>(L.pairs[j].sa, t - __builtin_amdgcn_readfirstlane(L.start[j]));
 }
 
@@ -873,7 +863,7 @@ template <bool COLOUR = false>
 __global__ __launch_bounds__(256) void k_phase_densify(const LevelLaunch L) {
     const int np = L.npairs;
     const int t = __builtin_amdgcn_readfirstlane(L.start[np]) + blockIdx.x;
-    const int j = seg_find(L.start, np, 2 * np, t) - np;
+    const int j = __builtin_amdgcn_readfirstlane(L.task_seg[t]) - np;
     const LevelPair& P = L.pairs[j];
     const int local = t - __builtin_amdgcn_readfirstlane(L.start[np + j]);
     densify_block<COLOUR>(P.da, local % P.dens_bx, local / P.dens_bx);
@@ -886,7 +876,7 @@ __global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
     const int phase = PL.phase;
     const int np = L.npairs, s0 = phase * np;
     const int t = __builtin_amdgcn_readfirstlane(L.start[s0]) + dis_xcd_tile(blockIdx.x, gridDim.x);
-    const int j = seg_find(L.start, s0, s0 + np, t) - s0;
+    const int j = __builtin_amdgcn_readfirstlane(L.task_seg[t]) - s0;
     const LevelPair& P = L.pairs[j];
     const RefPhase rp = L.rph[phase - 2];
     RefineArgs ra = P.ra;
@@ -1220,7 +1210,6 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
     int* head = L.sync;
     int* err = L.sync + 1;
     int* done = L.sync + 2;
-    const int nseg = L.nph * L.npairs;
     // every value steering this loop is made wave-uniform explicitly
     for (;;) {
         lane0_take(head, &s_task);
@@ -1228,7 +1217,7 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
         const int t = __builtin_amdgcn_readfirstlane(s_task);
         __syncthreads();   // s_task is rewritten on the next round
         if (t >= L.ntasks) break;
-        const int seg = seg_find(L.start, 0, nseg, t);
+        const int seg = __builtin_amdgcn_readfirstlane(L.task_seg[t]);
         const int phase = seg / L.npairs, pair = seg - phase * L.npairs;
         const int local = t - __builtin_amdgcn_readfirstlane(L.start[seg]);
         const int prev = phase > 0 ? seg - L.npairs : seg;
