@@ -898,21 +898,40 @@ __global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
 
 // A 256x4 block of the output: each thread computes four pixels 64 apart in
 // a row (every store instruction writes 64 consecutive elements), with all
-// their taps requested together.
+// their taps requested together.  The value is bilin() of each flow plane,
+// f times: the row's vertical taps and weight are shared by the pixels and
+// both planes, and x / f is a multiplication by 1 / f, exact for f = 2^s.
 __device__ __forceinline__ void upsample_block(const UpsArgs& a, int bx, int by) {
     const int y = by * 4 + (threadIdx.x >> 6);
     if (y >= a.H) return;
-    const size_t n = (size_t)a.W * a.H;
+    const int Ws = a.Ws, Hs = a.Hs;
+    const double f = a.f, inv_f = 1.0 / f;
+    const double* Uu = a.U;
+    const double* Uv = a.U + (size_t)Ws * Hs;
+    const double qy = a.centre_map ? ((double)y + 0.5) * inv_f - 0.5 : (double)y * inv_f;
+    double yf = floor(qy);
+    const double ay = qy - yf;
+    yf = fmin(fmax(yf, -2.0), (double)Hs + 1.0);
+    const int yi = (int)yf;
+    const int r0 = clampi(yi, 0, Hs - 1) * Ws, r1 = clampi(yi + 1, 0, Hs - 1) * Ws;
     double u4[4], v4[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int x = min(bx * 256 + k * 64 + (int)(threadIdx.x & 63), a.W - 1);
-        double qx, qy;
-        if (a.centre_map) { qx = ((double)x + 0.5) / a.f - 0.5; qy = ((double)y + 0.5) / a.f - 0.5; }
-        else { qx = (double)x / a.f; qy = (double)y / a.f; }
-        u4[k] = a.f * bilin(a.U, a.Ws, a.Hs, qx, qy);
-        v4[k] = a.f * bilin(a.U + (size_t)a.Ws * a.Hs, a.Ws, a.Hs, qx, qy);
+        const double qx = a.centre_map ? ((double)x + 0.5) * inv_f - 0.5 : (double)x * inv_f;
+        double xf = floor(qx);
+        const double ax = qx - xf;
+        xf = fmin(fmax(xf, -2.0), (double)Ws + 1.0);
+        const int xi = (int)xf;
+        const int c0 = clampi(xi, 0, Ws - 1), c1 = clampi(xi + 1, 0, Ws - 1);
+        const double ut = (1.0 - ax) * Uu[r0 + c0] + ax * Uu[r0 + c1];
+        const double ub = (1.0 - ax) * Uu[r1 + c0] + ax * Uu[r1 + c1];
+        const double vt = (1.0 - ax) * Uv[r0 + c0] + ax * Uv[r0 + c1];
+        const double vb = (1.0 - ax) * Uv[r1 + c0] + ax * Uv[r1 + c1];
+        u4[k] = f * ((1.0 - ay) * ut + ay * ub);
+        v4[k] = f * ((1.0 - ay) * vt + ay * vb);
     }
+    const size_t n = (size_t)a.W * a.H;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int x = bx * 256 + k * 64 + (int)(threadIdx.x & 63);
