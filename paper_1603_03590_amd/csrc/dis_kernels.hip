@@ -1171,14 +1171,6 @@ __global__ __launch_bounds__(NT) void k_small_level(const SmallLaunch S) {
                     }
                 }
                 __syncthreads();
-                if (a.tape) {
-                    double* tp = a.tape + (size_t)(it * nhalf + jh + c + 1) * 2 * n;
-                    for (int i = threadIdx.x; i < npx; i += NT) {
-                        tp[i] = sm.du[i];
-                        tp[n + i] = sm.dv[i];
-                    }
-                    __syncthreads();   // the next half sweep rewrites what was just copied
-                }
             }
         }
         // (the next step's first reads follow the last half sweep's barrier)

@@ -16,9 +16,9 @@ counter scaled by what it reads for the run's plain device copy of M MiB
 ``traffic:`` line that bench.py matches against the kernel family, the
 refinement tile, the launch mode and the hash of the kernel sources.
 
-Only dispatches after the last persistent-level or single-workgroup launch
-are used (``--after``): the autotuner's trials run first, then the timed
-launches with the tuned choices.
+Every dispatch of the run is used; ``--after REGEX`` keeps only those after
+the last dispatch whose kernel name matches (for a run whose autotuner
+trials precede the timed launches; bench.py with ``--tunables`` has none).
 """
 from __future__ import annotations
 
@@ -32,7 +32,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/dis_kernels.hip", "csrc/dis_refine_tile.h", "csrc/dis_internal.h")
-AFTER_DEFAULT = r"k_level<|k_small_level<"
+AFTER_DEFAULT = ""
 
 
 def source_hash() -> str:
@@ -50,6 +50,8 @@ def family(name: str) -> str:
 
 
 def _after(rows, pattern):
+    if not pattern:
+        return rows
     idx = [i for i, r in enumerate(rows) if re.search(pattern, r["Kernel_Name"])]
     return rows[(max(idx) + 1) if idx else 0:]
 

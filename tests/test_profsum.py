@@ -19,8 +19,8 @@ def _csv(d, rows):
 
 def test_traffic_record_scales_by_the_copy_probe(tmp_path):
     """Counters scaled so that the copy probe reads back its own size:
-    FETCH 2x, WRITE 1x here; only launches after the last persistent-level
-    launch count."""
+    FETCH 2x, WRITE 1x here; with the filter, only launches after the last
+    persistent-level launch count."""
     copy = 4 * 1024  # KiB of a 4 MiB copy
     f = [("__amd_rocclr_copyBuffer", "FETCH_SIZE", copy / 2)] * 5 + [
         ("k_level<8, 16>(LevelLaunch)", "FETCH_SIZE", 999.0),
@@ -32,7 +32,8 @@ def test_traffic_record_scales_by_the_copy_probe(tmp_path):
         ("k_phase_refine<8, 8, 512, false>(PhaseLaunch)", "WRITE_SIZE", 30.0)]
     _csv(str(tmp_path / "f"), f)
     _csv(str(tmp_path / "w"), w)
-    line, rec = profsum.traffic_record(str(tmp_path / "f"), str(tmp_path / "w"), "k_phase_refine<", 4, 7, 1)
+    line, rec = profsum.traffic_record(str(tmp_path / "f"), str(tmp_path / "w"), "k_phase_refine<", 4, 7, 1,
+                                       after=r"k_level<")
     assert rec["launches"] == 2 and rec["tile"] == 7 and rec["mode"] == 1
     assert abs(rec["fetch_bytes_per_launch"] - 2 * 200.0 * 1024) < 1e-6
     assert abs(rec["write_bytes_per_launch"] - 20.0 * 1024) < 1e-6
@@ -42,7 +43,10 @@ def test_traffic_record_scales_by_the_copy_probe(tmp_path):
     assert back["tile"] == 7 and back["mode"] == 1 and abs(back["bytes_per_launch"] - rec["bytes_per_launch"]) < 1.0
     assert back["source_sha"] == profsum.source_hash()
     table = profsum.util_table(str(tmp_path / "f"))
-    assert "`k_phase_refine<8, 8, 512, false>` | 2 | 200 |" in table
+    assert "`k_phase_refine<8, 8, 512, false>` | 2 | 200 |" in table and "`k_level<8, 16>` | 1 |" in table
+    # without the filter the persistent launch counts too
+    _, rec_all = profsum.traffic_record(str(tmp_path / "f"), str(tmp_path / "w"), "k_phase_refine<|k_level<", 4, 7, 1)
+    assert rec_all["launches"] == 3
 
 
 def test_committed_traffic_record_parses():
