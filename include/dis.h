@@ -192,7 +192,8 @@ int dis_autotune(dis_handle* h, const char* cache_path);
  * Set the launch choices that do not change results (for tests and the
  * autotuner): lanes_per_patch[s] (HOST array of 16, or NULL = automatic for
  * every scale) is the number of lanes sharing one patch in the search on
- * scale s (0 = automatic, else 4, 8 or 16 where compiled for the patch size);
+ * scale s (0 = automatic, else 4, 8, 16, 32 or 64 where compiled for the patch
+ * size);
  * refine_tile picks the refinement tile (core width x height, threads) of the
  * per-phase launches: 0: 32x16/256, 1: 16x16/256, 2: 64x8/256,
  * 3: 16x16/1024, 4: 32x16/1024, 5: 16x16/512, 6: 32x16/512, 7: 8x8/512,

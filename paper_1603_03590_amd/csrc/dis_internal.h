@@ -243,7 +243,8 @@ const void* dis_kernel_fb_scan();                      // FbLaunch, grid (1, 2),
 const void* dis_kernel_fb_scatter();                   // FbLaunch, grid (patch blocks, 2)
 const void* dis_kernel_fb_densify();                   // FbLaunch, grid (W/64, H/4, 2)
 const void* dis_kernel_colour_lin();                   // LevelLaunch of one pair, grid of the densification
-const void* dis_kernel_phase_search_colour(int ps);    // 3 channels, 16 lanes per patch; null when not compiled
+const void* dis_kernel_phase_search_colour(int ps);    // 3 channels; null when not compiled
+int dis_colour_lanes(int ps);                          // its lanes per patch
 const void* dis_kernel_level(int ps, int lpp);          // persistent level kernel, null when not compiled
 // refinement core tile (width, height, threads per block) of a tile id;
 // returns 0 for an unknown id

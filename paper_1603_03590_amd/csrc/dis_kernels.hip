@@ -148,13 +148,15 @@ __global__ __launch_bounds__(256) void k_pyramid_tab(const PyrTab T) {
 
 // ------------------------------------------------------------------ search
 
-// Canonical patch sums.  A patch's pixels p = 0..PS*PS-1 form 16 groups of
-// GS = ceil(PS*PS/16) consecutive pixels; a group is summed sequentially
-// (fma for products), then the 16 group sums pairwise in a fixed binary tree.
-// A lane holds GPL = 16/LPP consecutive groups; the tree levels inside a lane
-// are done in registers, the rest across the LPP lanes of the patch with DPP
-// moves that pair each block of lanes with the neighbouring block (every lane
-// of a block holds the block's sum by then, so the pairing is the tree's).
+// Canonical patch sums.  A patch's pixels p = 0..PS*PS-1 form NG groups of
+// GS = ceil(PS*PS/NG) consecutive pixels (NG = 64 from 8x8 patches up, 16
+// below; trailing groups may be empty); a group is summed sequentially (fma
+// for products), then the NG group sums pairwise in a fixed binary tree.  A
+// lane holds GPL = NG/LPP consecutive groups; the tree levels inside a lane are done in registers, the rest
+// across the LPP lanes of the patch, pairing each block of lanes with the
+// neighbouring block (every lane of a block holds the block's sum by then, so
+// the pairing is the tree's): DPP moves within a row of 16 lanes, lane
+// shuffles across rows.  Every LPP therefore gives the same bits.
 template <int GS, int GPL, int LPP>
 __device__ __forceinline__ double tree_finish(double (&g)[GPL]) {
 #pragma unroll
@@ -166,6 +168,8 @@ __device__ __forceinline__ double tree_finish(double (&g)[GPL]) {
     if (LPP >= 4) s = s + dpp_mov<0x4E>(s);    // quad_perm [2,3,0,1]
     if (LPP >= 8) s = s + dpp_mov<0x141>(s);   // row_half_mirror
     if (LPP >= 16) s = s + dpp_mov<0x140>(s);  // row_mirror
+    if (LPP >= 32) s = s + __shfl_xor(s, 16);   // the other row of the half wave
+    if (LPP >= 64) s = s + __shfl_xor(s, 32);   // the other half wave
     return s;
 }
 
@@ -221,8 +225,10 @@ struct SearchWin {
 template <int PS, int LPP, int NC = 1>
 __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
     constexpr int NP = PS * PS;
-    constexpr int GS = (NP + 15) / 16;
-    constexpr int GPL = 16 / LPP;
+    constexpr int NG = NP >= 64 ? 64 : 16;
+    static_assert(LPP <= NG, "more lanes than groups");
+    constexpr int GS = (NP + NG - 1) / NG;
+    constexpr int GPL = NG / LPP;
     constexpr int PPL = GS * GPL;
     const int W = a.W, H = a.H;
     const size_t n = (size_t)W * H;
@@ -1279,23 +1285,26 @@ const void* dis_kernel_fb_scatter() { return (const void*)&k_fb_scatter; }
 const void* dis_kernel_fb_densify() { return (const void*)&k_fb_densify; }
 const void* dis_kernel_colour_lin() { return (const void*)&k_colour_lin; }
 
-// colour search instances: 16 lanes per patch keep the three channels'
-// per-lane pixel arrays within the register file
+// colour search instances: 32 lanes per patch (16 below 8x8 patches) keep
+// the three channels' per-lane pixel arrays within the register file
+int dis_colour_lanes(int ps) { return ps < 8 ? 16 : 32; }
+
 const void* dis_kernel_phase_search_colour(int ps) {
     switch (ps) {
         case 4: return (const void*)&k_phase_search<4, 16, 3>;
         case 6: return (const void*)&k_phase_search<6, 16, 3>;
-        case 8: return (const void*)&k_phase_search<8, 16, 3>;
-        case 10: return (const void*)&k_phase_search<10, 16, 3>;
-        case 12: return (const void*)&k_phase_search<12, 16, 3>;
+        case 8: return (const void*)&k_phase_search<8, 32, 3>;
+        case 10: return (const void*)&k_phase_search<10, 32, 3>;
+        case 12: return (const void*)&k_phase_search<12, 32, 3>;
         default: return nullptr;
     }
 }
 
 // instances whose per-lane pixel arrays fit the 256 architectural VGPRs
 #define DIS_FOR_SEARCH_INSTANCES(X) \
-    X(4, 4) X(4, 8) X(4, 16) X(6, 4) X(6, 8) X(6, 16) X(8, 4) X(8, 8) X(8, 16) \
-    X(10, 8) X(10, 16) X(12, 8) X(12, 16) X(14, 16) X(16, 16)
+    X(4, 4) X(4, 8) X(4, 16) X(6, 4) X(6, 8) X(6, 16) X(8, 4) X(8, 8) X(8, 16) X(8, 32) X(8, 64) \
+    X(10, 8) X(10, 16) X(10, 32) X(10, 64) X(12, 8) X(12, 16) X(12, 32) X(12, 64) X(14, 16) X(14, 32) \
+    X(14, 64) X(16, 16) X(16, 32) X(16, 64)
 
 #define DIS_SEARCH_CASE(PS_, LPP_) \
     if (ps == PS_ && lpp == LPP_) return (const void*)&k_phase_search<PS_, LPP_>;

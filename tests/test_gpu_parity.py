@@ -196,6 +196,8 @@ def test_launch_choices_are_bitwise_invariant(case):
         t1 = torch.from_numpy(pr.I1).cuda()
         outs = []
         choices = [(None, 0, 0), ([4] * 16, 0, 0), ([8] * 16, 0, 0), (None, 0, 1)]
+        # 32 and 64 lanes per patch (the reduction tree crosses rows of the wave)
+        choices += [([32] * 16, 0, 1), ([64] * 16, 7, 1), ([64] * 16, 0, 0)]
         # every refinement tile shape / block size, with varied lanes per patch
         choices += [([[4, 8, 16][t % 3]] * 16, t, 1) for t in range(1, N_TILES)]
         # with the single-workgroup scales (launch mode bit 1)
@@ -314,3 +316,19 @@ def test_colour_refusals_and_padded_rows():
         assert e.value.code == _lib.DIS_EINVAL
     finally:
         d.close()
+
+
+def test_high_quality_c3a_full_size_parity():
+    """The high-quality configuration at full size (1024x436, motion up to
+    200 px, patch 12, overlap 0.75, 128 GN iterations, scales 4..0): the
+    long Gauss-Newton chains amplify rounding the most.  The oracle takes
+    about half a minute here."""
+    say("[parity] case c3a_layered_1024x436_full (oracle ~30-50 s)")
+    pr = pair("layered", 1024, 436, 200.0, 3)
+    p = params(104)
+    U_ref, _ = oracle_flow("c3a_full", pr.I0, pr.I1, oracle_params(p))
+    U = gpu_flow(pr.I0, pr.I1, p)
+    frac, erel, dmax = parity(U, U_ref, pr.flow)
+    say(f"[parity] c3a full: within 1e-2 px {frac:.6f}, mean EPE rel diff {erel:.2e}, max diff {dmax:.2e}")
+    assert frac >= PARITY_FRAC
+    assert erel <= PARITY_EPE_REL
