@@ -664,7 +664,9 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
 // derivative) is stored for pass 2, and the residual adjoints of the
 // covering patches go to J0 (a gather: plain add) and to J1's bilinear taps
 // (atomics, spread over the frame).
-__device__ __forceinline__ int bwd_cover(int x, int n, int ps, int st, int nr, int& k0) {
+// Covering patches of coordinate x along one axis: first index k0 (returned
+// through the reference) and last regular index (the flush patch is extra).
+__device__ __forceinline__ int bwd_cover(int x, int ps, int st, int nr, int& k0) {
     const int lo = x - ps + 1;
     k0 = lo <= 0 ? 0 : (lo + st - 1) / st;
     return min(x / st, nr - 1);
@@ -694,7 +696,7 @@ __global__ __launch_bounds__(256) void k_bwd_densify(const DensBwdArgs a) {
     const double j0 = a.J0[g];
     const int ps = a.ps, st = a.st;
     int kx0, ky0;
-    const int kx1 = bwd_cover(x, W, ps, st, a.nrx, kx0), ky1 = bwd_cover(y, H, ps, st, a.nry, ky0);
+    const int kx1 = bwd_cover(x, ps, st, a.nrx, kx0), ky1 = bwd_cover(y, ps, st, a.nry, ky0);
     const bool fx = (a.nx > a.nrx) && (x >= W - ps), fy = (a.ny > a.nry) && (y >= H - ps);
     const int kyend = ky1 + (fy ? 1 : 0), kxend = kx1 + (fx ? 1 : 0);
     double gj0 = 0.0;

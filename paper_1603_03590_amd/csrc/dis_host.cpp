@@ -368,12 +368,11 @@ void Seq::add(const void* fn, dim3 grid, dim3 block, const void* arg, size_t byt
     items.push_back(std::move(L));
 }
 
-int dis_pick_lpp(const dis_handle* h, int s, int N) {
+int dis_pick_lpp(const dis_handle* h, int s) {
     const int ps = h->p.patch_size;
     if (h->lpp[s] && dis_kernel_phase_search(ps, h->lpp[s])) return h->lpp[s];
     // the most lanes compiled for the patch size: the shortest dependent chain
     // per patch pays at every size measured (the autotuner tries the others)
-    (void)N;
     for (int l = 64; l > 16; l >>= 1)
         if (dis_kernel_phase_search(ps, l)) return l;
     return 16;
@@ -554,13 +553,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         dis_refine_phases(p, s, LH.rph);
         if (!p.refine) LH.rph.clear();
         LH.nph = 2 + (int)LH.rph.size();
-        long long totN = 0;
-        for (const PairRef& r : pairs) {
-            if (r.ss < s) continue;
-            LevelGrid g;
-            totN += dis_level_grid(h, r.w >> s, r.h >> s, &g);
-        }
-        LH.lpp = nc > 1 ? dis_colour_lanes(ps) : dis_pick_lpp(h, s, (int)std::min<long long>(totN, 1 << 30));
+        LH.lpp = nc > 1 ? dis_colour_lanes(ps) : dis_pick_lpp(h, s);
         LH.by[0] = LH.by[1] = LH.fl[0] = LH.fl[1] = 0.0;
         for (const PairRef& r : pairs) {
             if (r.ss < s) continue;

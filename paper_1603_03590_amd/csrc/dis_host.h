@@ -161,7 +161,7 @@ int dis_stride(const dis_params* p);
 inline int dis_channels(const dis_params* p) { return (p->flags & DIS_FLAG_COLOUR) ? 3 : 1; }
 int dis_coarsest(const dis_params* p, int w, int h);
 void dis_grid(int n, int ps, int st, int* nr, int* ntot);
-int dis_pick_lpp(const dis_handle* h, int s, int N);
+int dis_pick_lpp(const dis_handle* h, int s);
 int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const void* I0, const void* I1,
                    void* flow, Seq& seq, PairInfo* info, PlanTables& tabs);
 // Options of dis_build_levels for the backward pass's recomputation.
