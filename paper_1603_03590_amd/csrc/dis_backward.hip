@@ -522,18 +522,27 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
         for (int q = 0; q < 9; ++q) sm.acc[q][yy * TW + xx] = A.acc_load ? A.acc[q * n + gi] : 0.0;
     }
     // the tape state before a half sweep, region-wide, through registers so
-    // that the next one is in flight while the current one is reversed
+    // that the next one is in flight while the current one is reversed.  The
+    // state before half sweep j differs from the one before j + 1 only at the
+    // pixels half sweep j updated (colour j & 1), so after the first, full
+    // state only those are fetched and replaced (colour: 0, 1, or -1 = all)
     double* st_u = sm.f.u.inc.du;
     double* st_v = sm.f.u.inc.dv;
     double pu[NE], pv[NE];
-    auto fetch = [&](int j) {
+    auto in_set = [&](int i, int colour) {
+        if (i >= RW * RH) return false;
+        if (colour < 0) return true;
+        const int ly = i / RW, lx = i - ly * RW;
+        return ((rx0 + lx + ry0 + ly) & 1) == colour;
+    };
+    auto fetch = [&](int j, int colour) {
         const int m = A.m0 + j;
         const double* tp = m ? A.tape + (size_t)m * 2 * n : nullptr;
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
             const int i = threadIdx.x + e * NT;
             pu[e] = pv[e] = 0.0;
-            if (tp && i < RW * RH) {
+            if (tp && in_set(i, colour)) {
                 const int ly = i / RW, lx = i - ly * RW;
                 const size_t gi = (size_t)(ry0 + ly) * W + rx0 + lx;
                 pu[e] = tp[gi];
@@ -541,11 +550,11 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
             }
         }
     };
-    auto stash = [&]() {
+    auto stash = [&](int colour) {
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
             const int i = threadIdx.x + e * NT;
-            if (i < RW * RH) {
+            if (in_set(i, colour)) {
                 const int ly = i / RW, lx = i - ly * RW;
                 st_u[ly * LP + lx] = pu[e];
                 st_v[ly * LP + lx] = pv[e];
@@ -553,14 +562,14 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
         }
     };
     const int jhi = __builtin_amdgcn_readfirstlane(A.j_hi), jlo = __builtin_amdgcn_readfirstlane(A.j_lo);
-    fetch(jhi - 1);
-    stash();
+    fetch(jhi - 1, -1);
+    stash(-1);
     __syncthreads();
     // one reverse half sweep; the colour is a template constant so that the
     // per-pixel coefficient arrays stay in registers
     auto reverse = [&](auto colour, int j) {
         constexpr int c = decltype(colour)::value;   // the colour half sweep j updated
-        if (j > jlo) fetch(j - 1);
+        if (j > jlo) fetch(j - 1, c ^ 1);             // half sweep j - 1 updated the other colour
         // (a) pixels of colour c: replay the update, then its adjoint
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -620,7 +629,7 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
             sm.gu[l] += su;
             sm.gv[l] += sv;
         }
-        if (j > jlo) stash();
+        if (j > jlo) stash(c ^ 1);
         __syncthreads();
     };
     for (int j = jhi - 1; j >= jlo; --j) {
