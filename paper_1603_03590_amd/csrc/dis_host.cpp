@@ -719,6 +719,12 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         LL.ntasks = t;
         // the adjoint's reverse tiles read the cache the recomputation fills
         LL.lin_cache = (opt || !h->no_lin_cache) ? 1 : 0;
+        if (np == 1) {
+            LL.one = 1;
+            LL.sa1 = LH.lp[0].sa;
+            LL.da1 = LH.lp[0].da;
+            LL.dens_bx1 = LH.lp[0].dens_bx;
+        }
         if (mode == 0) {
             const void* fn = dis_kernel_level(ps, LH.lpp);
             if (!fn) return fail(h, DIS_EINVAL, "no level kernel for patch %d, %d lanes", ps, LH.lpp);
@@ -775,6 +781,20 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
                     std::memset(&PL, 0, sizeof PL);
                     PL.L = LL;
                     PL.phase = ph;
+                    if (LL.one) {
+                        // the buffers of this phase, as the kernel resolves them from the tables
+                        const LevelPair& P = LH.lp[0];
+                        const RefPhase& rp = LH.rph[ph - 2];
+                        RefineArgs& ra = PL.ra1;
+                        ra = P.ra;
+                        ra.dUf = rp.f < 0 ? nullptr : P.dU[rp.f];
+                        ra.dUin = rp.in < 0 ? nullptr : P.dU[rp.in];
+                        ra.dUout = P.dU[rp.out];
+                        ra.Uout = rp.last ? P.ra.Uout : nullptr;
+                        ra.nhalf = rp.nhalf;
+                        ra.tape_m0 = rp.m0;
+                        ra.lin_mode = nc > 1 ? 3 : (LL.lin_cache ? (rp.m0 == 0 ? 1 : 2) : 0);
+                    }
                     seq.add(nc > 1 ? dis_kernel_phase_refine_colour(tile_id) : dis_kernel_phase_refine(tile_id), dim3(n),
                             dim3(nt), &PL, sizeof PL, 0, "refine",
                             ph_by[ph], ph_fl[ph]);
@@ -789,7 +809,14 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             SL.n = (int)LH.small.size();
             SL.nouter = p.var_outer < 0 ? LH.s + 1 : p.var_outer;
             SL.nhalf = 2 * p.var_inner;
-            seq.add(dis_kernel_small_level(), dim3(SL.n), dim3(DIS_SMALL_THREADS), &SL, sizeof SL, 0, "small_level", LH.sby,
+            if (np == 1) {
+                SL.da1 = LH.lp[0].da;
+                SL.ra1 = LH.lp[0].ra;
+            }
+            int maxp = 0;
+            for (int q : LH.small) maxp = std::max(maxp, (LH.lp[q].ra.W + 1) / 2 * LH.lp[q].ra.H);
+            const int snt = maxp <= DIS_SMALL_PAIRS / 4 ? 512 : 1024;
+            seq.add(dis_kernel_small_level(snt, np == 1), dim3(SL.n), dim3(snt), &SL, sizeof SL, 0, "small_level", LH.sby,
                     LH.sfl);
         }
     }

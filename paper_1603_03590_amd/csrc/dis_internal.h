@@ -136,12 +136,21 @@ struct LevelLaunch {
     int* sync;              // [0] queue head, [1] wait-timeout flag, [2 + seg] finished tasks
     int npairs, nph, ntasks;
     int lin_cache;          // 1: a level's first refinement launch stores the linearisation, later ones load it
+    // With one pair its arguments also travel in the launch itself: a
+    // phase-major block then starts on its data at once, instead of after
+    // a chain of dependent table reads (start, task_seg, pairs), each a
+    // round trip to memory at the start of every launch.
+    int one;                // 1: npairs == 1 and the fields below are set
+    int dens_bx1;
+    SearchArgs sa1;
+    DensifyArgs da1;
 };
 
 // A phase-major refinement launch: phase `phase` of every pair of L.
 struct PhaseLaunch {
     LevelLaunch L;
     int phase;
+    RefineArgs ra1;         // L.one: the pair's arguments with this phase's buffers resolved
 };
 
 // Pair-levels small enough for one workgroup's LDS (at most DIS_SMALL_PAIRS
@@ -149,13 +158,14 @@ struct PhaseLaunch {
 // level in one block, without tiles.  Block b handles pairs[list[b]].
 #define DIS_SMALL_PAIRS 1024
 #define DIS_SMALL_PX 2112      // LDS plane capacity (pixels) of that block
-#define DIS_SMALL_THREADS 1024 // threads of that block (one pixel pair each)
 struct SmallLaunch {
     const LevelPair* pairs;
     const int* list;
     int n;
     int nouter;             // fixed-point steps of the level
     int nhalf;              // red-black half sweeps per step
+    DensifyArgs da1;        // one pair (a single block): its arguments, read in place
+    RefineArgs ra1;
 };
 
 // Forward-backward consistent densification (App. B ii): the two
@@ -237,7 +247,7 @@ const void* dis_kernel_phase_densify();
 const void* dis_kernel_phase_refine(int tile);          // tile id, see dis_refine_tile
 const void* dis_kernel_phase_refine_colour(int tile);   // colour frames (lin_mode 3)
 const void* dis_kernel_phase_densify_colour();
-const void* dis_kernel_small_level();                  // SmallLaunch, DIS_SMALL_THREADS threads
+const void* dis_kernel_small_level(int threads, bool one);   // SmallLaunch; 512 (<= 256 pairs) or 1024 threads
 const void* dis_kernel_fb_count();                     // FbLaunch, grid (patch blocks, 2)
 const void* dis_kernel_fb_scan();                      // FbLaunch, grid (1, 2), 1024 threads
 const void* dis_kernel_fb_scatter();                   // FbLaunch, grid (patch blocks, 2)

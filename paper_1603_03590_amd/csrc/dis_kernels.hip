@@ -902,43 +902,67 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
 template <int PS, int LPP, int NC = 1>
 __global__ __launch_bounds__(256) void k_phase_search(const LevelLaunch L) {
     const int t = blockIdx.x;                       // phase 0 starts at task 0
-    const int j = __builtin_amdgcn_readfirstlane(L.task_seg[t]);
-    search_block<PS, LPP, NC>(L.pairs[j].sa, t - __builtin_amdgcn_readfirstlane(L.start[j]));
+    SearchArgs sa;
+    int local = t;
+    if (L.one) {
+        sa = L.sa1;
+    } else {
+        const int j = __builtin_amdgcn_readfirstlane(L.task_seg[t]);
+        sa = L.pairs[j].sa;
+        local = t - __builtin_amdgcn_readfirstlane(L.start[j]);
+    }
+    search_block<PS, LPP, NC>(sa, local);
 }
 
 template <bool COLOUR = false>
 __global__ __launch_bounds__(256) void k_phase_densify(const LevelLaunch L) {
-    const int np = L.npairs;
-    const int t = __builtin_amdgcn_readfirstlane(L.start[np]) + blockIdx.x;
-    const int j = __builtin_amdgcn_readfirstlane(L.task_seg[t]) - np;
-    const LevelPair& P = L.pairs[j];
-    const int local = t - __builtin_amdgcn_readfirstlane(L.start[np + j]);
-    densify_block<COLOUR>(P.da, local % P.dens_bx, local / P.dens_bx);
+    DensifyArgs da;
+    int local = blockIdx.x, bx;
+    if (L.one) {
+        da = L.da1;
+        bx = L.dens_bx1;
+    } else {
+        const int np = L.npairs;
+        const int t = __builtin_amdgcn_readfirstlane(L.start[np]) + blockIdx.x;
+        const int j = __builtin_amdgcn_readfirstlane(L.task_seg[t]) - np;
+        const LevelPair& P = L.pairs[j];
+        da = P.da;
+        bx = P.dens_bx;
+        local = t - __builtin_amdgcn_readfirstlane(L.start[np + j]);
+    }
+    densify_block<COLOUR>(da, local % bx, local / bx);
 }
 
 template <int TW, int TH, int NT, bool COLOUR = false>
 __global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
     __shared__ RefineSmem<TW, TH> sm;
     const LevelLaunch& L = PL.L;
-    const int phase = PL.phase;
-    const int np = L.npairs, s0 = phase * np;
-    const int t = __builtin_amdgcn_readfirstlane(L.start[s0]) + dis_xcd_tile(blockIdx.x, gridDim.x);
-    const int j = __builtin_amdgcn_readfirstlane(L.task_seg[t]) - s0;
-    const LevelPair& P = L.pairs[j];
-    const RefPhase rp = L.rph[phase - 2];
-    RefineArgs ra = P.ra;
-    ra.dUf = rp.f < 0 ? nullptr : P.dU[rp.f];
-    ra.dUin = rp.in < 0 ? nullptr : P.dU[rp.in];
-    ra.dUout = P.dU[rp.out];
-    ra.Uout = rp.last ? P.ra.Uout : nullptr;
-    ra.nhalf = rp.nhalf;
-    ra.tape_m0 = rp.m0;
-    // the level's first launch fills the linearisation cache; colour frames
-    // read the per-channel linearisation of k_colour_lin
-    ra.lin_mode = COLOUR ? 3 : (L.lin_cache ? (rp.m0 == 0 ? 1 : 2) : 0);
-    const int t0 = __builtin_amdgcn_readfirstlane(L.start[s0 + j]);
-    const int nt = __builtin_amdgcn_readfirstlane(L.start[s0 + j + 1]) - t0;
-    refine_tile<TW, TH, NT, COLOUR>(ra, dis_band_tile(t - t0, ra.tiles_x, nt), sm);
+    RefineArgs ra;
+    int q = dis_xcd_tile(blockIdx.x, gridDim.x), nt = gridDim.x;   // the pair's tiles, in launch order
+    if (L.one) {
+        ra = PL.ra1;
+    } else {
+        const int phase = PL.phase;
+        const int np = L.npairs, s0 = phase * np;
+        const int t = __builtin_amdgcn_readfirstlane(L.start[s0]) + q;
+        const int j = __builtin_amdgcn_readfirstlane(L.task_seg[t]) - s0;
+        const LevelPair& P = L.pairs[j];
+        const RefPhase rp = L.rph[phase - 2];
+        ra = P.ra;
+        ra.dUf = rp.f < 0 ? nullptr : P.dU[rp.f];
+        ra.dUin = rp.in < 0 ? nullptr : P.dU[rp.in];
+        ra.dUout = P.dU[rp.out];
+        ra.Uout = rp.last ? P.ra.Uout : nullptr;
+        ra.nhalf = rp.nhalf;
+        ra.tape_m0 = rp.m0;
+        // the level's first launch fills the linearisation cache; colour
+        // frames read the per-channel linearisation of k_colour_lin
+        ra.lin_mode = COLOUR ? 3 : (L.lin_cache ? (rp.m0 == 0 ? 1 : 2) : 0);
+        const int t0 = __builtin_amdgcn_readfirstlane(L.start[s0 + j]);
+        nt = __builtin_amdgcn_readfirstlane(L.start[s0 + j + 1]) - t0;
+        q = t - t0;
+    }
+    refine_tile<TW, TH, NT, COLOUR>(ra, dis_band_tile(q, ra.tiles_x, nt), sm);
 }
 
 // ----------------------------------------------------------------- upscale
@@ -1029,13 +1053,9 @@ struct SmallSmem {
 };
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_small_level(const SmallLaunch S) {
+__device__ __forceinline__ void small_level(const DensifyArgs& da, const RefineArgs& a, int nouter_, int nhalf_,
+                                            SmallSmem& sm) {
     constexpr int PPT = DIS_SMALL_PAIRS / NT;
-    __shared__ SmallSmem sm;
-    const int j = __builtin_amdgcn_readfirstlane(S.list[blockIdx.x]);
-    const LevelPair& P = S.pairs[j];
-    const DensifyArgs& da = P.da;
-    const RefineArgs& a = P.ra;
     const int W = a.W, H = a.H;
     const int npx = W * H;
     const size_t n = (size_t)npx;
@@ -1075,8 +1095,8 @@ __global__ __launch_bounds__(NT) void k_small_level(const SmallLaunch S) {
     }
     const double om = a.omega, om1 = 1.0 - a.omega;
     const double eps2 = a.eps * a.eps;
-    const int nouter = __builtin_amdgcn_readfirstlane(S.nouter);
-    const int nhalf = __builtin_amdgcn_readfirstlane(S.nhalf);
+    const int nouter = __builtin_amdgcn_readfirstlane(nouter_);
+    const int nhalf = __builtin_amdgcn_readfirstlane(nhalf_);
     auto Ib = [&](int x, int y) { const int l = y * W + x; return 0.5 * (sm.J0[l] + sm.J1w[l]); };
     auto Ixa = [&](int x, int y) { return (Ib(min(x + 1, W - 1), y) - Ib(max(x - 1, 0), y)) / 2.0; };
     auto Iya = [&](int x, int y) { return (Ib(x, min(y + 1, H - 1)) - Ib(x, max(y - 1, 0))) / 2.0; };
@@ -1229,6 +1249,21 @@ __global__ __launch_bounds__(NT) void k_small_level(const SmallLaunch S) {
     }
 }
 
+// ONE: a single pair, whose arguments the launch carries (read in place);
+// else block b takes pairs[list[b]].  512 threads serve levels of at most
+// 256 pixel pairs (two pairs per thread in the loops, half of them empty),
+// 1024 threads the rest; the narrower block has twice the registers.
+template <int NT, bool ONE>
+__global__ __launch_bounds__(NT) void k_small_level(const SmallLaunch S) {
+    __shared__ SmallSmem sm;
+    if constexpr (ONE) {
+        small_level<NT>(S.da1, S.ra1, S.nouter, S.nhalf, sm);
+    } else {
+        const LevelPair& P = S.pairs[__builtin_amdgcn_readfirstlane(S.list[blockIdx.x])];
+        small_level<NT>(P.da, P.ra, S.nouter, S.nhalf, sm);
+    }
+}
+
 // Queue operations of thread 0.  They are kept out of line on purpose: the
 // level kernel's loop holds barriers, and with these thread-0 branches
 // inlined at the loop's edges the compiler's control-flow structurisation
@@ -1319,7 +1354,11 @@ const void* dis_kernel_upsample() { return (const void*)&k_upsample; }
 const void* dis_kernel_upsample_tab() { return (const void*)&k_upsample_tab; }
 const void* dis_kernel_phase_densify() { return (const void*)&k_phase_densify<false>; }
 const void* dis_kernel_phase_densify_colour() { return (const void*)&k_phase_densify<true>; }
-const void* dis_kernel_small_level() { return (const void*)&k_small_level<DIS_SMALL_THREADS>; }
+const void* dis_kernel_small_level(int threads, bool one) {
+    if (threads == 512) return one ? (const void*)&k_small_level<512, true> : (const void*)&k_small_level<512, false>;
+    if (threads == 1024) return one ? (const void*)&k_small_level<1024, true> : (const void*)&k_small_level<1024, false>;
+    return nullptr;
+}
 const void* dis_kernel_fb_count() { return (const void*)&k_fb_count; }
 const void* dis_kernel_fb_scan() { return (const void*)&k_fb_scan; }
 const void* dis_kernel_fb_scatter() { return (const void*)&k_fb_scatter; }
