@@ -815,7 +815,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             }
             int maxp = 0;
             for (int q : LH.small) maxp = std::max(maxp, (LH.lp[q].ra.W + 1) / 2 * LH.lp[q].ra.H);
-            const int snt = maxp <= DIS_SMALL_PAIRS / 4 ? 512 : 1024;
+            const int snt = maxp <= 512 ? 512 : 1024;   // one pixel pair per thread
             seq.add(dis_kernel_small_level(snt, np == 1), dim3(SL.n), dim3(snt), &SL, sizeof SL, 0, "small_level", LH.sby,
                     LH.sfl);
         }

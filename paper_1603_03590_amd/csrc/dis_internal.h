@@ -247,7 +247,7 @@ const void* dis_kernel_phase_densify();
 const void* dis_kernel_phase_refine(int tile);          // tile id, see dis_refine_tile
 const void* dis_kernel_phase_refine_colour(int tile);   // colour frames (lin_mode 3)
 const void* dis_kernel_phase_densify_colour();
-const void* dis_kernel_small_level(int threads, bool one);   // SmallLaunch; 512 (<= 256 pairs) or 1024 threads
+const void* dis_kernel_small_level(int threads, bool one);   // SmallLaunch; 512 (<= 512 pairs) or 1024 threads
 const void* dis_kernel_fb_count();                     // FbLaunch, grid (patch blocks, 2)
 const void* dis_kernel_fb_scan();                      // FbLaunch, grid (1, 2), 1024 threads
 const void* dis_kernel_fb_scatter();                   // FbLaunch, grid (patch blocks, 2)

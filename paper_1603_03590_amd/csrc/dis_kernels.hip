@@ -1052,10 +1052,14 @@ struct SmallSmem {
     double wr[DIS_SMALL_PX], wd[DIS_SMALL_PX];
 };
 
-template <int NT>
+template <int NT, int PPT>
 __device__ __forceinline__ void small_level(const DensifyArgs& da, const RefineArgs& a, int nouter_, int nhalf_,
                                             SmallSmem& sm) {
-    constexpr int PPT = DIS_SMALL_PAIRS / NT;
+    // J0 and the warped J1 stay fixed for the whole level, so with one pair
+    // per thread and registers to spare the linearisation of the owned
+    // pixels (derivatives and their normalisations, Sec. 2.3) is computed
+    // once, before the fixed-point steps
+    constexpr bool kLinReg = PPT == 1 && NT <= 512;
     const int W = a.W, H = a.H;
     const int npx = W * H;
     const size_t n = (size_t)npx;
@@ -1100,6 +1104,44 @@ __device__ __forceinline__ void small_level(const DensifyArgs& da, const RefineA
     auto Ib = [&](int x, int y) { const int l = y * W + x; return 0.5 * (sm.J0[l] + sm.J1w[l]); };
     auto Ixa = [&](int x, int y) { return (Ib(min(x + 1, W - 1), y) - Ib(max(x - 1, 0), y)) / 2.0; };
     auto Iya = [&](int x, int y) { return (Ib(x, min(y + 1, H - 1)) - Ib(x, max(y - 1, 0))) / 2.0; };
+    // Ix, Iy, Iz, Ixx, Ixy, Iyy, Ixz, Iyz, b0, bx, by of pixel l = (x, y)
+    auto linearise = [&](int l, int x, int y, double (&q)[11]) {
+        const int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
+        const int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
+        const double* t0 = sm.J0;
+        const double* t1 = sm.J1w;
+        const double Ix = Ixa(x, y), Iy = Iya(x, y);
+        const double Ixx = (Ixa(xp, y) - Ixa(xm, y)) / 2.0;
+        const double Ixy = (Ixa(x, yp) - Ixa(x, ym)) / 2.0;
+        const double Iyy = (Iya(x, yp) - Iya(x, ym)) / 2.0;
+        const int lxp = y * W + xp, lxm = y * W + xm, lyp = yp * W + x, lym = ym * W + x;
+        q[0] = Ix;
+        q[1] = Iy;
+        q[2] = t1[l] - t0[l];
+        q[3] = Ixx;
+        q[4] = Ixy;
+        q[5] = Iyy;
+        q[6] = (t1[lxp] - t1[lxm]) / 2.0 - (t0[lxp] - t0[lxm]) / 2.0;
+        q[7] = (t1[lyp] - t1[lym]) / 2.0 - (t0[lyp] - t0[lym]) / 2.0;
+        q[8] = 1.0 / ((Ix * Ix + Iy * Iy) + 0.01);
+        q[9] = 1.0 / ((Ixx * Ixx + Ixy * Ixy) + 0.01);
+        q[10] = 1.0 / ((Ixy * Ixy + Iyy * Iyy) + 0.01);
+    };
+    double r_u[PPT][2], r_v[PPT][2];   // the owned increments (zero at the start of the level)
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) r_u[k][c] = r_v[k][c] = 0.0;
+    double lin_r[kLinReg ? 2 : 1][11];
+    if constexpr (kLinReg) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int l = c_l[0][c];
+            if (l < 0) continue;
+            const int y = l / W, x = l - y * W;
+            linearise(l, x, y, lin_r[c]);
+        }
+    }
 
     for (int it = 0; it < nouter; ++it) {
         // the owned positions, re-derived each step: otherwise the compiler
@@ -1165,21 +1207,15 @@ __device__ __forceinline__ void small_level(const DensifyArgs& da, const RefineA
                 const int l = cl[k][c];
                 if (l < 0) continue;
                 const int y = l / W, x = l - y * W;
-                const int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
-                const int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
-                const double* t0 = sm.J0;
-                const double* t1 = sm.J1w;
-                const double Ix = Ixa(x, y), Iy = Iya(x, y);
-                const double Iz = t1[l] - t0[l];
-                const double Ixx = (Ixa(xp, y) - Ixa(xm, y)) / 2.0;
-                const double Ixy = (Ixa(x, yp) - Ixa(x, ym)) / 2.0;
-                const double Iyy = (Iya(x, yp) - Iya(x, ym)) / 2.0;
-                const int lxp = y * W + xp, lxm = y * W + xm, lyp = yp * W + x, lym = ym * W + x;
-                const double Ixz = (t1[lxp] - t1[lxm]) / 2.0 - (t0[lxp] - t0[lxm]) / 2.0;
-                const double Iyz = (t1[lyp] - t1[lym]) / 2.0 - (t0[lyp] - t0[lym]) / 2.0;
-                const double b0 = 1.0 / ((Ix * Ix + Iy * Iy) + 0.01);
-                const double bx = 1.0 / ((Ixx * Ixx + Ixy * Ixy) + 0.01);
-                const double by = 1.0 / ((Ixy * Ixy + Iyy * Iyy) + 0.01);
+                double q[11];
+                if constexpr (kLinReg) {
+#pragma unroll
+                    for (int i = 0; i < 11; ++i) q[i] = lin_r[c][i];
+                } else {
+                    linearise(l, x, y, q);
+                }
+                const double Ix = q[0], Iy = q[1], Iz = q[2], Ixx = q[3], Ixy = q[4], Iyy = q[5];
+                const double Ixz = q[6], Iyz = q[7], b0 = q[8], bx = q[9], by = q[10];
                 const double fu = it ? sm.du[l] : 0.0, fv = it ? sm.dv[l] : 0.0;
                 const double ri = (Ix * fu + Iy * fv) + Iz;
                 const double ei = b0 * (ri * ri);
@@ -1204,7 +1240,11 @@ __device__ __forceinline__ void small_level(const DensifyArgs& da, const RefineA
                 const double Vd = hd ? sm.uv[l + W] : 0.0, Vu = hu ? sm.uv[l - W] : 0.0;
                 const double NU = ((wr * Ur + wl * Ul) + wd * Ud) + wu * Uu;
                 const double NV = ((wr * Vr + wl * Vl) + wd * Vd) + wu * Vu;
-                c_m[k][c] = (hr ? 1 : 0) | (hl ? 2 : 0) | (hd ? 4 : 0) | (hu ? 8 : 0);
+                // 16: the pair's other pixel (columns 2m, 2m + 1) is to the right;
+                // 32: it exists
+                const bool rt = (x & 1) == 0;
+                c_m[k][c] = (hr ? 1 : 0) | (hl ? 2 : 0) | (hd ? 4 : 0) | (hu ? 8 : 0) | (rt ? 16 : 0) |
+                            ((rt ? hr : hl) ? 32 : 0);
                 c_wr[k][c] = wr; c_wl[k][c] = wl; c_wd[k][c] = wd; c_wu[k][c] = wu;
                 c_a12[k][c] = A12;
                 c_i1[k][c] = om / (A11 + Ssum);
@@ -1223,18 +1263,30 @@ __device__ __forceinline__ void small_level(const DensifyArgs& da, const RefineA
                 for (int k = 0; k < PPT; ++k) {
                     const int l = cl[k][c];
                     if (l < 0) continue;
+                    // with registers to spare, the owned increments and the
+                    // pair's other pixel come from registers (only this
+                    // thread writes them), three neighbours per plane from LDS
                     const int m = c_m[k][c];
-                    const int lr = (m & 1) ? l + 1 : l, ll = (m & 2) ? l - 1 : l;
+                    const bool right = m & 16, pin = m & 32;
+                    const int lh = right ? ((m & 2) ? l - 1 : l) : ((m & 1) ? l + 1 : l);
                     const int ld = (m & 4) ? l + W : l, lu = (m & 8) ? l - W : l;
-                    const double du = sm.du[l], dv = sm.dv[l];
-                    const double nu = ((c_wr[k][c] * sm.du[lr] + c_wl[k][c] * sm.du[ll]) + c_wd[k][c] * sm.du[ld]) +
-                                      c_wu[k][c] * sm.du[lu];
+                    const int lp = right ? l + 1 : l - 1;   // the pair's other pixel
+                    const double du = kLinReg ? r_u[k][c] : sm.du[l], dv = kLinReg ? r_v[k][c] : sm.dv[l];
+                    const double pu = pin ? (kLinReg ? r_u[k][c ^ 1] : sm.du[lp]) : du;
+                    const double hu_ = sm.du[lh];
+                    const double nu = ((c_wr[k][c] * (right ? pu : hu_) + c_wl[k][c] * (right ? hu_ : pu)) +
+                                       c_wd[k][c] * sm.du[ld]) + c_wu[k][c] * sm.du[lu];
                     const double dun = om1 * du + c_i1[k][c] * ((nu + c_c1[k][c]) - c_a12[k][c] * dv);
                     sm.du[l] = dun;
+                    r_u[k][c] = dun;
                     if (!a.stereo) {
-                        const double nv = ((c_wr[k][c] * sm.dv[lr] + c_wl[k][c] * sm.dv[ll]) +
+                        const double pv = pin ? (kLinReg ? r_v[k][c ^ 1] : sm.dv[lp]) : dv;
+                        const double hv_ = sm.dv[lh];
+                        const double nv = ((c_wr[k][c] * (right ? pv : hv_) + c_wl[k][c] * (right ? hv_ : pv)) +
                                            c_wd[k][c] * sm.dv[ld]) + c_wu[k][c] * sm.dv[lu];
-                        sm.dv[l] = om1 * dv + c_i2[k][c] * ((nv + c_c2[k][c]) - c_a12[k][c] * dun);
+                        const double dvn = om1 * dv + c_i2[k][c] * ((nv + c_c2[k][c]) - c_a12[k][c] * dun);
+                        sm.dv[l] = dvn;
+                        r_v[k][c] = dvn;
                     }
                 }
                 __syncthreads();
@@ -1250,17 +1302,19 @@ __device__ __forceinline__ void small_level(const DensifyArgs& da, const RefineA
 }
 
 // ONE: a single pair, whose arguments the launch carries (read in place);
-// else block b takes pairs[list[b]].  512 threads serve levels of at most
-// 256 pixel pairs (two pairs per thread in the loops, half of them empty),
-// 1024 threads the rest; the narrower block has twice the registers.
+// else block b takes pairs[list[b]].  One pixel pair per thread: 512
+// threads serve levels of at most 512 pairs, 1024 threads the rest; the
+// narrower block has twice the registers per thread, enough to keep the
+// linearisation.
 template <int NT, bool ONE>
 __global__ __launch_bounds__(NT) void k_small_level(const SmallLaunch S) {
+    static_assert(NT == 512 || NT == DIS_SMALL_PAIRS, "one pixel pair per thread, up to the LDS capacity");
     __shared__ SmallSmem sm;
     if constexpr (ONE) {
-        small_level<NT>(S.da1, S.ra1, S.nouter, S.nhalf, sm);
+        small_level<NT, 1>(S.da1, S.ra1, S.nouter, S.nhalf, sm);
     } else {
         const LevelPair& P = S.pairs[__builtin_amdgcn_readfirstlane(S.list[blockIdx.x])];
-        small_level<NT>(P.da, P.ra, S.nouter, S.nhalf, sm);
+        small_level<NT, 1>(P.da, P.ra, S.nouter, S.nhalf, sm);
     }
 }
 
