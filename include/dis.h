@@ -197,7 +197,7 @@ int dis_autotune(dis_handle* h, const char* cache_path);
  * refine_tile picks the refinement tile (core width x height, threads) of the
  * per-phase launches: 0: 32x16/256, 1: 16x16/256, 2: 64x8/256,
  * 3: 16x16/1024, 4: 32x16/1024, 5: 16x16/512, 6: 32x16/512, 7: 8x8/512,
- * 8: 16x8/512, 9: 8x8/256.  launch_mode bit 0: 0 runs each scale as one
+ * 8: 16x8/512, 9: 8x8/256, 10: 8x4/384.  launch_mode bit 0: 0 runs each scale as one
  * persistent launch over a task queue, 1 as one launch per phase; bit 1 set
  * turns on the single-workgroup path: a scale of at most 256 horizontal
  * pixel pairs (1024 with bit 4 also set) is densified and refined, every

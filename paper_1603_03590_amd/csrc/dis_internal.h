@@ -259,4 +259,4 @@ const void* dis_kernel_level(int ps, int lpp);          // persistent level kern
 // refinement core tile (width, height, threads per block) of a tile id;
 // returns 0 for an unknown id
 int dis_refine_tile(int tile, int* tw, int* th, int* nt);
-#define DIS_NUM_TILES 10
+#define DIS_NUM_TILES 11

@@ -770,7 +770,8 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
 
     dis_tile::TileCoef<PPT> C;
     double s_iu[Shape::NS][2], s_iv[Shape::NS][2];
-    dis_tile::refine_setup<TW, TH, NT, DIS_KMAX, COLOUR>(a, g, sm, C, s_iu, s_iv);
+    // the sweeps below update only pixels within khe - 1 of the core
+    dis_tile::refine_setup<TW, TH, NT, DIS_KMAX, COLOUR>(a, g, sm, C, s_iu, s_iv, 2 * ((kh + 1) / 2) - 1);
     __syncthreads();   // the image tile is dead from here on
     // 4. sweep start
     double* du_ = sm.u.inc.du;
@@ -1458,7 +1459,7 @@ const void* dis_kernel_level(int ps, int lpp) {
 // refinement tile shapes: core width, height, threads per block
 #define DIS_FOR_REFINE_TILES(X) \
     X(0, 32, 16, 256) X(1, 16, 16, 256) X(2, 64, 8, 256) X(3, 16, 16, 1024) X(4, 32, 16, 1024) \
-    X(5, 16, 16, 512) X(6, 32, 16, 512) X(7, 8, 8, 512) X(8, 16, 8, 512) X(9, 8, 8, 256)
+    X(5, 16, 16, 512) X(6, 32, 16, 512) X(7, 8, 8, 512) X(8, 16, 8, 512) X(9, 8, 8, 256) X(10, 8, 4, 384)
 
 int dis_refine_tile(int tile, int* tw, int* th, int* nt) {
 #define DIS_TILE_SHAPE(ID, TW_, TH_, NT_) \

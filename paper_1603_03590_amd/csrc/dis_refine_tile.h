@@ -84,13 +84,17 @@ struct TileShape {
 // one column / row into wr / wd, U on the region, J0 and the warped J1w on
 // the image tile; with few pairs per thread the frozen and starting
 // increments of the owned pixels go to registers), the smoothness weights,
-// and the coefficients.  Ends with the image tile still live; the caller
-// places a barrier before reusing it.
+// and the coefficients.  Owned pixels farther than `reach` (Chebyshev
+// distance) from the core get no coefficients and load no linearisation:
+// the caller never updates them (their starting increments and weights are
+// still set).  Ends with the image tile still live; the caller places a
+// barrier before reusing it.
 template <int TW, int TH, int NT, int KG = DIS_KMAX, bool COLOUR = false>
 __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom& g, RefineSmem<TW, TH, KG>& sm,
                                              TileCoef<TileShape<TW, TH, NT, KG>::PPT>& C,
                                              double (&s_iu)[TileShape<TW, TH, NT, KG>::NS][2],
-                                             double (&s_iv)[TileShape<TW, TH, NT, KG>::NS][2]) {
+                                             double (&s_iv)[TileShape<TW, TH, NT, KG>::NS][2],
+                                             int reach = 1 << 20) {
     using S = RefineSmem<TW, TH, KG>;
     constexpr int LP = S::LP, IP = S::IP;
     constexpr int PPT = TileShape<TW, TH, NT, KG>::PPT;
@@ -109,23 +113,29 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
     constexpr bool colour = COLOUR;   // lin_mode 3: per-channel linearisation
     double s_fu[kStage ? PPT : 1][2], s_fv[kStage ? PPT : 1][2];
     double s_lin[NL][2][11];
+    bool far[PPT][2];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int pr = threadIdx.x + k * NT;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             C.l[k][c] = -1;
+            far[k][c] = true;
             if constexpr (kStage) { s_fu[k][c] = s_fv[k][c] = s_iu[k][c] = s_iv[k][c] = 0.0; }
             if (pr >= npw * RH) continue;
             const int ly = pr / npw, m = pr - ly * npw;
             const int lx = 2 * m + (((rx0 + ry0 + ly) & 1) ^ c);
             if (lx >= RW) continue;
             C.l[k][c] = ly * LP + lx;
-            const size_t gi = (size_t)(ry0 + ly) * W + rx0 + lx;
+            const int x = rx0 + lx, y = ry0 + ly;
+            far[k][c] = max(max(max(g.cx0 - x, x - (g.cx1 - 1)), max(g.cy0 - y, y - (g.cy1 - 1))), 0) > reach;
+            const size_t gi = (size_t)y * W + x;
             if constexpr (kStage) {
-                if (F) { s_fu[k][c] = F[gi]; s_fv[k][c] = F[n + gi]; }
                 if (Din) { s_iu[k][c] = Din[gi]; s_iv[k][c] = Din[n + gi]; }
+                if (far[k][c]) continue;
+                if (F) { s_fu[k][c] = F[gi]; s_fv[k][c] = F[n + gi]; }
             }
+            if (far[k][c]) continue;
             if constexpr (kLin) {
                 if (lin_load) {
 #pragma unroll
@@ -221,7 +231,7 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
                 C.wr[k][c] = C.wl[k][c] = C.wd[k][c] = C.wu[k][c] = 0.0;
                 C.a12[k][c] = C.i1[k][c] = C.i2[k][c] = C.c1[k][c] = C.c2[k][c] = 0.0;
                 const int l = C.l[k][c];
-                if (l < 0) continue;
+                if (l < 0 || far[k][c]) continue;
                 const int ly = l / LP, lx = l - ly * LP;
                 const int x = rx0 + lx, y = ry0 + ly;
                 const size_t gi = (size_t)y * W + x;

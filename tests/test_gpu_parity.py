@@ -13,7 +13,7 @@ from paper_1603_03590_amd import DIS, DisError, params, _lib
 
 pytestmark = pytest.mark.gpu
 
-N_TILES = 10   # refinement tile ids the library knows
+N_TILES = 11   # refinement tile ids the library knows
 
 
 def say(*a):
