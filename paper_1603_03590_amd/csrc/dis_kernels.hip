@@ -157,25 +157,36 @@ __global__ __launch_bounds__(256) void k_pyramid_tab(const PyrTab T) {
 // neighbouring block (every lane of a block holds the block's sum by then, so
 // the pairing is the tree's): DPP moves within a row of 16 lanes, lane
 // shuffles across rows.  Every LPP therefore gives the same bits.
-template <int GS, int GPL, int LPP>
-__device__ __forceinline__ double tree_finish(double (&g)[GPL]) {
+//
+// tree_finish_n runs M such trees level by level (each value's tree is the
+// one above, so every sum keeps its bits): the cross-lane latency of a level
+// is paid once for all M sums instead of once per sum.
+template <int GPL, int LPP, int M>
+__device__ __forceinline__ void tree_finish_n(double (&g)[M][GPL], double (&s)[M]) {
 #pragma unroll
     for (int step = 1; step < GPL; step <<= 1)
 #pragma unroll
-        for (int j = 0; j < GPL; j += 2 * step) g[j] = g[j] + g[j + step];
-    double s = g[0];
-    if (LPP >= 2) s = s + dpp_mov<0xB1>(s);    // quad_perm [1,0,3,2]
-    if (LPP >= 4) s = s + dpp_mov<0x4E>(s);    // quad_perm [2,3,0,1]
-    if (LPP >= 8) s = s + dpp_mov<0x141>(s);   // row_half_mirror
-    if (LPP >= 16) s = s + dpp_mov<0x140>(s);  // row_mirror
-    if (LPP >= 32) s = s + __shfl_xor(s, 16);   // the other row of the half wave
-    if (LPP >= 64) s = s + __shfl_xor(s, 32);   // the other half wave
-    return s;
+        for (int j = 0; j < GPL; j += 2 * step)
+#pragma unroll
+            for (int m = 0; m < M; ++m) g[m][j] = g[m][j] + g[m][j + step];
+    double t[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) s[m] = g[m][0];
+#define DIS_TREE_LEVEL(MOVE)                                          \
+    _Pragma("unroll") for (int m = 0; m < M; ++m) t[m] = MOVE;        \
+    _Pragma("unroll") for (int m = 0; m < M; ++m) s[m] = s[m] + t[m];
+    if (LPP >= 2) { DIS_TREE_LEVEL(dpp_mov<0xB1>(s[m])) }    // quad_perm [1,0,3,2]
+    if (LPP >= 4) { DIS_TREE_LEVEL(dpp_mov<0x4E>(s[m])) }    // quad_perm [2,3,0,1]
+    if (LPP >= 8) { DIS_TREE_LEVEL(dpp_mov<0x141>(s[m])) }   // row_half_mirror
+    if (LPP >= 16) { DIS_TREE_LEVEL(dpp_mov<0x140>(s[m])) }  // row_mirror
+    if (LPP >= 32) { DIS_TREE_LEVEL(__shfl_xor(s[m], 16)) }   // the other row of the half wave
+    if (LPP >= 64) { DIS_TREE_LEVEL(__shfl_xor(s[m], 32)) }   // the other half wave
+#undef DIS_TREE_LEVEL
 }
 
-template <int GS, int GPL, int LPP>
-__device__ __forceinline__ double csum(const double (&v)[GS * GPL]) {
-    double g[GPL];
+// Group sums of a lane: plain (v) or of products (a b, fma after the first).
+template <int GS, int GPL>
+__device__ __forceinline__ void group_sums(const double (&v)[GS * GPL], double (&g)[GPL]) {
 #pragma unroll
     for (int j = 0; j < GPL; ++j) {
         double s = v[j * GS];
@@ -183,12 +194,11 @@ __device__ __forceinline__ double csum(const double (&v)[GS * GPL]) {
         for (int k = 1; k < GS; ++k) s = s + v[j * GS + k];
         g[j] = s;
     }
-    return tree_finish<GS, GPL, LPP>(g);
 }
 
-template <int GS, int GPL, int LPP>
-__device__ __forceinline__ double csum_prod(const double (&a)[GS * GPL], const double (&b)[GS * GPL]) {
-    double g[GPL];
+template <int GS, int GPL>
+__device__ __forceinline__ void group_sums(const double (&a)[GS * GPL], const double (&b)[GS * GPL],
+                                           double (&g)[GPL]) {
 #pragma unroll
     for (int j = 0; j < GPL; ++j) {
         double s = a[j * GS] * b[j * GS];
@@ -196,7 +206,14 @@ __device__ __forceinline__ double csum_prod(const double (&a)[GS * GPL], const d
         for (int k = 1; k < GS; ++k) s = fma(a[j * GS + k], b[j * GS + k], s);
         g[j] = s;
     }
-    return tree_finish<GS, GPL, LPP>(g);
+}
+
+template <int GS, int GPL, int LPP>
+__device__ __forceinline__ double csum(const double (&v)[GS * GPL]) {
+    double g[1][GPL], s[1];
+    group_sums<GS, GPL>(v, g[0]);
+    tree_finish_n<GPL, LPP, 1>(g, s);
+    return s[0];
 }
 
 constexpr int isqrt_floor(int v, int r = 0) { return (r + 1) * (r + 1) > v ? r : isqrt_floor(v, r + 1); }
@@ -293,19 +310,22 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
             }
         }
     }
-    double h11 = csum_prod<GS, GPL, LPP>(gx[0], gx[0]);
-    double h12 = csum_prod<GS, GPL, LPP>(gx[0], gy[0]);
-    double h22 = csum_prod<GS, GPL, LPP>(gy[0], gy[0]);
-    double sgx[NC], sgy[NC];
-    sgx[0] = csum<GS, GPL, LPP>(gx[0]);
-    sgy[0] = csum<GS, GPL, LPP>(gy[0]);
+    // H' (channel sums, channel 0 first) and the gradient sums, all of one
+    // channel's five trees at once
+    double h11 = 0.0, h12 = 0.0, h22 = 0.0, sgx[NC], sgy[NC];
 #pragma unroll
-    for (int ch = 1; ch < NC; ++ch) {
-        h11 = h11 + csum_prod<GS, GPL, LPP>(gx[ch], gx[ch]);
-        h12 = h12 + csum_prod<GS, GPL, LPP>(gx[ch], gy[ch]);
-        h22 = h22 + csum_prod<GS, GPL, LPP>(gy[ch], gy[ch]);
-        sgx[ch] = csum<GS, GPL, LPP>(gx[ch]);
-        sgy[ch] = csum<GS, GPL, LPP>(gy[ch]);
+    for (int ch = 0; ch < NC; ++ch) {
+        double g5[5][GPL], s5[5];
+        group_sums<GS, GPL>(gx[ch], gx[ch], g5[0]);
+        group_sums<GS, GPL>(gx[ch], gy[ch], g5[1]);
+        group_sums<GS, GPL>(gy[ch], gy[ch], g5[2]);
+        group_sums<GS, GPL>(gx[ch], g5[3]);
+        group_sums<GS, GPL>(gy[ch], g5[4]);
+        tree_finish_n<GPL, LPP, 5>(g5, s5);
+        if (ch == 0) { h11 = s5[0]; h12 = s5[1]; h22 = s5[2]; }
+        else { h11 = h11 + s5[0]; h12 = h12 + s5[1]; h22 = h22 + s5[2]; }
+        sgx[ch] = s5[3];
+        sgy[ch] = s5[4];
     }
     double ui = 0.0, vi = 0.0;
     if (has_un) {
@@ -398,19 +418,27 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
                     }
                 }
             }
-            const double sd = csum<GS, GPL, LPP>(d);
-            const double md = sd * inv_n;
-            if (it == a.iters) {
-                if (ch == 0) md0 = md;
-                if (NC > 1 && valid && lane == 0) a.mdc[(size_t)pi * NC + ch] = md;
-                continue;
-            }
             double c1, c2;
-            if (a.norm == 0) {
-                // b = sum grad(T) (d - mean d): the mean-normalised residual (Sec. 2.1)
-                c1 = csum_prod<GS, GPL, LPP>(gx[ch], d) - md * sgx[ch];
-                c2 = csum_prod<GS, GPL, LPP>(gy[ch], d) - md * sgy[ch];
+            if (a.norm == 0 && it < a.iters) {
+                // b = sum grad(T) (d - mean d): the mean-normalised residual
+                // (Sec. 2.1); the three sums share one tree pass
+                double g3[3][GPL], s3[3];
+                group_sums<GS, GPL>(d, g3[0]);
+                group_sums<GS, GPL>(gx[ch], d, g3[1]);
+                group_sums<GS, GPL>(gy[ch], d, g3[2]);
+                tree_finish_n<GPL, LPP, 3>(g3, s3);
+                const double md = s3[0] * inv_n;
+                c1 = s3[1] - md * sgx[ch];
+                c2 = s3[2] - md * sgy[ch];
             } else {
+                // the final warp (only the mean residual), or a robust norm
+                const double sd = csum<GS, GPL, LPP>(d);
+                const double md = sd * inv_n;
+                if (it == a.iters) {
+                    if (ch == 0) md0 = md;
+                    if (NC > 1 && valid && lane == 0) a.mdc[(size_t)pi * NC + ch] = md;
+                    continue;
+                }
                 // App. B iii: each mean-normalised residual e is transformed so
                 // that its square is the L1 or the Huber penalty of e
                 double r[PPL];
@@ -424,8 +452,12 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
                     else t = ae < a.huber_b ? ae : sqrt(2.0 * a.huber_b * ae - a.huber_b * a.huber_b);
                     r[k] = p < NP ? copysign(t, e) : 0.0;
                 }
-                c1 = csum_prod<GS, GPL, LPP>(gx[ch], r);
-                c2 = csum_prod<GS, GPL, LPP>(gy[ch], r);
+                double g2[2][GPL], s2[2];
+                group_sums<GS, GPL>(gx[ch], r, g2[0]);
+                group_sums<GS, GPL>(gy[ch], r, g2[1]);
+                tree_finish_n<GPL, LPP, 2>(g2, s2);
+                c1 = s2[0];
+                c2 = s2[1];
             }
             if (ch == 0) { b1 = c1; b2 = c2; }
             else { b1 = b1 + c1; b2 = b2 + c2; }
