@@ -177,10 +177,11 @@ def main():
     traffic = None
     traffic_src = None
     from paper_1603_03590_amd import profsum
-    rec = profsum.read_traffic(os.path.join(ROOT, "profiles", f"{top['name']}_c2a_1024x436_hbm_traffic.md"))
-    if rec and rec.get("source_sha") == profsum.source_hash() and (
-            top["name"] != "refine" or (int(rec.get("tile", -1)) == head["tuned"]["refine_tile"]
-                                        and int(rec.get("mode", -1)) == head["tuned"]["launch_mode"])):
+    is_ref = top["name"] == "refine"
+    rec = profsum.read_traffic(os.path.join(ROOT, "profiles", f"{top['name']}_c2a_1024x436_hbm_traffic.md"),
+                               tile=head["tuned"]["refine_tile"] if is_ref else None,
+                               mode=head["tuned"]["launch_mode"] if is_ref else None)
+    if rec and rec.get("source_sha") == profsum.source_hash():
         traffic = float(rec["bytes_per_launch"])
         traffic_src = f"profiles/{top['name']}_c2a_1024x436_hbm_traffic.md"
     roof.update(traffic=traffic, traffic_source=traffic_src, kernel=top["name"],

@@ -115,8 +115,9 @@ def util_table(d: str, after: str = AFTER_DEFAULT) -> str:
     return "\n".join(out)
 
 
-def read_traffic(path: str) -> dict | None:
-    """The ``traffic:`` record of a committed summary, or None."""
+def read_traffic(path: str, tile: int | None = None, mode: int | None = None) -> dict | None:
+    """The first ``traffic:`` record of a committed summary (with `tile` /
+    `mode` given, the first one measured with them), or None."""
     try:
         for ln in open(path):
             if ln.startswith("traffic: "):
@@ -129,7 +130,8 @@ def read_traffic(path: str) -> dict | None:
                         rec[k] = float(v)
                     else:
                         rec[k] = v
-                return rec
+                if (tile is None or rec.get("tile") == tile) and (mode is None or rec.get("mode") == mode):
+                    return rec
     except OSError:
         return None
     return None

@@ -42,6 +42,14 @@ def test_traffic_record_scales_by_the_copy_probe(tmp_path):
     back = profsum.read_traffic(str(p))
     assert back["tile"] == 7 and back["mode"] == 1 and abs(back["bytes_per_launch"] - rec["bytes_per_launch"]) < 1.0
     assert back["source_sha"] == profsum.source_hash()
+    # several records: the one measured with the asked tile and launch mode
+    _, rec10 = profsum.traffic_record(str(tmp_path / "f"), str(tmp_path / "w"), "k_phase_refine<", 4, 10, 3,
+                                      after=r"k_level<")
+    line10 = "traffic: " + " ".join(f"{k}={v}" for k, v in rec10.items())
+    p.write_text("# x\n\n" + line + "\n" + line10 + "\n")
+    assert profsum.read_traffic(str(p), tile=10, mode=3)["tile"] == 10
+    assert profsum.read_traffic(str(p), tile=7, mode=1)["tile"] == 7
+    assert profsum.read_traffic(str(p), tile=7, mode=3) is None
     table = profsum.util_table(str(tmp_path / "f"))
     assert "`k_phase_refine<8, 8, 512, false>` | 2 | 200 |" in table and "`k_level<8, 16>` | 1 |" in table
     # without the filter the persistent launch counts too
