@@ -47,6 +47,21 @@ __device__ __forceinline__ double dpp_mov(double v) {
     return __hiloint2double(h2, l2);
 }
 
+// Row broadcast of a double (DPP row_bcast:15 / row_bcast:31): rows whose
+// bit is set in ROWS receive the named lane's value, the others 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_bcast(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWS, 0xF, false);
+    const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xF, false);
+    return __hiloint2double(h2, l2);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
 // ------------------------------------------------------------------ pyramid
 
 // One 32x32 tile of level a of frame f, channel c: the tile's part of levels
@@ -155,8 +170,8 @@ __global__ __launch_bounds__(256) void k_pyramid_tab(const PyrTab T) {
 // lane holds GPL = NG/LPP consecutive groups; the tree levels inside a lane are done in registers, the rest
 // across the LPP lanes of the patch, pairing each block of lanes with the
 // neighbouring block (every lane of a block holds the block's sum by then, so
-// the pairing is the tree's): DPP moves within a row of 16 lanes, lane
-// shuffles across rows.  Every LPP therefore gives the same bits.
+// the pairing is the tree's): DPP moves within a row of 16 lanes, DPP row
+// broadcasts across rows.  Every LPP therefore gives the same bits.
 //
 // tree_finish_n runs M such trees level by level (each value's tree is the
 // one above, so every sum keeps its bits): the cross-lane latency of a level
@@ -179,9 +194,25 @@ __device__ __forceinline__ void tree_finish_n(double (&g)[M][GPL], double (&s)[M
     if (LPP >= 4) { DIS_TREE_LEVEL(dpp_mov<0x4E>(s[m])) }    // quad_perm [2,3,0,1]
     if (LPP >= 8) { DIS_TREE_LEVEL(dpp_mov<0x141>(s[m])) }   // row_half_mirror
     if (LPP >= 16) { DIS_TREE_LEVEL(dpp_mov<0x140>(s[m])) }  // row_mirror
-    if (LPP >= 32) { DIS_TREE_LEVEL(__shfl_xor(s[m], 16)) }   // the other row of the half wave
-    if (LPP >= 64) { DIS_TREE_LEVEL(__shfl_xor(s[m], 32)) }   // the other half wave
+    // across rows: rows 1 and 3 add the last lane of rows 0 and 2 (by now
+    // every lane of a row holds the row's sum), then row 3 adds lane 31; the
+    // pairing is the tree's and a + b == b + a, so the bits are those of a
+    // butterfly.  The other rows keep partial sums, and the patch's total,
+    // in its last row, is read back to every lane.
+    if (LPP >= 32) { DIS_TREE_LEVEL((dpp_bcast<0x142, 0xA>(s[m]))) }   // row_bcast:15 into rows 1, 3
+    if (LPP >= 64) { DIS_TREE_LEVEL((dpp_bcast<0x143, 0x8>(s[m]))) }   // row_bcast:31 into row 3
 #undef DIS_TREE_LEVEL
+    if constexpr (LPP == 64) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) s[m] = read_lane(s[m], 63);
+    } else if constexpr (LPP == 32) {
+        const bool upper = (threadIdx.x & 32) != 0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const double a = read_lane(s[m], 31), b = read_lane(s[m], 63);
+            s[m] = upper ? b : a;
+        }
+    }
 }
 
 // Group sums of a lane: plain (v) or of products (a b, fma after the first).
