@@ -41,8 +41,9 @@ def build(verbose: bool = True) -> str:
     t0 = time.time()
     for src in SOURCES:
         obj = os.path.join(build_dir, src + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        _run([HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+        # the host sources share the launch structures and their inline
+        # helpers with the kernels, so every file is compiled as HIP
+        _run([HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = OUT + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)

@@ -781,20 +781,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
                     std::memset(&PL, 0, sizeof PL);
                     PL.L = LL;
                     PL.phase = ph;
-                    if (LL.one) {
-                        // the buffers of this phase, as the kernel resolves them from the tables
-                        const LevelPair& P = LH.lp[0];
-                        const RefPhase& rp = LH.rph[ph - 2];
-                        RefineArgs& ra = PL.ra1;
-                        ra = P.ra;
-                        ra.dUf = rp.f < 0 ? nullptr : P.dU[rp.f];
-                        ra.dUin = rp.in < 0 ? nullptr : P.dU[rp.in];
-                        ra.dUout = P.dU[rp.out];
-                        ra.Uout = rp.last ? P.ra.Uout : nullptr;
-                        ra.nhalf = rp.nhalf;
-                        ra.tape_m0 = rp.m0;
-                        ra.lin_mode = nc > 1 ? 3 : (LL.lin_cache ? (rp.m0 == 0 ? 1 : 2) : 0);
-                    }
+                    if (LL.one) PL.ra1 = dis_phase_args(LH.lp[0], LH.rph[ph - 2], LL.lin_cache, nc > 1);
                     seq.add(nc > 1 ? dis_kernel_phase_refine_colour(tile_id) : dis_kernel_phase_refine(tile_id), dim3(n),
                             dim3(nt), &PL, sizeof PL, 0, "refine",
                             ph_by[ph], ph_fl[ph]);

@@ -146,6 +146,24 @@ struct LevelLaunch {
     DensifyArgs da1;
 };
 
+// The refinement arguments of phase rp of pair P: the pair's, with the
+// phase's increment buffers resolved.  A level's first refinement launch
+// fills the linearisation cache, later ones read it; colour frames read the
+// per-channel linearisation of k_colour_lin.  The kernels resolve it from
+// the tables, the host for the arguments a single-pair launch carries.
+__host__ __device__ inline RefineArgs dis_phase_args(const LevelPair& P, const RefPhase& rp, int lin_cache,
+                                                     bool colour) {
+    RefineArgs ra = P.ra;
+    ra.dUf = rp.f < 0 ? nullptr : P.dU[rp.f];
+    ra.dUin = rp.in < 0 ? nullptr : P.dU[rp.in];
+    ra.dUout = P.dU[rp.out];
+    ra.Uout = rp.last ? P.ra.Uout : nullptr;
+    ra.nhalf = rp.nhalf;
+    ra.tape_m0 = rp.m0;
+    ra.lin_mode = colour ? 3 : (lin_cache ? (rp.m0 == 0 ? 1 : 2) : 0);
+    return ra;
+}
+
 // A phase-major refinement launch: phase `phase` of every pair of L.
 struct PhaseLaunch {
     LevelLaunch L;

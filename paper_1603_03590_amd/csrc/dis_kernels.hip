@@ -1010,18 +1010,7 @@ __global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
         const int np = L.npairs, s0 = phase * np;
         const int t = __builtin_amdgcn_readfirstlane(L.start[s0]) + q;
         const int j = __builtin_amdgcn_readfirstlane(L.task_seg[t]) - s0;
-        const LevelPair& P = L.pairs[j];
-        const RefPhase rp = L.rph[phase - 2];
-        ra = P.ra;
-        ra.dUf = rp.f < 0 ? nullptr : P.dU[rp.f];
-        ra.dUin = rp.in < 0 ? nullptr : P.dU[rp.in];
-        ra.dUout = P.dU[rp.out];
-        ra.Uout = rp.last ? P.ra.Uout : nullptr;
-        ra.nhalf = rp.nhalf;
-        ra.tape_m0 = rp.m0;
-        // the level's first launch fills the linearisation cache; colour
-        // frames read the per-channel linearisation of k_colour_lin
-        ra.lin_mode = COLOUR ? 3 : (L.lin_cache ? (rp.m0 == 0 ? 1 : 2) : 0);
+        ra = dis_phase_args(L.pairs[j], L.rph[phase - 2], L.lin_cache, COLOUR);
         const int t0 = __builtin_amdgcn_readfirstlane(L.start[s0 + j]);
         nt = __builtin_amdgcn_readfirstlane(L.start[s0 + j + 1]) - t0;
         q = t - t0;
@@ -1444,15 +1433,8 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
             } else if (phase == 1) {
                 densify_block(P.da, local % P.dens_bx, local / P.dens_bx);
             } else {
-                const RefPhase rp = L.rph[phase - 2];
-                RefineArgs ra = P.ra;
-                ra.dUf = rp.f < 0 ? nullptr : P.dU[rp.f];
-                ra.dUin = rp.in < 0 ? nullptr : P.dU[rp.in];
-                ra.dUout = P.dU[rp.out];
-                ra.Uout = rp.last ? P.ra.Uout : nullptr;
-                ra.nhalf = __builtin_amdgcn_readfirstlane(rp.nhalf);
-                ra.tape_m0 = rp.m0;
-                ra.lin_mode = L.lin_cache ? (rp.m0 == 0 ? 1 : 2) : 0;
+                RefineArgs ra = dis_phase_args(P, L.rph[phase - 2], L.lin_cache, false);
+                ra.nhalf = __builtin_amdgcn_readfirstlane(ra.nhalf);
                 refine_tile<32, 16, 256>(ra, local, sm);
             }
         }
