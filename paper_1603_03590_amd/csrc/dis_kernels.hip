@@ -833,7 +833,8 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
 
     dis_tile::TileCoef<PPT> C;
     double s_iu[Shape::NS][2], s_iv[Shape::NS][2];
-    // the sweeps below update only pixels within khe - 1 of the core
+    // the sweeps below update only pixels closer to the core than the number
+    // of half sweeps they run
     dis_tile::refine_setup<TW, TH, NT, DIS_KMAX, COLOUR>(a, g, sm, C, s_iu, s_iv, 2 * ((kh + 1) / 2) - 1);
     __syncthreads();   // the image tile is dead from here on
     // 4. sweep start
