@@ -14,6 +14,7 @@
 #include <type_traits>
 #include "dis_backward.h"
 #include "dis_refine_tile.h"
+#include "dis_lanes.h"
 
 namespace {
 
@@ -769,12 +770,9 @@ __global__ __launch_bounds__(256) void k_bwd_densify_patch(const DensBwdArgs a) 
         s1 += gd * t.dy;
         if (!a.raw_residual) s2 -= gd;
     }
-#pragma unroll
-    for (int m = 8; m >= 1; m >>= 1) {
-        s0 += __shfl_xor(s0, m, 16);
-        s1 += __shfl_xor(s1, m, 16);
-        s2 += __shfl_xor(s2, m, 16);
-    }
+    s0 = lane_sum<16>(s0);
+    s1 = lane_sum<16>(s1);
+    s2 = lane_sum<16>(s2);
     if (valid && lane == 0) {
         double* gP = a.gP + (size_t)i * 4;
         gP[0] += s0;
@@ -881,10 +879,7 @@ __global__ __launch_bounds__(256) void k_bwd_search(const SearchBwdArgs A) {
         sgx_l += gx[k]; sgy_l += gy[k];
         h11_l += gx[k] * gx[k]; h12_l += gx[k] * gy[k]; h22_l += gy[k] * gy[k];
     }
-    auto red = [&](double v) {
-        for (int off = 1; off < LPP; off <<= 1) v += __shfl_xor(v, off, 64);
-        return v;
-    };
+    auto red = [&](double v) { return lane_sum<LPP>(v); };
     const double sgx = red(sgx_l), sgy = red(sgy_l);
     const double a11 = red(h11_l) + a.lam, a12 = red(h12_l), a22 = red(h22_l) + a.lam;
     const double idet = 1.0 / (a11 * a22 - a12 * a12);

@@ -14,6 +14,7 @@
 // kernels and the persistent level kernel both call them.
 #include <hip/hip_runtime.h>
 #include "dis_internal.h"
+#include "dis_lanes.h"
 #include "dis_refine_tile.h"
 
 namespace {
@@ -36,30 +37,6 @@ __device__ __forceinline__ double bilin(const double* __restrict__ img, int W, i
     const double top = (1.0 - ax) * img[y0 * W + x0] + ax * img[y0 * W + x1];
     const double bot = (1.0 - ax) * img[y1 * W + x0] + ax * img[y1 * W + x1];
     return (1.0 - ay) * top + ay * bot;
-}
-
-// Cross-lane move of a double with a DPP pattern (two 32-bit halves).
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    const int l2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
-    const int h2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
-    return __hiloint2double(h2, l2);
-}
-
-// Row broadcast of a double (DPP row_bcast:15 / row_bcast:31): rows whose
-// bit is set in ROWS receive the named lane's value, the others 0.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_bcast(double v) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWS, 0xF, false);
-    const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xF, false);
-    return __hiloint2double(h2, l2);
-}
-
-__device__ __forceinline__ double read_lane(double v, int lane) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
-                            __builtin_amdgcn_readlane(__double2loint(v), lane));
 }
 
 // ------------------------------------------------------------------ pyramid

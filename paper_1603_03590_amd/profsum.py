@@ -31,7 +31,7 @@ import statistics
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/dis_kernels.hip", "csrc/dis_refine_tile.h", "csrc/dis_internal.h")
+KERNEL_SOURCES = ("csrc/dis_kernels.hip", "csrc/dis_refine_tile.h", "csrc/dis_internal.h", "csrc/dis_lanes.h")
 AFTER_DEFAULT = ""
 
 
