@@ -504,8 +504,28 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
 
     dis_tile::TileCoef<PPT> C;
     double s_iu[Shape::NS][2], s_iv[Shape::NS][2];
-    dis_tile::refine_setup<TW, TH, NT, KG>(a, g, sm.f, C, s_iu, s_iv);
+    // the reverse steps below touch only pixels within kh of the core
+    dis_tile::refine_setup<TW, TH, NT, KG>(a, g, sm.f, C, s_iu, s_iv, kh);
     __syncthreads();   // the image tile is dead from here on
+    // The adjoint moves one pixel per reverse half sweep: after reverse step
+    // r (of kh) the core's outputs still depend on pixels within kh - 1 - r
+    // of it, so step r replays and reverses (a) pixels within kh - r and
+    // gathers (b) into pixels within kh - 1 - r; the rest are skipped (the
+    // tape supplies the forward states exactly, so the replay needs no
+    // cone).  The core's results keep their bits.  Each owned pixel's
+    // Chebyshev distance from the core goes to bits 8.. of its flag word.
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int l = C.l[k][c];
+            if (l < 0) continue;
+            const int ly = l / LP, lx = l - ly * LP;
+            const int x = rx0 + lx, y = ry0 + ly;
+            const int d = max(max(max(cx0 - x, x - (g.cx1 - 1)), max(cy0 - y, y - (g.cy1 - 1))), 0);
+            C.m[k][c] |= d << 8;
+        }
+    }
 
     // state adjoint on the region, coefficient adjoints of the core
     for (int i = threadIdx.x; i < RW * RH; i += NT) {
@@ -571,11 +591,12 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
     auto reverse = [&](auto colour, int j) {
         constexpr int c = decltype(colour)::value;   // the colour half sweep j updated
         if (j > jlo) fetch(j - 1, c ^ 1);             // half sweep j - 1 updated the other colour
+        const int r = jhi - 1 - j;                    // reverse steps done before this one
         // (a) pixels of colour c: replay the update, then its adjoint
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int l = C.l[k][c];
-            if (l < 0) continue;
+            if (l < 0 || (C.m[k][c] >> 8) > kh - r) continue;
             const int msk = C.m[k][c];
             const int lr = (msk & 1) ? l + 1 : l, ll = (msk & 2) ? l - 1 : l;
             const int ld = (msk & 4) ? l + LP : l, lu = (msk & 8) ? l - LP : l;
@@ -620,7 +641,7 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int l = C.l[k][c ^ 1];
-            if (l < 0) continue;
+            if (l < 0 || (C.m[k][c ^ 1] >> 8) > kh - 1 - r) continue;
             const int msk = C.m[k][c ^ 1];
             double su = 0.0, sv = 0.0;
             if (msk & 1) { su += C.wr[k][c ^ 1] * sm.nu[l + 1]; sv += C.wr[k][c ^ 1] * sm.nv[l + 1]; }
