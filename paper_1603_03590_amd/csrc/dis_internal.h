@@ -223,6 +223,16 @@ struct UpsTab {
     int n;
 };
 
+// Global-memory view of a device pointer.  Pointers that reach a kernel
+// inside an argument structure copied to registers are generic, so their
+// accesses compile to flat_* instructions, which also count against the LDS
+// wait counter; through this view they are global_* ones (measured: 13.4 ->
+// 12.9 us per refinement launch on the small scales).
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* dis_global(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 // Workgroups are handed to the 8 XCDs round-robin (block b to XCD b mod 8),
 // and each XCD has its own L2.  Blocks whose tiles share halo should sit on
 // one XCD: this maps the blocks XCD x receives to the x-th contiguous run of

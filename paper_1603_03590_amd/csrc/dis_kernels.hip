@@ -26,7 +26,8 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) {
 // Bilinear sample, pixel values at integer coordinates, taps clamped to the
 // image.  Coordinates far outside are pulled to two pixels beyond the
 // border first; that leaves the clamped taps (and so the value) unchanged.
-__device__ __forceinline__ double bilin(const double* __restrict__ img, int W, int H, double x, double y) {
+template <class P>
+__device__ __forceinline__ double bilin(P img, int W, int H, double x, double y) {
     double xf = floor(x), yf = floor(y);
     const double ax = x - xf, ay = y - yf;
     xf = fmin(fmax(xf, -2.0), (double)W + 1.0);
@@ -273,7 +274,7 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
     const bool has_un = a.Un != nullptr;
     double u00, u01, u10, u11, v00, v01, v10, v11, bax, bay;
     {
-        const double* Up = has_un ? a.Un : a.J0;
+        const auto* Up = dis_global(has_un ? a.Un : a.J0);
         const int Wn = has_un ? a.Wn : W, Hn = has_un ? a.Hn : H;
         const double c = 0.5 * (PS - 1);
         double qx = (double)x0 + c, qy = (double)y0 + c;
@@ -287,7 +288,7 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
         const int xi = (int)xf, yi = (int)yf;
         const int c0 = clampi(xi, 0, Wn - 1), c1 = clampi(xi + 1, 0, Wn - 1);
         const int r0 = clampi(yi, 0, Hn - 1) * Wn, r1 = clampi(yi + 1, 0, Hn - 1) * Wn;
-        const double* Vp = Up + (has_un ? (size_t)Wn * Hn : 0);
+        const auto* Vp = Up + (has_un ? (size_t)Wn * Hn : 0);
         u00 = Up[r0 + c0]; u01 = Up[r0 + c1]; u10 = Up[r1 + c0]; u11 = Up[r1 + c1];
         v00 = Vp[r0 + c0]; v01 = Vp[r0 + c1]; v10 = Vp[r1 + c0]; v11 = Vp[r1 + c1];
     }
@@ -295,7 +296,7 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
     double T[NC][PPL], gx[NC][PPL], gy[NC][PPL];
 #pragma unroll
     for (int ch = 0; ch < NC; ++ch) {
-        const double* __restrict__ J0 = a.J0 + ch * n;
+        const auto* __restrict__ J0 = dis_global(a.J0) + ch * n;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             const int p = lane * PPL + k;
@@ -365,7 +366,7 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
             for (int k = 0; k < NW; ++k) {
                 const int i = lane + k * LPP;
                 const int Y = i / WS, X = i - Y * WS;
-                wv[k] = i < WS * WS ? a.J1[ch * n + clampi(wy + Y, 0, H - 1) * W + clampi(wx + X, 0, W - 1)] : 0.0;
+                wv[k] = i < WS * WS ? dis_global(a.J1)[ch * n + clampi(wy + Y, 0, H - 1) * W + clampi(wx + X, 0, W - 1)] : 0.0;
             }
 #pragma unroll
             for (int k = 0; k < NW; ++k) {
@@ -409,7 +410,7 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
                     }
                 }
             } else {
-                const double* __restrict__ J1 = a.J1 + ch * n;
+                const auto* __restrict__ J1 = dis_global(a.J1) + ch * n;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
                     const int p = lane * PPL + k;
@@ -444,7 +445,7 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
                 const double md = sd * inv_n;
                 if (it == a.iters) {
                     if (ch == 0) md0 = md;
-                    if (NC > 1 && valid && lane == 0) a.mdc[(size_t)pi * NC + ch] = md;
+                    if (NC > 1 && valid && lane == 0) dis_global(a.mdc)[(size_t)pi * NC + ch] = md;
                     continue;
                 }
                 // App. B iii: each mean-normalised residual e is transformed so
@@ -479,10 +480,10 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
         }
     }
     if (valid && lane == 0) {
-        double* P = a.patch + (size_t)pi * 4;
+        auto* P = dis_global(a.patch) + (size_t)pi * 4;
         P[0] = u; P[1] = v; P[2] = md0; P[3] = moved;
-        a.uinit[(size_t)pi * 2] = ui;
-        a.uinit[(size_t)pi * 2 + 1] = vi;
+        dis_global(a.uinit)[(size_t)pi * 2] = ui;
+        dis_global(a.uinit)[(size_t)pi * 2 + 1] = vi;
     }
 }
 
@@ -511,7 +512,7 @@ __device__ __forceinline__ void densify_pixel(const DensifyArgs& a, int x, int y
     bool fx, fy;
     cover_range(x, W, a.ps, a.st, a.nrx, a.nx, kx0, kx1, fx);
     cover_range(y, H, a.ps, a.st, a.nry, a.ny, ky0, ky1, fy);
-    const double j0 = a.J0[y * W + x];
+    const double j0 = dis_global(a.J0)[y * W + x];
     double su = 0.0, sv = 0.0;
     sw = 0.0;
     const int kyend = ky1 + (fy ? 1 : 0), kxend = kx1 + (fx ? 1 : 0);
@@ -520,9 +521,9 @@ __device__ __forceinline__ void densify_pixel(const DensifyArgs& a, int x, int y
         for (int jx = kx0; jx <= kxend; ++jx) {
             const int kx = jx <= kx1 ? jx : a.nrx;
             const int i = ky * a.nx + kx;
-            const double* P = a.patch + (size_t)i * 4;
+            const auto* P = dis_global(a.patch) + (size_t)i * 4;
             const double u = P[0], v = P[1];
-            const double q = bilin(a.J1, W, H, (double)x + u, (double)y + v);
+            const double q = bilin(dis_global(a.J1), W, H, (double)x + u, (double)y + v);
             double ad;
             if constexpr (!COLOUR) {
                 ad = fabs(a.raw_residual ? (q - j0) : ((q - j0) - P[2]));
@@ -557,12 +558,12 @@ __device__ __forceinline__ void densify_block(const DensifyArgs& a, int bx, int 
     double U, V, sw;
     densify_pixel<COLOUR>(a, x, y, U, V, sw);
     const int g = y * W + x;
-    if (a.Z) a.Z[g] = sw;
-    a.U[g] = U;
-    a.U[W * H + g] = V;
+    if (a.Z) dis_global(a.Z)[g] = sw;
+    dis_global(a.U)[g] = U;
+    dis_global(a.U)[W * H + g] = V;
     if (a.J1w) {
         if constexpr (!COLOUR) {
-            a.J1w[g] = bilin(a.J1, W, H, (double)x + U, (double)y + V);
+            dis_global(a.J1w)[g] = bilin(dis_global(a.J1), W, H, (double)x + U, (double)y + V);
         } else {
             for (int ch = 0; ch < a.nc; ++ch)
                 a.J1w[(size_t)ch * W * H + g] = bilin(a.J1 + (size_t)ch * W * H, W, H, (double)x + U, (double)y + V);
@@ -691,7 +692,7 @@ __global__ __launch_bounds__(256) void k_fb_densify(const FbLaunch F) {
         bool fx, fy;
         cover_range(x, W, a.ps, a.st, a.nrx, a.nx, kx0, kx1, fx);
         cover_range(y, H, a.ps, a.st, a.nry, a.ny, ky0, ky1, fy);
-        const double j0 = a.J0[y * W + x];
+        const double j0 = dis_global(a.J0)[y * W + x];
         const int kyend = ky1 + (fy ? 1 : 0), kxend = kx1 + (fx ? 1 : 0);
         for (int jy = ky0; jy <= kyend; ++jy) {
             const int ky = jy <= ky1 ? jy : a.nry;
@@ -699,7 +700,7 @@ __global__ __launch_bounds__(256) void k_fb_densify(const FbLaunch F) {
                 const int kx = jx <= kx1 ? jx : a.nrx;
                 const double* P = a.patch + (size_t)(ky * a.nx + kx) * 4;
                 const double u = P[0], v = P[1];
-                const double q = bilin(a.J1, W, H, (double)x + u, (double)y + v);
+                const double q = bilin(dis_global(a.J1), W, H, (double)x + u, (double)y + v);
                 const double dd = a.raw_residual ? (q - j0) : ((q - j0) - P[2]);
                 const double wgt = 1.0 / fmax(1.0, fabs(dd));
                 su = su + wgt * u;
@@ -711,7 +712,7 @@ __global__ __launch_bounds__(256) void k_fb_densify(const FbLaunch F) {
     // candidates of the other direction: 2 x 2 cells
     const int ps = o.ps;
     const double xr = (double)x, yr = (double)y;
-    const double j0 = a.J0[y * W + x];
+    const double j0 = dis_global(a.J0)[y * W + x];
     auto covers = [&](int j, double& uj, double& vj, double& md) {
         const int ky = j / o.nx, kx = j - ky * o.nx;
         const int x0 = kx < o.nrx ? kx * o.st : o.W - ps;
@@ -804,7 +805,7 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
     const size_t n = (size_t)W * H;
     const int rx0 = g.rx0, ry0 = g.ry0, RW = g.RW, RH = g.RH;
     const int cx0 = g.cx0, cy0 = g.cy0, cx1 = g.cx1, cy1 = g.cy1;
-    const double* __restrict__ Din = a.dUin;
+    const auto* __restrict__ Din = dis_global(a.dUin);
     const double om1 = 1.0 - a.omega;
     const bool stereo = a.stereo != 0;
 
@@ -906,7 +907,7 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
             if (a.tape) {
                 // state after this half sweep, core pixels only (every pixel of
                 // the level is the core of exactly one tile)
-                double* tp = a.tape + (size_t)(a.tape_m0 + j + c + 1) * 2 * n;
+                auto* tp = dis_global(a.tape) + (size_t)(a.tape_m0 + j + c + 1) * 2 * n;
                 const int CW = cx1 - cx0, CH = cy1 - cy0;
                 for (int i = threadIdx.x; i < CW * CH; i += NT) {
                     const int yy = i / CW, xx = i - yy * CW;
@@ -928,11 +929,11 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
         const size_t gi = (size_t)y * W + x;
         const int l = (y - ry0) * LP + (x - rx0);
         const double du = du_[l], dv = dv_[l];
-        a.dUout[gi] = du;
-        a.dUout[n + gi] = dv;
+        dis_global(a.dUout)[gi] = du;
+        dis_global(a.dUout)[n + gi] = dv;
         if (a.Uout) {
-            a.Uout[gi] = sm.uu[l] + du;
-            a.Uout[n + gi] = sm.uv[l] + dv;
+            dis_global(a.Uout)[gi] = sm.uu[l] + du;
+            dis_global(a.Uout)[n + gi] = sm.uv[l] + dv;
         }
     }
     __syncthreads();   // LDS is reused by the caller's next tile

@@ -103,9 +103,9 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
     const size_t n = (size_t)W * H;
     const int rx0 = g.rx0, ry0 = g.ry0, RW = g.RW, RH = g.RH, npw = g.npw;
     const int ix0 = g.ix0, iy0 = g.iy0;
-    const double* __restrict__ U = a.U;
-    const double* __restrict__ F = a.dUf;
-    const double* __restrict__ Din = a.dUin;
+    const auto* __restrict__ U = dis_global(a.U);
+    const auto* __restrict__ F = dis_global(a.dUf);
+    const auto* __restrict__ Din = dis_global(a.dUin);
 
     constexpr bool kLin = TileShape<TW, TH, NT, KG>::kLin;
     constexpr int NL = TileShape<TW, TH, NT, KG>::NL;
@@ -139,7 +139,7 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
             if constexpr (kLin) {
                 if (lin_load) {
 #pragma unroll
-                    for (int q = 0; q < 11; ++q) s_lin[k][c][q] = a.lin[q * n + gi];
+                    for (int q = 0; q < 11; ++q) s_lin[k][c][q] = dis_global(a.lin)[q * n + gi];
                 }
             }
         }
@@ -167,8 +167,8 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
         for (int i = threadIdx.x; i < IW * IH; i += NT) {
             const int ly = i / IW, lx = i - ly * IW;
             const size_t gi = (size_t)(iy0 + ly) * W + ix0 + lx;
-            sm.u.img.t0[ly * IP + lx] = a.J0[gi];
-            sm.u.img.t1[ly * IP + lx] = a.J1w[gi];
+            sm.u.img.t0[ly * IP + lx] = dis_global(a.J0)[gi];
+            sm.u.img.t1[ly * IP + lx] = dis_global(a.J1w)[gi];
         }
     }
     __syncthreads();
@@ -296,7 +296,7 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
                     bx = 1.0 / ((Ixx * Ixx + Ixy * Ixy) + 0.01);
                     by = 1.0 / ((Ixy * Ixy + Iyy * Iyy) + 0.01);
                     if (a.lin_mode == 1 && x >= g.cx0 && x < g.cx1 && y >= g.cy0 && y < g.cy1) {
-                        double* Lo = a.lin + gi;
+                        auto* Lo = dis_global(a.lin) + gi;
                         Lo[0] = Ix; Lo[n] = Iy; Lo[2 * n] = Iz; Lo[3 * n] = Ixx; Lo[4 * n] = Ixy;
                         Lo[5 * n] = Iyy; Lo[6 * n] = Ixz; Lo[7 * n] = Iyz; Lo[8 * n] = b0; Lo[9 * n] = bx;
                         Lo[10 * n] = by;
