@@ -530,9 +530,9 @@ __device__ __forceinline__ void densify_pixel(const DensifyArgs& a, int x, int y
             } else {
                 double ss = 0.0;
                 for (int ch = 0; ch < a.nc; ++ch) {
-                    const double qc = ch ? bilin(a.J1 + ch * n, W, H, (double)x + u, (double)y + v) : q;
-                    const double jc = a.J0[ch * n + (size_t)y * W + x];
-                    const double dc = a.raw_residual ? (qc - jc) : ((qc - jc) - a.mdc[(size_t)i * a.nc + ch]);
+                    const double qc = ch ? bilin(dis_global(a.J1) + ch * n, W, H, (double)x + u, (double)y + v) : q;
+                    const double jc = dis_global(a.J0)[ch * n + (size_t)y * W + x];
+                    const double dc = a.raw_residual ? (qc - jc) : ((qc - jc) - dis_global(a.mdc)[(size_t)i * a.nc + ch]);
                     ss = ch ? ss + dc * dc : dc * dc;
                 }
                 ad = sqrt(ss);
@@ -566,7 +566,7 @@ __device__ __forceinline__ void densify_block(const DensifyArgs& a, int bx, int 
             dis_global(a.J1w)[g] = bilin(dis_global(a.J1), W, H, (double)x + U, (double)y + V);
         } else {
             for (int ch = 0; ch < a.nc; ++ch)
-                a.J1w[(size_t)ch * W * H + g] = bilin(a.J1 + (size_t)ch * W * H, W, H, (double)x + U, (double)y + V);
+                dis_global(a.J1w)[(size_t)ch * W * H + g] = bilin(dis_global(a.J1) + (size_t)ch * W * H, W, H, (double)x + U, (double)y + V);
         }
     }
 }
@@ -585,8 +585,8 @@ __global__ __launch_bounds__(256) void k_colour_lin(const LevelLaunch L) {
     const int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
     const int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
     for (int ch = 0; ch < a.nc; ++ch) {
-        const double* t0 = a.J0 + ch * n;
-        const double* t1 = a.J1w + ch * n;
+        const auto* t0 = dis_global(a.J0) + ch * n;
+        const auto* t1 = dis_global(a.J1w) + ch * n;
         auto Ib = [&](int xx, int yy) { const size_t l = (size_t)yy * W + xx; return 0.5 * (t0[l] + t1[l]); };
         auto Ixa = [&](int xx, int yy) { return (Ib(min(xx + 1, W - 1), yy) - Ib(max(xx - 1, 0), yy)) / 2.0; };
         auto Iya = [&](int xx, int yy) { return (Ib(xx, min(yy + 1, H - 1)) - Ib(xx, max(yy - 1, 0))) / 2.0; };
@@ -600,7 +600,7 @@ __global__ __launch_bounds__(256) void k_colour_lin(const LevelLaunch L) {
         const size_t lyp = (size_t)yp * W + x, lym = (size_t)ym * W + x;
         const double Ixz = (t1[lxp] - t1[lxm]) / 2.0 - (t0[lxp] - t0[lxm]) / 2.0;
         const double Iyz = (t1[lyp] - t1[lym]) / 2.0 - (t0[lyp] - t0[lym]) / 2.0;
-        double* Lo = a.lin + (size_t)ch * 11 * n + gi;
+        auto* Lo = dis_global(a.lin) + (size_t)ch * 11 * n + gi;
         Lo[0] = Ix; Lo[n] = Iy; Lo[2 * n] = Iz; Lo[3 * n] = Ixx; Lo[4 * n] = Ixy; Lo[5 * n] = Iyy;
         Lo[6 * n] = Ixz; Lo[7 * n] = Iyz;
         Lo[8 * n] = 1.0 / ((Ix * Ix + Iy * Iy) + 0.01);
@@ -698,7 +698,7 @@ __global__ __launch_bounds__(256) void k_fb_densify(const FbLaunch F) {
             const int ky = jy <= ky1 ? jy : a.nry;
             for (int jx = kx0; jx <= kxend; ++jx) {
                 const int kx = jx <= kx1 ? jx : a.nrx;
-                const double* P = a.patch + (size_t)(ky * a.nx + kx) * 4;
+                const auto* P = dis_global(a.patch) + (size_t)(ky * a.nx + kx) * 4;
                 const double u = P[0], v = P[1];
                 const double q = bilin(dis_global(a.J1), W, H, (double)x + u, (double)y + v);
                 const double dd = a.raw_residual ? (q - j0) : ((q - j0) - P[2]);
@@ -717,7 +717,7 @@ __global__ __launch_bounds__(256) void k_fb_densify(const FbLaunch F) {
         const int ky = j / o.nx, kx = j - ky * o.nx;
         const int x0 = kx < o.nrx ? kx * o.st : o.W - ps;
         const int y0 = ky < o.nry ? ky * o.st : o.H - ps;
-        const double* P = o.patch + (size_t)j * 4;
+        const auto* P = dis_global(o.patch) + (size_t)j * 4;
         uj = P[0]; vj = P[1]; md = P[2];
         const double xa = (double)x0 + uj, ya = (double)y0 + vj;
         return xa <= xr && xr <= (double)x0 + (double)(ps - 1) + uj && ya <= yr &&
@@ -730,8 +730,8 @@ __global__ __launch_bounds__(256) void k_fb_densify(const FbLaunch F) {
     for (int cy = cy1 - 1; cy <= cy1; ++cy)
         for (int cx = cx1 - 1; cx <= cx1; ++cx) {
             const int c = cy * F.Wc + cx;
-            for (int t = B.start[c]; t < B.start[c + 1]; ++t) {
-                const int j = B.list[t];
+            for (int t = dis_global(B.start)[c]; t < dis_global(B.start)[c + 1]; ++t) {
+                const int j = dis_global(B.list)[t];
                 double uj, vj, md;
                 if (!covers(j, uj, vj, md)) continue;
                 if (nc == DIS_FB_MAXCAND) { overflow = true; continue; }
@@ -744,7 +744,7 @@ __global__ __launch_bounds__(256) void k_fb_densify(const FbLaunch F) {
     auto vote = [&](int j) {
         double uj, vj, md;
         covers(j, uj, vj, md);
-        const double tv = bilin(o.J0, W, H, xr - uj, yr - vj);   // the other direction's template frame
+        const double tv = bilin(dis_global(o.J0), W, H, xr - uj, yr - vj);   // the other direction's template frame
         const double dd = a.raw_residual ? (j0 - tv) : ((j0 - tv) - md);
         const double wgt = 1.0 / fmax(1.0, fabs(dd));
         su = su - wgt * uj;
@@ -762,8 +762,8 @@ __global__ __launch_bounds__(256) void k_fb_densify(const FbLaunch F) {
             for (int cy = cy1 - 1; cy <= cy1; ++cy)
                 for (int cx = cx1 - 1; cx <= cx1; ++cx) {
                     const int c = cy * F.Wc + cx;
-                    for (int t = B.start[c]; t < B.start[c + 1]; ++t) {
-                        const int j = B.list[t];
+                    for (int t = dis_global(B.start)[c]; t < dis_global(B.start)[c + 1]; ++t) {
+                        const int j = dis_global(B.list)[t];
                         double uj, vj, md;
                         if (j > prev && j < best && covers(j, uj, vj, md)) best = j;
                     }
@@ -775,9 +775,9 @@ __global__ __launch_bounds__(256) void k_fb_densify(const FbLaunch F) {
     }
     const double Uo = su / sw, Vo = sv / sw;
     const int g = y * W + x;
-    a.U[g] = Uo;
-    a.U[W * H + g] = Vo;
-    if (a.J1w) a.J1w[g] = bilin(a.J1, W, H, xr + Uo, yr + Vo);
+    dis_global(a.U)[g] = Uo;
+    dis_global(a.U)[W * H + g] = Vo;
+    if (a.J1w) dis_global(a.J1w)[g] = bilin(dis_global(a.J1), W, H, xr + Uo, yr + Vo);
 }
 
 // --------------------------------------------------------------- refinement

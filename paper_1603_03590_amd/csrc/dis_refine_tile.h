@@ -245,7 +245,7 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
                     // terms at those weights (channel 0 first)
                     double ei = 0.0, eg = 0.0;
                     for (int ch = 0; ch < a.nc; ++ch) {
-                        const double* Lc = a.lin + (size_t)ch * 11 * n + gi;
+                        const auto* Lc = dis_global(a.lin) + (size_t)ch * 11 * n + gi;
                         const double cri = (Lc[0] * fu + Lc[n] * fv) + Lc[2 * n];
                         const double crx = (Lc[3 * n] * fu + Lc[4 * n] * fv) + Lc[6 * n];
                         const double cry = (Lc[4 * n] * fu + Lc[5 * n] * fv) + Lc[7 * n];
@@ -256,7 +256,7 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
                     const double pg = a.gamma / (2.0 * sqrt(eg + eps2));
                     A11 = A12 = A22 = B1 = B2 = 0.0;
                     for (int ch = 0; ch < a.nc; ++ch) {
-                        const double* Lc = a.lin + (size_t)ch * 11 * n + gi;
+                        const auto* Lc = dis_global(a.lin) + (size_t)ch * 11 * n + gi;
                         const double cIx = Lc[0], cIy = Lc[n], cIz = Lc[2 * n], cIxx = Lc[3 * n], cIxy = Lc[4 * n];
                         const double cIyy = Lc[5 * n], cIxz = Lc[6 * n], cIyz = Lc[7 * n];
                         const double cb0 = Lc[8 * n], cbx = Lc[9 * n], cby = Lc[10 * n];
