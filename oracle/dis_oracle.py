@@ -98,6 +98,9 @@ class OracleParams:
     huber_b: float = 1.0               # R17
     stereo: bool = False               # R18: horizontal displacement only
     eps: float = 1e-3                  # robust penaliser epsilon (Sec. 2.3)
+    # arithmetic type of the plain method (dis_flow): float64, unless a test
+    # measures how far a narrower type moves the result
+    dtype: torch.dtype = torch.float64
 
 
 # ---------------------------------------------------------------- pyramid ----
@@ -229,10 +232,10 @@ def init_displacements(U_next: Optional[torch.Tensor], x0, y0, p: OracleParams):
     flow sampled at half the patch centre."""
     n = x0.numel()
     if U_next is None:
-        return torch.zeros(n, 2, dtype=F64)
+        return torch.zeros(n, 2, dtype=p.dtype)
     c = (p.patch_size - 1) / 2.0
-    cx = x0.to(F64) + c
-    cy = y0.to(F64) + c
+    cx = x0.to(U_next.dtype) + c
+    cy = y0.to(U_next.dtype) + c
     if p.init_map == "literal":
         qx, qy = cx / 2.0, cy / 2.0
     else:
@@ -292,8 +295,8 @@ def inverse_search(J0, Gx, Gy, J1, x0, y0, u_init, p: OracleParams,
     lam = p.hessian_lambda
     a11, a12, a22 = h11 + lam, h12, h22 + lam      # R10
     det = a11 * a22 - a12 * a12
-    Xf = X.to(F64)
-    Yf = Y.to(F64)
+    Xf = X.to(J0.dtype)
+    Yf = Y.to(J0.dtype)
 
     u = u_init.clone()
     history = []
@@ -334,9 +337,9 @@ def densify(w: int, h: int, x0, y0, u, d, p: OracleParams):
     px, py = patch_offsets(ps)
     lin = ((y0[:, None] + py[None, :]) * w + (x0[:, None] + px[None, :])).reshape(-1)
     wgt = 1.0 / torch.clamp(d.abs(), min=1.0)         # [N, P]
-    num_u = torch.zeros(h * w, dtype=F64).index_add(0, lin, (wgt * u[:, 0:1]).reshape(-1))
-    num_v = torch.zeros(h * w, dtype=F64).index_add(0, lin, (wgt * u[:, 1:2]).reshape(-1))
-    Z = torch.zeros(h * w, dtype=F64).index_add(0, lin, wgt.reshape(-1))
+    num_u = torch.zeros(h * w, dtype=u.dtype).index_add(0, lin, (wgt * u[:, 0:1]).reshape(-1))
+    num_v = torch.zeros(h * w, dtype=u.dtype).index_add(0, lin, (wgt * u[:, 1:2]).reshape(-1))
+    Z = torch.zeros(h * w, dtype=u.dtype).index_add(0, lin, wgt.reshape(-1))
     U = torch.stack([num_u / Z, num_v / Z]).reshape(2, h, w)
     return U, Z.reshape(h, w)
 
@@ -373,7 +376,7 @@ class RefineTerms:
 
 def refine_linearise(J0, J1, U) -> RefineTerms:
     h, w = J0.shape
-    yy, xx = torch.meshgrid(torch.arange(h, dtype=F64), torch.arange(w, dtype=F64), indexing="ij")
+    yy, xx = torch.meshgrid(torch.arange(h, dtype=J0.dtype), torch.arange(w, dtype=J0.dtype), indexing="ij")
     J1w = bilinear(J1, xx + U[0], yy + U[1])
     Ib = 0.5 * (J0 + J1w)
     Ix = central_dx(Ib)
@@ -540,7 +543,7 @@ def upsample(U: torch.Tensor, w: int, h: int, s: int, p: OracleParams) -> torch.
     if s == 0:
         return U
     f = float(2 ** s)
-    yy, xx = torch.meshgrid(torch.arange(h, dtype=F64), torch.arange(w, dtype=F64), indexing="ij")
+    yy, xx = torch.meshgrid(torch.arange(h, dtype=U.dtype), torch.arange(w, dtype=U.dtype), indexing="ij")
     if p.init_map == "literal":
         qx, qy = xx / f, yy / f
     else:
@@ -568,8 +571,8 @@ def dis_flow(I0: torch.Tensor, I1: torch.Tensor, p: OracleParams, records: Optio
     """Dense Inverse Search, Alg. 1: coarse-to-fine over s = theta_ss .. theta_sf
     of grid, initialisation, inverse search, densification and refinement,
     then upscaling to the input resolution.  Returns the flow [2, H, W]."""
-    I0 = torch.as_tensor(I0).to(F64)
-    I1 = torch.as_tensor(I1).to(F64)
+    I0 = torch.as_tensor(I0).to(p.dtype)
+    I1 = torch.as_tensor(I1).to(p.dtype)
     h, w = I0.shape
     ss = coarsest_scale(w, h, p)
     sf = p.finest_scale

@@ -803,3 +803,127 @@ def test_r20_channel_order_does_not_matter_and_integer_shift_is_fixed():
     ui = torch.tensor([[2.0, 1.0]], dtype=F64).expand(int(keep.sum()), 2).clone()
     r = O.colour_search(J0, J1, x0[keep], y0[keep], ui, p8)
     assert torch.equal(r.u, ui)
+
+
+# ----------------------------------------- sample positions and borders -----
+def _affine_field(h, w, a, b):
+    """u(x, y) = a0 x + a1 y + a2, v(x, y) = b0 x + b1 y + b2 on the integer
+    grid of an h x w level (bilinear interpolation reproduces it exactly
+    between the samples)."""
+    yy, xx = torch.meshgrid(torch.arange(h, dtype=F64), torch.arange(w, dtype=F64), indexing="ij")
+    return torch.stack([a[0] * xx + a[1] * yy + a[2], b[0] * xx + b[1] * yy + b[2]])
+
+
+def test_r7_initialisation_samples_the_coarser_flow_at_half_the_patch_centre():
+    """Sec. 2.2 step 2: a patch starts from twice the coarser flow at its
+    centre mapped to the coarser scale.  On an affine coarse field the value
+    is known by hand for every patch whose sample point is inside the field;
+    a corner instead of the centre, a missing factor 2 or a wrong mapping
+    each move it."""
+    a, b = (0.5, 0.25, 1.0), (-0.125, 0.75, -2.0)
+    Un = _affine_field(20, 24, a, b)
+    p = params(patch_size=8)
+    # corner (10, 6): centre (13.5, 9.5); literal mapping samples (6.75, 4.75)
+    x0, y0 = torch.tensor([10, 0, 30]), torch.tensor([6, 4, 22])
+    u = O.init_displacements(Un, x0, y0, p)
+    assert u[0, 0].item() == 2.0 * (0.5 * 6.75 + 0.25 * 4.75 + 1.0) == 11.125
+    assert u[0, 1].item() == 2.0 * (-0.125 * 6.75 + 0.75 * 4.75 - 2.0) == 1.4375
+    # pixel-centre mapping samples ((13.5 + 0.5) / 2 - 0.5, (9.5 + 0.5) / 2 - 0.5) = (6.5, 4.5)
+    uc = O.init_displacements(Un, x0, y0, O.with_params(p, init_map="pixel_centre"))
+    assert uc[0, 0].item() == 2.0 * (0.5 * 6.5 + 0.25 * 4.5 + 1.0) == 10.75
+    assert uc[0, 1].item() == 2.0 * (-0.125 * 6.5 + 0.75 * 4.5 - 2.0) == 1.125
+    # every interior patch of a grid: twice the affine field at the sample point
+    x0g, y0g, _, _ = O.patch_grid(40, 36, p)
+    for mode, m in (("literal", lambda c: c / 2.0), ("pixel_centre", lambda c: (c + 0.5) / 2.0 - 0.5)):
+        ug = O.init_displacements(Un, x0g, y0g, O.with_params(p, init_map=mode))
+        qx, qy = m(x0g.double() + 3.5), m(y0g.double() + 3.5)
+        assert float(qx.max()) <= 23 and float(qy.max()) <= 19
+        assert torch.allclose(ug[:, 0], 2.0 * (a[0] * qx + a[1] * qy + a[2]), atol=1e-12, rtol=0)
+        assert torch.allclose(ug[:, 1], 2.0 * (b[0] * qx + b[1] * qy + b[2]), atol=1e-12, rtol=0)
+    # a 12x12 patch at corner (0, 4): centre (5.5, 9.5), sample (2.75, 4.75)
+    u12 = O.init_displacements(Un, torch.tensor([0]), torch.tensor([4]), params(patch_size=12))
+    assert u12[0, 0].item() == 2.0 * (0.5 * 2.75 + 0.25 * 4.75 + 1.0) == 7.125
+    # a sample point past the coarser field's last column (centre 47.5 ->
+    # 23.75 on a 24-wide field) takes the border column's value (R8)
+    ub = O.init_displacements(Un, torch.tensor([44]), torch.tensor([6]), p)
+    assert ub[0, 0].item() == 2.0 * (0.5 * 23 + 0.25 * 4.75 + 1.0)
+
+
+def test_sec31_upscaling_of_an_affine_field():
+    """End of Sec. 3.1: the finest computed flow is interpolated bilinearly to
+    the full resolution and its vectors scaled by 2^s.  An affine level field
+    A x + t becomes A x + 2^s t at every output pixel whose sample point lies
+    inside the level (literal mapping x / 2^s), and A (x + 1/2 - 2^s / 2) + 2^s t
+    under the pixel-centre mapping; a wrong sample point or scale fails."""
+    a, b = (0.5, -0.25, 1.5), (0.125, 0.375, -0.75)
+    hs, ws = 7, 9
+    U = _affine_field(hs, ws, a, b)
+    for s in (1, 2, 3):
+        f = 2 ** s
+        w, h = ws * f, hs * f
+        yy, xx = torch.meshgrid(torch.arange(h, dtype=F64), torch.arange(w, dtype=F64), indexing="ij")
+        up = O.upsample(U, w, h, s, params())
+        inside = (xx <= (ws - 1) * f) & (yy <= (hs - 1) * f)
+        ex_u = a[0] * xx + a[1] * yy + f * a[2]
+        ex_v = b[0] * xx + b[1] * yy + f * b[2]
+        assert torch.allclose(up[0][inside], ex_u[inside], atol=1e-12, rtol=0)
+        assert torch.allclose(up[1][inside], ex_v[inside], atol=1e-12, rtol=0)
+        # one pixel by hand: s = 1, pixel (x=3, y=5) samples (1.5, 2.5):
+        if s == 1:
+            assert up[0][5, 3].item() == 2.0 * (0.5 * 1.5 - 0.25 * 2.5 + 1.5)
+        upc = O.upsample(U, w, h, s, O.with_params(params(), init_map="pixel_centre"))
+        qx, qy = (xx + 0.5) / f - 0.5, (yy + 0.5) / f - 0.5
+        inside_c = (qx >= 0) & (qy >= 0) & (qx <= ws - 1) & (qy <= hs - 1)
+        ex_uc = a[0] * (xx + 0.5 - f / 2) + a[1] * (yy + 0.5 - f / 2) + f * a[2]
+        ex_vc = b[0] * (xx + 0.5 - f / 2) + b[1] * (yy + 0.5 - f / 2) + f * b[2]
+        assert torch.allclose(upc[0][inside_c], ex_uc[inside_c], atol=1e-12, rtol=0)
+        assert torch.allclose(upc[1][inside_c], ex_vc[inside_c], atol=1e-12, rtol=0)
+
+
+def test_sec23_data_term_normalisers_by_hand():
+    """Sec. 2.3: beta_0 = 1 / (|grad_2 I|^2 + 0.01) from the first spatial
+    derivatives, beta_x = 1 / (I_xx^2 + I_xy^2 + 0.01) from the gradient of
+    I_x and beta_y = 1 / (I_xy^2 + I_yy^2 + 0.01) from the gradient of I_y.
+    On quadratic frames (central differences exact) the second derivatives of
+    the mean image are the constants 0.55, -0.025 and -0.02, so the values are
+    fixed by hand; swapping I_xy and I_yy, or I_xx and I_yy, changes them."""
+    h, w = 20, 24
+    yy, xx = torch.meshgrid(torch.arange(h, dtype=F64), torch.arange(w, dtype=F64), indexing="ij")
+    q0 = 0.3 * xx * xx - 0.2 * xx * yy + 0.1 * yy * yy + 2 * xx - yy + 50
+    q1 = 0.25 * xx * xx + 0.15 * xx * yy - 0.12 * yy * yy - xx + 3 * yy + 40
+    t = O.refine_linearise(q0, q1, torch.zeros(2, h, w, dtype=F64))
+    ib = lambda f: f[2:-2, 2:-2]
+    bx = 1.0 / (0.3025 + 0.000625 + 0.01)        # 0.55^2 + 0.025^2 + 0.01
+    by = 1.0 / (0.000625 + 0.0004 + 0.01)        # 0.025^2 + 0.02^2 + 0.01
+    assert torch.allclose(ib(t.bx), torch.full_like(ib(xx), bx), rtol=1e-12, atol=0)
+    assert torch.allclose(ib(t.by), torch.full_like(ib(xx), by), rtol=1e-12, atol=0)
+    # pixel (x=10, y=8): I_x = 0.55*10 - 0.025*8 + 0.5 = 5.8, I_y = -0.25 - 0.16 + 1 = 0.59
+    assert abs(t.b0[8, 10].item() - 1.0 / (5.8 ** 2 + 0.59 ** 2 + 0.01)) < 1e-15
+    assert abs(t.b0[8, 10].item() - 1.0 / 33.9981) < 1e-15
+    # the values a plausible slip would give are different
+    assert abs(bx - 1.0 / (0.3025 + 0.0004 + 0.01)) > 1e-3 and abs(by - 1.0 / (0.000625 + 0.3025 + 0.01)) > 1
+
+
+def test_r8_bilinear_clamps_at_the_frame_border_by_hand():
+    """R8: pixel values sit at integer coordinates and every tap index is
+    clamped into the image.  Values by hand on a 3 x 4 image."""
+    img = torch.tensor([[1., 2., 4., 8.],
+                        [16., 32., 64., 128.],
+                        [3., 5., 7., 11.]], dtype=F64)
+    pts = [
+        # (x, y) -> value
+        ((-0.5, 1.0), 16.0),                     # left of the frame: column 0
+        ((-3.25, 0.5), 0.5 * 1.0 + 0.5 * 16.0),  # far left, between rows 0 and 1
+        ((3.25, 1.0), 128.0),                    # right of the last column
+        ((5.0, 2.0), 11.0),                      # right, bottom row
+        ((1.5, -2.7), 0.5 * (2.0 + 4.0)),        # above the frame: row 0
+        ((2.0, 2.5), 7.0),                       # below the last row
+        ((-1.0, -1.0), 1.0), ((-7.5, 9.0), 3.0), ((4.5, -0.5), 8.0), ((3.0, 2.0), 11.0),   # corners
+        ((2.5, 1.75), 0.25 * 0.5 * (64.0 + 128.0) + 0.75 * 0.5 * (7.0 + 11.0)),   # interior
+        ((0.25, 0.5), 0.5 * (0.75 * 1.0 + 0.25 * 2.0) + 0.5 * (0.75 * 16.0 + 0.25 * 32.0)),
+    ]
+    x = torch.tensor([p[0][0] for p in pts], dtype=F64)
+    y = torch.tensor([p[0][1] for p in pts], dtype=F64)
+    got = O.bilinear(img, x, y)
+    for k, (_, v) in enumerate(pts):
+        assert got[k].item() == v, (pts[k], got[k].item())
