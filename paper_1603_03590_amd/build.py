@@ -9,6 +9,7 @@ import os
 import subprocess
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -37,14 +38,14 @@ def _run(cmd):
 def build(verbose: bool = True) -> str:
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    objs = []
     t0 = time.time()
-    for src in SOURCES:
-        obj = os.path.join(build_dir, src + ".o")
-        # the host sources share the launch structures and their inline
-        # helpers with the kernels, so every file is compiled as HIP
-        _run([HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+    objs = [os.path.join(build_dir, src + ".o") for src in SOURCES]
+    # the host sources share the launch structures and their inline
+    # helpers with the kernels, so every file is compiled as HIP
+    cmds = [[HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+            for src, obj in zip(SOURCES, objs)]
+    with ThreadPoolExecutor(max_workers=min(len(cmds), 8)) as ex:
+        list(ex.map(_run, cmds))
     tmp = OUT + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, OUT)
