@@ -273,7 +273,7 @@ class SearchResult:
 
 
 def inverse_search(J0, Gx, Gy, J1, x0, y0, u_init, p: OracleParams,
-                   keep_history: bool = False) -> SearchResult:
+                   keep_history: bool = False, progress: Optional[Callable] = None) -> SearchResult:
     """Inverse-compositional Gauss-Newton search per patch (Sec. 2.1, Suppl. A).
 
     S' = grad T and H' = sum S'^T S' are fixed before the loop; each
@@ -300,7 +300,9 @@ def inverse_search(J0, Gx, Gy, J1, x0, y0, u_init, p: OracleParams,
 
     u = u_init.clone()
     history = []
-    for _ in range(p.gn_iters):                      # R11
+    for it in range(p.gn_iters):                     # R11
+        if progress is not None and it > 0 and it % 32 == 0:
+            progress(f"{it} of {p.gn_iters} iterations")
         Q = bilinear(J1, Xf + u[:, 0:1], Yf + u[:, 1:2])
         r = robust_residual((Q - Q.mean(dim=1, keepdim=True)) - Tn, p)
         b1 = (gx * r).sum(1)
@@ -567,10 +569,13 @@ def outer_iterations(s: int, p: OracleParams) -> int:
     return s + 1 if p.var_outer < 0 else p.var_outer
 
 
-def dis_flow(I0: torch.Tensor, I1: torch.Tensor, p: OracleParams, records: Optional[list] = None):
+def dis_flow(I0: torch.Tensor, I1: torch.Tensor, p: OracleParams, records: Optional[list] = None,
+             progress: Optional[Callable] = None):
     """Dense Inverse Search, Alg. 1: coarse-to-fine over s = theta_ss .. theta_sf
     of grid, initialisation, inverse search, densification and refinement,
-    then upscaling to the input resolution.  Returns the flow [2, H, W]."""
+    then upscaling to the input resolution.  Returns the flow [2, H, W].
+    `progress`, if given, receives a line of text as the work advances (long
+    runs); it takes no part in the computation."""
     I0 = torch.as_tensor(I0).to(p.dtype)
     I1 = torch.as_tensor(I1).to(p.dtype)
     h, w = I0.shape
@@ -588,12 +593,15 @@ def dis_flow(I0: torch.Tensor, I1: torch.Tensor, p: OracleParams, records: Optio
         Gx, Gy = sobel8(J0[s])
         x0, y0, _, _ = patch_grid(ws_, hs, p)
         u_init = init_displacements(U, x0, y0, p)
-        res = inverse_search(J0[s], Gx, Gy, J1[s], x0, y0, u_init, p)
+        tell = None if progress is None else (lambda m, s=s: progress(f"scale {s}: search, {m}"))
+        res = inverse_search(J0[s], Gx, Gy, J1[s], x0, y0, u_init, p, progress=tell)
         Ud, _ = densify(ws_, hs, x0, y0, res.u, res.d, p)
         n_outer = outer_iterations(s, p)
         Ur = refine(J0[s], J1[s], Ud, n_outer, p) if p.refine else Ud
         if records is not None:
             records.append(LevelRecord(s, u_init, res, Ud, Ur, n_outer))
+        if progress is not None:
+            progress(f"scale {s} done ({ws_}x{hs}, {x0.numel()} patches)")
         U = Ur
     return upsample(U, w, h, sf, p)
 

@@ -51,12 +51,14 @@ def pair(kind: str, w: int, h: int, disp: float, seed: int):
 _oracle_cache = {}
 
 
-def oracle_flow(key, I0, I1, op: O.OracleParams, records=False):
+def oracle_flow(key, I0, I1, op: O.OracleParams, records=False, progress=None):
     ck = (key, repr(op), records)
     if ck not in _oracle_cache:
         recs = [] if records else None
-        run = O.dis_flow_colour if I0.ndim == 3 else O.dis_flow
-        U = run(torch.from_numpy(I0), torch.from_numpy(I1), op, recs)
+        if I0.ndim == 3:
+            U = O.dis_flow_colour(torch.from_numpy(I0), torch.from_numpy(I1), op, recs)
+        else:
+            U = O.dis_flow(torch.from_numpy(I0), torch.from_numpy(I1), op, recs, progress=progress)
         _oracle_cache[ck] = (U.numpy(), recs)
     return _oracle_cache[ck]
 
