@@ -80,6 +80,49 @@ def test_batched_parity_with_oracle():
         d.close()
 
 
+def test_batched_wide_pairs_parity():
+    """The batch workload's two largest sizes, 1280x720 and 1920x1080, at its
+    100 px motion, next to a 640x480 pair: the automatic coarsest scale of
+    Sec. 3.1 is 6 for the wide frames and 5 for VGA (different pyramid depths
+    in one batch).  Each pair is bitwise equal to the plain call and at
+    parity with the oracle."""
+    sizes = [(1280, 720), (1920, 1080), (640, 480)]
+    say(f"[batched] wide pairs {sizes} at 100 px, auto coarsest scale")
+    prs = [pair("layered", w, h, 100.0, 1100 + k) for k, (w, h) in enumerate(sizes)]
+    p = params(106)
+    ref = plain(prs, p)
+    d = DIS(p, 1920, 1080, max_batch=len(prs))
+    try:
+        for mode in (1, 0):
+            say(f"[batched] wide pairs, launch mode {mode}")
+            d.set_tunables(None, 0, mode)
+            outs = d.flow_batched([torch.from_numpy(pr.I0).cuda() for pr in prs],
+                                  [torch.from_numpy(pr.I1).cuda() for pr in prs])
+            torch.cuda.synchronize()
+            for k, o in enumerate(outs):
+                assert np.array_equal(o.cpu().numpy(), ref[k]), f"pair {k}, mode {mode}"
+        for k, pr in enumerate(prs):
+            h, w = pr.I0.shape
+            dp = DIS(p, w, h)
+            try:
+                dp.flow(torch.from_numpy(pr.I0).cuda(), torch.from_numpy(pr.I1).cuda())
+                torch.cuda.synchronize()
+                info = dp.debug_level(3, _lib.DIS_DBG_INFO)
+                top = 6 if w > 1024 else 5
+                dp.debug_level(top, _lib.DIS_DBG_INFO)          # the coarsest scale was computed
+                with pytest.raises(DisError):
+                    dp.debug_level(top + 1, _lib.DIS_DBG_INFO)  # and nothing coarser
+            finally:
+                dp.close()
+            U_ref, _ = oracle_flow(f"wide{k}", pr.I0, pr.I1, oracle_params(p))
+            frac, erel, dmax = parity(ref[k].astype(np.float64), U_ref, pr.flow)
+            say(f"[batched] wide pair {k} {w}x{h} (scale 3 is {info[0]}x{info[1]}): within 1e-2 px {frac:.6f}, "
+                f"EPE rel {erel:.2e}, max {dmax:.2e}")
+            assert frac >= PARITY_FRAC and erel <= PARITY_EPE_REL
+    finally:
+        d.close()
+
+
 def test_autotune_keeps_results_and_writes_cache(tmp_path):
     say("[autotune] batched 3 pairs")
     prs = batch_pairs()[:3]

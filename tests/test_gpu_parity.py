@@ -326,10 +326,29 @@ def test_high_quality_c3a_full_size_parity():
     say("[parity] case c3a_layered_1024x436_full (oracle ~30-50 s)")
     pr = pair("layered", 1024, 436, 200.0, 3)
     p = params(104)
-    U_ref, _ = oracle_flow("c3a_full", pr.I0, pr.I1, oracle_params(p))
+    U_ref, _ = oracle_flow("c3a_full", pr.I0, pr.I1, oracle_params(p),
+                           progress=lambda m: say(f"[parity] c3a oracle: {m}"))
     U = gpu_flow(pr.I0, pr.I1, p)
     frac, erel, dmax = parity(U, U_ref, pr.flow)
     say(f"[parity] c3a full: within 1e-2 px {frac:.6f}, mean EPE rel diff {erel:.2e}, max diff {dmax:.2e}")
+    assert frac >= PARITY_FRAC
+    assert erel <= PARITY_EPE_REL
+
+
+def test_high_quality_c3b_full_size_parity():
+    """The high-quality configuration on the large frame size (2048x1024,
+    motion up to 200 px, patch 12, overlap 0.75, 128 GN iterations, scales
+    4..0): 230,520 patches on the finest scale.  The oracle takes a few
+    minutes here."""
+    say("[parity] case c3b_layered_2048x1024_full (oracle a few minutes)")
+    pr = pair("layered", 2048, 1024, 200.0, 4)
+    p = params(104)
+    U_ref, _ = oracle_flow("c3b_full", pr.I0, pr.I1, oracle_params(p),
+                           progress=lambda m: say(f"[parity] c3b oracle: {m}"))
+    say("[parity] c3b full: oracle done")
+    U = gpu_flow(pr.I0, pr.I1, p)
+    frac, erel, dmax = parity(U, U_ref, pr.flow)
+    say(f"[parity] c3b full: within 1e-2 px {frac:.6f}, mean EPE rel diff {erel:.2e}, max diff {dmax:.2e}")
     assert frac >= PARITY_FRAC
     assert erel <= PARITY_EPE_REL
 
