@@ -100,6 +100,8 @@ def main():
                     help="also run a plain device copy of this many MiB five times (calibrates HBM counters)")
     ap.add_argument("--hq-steps", type=int, default=20,
                     help="timed steps of the high-quality configuration at 1024x436 and 2048x1024; 0 skips")
+    ap.add_argument("--hq-parity", type=int, default=1,
+                    help="check the high-quality flows against the oracle (1) or not (0)")
     ap.add_argument("--ext-steps", type=int, default=100,
                     help="timed steps of each extension (robust norms, stereo, forward-backward, colour); 0 skips")
     ap.add_argument("--fwd-bwd-pairs", type=int, default=8,
@@ -321,8 +323,8 @@ def main():
                        mean_epe_px=mean_epe, dtype_io="f32", streams=nfb,
                        kernels=kernel_table(list(fb_k.values()), 3),
                        workload=f"{nfb} pairs 512x256 float32, smooth-bump generator (max 16 px, seeds "
-                                f"2000..{2000 + nfb - 1}); patch 8, overlap 0.5, scales 2..0 (3 clamped to the "
-                                f"patch), 16 GN iterations, theta_vo 3, theta_vi 5; loss = mean EPE vs ground truth; "
+                                f"2000..{2000 + nfb - 1}); patch 8, overlap 0.5, scales 3..0, "
+                                f"16 GN iterations, theta_vo 3, theta_vi 5; loss = mean EPE vs ground truth; "
                                 f"step = forward + loss + backward of every pair, one HIP stream per pair")
         for d_ in hs:
             d_.close()
@@ -356,7 +358,8 @@ def main():
             hq[name] = dict(value=w_ * h_ / t / 1e6, unit="Mpix/s", ms_per_step=t * 1e3, tunables=d.tunables(),
                             kernels=kernel_table(st, 3), roofline=r_,
                             workload=f"layered pair {w_}x{h_}, rigid motion up to 200 px (seed {seed}); patch 12, "
-                                     f"overlap 0.75, scales 4..0, 128 GN iterations, theta_vo 5, theta_vi 5")
+                                     f"overlap 0.75, scales 4..0, 128 GN iterations, theta_vo 5, theta_vi 5",
+                            _flow=o.cpu().numpy().astype(np.float64), _case=q)
             d.close()
             log(f"[bench] high quality {name}: {t * 1e3:.3f} ms/pair")
 
@@ -413,7 +416,8 @@ def main():
             return out
 
         def check(name, U, I0n, I1n, gt, p):
-            U_ref = O.dis_flow(torch.from_numpy(I0n), torch.from_numpy(I1n), oracle_params(p)).numpy()
+            U_ref = O.dis_flow(torch.from_numpy(I0n), torch.from_numpy(I1n), oracle_params(p),
+                               progress=lambda m: log(f"[bench] oracle for {name}: {m}")).numpy()
             frac, erel, dmax = parity_stats(U, U_ref, gt)
             epe = float(np.sqrt(((U - gt) ** 2).sum(0)).mean())
             parity[name] = {"frac_within_1e-2px": frac, "mean_epe_rel_diff": erel, "max_abs_diff_px": dmax,
@@ -451,6 +455,13 @@ def main():
             frac, erel, dmax = parity_stats(e["_flow"], U_ref, q.flow)
             parity[f"ext_{name}"] = {"frac_within_1e-2px": frac, "mean_epe_rel_diff": erel, "max_abs_diff_px": dmax,
                                      "passed": bool(frac >= 0.999 and erel <= 0.005)}
+        # the high-quality runs against the oracle (the 2048x1024 pair takes
+        # the oracle a few minutes: --hq-parity 0 leaves both out)
+        if args.hq_parity:
+            for name, e in hq.items():
+                q = e["_case"]
+                check(f"high_quality_{name}", e["_flow"], q.I0, q.I1, q.flow, params(104))
+                log(f"[bench] parity high quality {name}: {parity[f'high_quality_{name}']['frac_within_1e-2px']:.6f}")
         op_p = oracle_params(params(presets[args.op]))
         t0 = time.perf_counter()
         runs = 0
@@ -487,7 +498,7 @@ def main():
     if batched:
         batched.pop("_sample")
         batched.pop("_out")
-    for e in ext.values():
+    for e in list(ext.values()) + list(hq.values()):
         e.pop("_flow")
         e.pop("_case")
 
