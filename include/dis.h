@@ -286,6 +286,33 @@ int dis_profile_read(dis_handle* h, dis_kernel_stat* out, int max, int* n);
  * the handle's stream first, so pending work finishes before memory goes. */
 void dis_destroy(dis_handle* h);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the flow
+ * of dis_compute_flow without a handle.  Every intermediate buffer lives in
+ * one static device array of DIS_NOALLOC_SCRATCH_BYTES bytes that each GPU
+ * the library runs on holds until the process ends; this call never calls
+ * hipMalloc or hipFree.  p, I0, I1, w, hgt, pitch and flow are as for
+ * dis_create and dis_compute_flow (device frames and flow, caller-owned);
+ * the kernels are enqueued one by one (no graph) on `hip_stream` of the
+ * current device, without synchronising it.  The flow is bitwise equal to
+ * dis_compute_flow's for the same parameters and frames.
+ * All calls on one GPU share its array, which keeps the last call's
+ * contents: calls that overlap on one GPU (concurrent streams, or host
+ * threads) race and give wrong flow.  Calls from several host threads are
+ * serialised on the host, not on the GPU.
+ * Errors: DIS_EINVAL (bad parameter, NULL pointer, pitch < w, or a flag
+ * this call does not take: DIS_FLAG_KEEP_FOR_BACKWARD,
+ * DIS_FLAG_FB_CONSISTENCY, DIS_FLAG_COLOUR), DIS_ESIZE (the frame's
+ * buffers need more than DIS_NOALLOC_SCRATCH_BYTES -- about 104 bytes per
+ * pixel of the finest processed scale plus its coarser scales, e.g. fine
+ * for 1024x436 at theta_sf 0 -- or the finest scale is smaller than the
+ * patch), DIS_EHIP.  Messages through dis_last_error(NULL).
+ */
+#define DIS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int dis_compute_flow_noalloc(const dis_params* p, const void* I0, const void* I1, int w, int hgt,
+                             int pitch, void* flow, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

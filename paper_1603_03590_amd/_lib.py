@@ -53,7 +53,7 @@ EXPORTS = (
     "dis_default_params", "dis_create", "dis_compute_flow", "dis_compute_flow_batched",
     "dis_flow_backward", "dis_autotune", "dis_last_error", "dis_set_stream",
     "dis_debug_level", "dis_destroy", "dis_profile_enable", "dis_profile_read", "dis_set_tunables",
-    "dis_get_tunables",
+    "dis_get_tunables", "dis_compute_flow_noalloc",
 )
 
 
@@ -127,6 +127,8 @@ def load(path: str = LIB_PATH):
     lib.dis_profile_read.argtypes = [H, POINTER(dis_kernel_stat), c_int, POINTER(c_int)]
     lib.dis_set_tunables.argtypes = [H, POINTER(c_int), c_int, c_int]
     lib.dis_get_tunables.argtypes = [H, POINTER(c_int), POINTER(c_int), POINTER(c_int)]
+    lib.dis_compute_flow_noalloc.argtypes = [POINTER(dis_params), c_void_p, c_void_p, c_int, c_int, c_int, c_void_p,
+                                             c_void_p]
     lib.dis_destroy.argtypes = [H]
     lib.dis_destroy.restype = None
     for name in EXPORTS:
@@ -222,3 +224,9 @@ def dis_set_tunables(handle: int, lanes_per_patch=None, refine_tile: int = 0, la
         vals = list(lanes_per_patch) + [0] * (16 - len(lanes_per_patch))
         arr = (c_int * 16)(*vals[:16])
     _check(load().dis_set_tunables(c_void_p(handle), arr, refine_tile, launch_mode), c_void_p(handle))
+
+
+def dis_compute_flow_noalloc(params: dis_params, I0: int, I1: int, w: int, h: int, pitch: int, flow: int,
+                             stream: int = 0) -> None:
+    _check(load().dis_compute_flow_noalloc(ctypes.byref(params), c_void_p(I0), c_void_p(I1), w, h, pitch,
+                                           c_void_p(flow), c_void_p(stream)))

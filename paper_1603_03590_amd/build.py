@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdis.so")
-SOURCES = ["dis_kernels.hip", "dis_backward.hip", "dis_host.cpp", "dis_ext.cpp", "dis_bwd_host.cpp"]
+SOURCES = ["dis_kernels.hip", "dis_backward.hip", "dis_host.cpp", "dis_ext.cpp", "dis_bwd_host.cpp",
+           "dis_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -72,6 +72,9 @@ void dis_grid(int n, int ps, int st, int* nr, int* ntot) {
     *ntot = *nr + (((n - ps) % st) != 0 ? 1 : 0);
 }
 
+static int validate_params(const dis_params* p);
+int dis_validate_params(const dis_params* p) { return validate_params(p); }
+
 static int validate_params(const dis_params* p) {
     if (!p) return fail(nullptr, DIS_EINVAL, "params is NULL");
     if (!is_supported_ps(p->patch_size))
@@ -156,6 +159,14 @@ extern "C" int dis_default_params(int preset, dis_params* out) {
 int dis_dalloc(dis_handle* h, void** ptr, size_t bytes) {
     *ptr = nullptr;
     if (bytes == 0) return DIS_OK;
+    if (h->arena) {
+        const size_t off = (h->arena_used + 255) & ~(size_t)255;
+        if (off > h->arena_cap || bytes > h->arena_cap - off)
+            return fail(h, DIS_ESIZE, "the frame needs more than the %zu bytes of static scratch", h->arena_cap);
+        *ptr = h->arena + off;
+        h->arena_used = off + bytes;
+        return DIS_OK;
+    }
     hipError_t e = hipMalloc(ptr, bytes);
     if (e != hipSuccess) {
         *ptr = nullptr;
@@ -173,7 +184,7 @@ int dis_dalloc(dis_handle* h, void** ptr, size_t bytes) {
         if (r_ != DIS_OK) return r_;                               \
     } while (0)
 
-static int alloc_slot(dis_handle* h, SlotBuf& sb) {
+int dis_alloc_slot(dis_handle* h, SlotBuf& sb) {
     const dis_params& p = h->p;
     const int W = h->max_w, H = h->max_h, ps = p.patch_size, st = h->st;
     const int nc = dis_channels(&p);
@@ -203,10 +214,18 @@ static int alloc_slot(dis_handle* h, SlotBuf& sb) {
     const size_t pf = (size_t)(W >> sf) * (H >> sf);
     if (p.refine) {
         DALLOC(h, sb.J1w, nc * pf * sizeof(double));
-        DALLOC(h, sb.lin, 11 * nc * pf * sizeof(double));
+        // without the linearisation cache only colour frames use this buffer
+        if (!h->no_lin_cache || nc > 1) DALLOC(h, sb.lin, 11 * nc * pf * sizeof(double));
         for (int i = 0; i < 3; ++i) DALLOC(h, sb.dU[i], 2 * pf * sizeof(double));
     }
     return DIS_OK;
+}
+
+// Deepest pyramid level whose frames still hold a patch, for max_w x max_h.
+int dis_top_level(const dis_params* p, int max_w, int max_h) {
+    int top = 0;
+    while (top + 1 < DIS_MAXL && (max_w >> (top + 1)) >= p->patch_size && (max_h >> (top + 1)) >= p->patch_size) ++top;
+    return top;
 }
 
 extern "C" int dis_create(const dis_params* p, int max_w, int max_h, int max_batch, void* stream,
@@ -237,16 +256,14 @@ extern "C" int dis_create(const dis_params* p, int max_w, int max_h, int max_bat
         h->n_cu = hipGetDeviceProperties(&prop, h->device) == hipSuccess ? prop.multiProcessorCount : 256;
         if (h->n_cu < 1) h->n_cu = 256;
     }
-    int top = 0;
-    while (top + 1 < DIS_MAXL && (max_w >> (top + 1)) >= p->patch_size && (max_h >> (top + 1)) >= p->patch_size) ++top;
-    h->top = top;
+    h->top = dis_top_level(p, max_w, max_h);
     for (int s = 0; s < DIS_MAXL; ++s) h->lpp[s] = 0;
     h->refine_tile = 7;   // 8x8 cores, 512 threads: the fastest on small scales
     const bool fb = (p->flags & DIS_FLAG_FB_CONSISTENCY) != 0;
     const int nslots = fb ? std::max(max_batch, 2) : max_batch;
     h->slots.resize(nslots);
     for (int i = 0; i < nslots; ++i) {
-        r = alloc_slot(h, h->slots[i]);
+        r = dis_alloc_slot(h, h->slots[i]);
         if (r != DIS_OK) {
             g_null_err = h->err;
             dis_destroy(h);
@@ -529,7 +546,11 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     const bool fbm = (p.flags & DIS_FLAG_FB_CONSISTENCY) && !opt && pairs.size() == 2;
     const int nc = dis_channels(&p);
     // colour frames and the merged densification run phase-major only
-    const int mode = ((opt && opt->force_phase) || fbm || nc > 1) ? 1 : h->mode_phase;
+    const int mode = ((opt && opt->force_phase) || fbm || nc > 1 || h->arena) ? 1 : h->mode_phase;
+    // static-scratch plans carry every argument in the launches themselves
+    const bool no_tables = h->arena != nullptr;
+    if (no_tables && (pairs.size() != 1 || opt))
+        return fail(h, DIS_EINVAL, "internal: a static-scratch plan holds one pair and no recomputation");
     const int tile_id = mode ? h->refine_tile : DIS_LEVEL_TILE;
     int tw = 32, th = 16, nt = 256;
     dis_refine_tile(tile_id, &tw, &th, &nt);
@@ -670,10 +691,20 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     }
     const size_t sync_off = bytes;
     bytes += sizeof(int) * nsync;
-    HIPCHK(h, hipMalloc(&tabs.mem, bytes));
-    tabs.bytes = bytes;
-    tabs.sync = (int*)((char*)tabs.mem + sync_off);
-    tabs.nsync = nsync;
+    if (no_tables) {
+        // launches below only take table addresses; with one pair in
+        // phase-major order none is dereferenced (LevelLaunch::one)
+        tabs.mem = nullptr;
+        tabs.bytes = 0;
+        tabs.sync = nullptr;
+        tabs.nsync = 0;
+        tabs.err_index.clear();
+    } else {
+        HIPCHK(h, hipMalloc(&tabs.mem, bytes));
+        tabs.bytes = bytes;
+        tabs.sync = (int*)((char*)tabs.mem + sync_off);
+        tabs.nsync = nsync;
+    }
     std::vector<char> host(bytes, 0);
     for (size_t li = 0; li < levels.size(); ++li) {
         LevelHost& LH = levels[li];
@@ -709,11 +740,13 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         std::memcpy(host.data() + off_start[li], start.data(), sizeof(int) * (nseg + 1));
         LevelLaunch LL;
         std::memset(&LL, 0, sizeof LL);
-        LL.pairs = (const LevelPair*)((char*)tabs.mem + off_lp[li]);
-        LL.rph = (const RefPhase*)((char*)tabs.mem + off_rph[li]);
-        LL.start = (const int*)((char*)tabs.mem + off_start[li]);
-        LL.task_seg = (const int*)((char*)tabs.mem + off_tseg[li]);
-        LL.sync = tabs.sync + off_sync[li];
+        if (!no_tables) {
+            LL.pairs = (const LevelPair*)((char*)tabs.mem + off_lp[li]);
+            LL.rph = (const RefPhase*)((char*)tabs.mem + off_rph[li]);
+            LL.start = (const int*)((char*)tabs.mem + off_start[li]);
+            LL.task_seg = (const int*)((char*)tabs.mem + off_tseg[li]);
+            LL.sync = tabs.sync + off_sync[li];
+        }
         LL.npairs = np;
         LL.nph = LH.nph;
         LL.ntasks = t;
@@ -792,7 +825,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             SmallLaunch SL;
             std::memset(&SL, 0, sizeof SL);
             SL.pairs = LL.pairs;
-            SL.list = (const int*)((char*)tabs.mem + off_small[li]);
+            SL.list = no_tables ? nullptr : (const int*)((char*)tabs.mem + off_small[li]);
             SL.n = (int)LH.small.size();
             SL.nouter = p.var_outer < 0 ? LH.s + 1 : p.var_outer;
             SL.nhalf = 2 * p.var_inner;
@@ -807,7 +840,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
                     LH.sfl);
         }
     }
-    HIPCHK(h, hipMemcpy(tabs.mem, host.data(), bytes, hipMemcpyHostToDevice));
+    if (!no_tables) HIPCHK(h, hipMemcpy(tabs.mem, host.data(), bytes, hipMemcpyHostToDevice));
     return DIS_OK;
 }
 

@@ -133,6 +133,11 @@ struct dis_handle {
     int bwd_reference = 0;  // backward: one launch per reverse half sweep instead of reverse tiles
     int no_lin_cache = 0;   // forward refinement recomputes the linearisation in every launch
     int n_cu = 256;
+    // Static-scratch mode: device buffers are carved from [arena, arena +
+    // arena_cap) instead of allocated; plans are single-pair and phase-major,
+    // so no launch reads a device table.
+    char* arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
     // most recent plain forward call (debug and backward)
     bool have_last = false;
     int last_w = 0, last_h = 0, last_ss = 0, last_sf = 0, last_pitch = 0;
@@ -157,6 +162,9 @@ struct dis_handle {
 };
 
 int dis_stride(const dis_params* p);
+int dis_validate_params(const dis_params* p);
+int dis_top_level(const dis_params* p, int max_w, int max_h);
+int dis_alloc_slot(dis_handle* h, SlotBuf& sb);
 // image channels of a parameter block: 3 with DIS_FLAG_COLOUR, else 1
 inline int dis_channels(const dis_params* p) { return (p->flags & DIS_FLAG_COLOUR) ? 3 : 1; }
 int dis_coarsest(const dis_params* p, int w, int h);

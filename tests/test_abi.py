@@ -91,6 +91,19 @@ def test_null_handles():
     assert _lib.dis_last_error()
 
 
+def test_noalloc_call_checks_arguments_before_any_hip_call():
+    lib = _lib.load()
+    assert lib.dis_compute_flow_noalloc(None, None, None, 8, 8, 8, None, None) == _lib.DIS_EINVAL
+    p = params(102)
+    assert lib.dis_compute_flow_noalloc(ctypes.byref(p), None, None, 1024, 436, 1024, None, None) == _lib.DIS_EINVAL
+    p = params(105, flags=_lib.DIS_FLAG_COLOUR)
+    assert lib.dis_compute_flow_noalloc(ctypes.byref(p), 1, 1, 512, 256, 512, 1, None) == _lib.DIS_EINVAL
+    assert "DIS_FLAG_COLOUR" in _lib.dis_last_error()
+    p = params(102)
+    assert lib.dis_compute_flow_noalloc(ctypes.byref(p), 1, 1, 1024, 436, 1000, 1, None) == _lib.DIS_EINVAL
+    assert lib.dis_compute_flow_noalloc(ctypes.byref(p), 1, 1, 40, 40, 40, 1, None) == _lib.DIS_ESIZE
+
+
 def test_product_package_does_not_import_the_oracle():
     pkg = os.path.join(ROOT, "paper_1603_03590_amd")
     for dirpath, _, files in os.walk(pkg):
