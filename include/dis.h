@@ -162,7 +162,10 @@ int dis_compute_flow(dis_handle* h, const void* I0, const void* I1, int w, int h
  * takes work from a queue; the whole batch is replayed as one HIP graph per
  * batch composition.  Each pair's result is bitwise equal to
  * dis_compute_flow on that pair.  Errors as for dis_compute_flow, plus
- * DIS_ESIZE for n > max_batch.
+ * DIS_ESIZE for n > max_batch.  In the persistent launch a task that waits
+ * on its predecessors gives up after a bounded wait (about a second, which
+ * a working queue never reaches); the call then writes NaN into every flow
+ * of the batch, and DIS_DBG_WAIT_ERRORS counts the launches concerned.
  */
 int dis_compute_flow_batched(dis_handle* h, int n, const void* const* I0,
                              const void* const* I1, const int* w, const int* hgt,
@@ -182,9 +185,13 @@ int dis_flow_backward(dis_handle* h, const void* grad_flow, void* grad_I0, void*
 
 /*
  * Time the result-invariant launch choices (lanes per patch in the search,
- * tile shape of the refinement) for the handle's parameters at its maximum
- * size, keep the fastest, and append them to the JSON file `cache_path`
- * (NULL = no file).  Synchronises the stream.  Errors: DIS_EHIP.
+ * tile shape of the refinement, launch modes) on replays of the most recent
+ * forward call on h, keep the fastest, and append them to the JSON file
+ * `cache_path` (NULL = no file).  The replays read that call's frames again
+ * -- they must still be allocated and unchanged -- and write their flow into
+ * temporary buffers of their own (the caller's flow buffers are not
+ * touched).  Synchronises the stream.  Errors: DIS_ESTATE (no forward call
+ * yet), DIS_ENOMEM, DIS_EHIP.
  */
 int dis_autotune(dis_handle* h, const char* cache_path);
 
@@ -206,7 +213,10 @@ int dis_autotune(dis_handle* h, const char* cache_path);
  * one tiled launch per fixed-point step; bit 3 set makes every forward
  * refinement launch recompute the linearisation from the level images
  * instead of the scale's first launch storing it for the later ones (less
- * HBM traffic, more arithmetic per launch).  Every choice gives
+ * HBM traffic, more arithmetic per launch); bit 5 exists to test the
+ * failure path of the persistent launch: every wait there that would block
+ * gives up at once, as a timed-out wait does (the flow becomes NaN).  Every
+ * other choice gives
  * bitwise-identical flow (gradients agree to rounding: they are summed with
  * atomics).  Synchronises the stream and drops cached launch
  * plans.  Errors: DIS_EINVAL.
@@ -282,8 +292,9 @@ typedef struct dis_kernel_stat {
 int dis_profile_enable(dis_handle* h, int on);
 int dis_profile_read(dis_handle* h, dis_kernel_stat* out, int max, int* n);
 
-/* Release the handle and its device memory; NULL is ignored.  Synchronises
- * the handle's stream first, so pending work finishes before memory goes. */
+/* Release the handle and its device memory (allocated once in dis_create,
+ * as Suppl. C describes); NULL is ignored.  Synchronises the handle's stream
+ * first, so pending work finishes before memory goes. */
 void dis_destroy(dis_handle* h);
 
 /*

@@ -84,23 +84,45 @@ class DIS:
         if I0.shape != I1.shape or I0.stride() != I1.stride():
             raise ValueError("frames must have the same shape and strides")
         h, w = I0.shape[-2:]
+        cur = self._enter(I0.device)
         if out is None:
             out = torch.empty((2, h, w), dtype=self.dtype, device=I0.device)
         _lib.dis_compute_flow(self.handle, I0.data_ptr(), I1.data_ptr(), w, h, I0.stride(-2), out.data_ptr())
+        self._leave(cur)
         self._generation = getattr(self, "_generation", 0) + 1
+        self._last_frames = (I0, I1)     # dis_autotune reads them again
         return out
+
+    def _enter(self, device):
+        """The caller's current stream, after making the handle's stream wait
+        for the work queued on it (the frames' producers)."""
+        torch = _torch()
+        cur = torch.cuda.current_stream(device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+        return cur
+
+    def _leave(self, cur):
+        """Order the caller's stream after the handle's work, so that results
+        (and freeing the inputs) follow the kernels that use them."""
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
 
     def flow_batched(self, I0s, I1s, outs=None):
         """Flows of many pairs (lists of device tensors), one launch per level."""
         torch = _torch()
         I0s = [self._frame(a) for a in I0s]
         I1s = [self._frame(b) for b in I1s]
+        cur = self._enter(I0s[0].device) if I0s else None
         if outs is None:
             outs = [torch.empty((2,) + a.shape, dtype=self.dtype, device=a.device) for a in I0s]
         _lib.dis_compute_flow_batched(self.handle, [a.data_ptr() for a in I0s], [b.data_ptr() for b in I1s],
                                       [a.shape[1] for a in I0s], [a.shape[0] for a in I0s],
                                       [a.stride(0) for a in I0s], [o.data_ptr() for o in outs])
+        if cur is not None:
+            self._leave(cur)
         self._generation = getattr(self, "_generation", 0) + 1
+        self._last_frames = (list(I0s), list(I1s))     # dis_autotune reads them again
         return outs
 
     def backward(self, grad_flow, shape=None):
@@ -114,9 +136,11 @@ class DIS:
         if tuple(grad_flow.shape) != (2,) + shape:
             raise ValueError(f"grad_flow has shape {tuple(grad_flow.shape)}, expected {(2,) + shape}")
         gf = grad_flow.contiguous()
+        cur = self._enter(grad_flow.device)
         g0 = torch.empty(shape, dtype=self.dtype, device=grad_flow.device)
         g1 = torch.empty(shape, dtype=self.dtype, device=grad_flow.device)
         _lib.dis_flow_backward(self.handle, gf.data_ptr(), g0.data_ptr(), g1.data_ptr())
+        self._leave(cur)
         self._keep = gf      # alive until the next call on this handle
         return g0, g1
 
@@ -127,6 +151,9 @@ class DIS:
         return _lib.dis_get_tunables(self.handle)
 
     def autotune(self, cache_path=None):
+        """Time the result-invariant launch choices on a replay of the last
+        flow call (its frames, kept alive by this object; the flow it
+        returned is not written) and keep the fastest."""
         _lib.dis_autotune(self.handle, cache_path)
 
     def debug_level(self, s: int, what: int):

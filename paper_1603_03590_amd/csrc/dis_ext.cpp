@@ -88,7 +88,7 @@ static int build_batch(dis_handle* h, int n, const int* w, const int* hgt, const
     std::vector<int> ust{0};
     for (int k = 0; k < n; ++k) {
         Seq tmp;
-        dis_add_upsample(h, *pairs[k].sb, w[k], hgt[k], nullptr, tmp);
+        dis_add_upsample(h, *pairs[k].sb, w[k], hgt[k], nullptr, nullptr, tmp);
         const UpsArgs ua = *(const UpsArgs*)tmp.items[0].arg.data();
         bp->ups.push_back(ua);
         ust.push_back(ust.back() + ((w[k] + 255) / 256) * ((hgt[k] + 3) / 4));
@@ -146,6 +146,8 @@ static int build_batch(dis_handle* h, int n, const int* w, const int* hgt, const
         T0->zero = bp->tabs.sync;
         T0->nzero = bp->tabs.nsync;
     }
+    // a persistent wait that gives up turns every flow of the batch into NaN
+    for (UpsArgs& ua : bp->ups) ua.poison = bp->tabs.plan_err;
     UpsTab UT;
     std::memset(&UT, 0, sizeof UT);
     UT.tab = (const UpsArgs*)((char*)bp->io + bp->ups_off);
@@ -303,9 +305,40 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
         h->last_batch = b0; h->last_batch_I1 = b1; h->last_batch_flow = bf;
         h->last_batch_w = bw; h->last_batch_h = bh; h->last_batch_pitch = bpch;
     };
+    // The replays read the last call's frames (which the caller keeps alive
+    // and unchanged) but write their flow into buffers of their own: the
+    // caller's flow buffers are never touched.
+    const size_t elem = (h->p.flags & DIS_FLAG_IO_F64) ? sizeof(double) : sizeof(float);
+    std::vector<void*> tmp_flow;
+    auto free_tmp = [&]() {
+        hipStreamSynchronize(h->stream);
+        for (void* q : tmp_flow) hipFree(q);
+        tmp_flow.clear();
+    };
+    {
+        const int np = call == 1 ? 1 : (int)b0.size();
+        for (int k = 0; k < np; ++k) {
+            const size_t px = call == 1 ? (size_t)lw * lh : (size_t)bw[k] * bh[k];
+            void* q = nullptr;
+            if (hipMalloc(&q, 2 * px * elem) != hipSuccess) {
+                free_tmp();
+                return dis_fail(h, DIS_ENOMEM, "autotune: no memory for a %zu-pixel flow buffer", px);
+            }
+            tmp_flow.push_back(q);
+        }
+    }
+    void* flow_tmp = call == 1 ? tmp_flow[0] : nullptr;
+    std::vector<void*> bf_tmp = call == 1 ? std::vector<void*>() : tmp_flow;
+    auto restore_tmp = [&]() {
+        restore();
+        h->last_flow = flow_tmp;
+        h->last_batch_flow = bf_tmp;
+    };
     hipEvent_t e0, e1;
-    XHIPCHK(h, hipEventCreate(&e0));
-    XHIPCHK(h, hipEventCreate(&e1));
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        free_tmp();
+        return dis_fail(h, DIS_EHIP, "autotune: hipEventCreate failed");
+    }
     double best = 1e30;
     Cand bestc{0, 0, 1};
     int r = DIS_OK;
@@ -314,11 +347,11 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
         for (int s = 0; s < DIS_MAXL; ++s) lv[s] = c.lpp;
         int rr = dis_set_tunables(h, lv, c.tile, c.mode);
         if (rr != DIS_OK) return rr;
-        for (int i = 0; i < 3 && rr == DIS_OK; ++i) { restore(); rr = replay(); }
+        for (int i = 0; i < 3 && rr == DIS_OK; ++i) { restore_tmp(); rr = replay(); }
         if (rr != DIS_OK) return rr;
         const int reps = 10;
         hipEventRecord(e0, h->stream);
-        for (int i = 0; i < reps && rr == DIS_OK; ++i) { restore(); rr = replay(); }
+        for (int i = 0; i < reps && rr == DIS_OK; ++i) { restore_tmp(); rr = replay(); }
         hipEventRecord(e1, h->stream);
         if (rr != DIS_OK) return rr;
         hipEventSynchronize(e1);
@@ -337,6 +370,7 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
     if (r == DIS_OK) r = measure(Cand{0, 0, 0});
     for (int l : lpps)
         if (r == DIS_OK && dis_kernel_level(h->p.patch_size, l)) r = measure(Cand{l, 0, 0});
+    free_tmp();
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     h->p.flags = (uint32_t)save_flags;

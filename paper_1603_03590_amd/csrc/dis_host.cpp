@@ -335,7 +335,7 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     int tw, th;
     if (!dis_refine_tile(refine_tile, &tw, &th, nullptr))
         return fail(h, DIS_EINVAL, "unknown refinement tile %d", refine_tile);
-    if (launch_mode < 0 || launch_mode > 31) return fail(h, DIS_EINVAL, "launch mode %d outside 0..31", launch_mode);
+    if (launch_mode < 0 || launch_mode > 63) return fail(h, DIS_EINVAL, "launch mode %d outside 0..63", launch_mode);
     if (lanes_per_patch)
         for (int s = 0; s < DIS_MAXL; ++s) {
             const int l = lanes_per_patch[s];
@@ -349,6 +349,7 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     h->small_levels = (launch_mode & 2) ? ((launch_mode & 16) ? 2 : 1) : 0;
     h->bwd_reference = (launch_mode & 4) ? 1 : 0;
     h->no_lin_cache = (launch_mode & 8) ? 1 : 0;
+    h->fail_waits = (launch_mode & 32) ? 1 : 0;
     return DIS_OK;
 }
 
@@ -359,7 +360,7 @@ extern "C" int dis_get_tunables(const dis_handle* h, int* lanes_per_patch, int* 
     if (refine_tile) *refine_tile = h->refine_tile;
     if (launch_mode)
         *launch_mode = h->mode_phase | (h->small_levels ? 2 : 0) | (h->bwd_reference ? 4 : 0) | (h->no_lin_cache ? 8 : 0) |
-                       (h->small_levels == 2 ? 16 : 0);
+                       (h->small_levels == 2 ? 16 : 0) | (h->fail_waits ? 32 : 0);
     return DIS_OK;
 }
 
@@ -484,7 +485,7 @@ int dis_add_pyramid(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, int s
     return DIS_OK;
 }
 
-void dis_add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, Seq& seq) {
+void dis_add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, const int* poison, Seq& seq) {
     const dis_params& p = h->p;
     const int sf = p.finest_scale;
     const bool f64io = (p.flags & DIS_FLAG_IO_F64) != 0;
@@ -499,6 +500,7 @@ void dis_add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, Se
     ua.centre_map = (p.flags & DIS_FLAG_PIXEL_CENTRE) ? 1 : 0;
     ua.out = flow;
     ua.out_f64 = f64io ? 1 : 0;
+    ua.poison = poison;
     seq.add(dis_kernel_upsample(), dim3((w + 255) / 256, (hgt + 3) / 4), dim3(256), &ua, sizeof ua, 2, "upsample",
             16.0 * ua.Ws * ua.Hs + (f64io ? 16.0 : 8.0) * w * hgt, 20.0 * w * hgt);
 }
@@ -689,6 +691,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         tabs.err_index.push_back(nsync + 1);
         nsync += 2 + nseg;
     }
+    const int plan_err_index = nsync++;
     const size_t sync_off = bytes;
     bytes += sizeof(int) * nsync;
     if (no_tables) {
@@ -704,6 +707,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         tabs.bytes = bytes;
         tabs.sync = (int*)((char*)tabs.mem + sync_off);
         tabs.nsync = nsync;
+        tabs.plan_err = tabs.sync + plan_err_index;
     }
     std::vector<char> host(bytes, 0);
     for (size_t li = 0; li < levels.size(); ++li) {
@@ -746,7 +750,9 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             LL.start = (const int*)((char*)tabs.mem + off_start[li]);
             LL.task_seg = (const int*)((char*)tabs.mem + off_tseg[li]);
             LL.sync = tabs.sync + off_sync[li];
+            LL.plan_err = tabs.plan_err;
         }
+        LL.fail_waits = h->fail_waits;
         LL.npairs = np;
         LL.nph = LH.nph;
         LL.ntasks = t;
@@ -861,7 +867,7 @@ int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const 
     if (p.flags & DIS_FLAG_FB_CONSISTENCY) pr.push_back(PairRef{&h->slots[1], w, hgt, ss});
     r = dis_build_levels(h, pr, seq, tabs, nullptr);
     if (r != DIS_OK) return r;
-    dis_add_upsample(h, sb, w, hgt, flow, seq);
+    dis_add_upsample(h, sb, w, hgt, flow, tabs.plan_err, seq);
     // the first pyramid launch clears the level launches' queue state
     PyrArgs* pa = (PyrArgs*)seq.items[first].arg.data();
     pa->zero = tabs.sync;

@@ -77,6 +77,7 @@ struct PlanTables {
     int* sync = nullptr;    // queue state of every level launch, cleared by the first pyramid launch
     int nsync = 0;
     std::vector<int> err_index;   // wait-timeout flag of each level launch inside sync
+    int* plan_err = nullptr;      // inside sync: set by any level launch whose wait gave up (flows become NaN)
 };
 
 struct PairRef {
@@ -132,6 +133,7 @@ struct dis_handle {
     int small_levels = 0;   // single-launch refinement of scales of <= 256 (1) or <= 1024 (2) pixel pairs
     int bwd_reference = 0;  // backward: one launch per reverse half sweep instead of reverse tiles
     int no_lin_cache = 0;   // forward refinement recomputes the linearisation in every launch
+    int fail_waits = 0;     // failure-path testing: persistent waits that would block give up at once
     int n_cu = 256;
     // Static-scratch mode: device buffers are carved from [arena, arena +
     // arena_cap) instead of allocated; plans are single-pair and phase-major,
@@ -192,6 +194,6 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
 void dis_refine_phases(const dis_params& p, int s, std::vector<RefPhase>& out);
 int dis_add_pyramid(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, int ss, const void* I0, const void* I1,
                     Seq& seq);
-void dis_add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, Seq& seq);
+void dis_add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, const int* poison, Seq& seq);
 int dis_fail(dis_handle* h, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 int dis_launch_eager(dis_handle* h, Seq& seq);

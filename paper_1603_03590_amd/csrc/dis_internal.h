@@ -104,6 +104,7 @@ struct UpsArgs {
     int centre_map;
     void* out;
     int out_f64;
+    const int* poison;      // non-null and set: a persistent wait of this plan gave up, the flow is written as NaN
 };
 
 // One pair at one level inside a persistent level launch.  Its work is a
@@ -134,6 +135,8 @@ struct LevelLaunch {
     const int* start;       // [nph * npairs + 1] first task of each segment
     const int* task_seg;    // [ntasks] segment of each task (phase * npairs + pair)
     int* sync;              // [0] queue head, [1] wait-timeout flag, [2 + seg] finished tasks
+    int* plan_err;          // every level launch of the plan sets this too when a wait gives up
+    int fail_waits;         // failure-path testing: every wait of a later phase gives up at once
     int npairs, nph, ntasks;
     int lin_cache;          // 1: a level's first refinement launch stores the linearisation, later ones load it
     // With one pair its arguments also travel in the launch itself: a

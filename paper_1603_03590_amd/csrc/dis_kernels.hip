@@ -1035,6 +1035,10 @@ __device__ __forceinline__ void upsample_block(const UpsArgs& a, int bx, int by)
         v4[k] = f * ((1.0 - ay) * vt + ay * vb);
     }
     const size_t n = (size_t)a.W * a.H;
+    if (a.poison && __builtin_amdgcn_readfirstlane(*dis_global(a.poison)) != 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u4[k] = v4[k] = __builtin_nan("");
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int x = bx * 256 + k * 64 + (int)(threadIdx.x & 63);
@@ -1359,16 +1363,29 @@ __device__ __attribute__((noinline)) void lane0_take(int* head, int* s_task) {
     if (threadIdx.x == 0) *s_task = __hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __attribute__((noinline)) void lane0_wait(const int* ctr, int need, int* err, int* s_ok) {
+// A wait that gives up marks its launch (err) and the whole plan (plan_err):
+// the task is skipped, and the upscaling then writes the plan's flows as NaN,
+// so a failed wait cannot pass as a result.  `give_up` makes every wait on
+// a predecessor fail at once (the host forces it to test this path; every
+// kernel still runs to its end).
+__device__ __attribute__((noinline)) void lane0_wait(const int* ctr, int need, int* err, int* plan_err, int give_up,
+                                                     int* s_ok) {
     if (threadIdx.x == 0) {
         int ok = 1, spins = 0;
-        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > kSpinLimit) {
-                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
+        if (give_up && need > 0) {
+            ok = 0;
+        } else {
+            while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                if (++spins > kSpinLimit) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
             }
+        }
+        if (!ok) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (plan_err) __hip_atomic_store(plan_err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         *s_ok = ok;
     }
@@ -1401,7 +1418,7 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
         const int local = t - __builtin_amdgcn_readfirstlane(L.start[seg]);
         const int prev = phase > 0 ? seg - L.npairs : seg;
         const int need = phase > 0 ? __builtin_amdgcn_readfirstlane(L.start[prev + 1] - L.start[prev]) : 0;
-        lane0_wait(done + prev, need, err, &s_ok);
+        lane0_wait(done + prev, need, err, L.plan_err, L.fail_waits, &s_ok);
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const int ok = __builtin_amdgcn_readfirstlane(s_ok);

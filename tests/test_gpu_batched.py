@@ -144,6 +144,69 @@ def test_autotune_keeps_results_and_writes_cache(tmp_path):
         d.close()
 
 
+def test_persistent_wait_failure_poisons_the_flow():
+    """A persistent-launch wait that gives up (forced from the host: launch
+    mode bit 5 makes every wait on a predecessor fail at once, as a timed-out
+    wait would; every kernel still runs to its end) must not pass as a
+    result: every flow of the call is NaN and the wait-error count is set.
+    The next normal call on the same handle is back to the plain result."""
+    say("[batched] forced wait failures in the persistent launch (host flag, kernels exit normally)")
+    prs = batch_pairs()[:2]
+    p = params(106)
+    ref = plain(prs, p)
+    d = DIS(p, 1024, 480, max_batch=2)
+    try:
+        I0 = [torch.from_numpy(pr.I0).cuda() for pr in prs]
+        I1 = [torch.from_numpy(pr.I1).cuda() for pr in prs]
+        d.set_tunables(None, 0, 0 | 32)
+        outs = d.flow_batched(I0, I1)
+        torch.cuda.synchronize()
+        assert d.debug_level(3, _lib.DIS_DBG_WAIT_ERRORS) > 0
+        for o in outs:
+            assert torch.isnan(o).all()
+        # the plain call's persistent form poisons its flow the same way
+        h, w = prs[0].I0.shape
+        dp = DIS(p, w, h)
+        try:
+            dp.set_tunables(None, 0, 0 | 32)
+            o = dp.flow(I0[0], I1[0])
+            torch.cuda.synchronize()
+            assert torch.isnan(o).all()
+            dp.set_tunables(None, 0, 0)
+            o = dp.flow(I0[0], I1[0])
+            torch.cuda.synchronize()
+            assert np.array_equal(o.cpu().numpy(), ref[0])
+        finally:
+            dp.close()
+        d.set_tunables(None, 0, 0)
+        outs = d.flow_batched(I0, I1)
+        torch.cuda.synchronize()
+        assert d.debug_level(3, _lib.DIS_DBG_WAIT_ERRORS) == 0
+        for k, o in enumerate(outs):
+            assert np.array_equal(o.cpu().numpy(), ref[k])
+    finally:
+        d.close()
+
+
+def test_autotune_leaves_caller_buffers_alone():
+    """The autotuner replays the last call into buffers of its own: the flow
+    the caller holds (here overwritten with a marker) is not written."""
+    say("[autotune] replays do not write the caller's flow")
+    pr = batch_pairs()[0]
+    p = params(106)
+    h, w = pr.I0.shape
+    d = DIS(p, w, h)
+    try:
+        out = d.flow(torch.from_numpy(pr.I0).cuda(), torch.from_numpy(pr.I1).cuda())
+        torch.cuda.synchronize()
+        out.fill_(-7.0)
+        d.autotune()
+        torch.cuda.synchronize()
+        assert (out == -7.0).all()
+    finally:
+        d.close()
+
+
 def test_batched_errors():
     say("[batched] argument errors")
     d = DIS(params(106), 320, 240, max_batch=2)
