@@ -96,6 +96,16 @@ def main():
     ap.add_argument("--tunables", default="",
                     help="skip the autotuner and fix the launch choices of the headline, e.g. 'tile=7,mode=1,lanes=16' "
                          "(for counter runs, where the profiler's serialisation would mislead the autotuner)")
+    ap.add_argument("--only", default="all", choices=["all", "headline", "batched", "fwd_bwd", "hq"],
+                    help="measure one part only (for profiler runs); 'headline' is --headline-only")
+    ap.add_argument("--batch-tunables", default="",
+                    help="skip the batch's autotuner and untuned timings and fix its launch choices, "
+                         "e.g. 'tile=6,mode=1,lanes=0' (for counter runs)")
+    ap.add_argument("--hq-tunables", default="",
+                    help="skip the high-quality handles' autotuner and fix their launch choices (counter runs)")
+    ap.add_argument("--hq-only", default="", help="run only this high-quality pair (c3a_1024x436 or c3b_2048x1024)")
+    ap.add_argument("--fb-tunables", default="",
+                    help="skip the forward+backward handles' autotuner and fix their launch choices (counter runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB five times (calibrates HBM counters)")
     ap.add_argument("--hq-steps", type=int, default=20,
@@ -107,6 +117,9 @@ def main():
     ap.add_argument("--fwd-bwd-pairs", type=int, default=8,
                     help="pairs of 512x256 in the forward+backward measurement (0 skips it)")
     args = ap.parse_args()
+    if args.only == "headline":
+        args.headline_only = True
+    part = lambda name: args.only in ("all", name)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py measures one GPU: this build has no multi-GPU path (pairs would shard across GPUs "
             "with no exchange); run it with --gpus 1")
@@ -132,7 +145,7 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy probe: 5 copies of {args.copy_probe_mib} MiB")
         del src, dst
-    for op in ((args.op,) if args.headline_only else (args.op, other)):
+    for op in (() if not part("headline") else (args.op,) if args.headline_only else (args.op, other)):
         p = params(presets[op])
         d = DIS(p, W, H)
         out = torch.empty((2, H, W), device="cuda")
@@ -166,35 +179,38 @@ def main():
         results[op] = dict(ms=dt * 1e3, modes=modes, flow=f_tuned, kernels=kstats, tuned=tuned)
         log(f"[bench] {op}: tuned {dt * 1e3:.4f} ms/pair; untuned {modes}")
 
-    head = results[args.op]
-    mpix = W * H / (head["ms"] * 1e-3) / 1e6
-    # the paper's flow-only convention leaves out the pyramid (event-timed per step)
-    pyr_ms = sum(k["total_ms"] for k in head["kernels"] if k["name"] == "pyramid") / args.profile_steps
-    flow_only = dict(ms_per_step=head["ms"] - pyr_ms, value=W * H / ((head["ms"] - pyr_ms) * 1e-3) / 1e6,
-                     unit="Mpix/s", excluded="pyramid (the Sobel gradients are computed inside the search)")
-    roof, top, avg_ms = roofline_of(head["kernels"])
-    # HBM traffic per launch of that kernel family, from the committed
-    # counter summary when it was taken on these kernel sources with this
-    # refinement tile (else null)
-    traffic = None
-    traffic_src = None
-    from paper_1603_03590_amd import profsum
-    is_ref = top["name"] == "refine"
-    rec = profsum.read_traffic(os.path.join(ROOT, "profiles", f"{top['name']}_c2a_1024x436_hbm_traffic.md"),
-                               tile=head["tuned"]["refine_tile"] if is_ref else None,
-                               mode=head["tuned"]["launch_mode"] if is_ref else None)
-    if rec and rec.get("source_sha") == profsum.source_hash():
-        traffic = float(rec["bytes_per_launch"])
-        traffic_src = f"profiles/{top['name']}_c2a_1024x436_hbm_traffic.md"
-    roof.update(traffic=traffic, traffic_source=traffic_src, kernel=top["name"],
-                launches_per_step=top["launches"] / args.profile_steps,
-                avg_launch_us=avg_ms * 1e3, algorithmic_bytes_per_launch=top["bytes"] / top["launches"],
-                algorithmic_flops_per_launch=top["flops"] / top["launches"])
+    if not part("headline"):
+        head = None
+    else:
+        head = results[args.op]
+        mpix = W * H / (head["ms"] * 1e-3) / 1e6
+        # the paper's flow-only convention leaves out the pyramid (event-timed per step)
+        pyr_ms = sum(k["total_ms"] for k in head["kernels"] if k["name"] == "pyramid") / args.profile_steps
+        flow_only = dict(ms_per_step=head["ms"] - pyr_ms, value=W * H / ((head["ms"] - pyr_ms) * 1e-3) / 1e6,
+                         unit="Mpix/s", excluded="pyramid (the Sobel gradients are computed inside the search)")
+        roof, top, avg_ms = roofline_of(head["kernels"])
+        # HBM traffic per launch of that kernel family, from the committed
+        # counter summary when it was taken on these kernel sources with this
+        # refinement tile (else null)
+        traffic = None
+        traffic_src = None
+        from paper_1603_03590_amd import profsum
+        is_ref = top["name"] == "refine"
+        rec = profsum.read_traffic(os.path.join(ROOT, "profiles", f"{top['name']}_c2a_1024x436_hbm_traffic.md"),
+                                   tile=head["tuned"]["refine_tile"] if is_ref else None,
+                                   mode=head["tuned"]["launch_mode"] if is_ref else None)
+        if rec and rec.get("source_sha") == profsum.source_hash():
+            traffic = float(rec["bytes_per_launch"])
+            traffic_src = f"profiles/{top['name']}_c2a_1024x436_hbm_traffic.md"
+        roof.update(traffic=traffic, traffic_source=traffic_src, kernel=top["name"],
+                    launches_per_step=top["launches"] / args.profile_steps,
+                    avg_launch_us=avg_ms * 1e3, algorithmic_bytes_per_launch=top["bytes"] / top["launches"],
+                    algorithmic_flops_per_launch=top["flops"] / top["launches"])
 
     # batched: 64 pairs of uneven sizes, one call per step
     batched = None
     bpairs = []
-    if args.batch > 0:
+    if args.batch > 0 and part("batched"):
         sizes = synth.batch_sizes(args.batch, 4000)
         t0 = time.perf_counter()
         with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
@@ -209,11 +225,16 @@ def main():
         bout = [torch.empty((2,) + a.shape, device="cuda") for a in bI0]
         call = lambda: d.flow_batched(bI0, bI1, bout)
         bmodes = {}
-        for name, mode in (("phase", 1), ("persistent", 0)):
-            d.set_tunables(None, 0, mode)
-            bmodes[name] = time_calls(call, max(5, args.steps // 20), 3) * 1e3
-        call()
-        d.autotune()
+        if args.batch_tunables:
+            kv = dict(x.split("=") for x in args.batch_tunables.split(","))
+            lanes = int(kv.get("lanes", 0))
+            d.set_tunables([lanes] * 16 if lanes else None, int(kv.get("tile", 7)), int(kv.get("mode", 1)))
+        else:
+            for name, mode in (("phase", 1), ("persistent", 0)):
+                d.set_tunables(None, 0, mode)
+                bmodes[name] = time_calls(call, max(5, args.steps // 20), 3) * 1e3
+            call()
+            d.autotune()
         bdt = time_calls(call, max(10, args.steps // 10), 3)
         torch.cuda.synchronize()
         # per-kernel event timing of the tuned batch (launches one by one)
@@ -225,6 +246,18 @@ def main():
         bstats = _lib.dis_profile_read(d.handle)
         _lib.dis_profile_enable(d.handle, False)
         broof, btop, bavg = roofline_of(bstats)
+        # counter bytes per launch of that kernel family in the committed
+        # summary of this batch, while the sources and launch choices match
+        from paper_1603_03590_amd import profsum
+        btuned = d.tunables()
+        b_is_ref = btop["name"] == "refine"
+        bpath = f"profiles/{btop['name']}_c4_batch{args.batch}_hbm_traffic.md"
+        brec = profsum.read_traffic(os.path.join(ROOT, bpath), tile=btuned["refine_tile"] if b_is_ref else None,
+                                    mode=btuned["launch_mode"] if b_is_ref else None)
+        btraffic = None
+        if brec and brec.get("source_sha") == profsum.source_hash():
+            btraffic = float(brec["bytes_per_launch"])
+        broof.update(traffic=btraffic, traffic_source=bpath if btraffic is not None else None)
         broof.update(kernel=btop["name"], avg_launch_us=bavg * 1e3,
                      algorithmic_bytes_per_launch=btop["bytes"] / btop["launches"],
                      algorithmic_flops_per_launch=btop["flops"] / btop["launches"])
@@ -258,7 +291,7 @@ def main():
     # own HIP graphs
     fwd_bwd = None
     fb_check = None
-    if args.fwd_bwd_pairs > 0:
+    if args.fwd_bwd_pairs > 0 and part("fwd_bwd"):
         from paper_1603_03590_amd import dis_flow
         nfb = args.fwd_bwd_pairs
         fbp = [synth.smooth_bump_pair(512, 256, 16.0, 2000 + k) for k in range(nfb)]
@@ -292,7 +325,12 @@ def main():
 
         f_step()
         for d_ in hs:
-            d_.autotune()
+            if args.fb_tunables:
+                kv = dict(x.split("=") for x in args.fb_tunables.split(","))
+                lanes = int(kv.get("lanes", 0))
+                d_.set_tunables([lanes] * 16 if lanes else None, int(kv.get("tile", 7)), int(kv.get("mode", 1)))
+            else:
+                d_.autotune()
         torch.cuda.synchronize()
 
         fsteps = max(10, args.steps // 5)
@@ -320,7 +358,7 @@ def main():
         pix = nfb * 512 * 256
         fwd_bwd = dict(value=pix / t_fb / 1e6, unit="Mpix/s", ms_per_step=t_fb * 1e3, pairs=nfb,
                        forward_only=dict(value=pix / t_f / 1e6, ms_per_step=t_f * 1e3),
-                       mean_epe_px=mean_epe, dtype_io="f32", streams=nfb,
+                       mean_epe_px=mean_epe, dtype_io="f32", streams=nfb, tunables=hs[0].tunables(),
                        kernels=kernel_table(list(fb_k.values()), 3),
                        workload=f"{nfb} pairs 512x256 float32, smooth-bump generator (max 16 px, seeds "
                                 f"2000..{2000 + nfb - 1}); patch 8, overlap 0.5, scales 3..0, "
@@ -335,16 +373,23 @@ def main():
     # scales 4..0, theta_vo 5): the search's arithmetic dominates, so its
     # kernel's fp64 rate is the meaningful roofline there
     hq = {}
-    if not args.headline_only and args.hq_steps > 0:
+    if part("hq") and not args.headline_only and args.hq_steps > 0:
         for name, (w_, h_, seed) in (("c3a_1024x436", (1024, 436, 3)), ("c3b_2048x1024", (2048, 1024, 4))):
+            if args.hq_only and name != args.hq_only:
+                continue
             q = synth.layered_pair(w_, h_, 200.0, seed)
             d = DIS(params(104), w_, h_)
             a = torch.from_numpy(q.I0).cuda()
             b = torch.from_numpy(q.I1).cuda()
             o = torch.empty((2, h_, w_), device="cuda")
             call = lambda: d.flow(a, b, o)
-            call()
-            d.autotune()
+            if args.hq_tunables:
+                kv = dict(x.split("=") for x in args.hq_tunables.split(","))
+                lanes = int(kv.get("lanes", 0))
+                d.set_tunables([lanes] * 16 if lanes else None, int(kv.get("tile", 7)), int(kv.get("mode", 1)))
+            else:
+                call()
+                d.autotune()
             t = time_calls(call, args.hq_steps, 3)
             _lib.dis_profile_enable(d.handle, True)
             call()
@@ -367,7 +412,7 @@ def main():
     # operating point: robust norms, stereo, forward-backward consistency,
     # colour frames; autotuned, graph replay, frames resident in HBM
     ext = {}
-    if not args.headline_only and args.ext_steps > 0:
+    if args.only == "all" and not args.headline_only and args.ext_steps > 0:
         hb = synth.smooth_bump_pair(W, H, 40.0, 2, horizontal=True)
         cb = synth.smooth_bump_pair(W, H, 40.0, 2, channels=3)
         cases = [
@@ -501,6 +546,12 @@ def main():
     for e in list(ext.values()) + list(hq.values()):
         e.pop("_flow")
         e.pop("_case")
+
+    if head is None:
+        # a part measured on its own (profiler runs): no headline line
+        print(json.dumps({"only": args.only, "batched": batched, "fwd_bwd": fwd_bwd, "high_quality": hq or None}),
+              flush=True)
+        return
 
     cfg = dict(
         workload=f"plain DIS, one {W}x{H} grayscale float32 pair: layered scene (background + 6 textured "
