@@ -281,7 +281,7 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
     // the search's lanes per patch and the refinement tile touch different
     // kernels of a phase-major launch, so they are tuned one after the other;
     // the persistent launch (fixed tile) is tried with every lane count
-    const int lpps[5] = {4, 8, 16, 32, 64};
+    const int lpps[7] = {1, 2, 4, 8, 16, 32, 64};
     const int save_flags = (int)h->p.flags;
     h->p.flags &= ~DIS_FLAG_NO_GRAPH;   // time what callers run: graph replay
     auto replay = [&]() -> int {
@@ -363,13 +363,15 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
     for (int t = 0; t < DIS_NUM_TILES && r == DIS_OK; ++t) r = measure(Cand{0, t, 1});
     const int tile = bestc.tile;
     for (int l : lpps)
-        if (r == DIS_OK && dis_kernel_phase_search(h->p.patch_size, l)) r = measure(Cand{l, tile, 1});
+        if (r == DIS_OK && dis_search_has_lanes(&h->p, l)) r = measure(Cand{l, tile, 1});
     if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, 3});    // single-workgroup scales of <= 256 pairs
     if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, 19});   // ... of <= 1024 pairs
     if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, bestc.mode | 8});   // no linearisation cache
     if (r == DIS_OK) r = measure(Cand{0, 0, 0});
     for (int l : lpps)
-        if (r == DIS_OK && dis_kernel_level(h->p.patch_size, l)) r = measure(Cand{l, 0, 0});
+        if (r == DIS_OK && dis_search_has_lanes(&h->p, l) &&
+            (dis_search_rows_path(&h->p) ? dis_kernel_level_rows(h->p.patch_size, l) : dis_kernel_level(h->p.patch_size, l)))
+            r = measure(Cand{l, 0, 0});
     free_tmp();
     hipEventDestroy(e0);
     hipEventDestroy(e1);

@@ -339,7 +339,8 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     if (lanes_per_patch)
         for (int s = 0; s < DIS_MAXL; ++s) {
             const int l = lanes_per_patch[s];
-            if (l != 0 && !dis_kernel_phase_search(h->p.patch_size, l))
+            if (l != 0 && !dis_kernel_phase_search(h->p.patch_size, l) &&
+                !dis_kernel_phase_search_rows(h->p.patch_size, l))
                 return fail(h, DIS_EINVAL, "no search kernel for patch %d with %d lanes", h->p.patch_size, l);
         }
     drop_plans(h);
@@ -386,11 +387,32 @@ void Seq::add(const void* fn, dim3 grid, dim3 block, const void* arg, size_t byt
     items.push_back(std::move(L));
 }
 
+// Grey frames with the L2 norm take the row-owned search where a layout is
+// compiled for the patch size; colour frames and the robust norms the
+// per-pixel one.
+bool dis_search_rows_path(const dis_params* p) {
+    if (dis_channels(p) != 1 || p->norm != DIS_NORM_L2) return false;
+    for (int l = 1; l <= 16; l <<= 1)
+        if (dis_kernel_phase_search_rows(p->patch_size, l)) return true;
+    return false;
+}
+
+// Is `lpp` a lanes-per-patch count of the search this parameter block uses?
+bool dis_search_has_lanes(const dis_params* p, int lpp) {
+    return dis_search_rows_path(p) ? dis_kernel_phase_search_rows(p->patch_size, lpp) != nullptr
+                                   : dis_kernel_phase_search(p->patch_size, lpp) != nullptr;
+}
+
 int dis_pick_lpp(const dis_handle* h, int s) {
     const int ps = h->p.patch_size;
-    if (h->lpp[s] && dis_kernel_phase_search(ps, h->lpp[s])) return h->lpp[s];
+    // a requested count the search was not compiled for falls back to the default
+    if (h->lpp[s] && dis_search_has_lanes(&h->p, h->lpp[s])) return h->lpp[s];
     // the most lanes compiled for the patch size: the shortest dependent chain
-    // per patch pays at every size measured (the autotuner tries the others)
+    // per patch (the autotuner tries the others)
+    if (dis_search_rows_path(&h->p)) {
+        for (int l = 16; l >= 1; l >>= 1)
+            if (dis_kernel_phase_search_rows(ps, l)) return l;
+    }
     for (int l = 64; l > 16; l >>= 1)
         if (dis_kernel_phase_search(ps, l)) return l;
     return 16;
@@ -658,9 +680,13 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     std::vector<int> off_sync;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     // tasks (blocks) of segment (phase ph, pair j) of a level
+    // the row-owned search runs one wave per block in its own launch, and
+    // 256 threads per task inside the persistent level kernel
+    const bool rows = nc == 1 && dis_search_rows_path(&p);
+    const int sblock = (rows && mode == 1) ? 64 : 256;
     auto seg_count = [&](const LevelHost& LH, int ph, int j) {
         const LevelPair& P = LH.lp[j];
-        if (ph == 0) return (P.sa.nx * P.sa.ny * LH.lpp + 255) / 256;
+        if (ph == 0) return (P.sa.nx * P.sa.ny * LH.lpp + sblock - 1) / sblock;
         if (LH.is_small[j]) return 0;   // densified and refined by the single-workgroup launch
         if (ph == 1) return P.dens_bx * ((P.da.H + 3) / 4);
         return P.ra.tiles_x * ((P.ra.H + th - 1) / th);
@@ -765,21 +791,22 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             LL.dens_bx1 = LH.lp[0].dens_bx;
         }
         if (mode == 0) {
-            const void* fn = dis_kernel_level(ps, LH.lpp);
+            const void* fn = rows ? dis_kernel_level_rows(ps, LH.lpp) : dis_kernel_level(ps, LH.lpp);
             if (!fn) return fail(h, DIS_EINVAL, "no level kernel for patch %d, %d lanes", ps, LH.lpp);
             double by = 0.0, fl = 0.0;
             for (int ph = 0; ph < LH.nph; ++ph) { by += ph_by[ph]; fl += ph_fl[ph]; }
             const int grid = std::max(1, std::min(t, h->n_cu * 2));
             seq.add(fn, dim3(grid), dim3(256), &LL, sizeof LL, 0, "level", by, fl);
         } else {
-            const void* fs = nc > 1 ? dis_kernel_phase_search_colour(ps) : dis_kernel_phase_search(ps, LH.lpp);
+            const void* fs = nc > 1 ? dis_kernel_phase_search_colour(ps)
+                             : rows ? dis_kernel_phase_search_rows(ps, LH.lpp) : dis_kernel_phase_search(ps, LH.lpp);
             if (!fs) return fail(h, DIS_EINVAL, "no search kernel for patch %d, %d lanes", ps, LH.lpp);
             for (int ph = 0; ph < LH.nph; ++ph) {
                 const int n = start[(ph + 1) * np] - start[ph * np];
                 if (n == 0) continue;
                 if (ph == 0) {
                     if (opt && opt->skip_search) continue;
-                    seq.add(fs, dim3(n), dim3(256), &LL, sizeof LL, 0, "search", ph_by[0], ph_fl[0]);
+                    seq.add(fs, dim3(n), dim3(sblock), &LL, sizeof LL, 0, "search", ph_by[0], ph_fl[0]);
                 } else if (ph == 1 && fbm) {
                     // merged densification of both directions (App. B ii):
                     // bin each direction's patches by displaced corner, then gather

@@ -172,6 +172,8 @@ inline int dis_channels(const dis_params* p) { return (p->flags & DIS_FLAG_COLOU
 int dis_coarsest(const dis_params* p, int w, int h);
 void dis_grid(int n, int ps, int st, int* nr, int* ntot);
 int dis_pick_lpp(const dis_handle* h, int s);
+bool dis_search_rows_path(const dis_params* p);
+bool dis_search_has_lanes(const dis_params* p, int lpp);
 int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const void* I0, const void* I1,
                    void* flow, Seq& seq, PairInfo* info, PlanTables& tabs);
 // Options of dis_build_levels for the backward pass's recomputation.

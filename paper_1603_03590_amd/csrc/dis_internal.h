@@ -287,6 +287,10 @@ const void* dis_kernel_colour_lin();                   // LevelLaunch of one pai
 const void* dis_kernel_phase_search_colour(int ps);    // 3 channels; null when not compiled
 int dis_colour_lanes(int ps);                          // its lanes per patch
 const void* dis_kernel_level(int ps, int lpp);          // persistent level kernel, null when not compiled
+// the row-owned search of grey frames with the L2 norm (64-thread blocks)
+// and its persistent level kernel; null when no layout has lpp lanes
+const void* dis_kernel_phase_search_rows(int ps, int lpp);
+const void* dis_kernel_level_rows(int ps, int lpp);
 // refinement core tile (width, height, threads per block) of a tile id;
 // returns 0 for an unknown id
 int dis_refine_tile(int tile, int* tw, int* th, int* nt);

@@ -487,6 +487,8 @@ __device__ __forceinline__ void search_block(const SearchArgs& a, int block) {
     }
 }
 
+#include "dis_search_rows.h"
+
 // ------------------------------------------------------------ densification
 
 __device__ __forceinline__ void cover_range(int x, int n, int ps, int st, int nr, int ntot,
@@ -957,6 +959,23 @@ __global__ __launch_bounds__(256) void k_phase_search(const LevelLaunch L) {
     search_block<PS, LPP, NC>(sa, local);
 }
 
+// Row-owned search (grey frames, L2 norm), one wave per block.
+template <int PS, int NRB, int NH, int R>
+__global__ __launch_bounds__(64) void k_phase_search_rows(const LevelLaunch L) {
+    __shared__ double s_win[(64 / (NRB * NH)) * RowWin<PS, R>::SIZE];
+    const int t = blockIdx.x;                       // phase 0 starts at task 0
+    SearchArgs sa;
+    int local = t;
+    if (L.one) {
+        sa = L.sa1;
+    } else {
+        const int j = __builtin_amdgcn_readfirstlane(L.task_seg[t]);
+        sa = L.pairs[j].sa;
+        local = t - __builtin_amdgcn_readfirstlane(L.start[j]);
+    }
+    search_rows<PS, NRB, NH, R, 64>(sa, local, s_win);
+}
+
 template <bool COLOUR = false>
 __global__ __launch_bounds__(256) void k_phase_densify(const LevelLaunch L) {
     DensifyArgs da;
@@ -1398,10 +1417,17 @@ __device__ __attribute__((noinline)) void lane0_signal(int* ctr) {
 // Every pair's work at one level as one launch.  Blocks take tasks from the
 // queue in order; a task of phase p of pair j first waits until phase p-1 of
 // pair j has finished (all those tasks were taken earlier, by running blocks).
-template <int PS, int LPP>
+// RNRB > 0: the search is the row-owned one (layout RNRB x RNH, window
+// radius RR), whose windows share LDS with the refinement tile.
+template <int PS, int LPP, int RNRB = 0, int RNH = 0, int RR = 0>
 __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
     static_assert(DIS_LEVEL_TILE == 0, "the level kernel refines 32x16 tiles");
-    __shared__ RefineSmem<32, 16> sm;
+    constexpr int WIN = RNRB > 0 ? (256 / LPP) * RowWin<PS, RR>::SIZE : 1;
+    __shared__ union LevelSmem {
+        RefineSmem<32, 16> r;
+        double win[WIN];
+    } smu;
+    RefineSmem<32, 16>& sm = smu.r;
     __shared__ int s_task, s_ok;
     int* head = L.sync;
     int* err = L.sync + 1;
@@ -1425,7 +1451,8 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
         const LevelPair& P = L.pairs[pair];
         if (ok) {
             if (phase == 0) {
-                search_block<PS, LPP>(P.sa, local);
+                if constexpr (RNRB > 0) search_rows<PS, RNRB, RNH, RR, 256>(P.sa, local, smu.win);
+                else search_block<PS, LPP>(P.sa, local);
             } else if (phase == 1) {
                 densify_block(P.da, local % P.dens_bx, local / P.dens_bx);
             } else {
@@ -1494,6 +1521,37 @@ const void* dis_kernel_phase_search(int ps, int lpp) {
 
 const void* dis_kernel_level(int ps, int lpp) {
     DIS_FOR_SEARCH_INSTANCES(DIS_LEVEL_CASE)
+    return nullptr;
+}
+
+// row-owned search layouts (patch size, row blocks, column halves, window
+// radius): lanes per patch = row blocks x halves
+#define DIS_FOR_ROW_INSTANCES(X) \
+    X(4, 4, 1, 3) X(4, 4, 2, 3) X(6, 2, 1, 3) X(6, 2, 2, 3) X(8, 4, 1, 3) X(8, 4, 2, 3) X(8, 8, 2, 3) \
+    X(10, 2, 2, 2) X(12, 2, 2, 2) X(12, 4, 2, 2) X(16, 4, 2, 2) X(16, 8, 2, 2)
+
+const void* dis_kernel_phase_search_rows(int ps, int lpp) {
+#define DIS_ROWS_CASE(PS_, NRB_, NH_, R_) \
+    if (ps == PS_ && lpp == NRB_ * NH_) return (const void*)&k_phase_search_rows<PS_, NRB_, NH_, R_>;
+    DIS_FOR_ROW_INSTANCES(DIS_ROWS_CASE)
+#undef DIS_ROWS_CASE
+    return nullptr;
+}
+
+// inside the 256-thread level kernel the windows of 256 / lpp patches share
+// LDS with the refinement tile: the radius shrinks until they fit 96 KB (the
+// radius never changes a result, only how often a window is reloaded)
+constexpr int dis_level_win_r(int ps, int lpp, int r) {
+    return (r > 0 && (256 / lpp) * (ps + 1 + 2 * r) * (ps + 1 + 2 * r) * 8 > 96 * 1024) ? dis_level_win_r(ps, lpp, r - 1)
+                                                                                       : r;
+}
+
+const void* dis_kernel_level_rows(int ps, int lpp) {
+#define DIS_ROWS_LEVEL_CASE(PS_, NRB_, NH_, R_) \
+    if (ps == PS_ && lpp == NRB_ * NH_)                                                       \
+        return (const void*)&k_level<PS_, NRB_ * NH_, NRB_, NH_, dis_level_win_r(PS_, NRB_ * NH_, R_)>;
+    DIS_FOR_ROW_INSTANCES(DIS_ROWS_LEVEL_CASE)
+#undef DIS_ROWS_LEVEL_CASE
     return nullptr;
 }
 

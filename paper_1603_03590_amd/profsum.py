@@ -31,7 +31,8 @@ import statistics
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/dis_kernels.hip", "csrc/dis_refine_tile.h", "csrc/dis_internal.h", "csrc/dis_lanes.h")
+KERNEL_SOURCES = ("csrc/dis_kernels.hip", "csrc/dis_refine_tile.h", "csrc/dis_internal.h", "csrc/dis_lanes.h",
+                  "csrc/dis_search_rows.h")
 AFTER_DEFAULT = ""
 
 
