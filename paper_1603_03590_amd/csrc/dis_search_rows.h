@@ -23,9 +23,11 @@
 // the lane butterfly pairs row blocks of one half first and the halves last:
 // every layout, and so every lanes-per-patch choice, gives the same bits.
 //
-// The right-hand side uses sum g (d - mean d) = sum (g - mean g) d, with
-// g the template gradient and d = I1(x + u) - T: the centred gradients are
-// formed once per patch, and each iteration needs two sums, not three.
+// The right-hand side uses sum g (d - mean d) = sum (g - mean g) Q -
+// sum (g - mean g) T, with g the template gradient, Q = I1(x + u) and
+// d = Q - T: the centred gradients and the template term are formed once per
+// patch, and each iteration needs two sums of products with Q, not three
+// sums.
 #pragma once
 #include <type_traits>
 
@@ -239,11 +241,32 @@ __device__ __forceinline__ void search_rows(const SearchArgs& a, int block, doub
         mgx = s5[3] / (double)(PS * PS);
         mgy = s5[4] / (double)(PS * PS);
     }
-    // centred gradients: sum g (d - mean d) == sum (g - mean g) d
+    // centred gradients: sum g (d - mean d) == sum (g - mean g) d, and with
+    // d = Q - T that is sum (g - mean g) Q - sum (g - mean g) T: the second
+    // sum and the template's own sum (for the final mean residual) are
+    // formed once here
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int c = 0; c < CB; ++c) { gx[r][c] = gx[r][c] - mgx; gy[r][c] = gy[r][c] - mgy; }
+    double cTx, cTy, sT;
+    {
+        double src[2][RB][CB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < CB; ++c) { src[0][r][c] = gx[r][c]; src[1][r][c] = gy[r][c]; }
+        double pa[2][2], pb[1][2];
+        rows_partial<L, 2, true>(src, T, pa);
+        rows_partial<L, 1, false>(&T, T, pb);
+        double p3[3][2], s3[3];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) { p3[0][k] = pa[0][k]; p3[1][k] = pa[1][k]; p3[2][k] = pb[0][k]; }
+        rows_finish<L, 3>(p3, s3);
+        cTx = s3[0];
+        cTy = s3[1];
+        sT = s3[2];
+    }
 
     double ui = 0.0, vi = 0.0;
     if (has_un) {
@@ -262,9 +285,9 @@ __device__ __forceinline__ void search_rows(const SearchArgs& a, int block, doub
 
     constexpr int HALVES = NH == 1 ? 2 : 1, HC = CB / HALVES, GPL = L::GPL, RG = L::RG;
     int wu_ = wu, wv_ = wv;
-    // the warped pixels d = I1(x + u) - T of the lane, row by row, folded
-    // into the canonical partial sums as they are formed: PROD = the two sums
-    // of the centred gradients times d, else the sum of d
+    // the warped pixels Q = I1(x + u) of the lane, row by row, folded into
+    // the canonical partial sums as they are formed: PROD = the two sums of
+    // the centred gradients times Q, else the sum of Q
     auto warp_sums = [&](double uu, double vv, auto prod_tag, double (&part)[2][2]) {
         constexpr bool PROD = decltype(prod_tag)::value;
         const double fu = floor(uu), fv = floor(vv);
@@ -291,7 +314,7 @@ __device__ __forceinline__ void search_rows(const SearchArgs& a, int block, doub
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
                 const double hn = fma(ax, row[c + 1] - row[c], row[c]);
-                dr[c] = fma(ay, hn - hp[c], hp[c]) - T[r][c];
+                dr[c] = fma(ay, hn - hp[c], hp[c]);
                 hp[c] = hn;
             }
             const int g = r / RG, rr = r - g * RG;
@@ -334,7 +357,7 @@ __device__ __forceinline__ void search_rows(const SearchArgs& a, int block, doub
         double part[2][2], s2[2];
         warp_sums(u, v, std::true_type{}, part);
         rows_finish<L, 2>(part, s2);
-        const double b1 = s2[0], b2 = s2[1];
+        const double b1 = s2[0] - cTx, b2 = s2[1] - cTy;
         if (a.stereo) {
             u = u - b1 / a11;   // App. I: one degree of freedom, v stays at its start (zero)
         } else {
@@ -353,7 +376,7 @@ __device__ __forceinline__ void search_rows(const SearchArgs& a, int block, doub
         warp_sums(u, v, std::false_type{}, part);
         double p1[1][2] = {{part[0][0], part[0][1]}};
         rows_finish<L, 1>(p1, s1);
-        md0 = s1[0] / (double)(PS * PS);
+        md0 = (s1[0] - sT) / (double)(PS * PS);
     }
     if (valid && lane == 0) {
         auto* P = dis_global(a.patch) + (size_t)pi * 4;
