@@ -272,7 +272,11 @@ def main():
             torch.cuda.synchronize()
             bit_equal &= bool(torch.equal(o, bout[k]))
             dp.close()
+        btun = d.tunables()
+        form = ("phase-major: one launch per phase of every level, all pairs in each" if btun["launch_mode"] & 1 else
+                "persistent: one launch per level taking runs of tasks from a queue")
         batched = dict(value=pix / bdt / 1e6, unit="Mpix/s", ms_per_batch=bdt * 1e3, pairs=args.batch,
+                       launch_form=form + " (the autotuner's pick; untuned_ms times both forms)",
                        output_mpix=pix / 1e6, untuned_ms={k: v for k, v in bmodes.items()},
                        plain_bitwise_equal_sample=bit_equal, tunables=d.tunables(),
                        kernels=kernel_table(bstats, 3), roofline=broof,

@@ -676,7 +676,8 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     // device tables for every level, one allocation
     size_t bytes = 0;
     int nsync = 0;
-    std::vector<size_t> off_lp, off_rph, off_start, off_small, off_fb, off_tseg;
+    std::vector<size_t> off_lp, off_rph, off_start, off_small, off_fb, off_tseg, off_runs;
+    std::vector<int> nruns_of;
     std::vector<int> off_sync;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     // tasks (blocks) of segment (phase ph, pair j) of a level
@@ -698,6 +699,8 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             for (int j = 0; j < np; ++j) ntask += (size_t)seg_count(LH, ph, j);
         off_tseg.push_back(bytes);
         bytes = al(bytes + sizeof(int) * std::max<size_t>(1, ntask));
+        off_runs.push_back(bytes);
+        bytes = al(bytes + sizeof(int) * (ntask + 1));
         off_lp.push_back(bytes);
         bytes = al(bytes + sizeof(LevelPair) * np);
         off_rph.push_back(bytes);
@@ -768,6 +771,18 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         }
         start[nseg] = t;
         std::memcpy(host.data() + off_start[li], start.data(), sizeof(int) * (nseg + 1));
+        // runs of the persistent queue: up to rl consecutive tasks of one
+        // segment, rl growing with the level's work so that each of the
+        // 2 n_cu blocks still takes several runs
+        {
+            const int rl = std::max(1, std::min(8, t / (8 * h->n_cu)));
+            int* rs = (int*)(host.data() + off_runs[li]);
+            int nr = 0;
+            for (int sg = 0; sg < nseg; ++sg)
+                for (int q = start[sg]; q < start[sg + 1]; q += rl) rs[nr++] = q;
+            rs[nr] = t;
+            nruns_of.push_back(nr);
+        }
         LevelLaunch LL;
         std::memset(&LL, 0, sizeof LL);
         if (!no_tables) {
@@ -775,6 +790,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             LL.rph = (const RefPhase*)((char*)tabs.mem + off_rph[li]);
             LL.start = (const int*)((char*)tabs.mem + off_start[li]);
             LL.task_seg = (const int*)((char*)tabs.mem + off_tseg[li]);
+            LL.run_start = (const int*)((char*)tabs.mem + off_runs[li]);
             LL.sync = tabs.sync + off_sync[li];
             LL.plan_err = tabs.plan_err;
         }
@@ -782,6 +798,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         LL.npairs = np;
         LL.nph = LH.nph;
         LL.ntasks = t;
+        LL.nruns = nruns_of[li];
         // the adjoint's reverse tiles read the cache the recomputation fills
         LL.lin_cache = (opt || !h->no_lin_cache) ? 1 : 0;
         if (np == 1) {
@@ -795,7 +812,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             if (!fn) return fail(h, DIS_EINVAL, "no level kernel for patch %d, %d lanes", ps, LH.lpp);
             double by = 0.0, fl = 0.0;
             for (int ph = 0; ph < LH.nph; ++ph) { by += ph_by[ph]; fl += ph_fl[ph]; }
-            const int grid = std::max(1, std::min(t, h->n_cu * 2));
+            const int grid = std::max(1, std::min(LL.nruns, h->n_cu * 2));
             seq.add(fn, dim3(grid), dim3(256), &LL, sizeof LL, 0, "level", by, fl);
         } else {
             const void* fs = nc > 1 ? dis_kernel_phase_search_colour(ps)

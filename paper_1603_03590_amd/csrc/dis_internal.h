@@ -138,6 +138,11 @@ struct LevelLaunch {
     int* plan_err;          // every level launch of the plan sets this too when a wait gives up
     int fail_waits;         // failure-path testing: every wait of a later phase gives up at once
     int npairs, nph, ntasks;
+    // the queue hands out runs of consecutive tasks of one segment: run r is
+    // tasks run_start[r] .. run_start[r + 1] - 1, so one wait, one acquire and
+    // one release cover the whole run
+    const int* run_start;   // [nruns + 1]
+    int nruns;
     int lin_cache;          // 1: a level's first refinement launch stores the linearisation, later ones load it
     // With one pair its arguments also travel in the launch itself: a
     // phase-major block then starts on its data at once, instead of after

@@ -1410,8 +1410,8 @@ __device__ __attribute__((noinline)) void lane0_wait(const int* ctr, int need, i
     }
 }
 
-__device__ __attribute__((noinline)) void lane0_signal(int* ctr) {
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __attribute__((noinline)) void lane0_signal(int* ctr, int n) {
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Every pair's work at one level as one launch.  Blocks take tasks from the
@@ -1436,12 +1436,14 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
     for (;;) {
         lane0_take(head, &s_task);
         __syncthreads();
-        const int t = __builtin_amdgcn_readfirstlane(s_task);
+        const int r = __builtin_amdgcn_readfirstlane(s_task);
         __syncthreads();   // s_task is rewritten on the next round
-        if (t >= L.ntasks) break;
-        const int seg = __builtin_amdgcn_readfirstlane(L.task_seg[t]);
+        if (r >= L.nruns) break;
+        const int t0 = __builtin_amdgcn_readfirstlane(L.run_start[r]);
+        const int t1 = __builtin_amdgcn_readfirstlane(L.run_start[r + 1]);
+        const int seg = __builtin_amdgcn_readfirstlane(L.task_seg[t0]);
         const int phase = seg / L.npairs, pair = seg - phase * L.npairs;
-        const int local = t - __builtin_amdgcn_readfirstlane(L.start[seg]);
+        const int first = __builtin_amdgcn_readfirstlane(L.start[seg]);
         const int prev = phase > 0 ? seg - L.npairs : seg;
         const int need = phase > 0 ? __builtin_amdgcn_readfirstlane(L.start[prev + 1] - L.start[prev]) : 0;
         lane0_wait(done + prev, need, err, L.plan_err, L.fail_waits, &s_ok);
@@ -1449,7 +1451,8 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const int ok = __builtin_amdgcn_readfirstlane(s_ok);
         const LevelPair& P = L.pairs[pair];
-        if (ok) {
+        for (int t = t0; t < t1 && ok; ++t) {
+            const int local = t - first;
             if (phase == 0) {
                 if constexpr (RNRB > 0) search_rows<PS, RNRB, RNH, RR, 256>(P.sa, local, smu.win);
                 else search_block<PS, LPP>(P.sa, local);
@@ -1460,10 +1463,11 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
                 ra.nhalf = __builtin_amdgcn_readfirstlane(ra.nhalf);
                 refine_tile<32, 16, 256>(ra, local, sm);
             }
+            __syncthreads();   // LDS (windows, tile) is reused by the run's next task
         }
         __threadfence();
         __syncthreads();
-        lane0_signal(done + seg);
+        lane0_signal(done + seg, t1 - t0);
     }
 }
 
