@@ -194,26 +194,30 @@ __device__ __forceinline__ void search_rows(const SearchArgs& a, int block, doub
         v00 = Vp[rr0 + cc0]; v01 = Vp[rr0 + cc1]; v10 = Vp[rr1 + cc0]; v11 = Vp[rr1 + cc1];
     }
 
-    // template and Sobel/8 gradients of the lane's pixels (replicated border)
+    // template and Sobel/8 gradients of the lane's pixels (replicated
+    // border): the lane's block and a one-pixel ring, each tap loaded once
     double T[RB][CB], gx[RB][CB], gy[RB][CB];
     {
         const auto* __restrict__ J0 = dis_global(a.J0);
+        double b[RB + 2][CB + 2];
+#pragma unroll
+        for (int r = 0; r < RB + 2; ++r) {
+            const int y = clampi(y0 + r0 + r - 1, 0, H - 1);
+#pragma unroll
+            for (int c = 0; c < CB + 2; ++c) b[r][c] = J0[y * W + clampi(x0 + c0 + c - 1, 0, W - 1)];
+        }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const int y = y0 + r0 + r;
-            const int ym = y > 0 ? y - 1 : 0, yp = y < H - 1 ? y + 1 : H - 1;
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
-                const int x = x0 + c0 + c;
-                const int xm = x > 0 ? x - 1 : 0, xp = x < W - 1 ? x + 1 : W - 1;
-                T[r][c] = J0[y * W + x];
-                const double dm = J0[ym * W + xp] - J0[ym * W + xm];
-                const double d0 = J0[y * W + xp] - J0[y * W + xm];
-                const double dp = J0[yp * W + xp] - J0[yp * W + xm];
+                T[r][c] = b[r + 1][c + 1];
+                const double dm = b[r][c + 2] - b[r][c];
+                const double d0 = b[r + 1][c + 2] - b[r + 1][c];
+                const double dp = b[r + 2][c + 2] - b[r + 2][c];
                 gx[r][c] = ((dm + 2.0 * d0) + dp) / 8.0;
-                const double em = J0[yp * W + xm] - J0[ym * W + xm];
-                const double e0 = J0[yp * W + x] - J0[ym * W + x];
-                const double ep = J0[yp * W + xp] - J0[ym * W + xp];
+                const double em = b[r + 2][c] - b[r][c];
+                const double e0 = b[r + 2][c + 1] - b[r][c + 1];
+                const double ep = b[r + 2][c + 2] - b[r][c + 2];
                 gy[r][c] = ((em + 2.0 * e0) + ep) / 8.0;
             }
         }
