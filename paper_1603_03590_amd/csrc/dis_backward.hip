@@ -841,7 +841,7 @@ __global__ __launch_bounds__(256) void k_bwd_pyramid(const PyrBwdArgs a) {
 // taps of J1, the template and its Sobel gradients in J0, and, through the
 // initialisation 2 U_{s+1}(c/2), the coarser flow.
 template <int PS, int LPP>
-__global__ __launch_bounds__(256) void k_bwd_search(const SearchBwdArgs A) {
+__device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
     constexpr int NP = PS * PS;
     constexpr int PPL = (NP + LPP - 1) / LPP;
     constexpr int GROUPS = 256 / LPP;
@@ -1095,6 +1095,19 @@ __global__ __launch_bounds__(256) void k_bwd_search(const SearchBwdArgs A) {
     }
 }
 
+// Up to 8x8 patches the reverse search fits two waves per SIMD in 256
+// registers (a few spill), which hides more of its latency than one wave with
+// all the registers it asks for; larger patches would spill heavily.
+template <int PS, int LPP>
+__global__ __launch_bounds__(256) void k_bwd_search(const SearchBwdArgs A) {
+    bwd_search_block<PS, LPP>(A);
+}
+
+template <int PS, int LPP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_bwd_search_w2(const SearchBwdArgs A) {
+    bwd_search_block<PS, LPP>(A);
+}
+
 // ------------------------------------------------------------ kernel table
 
 const void* dis_kernel_bzero() { return (const void*)&k_bzero; }
@@ -1117,7 +1130,7 @@ const void* dis_kernel_bwd_densify() { return (const void*)&k_bwd_densify; }
 const void* dis_kernel_bwd_pyramid() { return (const void*)&k_bwd_pyramid; }
 
 #define DIS_BWD_SEARCH_CASE(PS_) \
-    if (ps == PS_) return (const void*)&k_bwd_search<PS_, 16>;
+    if (ps == PS_) return PS_ <= 8 ? (const void*)&k_bwd_search_w2<PS_, 16> : (const void*)&k_bwd_search<PS_, 16>;
 const void* dis_kernel_bwd_search(int ps) {
     DIS_BWD_SEARCH_CASE(4) DIS_BWD_SEARCH_CASE(6) DIS_BWD_SEARCH_CASE(8) DIS_BWD_SEARCH_CASE(10)
     DIS_BWD_SEARCH_CASE(12) DIS_BWD_SEARCH_CASE(14) DIS_BWD_SEARCH_CASE(16)
