@@ -171,17 +171,21 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
         const size_t n = (size_t)W * H;
         const double px = (double)n;
 
-        // recompute densification and refinement of this scale
-        LevelOpts o;
-        o.only_level = s;
-        o.tape = p.refine ? B.tape : nullptr;
-        o.Z = B.Z;
-        o.skip_search = 1;
-        o.force_phase = 1;
-        bp->tabs.emplace_back();
-        std::vector<PairRef> pr{PairRef{&sb, w, hgt, ss}};
-        int r = dis_build_levels(h, pr, q, bp->tabs.back(), &o);
-        if (r != DIS_OK) return r;
+        // recompute densification and refinement of this scale; the finest
+        // scale's weight sums, tape, warped frame and linearisation are still
+        // those the forward left (it recorded them)
+        if (s != sf || !dis_forward_keeps_finest(h)) {
+            LevelOpts o;
+            o.only_level = s;
+            o.tape = p.refine ? B.tape : nullptr;
+            o.Z = B.Z;
+            o.skip_search = 1;
+            o.force_phase = 1;
+            bp->tabs.emplace_back();
+            std::vector<PairRef> pr{PairRef{&sb, w, hgt, ss}};
+            int r = dis_build_levels(h, pr, q, bp->tabs.back(), &o);
+            if (r != DIS_OK) return r;
+        }
 
         const double* gUd = B.gU[s];
         const double* gJ1w = nullptr;

@@ -560,6 +560,12 @@ void dis_refine_phases(const dis_params& p, int s, std::vector<RefPhase>& out) {
 // in device tables; launch mode 0 runs each level as one persistent k_level
 // launch over that queue, mode 1 as one launch per phase covering every
 // pair.  Both give the same bits.
+bool dis_forward_keeps_finest(const dis_handle* h) {
+    const dis_params& p = h->p;
+    return (p.flags & DIS_FLAG_KEEP_FOR_BACKWARD) && p.refine && !(p.flags & DIS_FLAG_FB_CONSISTENCY) &&
+           dis_channels(&p) == 1 && h->bwd.tape != nullptr && h->bwd.Z != nullptr;
+}
+
 int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs,
                      const LevelOpts* opt) {
     const dis_params& p = h->p;
@@ -569,6 +575,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     for (const PairRef& r : pairs) top = std::max(top, r.ss);
     const bool fbm = (p.flags & DIS_FLAG_FB_CONSISTENCY) && !opt && pairs.size() == 2;
     const int nc = dis_channels(&p);
+    const bool keep_tape = !opt && pairs.size() == 1 && dis_forward_keeps_finest(h);
     // colour frames and the merged densification run phase-major only
     const int mode = ((opt && opt->force_phase) || fbm || nc > 1 || h->arena) ? 1 : h->mode_phase;
     // static-scratch plans carry every argument in the launches themselves
@@ -631,7 +638,11 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             da.raw_residual = (p.flags & DIS_FLAG_RAW_RESIDUAL) ? 1 : 0;
             da.U = L.Ud;
             da.J1w = p.refine ? sb.J1w : nullptr;
-            da.Z = opt ? opt->Z : nullptr;
+            // a forward kept for the adjoint records the finest scale's SOR
+            // tape and weight sums as it goes, so the adjoint starts there
+            // without recomputing that scale (the buffers hold one scale)
+            const bool record = keep_tape && s == sf;
+            da.Z = opt ? opt->Z : (record ? h->bwd.Z : nullptr);
             da.nc = nc;
             da.mdc = L.mdc;
             RefineArgs& ra = P.ra;
@@ -639,7 +650,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             ra.lin = sb.lin;
             ra.stereo = (p.flags & DIS_FLAG_STEREO) ? 1 : 0;
             ra.nc = nc;
-            ra.tape = opt ? opt->tape : nullptr;
+            ra.tape = opt ? opt->tape : (record ? h->bwd.tape : nullptr);
             ra.W = W; ra.H = Hh;
             ra.tiles_x = (W + tw - 1) / tw;
             ra.delta = p.w_intensity; ra.gamma = p.w_gradient; ra.alpha = p.w_smooth;
@@ -651,7 +662,8 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             const int small_max = h->small_levels == 2 ? DIS_SMALL_PAIRS : DIS_SMALL_PAIRS / 4;
             // (not in the adjoint's recomputation: its reverse tiles read the
             // linearisation cache, which only the tiled refinement fills)
-            const bool small = p.refine && h->small_levels && !opt && !fbm && nc == 1 && ((W + 1) / 2) * Hh <= small_max;
+            const bool small = p.refine && h->small_levels && !opt && !fbm && nc == 1 && !record &&
+                               ((W + 1) / 2) * Hh <= small_max;
             if (small) LH.small.push_back((int)LH.lp.size());
             LH.is_small.push_back(small ? 1 : 0);
             LH.lp.push_back(P);
@@ -800,7 +812,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         LL.ntasks = t;
         LL.nruns = nruns_of[li];
         // the adjoint's reverse tiles read the cache the recomputation fills
-        LL.lin_cache = (opt || !h->no_lin_cache) ? 1 : 0;
+        LL.lin_cache = (opt || !h->no_lin_cache || (keep_tape && LH.s == sf)) ? 1 : 0;
         if (np == 1) {
             LL.one = 1;
             LL.sa1 = LH.lp[0].sa;

@@ -186,6 +186,10 @@ struct LevelOpts {
 };
 
 int dis_alloc_backward(dis_handle* h);
+// A single-pair forward of this handle records its finest scale's weight sums,
+// SOR tape, warped frame and linearisation in the adjoint's buffers, and the
+// adjoint starts from them instead of recomputing that scale.
+bool dis_forward_keeps_finest(const dis_handle* h);
 int dis_dalloc(dis_handle* h, void** ptr, size_t bytes);
 int dis_build_graph_seq(dis_handle* h, Seq& seq, hipGraph_t* graph, hipGraphExec_t* exec,
                         std::vector<hipGraphNode_t>* nodes);

@@ -271,3 +271,24 @@ def test_backward_errors():
     finally:
         d.close()
     torch.cuda.synchronize()
+
+
+def test_forward_kept_for_backward_is_the_plain_forward():
+    """A forward kept for the adjoint (which records the finest scale's SOR
+    tape and weight sums on the way) returns the plain forward's flow bit for
+    bit, in every launch mode."""
+    say("[adjoint] case kept forward vs plain forward, 512x256")
+    pr = pair("bump", 512, 256, 16.0, 2000)
+    a = torch.from_numpy(pr.I0).to(torch.float64).cuda()
+    b = torch.from_numpy(pr.I1).to(torch.float64).cuda()
+    for mode in (1, 3, 9, 0):
+        outs = []
+        for flags in (F64, F64 | KEEP):
+            d = DIS(params(105, flags=flags), 512, 256)
+            try:
+                d.set_tunables(None, 7, mode)
+                outs.append(d.flow(a, b).cpu().numpy())
+                torch.cuda.synchronize()
+            finally:
+                d.close()
+        assert np.array_equal(outs[0], outs[1]), mode
