@@ -65,9 +65,10 @@ struct SweepBwdArgs {
 };
 
 // Reverse of the half sweeps j_hi-1 .. j_lo of one fixed-point step of the
-// refinement on one tile (core grown by j_hi - j_lo on every cut side): the
-// step's coefficients are recomputed as in the forward tile, the states
-// before each half sweep come from the tape, the state adjoint lives in LDS.
+// refinement on one tile (core grown by j_hi - j_lo + 1 on every cut side):
+// the step's coefficients are recomputed as in the forward tile, the states
+// before each half sweep come from the tape, the state adjoint lives in the
+// owning threads' registers.
 // Core pixels write the adjoint of the state before half sweep j_lo, their 9
 // coefficient adjoints (summed over the step's half sweeps) and the
 // coefficients the linearisation adjoint needs.
@@ -75,7 +76,7 @@ struct BwdStepArgs {
     RefineArgs ra;          // the forward step: U = Ud, J0, J1w, dUf = frozen increment (null = zero), tiles_x
     const double* tape;     // state before half sweep j at tape + (m0 + j) * 2 W H; zero when m0 + j == 0
     int m0;
-    int j_lo, j_hi;         // j_hi - j_lo <= DIS_KMAX
+    int j_lo, j_hi;         // j_hi - j_lo <= the shape's half sweeps per launch
     const double* gd_in;    // adjoint of the state after half sweep j_hi - 1 [2][H][W]
     const double* gadd;     // added to gd_in, or null
     double* gd_out;         // adjoint of the state before half sweep j_lo
@@ -122,10 +123,12 @@ struct SearchBwdArgs {
 
 const void* dis_kernel_bzero();
 const void* dis_kernel_bzero_list();
-// reverse refinement tile: 0 = 8x8 cores (small scales), 1 = 16x16 cores
-// (large scales, less halo overlap); 512 threads either way
-const void* dis_kernel_bwd_step(int tile);
-int dis_bwd_step_tile(int tile);        // core side of a reverse tile id
+// reverse refinement tiles, by shape id: core width and height and the most
+// half sweeps one launch reverses (0: 8x8 cores over up to 10 half sweeps,
+// 1: 16x16 cores over up to 5); 512 threads, two blocks per compute unit;
+// null / 0 past the last id
+const void* dis_kernel_bwd_step(int shape);
+int dis_bwd_step_shape(int shape, int* tw, int* th, int* kh);
 #define DIS_BWD_THREADS 512
 const void* dis_kernel_bcopy();
 const void* dis_kernel_baxpy();

@@ -470,28 +470,37 @@ namespace {
 // The reverse of kh half sweeps needs a region one pixel wider than the
 // forward's: within one reverse half sweep an error entering at the cut
 // reaches the pixels of the other colour next to it (part b), so after kh
-// of them it has moved kh + 1 pixels in.
-template <int TW, int TH>
+// of them it has moved kh + 1 pixels in.  The forward set-up's planes are
+// dead once the coefficients are in registers, so the reverse's planes
+// share their LDS; the state adjoint lives in the owners' registers (only
+// a pixel's owner reads or writes it).
+template <int TW, int TH, int KH>
 struct BwdStepSmem {
-    using F = dis_tile::RefineSmem<TW, TH, DIS_KMAX + 1>;
-    F f;                                // forward set-up; its increment planes then hold the tape state
+    using F = dis_tile::RefineSmem<TW, TH, KH + 1>;
     static constexpr int RP = F::RHM * F::LP;
-    double gu[RP], gv[RP];              // adjoint of the state
-    double nu[RP], nv[RP];              // adjoints of the neighbour sums of the last reverse half sweep
-    double acc[9][TW * TH];             // coefficient adjoints of the core pixels
+    union {
+        F f;                            // forward set-up
+        struct {
+            double st_u[RP], st_v[RP];  // tape state before the half sweep being reversed
+            double nu[RP], nv[RP];      // adjoints of the neighbour sums of the last reverse half sweep
+            double acc[9][TW * TH];     // coefficient adjoints of the core pixels
+        } r;
+    };
 };
 
 }  // namespace
 
-template <int TW, int TH, int NT>
-__global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
-    constexpr int KG = DIS_KMAX + 1;
+// WPE: waves per SIMD the register allocation must allow (4: two blocks of
+// 512 threads per compute unit; both shapes in use fit without spilling)
+template <int TW, int TH, int KH, int NT, int WPE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_bwd_step(const BwdStepArgs A) {
+    constexpr int KG = KH + 1;
     using S = dis_tile::RefineSmem<TW, TH, KG>;
     using Shape = dis_tile::TileShape<TW, TH, NT, KG>;
     constexpr int LP = S::LP;
     constexpr int PPT = Shape::PPT;
     constexpr int NE = (S::RWM * S::RHM + NT - 1) / NT;   // region elements per thread
-    __shared__ BwdStepSmem<TW, TH> sm;
+    __shared__ BwdStepSmem<TW, TH, KH> sm;
     const RefineArgs& a = A.ra;
     const int kh = __builtin_amdgcn_readfirstlane(A.j_hi - A.j_lo);
     const dis_tile::TileGeom g =
@@ -505,8 +514,10 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
     dis_tile::TileCoef<PPT> C;
     double s_iu[Shape::NS][2], s_iv[Shape::NS][2];
     // the reverse steps below touch only pixels within kh of the core
-    dis_tile::refine_setup<TW, TH, NT, KG>(a, g, sm.f, C, s_iu, s_iv, kh);
-    __syncthreads();   // the image tile is dead from here on
+    // (the linearisation is read where it is used: registers are what
+    // limits how many of these blocks share a compute unit)
+    dis_tile::refine_setup<TW, TH, NT, KG, false, false>(a, g, sm.f, C, s_iu, s_iv, kh);
+    __syncthreads();   // the set-up planes are dead from here on
     // The adjoint moves one pixel per reverse half sweep: after reverse step
     // r (of kh) the core's outputs still depend on pixels within kh - 1 - r
     // of it, so step r replays and reverses (a) pixels within kh - r and
@@ -514,41 +525,40 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
     // tape supplies the forward states exactly, so the replay needs no
     // cone).  The core's results keep their bits.  Each owned pixel's
     // Chebyshev distance from the core goes to bits 8.. of its flag word.
+    // State adjoint of the owned pixels, from gd_in (+ gadd).
+    double ga_u[PPT][2], ga_v[PPT][2];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
+            ga_u[k][c] = ga_v[k][c] = 0.0;
             const int l = C.l[k][c];
             if (l < 0) continue;
             const int ly = l / LP, lx = l - ly * LP;
             const int x = rx0 + lx, y = ry0 + ly;
             const int d = max(max(max(cx0 - x, x - (g.cx1 - 1)), max(cy0 - y, y - (g.cy1 - 1))), 0);
             C.m[k][c] |= d << 8;
+            const size_t gi = (size_t)y * W + x;
+            double u = A.gd_in[gi], v = A.gd_in[n + gi];
+            if (A.gadd) { u = u + A.gadd[gi]; v = v + A.gadd[n + gi]; }
+            ga_u[k][c] = u;
+            ga_v[k][c] = v;
         }
     }
-
-    // state adjoint on the region, coefficient adjoints of the core
-    for (int i = threadIdx.x; i < RW * RH; i += NT) {
-        const int ly = i / RW, lx = i - ly * RW;
-        const size_t gi = (size_t)(ry0 + ly) * W + rx0 + lx;
-        double u = A.gd_in[gi], v = A.gd_in[n + gi];
-        if (A.gadd) { u = u + A.gadd[gi]; v = v + A.gadd[n + gi]; }
-        sm.gu[ly * LP + lx] = u;
-        sm.gv[ly * LP + lx] = v;
-    }
+    // coefficient adjoints of the core
     for (int i = threadIdx.x; i < CW * CH; i += NT) {
         const int yy = i / CW, xx = i - yy * CW;
         const size_t gi = (size_t)(cy0 + yy) * W + cx0 + xx;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) sm.acc[q][yy * TW + xx] = A.acc_load ? A.acc[q * n + gi] : 0.0;
+        for (int q = 0; q < 9; ++q) sm.r.acc[q][yy * TW + xx] = A.acc_load ? A.acc[q * n + gi] : 0.0;
     }
     // the tape state before a half sweep, region-wide, through registers so
     // that the next one is in flight while the current one is reversed.  The
     // state before half sweep j differs from the one before j + 1 only at the
     // pixels half sweep j updated (colour j & 1), so after the first, full
     // state only those are fetched and replaced (colour: 0, 1, or -1 = all)
-    double* st_u = sm.f.u.inc.du;
-    double* st_v = sm.f.u.inc.dv;
+    double* st_u = sm.r.st_u;
+    double* st_v = sm.r.st_v;
     double pu[NE], pv[NE];
     auto in_set = [&](int i, int colour) {
         if (i >= RW * RH) return false;
@@ -612,28 +622,28 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
             const double dun = om1 * dup + i1 * r1;
             const double nv = ((wr * dvr + wl * dvl) + wd * dvd) + wu * dvu;
             const double r2 = (nv + C.c2[k][c]) - A12 * dun;
-            const double adv = sm.gv[l];
+            const double adv = ga_v[k][c];
             const double gr2 = i2 * adv;
-            const double adu = sm.gu[l] - A12 * gr2;
+            const double adu = ga_u[k][c] - A12 * gr2;
             const double gr1 = i1 * adu;
             const int ly = l / LP, lx = l - ly * LP;
             const int xx = rx0 + lx - cx0, yy = ry0 + ly - cy0;
             if (xx >= 0 && xx < CW && yy >= 0 && yy < CH) {
                 const int q = yy * TW + xx;
-                sm.acc[0][q] += r1 * adu;
-                sm.acc[1][q] += r2 * adv;
-                sm.acc[2][q] += gr1;
-                sm.acc[3][q] += gr2;
-                sm.acc[4][q] += -dun * gr2 - dvp * gr1;
-                sm.acc[5][q] += dur * gr1 + dvr * gr2;
-                sm.acc[6][q] += dul * gr1 + dvl * gr2;
-                sm.acc[7][q] += dud * gr1 + dvd * gr2;
-                sm.acc[8][q] += duu * gr1 + dvu * gr2;
+                sm.r.acc[0][q] += r1 * adu;
+                sm.r.acc[1][q] += r2 * adv;
+                sm.r.acc[2][q] += gr1;
+                sm.r.acc[3][q] += gr2;
+                sm.r.acc[4][q] += -dun * gr2 - dvp * gr1;
+                sm.r.acc[5][q] += dur * gr1 + dvr * gr2;
+                sm.r.acc[6][q] += dul * gr1 + dvl * gr2;
+                sm.r.acc[7][q] += dud * gr1 + dvd * gr2;
+                sm.r.acc[8][q] += duu * gr1 + dvu * gr2;
             }
-            sm.gu[l] = om1 * adu;
-            sm.gv[l] = om1 * adv - A12 * gr1;
-            sm.nu[l] = gr1;
-            sm.nv[l] = gr2;
+            ga_u[k][c] = om1 * adu;
+            ga_v[k][c] = om1 * adv - A12 * gr1;
+            sm.r.nu[l] = gr1;
+            sm.r.nv[l] = gr2;
         }
         __syncthreads();
         // (b) pixels of the other colour collect what their neighbours'
@@ -644,12 +654,12 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
             if (l < 0 || (C.m[k][c ^ 1] >> 8) > kh - 1 - r) continue;
             const int msk = C.m[k][c ^ 1];
             double su = 0.0, sv = 0.0;
-            if (msk & 1) { su += C.wr[k][c ^ 1] * sm.nu[l + 1]; sv += C.wr[k][c ^ 1] * sm.nv[l + 1]; }
-            if (msk & 2) { su += C.wl[k][c ^ 1] * sm.nu[l - 1]; sv += C.wl[k][c ^ 1] * sm.nv[l - 1]; }
-            if (msk & 4) { su += C.wd[k][c ^ 1] * sm.nu[l + LP]; sv += C.wd[k][c ^ 1] * sm.nv[l + LP]; }
-            if (msk & 8) { su += C.wu[k][c ^ 1] * sm.nu[l - LP]; sv += C.wu[k][c ^ 1] * sm.nv[l - LP]; }
-            sm.gu[l] += su;
-            sm.gv[l] += sv;
+            if (msk & 1) { su += C.wr[k][c ^ 1] * sm.r.nu[l + 1]; sv += C.wr[k][c ^ 1] * sm.r.nv[l + 1]; }
+            if (msk & 2) { su += C.wl[k][c ^ 1] * sm.r.nu[l - 1]; sv += C.wl[k][c ^ 1] * sm.r.nv[l - 1]; }
+            if (msk & 4) { su += C.wd[k][c ^ 1] * sm.r.nu[l + LP]; sv += C.wd[k][c ^ 1] * sm.r.nv[l + LP]; }
+            if (msk & 8) { su += C.wu[k][c ^ 1] * sm.r.nu[l - LP]; sv += C.wu[k][c ^ 1] * sm.r.nv[l - LP]; }
+            ga_u[k][c ^ 1] += su;
+            ga_v[k][c ^ 1] += sv;
         }
         if (j > jlo) stash(c ^ 1);
         __syncthreads();
@@ -659,16 +669,15 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
         else reverse(std::integral_constant<int, 0>{}, j);
     }
 
-    // the core: state adjoint, coefficient adjoints, and the coefficients
-    // the linearisation adjoint reads
+    // the core: coefficient adjoints, then per owned pixel the state adjoint
+    // and the coefficients the linearisation adjoint reads (the smoothness
+    // weight of the pixel's right edge, or of its lower edge in the last
+    // column; core pixels see both neighbours whenever the image has them)
     for (int i = threadIdx.x; i < CW * CH; i += NT) {
         const int yy = i / CW, xx = i - yy * CW;
         const size_t gi = (size_t)(cy0 + yy) * W + cx0 + xx;
-        const int l = (cy0 + yy - ry0) * LP + (cx0 + xx - rx0);
-        A.gd_out[gi] = sm.gu[l];
-        A.gd_out[n + gi] = sm.gv[l];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) A.acc[q * n + gi] = sm.acc[q][yy * TW + xx];
+        for (int q = 0; q < 9; ++q) A.acc[q * n + gi] = sm.r.acc[q][yy * TW + xx];
     }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -680,9 +689,11 @@ __global__ __launch_bounds__(NT) void k_bwd_step(const BwdStepArgs A) {
             const int x = rx0 + lx, y = ry0 + ly;
             if (x < cx0 || x >= g.cx1 || y < cy0 || y >= g.cy1) continue;
             const size_t gi = (size_t)y * W + x;
+            A.gd_out[gi] = ga_u[k][c];
+            A.gd_out[n + gi] = ga_v[k][c];
             A.coef[n + gi] = C.i1[k][c];
             A.coef[2 * n + gi] = C.i2[k][c];
-            A.coef[5 * n + gi] = x < W - 1 ? sm.f.wr[l] : sm.f.wd[l];
+            A.coef[5 * n + gi] = x < W - 1 ? C.wr[k][c] : C.wd[k][c];
         }
     }
 }
@@ -1112,10 +1123,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
 const void* dis_kernel_bzero() { return (const void*)&k_bzero; }
 const void* dis_kernel_bzero_list() { return (const void*)&k_bzero_list; }
-const void* dis_kernel_bwd_step(int tile) {
-    return tile ? (const void*)&k_bwd_step<16, 16, DIS_BWD_THREADS> : (const void*)&k_bwd_step<8, 8, DIS_BWD_THREADS>;
+// reverse refinement tiles: core width, height and half sweeps per launch
+// (and the waves per SIMD their registers allow)
+#define DIS_BWD_STEP_SHAPES(X) X(8, 8, 10, 4) X(16, 16, 5, 4)
+const void* dis_kernel_bwd_step(int shape) {
+    int i = 0;
+#define X(tw, th, kh, wpe) if (shape == i++) return (const void*)&k_bwd_step<tw, th, kh, DIS_BWD_THREADS, wpe>;
+    DIS_BWD_STEP_SHAPES(X)
+#undef X
+    return nullptr;
 }
-int dis_bwd_step_tile(int tile) { return tile ? 16 : 8; }
+int dis_bwd_step_shape(int shape, int* tw, int* th, int* kh) {
+    int i = 0;
+#define X(w_, h_, k_, wpe) if (shape == i++) { *tw = w_; *th = h_; *kh = k_; return 1; }
+    DIS_BWD_STEP_SHAPES(X)
+#undef X
+    return 0;
+}
 const void* dis_kernel_bcopy() { return (const void*)&k_bcopy; }
 const void* dis_kernel_baxpy() { return (const void*)&k_baxpy; }
 const void* dis_kernel_bwd_upsample() { return (const void*)&k_bwd_upsample; }

@@ -116,6 +116,17 @@ static void add_zero_list(Seq& q, const std::vector<std::pair<double*, size_t>>&
     }
 }
 
+// Reverse refinement tile of a W x H scale.  Scales with at least one
+// 16x16 tile per two compute units take 16x16 cores over 5 half sweeps per
+// launch: a region of 28x28 per core of 256 pixels, against 30x30 per 64
+// for 8x8 cores over 10 (twice the launches, a third of the halo work).
+// Smaller scales take 8x8 cores over 10 half sweeps, which keep more
+// blocks in flight.  (8 pairs of 512x256: 5.91 ms forward+backward, against
+// 6.39 with 16x16 cores over 10 half sweeps on the two finest scales.)
+static int bwd_step_pick(const dis_handle* h, int W, int H) {
+    return 2 * ((W + 15) / 16) * ((H + 15) / 16) >= h->n_cu ? 1 : 0;
+}
+
 static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
     const dis_params& p = h->p;
     BwdBuf& B = h->bwd;
@@ -198,12 +209,11 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
             // adjoint of the state between half sweeps: ping-pong between gd and gn
             double* gdb[2] = {B.gd, B.gn};
             int cur = 0;
-            // 8x8 cores while they give at most two blocks per compute unit,
-            // else 16x16 (a quarter of the blocks, a third of the halo work)
-            const int bt = ((W + 7) / 8) * ((H + 7) / 8) > 2 * h->n_cu ? 1 : 0;
-            const int TS = dis_bwd_step_tile(bt);
-            const int tiles_x = (W + TS - 1) / TS;
-            const int ntiles = tiles_x * ((H + TS - 1) / TS);
+            const int shape = bwd_step_pick(h, W, H);
+            int TW = 8, TH = 8, KH = 1;
+            if (!dis_bwd_step_shape(shape, &TW, &TH, &KH)) return dis_fail(h, DIS_EINVAL, "internal: reverse tile %d", shape);
+            const int tiles_x = (W + TW - 1) / TW;
+            const int ntiles = tiles_x * ((H + TH - 1) / TH);
             for (int k = nout - 1; k >= 0; --k) {
                 RefBwdArgs ra;
                 std::memset(&ra, 0, sizeof ra);
@@ -226,11 +236,11 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
                 ra.omega = p.sor_omega;
                 ra.eps = 1e-3;
                 if (tiled) {
-                    // reverse of the step's half sweeps, at most DIS_KMAX per launch
+                    // reverse of the step's half sweeps, at most KH per launch
                     int j_hi = nh;
                     bool first = true;
                     while (j_hi > 0) {
-                        const int j_lo = std::max(0, j_hi - DIS_KMAX);
+                        const int j_lo = std::max(0, j_hi - KH);
                         BwdStepArgs st;
                         std::memset(&st, 0, sizeof st);
                         RefineArgs& f = st.ra;
@@ -262,7 +272,7 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
                         const int kh = j_hi - j_lo;
                         // in: U, dUf, J0, J1w, state adjoint (+ added), kh tape states;
                         // out: state adjoint, 9 coefficient adjoints, 3 coefficients
-                        q.add(dis_kernel_bwd_step(bt), dim3(ntiles), dim3(DIS_BWD_THREADS), &st, sizeof st, 0,
+                        q.add(dis_kernel_bwd_step(shape), dim3(ntiles), dim3(DIS_BWD_THREADS), &st, sizeof st, 0,
                               "bwd_step", px * (16.0 + 16.0 + 16.0 + 32.0 + 16.0 * kh + 16.0 + 72.0 + 24.0),
                               px * (155.0 + 20.0 * kh));
                         cur ^= 1;

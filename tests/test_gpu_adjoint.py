@@ -181,6 +181,8 @@ def test_backward_repeat_and_graph_agree_with_eager():
     ("ragged_45x37", (5, 45, 37), {}),
     ("vi7_two_launches_per_step", (2, 40, 32), dict(var_inner=7)),
     ("vo_auto_sf1", (4, 48, 40), dict(var_outer=-1, finest_scale=1, coarsest_scale=2)),
+    # finest scale wide enough for 16x16 reverse cores (two launches per step)
+    ("cores16_256x128", (0, 256, 128), {}),
 ])
 def test_tiled_reverse_sweeps_match_reference_form(name, cr, over):
     """The tiled reverse of each fixed-point step against one launch per
