@@ -1,15 +1,13 @@
 // Host side of the adjoint: buffers, the per-shape launch plan and
 // dis_flow_backward.
 //
-// The plan walks the scales from fine to coarse.  At each scale it runs the
-// reverse of the refinement's fixed-point steps, of the densification with
-// the warped frame, and of the inverse search with its initialisation from
-// the coarser flow, reading what the forward kept: the patch records and
-// flows of every scale, and, written by a forward on a handle that keeps
-// state for the adjoint, each scale's densification weight sums, warped
-// frame, linearisation and SOR tape (the state after every half sweep).
-// Gradients of the level images of every scale are summed into the frames
-// by the pyramid adjoint at the end.
+// The plan walks the scales from fine to coarse.  At each scale it first
+// re-runs that scale's densification and refinement from the kept patch
+// records (writing the SOR tape and the densification weight sums), then
+// runs the reverse of the refinement's fixed-point steps, of the
+// densification with the warped frame, and of the inverse search with its
+// initialisation from the coarser flow.  Gradients of the level images of
+// every scale are summed into the frames by the pyramid adjoint at the end.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,6 +34,7 @@
 
 struct BwdPlan {
     Seq seq;
+    std::vector<PlanTables> tabs;       // tables of the per-scale recomputation
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<hipGraphNode_t> nodes;
@@ -46,19 +45,21 @@ void dis_bwd_plan_free(BwdPlan* bp) {
     if (!bp) return;
     if (bp->exec) hipGraphExecDestroy(bp->exec);
     if (bp->graph) hipGraphDestroy(bp->graph);
+    for (PlanTables& t : bp->tabs)
+        if (t.mem) hipFree(t.mem);
     delete bp;
 }
 
 static int outer_steps(const dis_params& p, int s) { return p.var_outer < 0 ? s + 1 : p.var_outer; }
 
-// Gradient planes and recorded forward state of every processed scale, and
-// the scratch of one scale (sized for the largest), for slot 0.
+// Gradient planes of every processed scale and the scratch of one scale
+// (sized for the largest), for slot 0.
 int dis_alloc_backward(dis_handle* h) {
     const dis_params& p = h->p;
     BwdBuf& B = h->bwd;
     std::memset(&B, 0, sizeof B);
     const int sf = p.finest_scale;
-    size_t pxmax = 0;
+    size_t tape = 0, pxmax = 0;
     for (int s = sf; s <= h->top; ++s) {
         const LevelBuf& L = h->slots[0].lv[s];
         if (!L.U) continue;
@@ -67,15 +68,11 @@ int dis_alloc_backward(dis_handle* h) {
         DALLOC(h, B.gJ1[s], px * sizeof(double));
         DALLOC(h, B.gU[s], 2 * px * sizeof(double));
         DALLOC(h, B.gP[s], (size_t)L.maxN * 4 * sizeof(double));
-        DALLOC(h, B.Z[s], px * sizeof(double));
-        if (p.refine) {
-            DALLOC(h, B.J1w[s], px * sizeof(double));
-            DALLOC(h, B.lin[s], 11 * px * sizeof(double));
-            DALLOC(h, B.tape[s], ((size_t)outer_steps(p, s) * 2 * p.var_inner + 1) * 2 * px * sizeof(double));
-        }
         pxmax = std::max(pxmax, px);
+        if (p.refine) tape = std::max(tape, ((size_t)outer_steps(p, s) * 2 * p.var_inner + 1) * 2 * px);
     }
     B.scratch_px = pxmax;
+    DALLOC(h, B.Z, pxmax * sizeof(double));
     DALLOC(h, B.gq, 2 * pxmax * sizeof(double));
     if (p.refine) {
         DALLOC(h, B.gUd, 2 * pxmax * sizeof(double));
@@ -88,6 +85,8 @@ int dis_alloc_backward(dis_handle* h) {
         int nout_max = 1;
         for (int s = sf; s <= h->top; ++s) nout_max = std::max(nout_max, outer_steps(p, s));
         DALLOC(h, B.gFacc, (size_t)nout_max * 2 * pxmax * sizeof(double));
+        DALLOC(h, B.tape, tape * sizeof(double));
+        B.tape_len = tape;
     }
     return DIS_OK;
 }
@@ -135,7 +134,6 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
     const int ss = dis_coarsest(&p, w, hgt);
     const int cmap = (p.flags & DIS_FLAG_PIXEL_CENTRE) ? 1 : 0;
     const bool f64io = (p.flags & DIS_FLAG_IO_F64) != 0;
-    if (!dis_forward_records(h)) return dis_fail(h, DIS_ESTATE, "internal: the forward keeps no state for the adjoint");
     // search reverse: iterates of 16 patches, then a J1-adjoint window per
     // patch, as wide as 64 KB of LDS allows (span 0..12 extra pixels)
     const size_t traj = (size_t)16 * (p.gn_iters + 1) * 2 * sizeof(double);
@@ -184,10 +182,21 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
         const size_t n = (size_t)W * H;
         const double px = (double)n;
 
-        // this scale's weight sums, warped frame, linearisation and tape,
-        // as the forward recorded them
-        double* const tape = B.tape[s];
-        const double* const J1w = B.J1w[s];
+        // recompute densification and refinement of this scale; the finest
+        // scale's weight sums, tape, warped frame and linearisation are still
+        // those the forward left (it recorded them)
+        if (s != sf || !dis_forward_keeps_finest(h)) {
+            LevelOpts o;
+            o.only_level = s;
+            o.tape = p.refine ? B.tape : nullptr;
+            o.Z = B.Z;
+            o.skip_search = 1;
+            o.force_phase = 1;
+            bp->tabs.emplace_back();
+            std::vector<PairRef> pr{PairRef{&sb, w, hgt, ss}};
+            int r = dis_build_levels(h, pr, q, bp->tabs.back(), &o);
+            if (r != DIS_OK) return r;
+        }
 
         const double* gUd = B.gU[s];
         const double* gJ1w = nullptr;
@@ -218,9 +227,9 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
                 RefBwdArgs ra;
                 std::memset(&ra, 0, sizeof ra);
                 ra.U = L.Ud;
-                ra.F = k ? tape + (size_t)k * nh * 2 * n : nullptr;
+                ra.F = k ? B.tape + (size_t)k * nh * 2 * n : nullptr;
                 ra.J0 = L.J0;
-                ra.J1w = J1w;
+                ra.J1w = sb.J1w;
                 ra.coef = B.coef;
                 ra.acc = B.acc;
                 ra.edge = B.edge;
@@ -246,9 +255,9 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
                         RefineArgs& f = st.ra;
                         f.U = L.Ud;
                         f.J0 = L.J0;
-                        f.J1w = J1w;
-                        f.lin = B.lin[s];
-                        f.lin_mode = 2;   // filled by the forward's first refinement launch of the scale
+                        f.J1w = sb.J1w;
+                        f.lin = sb.lin;
+                        f.lin_mode = 2;   // filled by the recomputation's first refinement launch
                         f.dUf = ra.F;
                         f.W = W;
                         f.H = H;
@@ -259,7 +268,7 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
                         f.alpha = p.w_smooth;
                         f.omega = p.sor_omega;
                         f.eps = 1e-3;
-                        st.tape = tape;
+                        st.tape = B.tape;
                         st.m0 = k * nh;
                         st.j_lo = j_lo;
                         st.j_hi = j_hi;
@@ -289,7 +298,7 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
                         const int m = k * nh + j;
                         SweepBwdArgs sw;
                         std::memset(&sw, 0, sizeof sw);
-                        sw.state = m ? tape + (size_t)m * 2 * n : nullptr;
+                        sw.state = m ? B.tape + (size_t)m * 2 * n : nullptr;
                         sw.coef = B.coef;
                         sw.gd = B.gd;
                         sw.gn = B.gn;
@@ -331,7 +340,7 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
         da.ny = g.ny;
         da.raw_residual = (p.flags & DIS_FLAG_RAW_RESIDUAL) ? 1 : 0;
         da.Ud = L.Ud;
-        da.Z = B.Z[s];
+        da.Z = B.Z;
         da.gUd = gUd;
         da.gJ1w = gJ1w;
         da.gJ0 = B.gJ0[s];

@@ -139,7 +139,7 @@ static int build_batch(dis_handle* h, int n, const int* w, const int* hgt, const
         bp->seq.add(dis_kernel_pyramid_tab(), dim3(pstart[i].back(), 2), dim3(256), &T, sizeof T, 0, "pyramid", by,
                     0.0);
     }
-    int r = dis_build_levels(h, pairs, bp->seq, bp->tabs);
+    int r = dis_build_levels(h, pairs, bp->seq, bp->tabs, nullptr);
     if (r != DIS_OK) return r;
     {
         PyrTab* T0 = (PyrTab*)bp->seq.items[first].arg.data();

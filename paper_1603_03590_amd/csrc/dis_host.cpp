@@ -560,27 +560,28 @@ void dis_refine_phases(const dis_params& p, int s, std::vector<RefPhase>& out) {
 // in device tables; launch mode 0 runs each level as one persistent k_level
 // launch over that queue, mode 1 as one launch per phase covering every
 // pair.  Both give the same bits.
-bool dis_forward_records(const dis_handle* h) {
+bool dis_forward_keeps_finest(const dis_handle* h) {
     const dis_params& p = h->p;
-    return (p.flags & DIS_FLAG_KEEP_FOR_BACKWARD) && !(p.flags & DIS_FLAG_FB_CONSISTENCY) && dis_channels(&p) == 1 &&
-           h->bwd.Z[p.finest_scale] != nullptr;
+    return (p.flags & DIS_FLAG_KEEP_FOR_BACKWARD) && p.refine && !(p.flags & DIS_FLAG_FB_CONSISTENCY) &&
+           dis_channels(&p) == 1 && h->bwd.tape != nullptr && h->bwd.Z != nullptr;
 }
 
-int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs) {
+int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs,
+                     const LevelOpts* opt) {
     const dis_params& p = h->p;
     const int ps = p.patch_size, sf = p.finest_scale;
     const int cmap = (p.flags & DIS_FLAG_PIXEL_CENTRE) ? 1 : 0;
     int top = sf;
     for (const PairRef& r : pairs) top = std::max(top, r.ss);
-    const bool fbm = (p.flags & DIS_FLAG_FB_CONSISTENCY) && pairs.size() == 2;
+    const bool fbm = (p.flags & DIS_FLAG_FB_CONSISTENCY) && !opt && pairs.size() == 2;
     const int nc = dis_channels(&p);
-    // a forward kept for the adjoint writes what the adjoint reads as it goes
-    const bool record = pairs.size() == 1 && dis_forward_records(h);
+    const bool keep_tape = !opt && pairs.size() == 1 && dis_forward_keeps_finest(h);
     // colour frames and the merged densification run phase-major only
-    const int mode = (fbm || nc > 1 || h->arena) ? 1 : h->mode_phase;
+    const int mode = ((opt && opt->force_phase) || fbm || nc > 1 || h->arena) ? 1 : h->mode_phase;
     // static-scratch plans carry every argument in the launches themselves
     const bool no_tables = h->arena != nullptr;
-    if (no_tables && pairs.size() != 1) return fail(h, DIS_EINVAL, "internal: a static-scratch plan holds one pair");
+    if (no_tables && (pairs.size() != 1 || opt))
+        return fail(h, DIS_EINVAL, "internal: a static-scratch plan holds one pair and no recomputation");
     const int tile_id = mode ? h->refine_tile : DIS_LEVEL_TILE;
     int tw = 32, th = 16, nt = 256;
     dis_refine_tile(tile_id, &tw, &th, &nt);
@@ -597,6 +598,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     };
     std::vector<LevelHost> levels;
     for (int s = top; s >= sf; --s) {
+        if (opt && opt->only_level >= 0 && s != opt->only_level) continue;
         LevelHost LH;
         LH.s = s;
         LH.sby = LH.sfl = 0.0;
@@ -635,18 +637,20 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             da.ps = ps; da.st = g.st; da.nrx = g.nrx; da.nry = g.nry; da.nx = g.nx; da.ny = g.ny;
             da.raw_residual = (p.flags & DIS_FLAG_RAW_RESIDUAL) ? 1 : 0;
             da.U = L.Ud;
-            // (recorded per scale for the adjoint, else one buffer reused by every scale)
-            double* J1w = record ? h->bwd.J1w[s] : sb.J1w;
-            da.J1w = p.refine ? J1w : nullptr;
-            da.Z = record ? h->bwd.Z[s] : nullptr;
+            da.J1w = p.refine ? sb.J1w : nullptr;
+            // a forward kept for the adjoint records the finest scale's SOR
+            // tape and weight sums as it goes, so the adjoint starts there
+            // without recomputing that scale (the buffers hold one scale)
+            const bool record = keep_tape && s == sf;
+            da.Z = opt ? opt->Z : (record ? h->bwd.Z : nullptr);
             da.nc = nc;
             da.mdc = L.mdc;
             RefineArgs& ra = P.ra;
-            ra.U = L.Ud; ra.J0 = L.J0; ra.J1w = J1w; ra.Uout = L.U;
-            ra.lin = record ? h->bwd.lin[s] : sb.lin;
+            ra.U = L.Ud; ra.J0 = L.J0; ra.J1w = sb.J1w; ra.Uout = L.U;
+            ra.lin = sb.lin;
             ra.stereo = (p.flags & DIS_FLAG_STEREO) ? 1 : 0;
             ra.nc = nc;
-            ra.tape = record ? h->bwd.tape[s] : nullptr;
+            ra.tape = opt ? opt->tape : (record ? h->bwd.tape : nullptr);
             ra.W = W; ra.H = Hh;
             ra.tiles_x = (W + tw - 1) / tw;
             ra.delta = p.w_intensity; ra.gamma = p.w_gradient; ra.alpha = p.w_smooth;
@@ -656,9 +660,10 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             // single-workgroup scales: up to 256 pixel pairs, or up to the
             // block's capacity with the wider setting
             const int small_max = h->small_levels == 2 ? DIS_SMALL_PAIRS : DIS_SMALL_PAIRS / 4;
-            // (not in a forward kept for the adjoint: its reverse tiles read the
-            // tape and the linearisation cache, which the tiled refinement writes)
-            const bool small = p.refine && h->small_levels && !fbm && nc == 1 && !record &&
+            // (not in the adjoint's recomputation nor at a scale a forward
+            // records for it: the reverse tiles read the tape and the
+            // linearisation cache, which only the tiled refinement writes)
+            const bool small = p.refine && h->small_levels && !opt && !fbm && nc == 1 && !record &&
                                ((W + 1) / 2) * Hh <= small_max;
             if (small) LH.small.push_back((int)LH.lp.size());
             LH.is_small.push_back(small ? 1 : 0);
@@ -807,8 +812,8 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         LL.nph = LH.nph;
         LL.ntasks = t;
         LL.nruns = nruns_of[li];
-        // the adjoint's reverse tiles read the cache a recording forward fills
-        LL.lin_cache = (record || !h->no_lin_cache) ? 1 : 0;
+        // the adjoint's reverse tiles read the cache the recomputation fills
+        LL.lin_cache = (opt || !h->no_lin_cache || (keep_tape && LH.s == sf)) ? 1 : 0;
         if (np == 1) {
             LL.one = 1;
             LL.sa1 = LH.lp[0].sa;
@@ -830,6 +835,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
                 const int n = start[(ph + 1) * np] - start[ph * np];
                 if (n == 0) continue;
                 if (ph == 0) {
+                    if (opt && opt->skip_search) continue;
                     seq.add(fs, dim3(n), dim3(sblock), &LL, sizeof LL, 0, "search", ph_by[0], ph_fl[0]);
                 } else if (ph == 1 && fbm) {
                     // merged densification of both directions (App. B ii):
@@ -916,7 +922,7 @@ int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const 
     if (r != DIS_OK) return r;
     std::vector<PairRef> pr{PairRef{&sb, w, hgt, ss}};
     if (p.flags & DIS_FLAG_FB_CONSISTENCY) pr.push_back(PairRef{&h->slots[1], w, hgt, ss});
-    r = dis_build_levels(h, pr, seq, tabs);
+    r = dis_build_levels(h, pr, seq, tabs, nullptr);
     if (r != DIS_OK) return r;
     dis_add_upsample(h, sb, w, hgt, flow, tabs.plan_err, seq);
     // the first pyramid launch clears the level launches' queue state

@@ -103,13 +103,11 @@ struct BwdBuf {
     double* gJ1[DIS_MAXL];
     double* gU[DIS_MAXL];
     double* gP[DIS_MAXL];
-    // what the forward records at every processed scale for the adjoint
-    double* Z[DIS_MAXL];        // densification weight sums, [H][W]
-    double* J1w[DIS_MAXL];      // warped second frame, [H][W]
-    double* lin[DIS_MAXL];      // linearisation cache, [11][H][W]
-    double* tape[DIS_MAXL];     // SOR state after every half sweep, [half sweep][2][H][W]
+    double* Z;
     double *gUd, *gJ1w, *gd, *gn, *acc, *coef, *edge, *gFacc;
     double* gq;      // [2][px] flow adjoint handed between the two densification passes
+    double* tape;               // SOR states of one level, [half sweep][2][H][W]
+    size_t tape_len;            // capacity in doubles
     size_t scratch_px;          // pixels of the largest processed level
 };
 struct BatchPlan;
@@ -178,17 +176,27 @@ bool dis_search_rows_path(const dis_params* p);
 bool dis_search_has_lanes(const dis_params* p, int lpp);
 int dis_build_pair(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, const void* I0, const void* I1,
                    void* flow, Seq& seq, PairInfo* info, PlanTables& tabs);
+// Options of dis_build_levels for the backward pass's recomputation.
+struct LevelOpts {
+    int only_level = -1;        // build only this scale
+    double* tape = nullptr;     // record every SOR half sweep's state
+    double* Z = nullptr;        // keep the densification weight sums
+    int skip_search = 0;        // the patch records are kept: recompute from densification on
+    int force_phase = 0;        // one launch per phase whatever the tuned launch mode
+};
+
 int dis_alloc_backward(dis_handle* h);
-// A single-pair forward of this handle records, at every scale, the weight
-// sums, warped frame, linearisation and SOR tape in the adjoint's buffers;
-// the adjoint reads them and recomputes nothing.
-bool dis_forward_records(const dis_handle* h);
+// A single-pair forward of this handle records its finest scale's weight sums,
+// SOR tape, warped frame and linearisation in the adjoint's buffers, and the
+// adjoint starts from them instead of recomputing that scale.
+bool dis_forward_keeps_finest(const dis_handle* h);
 int dis_dalloc(dis_handle* h, void** ptr, size_t bytes);
 int dis_build_graph_seq(dis_handle* h, Seq& seq, hipGraph_t* graph, hipGraphExec_t* exec,
                         std::vector<hipGraphNode_t>* nodes);
 int dis_update_graph_seq(dis_handle* h, Seq& seq, hipGraphExec_t exec, const std::vector<hipGraphNode_t>& nodes);
 int dis_level_grid(const dis_handle* h, int W, int H, LevelGrid* g);   // patch grid of a W x H level; returns N
-int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs);
+int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs,
+                     const LevelOpts* opt);
 void dis_refine_phases(const dis_params& p, int s, std::vector<RefPhase>& out);
 int dis_add_pyramid(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, int ss, const void* I0, const void* I1,
                     Seq& seq);

@@ -186,10 +186,10 @@ def test_backward_repeat_and_graph_agree_with_eager():
 ])
 def test_tiled_reverse_sweeps_match_reference_form(name, cr, over):
     """The tiled reverse of each fixed-point step against one launch per
-    reverse half sweep (launch mode bit 2) and against a handle whose plain
-    forward would run these scales as single workgroups (bits 1 and 4; a
-    forward kept for the adjoint runs them as tiles, which record the tape),
-    and all against the oracle."""
+    reverse half sweep (launch mode bit 2) and against a handle whose forward
+    runs the coarser scales as single workgroups (bits 1 and 4; the finest
+    scale, whose tape the forward keeps, runs tiled, and the adjoint
+    recomputes the coarser ones tiled), and all against the oracle."""
     say(f"[adjoint] case tiled vs reference {name}")
     I0, I1, gt = crop(*cr)
     h, w = I0.shape
@@ -277,10 +277,10 @@ def test_backward_errors():
 
 
 def test_forward_kept_for_backward_is_the_plain_forward():
-    """A forward kept for the adjoint (which records every scale's SOR tape,
-    weight sums, warped frame and linearisation on the way, and runs the
-    scales a plain forward gives single workgroups as tiles) returns the plain
-    forward's flow bit for bit, in every launch mode."""
+    """A forward kept for the adjoint (which records the finest scale's SOR
+    tape, weight sums, warped frame and linearisation on the way, and runs
+    that scale tiled) returns the plain forward's flow bit for bit, in every
+    launch mode."""
     say("[adjoint] case kept forward vs plain forward, 512x256")
     pr = pair("bump", 512, 256, 16.0, 2000)
     a = torch.from_numpy(pr.I0).to(torch.float64).cuda()
