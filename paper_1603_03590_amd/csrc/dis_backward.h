@@ -43,7 +43,6 @@ struct RefBwdArgs {
     const double* J1w;
     double* coef;           // [6][H][W]: A12, om/(A11+S), om/(A22+S), c1, c2, ws
     double* acc;            // [9][H][W] coefficient adjoints from the sweeps
-    double* edge;           // [4][H][W] edge-weight adjoints seen from each endpoint (r, l, d, u)
     double* gU;             // += adjoint of Ud
     double* gF;             // += adjoint of F
     double* gJ0;            // += adjoint of J0 (level)
@@ -137,8 +136,7 @@ const void* dis_kernel_bwd_coef();
 const void* dis_kernel_bwd_coef2();
 const void* dis_kernel_bwd_sweep_a();
 const void* dis_kernel_bwd_sweep_b();
-const void* dis_kernel_bwd_lin();
-const void* dis_kernel_bwd_ws();
+const void* dis_kernel_bwd_lin_ws();
 const void* dis_kernel_bwd_densify();         // pass 1, per pixel
 const void* dis_kernel_bwd_densify_patch();   // pass 2, 16 lanes per patch
 const void* dis_kernel_bwd_pyramid();

@@ -293,42 +293,49 @@ __global__ __launch_bounds__(256) void k_bwd_sweep_b(const SweepBwdArgs a) {
     a.gd[n + g] += sv;
 }
 
+// Adjoints of A11 and A22 (through i = omega / (A + S)), of the pixel's
+// weight sum S and of c1, c2 (c = N - S U - B) from the step's coefficient
+// adjoints.
+struct PixAdj {
+    double gA11, gA22, gS, gc1, gc2;
+};
+__device__ __forceinline__ PixAdj pix_adj(const RefBwdArgs& a, size_t g, size_t n) {
+    const double* acc = a.acc;
+    const double i1 = a.coef[n + g], i2 = a.coef[2 * n + g];
+    const double gi1 = acc[g], gi2 = acc[n + g];
+    PixAdj r;
+    r.gc1 = acc[2 * n + g];
+    r.gc2 = acc[3 * n + g];
+    r.gA11 = -gi1 * i1 * i1 / a.omega;
+    r.gA22 = -gi2 * i2 * i2 / a.omega;
+    r.gS = r.gA11 + r.gA22 - a.U[g] * r.gc1 - a.U[n + g] * r.gc2;
+    return r;
+}
+
 // The coefficient adjoints of one fixed-point step, part 1 (per pixel):
 // through omega/(A+S), c = N - S U - B, the neighbour sums N and S, the
 // robust data weights and the linearisation, down to U, F, J0 and J1w.
-// Edge-weight adjoints as seen from each endpoint go to `edge` for part 2.
 __device__ __forceinline__ void bwd_lin_pixel(const RefBwdArgs& a, int x, int y, double (&simg)[2][8][68], int ox,
                                               int oy) {
     const int W = a.W, H = a.H;
     const size_t g = (size_t)y * W + x, n = (size_t)W * H;
     const double* ws = a.coef + 5 * n;
     const double* acc = a.acc;
-    const double om = a.omega;
     const bool hr = x < W - 1, hl = x > 0, hd = y < H - 1, hu = y > 0;
     const double wr = hr ? ws[g] : 0.0, wl = hl ? ws[g - 1] : 0.0;
     const double wd = hd ? ws[g] : 0.0, wu = hu ? ws[g - W] : 0.0;
     const double S = ((wr + wl) + wd) + wu;
-    const double i1 = a.coef[n + g], i2 = a.coef[2 * n + g];
-    const double gi1 = acc[g], gi2 = acc[n + g], gc1 = acc[2 * n + g], gc2 = acc[3 * n + g];
+    const PixAdj pa = pix_adj(a, g, n);
+    const double gA11 = pa.gA11, gA22 = pa.gA22, gc1 = pa.gc1, gc2 = pa.gc2;
     const double gA12 = acc[4 * n + g];
-    const double* U = a.U;
-    const double Up = U[g], Vp = U[n + g];
-    // i = omega / (A + S)
-    const double gA11 = -gi1 * i1 * i1 / om, gA22 = -gi2 * i2 * i2 / om;
-    const double gS = gA11 + gA22 - Up * gc1 - Vp * gc2;
     const double gB1 = -gc1, gB2 = -gc2;
     // c = N - S U - B: U at the pixel and its neighbours
     atom(a.gU + g, -S * gc1);
     atom(a.gU + n + g, -S * gc2);
-    double* E = a.edge;
     if (hr) { atom(a.gU + g + 1, wr * gc1); atom(a.gU + n + g + 1, wr * gc2); }
     if (hl) { atom(a.gU + g - 1, wl * gc1); atom(a.gU + n + g - 1, wl * gc2); }
     if (hd) { atom(a.gU + g + W, wd * gc1); atom(a.gU + n + g + W, wd * gc2); }
     if (hu) { atom(a.gU + g - W, wu * gc1); atom(a.gU + n + g - W, wu * gc2); }
-    E[0 * n + g] = hr ? acc[5 * n + g] + gS + gc1 * U[g + 1] + gc2 * U[n + g + 1] : 0.0;
-    E[1 * n + g] = hl ? acc[6 * n + g] + gS + gc1 * U[g - 1] + gc2 * U[n + g - 1] : 0.0;
-    E[2 * n + g] = hd ? acc[7 * n + g] + gS + gc1 * U[g + W] + gc2 * U[n + g + W] : 0.0;
-    E[3 * n + g] = hu ? acc[8 * n + g] + gS + gc1 * U[g - W] + gc2 * U[n + g - W] : 0.0;
 
     // robust data weights and linearisation
     const Lin L = lin_at(a, x, y);
@@ -405,17 +412,36 @@ __device__ __forceinline__ void bwd_lin_pixel(const RefBwdArgs& a, int x, int y,
     lds(0, x, yp, -gIyz / 2.0); lds(0, x, ym, gIyz / 2.0);
 }
 
-__global__ __launch_bounds__(256) void k_bwd_lin(const RefBwdArgs a) {
-    // the image adjoints of a 64x4 block land within 2 pixels of it: they are
-    // summed in LDS first (68x8 cells per image), then added to memory once
-    // per cell, which takes most of the float64 atomics off the memory side
+// One fixed-point step's coefficient adjoints on a 64x4 block.  Part 1 per
+// pixel (bwd_lin_pixel).  The image adjoints of the block land within 2
+// pixels of it: they are summed in LDS first (68x8 cells per image), then
+// added to memory once per cell, which takes most of the float64 atomics off
+// the memory side.  Part 2 per owner pixel: the adjoint of the edge weights
+// it owns (right and lower edge, each seen from both endpoints: the
+// coefficient adjoint of the edge plus the endpoint's dS and dc terms), then
+// through ws = alpha / (2 sqrt(E_S + eps^2)) and the forward differences of
+// U + F.  The endpoint terms of the block's pixels and of the column to its
+// right and the row below it are formed once, into LDS.
+__global__ __launch_bounds__(256) void k_bwd_lin_ws(const RefBwdArgs a) {
     __shared__ double simg[2][8][68];
+    __shared__ double sadj[3][5][65];   // dS, dc1, dc2
     for (int i = threadIdx.x; i < 2 * 8 * 68; i += 256) (&simg[0][0][0])[i] = 0.0;
-    __syncthreads();
-    const int ox = (int)blockIdx.x * 64 - 2, oy = (int)blockIdx.y * 4 - 2;
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     const int W = a.W, H = a.H;
+    const size_t n = (size_t)W * H;
+    const int x0 = (int)blockIdx.x * 64, y0 = (int)blockIdx.y * 4;
+    for (int i = threadIdx.x; i < 5 * 65; i += 256) {
+        const int ly = i / 65, lx = i - ly * 65;
+        const int xx = x0 + lx, yy = y0 + ly;
+        if (xx >= W || yy >= H) continue;
+        const PixAdj pa = pix_adj(a, (size_t)yy * W + xx, n);
+        sadj[0][ly][lx] = pa.gS;
+        sadj[1][ly][lx] = pa.gc1;
+        sadj[2][ly][lx] = pa.gc2;
+    }
+    __syncthreads();
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int x = x0 + lx, y = y0 + ly;
+    const int ox = x0 - 2, oy = y0 - 2;
     if (x < W && y < H) bwd_lin_pixel(a, x, y, simg, ox, oy);
     __syncthreads();
     for (int i = threadIdx.x; i < 2 * 8 * 68; i += 256) {
@@ -425,21 +451,18 @@ __global__ __launch_bounds__(256) void k_bwd_lin(const RefBwdArgs a) {
         if (v != 0.0 && gx >= 0 && gx < W && gy >= 0 && gy < H)
             unsafeAtomicAdd((f ? a.gJ1w : a.gJ0) + (size_t)gy * W + gx, v);
     }
-}
-
-// Part 2, per owner pixel: the adjoint of its edge weight (both edges, both
-// endpoints), then through ws = alpha / (2 sqrt(E_S + eps^2)) and the forward
-// differences of U + F.
-__global__ __launch_bounds__(256) void k_bwd_ws(const RefBwdArgs a) {
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int W = a.W, H = a.H;
     if (x >= W || y >= H) return;
-    const size_t g = (size_t)y * W + x, n = (size_t)W * H;
-    const double* E = a.edge;
+    const size_t g = (size_t)y * W + x;
+    const double* acc = a.acc;
+    const double* U = a.U;
+    // an edge's adjoint as seen from its endpoint ge (block cell cx, cy),
+    // whose coefficient adjoint of that edge is plane q; go: the other endpoint
+    auto seen = [&](int q, size_t ge, int cx, int cy, size_t go) {
+        return ((acc[q * n + ge] + sadj[0][cy][cx]) + sadj[1][cy][cx] * U[go]) + sadj[2][cy][cx] * U[n + go];
+    };
     double gws = 0.0;
-    if (x < W - 1) gws += E[0 * n + g] + E[1 * n + g + 1];
-    if (y < H - 1) gws += E[2 * n + g] + E[3 * n + g + W];
+    if (x < W - 1) gws += seen(5, g, lx, ly, g + 1) + seen(6, g + 1, lx + 1, ly, g);
+    if (y < H - 1) gws += seen(7, g, lx, ly, g + W) + seen(8, g + W, lx, ly + 1, g);
     if (gws == 0.0) return;
     double es;
     const double ws = ws_at(a, x, y, &es);
@@ -1147,8 +1170,7 @@ const void* dis_kernel_bwd_coef() { return (const void*)&k_bwd_coef; }
 const void* dis_kernel_bwd_coef2() { return (const void*)&k_bwd_coef2; }
 const void* dis_kernel_bwd_sweep_a() { return (const void*)&k_bwd_sweep_a; }
 const void* dis_kernel_bwd_sweep_b() { return (const void*)&k_bwd_sweep_b; }
-const void* dis_kernel_bwd_lin() { return (const void*)&k_bwd_lin; }
-const void* dis_kernel_bwd_ws() { return (const void*)&k_bwd_ws; }
+const void* dis_kernel_bwd_lin_ws() { return (const void*)&k_bwd_lin_ws; }
 const void* dis_kernel_bwd_densify_patch() { return (const void*)&k_bwd_densify_patch; }
 const void* dis_kernel_bwd_densify() { return (const void*)&k_bwd_densify; }
 const void* dis_kernel_bwd_pyramid() { return (const void*)&k_bwd_pyramid; }

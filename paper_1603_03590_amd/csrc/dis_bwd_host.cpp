@@ -81,7 +81,6 @@ int dis_alloc_backward(dis_handle* h) {
         DALLOC(h, B.gn, 2 * pxmax * sizeof(double));
         DALLOC(h, B.acc, 9 * pxmax * sizeof(double));
         DALLOC(h, B.coef, 6 * pxmax * sizeof(double));
-        DALLOC(h, B.edge, 4 * pxmax * sizeof(double));
         int nout_max = 1;
         for (int s = sf; s <= h->top; ++s) nout_max = std::max(nout_max, outer_steps(p, s));
         DALLOC(h, B.gFacc, (size_t)nout_max * 2 * pxmax * sizeof(double));
@@ -232,7 +231,6 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
                 ra.J1w = sb.J1w;
                 ra.coef = B.coef;
                 ra.acc = B.acc;
-                ra.edge = B.edge;
                 ra.gU = B.gUd;
                 ra.gF = tiled ? (k ? B.gFacc + (size_t)k * 2 * n : nullptr) : B.gFacc;
                 ra.gJ0 = B.gJ0[s];
@@ -313,10 +311,8 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
                               0.5 * 80.0 * px, 0.5 * 16.0 * px);
                     }
                 }
-                q.add(dis_kernel_bwd_lin(), grid2d(W, H), dim3(256), &ra, sizeof ra, 0, "bwd_lin", 200.0 * px,
-                      400.0 * px);
-                q.add(dis_kernel_bwd_ws(), grid2d(W, H), dim3(256), &ra, sizeof ra, 0, "bwd_ws", 96.0 * px,
-                      60.0 * px);
+                q.add(dis_kernel_bwd_lin_ws(), grid2d(W, H), dim3(256), &ra, sizeof ra, 0, "bwd_lin", 232.0 * px,
+                      460.0 * px);
                 if (!tiled && k) {
                     BCopyArgs ax{B.gd, B.gFacc, nullptr, 2 * n};
                     q.add(dis_kernel_baxpy(), dim3((unsigned)((2 * n + 255) / 256)), dim3(256), &ax, sizeof ax, 0,

@@ -104,7 +104,7 @@ struct BwdBuf {
     double* gU[DIS_MAXL];
     double* gP[DIS_MAXL];
     double* Z;
-    double *gUd, *gJ1w, *gd, *gn, *acc, *coef, *edge, *gFacc;
+    double *gUd, *gJ1w, *gd, *gn, *acc, *coef, *gFacc;
     double* gq;      // [2][px] flow adjoint handed between the two densification passes
     double* tape;               // SOR states of one level, [half sweep][2][H][W]
     size_t tape_len;            // capacity in doubles
