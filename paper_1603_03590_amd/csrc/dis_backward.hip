@@ -537,9 +537,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     dis_tile::TileCoef<PPT> C;
     double s_iu[Shape::NS][2], s_iv[Shape::NS][2];
     // the reverse steps below touch only pixels within kh of the core
-    // (the linearisation is read where it is used: registers are what
-    // limits how many of these blocks share a compute unit)
-    dis_tile::refine_setup<TW, TH, NT, KG, false, false>(a, g, sm.f, C, s_iu, s_iv, kh);
+    dis_tile::refine_setup<TW, TH, NT, KG>(a, g, sm.f, C, s_iu, s_iv, kh);
     __syncthreads();   // the set-up planes are dead from here on
     // The adjoint moves one pixel per reverse half sweep: after reverse step
     // r (of kh) the core's outputs still depend on pixels within kh - 1 - r

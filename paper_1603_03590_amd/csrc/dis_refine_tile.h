@@ -89,7 +89,7 @@ struct TileShape {
 // the caller never updates them (their starting increments and weights are
 // still set).  Ends with the image tile still live; the caller places a
 // barrier before reusing it.
-template <int TW, int TH, int NT, int KG = DIS_KMAX, bool COLOUR = false, bool LIN_PREFETCH = true>
+template <int TW, int TH, int NT, int KG = DIS_KMAX, bool COLOUR = false>
 __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom& g, RefineSmem<TW, TH, KG>& sm,
                                              TileCoef<TileShape<TW, TH, NT, KG>::PPT>& C,
                                              double (&s_iu)[TileShape<TW, TH, NT, KG>::NS][2],
@@ -108,10 +108,7 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
     const auto* __restrict__ Din = dis_global(a.dUin);
 
     constexpr bool kLin = TileShape<TW, TH, NT, KG>::kLin;
-    // cached linearisation: into registers with the first loads, or (fewer
-    // registers) read where the coefficients are formed
-    constexpr bool kLinPf = kLin && LIN_PREFETCH;
-    constexpr int NL = kLinPf ? TileShape<TW, TH, NT, KG>::NL : 1;
+    constexpr int NL = TileShape<TW, TH, NT, KG>::NL;
     const bool lin_load = kLin && a.lin_mode == 2;
     constexpr bool colour = COLOUR;   // lin_mode 3: per-channel linearisation
     double s_fu[kStage ? PPT : 1][2], s_fv[kStage ? PPT : 1][2];
@@ -139,7 +136,7 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
                 if (F) { s_fu[k][c] = F[gi]; s_fv[k][c] = F[n + gi]; }
             }
             if (far[k][c]) continue;
-            if constexpr (kLinPf) {
+            if constexpr (kLin) {
                 if (lin_load) {
 #pragma unroll
                     for (int q = 0; q < 11; ++q) s_lin[k][c][q] = dis_global(a.lin)[q * n + gi];
@@ -275,16 +272,10 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
                 bool cached = false;
                 if constexpr (kLin) {
                     if (lin_load) {
-                        double q[11];
-#pragma unroll
-                        for (int i = 0; i < 11; ++i) {
-                            if constexpr (kLinPf) q[i] = s_lin[k][c][i];
-                            else q[i] = dis_global(a.lin)[i * n + gi];
-                        }
-                        Ix = q[0]; Iy = q[1]; Iz = q[2];
-                        Ixx = q[3]; Ixy = q[4]; Iyy = q[5];
-                        Ixz = q[6]; Iyz = q[7];
-                        b0 = q[8]; bx = q[9]; by = q[10];
+                        Ix = s_lin[k][c][0]; Iy = s_lin[k][c][1]; Iz = s_lin[k][c][2];
+                        Ixx = s_lin[k][c][3]; Ixy = s_lin[k][c][4]; Iyy = s_lin[k][c][5];
+                        Ixz = s_lin[k][c][6]; Iyz = s_lin[k][c][7];
+                        b0 = s_lin[k][c][8]; bx = s_lin[k][c][9]; by = s_lin[k][c][10];
                         cached = true;
                     }
                 }
