@@ -76,7 +76,7 @@ static int build_batch(dis_handle* h, int n, const int* w, const int* hgt, const
             if (idx >= tmp.items.size()) continue;
             const PyrArgs pa = *(const PyrArgs*)tmp.items[idx].arg.data();
             tab.push_back(pa);
-            st.push_back(st.back() + pa.tiles_x * ((pa.h0 + 31) / 32));
+            st.push_back(st.back() + dis_pyramid_tiles(pa));
         }
         if (tab.empty()) break;
         passes.push_back(tab);
@@ -91,7 +91,7 @@ static int build_batch(dis_handle* h, int n, const int* w, const int* hgt, const
         dis_add_upsample(h, *pairs[k].sb, w[k], hgt[k], nullptr, nullptr, tmp);
         const UpsArgs ua = *(const UpsArgs*)tmp.items[0].arg.data();
         bp->ups.push_back(ua);
-        ust.push_back(ust.back() + ((w[k] + 255) / 256) * ((hgt[k] + 3) / 4));
+        ust.push_back(ust.back() + ((w[k] + 255) / 256) * dis_upsample_blocks_y(hgt[k]));
     }
     // device layout of the pyramid and upscaling tables
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -136,7 +136,7 @@ static int build_batch(dis_handle* h, int n, const int* w, const int* hgt, const
         T.n = (int)passes[i].size();
         double by = 0.0;
         for (const PyrArgs& pa : passes[i]) by += 2.0 * pa.w0 * pa.h0 * (i == 0 ? (f64io ? 8 : 4) : 8);
-        bp->seq.add(dis_kernel_pyramid_tab(), dim3(pstart[i].back(), 2), dim3(256), &T, sizeof T, 0, "pyramid", by,
+        bp->seq.add(dis_kernel_pyramid_tab(), dim3(pstart[i].back(), 2), dim3(DIS_PYR_THREADS), &T, sizeof T, 0, "pyramid", by,
                     0.0);
     }
     int r = dis_build_levels(h, pairs, bp->seq, bp->tabs, nullptr);

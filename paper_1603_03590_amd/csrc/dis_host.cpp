@@ -490,8 +490,8 @@ int dis_add_pyramid(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, int s
             // keep the levels that are processed, and the start of the next pass
             if (s >= sf || (s == a + 5 && s < ss)) { pa.dst[0][k] = sb.lv[s].J0; pa.dst[1][k] = sb.lv[s].J1; }
         }
-        pa.tiles_x = (w0 + 31) / 32;
-        const int tiles = pa.tiles_x * ((h0 + 31) / 32);
+        pa.tiles_x = (w0 + 255) / 256;
+        const int tiles = dis_pyramid_tiles(pa);
         // traffic: both frames of level a in, every kept level out (float64)
         double by = 2.0 * (double)w0 * h0 * (a == 0 ? (f64io ? 8 : 4) : 8), fl = a == 0 ? 2.0 * w0 * h0 : 0.0;
         if (pa.lvl0[0]) by += 16.0 * w0 * h0;
@@ -500,7 +500,7 @@ int dis_add_pyramid(dis_handle* h, SlotBuf& sb, int w, int hgt, int pitch, int s
             fl += 2.0 * 4.0 * px;
             if (pa.dst[0][k]) by += 16.0 * px;
         }
-        seq.add(dis_kernel_pyramid(), dim3(tiles, 2 * nc), dim3(256), &pa, sizeof pa, a == 0 ? 1 : 0, "pyramid",
+        seq.add(dis_kernel_pyramid(), dim3(tiles, 2 * nc), dim3(DIS_PYR_THREADS), &pa, sizeof pa, a == 0 ? 1 : 0, "pyramid",
                 nc * by, nc * fl);
         if (ss == 0) break;
     }
@@ -523,7 +523,7 @@ void dis_add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, co
     ua.out = flow;
     ua.out_f64 = f64io ? 1 : 0;
     ua.poison = poison;
-    seq.add(dis_kernel_upsample(), dim3((w + 255) / 256, (hgt + 3) / 4), dim3(256), &ua, sizeof ua, 2, "upsample",
+    seq.add(dis_kernel_upsample(), dim3((w + 255) / 256, dis_upsample_blocks_y(hgt)), dim3(256), &ua, sizeof ua, 2, "upsample",
             16.0 * ua.Ws * ua.Hs + (f64io ? 16.0 : 8.0) * w * hgt, 20.0 * w * hgt);
 }
 

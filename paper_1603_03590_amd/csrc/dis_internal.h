@@ -28,6 +28,14 @@ struct PyrArgs {
     int nzero;
 };
 
+// 256x32 tiles (512-thread blocks) of level a a pyramid pass covers
+#define DIS_PYR_THREADS 512
+inline int dis_pyramid_tiles(const PyrArgs& pa) { return pa.tiles_x * ((pa.h0 + 31) / 32); }
+
+// output rows of one upscaling block (256 columns wide), and the blocks of a W x H flow
+#define DIS_UPS_ROWS 16
+inline int dis_upsample_blocks_y(int H) { return (H + DIS_UPS_ROWS - 1) / DIS_UPS_ROWS; }
+
 // Inverse search on one level: grid, initialisation, Gauss-Newton, reset,
 // final residual mean.
 struct SearchArgs {

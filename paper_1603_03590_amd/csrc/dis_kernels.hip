@@ -42,13 +42,19 @@ __device__ __forceinline__ double bilin(P img, int W, int H, double x, double y)
 
 // ------------------------------------------------------------------ pyramid
 
-// One 32x32 tile of level a of frame f, channel c: the tile's part of levels
-// a+1..a+nlev.  The argument block is read once, before the tile's loads
-// (in the table-driven launch it sits in memory, and the barriers between
-// levels would otherwise make every level read it again).
+// One 256x32 tile of level a of frame f, channel c (512 threads): the tile's
+// part of levels a+1..a+nlev.  Each thread owns a 4x4 block of level a (a
+// wave covers 256 consecutive columns of four rows: every row of the tile is
+// read as one 1 KB run) and forms its 2x2 of level a+1 and its pixel of level
+// a+2 in registers; levels a+3.. come from LDS.  Every level pixel is the
+// mean of a 2x2 block of the level below, summed row-major ((a+b)+c)+d, then
+// scaled, whichever way it is reached.  Pixels outside level a read as 0;
+// they never reach a stored pixel (levels are floor-halved).  The argument
+// block is read once, before the tile's loads (in the table-driven launch it
+// sits in memory).
 __device__ __forceinline__ void pyramid_tile(const PyrArgs& A, int tile, int f, int c) {
-    __shared__ double t0[32][33];
-    __shared__ double t1[16][17];
+    __shared__ double t2[8][65];
+    __shared__ double t3[4][33];
     const int tiles_x = A.tiles_x, w0 = A.w0, h0 = A.h0, nlev = A.nlev, kind = A.src_kind, pitch = A.src_pitch;
     const double scale = A.scale;
     const size_t cs = (size_t)c * A.src_cstride;
@@ -63,77 +69,105 @@ __device__ __forceinline__ void pyramid_tile(const PyrArgs& A, int tile, int f, 
         hs[k] = A.hs[k];
     }
     const int bx = tile % tiles_x, by = tile / tiles_x;
-    const int X0 = bx * 32, Y0 = by * 32;
-    // the four loads of a thread are issued before any is used, so the tile
-    // costs one round of memory latency
-    double v4[4];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int x0 = bx * 256 + 4 * tx, y0 = by * 32 + 4 * ty;   // the thread's 4x4 block of level a
+    // the loads are issued before any is used: one round of latency.  A row of
+    // the block is one 16-byte load of a float32 frame (two of float64 data)
+    // when the rows are 16-byte aligned and the block lies inside the level.
+    const bool vec = ((reinterpret_cast<size_t>(src) | ((size_t)pitch * (kind == 1 ? 4 : 8)) |
+                       (cs * (kind == 1 ? 4 : 8))) & 15) == 0;
+    double v[4][4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int i = threadIdx.x + k * 256;
-        const int ly = i >> 5, lx = i & 31;
-        const int x = X0 + lx, y = Y0 + ly;
-        v4[k] = 0.0;
-        if (x < w0 && y < h0) {
-            const size_t g = cs + (size_t)y * pitch + x;
-            if (kind == 1)
-                v4[k] = (double)((const float*)src)[g];
-            else
-                v4[k] = ((const double*)src)[g];
+    for (int r = 0; r < 4; ++r) {
+        const int y = y0 + r;
+        const size_t g0 = cs + (size_t)y * pitch + x0;
+        if (vec && y < h0 && x0 + 3 < w0) {
+            if (kind == 1) {
+                const float4 q4 = *reinterpret_cast<const float4*>((const float*)src + g0);
+                v[r][0] = (double)q4.x; v[r][1] = (double)q4.y; v[r][2] = (double)q4.z; v[r][3] = (double)q4.w;
+            } else {
+                const double2 p0 = *reinterpret_cast<const double2*>((const double*)src + g0);
+                const double2 p1 = *reinterpret_cast<const double2*>((const double*)src + g0 + 2);
+                v[r][0] = p0.x; v[r][1] = p0.y; v[r][2] = p1.x; v[r][3] = p1.y;
+            }
+            continue;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int x = x0 + q;
+            v[r][q] = 0.0;
+            if (x < w0 && y < h0) {
+                if (kind == 1)
+                    v[r][q] = (double)((const float*)src)[g0 + q];
+                else
+                    v[r][q] = ((const double*)src)[g0 + q];
+            }
         }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int i = threadIdx.x + k * 256;
-        const int ly = i >> 5, lx = i & 31;
-        const int x = X0 + lx, y = Y0 + ly;
-        double v = 0.0;
-        if (x < w0 && y < h0) {
-            v = scale * v4[k];
-            if (lvl0) lvl0[((size_t)c * h0 + y) * w0 + x] = v;
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int x = x0 + q, y = y0 + r;
+            v[r][q] = (x < w0 && y < h0) ? scale * v[r][q] : 0.0;
+            if (lvl0 && x < w0 && y < h0) lvl0[((size_t)c * h0 + y) * w0 + x] = v[r][q];
         }
-        t0[ly][lx] = v;
     }
+    auto mean4 = [](double p, double q, double r, double s) { return 0.25 * (((p + q) + r) + s); };
+    auto put = [&](int k, int xs, int ys, double val) {
+        double* d = dst[k];
+        if (d && xs < ws[k] && ys < hs[k]) d[((size_t)c * hs[k] + ys) * ws[k] + xs] = val;
+    };
+    // level a+1 (2x2) and a+2 (1) of the block
+    double l1[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            l1[r][q] = mean4(v[2 * r][2 * q], v[2 * r][2 * q + 1], v[2 * r + 1][2 * q], v[2 * r + 1][2 * q + 1]);
+            if (nlev >= 1) put(1, (x0 >> 1) + q, (y0 >> 1) + r, l1[r][q]);
+        }
+    const double l2 = mean4(l1[0][0], l1[0][1], l1[1][0], l1[1][1]);
+    if (nlev >= 2) put(2, x0 >> 2, y0 >> 2, l2);
+    if (nlev < 3) return;   // uniform over the block
+    t2[ty][tx] = l2;
     __syncthreads();
-#pragma unroll
-    for (int k = 1; k < 6; ++k) {
-        if (k > nlev) break;
-        const int n = 32 >> k;
-        // level k of the tile (n x n <= 256, one pixel per thread): mean of a
-        // 2x2 block of level k-1, summed row-major ((a+b)+c)+d, then scaled
-        const bool from0 = (k & 1);
-        const bool act = threadIdx.x < n * n;
-        const int ly = threadIdx.x / n, lx = threadIdx.x - ly * n;
-        double v = 0.0;
-        if (act) {
-            if (from0)
-                v = 0.25 * (((t0[2 * ly][2 * lx] + t0[2 * ly][2 * lx + 1]) + t0[2 * ly + 1][2 * lx]) +
-                            t0[2 * ly + 1][2 * lx + 1]);
-            else
-                v = 0.25 * (((t1[2 * ly][2 * lx] + t1[2 * ly][2 * lx + 1]) + t1[2 * ly + 1][2 * lx]) +
-                            t1[2 * ly + 1][2 * lx + 1]);
-            const int xs = (X0 >> k) + lx, ys = (Y0 >> k) + ly;
-            double* d = dst[k];
-            if (d && xs < ws[k] && ys < hs[k]) d[((size_t)c * hs[k] + ys) * ws[k] + xs] = v;
-        }
-        __syncthreads();   // every read of the source buffer precedes the overwrite
-        if (act) {
-            if (from0) t1[ly][lx] = v; else t0[ly][lx] = v;
-        }
-        __syncthreads();
+    // level a+3: 32x4, level a+4: 16x2, level a+5: 8x1 of the tile
+    if (threadIdx.x < 128) {
+        const int ly = threadIdx.x >> 5, lx = threadIdx.x & 31;
+        const double l3 = mean4(t2[2 * ly][2 * lx], t2[2 * ly][2 * lx + 1], t2[2 * ly + 1][2 * lx], t2[2 * ly + 1][2 * lx + 1]);
+        put(3, bx * 32 + lx, by * 4 + ly, l3);
+        t3[ly][lx] = l3;
+    }
+    if (nlev < 4) return;
+    __syncthreads();
+    double l4 = 0.0;
+    if (threadIdx.x < 32) {
+        const int ly = threadIdx.x >> 4, lx = threadIdx.x & 15;
+        l4 = mean4(t3[2 * ly][2 * lx], t3[2 * ly][2 * lx + 1], t3[2 * ly + 1][2 * lx], t3[2 * ly + 1][2 * lx + 1]);
+        put(4, bx * 16 + lx, by * 2 + ly, l4);
+    }
+    if (nlev < 5) return;
+    // (t2 was last read before the barrier above)
+    if (threadIdx.x < 32) t2[threadIdx.x >> 4][threadIdx.x & 15] = l4;
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        const int lx = threadIdx.x;
+        put(5, bx * 8 + lx, by, mean4(t2[0][2 * lx], t2[0][2 * lx + 1], t2[1][2 * lx], t2[1][2 * lx + 1]));
     }
 }
 
-__global__ __launch_bounds__(256) void k_pyramid(const PyrArgs a) {
+__global__ __launch_bounds__(512) void k_pyramid(const PyrArgs a) {
     if (blockIdx.x == 0 && blockIdx.y == 0)
-        for (int i = threadIdx.x; i < a.nzero; i += 256) a.zero[i] = 0;
+        for (int i = threadIdx.x; i < a.nzero; i += 512) a.zero[i] = 0;
     pyramid_tile(a, blockIdx.x, blockIdx.y & 1, blockIdx.y >> 1);
 }
 
 // Pyramid passes of many pairs in one launch (tiles of pair j are
 // start[j] .. start[j+1]-1).
-__global__ __launch_bounds__(256) void k_pyramid_tab(const PyrTab T) {
+__global__ __launch_bounds__(512) void k_pyramid_tab(const PyrTab T) {
     if (blockIdx.x == 0 && blockIdx.y == 0)
-        for (int i = threadIdx.x; i < T.nzero; i += 256) T.zero[i] = 0;
+        for (int i = threadIdx.x; i < T.nzero; i += 512) T.zero[i] = 0;
     const int t = blockIdx.x;
     const int j = __builtin_amdgcn_readfirstlane(T.blk[t]);
     pyramid_tile(T.tab[j], t - __builtin_amdgcn_readfirstlane(T.start[j]), blockIdx.y, 0);
@@ -1018,57 +1052,59 @@ __global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
 
 // ----------------------------------------------------------------- upscale
 
-// A 256x4 block of the output: each thread computes four pixels 64 apart in
-// a row (every store instruction writes 64 consecutive elements), with all
-// their taps requested together.  The value is bilin() of each flow plane,
-// f times: the row's vertical taps and weight are shared by the pixels and
-// both planes, and x / f is a multiplication by 1 / f, exact for f = 2^s.
+// A block of the output, 256 columns by DIS_UPS_ROWS rows: each thread one
+// column (every store instruction writes 64 consecutive elements).  The value
+// is bilin() of each flow plane, f times.  A column's horizontal taps and
+// weight are the same in every row, and a row's vertical ones are the same
+// in every column; consecutive rows usually share their two source rows
+// (f >= 2), so the four taps of both planes and their horizontal blends are
+// formed again only when those change.  x / f is a multiplication by 1 / f,
+// exact for f = 2^s.
 __device__ __forceinline__ void upsample_block(const UpsArgs& a, int bx, int by) {
-    const int y = by * 4 + (threadIdx.x >> 6);
-    if (y >= a.H) return;
     const int Ws = a.Ws, Hs = a.Hs;
     const double f = a.f, inv_f = 1.0 / f;
     const double* Uu = a.U;
     const double* Uv = a.U + (size_t)Ws * Hs;
-    const double qy = a.centre_map ? ((double)y + 0.5) * inv_f - 0.5 : (double)y * inv_f;
-    double yf = floor(qy);
-    const double ay = qy - yf;
-    yf = fmin(fmax(yf, -2.0), (double)Hs + 1.0);
-    const int yi = (int)yf;
-    const int r0 = clampi(yi, 0, Hs - 1) * Ws, r1 = clampi(yi + 1, 0, Hs - 1) * Ws;
-    double u4[4], v4[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int x = min(bx * 256 + k * 64 + (int)(threadIdx.x & 63), a.W - 1);
-        const double qx = a.centre_map ? ((double)x + 0.5) * inv_f - 0.5 : (double)x * inv_f;
-        double xf = floor(qx);
-        const double ax = qx - xf;
-        xf = fmin(fmax(xf, -2.0), (double)Ws + 1.0);
-        const int xi = (int)xf;
-        const int c0 = clampi(xi, 0, Ws - 1), c1 = clampi(xi + 1, 0, Ws - 1);
-        const double ut = (1.0 - ax) * Uu[r0 + c0] + ax * Uu[r0 + c1];
-        const double ub = (1.0 - ax) * Uu[r1 + c0] + ax * Uu[r1 + c1];
-        const double vt = (1.0 - ax) * Uv[r0 + c0] + ax * Uv[r0 + c1];
-        const double vb = (1.0 - ax) * Uv[r1 + c0] + ax * Uv[r1 + c1];
-        u4[k] = f * ((1.0 - ay) * ut + ay * ub);
-        v4[k] = f * ((1.0 - ay) * vt + ay * vb);
-    }
+    const int xo = bx * 256 + (int)threadIdx.x;
+    const int x = min(xo, a.W - 1);
+    const double qx = a.centre_map ? ((double)x + 0.5) * inv_f - 0.5 : (double)x * inv_f;
+    double xf = floor(qx);
+    const double ax = qx - xf;
+    xf = fmin(fmax(xf, -2.0), (double)Ws + 1.0);
+    const int xi = (int)xf;
+    const int c0 = clampi(xi, 0, Ws - 1), c1 = clampi(xi + 1, 0, Ws - 1);
     const size_t n = (size_t)a.W * a.H;
-    if (a.poison && __builtin_amdgcn_readfirstlane(*dis_global(a.poison)) != 0) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) u4[k] = v4[k] = __builtin_nan("");
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int x = bx * 256 + k * 64 + (int)(threadIdx.x & 63);
-        if (x >= a.W) continue;
-        const size_t g = (size_t)y * a.W + x;
+    const bool bad = a.poison && __builtin_amdgcn_readfirstlane(*dis_global(a.poison)) != 0;
+    const int y0 = by * DIS_UPS_ROWS, yn = min(DIS_UPS_ROWS, a.H - y0);
+    int p0 = -1, p1 = -1;
+    double ut = 0.0, ub = 0.0, vt = 0.0, vb = 0.0;
+    for (int i = 0; i < yn; ++i) {
+        const int y = y0 + i;
+        const double qy = a.centre_map ? ((double)y + 0.5) * inv_f - 0.5 : (double)y * inv_f;
+        double yf = floor(qy);
+        const double ay = qy - yf;
+        yf = fmin(fmax(yf, -2.0), (double)Hs + 1.0);
+        const int yi = (int)yf;
+        const int r0 = clampi(yi, 0, Hs - 1) * Ws, r1 = clampi(yi + 1, 0, Hs - 1) * Ws;
+        if (r0 != p0 || r1 != p1) {   // uniform: the rows depend on y only
+            ut = (1.0 - ax) * Uu[r0 + c0] + ax * Uu[r0 + c1];
+            ub = (1.0 - ax) * Uu[r1 + c0] + ax * Uu[r1 + c1];
+            vt = (1.0 - ax) * Uv[r0 + c0] + ax * Uv[r0 + c1];
+            vb = (1.0 - ax) * Uv[r1 + c0] + ax * Uv[r1 + c1];
+            p0 = r0;
+            p1 = r1;
+        }
+        double u = f * ((1.0 - ay) * ut + ay * ub);
+        double v = f * ((1.0 - ay) * vt + ay * vb);
+        if (bad) u = v = __builtin_nan("");
+        if (xo >= a.W) continue;
+        const size_t g = (size_t)y * a.W + xo;
         if (a.out_f64) {
-            ((double*)a.out)[g] = u4[k];
-            ((double*)a.out)[n + g] = v4[k];
+            ((double*)a.out)[g] = u;
+            ((double*)a.out)[n + g] = v;
         } else {
-            ((float*)a.out)[g] = (float)u4[k];
-            ((float*)a.out)[n + g] = (float)v4[k];
+            ((float*)a.out)[g] = (float)u;
+            ((float*)a.out)[n + g] = (float)v;
         }
     }
 }
