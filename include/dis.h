@@ -204,7 +204,8 @@ int dis_autotune(dis_handle* h, const char* cache_path);
  * refine_tile picks the refinement tile (core width x height, threads) of the
  * per-phase launches: 0: 32x16/256, 1: 16x16/256, 2: 64x8/256,
  * 3: 16x16/1024, 4: 32x16/1024, 5: 16x16/512, 6: 32x16/512, 7: 8x8/512,
- * 8: 16x8/512, 9: 8x8/256, 10: 8x4/384.  launch_mode bit 0: 0 runs each scale as one
+ * 8: 16x8/512, 9: 8x8/256, 10: 8x4/384, and with no LDS copy of U (two blocks
+ * per compute unit) 11: 32x16/512, 12: 16x16/512.  launch_mode bit 0: 0 runs each scale as one
  * persistent launch over a task queue, 1 as one launch per phase; bit 1 set
  * turns on the single-workgroup path: a scale of at most 256 horizontal
  * pixel pairs (1024 with bit 4 also set) is densified and refined, every
@@ -215,7 +216,10 @@ int dis_autotune(dis_handle* h, const char* cache_path);
  * instead of the scale's first launch storing it for the later ones (less
  * HBM traffic, more arithmetic per launch); bit 5 exists to test the
  * failure path of the persistent launch: every wait there that would block
- * gives up at once, as a timed-out wait does (the flow becomes NaN).  Every
+ * gives up at once, as a timed-out wait does (the flow becomes NaN); bit 6
+ * set runs the per-phase refinement of a scale whose tiles number at least
+ * twice the compute units with the lean tile of the same core and threads
+ * (tile 6 -> 11, 5 -> 12) where there is one.  Every
  * other choice gives
  * bitwise-identical flow (gradients agree to rounding: they are summed with
  * atomics).  Synchronises the stream and drops cached launch

@@ -91,7 +91,7 @@ static int build_batch(dis_handle* h, int n, const int* w, const int* hgt, const
         dis_add_upsample(h, *pairs[k].sb, w[k], hgt[k], nullptr, nullptr, tmp);
         const UpsArgs ua = *(const UpsArgs*)tmp.items[0].arg.data();
         bp->ups.push_back(ua);
-        ust.push_back(ust.back() + ((w[k] + 255) / 256) * dis_upsample_blocks_y(hgt[k]));
+        ust.push_back(ust.back() + ((w[k] + 255) / 256) * dis_upsample_blocks_y(w[k], hgt[k]));
     }
     // device layout of the pyramid and upscaling tables
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -367,6 +367,8 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
     if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, 3});    // single-workgroup scales of <= 256 pairs
     if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, 19});   // ... of <= 1024 pairs
     if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, bestc.mode | 8});   // no linearisation cache
+    if (r == DIS_OK && dis_refine_tile_lean(bestc.tile) >= 0 && !(bestc.mode & 64))
+        r = measure(Cand{bestc.lpp, bestc.tile, bestc.mode | 64});   // lean twin on the large scales
     if (r == DIS_OK) r = measure(Cand{0, 0, 0});
     for (int l : lpps)
         if (r == DIS_OK && dis_search_has_lanes(&h->p, l) &&

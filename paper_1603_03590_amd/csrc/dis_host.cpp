@@ -335,7 +335,7 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     int tw, th;
     if (!dis_refine_tile(refine_tile, &tw, &th, nullptr))
         return fail(h, DIS_EINVAL, "unknown refinement tile %d", refine_tile);
-    if (launch_mode < 0 || launch_mode > 63) return fail(h, DIS_EINVAL, "launch mode %d outside 0..63", launch_mode);
+    if (launch_mode < 0 || launch_mode > 127) return fail(h, DIS_EINVAL, "launch mode %d outside 0..127", launch_mode);
     if (lanes_per_patch)
         for (int s = 0; s < DIS_MAXL; ++s) {
             const int l = lanes_per_patch[s];
@@ -351,6 +351,7 @@ extern "C" int dis_set_tunables(dis_handle* h, const int* lanes_per_patch, int r
     h->bwd_reference = (launch_mode & 4) ? 1 : 0;
     h->no_lin_cache = (launch_mode & 8) ? 1 : 0;
     h->fail_waits = (launch_mode & 32) ? 1 : 0;
+    h->lean_big = (launch_mode & 64) ? 1 : 0;
     return DIS_OK;
 }
 
@@ -361,7 +362,7 @@ extern "C" int dis_get_tunables(const dis_handle* h, int* lanes_per_patch, int* 
     if (refine_tile) *refine_tile = h->refine_tile;
     if (launch_mode)
         *launch_mode = h->mode_phase | (h->small_levels ? 2 : 0) | (h->bwd_reference ? 4 : 0) | (h->no_lin_cache ? 8 : 0) |
-                       (h->small_levels == 2 ? 16 : 0) | (h->fail_waits ? 32 : 0);
+                       (h->small_levels == 2 ? 16 : 0) | (h->fail_waits ? 32 : 0) | (h->lean_big ? 64 : 0);
     return DIS_OK;
 }
 
@@ -523,7 +524,8 @@ void dis_add_upsample(dis_handle* h, SlotBuf& sb, int w, int hgt, void* flow, co
     ua.out = flow;
     ua.out_f64 = f64io ? 1 : 0;
     ua.poison = poison;
-    seq.add(dis_kernel_upsample(), dim3((w + 255) / 256, dis_upsample_blocks_y(hgt)), dim3(256), &ua, sizeof ua, 2, "upsample",
+    ua.rows = dis_upsample_rows(w, hgt);
+    seq.add(dis_kernel_upsample(), dim3((w + 255) / 256, dis_upsample_blocks_y(w, hgt)), dim3(256), &ua, sizeof ua, 2, "upsample",
             16.0 * ua.Ws * ua.Hs + (f64io ? 16.0 : 8.0) * w * hgt, 20.0 * w * hgt);
 }
 
@@ -878,7 +880,11 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
                     PL.L = LL;
                     PL.phase = ph;
                     if (LL.one) PL.ra1 = dis_phase_args(LH.lp[0], LH.rph[ph - 2], LL.lin_cache, nc > 1);
-                    seq.add(nc > 1 ? dis_kernel_phase_refine_colour(tile_id) : dis_kernel_phase_refine(tile_id), dim3(n),
+                    // (launch-mode bit 6: the lean twin, same core and threads,
+                    // where the tiles fill every CU at least twice)
+                    const int twin = dis_refine_tile_lean(tile_id);
+                    const int tl = (h->lean_big && twin >= 0 && n >= 2 * h->n_cu) ? twin : tile_id;
+                    seq.add(nc > 1 ? dis_kernel_phase_refine_colour(tl) : dis_kernel_phase_refine(tl), dim3(n),
                             dim3(nt), &PL, sizeof PL, 0, "refine",
                             ph_by[ph], ph_fl[ph]);
                 }

@@ -134,6 +134,7 @@ struct dis_handle {
     int bwd_reference = 0;  // backward: one launch per reverse half sweep instead of reverse tiles
     int no_lin_cache = 0;   // forward refinement recomputes the linearisation in every launch
     int fail_waits = 0;     // failure-path testing: persistent waits that would block give up at once
+    int lean_big = 0;       // lean twin of the refinement tile on scales with at least two tiles per CU
     int n_cu = 256;
     // Static-scratch mode: device buffers are carved from [arena, arena +
     // arena_cap) instead of allocated; plans are single-pair and phase-major,

@@ -32,9 +32,11 @@ struct PyrArgs {
 #define DIS_PYR_THREADS 512
 inline int dis_pyramid_tiles(const PyrArgs& pa) { return pa.tiles_x * ((pa.h0 + 31) / 32); }
 
-// output rows of one upscaling block (256 columns wide), and the blocks of a W x H flow
-#define DIS_UPS_ROWS 16
-inline int dis_upsample_blocks_y(int H) { return (H + DIS_UPS_ROWS - 1) / DIS_UPS_ROWS; }
+// output rows of one upscaling block (256 columns wide) of a W x H flow: 16
+// from a megapixel up (fewer tap rounds per pixel), else 8 (more blocks in
+// flight for a short launch); and the block rows of the flow
+inline int dis_upsample_rows(int W, int H) { return (long long)W * H >= (1 << 20) ? 16 : 8; }
+inline int dis_upsample_blocks_y(int W, int H) { return (H + dis_upsample_rows(W, H) - 1) / dis_upsample_rows(W, H); }
 
 // Inverse search on one level: grid, initialisation, Gauss-Newton, reset,
 // final residual mean.
@@ -112,6 +114,7 @@ struct UpsArgs {
     int centre_map;
     void* out;
     int out_f64;
+    int rows;               // output rows per block
     const int* poison;      // non-null and set: a persistent wait of this plan gave up, the flow is written as NaN
 };
 
@@ -307,4 +310,7 @@ const void* dis_kernel_level_rows(int ps, int lpp);
 // refinement core tile (width, height, threads per block) of a tile id;
 // returns 0 for an unknown id
 int dis_refine_tile(int tile, int* tw, int* th, int* nt);
-#define DIS_NUM_TILES 11
+// the lean tile id with the same core and threads as a tile id (itself when
+// it is lean), or -1
+int dis_refine_tile_lean(int tile);
+#define DIS_NUM_TILES 13

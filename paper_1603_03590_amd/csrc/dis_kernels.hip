@@ -828,10 +828,10 @@ using dis_tile::RefineSmem;
 // owns pairs of horizontally adjacent pixels (one of each colour) and keeps
 // their SOR coefficients in registers; LDS holds the increments, the edge
 // weights and U.  Every global read is issued in one round at the start.
-template <int TW, int TH, int NT, bool COLOUR = false>
-__device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, RefineSmem<TW, TH>& sm) {
-    using S = RefineSmem<TW, TH>;
-    using Shape = dis_tile::TileShape<TW, TH, NT>;
+template <int TW, int TH, int NT, bool COLOUR = false, bool LEAN = false>
+__device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, RefineSmem<TW, TH, DIS_KMAX, LEAN>& sm) {
+    using S = RefineSmem<TW, TH, DIS_KMAX, LEAN>;
+    using Shape = dis_tile::TileShape<TW, TH, NT, DIS_KMAX, LEAN>;
     constexpr int LP = S::LP;
     constexpr int PPT = Shape::PPT;
     constexpr bool kStage = Shape::kStage;
@@ -849,7 +849,7 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
     double s_iu[Shape::NS][2], s_iv[Shape::NS][2];
     // the sweeps below update only pixels closer to the core than the number
     // of half sweeps they run
-    dis_tile::refine_setup<TW, TH, NT, DIS_KMAX, COLOUR>(a, g, sm, C, s_iu, s_iv, 2 * ((kh + 1) / 2) - 1);
+    dis_tile::refine_setup<TW, TH, NT, DIS_KMAX, COLOUR, LEAN>(a, g, sm, C, s_iu, s_iv, 2 * ((kh + 1) / 2) - 1);
     __syncthreads();   // the image tile is dead from here on
     // 4. sweep start
     double* du_ = sm.u.inc.du;
@@ -883,30 +883,48 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
     // d from the core can still reach the core's final values only while
     // d < (half sweeps left), so the sweep skips it after that: the core's
     // bits do not change, the work falls to about 40%.
+    // Per owned pixel: its Chebyshev distance from the core, the LDS indices
+    // of its horizontal (pair partner's other side) and vertical neighbours,
+    // and whether its pair partner is to the right and inside the region.  A
+    // lean tile packs them into one word (neighbours in the region: bits 0..3
+    // as C.m, partner right: bit 4, partner inside: bit 5, distance: bits
+    // 8..) and forms the indices in each half sweep, for registers.
+    constexpr int NA = LEAN ? 1 : PPT, NP = LEAN ? PPT : 1;
     double ru[PPT][2], rv[PPT][2];
-    int cd[PPT][2], lh[PPT][2], lvd[PPT][2], lvu[PPT][2];
-    unsigned hs[PPT][2];   // 1: pair partner to the right, 2: partner in the region
+    int cd[NA][2], lh[NA][2], lvd[NA][2], lvu[NA][2];
+    unsigned hs[NA][2];   // 1: pair partner to the right, 2: partner in the region
+    int pk[NP][2];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const int l = C.l[k][c];
             ru[k][c] = rv[k][c] = 0.0;
-            cd[k][c] = 1 << 20;
-            lh[k][c] = lvd[k][c] = lvu[k][c] = 0;
-            hs[k][c] = 0;
+            if constexpr (LEAN) {
+                pk[k][c] = 0;
+            } else {
+                cd[k][c] = 1 << 20;
+                lh[k][c] = lvd[k][c] = lvu[k][c] = 0;
+                hs[k][c] = 0;
+            }
             if (l < 0) continue;
             ru[k][c] = du_[l];
             rv[k][c] = dv_[l];
             const int ly = l / LP, lx = l - ly * LP;
             const int x = rx0 + lx, y = ry0 + ly;
-            cd[k][c] = max(max(max(cx0 - x, x - (cx1 - 1)), max(cy0 - y, y - (cy1 - 1))), 0);
+            const int d = max(max(max(cx0 - x, x - (cx1 - 1)), max(cy0 - y, y - (cy1 - 1))), 0);
             const int m = C.m[k][c];
             const bool right = (lx & 1) == 0;   // pair m covers columns 2m (partner right) and 2m + 1
-            lh[k][c] = right ? ((m & 2) ? l - 1 : l) : ((m & 1) ? l + 1 : l);
-            lvd[k][c] = (m & 4) ? l + LP : l;
-            lvu[k][c] = (m & 8) ? l - LP : l;
-            hs[k][c] = (right ? 1u : 0u) | ((right ? (m & 1) : (m & 2)) ? 2u : 0u);
+            const bool pin = right ? (m & 1) : (m & 2);
+            if constexpr (LEAN) {
+                pk[k][c] = (m & 15) | (right ? 16 : 0) | (pin ? 32 : 0) | (d << 8);
+            } else {
+                cd[k][c] = d;
+                lh[k][c] = right ? ((m & 2) ? l - 1 : l) : ((m & 1) ? l + 1 : l);
+                lvd[k][c] = (m & 4) ? l + LP : l;
+                lvu[k][c] = (m & 8) ? l - LP : l;
+                hs[k][c] = (right ? 1u : 0u) | (pin ? 2u : 0u);
+            }
         }
     }
     const int khe = 2 * ((kh + 1) / 2);   // half sweeps this launch runs
@@ -919,21 +937,38 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const int l = C.l[k][c];
-                if (l < 0 || cd[k][c] > reach) continue;
-                const bool right = hs[k][c] & 1u, pin = hs[k][c] & 2u;
+                int dist, ih, ivd, ivu;
+                bool right, pin;
+                if constexpr (LEAN) {
+                    const int q = pk[k][c];
+                    dist = q >> 8;
+                    right = q & 16;
+                    pin = q & 32;
+                    ih = right ? ((q & 2) ? l - 1 : l) : ((q & 1) ? l + 1 : l);
+                    ivd = (q & 4) ? l + LP : l;
+                    ivu = (q & 8) ? l - LP : l;
+                } else {
+                    dist = cd[k][c];
+                    right = hs[k][c] & 1u;
+                    pin = hs[k][c] & 2u;
+                    ih = lh[k][c];
+                    ivd = lvd[k][c];
+                    ivu = lvu[k][c];
+                }
+                if (l < 0 || dist > reach) continue;
                 const double du = ru[k][c], dv = rv[k][c];
                 const double pu = pin ? ru[k][c ^ 1] : du;
-                const double hu = du_[lh[k][c]];
+                const double hu = du_[ih];
                 const double nu = ((C.wr[k][c] * (right ? pu : hu) + C.wl[k][c] * (right ? hu : pu)) +
-                                   C.wd[k][c] * du_[lvd[k][c]]) + C.wu[k][c] * du_[lvu[k][c]];
+                                   C.wd[k][c] * du_[ivd]) + C.wu[k][c] * du_[ivu];
                 const double dun = om1 * du + C.i1[k][c] * ((nu + C.c1[k][c]) - C.a12[k][c] * dv);
                 du_[l] = dun;
                 ru[k][c] = dun;
                 if (!stereo) {
                     const double pv = pin ? rv[k][c ^ 1] : dv;
-                    const double hv = dv_[lh[k][c]];
+                    const double hv = dv_[ih];
                     const double nv = ((C.wr[k][c] * (right ? pv : hv) + C.wl[k][c] * (right ? hv : pv)) +
-                                       C.wd[k][c] * dv_[lvd[k][c]]) + C.wu[k][c] * dv_[lvu[k][c]];
+                                       C.wd[k][c] * dv_[ivd]) + C.wu[k][c] * dv_[ivu];
                     const double dvn = om1 * dv + C.i2[k][c] * ((nv + C.c2[k][c]) - C.a12[k][c] * dun);
                     dv_[l] = dvn;
                     rv[k][c] = dvn;
@@ -968,8 +1003,16 @@ __device__ __forceinline__ void refine_tile(const RefineArgs& a, int tile, Refin
         dis_global(a.dUout)[gi] = du;
         dis_global(a.dUout)[n + gi] = dv;
         if (a.Uout) {
-            dis_global(a.Uout)[gi] = sm.uu[l] + du;
-            dis_global(a.Uout)[n + gi] = sm.uv[l] + dv;
+            double u0, v0;
+            if constexpr (LEAN) {
+                u0 = dis_global(a.U)[gi];
+                v0 = dis_global(a.U)[n + gi];
+            } else {
+                u0 = sm.uu[l];
+                v0 = sm.uv[l];
+            }
+            dis_global(a.Uout)[gi] = u0 + du;
+            dis_global(a.Uout)[n + gi] = v0 + dv;
         }
     }
     __syncthreads();   // LDS is reused by the caller's next tile
@@ -1029,9 +1072,11 @@ __global__ __launch_bounds__(256) void k_phase_densify(const LevelLaunch L) {
     densify_block<COLOUR>(da, local % bx, local / bx);
 }
 
-template <int TW, int TH, int NT, bool COLOUR = false>
-__global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
-    __shared__ RefineSmem<TW, TH> sm;
+// A lean tile asks for registers that let two blocks share a CU.
+template <int TW, int TH, int NT, bool COLOUR = false, bool LEAN = false>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(LEAN ? NT / 128 : 1)))
+void k_phase_refine(const PhaseLaunch PL) {
+    __shared__ RefineSmem<TW, TH, DIS_KMAX, LEAN> sm;
     const LevelLaunch& L = PL.L;
     RefineArgs ra;
     int q = dis_xcd_tile(blockIdx.x, gridDim.x), nt = gridDim.x;   // the pair's tiles, in launch order
@@ -1047,12 +1092,12 @@ __global__ __launch_bounds__(NT) void k_phase_refine(const PhaseLaunch PL) {
         nt = __builtin_amdgcn_readfirstlane(L.start[s0 + j + 1]) - t0;
         q = t - t0;
     }
-    refine_tile<TW, TH, NT, COLOUR>(ra, dis_band_tile(q, ra.tiles_x, nt), sm);
+    refine_tile<TW, TH, NT, COLOUR, LEAN>(ra, dis_band_tile(q, ra.tiles_x, nt), sm);
 }
 
 // ----------------------------------------------------------------- upscale
 
-// A block of the output, 256 columns by DIS_UPS_ROWS rows: each thread one
+// A block of the output, 256 columns by a.rows rows: each thread one
 // column (every store instruction writes 64 consecutive elements).  The value
 // is bilin() of each flow plane, f times.  A column's horizontal taps and
 // weight are the same in every row, and a row's vertical ones are the same
@@ -1075,7 +1120,7 @@ __device__ __forceinline__ void upsample_block(const UpsArgs& a, int bx, int by)
     const int c0 = clampi(xi, 0, Ws - 1), c1 = clampi(xi + 1, 0, Ws - 1);
     const size_t n = (size_t)a.W * a.H;
     const bool bad = a.poison && __builtin_amdgcn_readfirstlane(*dis_global(a.poison)) != 0;
-    const int y0 = by * DIS_UPS_ROWS, yn = min(DIS_UPS_ROWS, a.H - y0);
+    const int y0 = by * a.rows, yn = min(a.rows, a.H - y0);
     int p0 = -1, p1 = -1;
     double ut = 0.0, ub = 0.0, vt = 0.0, vb = 0.0;
     for (int i = 0; i < yn; ++i) {
@@ -1595,30 +1640,43 @@ const void* dis_kernel_level_rows(int ps, int lpp) {
     return nullptr;
 }
 
-// refinement tile shapes: core width, height, threads per block
+// refinement tile shapes: core width, height, threads per block, lean (no
+// LDS copy of U, two blocks per CU)
 #define DIS_FOR_REFINE_TILES(X) \
-    X(0, 32, 16, 256) X(1, 16, 16, 256) X(2, 64, 8, 256) X(3, 16, 16, 1024) X(4, 32, 16, 1024) \
-    X(5, 16, 16, 512) X(6, 32, 16, 512) X(7, 8, 8, 512) X(8, 16, 8, 512) X(9, 8, 8, 256) X(10, 8, 4, 384)
+    X(0, 32, 16, 256, false) X(1, 16, 16, 256, false) X(2, 64, 8, 256, false) X(3, 16, 16, 1024, false) \
+    X(4, 32, 16, 1024, false) X(5, 16, 16, 512, false) X(6, 32, 16, 512, false) X(7, 8, 8, 512, false) \
+    X(8, 16, 8, 512, false) X(9, 8, 8, 256, false) X(10, 8, 4, 384, false) X(11, 32, 16, 512, true) \
+    X(12, 16, 16, 512, true)
 
 int dis_refine_tile(int tile, int* tw, int* th, int* nt) {
-#define DIS_TILE_SHAPE(ID, TW_, TH_, NT_) \
+#define DIS_TILE_SHAPE(ID, TW_, TH_, NT_, LEAN_) \
     if (tile == ID) { *tw = TW_; *th = TH_; if (nt) *nt = NT_; return 1; }
     DIS_FOR_REFINE_TILES(DIS_TILE_SHAPE)
 #undef DIS_TILE_SHAPE
     return 0;
 }
 
+int dis_refine_tile_lean(int tile) {
+    int tw, th, nt;
+    if (!dis_refine_tile(tile, &tw, &th, &nt)) return -1;
+#define DIS_TILE_TWIN(ID, TW_, TH_, NT_, LEAN_) \
+    if (LEAN_ && TW_ == tw && TH_ == th && NT_ == nt) return ID;
+    DIS_FOR_REFINE_TILES(DIS_TILE_TWIN)
+#undef DIS_TILE_TWIN
+    return -1;
+}
+
 const void* dis_kernel_phase_refine(int tile) {
-#define DIS_TILE_KERNEL(ID, TW_, TH_, NT_) \
-    if (tile == ID) return (const void*)&k_phase_refine<TW_, TH_, NT_>;
+#define DIS_TILE_KERNEL(ID, TW_, TH_, NT_, LEAN_) \
+    if (tile == ID) return (const void*)&k_phase_refine<TW_, TH_, NT_, false, LEAN_>;
     DIS_FOR_REFINE_TILES(DIS_TILE_KERNEL)
 #undef DIS_TILE_KERNEL
     return nullptr;
 }
 
 const void* dis_kernel_phase_refine_colour(int tile) {
-#define DIS_TILE_KERNEL(ID, TW_, TH_, NT_) \
-    if (tile == ID) return (const void*)&k_phase_refine<TW_, TH_, NT_, true>;
+#define DIS_TILE_KERNEL(ID, TW_, TH_, NT_, LEAN_) \
+    if (tile == ID) return (const void*)&k_phase_refine<TW_, TH_, NT_, true, LEAN_>;
     DIS_FOR_REFINE_TILES(DIS_TILE_KERNEL)
 #undef DIS_TILE_KERNEL
     return nullptr;

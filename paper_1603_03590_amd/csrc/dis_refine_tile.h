@@ -7,13 +7,24 @@
 
 namespace dis_tile {
 
+// U on the region (uu, uv), kept in LDS unless the tile is lean.
+template <int N, bool KEEP>
+struct RegionU {
+    double uu[N], uv[N];
+};
+template <int N>
+struct RegionU<N, false> {};
+
 // LDS of one refinement tile: the core (TW x TH) grows by up to K = DIS_KMAX
 // pixels per side (the region); the image tile grows by 2 more for the
 // second differences.  The edge-weight planes first hold U + dUf (one more
 // row and column, for the forward differences of E_S); the increments share
-// storage with the image tile, which is dead by the time they are stored.
-template <int TW, int TH, int KG = DIS_KMAX>
-struct RefineSmem {
+// storage with the image tile, which is dead by the time they are stored.  A
+// lean tile keeps no copy of U on the region (its set-up and store read U
+// from memory, where the same values are), so that two 512-thread blocks of
+// the larger cores fit one CU.
+template <int TW, int TH, int KG = DIS_KMAX, bool LEAN = false>
+struct RefineSmem : RegionU<(TH + 2 * KG) * (TW + 2 * KG + 1), !LEAN> {
     static constexpr int K = KG;                     // largest growth of the core on each side
     static constexpr int RWM = TW + 2 * K, RHM = TH + 2 * K;
     static constexpr int LP = RWM + 1;               // region row pitch
@@ -21,7 +32,6 @@ struct RefineSmem {
     static constexpr int IP = IWM + 1;               // image-tile row pitch
     double wr[(RHM + 1) * LP];                      // U + dUf (u), then the weight of the edge to the right
     double wd[(RHM + 1) * LP];                      // U + dUf (v), then the weight of the edge below
-    double uu[RHM * LP], uv[RHM * LP];              // U on the region
     union {
         struct { double t0[IHM * IP], t1[IHM * IP]; } img;   // J0 / J1w
         struct { double du[RHM * LP], dv[RHM * LP]; } inc;
@@ -70,14 +80,18 @@ struct TileCoef {
     double a12[PPT][2], i1[PPT][2], i2[PPT][2], c1[PPT][2], c2[PPT][2];
 };
 
-template <int TW, int TH, int NT, int KG = DIS_KMAX>
+// A lean tile keeps its registers for two blocks per CU: the owned pixels'
+// increments and cached linearisation are read where they are used instead
+// of being staged in registers with the first loads.
+template <int TW, int TH, int NT, int KG = DIS_KMAX, bool LEAN = false>
 struct TileShape {
     using S = RefineSmem<TW, TH, KG>;
     static constexpr int PPT = ((S::RWM + 1) / 2 * S::RHM + NT - 1) / NT;
-    static constexpr bool kStage = PPT <= 2 && NT <= 512;   // register budget of 1024-thread blocks
+    static constexpr bool kStage = PPT <= 2 && NT <= 512 && !LEAN;   // register budget of 1024-thread blocks
     static constexpr int NS = kStage ? PPT : 1;
     static constexpr bool kLin = PPT <= 2 && NT <= 512;     // linearisation may come from the level's cache
-    static constexpr int NL = kLin ? PPT : 1;
+    static constexpr bool kLinPf = kLin && !LEAN;           // ... staged in registers with the first loads
+    static constexpr int NL = kLinPf ? PPT : 1;
 };
 
 // Steps 1-3 of a tile: one round of global loads (U + dUf on the region plus
@@ -89,16 +103,17 @@ struct TileShape {
 // the caller never updates them (their starting increments and weights are
 // still set).  Ends with the image tile still live; the caller places a
 // barrier before reusing it.
-template <int TW, int TH, int NT, int KG = DIS_KMAX, bool COLOUR = false>
-__device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom& g, RefineSmem<TW, TH, KG>& sm,
-                                             TileCoef<TileShape<TW, TH, NT, KG>::PPT>& C,
-                                             double (&s_iu)[TileShape<TW, TH, NT, KG>::NS][2],
-                                             double (&s_iv)[TileShape<TW, TH, NT, KG>::NS][2],
+template <int TW, int TH, int NT, int KG = DIS_KMAX, bool COLOUR = false, bool LEAN = false>
+__device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom& g, RefineSmem<TW, TH, KG, LEAN>& sm,
+                                             TileCoef<TileShape<TW, TH, NT, KG, LEAN>::PPT>& C,
+                                             double (&s_iu)[TileShape<TW, TH, NT, KG, LEAN>::NS][2],
+                                             double (&s_iv)[TileShape<TW, TH, NT, KG, LEAN>::NS][2],
                                              int reach = 1 << 20) {
-    using S = RefineSmem<TW, TH, KG>;
+    using S = RefineSmem<TW, TH, KG, LEAN>;
     constexpr int LP = S::LP, IP = S::IP;
-    constexpr int PPT = TileShape<TW, TH, NT, KG>::PPT;
-    constexpr bool kStage = TileShape<TW, TH, NT, KG>::kStage;
+    using Shape = TileShape<TW, TH, NT, KG, LEAN>;
+    constexpr int PPT = Shape::PPT;
+    constexpr bool kStage = Shape::kStage;
     const int W = g.W, H = g.H;
     const size_t n = (size_t)W * H;
     const int rx0 = g.rx0, ry0 = g.ry0, RW = g.RW, RH = g.RH, npw = g.npw;
@@ -107,8 +122,9 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
     const auto* __restrict__ F = dis_global(a.dUf);
     const auto* __restrict__ Din = dis_global(a.dUin);
 
-    constexpr bool kLin = TileShape<TW, TH, NT, KG>::kLin;
-    constexpr int NL = TileShape<TW, TH, NT, KG>::NL;
+    constexpr bool kLin = Shape::kLin;
+    constexpr bool kLinPf = Shape::kLinPf;
+    constexpr int NL = Shape::NL;
     const bool lin_load = kLin && a.lin_mode == 2;
     constexpr bool colour = COLOUR;   // lin_mode 3: per-channel linearisation
     double s_fu[kStage ? PPT : 1][2], s_fv[kStage ? PPT : 1][2];
@@ -136,7 +152,7 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
                 if (F) { s_fu[k][c] = F[gi]; s_fv[k][c] = F[n + gi]; }
             }
             if (far[k][c]) continue;
-            if constexpr (kLin) {
+            if constexpr (kLinPf) {
                 if (lin_load) {
 #pragma unroll
                     for (int q = 0; q < 11; ++q) s_lin[k][c][q] = dis_global(a.lin)[q * n + gi];
@@ -156,9 +172,11 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
             const double u0 = U[gi], v0 = U[n + gi];
             sm.wr[ly * LP + lx] = F ? u0 + F[gi] : u0;
             sm.wd[ly * LP + lx] = F ? v0 + F[n + gi] : v0;
-            if (lx < RW && ly < RH) {
-                sm.uu[ly * LP + lx] = u0;
-                sm.uv[ly * LP + lx] = v0;
+            if constexpr (!LEAN) {
+                if (lx < RW && ly < RH) {
+                    sm.uu[ly * LP + lx] = u0;
+                    sm.uv[ly * LP + lx] = v0;
+                }
             }
         }
         const int ix1 = min(rx0 + RW + 2, W), iy1 = min(ry0 + RH + 2, H);
@@ -272,10 +290,16 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
                 bool cached = false;
                 if constexpr (kLin) {
                     if (lin_load) {
-                        Ix = s_lin[k][c][0]; Iy = s_lin[k][c][1]; Iz = s_lin[k][c][2];
-                        Ixx = s_lin[k][c][3]; Ixy = s_lin[k][c][4]; Iyy = s_lin[k][c][5];
-                        Ixz = s_lin[k][c][6]; Iyz = s_lin[k][c][7];
-                        b0 = s_lin[k][c][8]; bx = s_lin[k][c][9]; by = s_lin[k][c][10];
+                        double q[11];
+#pragma unroll
+                        for (int i = 0; i < 11; ++i) {
+                            if constexpr (kLinPf) q[i] = s_lin[k][c][i];
+                            else q[i] = dis_global(a.lin)[i * n + gi];
+                        }
+                        Ix = q[0]; Iy = q[1]; Iz = q[2];
+                        Ixx = q[3]; Ixy = q[4]; Iyy = q[5];
+                        Ixz = q[6]; Iyz = q[7];
+                        b0 = q[8]; bx = q[9]; by = q[10];
                         cached = true;
                     }
                 }
@@ -323,11 +347,21 @@ __device__ __forceinline__ void refine_setup(const RefineArgs& a, const TileGeom
                 const double wr = hr ? sm.wr[l] : 0.0, wl = hl ? sm.wr[l - 1] : 0.0;
                 const double wd = hd ? sm.wd[l] : 0.0, wu = hu ? sm.wd[l - LP] : 0.0;
                 const double Ssum = ((wr + wl) + wd) + wu;
-                const double Up = sm.uu[l], Vp = sm.uv[l];
-                const double Ur = hr ? sm.uu[l + 1] : 0.0, Ul = hl ? sm.uu[l - 1] : 0.0;
-                const double Ud = hd ? sm.uu[l + LP] : 0.0, Uu = hu ? sm.uu[l - LP] : 0.0;
-                const double Vr = hr ? sm.uv[l + 1] : 0.0, Vl = hl ? sm.uv[l - 1] : 0.0;
-                const double Vd = hd ? sm.uv[l + LP] : 0.0, Vu = hu ? sm.uv[l - LP] : 0.0;
+                double Up, Vp, Ur, Ul, Ud, Uu, Vr, Vl, Vd, Vu;
+                if constexpr (LEAN) {
+                    // the same values, from memory (gi: the pixel; its neighbours one column / row away)
+                    Up = U[gi]; Vp = U[n + gi];
+                    Ur = hr ? U[gi + 1] : 0.0; Ul = hl ? U[gi - 1] : 0.0;
+                    Ud = hd ? U[gi + W] : 0.0; Uu = hu ? U[gi - W] : 0.0;
+                    Vr = hr ? U[n + gi + 1] : 0.0; Vl = hl ? U[n + gi - 1] : 0.0;
+                    Vd = hd ? U[n + gi + W] : 0.0; Vu = hu ? U[n + gi - W] : 0.0;
+                } else {
+                    Up = sm.uu[l]; Vp = sm.uv[l];
+                    Ur = hr ? sm.uu[l + 1] : 0.0; Ul = hl ? sm.uu[l - 1] : 0.0;
+                    Ud = hd ? sm.uu[l + LP] : 0.0; Uu = hu ? sm.uu[l - LP] : 0.0;
+                    Vr = hr ? sm.uv[l + 1] : 0.0; Vl = hl ? sm.uv[l - 1] : 0.0;
+                    Vd = hd ? sm.uv[l + LP] : 0.0; Vu = hu ? sm.uv[l - LP] : 0.0;
+                }
                 const double NU = ((wr * Ur + wl * Ul) + wd * Ud) + wu * Uu;
                 const double NV = ((wr * Vr + wl * Vl) + wd * Vd) + wu * Vu;
                 C.m[k][c] = (hr ? 1 : 0) | (hl ? 2 : 0) | (hd ? 4 : 0) | (hu ? 8 : 0);

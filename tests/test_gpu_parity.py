@@ -13,7 +13,7 @@ from paper_1603_03590_amd import DIS, DisError, params, _lib
 
 pytestmark = pytest.mark.gpu
 
-N_TILES = 11   # refinement tile ids the library knows
+N_TILES = 13   # refinement tile ids the library knows
 
 
 def say(*a):
@@ -170,6 +170,29 @@ def test_size_errors():
         d.close()
 
 
+def test_lean_tiles_on_large_scales_are_bitwise_invariant():
+    """A scale large enough for the lean twins of launch-mode bit 6 (the
+    1024x436 pair refined at full resolution: 896 tiles of 32x16): the lean
+    tiles, alone or only where a scale fills every CU twice, give the bits of
+    the tiles that keep U in LDS."""
+    say("[tunables] lean tiles, 1024x436 refined at scale 0")
+    pr, p = pair("layered", 1024, 436, 100.0, 2), params(103, finest_scale=0)
+    d = DIS(p, 1024, 436)
+    try:
+        t0 = torch.from_numpy(pr.I0).cuda()
+        t1 = torch.from_numpy(pr.I1).cuda()
+        outs = []
+        for tile, mode in ((6, 1), (6, 65), (11, 1), (5, 1), (5, 65), (12, 9), (6, 73)):
+            d.set_tunables(None, tile, mode)
+            o = d.flow(t0, t1)
+            torch.cuda.synchronize()
+            outs.append(o.cpu().numpy())
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0])
+    finally:
+        d.close()
+
+
 @pytest.mark.parametrize("case", ["c2b", "c1", "inner7", "l1", "stereo", "fb", "colour"])
 def test_launch_choices_are_bitwise_invariant(case):
     """Persistent vs per-phase launches, lanes per patch and refinement tiles
@@ -204,6 +227,8 @@ def test_launch_choices_are_bitwise_invariant(case):
         choices += [(None, 0, 3), (None, 3, 3), (None, 0, 2), (None, 7, 19), (None, 0, 18)]
         # without the linearisation cache (launch mode bit 3)
         choices += [(None, 7, 9), (None, 0, 8), (None, 2, 11)]
+        # lean twins of the 32x16 and 16x16 tiles on the larger scales (launch mode bit 6)
+        choices += [(None, 6, 65), (None, 5, 73)]
         for lpp, tile, mode in choices:
             d.set_tunables(lpp, tile, mode)
             o = d.flow(t0, t1)
