@@ -367,8 +367,10 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
     if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, 3});    // single-workgroup scales of <= 256 pairs
     if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, 19});   // ... of <= 1024 pairs
     if (r == DIS_OK) r = measure(Cand{bestc.lpp, bestc.tile, bestc.mode | 8});   // no linearisation cache
-    if (r == DIS_OK && dis_refine_tile_lean(bestc.tile) >= 0 && !(bestc.mode & 64))
-        r = measure(Cand{bestc.lpp, bestc.tile, bestc.mode | 64});   // lean twin on the large scales
+    // the lean twin on the large scales (a tile that is lean itself has no other)
+    const int twin = dis_refine_tile_lean(bestc.tile);
+    if (r == DIS_OK && twin >= 0 && twin != bestc.tile && !(bestc.mode & 64))
+        r = measure(Cand{bestc.lpp, bestc.tile, bestc.mode | 64});
     if (r == DIS_OK) r = measure(Cand{0, 0, 0});
     for (int l : lpps)
         if (r == DIS_OK && dis_search_has_lanes(&h->p, l) &&
