@@ -158,9 +158,11 @@ int dis_compute_flow(dis_handle* h, const void* I0, const void* I1, int w, int h
  * Flow for n independent pairs of possibly different sizes, one pair per
  * slot (n <= max_batch).  The arrays I0[], I1[], flow[] (device pointers)
  * and w[], hgt[], pitch[] are HOST arrays of length n.  All pairs of one
- * pyramid level are processed by a single persistent kernel launch that
- * takes work from a queue; the whole batch is replayed as one HIP graph per
- * batch composition.  Each pair's result is bitwise equal to
+ * pyramid level are processed together: by a single persistent kernel
+ * launch that takes work from a queue (launch mode bit 0 clear), or by one
+ * launch per phase of the level covering every pair (bit 0 set, see
+ * dis_set_tunables); the whole batch is replayed as one HIP graph per batch
+ * composition.  Each pair's result is bitwise equal to
  * dis_compute_flow on that pair.  Errors as for dis_compute_flow, plus
  * DIS_ESIZE for n > max_batch.  In the persistent launch a task that waits
  * on its predecessors gives up after a bounded wait (about a second, which
@@ -176,10 +178,12 @@ int dis_compute_flow_batched(dis_handle* h, int n, const void* const* I0,
  * grad_flow = dL/dflow ([2][h][w], device) for the most recent
  * dis_compute_flow on this handle (which must have run with
  * DIS_FLAG_KEEP_FOR_BACKWARD).  Writes dL/dI0 and dL/dI1 ([h][w], dense,
- * pitch = w) into caller buffers.  Each scale is recomputed from the kept
- * coarser flow before its adjoint runs, so scratch stays bounded by one
- * scale.  Errors: DIS_EINVAL (NULL pointer), DIS_ESTATE (no kept forward),
- * DIS_EHIP.
+ * pitch = w) into caller buffers.  Each scale coarser than the finest is
+ * recomputed from its kept patch records before its adjoint runs; the
+ * finest scale's SOR states, weight sums, warped frame and linearisation are
+ * the ones the forward wrote into the same one-scale buffers as it ran.
+ * Scratch stays bounded by one scale.  Errors: DIS_EINVAL (NULL pointer),
+ * DIS_ESTATE (no kept forward), DIS_EHIP.
  */
 int dis_flow_backward(dis_handle* h, const void* grad_flow, void* grad_I0, void* grad_I1);
 
