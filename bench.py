@@ -121,7 +121,7 @@ def main():
         args.headline_only = True
     part = lambda name: args.only in ("all", name)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        log("bench.py measures one GPU: this build has no multi-GPU path (pairs would shard across GPUs "
+        log("bench.py measures one GPU: the library has no multi-GPU path (pairs would shard across GPUs "
             "with no exchange); run it with --gpus 1")
         sys.exit(2)
 
