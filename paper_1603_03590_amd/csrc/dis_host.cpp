@@ -557,17 +557,17 @@ void dis_refine_phases(const dis_params& p, int s, std::vector<RefPhase>& out) {
     }
 }
 
-// Search, densification and refinement of every pair at every level.
-// The per-level work is laid out as queue segments (phase-major, then pair)
-// in device tables; launch mode 0 runs each level as one persistent k_level
-// launch over that queue, mode 1 as one launch per phase covering every
-// pair.  Both give the same bits.
 bool dis_forward_keeps_finest(const dis_handle* h) {
     const dis_params& p = h->p;
     return (p.flags & DIS_FLAG_KEEP_FOR_BACKWARD) && p.refine && !(p.flags & DIS_FLAG_FB_CONSISTENCY) &&
            dis_channels(&p) == 1 && h->bwd.tape != nullptr && h->bwd.Z != nullptr;
 }
 
+// Search, densification and refinement of every pair at every level.
+// The per-level work is laid out as queue segments (phase-major, then pair)
+// in device tables; launch mode 0 runs each level as one persistent k_level
+// launch over that queue, mode 1 as one launch per phase covering every
+// pair.  Both give the same bits.
 int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq, PlanTables& tabs,
                      const LevelOpts* opt) {
     const dis_params& p = h->p;
@@ -814,7 +814,8 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
         LL.nph = LH.nph;
         LL.ntasks = t;
         LL.nruns = nruns_of[li];
-        // the adjoint's reverse tiles read the cache the recomputation fills
+        // the adjoint's reverse tiles read the cache that the recomputation,
+        // or a forward recording the finest scale, fills
         LL.lin_cache = (opt || !h->no_lin_cache || (keep_tape && LH.s == sf)) ? 1 : 0;
         if (np == 1) {
             LL.one = 1;
