@@ -210,7 +210,9 @@ int dis_autotune(dis_handle* h, const char* cache_path);
  * 3: 16x16/1024, 4: 32x16/1024, 5: 16x16/512, 6: 32x16/512, 7: 8x8/512,
  * 8: 16x8/512, 9: 8x8/256, 10: 8x4/384, and with no LDS copy of U (two blocks
  * per compute unit) 11: 32x16/512, 12: 16x16/512.  launch_mode bit 0: 0 runs each scale as one
- * persistent launch over a task queue, 1 as one launch per phase; bit 1 set
+ * persistent launch over a task queue (refining with tile 0, or with tile 1
+ * when that is the chosen tile and the search is the grey L2 one), 1 as one
+ * launch per phase; bit 1 set
  * turns on the single-workgroup path: a scale of at most 256 horizontal
  * pixel pairs (1024 with bit 4 also set) is densified and refined, every
  * fixed-point step, by one block instead of tiles; bit 2 set makes dis_flow_backward reverse the SOR

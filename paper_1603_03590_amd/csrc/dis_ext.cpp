@@ -371,11 +371,16 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
     const int twin = dis_refine_tile_lean(bestc.tile);
     if (r == DIS_OK && twin >= 0 && twin != bestc.tile && !(bestc.mode & 64))
         r = measure(Cand{bestc.lpp, bestc.tile, bestc.mode | 64});
-    if (r == DIS_OK) r = measure(Cand{0, 0, 0});
-    for (int l : lpps)
-        if (r == DIS_OK && dis_search_has_lanes(&h->p, l) &&
-            (dis_search_rows_path(&h->p) ? dis_kernel_level_rows(h->p.patch_size, l) : dis_kernel_level(h->p.patch_size, l)))
-            r = measure(Cand{l, 0, 0});
+    // the persistent launch, with each lane count, on its 32x16 tile and (row-owned search) its 16x16 one
+    const bool rows = dis_search_rows_path(&h->p) && dis_channels(&h->p) == 1;
+    for (int tile : {0, 1}) {
+        if (tile == 1 && !rows) break;
+        if (r == DIS_OK) r = measure(Cand{0, tile, 0});
+        for (int l : lpps)
+            if (r == DIS_OK && dis_search_has_lanes(&h->p, l) &&
+                (rows ? dis_kernel_level_rows(h->p.patch_size, l, tile) : dis_kernel_level(h->p.patch_size, l)))
+                r = measure(Cand{l, tile, 0});
+    }
     free_tmp();
     hipEventDestroy(e0);
     hipEventDestroy(e1);

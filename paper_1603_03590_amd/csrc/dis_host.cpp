@@ -584,7 +584,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
     const bool no_tables = h->arena != nullptr;
     if (no_tables && (pairs.size() != 1 || opt))
         return fail(h, DIS_EINVAL, "internal: a static-scratch plan holds one pair and no recomputation");
-    const int tile_id = mode ? h->refine_tile : DIS_LEVEL_TILE;
+    const int tile_id = mode ? h->refine_tile : dis_level_tile(h->refine_tile, nc == 1 && dis_search_rows_path(&p));
     int tw = 32, th = 16, nt = 256;
     dis_refine_tile(tile_id, &tw, &th, &nt);
 
@@ -824,7 +824,7 @@ int dis_build_levels(dis_handle* h, const std::vector<PairRef>& pairs, Seq& seq,
             LL.dens_bx1 = LH.lp[0].dens_bx;
         }
         if (mode == 0) {
-            const void* fn = rows ? dis_kernel_level_rows(ps, LH.lpp) : dis_kernel_level(ps, LH.lpp);
+            const void* fn = rows ? dis_kernel_level_rows(ps, LH.lpp, tile_id) : dis_kernel_level(ps, LH.lpp);
             if (!fn) return fail(h, DIS_EINVAL, "no level kernel for patch %d, %d lanes", ps, LH.lpp);
             double by = 0.0, fl = 0.0;
             for (int ph = 0; ph < LH.nph; ++ph) { by += ph_by[ph]; fl += ph_fl[ph]; }

@@ -7,7 +7,11 @@
 
 #define DIS_MAXL 16   // pyramid levels a handle can hold
 #define DIS_KMAX 10   // red-black half sweeps one refinement launch can fuse
-#define DIS_LEVEL_TILE 0   // refinement tile id used inside the persistent level kernel
+#define DIS_LEVEL_TILE 0   // refinement tile id used inside the persistent level kernel by default
+// the refinement tile the persistent level kernel uses when `tile` is asked
+// for: tile 1 (16x16 on 256 threads) with the row-owned search, else tile 0
+// (32x16 on 256 threads)
+inline int dis_level_tile(int tile, bool rows) { return (rows && tile == 1) ? 1 : DIS_LEVEL_TILE; }
 
 // Pyramid: from level `a` (the caller's frames when a == 0) compute the
 // 2x2-box levels a+1 .. a+nlev (nlev <= 5) in one pass over 32x32 tiles.
@@ -306,7 +310,7 @@ const void* dis_kernel_level(int ps, int lpp);          // persistent level kern
 // the row-owned search of grey frames with the L2 norm (64-thread blocks)
 // and its persistent level kernel; null when no layout has lpp lanes
 const void* dis_kernel_phase_search_rows(int ps, int lpp);
-const void* dis_kernel_level_rows(int ps, int lpp);
+const void* dis_kernel_level_rows(int ps, int lpp, int tile);   // tile 0 or 1 (dis_level_tile)
 // refinement core tile (width, height, threads per block) of a tile id;
 // returns 0 for an unknown id
 int dis_refine_tile(int tile, int* tw, int* th, int* nt);

@@ -1500,15 +1500,16 @@ __device__ __attribute__((noinline)) void lane0_signal(int* ctr, int n) {
 // pair j has finished (all those tasks were taken earlier, by running blocks).
 // RNRB > 0: the search is the row-owned one (layout RNRB x RNH, window
 // radius RR), whose windows share LDS with the refinement tile.
-template <int PS, int LPP, int RNRB = 0, int RNH = 0, int RR = 0>
+// TW x TH: the refinement core of the level's tiles (on 256 threads, as
+// every task of the launch)
+template <int PS, int LPP, int RNRB = 0, int RNH = 0, int RR = 0, int TW = 32, int TH = 16>
 __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
-    static_assert(DIS_LEVEL_TILE == 0, "the level kernel refines 32x16 tiles");
     constexpr int WIN = RNRB > 0 ? (256 / LPP) * RowWin<PS, RR>::SIZE : 1;
     __shared__ union LevelSmem {
-        RefineSmem<32, 16> r;
+        RefineSmem<TW, TH> r;
         double win[WIN];
     } smu;
-    RefineSmem<32, 16>& sm = smu.r;
+    RefineSmem<TW, TH>& sm = smu.r;
     __shared__ int s_task, s_ok;
     int* head = L.sync;
     int* err = L.sync + 1;
@@ -1542,7 +1543,7 @@ __global__ __launch_bounds__(256) void k_level(const LevelLaunch L) {
             } else {
                 RefineArgs ra = dis_phase_args(P, L.rph[phase - 2], L.lin_cache, false);
                 ra.nhalf = __builtin_amdgcn_readfirstlane(ra.nhalf);
-                refine_tile<32, 16, 256>(ra, local, sm);
+                refine_tile<TW, TH, 256>(ra, local, sm);
             }
             __syncthreads();   // LDS (windows, tile) is reused by the run's next task
         }
@@ -1631,10 +1632,12 @@ constexpr int dis_level_win_r(int ps, int lpp, int r) {
                                                                                        : r;
 }
 
-const void* dis_kernel_level_rows(int ps, int lpp) {
-#define DIS_ROWS_LEVEL_CASE(PS_, NRB_, NH_, R_) \
-    if (ps == PS_ && lpp == NRB_ * NH_)                                                       \
-        return (const void*)&k_level<PS_, NRB_ * NH_, NRB_, NH_, dis_level_win_r(PS_, NRB_ * NH_, R_)>;
+const void* dis_kernel_level_rows(int ps, int lpp, int tile) {
+#define DIS_ROWS_LEVEL_CASE(PS_, NRB_, NH_, R_)                                                                    \
+    if (ps == PS_ && lpp == NRB_ * NH_)                                                                            \
+        return tile == 1 ? (const void*)&k_level<PS_, NRB_ * NH_, NRB_, NH_, dis_level_win_r(PS_, NRB_ * NH_, R_), \
+                                                 16, 16>                                                           \
+                         : (const void*)&k_level<PS_, NRB_ * NH_, NRB_, NH_, dis_level_win_r(PS_, NRB_ * NH_, R_)>;
     DIS_FOR_ROW_INSTANCES(DIS_ROWS_LEVEL_CASE)
 #undef DIS_ROWS_LEVEL_CASE
     return nullptr;

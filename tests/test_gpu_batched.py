@@ -37,15 +37,15 @@ def plain(prs, p):
     return outs
 
 
-@pytest.mark.parametrize("mode", [1, 0])
-def test_batched_equals_plain_bitwise(mode):
-    say(f"[batched] {len(SIZES)} uneven pairs, launch mode {mode}")
+@pytest.mark.parametrize("mode,tile", [(1, 0), (0, 0), (0, 1)])
+def test_batched_equals_plain_bitwise(mode, tile):
+    say(f"[batched] {len(SIZES)} uneven pairs, launch mode {mode}, tile {tile}")
     prs = batch_pairs()
     p = params(106)
     ref = plain(prs, p)
     d = DIS(p, 1024, 480, max_batch=len(prs))
     try:
-        d.set_tunables(None, 0, mode)
+        d.set_tunables(None, tile, mode)
         I0 = [torch.from_numpy(pr.I0).cuda() for pr in prs]
         I1 = [torch.from_numpy(pr.I1).cuda() for pr in prs]
         outs = d.flow_batched(I0, I1)

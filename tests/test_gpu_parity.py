@@ -219,6 +219,8 @@ def test_launch_choices_are_bitwise_invariant(case):
         t1 = torch.from_numpy(pr.I1).cuda()
         outs = []
         choices = [(None, 0, 0), ([4] * 16, 0, 0), ([8] * 16, 0, 0), (None, 0, 1)]
+        # the persistent launch on its 16x16 tile
+        choices += [(None, 1, 0), ([16] * 16, 1, 0)]
         # 32 and 64 lanes per patch (the reduction tree crosses rows of the wave)
         choices += [([32] * 16, 0, 1), ([64] * 16, 7, 1), ([64] * 16, 0, 0)]
         # every refinement tile shape / block size, with varied lanes per patch

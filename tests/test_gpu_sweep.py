@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 # (lanes per patch or None = automatic, refinement tile, launch mode)
 CHOICES = [(None, t, 1) for t in range(13)] + [
     (None, 7, 3), (None, 10, 3), (None, 10, 19), (None, 7, 0), ([16] * 16, 10, 3), ([32] * 16, 7, 3),
-    (None, 10, 11), (None, 6, 65), (None, 5, 67)]
+    (None, 10, 11), (None, 6, 65), (None, 5, 67), (None, 1, 0), ([8] * 16, 1, 0)]
 
 
 def cases(n=16, seed=7):
