@@ -341,10 +341,12 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
     }
     double best = 1e30;
     Cand bestc{0, 0, 1};
+    int best_lv[DIS_MAXL] = {0};   // lanes per patch of each scale in the best choice
     int r = DIS_OK;
-    auto measure = [&](const Cand& c) -> int {
+    // times one choice; `lv` (per scale) overrides c.lpp
+    auto measure = [&](const Cand& c, const int* lv_in = nullptr) -> int {
         int lv[DIS_MAXL];
-        for (int s = 0; s < DIS_MAXL; ++s) lv[s] = c.lpp;
+        for (int s = 0; s < DIS_MAXL; ++s) lv[s] = lv_in ? lv_in[s] : c.lpp;
         int rr = dis_set_tunables(h, lv, c.tile, c.mode);
         if (rr != DIS_OK) return rr;
         for (int i = 0; i < 3 && rr == DIS_OK; ++i) { restore_tmp(); rr = replay(); }
@@ -357,7 +359,11 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
         hipEventSynchronize(e1);
         float ms = 0.f;
         hipEventElapsedTime(&ms, e0, e1);
-        if (ms / reps < best) { best = ms / reps; bestc = c; }
+        if (ms / reps < best) {
+            best = ms / reps;
+            bestc = c;
+            for (int s = 0; s < DIS_MAXL; ++s) best_lv[s] = lv[s];
+        }
         return DIS_OK;
     };
     for (int t = 0; t < DIS_NUM_TILES && r == DIS_OK; ++t) r = measure(Cand{0, t, 1});
@@ -381,15 +387,40 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
                 (rows ? dis_kernel_level_rows(h->p.patch_size, l, tile) : dis_kernel_level(h->p.patch_size, l)))
                 r = measure(Cand{l, tile, 0});
     }
+    // then the lanes per patch of each processed scale on its own (the scales'
+    // searches differ in patch count), coarsest first, the others held
+    {
+        int top = dis_coarsest(&h->p, lw, lh);
+        if (call != 1) {
+            top = h->p.finest_scale;
+            for (size_t k = 0; k < bw.size(); ++k) top = std::max(top, dis_coarsest(&h->p, bw[k], bh[k]));
+        }
+        const Cand c = bestc;
+        for (int s = top; s >= h->p.finest_scale && r == DIS_OK; --s) {
+            int cur[DIS_MAXL];
+            std::memcpy(cur, best_lv, sizeof cur);
+            for (int l : lpps) {
+                if (r != DIS_OK || l == cur[s] || !dis_search_has_lanes(&h->p, l)) continue;
+                if (!(c.mode & 1)) {   // the persistent launch has its own kernels per lane count
+                    const bool ok = dis_search_rows_path(&h->p) && dis_channels(&h->p) == 1
+                                        ? dis_kernel_level_rows(h->p.patch_size, l, dis_level_tile(c.tile, true)) != nullptr
+                                        : dis_kernel_level(h->p.patch_size, l) != nullptr;
+                    if (!ok) continue;
+                }
+                int t[DIS_MAXL];
+                std::memcpy(t, cur, sizeof t);
+                t[s] = l;
+                r = measure(c, t);
+            }
+        }
+    }
     free_tmp();
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     h->p.flags = (uint32_t)save_flags;
     restore();
     if (r != DIS_OK) return r;
-    int lv[DIS_MAXL];
-    for (int s = 0; s < DIS_MAXL; ++s) lv[s] = bestc.lpp;
-    r = dis_set_tunables(h, lv, bestc.tile, bestc.mode);
+    r = dis_set_tunables(h, best_lv, bestc.tile, bestc.mode);
     if (r != DIS_OK) return r;
     h->tuned_ms = best;
     if (cache_path) {
@@ -397,10 +428,11 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
         if (!f) return dis_fail(h, DIS_EINVAL, "cannot open %s", cache_path);
         std::fprintf(f,
                      "{\"arch\": \"gfx950\", \"call\": \"%s\", \"w\": %d, \"h\": %d, \"pairs\": %d, \"patch\": %d, "
-                     "\"overlap\": %g, \"iters\": %d, \"lanes_per_patch\": %d, \"refine_tile\": %d, "
-                     "\"launch_mode\": %d, \"ms\": %.5f}\n",
+                     "\"overlap\": %g, \"iters\": %d, \"lanes_per_patch\": [",
                      call == 1 ? "plain" : "batched", lw, lh, call == 1 ? 1 : (int)b0.size(), h->p.patch_size,
-                     h->p.overlap, h->p.gn_iters, bestc.lpp, bestc.tile, bestc.mode, best);
+                     h->p.overlap, h->p.gn_iters);
+        for (int s = 0; s < DIS_MAXL; ++s) std::fprintf(f, "%s%d", s ? ", " : "", best_lv[s]);
+        std::fprintf(f, "], \"refine_tile\": %d, \"launch_mode\": %d, \"ms\": %.5f}\n", bestc.tile, bestc.mode, best);
         std::fclose(f);
     }
     return DIS_OK;
