@@ -117,7 +117,7 @@ struct SearchBwdArgs {
     double* gJ0;
     double* gJ1;
     double* gUn;            // adjoint of the coarser flow (null on the coarsest level)
-    int span;               // LDS window of each patch: (PS + 1 + span)^2 cells; patches whose warps spread wider use global atomics
+    int win;                // cells per side of each patch's LDS window(s), at least PS + 3; taps outside it go through memory
 };
 
 const void* dis_kernel_bzero();
@@ -141,3 +141,5 @@ const void* dis_kernel_bwd_densify();         // pass 1, per pixel
 const void* dis_kernel_bwd_densify_patch();   // pass 2, 16 lanes per patch
 const void* dis_kernel_bwd_pyramid();
 const void* dis_kernel_bwd_search(int ps);
+// LDS windows per patch of that kernel: 2 (adjoint and J1 values) or 1
+int dis_bwd_search_windows(int ps);

@@ -872,24 +872,32 @@ __global__ __launch_bounds__(256) void k_bwd_pyramid(const PyrBwdArgs a) {
 // u <- u - M b(u) (M = (H + lambda I)^-1) are reversed; gradients reach the
 // taps of J1, the template and its Sobel gradients in J0, and, through the
 // initialisation 2 U_{s+1}(c/2), the coarser flow.
-template <int PS, int LPP>
+//
+// Each patch owns a WIN x WIN LDS window of J1 positions (before the border
+// clamp): it collects the patch's J1 adjoint and, with VW, also holds the J1
+// values the warps read, so that both passes over the iterates sample LDS
+// instead of gathering from memory.  With VW the window is placed before the
+// recomputation, around the initial and the final displacement (the
+// iterates usually move between the two); without it, around the recomputed
+// iterates.  A tap outside the window reads and scatters through global
+// memory, with the same arithmetic.
+template <int PS, int LPP, bool VW>
 __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
     constexpr int NP = PS * PS;
     constexpr int PPL = (NP + LPP - 1) / LPP;
     constexpr int GROUPS = 256 / LPP;
-    // dynamic LDS: [GROUPS][iters + 1][2] iterates, then [GROUPS][WIN][WIN]
-    // windows collecting each patch's J1 adjoint (WIN = PS + 3 + span: the
-    // taps of every warp plus a pixel on each side, for a position whose
-    // fraction rounds up to the next integer)
+    // dynamic LDS: [GROUPS][iters + 1][2] iterates, then per group the
+    // adjoint window and (VW) the value window, WIN * WIN cells each
     extern __shared__ double s_dyn[];
     const SearchArgs& a = A.sa;
     const int W = a.W, H = a.H;
     const int lane = threadIdx.x & (LPP - 1);
     const int grp = threadIdx.x / LPP;
     const int N = a.nx * a.ny;
-    const int WIN = PS + 3 + A.span;
+    const int WIN = A.win;
     double* s_u = s_dyn;
-    double* win = s_dyn + (size_t)GROUPS * (a.iters + 1) * 2 + (size_t)grp * WIN * WIN;
+    double* win = s_dyn + (size_t)GROUPS * (a.iters + 1) * 2 + (size_t)grp * (VW ? 2 : 1) * WIN * WIN;
+    double* vwin = win + WIN * WIN;
     int pi = (int)((blockIdx.x * 256u + threadIdx.x) / LPP);
     const bool valid = pi < N;
     if (!valid) pi = N - 1;
@@ -952,8 +960,42 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
 
     // integer part of a warp position (the displacement clamp included)
     auto ifloor = [&](double u) { return (int)fmin(fmax(floor(u), -lim), lim); };
+    // window origin: the integer extent [lo, hi] of the warps in the middle,
+    // with room for the patch, a pixel before it and two after it (a
+    // position whose fraction rounds up to the next integer)
+    int wx0 = 0, wy0 = 0;
+    auto place = [&](int xlo, int xhi, int ylo, int yhi) {
+        wx0 = x0 + xlo - 1 - max(WIN - (PS + 3) - (xhi - xlo), 0) / 2;
+        wy0 = y0 + ylo - 1 - max(WIN - (PS + 3) - (yhi - ylo), 0) / 2;
+    };
+    // one bilinear sample of J1: taps (floor before any clamp, fractions),
+    // value and its partial derivatives, as taps_of computes them
+    struct Tap { int fx, fy; double ax, ay; };
+    auto sample = [&](double x, double y, Tap& t, double& val, double& dx, double& dy) {
+        const double xf = floor(x), yf = floor(y);
+        t.ax = x - xf;
+        t.ay = y - yf;
+        t.fx = (int)xf;
+        t.fy = (int)yf;
+        const int X = t.fx - wx0, Y = t.fy - wy0;
+        double va, vb, vc, vd;
+        if (VW && X >= 0 && Y >= 0 && X + 1 < WIN && Y + 1 < WIN) {
+            const double* c = vwin + Y * WIN + X;
+            va = c[0]; vb = c[1]; vc = c[WIN]; vd = c[WIN + 1];
+        } else {
+            const int ix0 = clampi(t.fx, 0, W - 1), ix1 = clampi(t.fx + 1, 0, W - 1);
+            const int iy0 = clampi(t.fy, 0, H - 1), iy1 = clampi(t.fy + 1, 0, H - 1);
+            va = J1[iy0 * W + ix0]; vb = J1[iy0 * W + ix1];
+            vc = J1[iy1 * W + ix0]; vd = J1[iy1 * W + ix1];
+        }
+        const double ax = t.ax, ay = t.ay;
+        const double top = (1.0 - ax) * va + ax * vb, bot = (1.0 - ax) * vc + ax * vd;
+        val = (1.0 - ay) * top + ay * bot;
+        dx = (1.0 - ay) * (vb - va) + ay * (vd - vc);
+        dy = bot - top;
+    };
     // residual of the patch at displacement (u, v): d_p, its derivatives, taps
-    auto warp = [&](double u, double v, double (&d)[PPL], double (&dx)[PPL], double (&dy)[PPL], Taps (&tp)[PPL]) {
+    auto warp = [&](double u, double v, double (&d)[PPL], double (&dx)[PPL], double (&dy)[PPL], Tap (&tp)[PPL]) {
         const double fu = floor(u), fv = floor(v);
         const double cu = fmin(fmax(fu, -lim), lim) + (u - fu), cv = fmin(fmax(fv, -lim), lim) + (v - fv);
 #pragma unroll
@@ -962,21 +1004,37 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
             d[k] = dx[k] = dy[k] = 0.0;
             if (p < NP) {
                 const int py = p / PS, px = p - py * PS;
-                tp[k] = taps_of(J1, W, H, (double)(x0 + px) + cu, (double)(y0 + py) + cv);
-                d[k] = tp[k].val - T[k];
-                dx[k] = tp[k].dx;
-                dy[k] = tp[k].dy;
+                double val;
+                sample((double)(x0 + px) + cu, (double)(y0 + py) + cv, tp[k], val, dx[k], dy[k]);
+                d[k] = val - T[k];
             }
         }
     };
+    // clear the adjoint window (and fill the value window) at the origin
+    auto fill = [&]() {
+        for (int i = lane; i < WIN * WIN; i += LPP) {
+            win[i] = 0.0;
+            if (VW) {
+                const int Y = i / WIN, X = i - Y * WIN;
+                vwin[i] = J1[(size_t)clampi(wy0 + Y, 0, H - 1) * W + clampi(wx0 + X, 0, W - 1)];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
 
+    if (VW) {
+        const int fxu = ifloor(uf), fyv = ifloor(vf);
+        const int ixa = iterate ? ifloor(ui) : fxu, iya = iterate ? ifloor(vi) : fyv;
+        place(min(ixa, fxu), max(ixa, fxu), min(iya, fyv), max(iya, fyv));
+        fill();
+    }
     // forward iterates u_0 .. u_iters (every lane of the patch holds the same
     // bits of (u, v): the butterfly sums are commutative), and the integer
     // extent of every warp the reverse touches
     double* su_ = s_u + (size_t)grp * (a.iters + 1) * 2;
     int ix_lo = ifloor(uf), ix_hi = ix_lo, iy_lo = ifloor(vf), iy_hi = iy_lo;
     double d[PPL], dqx[PPL], dqy[PPL];
-    Taps tp[PPL];
+    Tap tp[PPL];
     if (iterate) {
         double u = ui, v = vi;
         for (int it = 0; it < a.iters; ++it) {
@@ -995,26 +1053,30 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
             v = v - (m12 * b1 + m22 * b2);
         }
     }
-    // the J1 adjoint of this patch goes to its LDS window when every warp
-    // fits; window cell (X, Y) is position (wx0 + X, wy0 + Y) before the tap
-    // clamp, which the flush applies
-    const bool use_win = (ix_hi - ix_lo) <= A.span && (iy_hi - iy_lo) <= A.span;
-    const int wx0 = x0 + ix_lo - 1, wy0 = y0 + iy_lo - 1;
-    const int wdx = PS + 3 + (ix_hi - ix_lo), wdy = PS + 3 + (iy_hi - iy_lo);
-    if (use_win)
-        for (int i = lane; i < WIN * WIN; i += LPP) win[i] = 0.0;
-    __builtin_amdgcn_wave_barrier();
+    if (!VW) {
+        place(ix_lo, ix_hi, iy_lo, iy_hi);
+        fill();
+    }
+    // the J1 adjoint of one tap set: into the window where all four taps
+    // fall inside it, else straight to memory
     auto scatter_j1 = [&](int k, double val) {
-        const Taps& t = tp[k];
+        const Tap& t = tp[k];
+        const double ax = t.ax, ay = t.ay;
+        const double w00 = (1.0 - ay) * (1.0 - ax), w01 = (1.0 - ay) * ax, w10 = ay * (1.0 - ax), w11 = ay * ax;
         const int X = t.fx - wx0, Y = t.fy - wy0;
-        if (use_win && X >= 0 && Y >= 0 && X + 1 < wdx && Y + 1 < wdy) {
+        if (X >= 0 && Y >= 0 && X + 1 < WIN && Y + 1 < WIN) {
             double* c = win + Y * WIN + X;
-            if (val * t.w00 != 0.0) unsafeAtomicAdd(c, val * t.w00);
-            if (val * t.w01 != 0.0) unsafeAtomicAdd(c + 1, val * t.w01);
-            if (val * t.w10 != 0.0) unsafeAtomicAdd(c + WIN, val * t.w10);
-            if (val * t.w11 != 0.0) unsafeAtomicAdd(c + WIN + 1, val * t.w11);
+            if (val * w00 != 0.0) unsafeAtomicAdd(c, val * w00);
+            if (val * w01 != 0.0) unsafeAtomicAdd(c + 1, val * w01);
+            if (val * w10 != 0.0) unsafeAtomicAdd(c + WIN, val * w10);
+            if (val * w11 != 0.0) unsafeAtomicAdd(c + WIN + 1, val * w11);
         } else {
-            scatter_taps(A.gJ1, tp[k], val);
+            const int ix0 = clampi(t.fx, 0, W - 1), ix1 = clampi(t.fx + 1, 0, W - 1);
+            const int iy0 = clampi(t.fy, 0, H - 1), iy1 = clampi(t.fy + 1, 0, H - 1);
+            atom(A.gJ1 + iy0 * W + ix0, val * w00);
+            atom(A.gJ1 + iy0 * W + ix1, val * w01);
+            atom(A.gJ1 + iy1 * W + ix0, val * w10);
+            atom(A.gJ1 + iy1 * W + ix1, val * w11);
         }
     };
 
@@ -1081,10 +1143,10 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
     }
     // the window, with the taps' clamp to the image
     __builtin_amdgcn_wave_barrier();
-    if (use_win && valid) {
-        for (int i = lane; i < wdx * wdy; i += LPP) {
-            const int Y = i / wdx, X = i - Y * wdx;
-            const double v = win[Y * WIN + X];
+    if (valid) {
+        for (int i = lane; i < WIN * WIN; i += LPP) {
+            const int Y = i / WIN, X = i - Y * WIN;
+            const double v = win[i];
             if (v != 0.0) unsafeAtomicAdd(A.gJ1 + (size_t)clampi(wy0 + Y, 0, H - 1) * W + clampi(wx0 + X, 0, W - 1), v);
         }
     }
@@ -1128,16 +1190,17 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
 }
 
 // Up to 8x8 patches the reverse search fits two waves per SIMD in 256
-// registers (a few spill), which hides more of its latency than one wave with
-// all the registers it asks for; larger patches would spill heavily.
+// registers, which hides more of its latency than one wave with all the
+// registers it asks for, and keeps its J1 values in the LDS window; larger
+// patches sample J1 in memory (two windows would not fit 64 KB of LDS).
 template <int PS, int LPP>
 __global__ __launch_bounds__(256) void k_bwd_search(const SearchBwdArgs A) {
-    bwd_search_block<PS, LPP>(A);
+    bwd_search_block<PS, LPP, false>(A);
 }
 
 template <int PS, int LPP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_bwd_search_w2(const SearchBwdArgs A) {
-    bwd_search_block<PS, LPP>(A);
+    bwd_search_block<PS, LPP, true>(A);
 }
 
 // ------------------------------------------------------------ kernel table
@@ -1175,6 +1238,7 @@ const void* dis_kernel_bwd_pyramid() { return (const void*)&k_bwd_pyramid; }
 
 #define DIS_BWD_SEARCH_CASE(PS_) \
     if (ps == PS_) return PS_ <= 8 ? (const void*)&k_bwd_search_w2<PS_, 16> : (const void*)&k_bwd_search<PS_, 16>;
+int dis_bwd_search_windows(int ps) { return ps <= 8 ? 2 : 1; }
 const void* dis_kernel_bwd_search(int ps) {
     DIS_BWD_SEARCH_CASE(4) DIS_BWD_SEARCH_CASE(6) DIS_BWD_SEARCH_CASE(8) DIS_BWD_SEARCH_CASE(10)
     DIS_BWD_SEARCH_CASE(12) DIS_BWD_SEARCH_CASE(14) DIS_BWD_SEARCH_CASE(16)

@@ -133,15 +133,17 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
     const int ss = dis_coarsest(&p, w, hgt);
     const int cmap = (p.flags & DIS_FLAG_PIXEL_CENTRE) ? 1 : 0;
     const bool f64io = (p.flags & DIS_FLAG_IO_F64) != 0;
-    // search reverse: iterates of 16 patches, then a J1-adjoint window per
-    // patch, as wide as 64 KB of LDS allows (span 0..12 extra pixels)
+    // search reverse: iterates of 16 patches, then one or two LDS windows
+    // per patch (J1 adjoint, J1 values), as wide as 64 KB of LDS allows
+    // (PS + 3 to PS + 15 cells a side)
     const size_t traj = (size_t)16 * (p.gn_iters + 1) * 2 * sizeof(double);
-    if (traj > 65536 - 16 * 8 * (size_t)(ps + 3) * (ps + 3))
+    const size_t wbytes = (size_t)16 * 8 * dis_bwd_search_windows(ps);
+    if (traj > 65536 - wbytes * (ps + 3) * (ps + 3))
         return dis_fail(h, DIS_EINVAL, "backward supports at most %d Gauss-Newton iterations for patch %d",
-                        (int)((65536 - 16 * 8 * (ps + 3) * (ps + 3)) / (16 * 2 * 8)) - 1, ps);
-    int span = 12;
-    while (span > 0 && traj + (size_t)16 * 8 * (ps + 3 + span) * (ps + 3 + span) > 65536) --span;
-    const size_t shmem = traj + (size_t)16 * 8 * (ps + 3 + span) * (ps + 3 + span);
+                        (int)((65536 - wbytes * (ps + 3) * (ps + 3)) / (16 * 2 * 8)) - 1, ps);
+    int win = ps + 15;
+    while (win > ps + 3 && traj + wbytes * win * win > 65536) --win;
+    const size_t shmem = traj + wbytes * win * win;
     Seq& q = bp->seq;
 
     {
@@ -375,7 +377,7 @@ static int build_backward(dis_handle* h, int w, int hgt, BwdPlan* bp) {
         sa.gP = B.gP[s];
         sa.gJ0 = B.gJ0[s];
         sa.gJ1 = B.gJ1[s];
-        sa.span = span;
+        sa.win = win;
         const void* fs = dis_kernel_bwd_search(ps);
         if (!fs) return dis_fail(h, DIS_EINVAL, "no backward search kernel for patch %d", ps);
         const unsigned nb = (unsigned)(((size_t)N * 16 + 255) / 256);
