@@ -116,6 +116,10 @@ def main():
                     help="timed steps of each extension (robust norms, stereo, forward-backward, colour); 0 skips")
     ap.add_argument("--fwd-bwd-pairs", type=int, default=8,
                     help="pairs of 512x256 in the forward+backward measurement (0 skips it)")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="hardware queues HIP may open for this process (GPU_MAX_HW_QUEUES, 1..32); the "
+                         "forward+backward line runs its pairs on that many streams, and streams that share "
+                         "a queue run one after the other")
     args = ap.parse_args()
     if args.only == "headline":
         args.headline_only = True
@@ -125,6 +129,11 @@ def main():
             "with no exchange); run it with --gpus 1")
         sys.exit(2)
 
+    # read by the HIP runtime when the process first touches the GPU
+    if not 1 <= args.hw_queues <= 32:
+        log("--hw-queues takes 1..32")
+        sys.exit(2)
+    os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     import numpy as np
     import torch
     from paper_1603_03590_amd import DIS, params, synth, _lib
@@ -362,7 +371,8 @@ def main():
         pix = nfb * 512 * 256
         fwd_bwd = dict(value=pix / t_fb / 1e6, unit="Mpix/s", ms_per_step=t_fb * 1e3, pairs=nfb,
                        forward_only=dict(value=pix / t_f / 1e6, ms_per_step=t_f * 1e3),
-                       mean_epe_px=mean_epe, dtype_io="f32", streams=nfb, tunables=hs[0].tunables(),
+                       mean_epe_px=mean_epe, dtype_io="f32", streams=nfb, hw_queues=args.hw_queues,
+                       tunables=hs[0].tunables(),
                        kernels=kernel_table(list(fb_k.values()), 3),
                        workload=f"{nfb} pairs 512x256 float32, smooth-bump generator (max 16 px, seeds "
                                 f"2000..{2000 + nfb - 1}); patch 8, overlap 0.5, scales 3..0, "
