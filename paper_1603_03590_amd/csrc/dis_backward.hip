@@ -315,8 +315,13 @@ __device__ __forceinline__ PixAdj pix_adj(const RefBwdArgs& a, size_t g, size_t 
 // The coefficient adjoints of one fixed-point step, part 1 (per pixel):
 // through omega/(A+S), c = N - S U - B, the neighbour sums N and S, the
 // robust data weights and the linearisation, down to U, F, J0 and J1w.
-__device__ __forceinline__ void bwd_lin_pixel(const RefBwdArgs& a, int x, int y, double (&simg)[2][8][68], int ox,
-                                              int oy) {
+__device__ __forceinline__ void bwd_lin_pixel(const RefBwdArgs& a, int x, int y, double (&simg)[2][8][68],
+                                              double (&sfl)[2][2][6][66], int x0, int y0) {
+    const int ox = x0 - 2, oy = y0 - 2;
+    // flow adjoints (field 0: U, 1: F; plane c) into the block's LDS cells
+    auto fl = [&](int f, int c, int xx, int yy, double v) {
+        if (v != 0.0) unsafeAtomicAdd(&sfl[f][c][yy - y0 + 1][xx - x0 + 1], v);
+    };
     const int W = a.W, H = a.H;
     const size_t g = (size_t)y * W + x, n = (size_t)W * H;
     const double* ws = a.coef + 5 * n;
@@ -330,12 +335,12 @@ __device__ __forceinline__ void bwd_lin_pixel(const RefBwdArgs& a, int x, int y,
     const double gA12 = acc[4 * n + g];
     const double gB1 = -gc1, gB2 = -gc2;
     // c = N - S U - B: U at the pixel and its neighbours
-    atom(a.gU + g, -S * gc1);
-    atom(a.gU + n + g, -S * gc2);
-    if (hr) { atom(a.gU + g + 1, wr * gc1); atom(a.gU + n + g + 1, wr * gc2); }
-    if (hl) { atom(a.gU + g - 1, wl * gc1); atom(a.gU + n + g - 1, wl * gc2); }
-    if (hd) { atom(a.gU + g + W, wd * gc1); atom(a.gU + n + g + W, wd * gc2); }
-    if (hu) { atom(a.gU + g - W, wu * gc1); atom(a.gU + n + g - W, wu * gc2); }
+    fl(0, 0, x, y, -S * gc1);
+    fl(0, 1, x, y, -S * gc2);
+    if (hr) { fl(0, 0, x + 1, y, wr * gc1); fl(0, 1, x + 1, y, wr * gc2); }
+    if (hl) { fl(0, 0, x - 1, y, wl * gc1); fl(0, 1, x - 1, y, wl * gc2); }
+    if (hd) { fl(0, 0, x, y + 1, wd * gc1); fl(0, 1, x, y + 1, wd * gc2); }
+    if (hu) { fl(0, 0, x, y - 1, wu * gc1); fl(0, 1, x, y - 1, wu * gc2); }
 
     // robust data weights and linearisation
     const Lin L = lin_at(a, x, y);
@@ -373,7 +378,7 @@ __device__ __forceinline__ void bwd_lin_pixel(const RefBwdArgs& a, int x, int y,
     gIyy += gry * L.fv; gIyz += gry;
     gfu += grx * Ixx + gry * Ixy;
     gfv += grx * Ixy + gry * Iyy;
-    if (a.F) { atom(a.gF + g, gfu); atom(a.gF + n + g, gfv); }
+    if (a.F) { fl(1, 0, x, y, gfu); fl(1, 1, x, y, gfv); }
     // beta = 1 / (a^2 + b^2 + 0.01)
     gIx += gb0 * (-b0 * b0) * 2.0 * Ix; gIy += gb0 * (-b0 * b0) * 2.0 * Iy;
     gIxx += gbx * (-bx * bx) * 2.0 * Ixx; gIxy += gbx * (-bx * bx) * 2.0 * Ixy;
@@ -413,19 +418,22 @@ __device__ __forceinline__ void bwd_lin_pixel(const RefBwdArgs& a, int x, int y,
 }
 
 // One fixed-point step's coefficient adjoints on a 64x4 block.  Part 1 per
-// pixel (bwd_lin_pixel).  The image adjoints of the block land within 2
-// pixels of it: they are summed in LDS first (68x8 cells per image), then
-// added to memory once per cell, which takes most of the float64 atomics off
-// the memory side.  Part 2 per owner pixel: the adjoint of the edge weights
-// it owns (right and lower edge, each seen from both endpoints: the
+// pixel (bwd_lin_pixel).  Part 2 per owner pixel: the adjoint of the edge
+// weights it owns (right and lower edge, each seen from both endpoints: the
 // coefficient adjoint of the edge plus the endpoint's dS and dc terms), then
 // through ws = alpha / (2 sqrt(E_S + eps^2)) and the forward differences of
 // U + F.  The endpoint terms of the block's pixels and of the column to its
-// right and the row below it are formed once, into LDS.
+// right and the row below it are formed once, into LDS.  Every adjoint the
+// block produces lands within 2 pixels of it (the images') or 1 (the flow's
+// U and F): they are summed in LDS first (68x8 and 66x6 cells per plane),
+// then added to memory once per cell, which takes most of the float64
+// atomics off the memory side.
 __global__ __launch_bounds__(256) void k_bwd_lin_ws(const RefBwdArgs a) {
     __shared__ double simg[2][8][68];
+    __shared__ double sfl[2][2][6][66];
     __shared__ double sadj[3][5][65];   // dS, dc1, dc2
     for (int i = threadIdx.x; i < 2 * 8 * 68; i += 256) (&simg[0][0][0])[i] = 0.0;
+    for (int i = threadIdx.x; i < 2 * 2 * 6 * 66; i += 256) (&sfl[0][0][0][0])[i] = 0.0;
     const int W = a.W, H = a.H;
     const size_t n = (size_t)W * H;
     const int x0 = (int)blockIdx.x * 64, y0 = (int)blockIdx.y * 4;
@@ -441,48 +449,58 @@ __global__ __launch_bounds__(256) void k_bwd_lin_ws(const RefBwdArgs a) {
     __syncthreads();
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     const int x = x0 + lx, y = y0 + ly;
-    const int ox = x0 - 2, oy = y0 - 2;
-    if (x < W && y < H) bwd_lin_pixel(a, x, y, simg, ox, oy);
+    if (x < W && y < H) {
+        bwd_lin_pixel(a, x, y, simg, sfl, x0, y0);
+        const size_t g = (size_t)y * W + x;
+        const double* acc = a.acc;
+        const double* U = a.U;
+        // an edge's adjoint as seen from its endpoint ge (block cell cx, cy),
+        // whose coefficient adjoint of that edge is plane q; go: the other endpoint
+        auto seen = [&](int q, size_t ge, int cx, int cy, size_t go) {
+            return ((acc[q * n + ge] + sadj[0][cy][cx]) + sadj[1][cy][cx] * U[go]) + sadj[2][cy][cx] * U[n + go];
+        };
+        double gws = 0.0;
+        if (x < W - 1) gws += seen(5, g, lx, ly, g + 1) + seen(6, g + 1, lx + 1, ly, g);
+        if (y < H - 1) gws += seen(7, g, lx, ly, g + W) + seen(8, g + W, lx, ly + 1, g);
+        if (gws != 0.0) {
+            double es;
+            const double ws = ws_at(a, x, y, &es);
+            const double gE = -gws * ws / (2.0 * (es + a.eps * a.eps));
+            auto uu = [&](size_t i) { return a.F ? a.U[i] + a.F[i] : a.U[i]; };
+            auto vv = [&](size_t i) { return a.F ? a.U[n + i] + a.F[n + i] : a.U[n + i]; };
+            auto add = [&](int c, int xx, int yy, double v) {   // full flow U + F
+                if (v == 0.0) return;
+                unsafeAtomicAdd(&sfl[0][c][yy - y0 + 1][xx - x0 + 1], v);
+                if (a.F) unsafeAtomicAdd(&sfl[1][c][yy - y0 + 1][xx - x0 + 1], v);
+            };
+            const double u0 = uu(g), v0 = vv(g);
+            if (x < W - 1) {
+                const double dxu = uu(g + 1) - u0, dxv = vv(g + 1) - v0;
+                add(0, x + 1, y, 2.0 * dxu * gE); add(0, x, y, -2.0 * dxu * gE);
+                add(1, x + 1, y, 2.0 * dxv * gE); add(1, x, y, -2.0 * dxv * gE);
+            }
+            if (y < H - 1) {
+                const double dyu = uu(g + W) - u0, dyv = vv(g + W) - v0;
+                add(0, x, y + 1, 2.0 * dyu * gE); add(0, x, y, -2.0 * dyu * gE);
+                add(1, x, y + 1, 2.0 * dyv * gE); add(1, x, y, -2.0 * dyv * gE);
+            }
+        }
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < 2 * 8 * 68; i += 256) {
         const int f = i / (8 * 68), r = i - f * (8 * 68), cy = r / 68, cx = r - cy * 68;
-        const int gx = ox + cx, gy = oy + cy;
+        const int gx = x0 - 2 + cx, gy = y0 - 2 + cy;
         const double v = simg[f][cy][cx];
         if (v != 0.0 && gx >= 0 && gx < W && gy >= 0 && gy < H)
             unsafeAtomicAdd((f ? a.gJ1w : a.gJ0) + (size_t)gy * W + gx, v);
     }
-    if (x >= W || y >= H) return;
-    const size_t g = (size_t)y * W + x;
-    const double* acc = a.acc;
-    const double* U = a.U;
-    // an edge's adjoint as seen from its endpoint ge (block cell cx, cy),
-    // whose coefficient adjoint of that edge is plane q; go: the other endpoint
-    auto seen = [&](int q, size_t ge, int cx, int cy, size_t go) {
-        return ((acc[q * n + ge] + sadj[0][cy][cx]) + sadj[1][cy][cx] * U[go]) + sadj[2][cy][cx] * U[n + go];
-    };
-    double gws = 0.0;
-    if (x < W - 1) gws += seen(5, g, lx, ly, g + 1) + seen(6, g + 1, lx + 1, ly, g);
-    if (y < H - 1) gws += seen(7, g, lx, ly, g + W) + seen(8, g + W, lx, ly + 1, g);
-    if (gws == 0.0) return;
-    double es;
-    const double ws = ws_at(a, x, y, &es);
-    const double gE = -gws * ws / (2.0 * (es + a.eps * a.eps));
-    auto uu = [&](size_t i) { return a.F ? a.U[i] + a.F[i] : a.U[i]; };
-    auto vv = [&](size_t i) { return a.F ? a.U[n + i] + a.F[n + i] : a.U[n + i]; };
-    auto add = [&](size_t i, double v) {   // full flow U + F
-        atom(a.gU + i, v);
-        if (a.F) atom(a.gF + i, v);
-    };
-    const double u0 = uu(g), v0 = vv(g);
-    if (x < W - 1) {
-        const double dxu = uu(g + 1) - u0, dxv = vv(g + 1) - v0;
-        add(g + 1, 2.0 * dxu * gE); add(g, -2.0 * dxu * gE);
-        add(n + g + 1, 2.0 * dxv * gE); add(n + g, -2.0 * dxv * gE);
-    }
-    if (y < H - 1) {
-        const double dyu = uu(g + W) - u0, dyv = vv(g + W) - v0;
-        add(g + W, 2.0 * dyu * gE); add(g, -2.0 * dyu * gE);
-        add(n + g + W, 2.0 * dyv * gE); add(n + g, -2.0 * dyv * gE);
+    for (int i = threadIdx.x; i < 2 * 2 * 6 * 66; i += 256) {
+        const int f = i / (2 * 6 * 66), r = i - f * (2 * 6 * 66), c = r / (6 * 66), r2 = r - c * (6 * 66);
+        const int cy = r2 / 66, cx = r2 - cy * 66;
+        const int gx = x0 - 1 + cx, gy = y0 - 1 + cy;
+        const double v = sfl[f][c][cy][cx];
+        if (v != 0.0 && gx >= 0 && gx < W && gy >= 0 && gy < H)
+            unsafeAtomicAdd((f ? a.gF : a.gU) + c * n + (size_t)gy * W + gx, v);
     }
 }
 
