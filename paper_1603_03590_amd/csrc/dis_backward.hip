@@ -753,52 +753,83 @@ __device__ __forceinline__ int bwd_cover(int x, int ps, int st, int nr, int& k0)
     return min(x / st, nr - 1);
 }
 
+// The J1 adjoint a 64x4 block scatters lands near it wherever the flow and
+// the covering patches' displacements are small: positions within
+// DENS_WM pixels of the block (before the border clamp) are summed in LDS
+// and added to memory once per cell; taps beyond go to memory directly.
+constexpr int DENS_WM = 16, DENS_WW = 64 + 2 * DENS_WM, DENS_WH = 4 + 2 * DENS_WM;
+
 __global__ __launch_bounds__(256) void k_bwd_densify(const DensBwdArgs a) {
+    __shared__ double win[DENS_WH * DENS_WW];
+    for (int i = threadIdx.x; i < DENS_WH * DENS_WW; i += 256) win[i] = 0.0;
+    __syncthreads();
+    const int W = a.W, H = a.H;
+    const int wx0 = (int)blockIdx.x * 64 - DENS_WM, wy0 = (int)blockIdx.y * 4 - DENS_WM;
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int W = a.W, H = a.H;
-    if (x >= W || y >= H) return;
-    const size_t g = (size_t)y * W + x, n = (size_t)W * H;
-    const double Ux = a.Ud[g], Vx = a.Ud[n + g];
-    double gUx = a.gUd[g], gVx = a.gUd[n + g];
-    if (a.gJ1w) {
-        const double gw = a.gJ1w[g];
-        if (gw != 0.0) {
-            const Taps t = taps_of(a.J1, W, H, (double)x + Ux, (double)y + Vx);
-            gUx += gw * t.dx;
-            gVx += gw * t.dy;
-            scatter_taps(a.gJ1, t, gw);
+    auto scatter = [&](const Taps& t, double v) {
+        const int X = t.fx - wx0, Y = t.fy - wy0;
+        if (X >= 0 && Y >= 0 && X + 1 < DENS_WW && Y + 1 < DENS_WH) {
+            double* c = win + Y * DENS_WW + X;
+            if (v * t.w00 != 0.0) unsafeAtomicAdd(c, v * t.w00);
+            if (v * t.w01 != 0.0) unsafeAtomicAdd(c + 1, v * t.w01);
+            if (v * t.w10 != 0.0) unsafeAtomicAdd(c + DENS_WW, v * t.w10);
+            if (v * t.w11 != 0.0) unsafeAtomicAdd(c + DENS_WW + 1, v * t.w11);
+        } else {
+            scatter_taps(a.gJ1, t, v);
         }
-    }
-    a.gq[g] = gUx;
-    a.gq[n + g] = gVx;
-    if (gUx == 0.0 && gVx == 0.0) return;
-    const double Z = a.Z[g];
-    const double j0 = a.J0[g];
-    const int ps = a.ps, st = a.st;
-    int kx0, ky0;
-    const int kx1 = bwd_cover(x, ps, st, a.nrx, kx0), ky1 = bwd_cover(y, ps, st, a.nry, ky0);
-    const bool fx = (a.nx > a.nrx) && (x >= W - ps), fy = (a.ny > a.nry) && (y >= H - ps);
-    const int kyend = ky1 + (fy ? 1 : 0), kxend = kx1 + (fx ? 1 : 0);
-    double gj0 = 0.0;
-    for (int jy = ky0; jy <= kyend; ++jy) {
-        const int ky = jy <= ky1 ? jy : a.nry;
-        for (int jx = kx0; jx <= kxend; ++jx) {
-            const int kx = jx <= kx1 ? jx : a.nrx;
-            const double* P = a.patch + (size_t)(ky * a.nx + kx) * 4;
-            const double u = P[0], v = P[1];
-            const Taps t = taps_of(a.J1, W, H, (double)x + u, (double)y + v);
-            const double d = a.raw_residual ? (t.val - j0) : ((t.val - j0) - P[2]);
-            const double ad = fabs(d);
-            const double gw = (gUx * (u - Ux) + gVx * (v - Vx)) / Z;
-            const double gd = ad > 1.0 ? gw * (d > 0.0 ? -1.0 : 1.0) / (d * d) : 0.0;
-            if (gd != 0.0) {
-                scatter_taps(a.gJ1, t, gd);
-                gj0 -= gd;
+    };
+    auto pixel = [&]() {
+        const size_t g = (size_t)y * W + x, n = (size_t)W * H;
+        const double Ux = a.Ud[g], Vx = a.Ud[n + g];
+        double gUx = a.gUd[g], gVx = a.gUd[n + g];
+        if (a.gJ1w) {
+            const double gw = a.gJ1w[g];
+            if (gw != 0.0) {
+                const Taps t = taps_of(a.J1, W, H, (double)x + Ux, (double)y + Vx);
+                gUx += gw * t.dx;
+                gVx += gw * t.dy;
+                scatter(t, gw);
             }
         }
+        a.gq[g] = gUx;
+        a.gq[n + g] = gVx;
+        if (gUx == 0.0 && gVx == 0.0) return;
+        const double Z = a.Z[g];
+        const double j0 = a.J0[g];
+        const int ps = a.ps, st = a.st;
+        int kx0, ky0;
+        const int kx1 = bwd_cover(x, ps, st, a.nrx, kx0), ky1 = bwd_cover(y, ps, st, a.nry, ky0);
+        const bool fx = (a.nx > a.nrx) && (x >= W - ps), fy = (a.ny > a.nry) && (y >= H - ps);
+        const int kyend = ky1 + (fy ? 1 : 0), kxend = kx1 + (fx ? 1 : 0);
+        double gj0 = 0.0;
+        for (int jy = ky0; jy <= kyend; ++jy) {
+            const int ky = jy <= ky1 ? jy : a.nry;
+            for (int jx = kx0; jx <= kxend; ++jx) {
+                const int kx = jx <= kx1 ? jx : a.nrx;
+                const double* P = a.patch + (size_t)(ky * a.nx + kx) * 4;
+                const double u = P[0], v = P[1];
+                const Taps t = taps_of(a.J1, W, H, (double)x + u, (double)y + v);
+                const double d = a.raw_residual ? (t.val - j0) : ((t.val - j0) - P[2]);
+                const double ad = fabs(d);
+                const double gw = (gUx * (u - Ux) + gVx * (v - Vx)) / Z;
+                const double gd = ad > 1.0 ? gw * (d > 0.0 ? -1.0 : 1.0) / (d * d) : 0.0;
+                if (gd != 0.0) {
+                    scatter(t, gd);
+                    gj0 -= gd;
+                }
+            }
+        }
+        a.gJ0[g] += gj0;
+    };
+    if (x < W && y < H) pixel();
+    __syncthreads();
+    for (int i = threadIdx.x; i < DENS_WH * DENS_WW; i += 256) {
+        const double v = win[i];
+        if (v == 0.0) continue;
+        const int Y = i / DENS_WW, X = i - Y * DENS_WW;
+        unsafeAtomicAdd(a.gJ1 + (size_t)clampi(wy0 + Y, 0, H - 1) * W + clampi(wx0 + X, 0, W - 1), v);
     }
-    a.gJ0[g] += gj0;
 }
 
 // Pass 2, per patch (16 lanes, a lane's pixels strided by 16): the patch's
