@@ -63,6 +63,14 @@ __device__ __forceinline__ void scatter_taps(double* g, const Taps& t, double v)
     atom(g + t.i11, v * t.w11);
 }
 
+// An LDS pointer the compiler knows to be one (a pointer into dynamic shared
+// memory that meets a global one in a branch is otherwise accessed through
+// flat instructions on both sides).
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(3))) T* dis_lds(T* p) {
+    return (__attribute__((address_space(3))) T*)p;
+}
+
 }  // namespace
 
 // --------------------------------------------------------------- utilities
@@ -944,9 +952,9 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
     const int grp = threadIdx.x / LPP;
     const int N = a.nx * a.ny;
     const int WIN = A.win;
-    double* s_u = s_dyn;
+    auto* s_u = dis_lds(s_dyn);
     double* win = s_dyn + (size_t)GROUPS * (a.iters + 1) * 2 + (size_t)grp * (VW ? 2 : 1) * WIN * WIN;
-    double* vwin = win + WIN * WIN;
+    auto* vwin = dis_lds(win + WIN * WIN);
     int pi = (int)((blockIdx.x * 256u + threadIdx.x) / LPP);
     const bool valid = pi < N;
     if (!valid) pi = N - 1;
@@ -963,8 +971,8 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
         ui = 2.0 * taps_of(a.Un, a.Wn, a.Hn, qx, qy).val;
         vi = 2.0 * taps_of(a.Un + (size_t)a.Wn * a.Hn, a.Wn, a.Hn, qx, qy).val;
     }
-    const double* J0 = a.J0;
-    const double* J1 = a.J1;
+    const auto* J0 = dis_global(a.J0);
+    const auto* J1 = dis_global(a.J1);
     // pixels of this lane: p = lane + k * LPP
     double T[PPL], gx[PPL], gy[PPL];
     double sgx_l = 0.0, sgy_l = 0.0, h11_l = 0.0, h12_l = 0.0, h22_l = 0.0;
@@ -996,10 +1004,10 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
     const double m11 = a22 * idet, m12 = -a12 * idet, m22 = a11 * idet;
     const double inv_n = 1.0 / (double)NP;
     const double lim = (double)(W + H + 2 * PS + 4);
-    const double* P = a.patch + (size_t)pi * 4;
+    const auto* P = dis_global(a.patch) + (size_t)pi * 4;
     const double uf = P[0], vf = P[1];
     const bool reset = P[3] > (double)PS;
-    const double* gP = A.gP + (size_t)pi * 4;
+    const auto* gP = dis_global(A.gP) + (size_t)pi * 4;
     double gu = gP[0], gv = gP[1];
     const double gmd = gP[2];
     const bool iterate = !reset && a.iters > 0;
@@ -1029,7 +1037,7 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
         const int X = t.fx - wx0, Y = t.fy - wy0;
         double va, vb, vc, vd;
         if (VW && X >= 0 && Y >= 0 && X + 1 < WIN && Y + 1 < WIN) {
-            const double* c = vwin + Y * WIN + X;
+            const auto* c = vwin + Y * WIN + X;
             va = c[0]; vb = c[1]; vc = c[WIN]; vd = c[WIN + 1];
         } else {
             const int ix0 = clampi(t.fx, 0, W - 1), ix1 = clampi(t.fx + 1, 0, W - 1);
@@ -1080,7 +1088,7 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
     // forward iterates u_0 .. u_iters (every lane of the patch holds the same
     // bits of (u, v): the butterfly sums are commutative), and the integer
     // extent of every warp the reverse touches
-    double* su_ = s_u + (size_t)grp * (a.iters + 1) * 2;
+    auto* su_ = s_u + (size_t)grp * (a.iters + 1) * 2;
     int ix_lo = ifloor(uf), ix_hi = ix_lo, iy_lo = ifloor(vf), iy_hi = iy_lo;
     double d[PPL], dqx[PPL], dqy[PPL];
     Tap tp[PPL];
