@@ -1025,19 +1025,28 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
         wx0 = x0 + xlo - 1 - max(WIN - (PS + 3) - (xhi - xlo), 0) / 2;
         wy0 = y0 + ylo - 1 - max(WIN - (PS + 3) - (yhi - ylo), 0) / 2;
     };
-    // one bilinear sample of J1: taps (floor before any clamp, fractions),
-    // value and its partial derivatives, as taps_of computes them
+    // whether every tap of the warp at displacement (u, v) falls inside the
+    // window: a tap's floor lies 0 or 1 (a fraction rounding up) past
+    // x0 + px + floor(u), so floor(u) within [wx0 - x0, wx0 - x0 + WIN - PS
+    // - 2] suffices; the same in y.  Uniform over the patch's lanes, which
+    // hold the same (u, v).
+    auto inside = [&](double u, double v) {
+        const int iu = ifloor(u) - (wx0 - x0), iv = ifloor(v) - (wy0 - y0);
+        return iu >= 0 && iu <= WIN - PS - 2 && iv >= 0 && iv <= WIN - PS - 2;
+    };
+    // one bilinear sample of J1 (from the value window when inw): taps
+    // (floor before any clamp, fractions), value and its partial
+    // derivatives, as taps_of computes them
     struct Tap { int fx, fy; double ax, ay; };
-    auto sample = [&](double x, double y, Tap& t, double& val, double& dx, double& dy) {
+    auto sample = [&](bool inw, double x, double y, Tap& t, double& val, double& dx, double& dy) {
         const double xf = floor(x), yf = floor(y);
         t.ax = x - xf;
         t.ay = y - yf;
         t.fx = (int)xf;
         t.fy = (int)yf;
-        const int X = t.fx - wx0, Y = t.fy - wy0;
         double va, vb, vc, vd;
-        if (VW && X >= 0 && Y >= 0 && X + 1 < WIN && Y + 1 < WIN) {
-            const auto* c = vwin + Y * WIN + X;
+        if (VW && inw) {
+            const auto* c = vwin + (t.fy - wy0) * WIN + (t.fx - wx0);
             va = c[0]; vb = c[1]; vc = c[WIN]; vd = c[WIN + 1];
         } else {
             const int ix0 = clampi(t.fx, 0, W - 1), ix1 = clampi(t.fx + 1, 0, W - 1);
@@ -1052,7 +1061,8 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
         dy = bot - top;
     };
     // residual of the patch at displacement (u, v): d_p, its derivatives, taps
-    auto warp = [&](double u, double v, double (&d)[PPL], double (&dx)[PPL], double (&dy)[PPL], Tap (&tp)[PPL]) {
+    auto warp = [&](bool inw, double u, double v, double (&d)[PPL], double (&dx)[PPL], double (&dy)[PPL],
+                    Tap (&tp)[PPL]) {
         const double fu = floor(u), fv = floor(v);
         const double cu = fmin(fmax(fu, -lim), lim) + (u - fu), cv = fmin(fmax(fv, -lim), lim) + (v - fv);
 #pragma unroll
@@ -1062,7 +1072,7 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
             if (p < NP) {
                 const int py = p / PS, px = p - py * PS;
                 double val;
-                sample((double)(x0 + px) + cu, (double)(y0 + py) + cv, tp[k], val, dx[k], dy[k]);
+                sample(inw, (double)(x0 + px) + cu, (double)(y0 + py) + cv, tp[k], val, dx[k], dy[k]);
                 d[k] = val - T[k];
             }
         }
@@ -1100,7 +1110,7 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
             const int iu = ifloor(u), iv = ifloor(v);
             ix_lo = min(ix_lo, iu); ix_hi = max(ix_hi, iu);
             iy_lo = min(iy_lo, iv); iy_hi = max(iy_hi, iv);
-            warp(u, v, d, dqx, dqy, tp);
+            warp(VW && inside(u, v), u, v, d, dqx, dqy, tp);
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) { s0 += d[k]; s1 += gx[k] * d[k]; s2 += gy[k] * d[k]; }
@@ -1114,19 +1124,18 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
         place(ix_lo, ix_hi, iy_lo, iy_hi);
         fill();
     }
-    // the J1 adjoint of one tap set: into the window where all four taps
-    // fall inside it, else straight to memory
-    auto scatter_j1 = [&](int k, double val) {
+    // the J1 adjoint of one tap set: into the window when the warp's taps
+    // all fall inside it (inw), else straight to memory
+    auto scatter_j1 = [&](bool inw, int k, double val) {
         const Tap& t = tp[k];
         const double ax = t.ax, ay = t.ay;
         const double w00 = (1.0 - ay) * (1.0 - ax), w01 = (1.0 - ay) * ax, w10 = ay * (1.0 - ax), w11 = ay * ax;
-        const int X = t.fx - wx0, Y = t.fy - wy0;
-        if (X >= 0 && Y >= 0 && X + 1 < WIN && Y + 1 < WIN) {
-            double* c = win + Y * WIN + X;
-            if (val * w00 != 0.0) unsafeAtomicAdd(c, val * w00);
-            if (val * w01 != 0.0) unsafeAtomicAdd(c + 1, val * w01);
-            if (val * w10 != 0.0) unsafeAtomicAdd(c + WIN, val * w10);
-            if (val * w11 != 0.0) unsafeAtomicAdd(c + WIN + 1, val * w11);
+        if (inw) {
+            double* c = win + (t.fy - wy0) * WIN + (t.fx - wx0);
+            unsafeAtomicAdd(c, val * w00);
+            unsafeAtomicAdd(c + 1, val * w01);
+            unsafeAtomicAdd(c + WIN, val * w10);
+            unsafeAtomicAdd(c + WIN + 1, val * w11);
         } else {
             const int ix0 = clampi(t.fx, 0, W - 1), ix1 = clampi(t.fx + 1, 0, W - 1);
             const int iy0 = clampi(t.fy, 0, H - 1), iy1 = clampi(t.fy + 1, 0, H - 1);
@@ -1139,7 +1148,8 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
 
     // mean residual at the final displacement (used by the densification)
     if (gmd != 0.0) {
-        warp(uf, vf, d, dqx, dqy, tp);
+        const bool inw = inside(uf, vf);
+        warp(VW && inw, uf, vf, d, dqx, dqy, tp);
         const double q = gmd * inv_n;
         double su = 0.0, sv = 0.0;
 #pragma unroll
@@ -1148,7 +1158,7 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
             if (p < NP) {
                 su += q * dqx[k];
                 sv += q * dqy[k];
-                if (valid) scatter_j1(k, q);
+                if (valid) scatter_j1(inw, k, q);
                 gT[k] -= q;
             }
         }
@@ -1160,7 +1170,8 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
         double H11 = 0.0, H12 = 0.0, H21 = 0.0, H22 = 0.0;   // adjoint of H
         for (int it = a.iters - 1; it >= 0; --it) {
             const double uk = su_[2 * it], vk = su_[2 * it + 1];
-            warp(uk, vk, d, dqx, dqy, tp);
+            const bool inw = inside(uk, vk);
+            warp(VW && inw, uk, vk, d, dqx, dqy, tp);
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) { s0 += d[k]; s1 += gx[k] * d[k]; s2 += gy[k] * d[k]; }
@@ -1183,7 +1194,7 @@ __device__ __forceinline__ void bwd_search_block(const SearchBwdArgs& A) {
                     gT[k] -= dd;
                     su += dd * dqx[k];
                     sv += dd * dqy[k];
-                    if (valid) scatter_j1(k, dd);
+                    if (valid) scatter_j1(inw, k, dd);
                 }
             }
             gu += red(su);
