@@ -85,6 +85,11 @@ VARIANTS = [
     ("ps4_ov0", (1, 24, 24), 105, dict(patch_size=4, overlap=0.0, gn_iters=8)),
     ("ps12_ov075_single_level", (2, 32, 32), 105, dict(patch_size=12, overlap=0.75, coarsest_scale=0, gn_iters=20)),
     ("gn0_init_only", (3, 32, 32), 105, dict(gn_iters=0)),
+    # one scale from a zero start to motions of about 5 px: the reverse
+    # search's iterates leave the patch's LDS window (which then spans the
+    # start and the end) part of the way, so both its sampling paths run
+    ("ps8_single_level_5px", (1, 40, 40), 105, dict(coarsest_scale=0)),
+    ("ps6_window", (5, 36, 36), 105, dict(patch_size=6)),
 ]
 
 
