@@ -280,7 +280,8 @@ extern "C" int dis_autotune(dis_handle* h, const char* cache_path) {
     struct Cand { int lpp, tile, mode; };
     // the search's lanes per patch and the refinement tile touch different
     // kernels of a phase-major launch, so they are tuned one after the other;
-    // the persistent launch (fixed tile) is tried with every lane count
+    // the persistent launch is tried with every lane count on each of its
+    // two refinement tiles
     const int lpps[7] = {1, 2, 4, 8, 16, 32, 64};
     const int save_flags = (int)h->p.flags;
     h->p.flags &= ~DIS_FLAG_NO_GRAPH;   // time what callers run: graph replay
