@@ -182,8 +182,10 @@ int dis_compute_flow_batched(dis_handle* h, int n, const void* const* I0,
  * recomputed from its kept patch records before its adjoint runs; the
  * finest scale's SOR states, weight sums, warped frame and linearisation are
  * the ones the forward wrote into the same one-scale buffers as it ran.
- * Scratch stays bounded by one scale.  Errors: DIS_EINVAL (NULL pointer),
- * DIS_ESTATE (no kept forward), DIS_EHIP.
+ * Scratch stays bounded by one scale.  Errors: DIS_EINVAL (NULL pointer, or
+ * more Gauss-Newton iterations than the reverse search keeps in 64 KB of
+ * LDS: 134 for 8x8 patches, 142 for 12x12, 74 for 16x16; the message gives
+ * the limit), DIS_ESTATE (no kept forward), DIS_EHIP.
  */
 int dis_flow_backward(dis_handle* h, const void* grad_flow, void* grad_I0, void* grad_I1);
 

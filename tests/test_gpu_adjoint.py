@@ -270,6 +270,20 @@ def test_backward_errors():
                 assert e.value.code == _lib.DIS_EINVAL
             finally:
                 dn.close()
+        # more Gauss-Newton iterations than the reverse search keeps in LDS
+        # (134 for 8x8 patches); the limit itself runs
+        for iters, ok in ((135, False), (134, True)):
+            dn = DIS(params(105, flags=F64 | KEEP, gn_iters=iters), 32, 32)
+            try:
+                dn.flow(a, b)
+                if ok:
+                    dn.backward(g)
+                else:
+                    with pytest.raises(DisError) as e:
+                        dn.backward(g)
+                    assert e.value.code == _lib.DIS_EINVAL and "at most 134" in str(e.value)
+            finally:
+                dn.close()
         # the autograd Function refuses a stale forward
         a2 = a.clone().requires_grad_(True)
         f = dis_flow(a2, b, d)
