@@ -366,7 +366,7 @@ def main():
             _lib.dis_profile_enable(d_.handle, False)
         torch.cuda.synchronize()
         fb_check = (fbp[0], fI0[0].grad.double().cpu().numpy(), fI1[0].grad.double().cpu().numpy(),
-                    float(losses[0]))
+                    float(losses[0].detach()))
         mean_epe = float(torch.stack([l.detach() for l in losses]).mean())
         pix = nfb * 512 * 256
         fwd_bwd = dict(value=pix / t_fb / 1e6, unit="Mpix/s", ms_per_step=t_fb * 1e3, pairs=nfb,

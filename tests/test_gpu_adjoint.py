@@ -46,7 +46,7 @@ def oracle_grad(I0, I1, gt, p):
     b = torch.from_numpy(I1).to(torch.float64).requires_grad_(True)
     L = epe_loss(O.dis_flow(a, b, oracle_params(p)), torch.from_numpy(gt).to(torch.float64))
     g0, g1 = torch.autograd.grad(L, (a, b))
-    return float(L), g0.numpy(), g1.numpy()
+    return float(L.detach()), g0.numpy(), g1.numpy()
 
 
 def gpu_grad(I0, I1, gt, p, d=None):
@@ -61,7 +61,7 @@ def gpu_grad(I0, I1, gt, p, d=None):
     L = epe_loss(dis_flow(a, b, d), torch.from_numpy(gt).to(dt).cuda())
     L.backward()
     torch.cuda.synchronize()
-    out = float(L), a.grad.double().cpu().numpy(), b.grad.double().cpu().numpy()
+    out = float(L.detach()), a.grad.double().cpu().numpy(), b.grad.double().cpu().numpy()
     if own:
         d.close()
     return out
