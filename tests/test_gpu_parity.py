@@ -69,6 +69,11 @@ CASES = [
     ("colour_ps4_l1_inner7_203x149", ("cbump", 203, 149, 6.0, 34), 103,
      dict(flags=0x80, patch_size=4, norm=1, var_inner=7, coarsest_scale=3, finest_scale=0)),
     ("colour_stereo_256x192", ("chbump", 256, 192, 8.0, 35), 101, dict(flags=0x80 | 0x20, gn_iters=4)),
+    # degenerate sizes: a coarsest level of exactly one patch, a frame of
+    # exactly one patch, and a frame one patch high with a ragged width
+    ("tiny_16x16_one_patch_coarsest", ("bump", 16, 16, 2.0, 41), 105, dict(coarsest_scale=1, finest_scale=0)),
+    ("tiny_8x8_single_patch", ("bump", 8, 8, 2.0, 41), 105, dict(coarsest_scale=0, finest_scale=0)),
+    ("tiny_19x11", ("bump", 19, 11, 2.0, 41), 105, dict(coarsest_scale=0, finest_scale=0)),
 ]
 
 
